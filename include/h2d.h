@@ -1,0 +1,178 @@
+/*
+ * h2d.h -- C ABI of the MI355X (gfx950) HODLR2D library.
+ *
+ * HODLR2D (arxiv 2204.05536) represents the dense N x N kernel matrix
+ * A_ij = K(x_i, x_j) of N points in the plane on a balanced quadtree:
+ *   - at the leaf level, the self block and the blocks of the (at most 4)
+ *     edge-sharing boxes are dense (Section 4, Algorithm 1);
+ *   - at every level 1..kappa, each box interacts with the boxes of its
+ *     interaction list (vertex-sharing or well-separated boxes of its clan,
+ *     Section 4 definitions and eq. (4.2)) through a low-rank block U V^T
+ *     obtained by adaptive cross approximation (Algorithm 1).
+ * The matrix-vector product of Algorithm 2 then costs O(p N log N).
+ *
+ * Conventions for every entry point:
+ *   - Buffers named "device" are device pointers on the current HIP device;
+ *     buffers named "host" are host pointers.  The caller owns every buffer
+ *     it passes; the library owns everything behind an h2d_t until
+ *     h2d_destroy().
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     on it; entry points that must read results back (build, solve, info,
+ *     export) synchronise that stream before returning.
+ *   - Vectors are in the caller's point order (the order of `xy`).  The tree
+ *     order is internal.
+ *   - Errors are returned as h2d_status; h2d_last_error() gives a message
+ *     for the calling thread.  No C++ exception crosses this boundary.
+ *   - Calls on one handle must not overlap in time (a handle owns scratch
+ *     vectors used by matvec and solve).
+ */
+#ifndef H2D_H
+#define H2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2d_s* h2d_t;
+
+typedef enum {
+    H2D_OK = 0,
+    H2D_EINVAL = 1,       /* bad argument or non-finite input */
+    H2D_ENOMEM = 2,       /* device or host allocation failed */
+    H2D_EDEVICE = 3,      /* a HIP call failed */
+    H2D_EDUP = 4,         /* two distinct points coincide and the kernel is singular at r = 0 */
+    H2D_ENOCONV = 5,      /* solver did not reach the tolerance; ACA hit its rank cap */
+    H2D_EUNSUPPORTED = 6, /* option not built in */
+    H2D_EDEPTH = 7        /* quadtree deeper than 16 levels needed for leaf_max */
+} h2d_status;
+
+/* Kernel functions K(x, y) = phi(|x - y|) (plus a separable test kernel).
+ *   LOG    phi = log r                      (Section 3)
+ *   INVR   phi = 1 / r                      (Section 5.1)
+ *   MQ     phi = sqrt(1 + (r / c)^2)        multiquadric RBF
+ *   GAUSS  phi = exp(-(r / c)^2)            Gaussian RBF
+ *   PHI1   phi = log r / log a (r >= a), (r log r - 1)/(a log a - 1) (r < a), a = c  (Section 5.2)
+ *   PHI2   phi = a / r (r >= a), r / a (r < a), a = c                                 (Section 5.2)
+ *   SEP    sum_{q < c} cos(q (1.3 x1 + 0.7 x2)) cos(q (0.9 y1 - 1.1 y2)), exact rank c (test kernel)
+ * Diagonal rule (decided by index equality i == j, never by r == 0):
+ *   REPLACE  A_ii = diag_value          (e.g. N for log, beta for phi_1/phi_2, 0 for 1/r)
+ *   ADD      A_ii = phi(0) + diag_value (MQ, Gauss: 1 + shift)
+ *   FORMULA  A_ii = K(x_i, x_i)         (only for kernels finite at r = 0) */
+typedef enum {
+    H2D_K_LOG = 0, H2D_K_INVR = 1, H2D_K_MQ = 2, H2D_K_GAUSS = 3,
+    H2D_K_PHI1 = 4, H2D_K_PHI2 = 5, H2D_K_SEP = 6
+} h2d_kind;
+
+typedef enum { H2D_DIAG_REPLACE = 0, H2D_DIAG_ADD = 1, H2D_DIAG_FORMULA = 2 } h2d_diag;
+
+typedef struct {
+    int32_t kind;        /* h2d_kind */
+    int32_t diag_mode;   /* h2d_diag */
+    double c;            /* shape parameter (see above) */
+    double diag_value;   /* diagonal replacement / shift */
+} h2d_kernel;
+
+/* Storage precision of U, V and the dense blocks used by a matvec. */
+typedef enum { H2D_P_FP64 = 0, H2D_P_FP16 = 1, H2D_P_BF16 = 2 } h2d_prec;
+#define H2D_PREC_BIT(p) (1u << (p))
+
+/* Algorithm 1 (InitializeHODLR2D(N_max, eps)) on the GPU.
+ *   xy        device, n x 2 row-major FP64 point coordinates (copied)
+ *   n         number of points, 1 <= n < 2^31
+ *   kernel    host, the kernel function and diagonal rule
+ *   leaf_max  N_max: the tree has the smallest depth kappa (<= 16) at which
+ *             no leaf box holds more than leaf_max points
+ *   tol       ACA tolerance eps (relative, per block), >= 0
+ *   prec_mask H2D_PREC_BIT(H2D_P_FP64) is always built; add FP16 / BF16
+ *             bits to also keep half-precision copies of every factor
+ *   stream    hipStream_t
+ *   out       receives the handle
+ * Box B = [-R, R]^2 with R the smallest power of two >= max |coordinate|;
+ * cells are half-open [lo, mid) / [mid, hi] (Section 3).  Points are ordered
+ * by (leaf Morton key, caller index).  Errors: EINVAL (bad sizes, non-finite
+ * coordinates), EDUP, EDEPTH, ENOMEM, ENOCONV (ACA rank cap), EDEVICE. */
+h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int32_t leaf_max,
+                     double tol, uint32_t prec_mask, void* stream, h2d_t* out);
+
+/* Algorithm 2 (MatVec(psi)): y = A_hat x for nrhs right-hand sides.
+ *   x, y    device, FP64, column-major n x nrhs with leading dimension ld >= n
+ *   prec    storage precision to read (must have been built); FP16/BF16
+ *           accumulate in FP32 and round the result to FP64
+ * Asynchronous on `stream`.  Errors: EINVAL, EUNSUPPORTED (precision not
+ * built), EDEVICE. */
+h2d_status h2d_matvec(h2d_t H, const double* x, double* y, int32_t nrhs, int64_t ld,
+                      int32_t prec, void* stream);
+
+/* Solver modes for h2d_solve. */
+typedef enum {
+    H2D_SOLVE_PLAIN = 0,   /* restarted GMRES on the FP64 operator */
+    H2D_SOLVE_REFINE = 1   /* FP64 iterative refinement around an inner GMRES
+                              on the FP16/BF16 operator (inner_prec) */
+} h2d_solve_mode;
+
+typedef struct {
+    int32_t mode;          /* h2d_solve_mode */
+    int32_t restart;       /* GMRES restart length (e.g. 50) */
+    int32_t max_iter;      /* cap on total inner Arnoldi steps */
+    int32_t inner_prec;    /* REFINE: H2D_P_FP16 or H2D_P_BF16 */
+    double inner_tol;      /* REFINE: relative tolerance of each inner solve */
+    int32_t max_outer;     /* REFINE: cap on refinement steps */
+    int32_t pad;
+} h2d_solve_opts;
+
+typedef struct {
+    int32_t iters;         /* total inner Arnoldi steps (matvecs of the inner operator) */
+    int32_t outer;         /* refinement steps (REFINE) or restarts (PLAIN) */
+    double relres;         /* true relative residual |b - A_hat x| / |b| in FP64 at exit */
+    double seconds;        /* wall time of the call */
+} h2d_solve_info;
+
+/* Solve A_hat x = b to relative residual rtol (GMRES as used in Section 5,
+ * x0 = 0).  b, x: device FP64, n entries, caller order.  The convergence
+ * test is always the true FP64 residual.  Returns OK or ENOCONV (x then holds
+ * the last iterate and info->relres its residual). */
+h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d_solve_opts* opts,
+                     h2d_solve_info* info, void* stream);
+
+typedef struct {
+    int64_t n;
+    int32_t kappa, leaf_max;
+    double R, tol;
+    int64_t n_near;        /* dense leaf blocks (self + edge sharers) */
+    int64_t n_il;          /* interaction-list blocks, all levels */
+    int64_t n_il_dense;    /* interaction-list blocks stored dense */
+    int64_t max_rank, sum_rank;
+    int64_t u_elems, v_elems, d_elems;   /* stored values in U, V, dense pools */
+    double alg_bytes_fp64; /* bytes one FP64 single-RHS matvec must move */
+    double alg_bytes_half; /* same for FP16/BF16 storage */
+    double flops;          /* 2 (sum_lowrank k (m + n) + sum_dense m n) */
+    double build_seconds;
+    uint32_t prec_mask;
+    int32_t pad;
+} h2d_stats;
+
+/* Sizes, ranks and traffic of a built handle (host struct). */
+h2d_status h2d_info(h2d_t H, h2d_stats* s);
+
+/* Write H to `path` (little-endian, format "H2DX" version 1, the same the
+ * CPU oracle writes).  flags bit 0: include the factors (else structure
+ * only: tree, perm, levels, block tables with kinds and ranks). */
+h2d_status h2d_export(h2d_t H, const char* path, uint32_t flags);
+
+/* Read a file written by h2d_export (with factors) or by the oracle and
+ * upload it: the resulting handle applies exactly the stored operator. */
+h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t* out);
+
+/* Free every allocation of H (NULL is a no-op). */
+void h2d_destroy(h2d_t H);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* h2d_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2D_H */

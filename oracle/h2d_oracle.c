@@ -787,9 +787,11 @@ int orc_export(const orc_h* h, const char* path)
     FILE* f = fopen(path, "wb");
     if (!f) return ORC_EINVAL;
     const char magic[4] = {'H', '2', 'D', 'X'};
-    uint32_t version = 1;
+    uint32_t version = 1, flags = 1, reserved = 0;   /* flags bit 0: factors present */
     fwrite(magic, 1, 4, f);
     fwrite(&version, 4, 1, f);
+    fwrite(&flags, 4, 1, f);
+    fwrite(&reserved, 4, 1, f);
     fwrite(&h->n, 8, 1, f);
     fwrite(&h->kappa, 4, 1, f);
     fwrite(&h->leaf_max, 4, 1, f);

@@ -1,0 +1,413 @@
+// C ABI of the HODLR2D library: argument checks, error reporting, handle
+// lifetime, build orchestration, import / export.
+#include "h2d_impl.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+namespace h2d {
+
+static thread_local std::string g_last_error;
+
+void fail(h2d_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char* what, const char* file, int line)
+{
+    if (e == hipSuccess) return;
+    (void)hipGetLastError();
+    h2d_status code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? H2D_ENOMEM : H2D_EDEVICE;
+    fail(code, std::string(what) + ": " + hipGetErrorString(e) + " (" + file + ":" + std::to_string(line) + ")");
+}
+
+
+
+template <typename F>
+static h2d_status guarded(F&& f)
+{
+    try {
+        g_last_error.clear();
+        f();
+        return H2D_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return H2D_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return H2D_EINVAL;
+    }
+}
+
+template <typename T>
+static void up(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
+{
+    d.alloc(std::max<size_t>(h.size(), 1));
+    if (!h.empty()) HIPCK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+static void check_kernel(const h2d_kernel* k)
+{
+    if (!k) fail(H2D_EINVAL, "kernel is NULL");
+    if (k->kind < H2D_K_LOG || k->kind > H2D_K_SEP) fail(H2D_EINVAL, "unknown kernel kind");
+    if (k->diag_mode < H2D_DIAG_REPLACE || k->diag_mode > H2D_DIAG_FORMULA) fail(H2D_EINVAL, "unknown diagonal rule");
+    if ((k->kind == H2D_K_MQ || k->kind == H2D_K_GAUSS || k->kind == H2D_K_PHI1 || k->kind == H2D_K_PHI2) &&
+        !(k->c > 0.0))
+        fail(H2D_EINVAL, "shape parameter c must be > 0");
+    if (k->kind == H2D_K_PHI1 && k->c >= 1.0) fail(H2D_EINVAL, "phi_1 needs 0 < a < 1");
+    if (k->kind == H2D_K_SEP && !(k->c >= 0.0 && k->c <= 64.0)) fail(H2D_EINVAL, "separable rank must be in [0, 64]");
+    if ((k->kind == H2D_K_LOG || k->kind == H2D_K_INVR) && k->diag_mode != H2D_DIAG_REPLACE)
+        fail(H2D_EINVAL, "log and 1/r are singular at r = 0: use the REPLACE diagonal rule");
+    if (!std::isfinite(k->c) || !std::isfinite(k->diag_value)) fail(H2D_EINVAL, "non-finite kernel parameter");
+}
+
+// ---------------------------------------------------------------------
+// Export / import ("H2DX" version 1)
+// ---------------------------------------------------------------------
+struct File {
+    FILE* f = nullptr;
+    explicit File(const char* path, const char* mode) : f(std::fopen(path, mode))
+    {
+        if (!f) fail(H2D_EINVAL, std::string("cannot open ") + path);
+    }
+    ~File() { if (f) std::fclose(f); }
+    template <typename T>
+    void w(const T* p, size_t n) { if (n && std::fwrite(p, sizeof(T), n, f) != n) fail(H2D_EINVAL, "write failed"); }
+    template <typename T>
+    void w1(T v) { w(&v, 1); }
+    template <typename T>
+    void r(T* p, size_t n) { if (n && std::fread(p, sizeof(T), n, f) != n) fail(H2D_EINVAL, "truncated file"); }
+    template <typename T>
+    T r1() { T v; r(&v, 1); return v; }
+};
+
+template <typename T>
+static std::vector<T> dl(const T* d, size_t n)
+{
+    std::vector<T> h(n);
+    if (n) HIPCK(hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost));
+    return h;
+}
+
+static void export_handle(Handle& H, const char* path, uint32_t flags)
+{
+    const bool fac = flags & 1u;
+    File F(path, "wb");
+    F.w("H2DX", 4);
+    F.w1<uint32_t>(1);
+    F.w1<uint32_t>(fac ? 1u : 0u);
+    F.w1<uint32_t>(0);
+    F.w1<int64_t>(H.n);
+    F.w1<int32_t>(H.kappa);
+    F.w1<int32_t>(H.leaf_max);
+    F.w1<double>(H.R);
+    F.w1<double>(H.tol);
+    F.w1<int32_t>(H.kern.kind);
+    F.w1<int32_t>(H.kern.diag_mode);
+    F.w1<double>(H.kern.c);
+    F.w1<double>(H.kern.diag_value);
+    auto xy = dl(H.xy.p, (size_t)(2 * H.n));
+    F.w(xy.data(), xy.size());
+    std::vector<int64_t> p64(H.h_perm.begin(), H.h_perm.end());
+    F.w(p64.data(), p64.size());
+    for (int l = 0; l <= H.kappa; ++l) {
+        const Level& L = H.lev[l];
+        F.w1<int64_t>(L.nbox);
+        F.w(L.h_key.data(), L.h_key.size());
+        std::vector<int64_t> b(L.h_begin.begin(), L.h_begin.end()), c(L.h_count.begin(), L.h_count.end()),
+            p(L.h_parent.begin(), L.h_parent.end());
+        F.w(b.data(), b.size());
+        F.w(c.data(), c.size());
+        F.w(p.data(), p.size());
+    }
+    const Level& LL = H.lev[H.kappa];
+    std::vector<double> U, V, D;
+    if (fac) { U = dl(H.U64.p, H.u_elems); V = dl(H.V64.p, H.v_elems); D = dl(H.D64.p, H.d_elems); }
+    F.w1<int64_t>((int64_t)H.h_near_src.size());
+    for (int64_t x = 0; x < LL.nbox; ++x)
+        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+            F.w1<int64_t>(x);
+            F.w1<int64_t>(H.h_near_src[q]);
+            if (fac) F.w(D.data() + H.h_near_off[q], (size_t)LL.h_count[x] * LL.h_count[H.h_near_src[q]]);
+        }
+    F.w1<int64_t>(H.n_il);
+    std::vector<double> Vc;
+    for (int64_t b = 0; b < H.n_il; ++b) {
+        const Level& L = H.lev[H.h_il_level[b]];
+        int64_t m = L.h_count[H.h_il_tgt[b]], n = L.h_count[H.h_il_src[b]], k = H.h_il_k[b];
+        F.w1<int32_t>(H.h_il_level[b]);
+        F.w1<int32_t>(H.h_il_kind[b]);
+        F.w1<int64_t>(H.h_il_tgt[b]);
+        F.w1<int64_t>(H.h_il_src[b]);
+        F.w1<int64_t>(k);
+        if (!fac) continue;
+        if (H.h_il_kind[b] == kDense) {
+            F.w(D.data() + H.h_il_off[b], (size_t)(m * n));
+        } else {
+            F.w(U.data() + H.h_il_off[b], (size_t)(m * k));
+            Vc.resize((size_t)(n * k));
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t q = 0; q < k; ++q) Vc[q * n + j] = V[H.h_il_voff[b] + j * k + q];
+            F.w(Vc.data(), Vc.size());
+        }
+    }
+}
+
+static void import_handle(Handle& H, const char* path, hipStream_t s)
+{
+    File F(path, "rb");
+    char magic[4];
+    F.r(magic, 4);
+    if (std::memcmp(magic, "H2DX", 4) != 0) fail(H2D_EINVAL, "not an H2DX file");
+    uint32_t version = F.r1<uint32_t>(), flags = F.r1<uint32_t>();
+    (void)F.r1<uint32_t>();
+    if (version != 1) fail(H2D_EINVAL, "unsupported H2DX version");
+    if (!(flags & 1u)) fail(H2D_EINVAL, "file holds no factors");
+    H.n = F.r1<int64_t>();
+    H.kappa = F.r1<int32_t>();
+    H.leaf_max = F.r1<int32_t>();
+    H.R = F.r1<double>();
+    H.tol = F.r1<double>();
+    H.kern.kind = F.r1<int32_t>();
+    H.kern.diag_mode = F.r1<int32_t>();
+    H.kern.c = F.r1<double>();
+    H.kern.diag_value = F.r1<double>();
+    if (H.n < 1 || H.n >= (int64_t)1 << 31 || H.kappa < 0 || H.kappa > kMaxLevel) fail(H2D_EINVAL, "bad header");
+    const int64_t n = H.n;
+    std::vector<double> xy((size_t)(2 * n));
+    F.r(xy.data(), xy.size());
+    std::vector<int64_t> p64((size_t)n);
+    F.r(p64.data(), p64.size());
+    H.h_perm.assign(p64.begin(), p64.end());
+    for (int l = 0; l <= H.kappa; ++l) {
+        Level& L = H.lev[l];
+        L.nbox = F.r1<int64_t>();
+        if (L.nbox < 1 || L.nbox > n) fail(H2D_EINVAL, "bad level table");
+        L.h_key.resize(L.nbox);
+        F.r(L.h_key.data(), L.nbox);
+        std::vector<int64_t> b(L.nbox), c(L.nbox), p(L.nbox);
+        F.r(b.data(), L.nbox); F.r(c.data(), L.nbox); F.r(p.data(), L.nbox);
+        L.h_begin.assign(b.begin(), b.end());
+        L.h_count.assign(c.begin(), c.end());
+        L.h_parent.assign(p.begin(), p.end());
+    }
+    const Level& LL = H.lev[H.kappa];
+    // near blocks, (target, source) order
+    int64_t nn = F.r1<int64_t>();
+    std::vector<double> D;
+    H.h_near_ptr.assign(LL.nbox + 1, 0);
+    H.h_near_src.resize(nn);
+    H.h_near_off.resize(nn);
+    std::vector<int64_t> ntgt(nn);
+    for (int64_t q = 0; q < nn; ++q) {
+        int64_t t = F.r1<int64_t>(), u = F.r1<int64_t>();
+        if (t < 0 || t >= LL.nbox || u < 0 || u >= LL.nbox || (q > 0 && t < ntgt[q - 1]))
+            fail(H2D_EINVAL, "bad near block");
+        ntgt[q] = t;
+        H.h_near_src[q] = (int32_t)u;
+        H.h_near_off[q] = (int64_t)D.size();
+        size_t e = (size_t)LL.h_count[t] * LL.h_count[u];
+        size_t o = D.size();
+        D.resize(o + e);
+        F.r(D.data() + o, e);
+        H.h_near_ptr[t + 1]++;
+    }
+    for (int64_t x = 0; x < LL.nbox; ++x) H.h_near_ptr[x + 1] += H.h_near_ptr[x];
+    // interaction-list blocks
+    H.n_il = F.r1<int64_t>();
+    const int64_t nil = H.n_il;
+    H.h_il_level.resize(nil); H.h_il_kind.resize(nil); H.h_il_tgt.resize(nil); H.h_il_src.resize(nil);
+    H.h_il_k.resize(nil); H.h_il_off.resize(nil); H.h_il_voff.assign(nil, 0);
+    std::vector<double> U, V;
+    std::vector<double> Vc;
+    for (int64_t b = 0; b < nil; ++b) {
+        int32_t lv = F.r1<int32_t>(), kind = F.r1<int32_t>();
+        int64_t t = F.r1<int64_t>(), u = F.r1<int64_t>(), k = F.r1<int64_t>();
+        if (lv < 1 || lv > H.kappa) fail(H2D_EINVAL, "bad block level");
+        const Level& L = H.lev[lv];
+        if (t < 0 || t >= L.nbox || u < 0 || u >= L.nbox || k < 0) fail(H2D_EINVAL, "bad block");
+        if (b > 0 && (lv < H.h_il_level[b - 1] || (lv == H.h_il_level[b - 1] && t < H.h_il_tgt[b - 1])))
+            fail(H2D_EINVAL, "blocks not in (level, target) order");
+        int64_t m = L.h_count[t], nc = L.h_count[u];
+        H.h_il_level[b] = lv; H.h_il_kind[b] = kind; H.h_il_tgt[b] = (int32_t)t; H.h_il_src[b] = (int32_t)u;
+        H.h_il_k[b] = (int32_t)k;
+        if (kind == kDense) {
+            H.h_il_off[b] = (int64_t)D.size();
+            size_t o = D.size();
+            D.resize(o + (size_t)(m * nc));
+            F.r(D.data() + o, (size_t)(m * nc));
+        } else if (kind == kLowRank) {
+            if (k > std::min(m, nc)) fail(H2D_EINVAL, "rank exceeds block size");
+            H.h_il_off[b] = (int64_t)U.size();
+            H.h_il_voff[b] = (int64_t)V.size();
+            size_t o = U.size();
+            U.resize(o + (size_t)(m * k));
+            F.r(U.data() + o, (size_t)(m * k));
+            Vc.resize((size_t)(nc * k));
+            F.r(Vc.data(), Vc.size());
+            size_t ov = V.size();
+            V.resize(ov + (size_t)(nc * k));
+            for (int64_t j = 0; j < nc; ++j)
+                for (int64_t q = 0; q < k; ++q) V[ov + j * k + q] = Vc[q * nc + j];
+        } else {
+            fail(H2D_EINVAL, "bad block kind");
+        }
+    }
+    // CSR of IL blocks per level box
+    for (int l = 0; l <= H.kappa; ++l) H.lev[l].h_il_ptr.assign(H.lev[l].nbox + 1, 0);
+    {
+        std::vector<int64_t> cnt;
+        for (int64_t b = 0; b < nil; ++b) H.lev[H.h_il_level[b]].h_il_ptr[H.h_il_tgt[b] + 1]++;
+        int64_t run = 0;
+        for (int l = 1; l <= H.kappa; ++l) {
+            Level& L = H.lev[l];
+            L.h_il_ptr[0] = (int32_t)run;
+            for (int64_t x = 0; x < L.nbox; ++x) L.h_il_ptr[x + 1] += L.h_il_ptr[x];
+            run = L.h_il_ptr[L.nbox];
+        }
+    }
+    // device copies
+    up(H.xy, xy, s);
+    std::vector<double> xyt((size_t)(2 * n));
+    for (int64_t i = 0; i < n; ++i) { xyt[2 * i] = xy[2 * H.h_perm[i]]; xyt[2 * i + 1] = xy[2 * H.h_perm[i] + 1]; }
+    up(H.xyt, xyt, s);
+    up(H.perm, H.h_perm, s);
+    for (int l = 0; l <= H.kappa; ++l) {
+        Level& L = H.lev[l];
+        up(L.key, L.h_key, s);
+        up(L.begin, L.h_begin, s);
+        up(L.count, L.h_count, s);
+        up(L.parent, L.h_parent, s);
+    }
+    H.u_elems = (int64_t)U.size(); H.v_elems = (int64_t)V.size(); H.d_elems = (int64_t)D.size();
+    up(H.U64, U, s);
+    up(H.V64, V, s);
+    up(H.D64, D, s);
+    HIPCK(hipStreamSynchronize(s));
+}
+
+}  // namespace h2d
+
+using namespace h2d;
+
+extern "C" {
+
+struct h2d_s {
+    Handle h;
+};
+
+const char* h2d_last_error(void) { return g_last_error.c_str(); }
+
+h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int32_t leaf_max, double tol,
+                     uint32_t prec_mask, void* stream, h2d_t* out)
+{
+    return guarded([&] {
+        if (!out) fail(H2D_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!xy) fail(H2D_EINVAL, "xy is NULL");
+        if (n < 1 || n >= ((int64_t)1 << 31)) fail(H2D_EINVAL, "n must be in [1, 2^31)");
+        if (leaf_max < 1) fail(H2D_EINVAL, "leaf_max must be >= 1");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(H2D_EINVAL, "tol must be finite and >= 0");
+        if (prec_mask & ~7u) fail(H2D_EINVAL, "unknown precision bits");
+        check_kernel(kernel);
+        hipStream_t s = (hipStream_t)stream;
+        auto t0 = std::chrono::steady_clock::now();
+        auto up_ = std::make_unique<h2d_s>();
+        Handle& H = up_->h;
+        HIPCK(hipGetDevice(&H.device));
+        H.n = n; H.leaf_max = leaf_max; H.tol = tol;
+        H.kern = KernelParams{kernel->kind, kernel->diag_mode, kernel->c, kernel->diag_value};
+        H.xy.alloc((size_t)(2 * n));
+        HIPCK(hipMemcpyAsync(H.xy.p, xy, sizeof(double) * 2 * n, hipMemcpyDefault, s));
+        build_tree_and_lists(H, s);
+        build_factors(H, s);
+        finalize(H, s);
+        make_half_pools(H, prec_mask, s);
+        HIPCK(hipStreamSynchronize(s));
+        H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = up_.release();
+    });
+}
+
+h2d_status h2d_matvec(h2d_t H, const double* x, double* y, int32_t nrhs, int64_t ld, int32_t prec, void* stream)
+{
+    return guarded([&] {
+        if (!H || !x || !y) fail(H2D_EINVAL, "NULL argument");
+        if (nrhs < 1 || ld < H->h.n) fail(H2D_EINVAL, "need nrhs >= 1 and ld >= n");
+        if (prec < H2D_P_FP64 || prec > H2D_P_BF16) fail(H2D_EINVAL, "unknown precision");
+        if (!(H->h.prec_mask & H2D_PREC_BIT(prec))) fail(H2D_EUNSUPPORTED, "precision was not built for this handle");
+        launch_matvec(H->h, x, y, nrhs, ld, prec, (hipStream_t)stream);
+    });
+}
+
+h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d_solve_opts* opts,
+                     h2d_solve_info* info, void* stream)
+{
+    h2d_status st = H2D_OK;
+    h2d_status g = guarded([&] {
+        if (!H || !b || !x || !opts) fail(H2D_EINVAL, "NULL argument");
+        if (!(rtol > 0.0)) fail(H2D_EINVAL, "rtol must be > 0");
+        if (opts->restart < 1 || opts->max_iter < 1) fail(H2D_EINVAL, "restart and max_iter must be >= 1");
+        st = solve(H->h, b, x, rtol, *opts, info, (hipStream_t)stream);
+    });
+    return g != H2D_OK ? g : st;
+}
+
+h2d_status h2d_info(h2d_t H, h2d_stats* s)
+{
+    return guarded([&] {
+        if (!H || !s) fail(H2D_EINVAL, "NULL argument");
+        const Handle& h = H->h;
+        std::memset(s, 0, sizeof(*s));
+        s->n = h.n; s->kappa = h.kappa; s->leaf_max = h.leaf_max; s->R = h.R; s->tol = h.tol;
+        s->n_near = (int64_t)h.h_near_src.size(); s->n_il = h.n_il; s->n_il_dense = h.n_il_dense;
+        s->max_rank = h.max_rank; s->sum_rank = h.sum_rank;
+        s->u_elems = h.u_elems; s->v_elems = h.v_elems; s->d_elems = h.d_elems;
+        s->alg_bytes_fp64 = h.alg_bytes_fp64; s->alg_bytes_half = h.alg_bytes_half; s->flops = h.flops;
+        s->build_seconds = h.build_seconds; s->prec_mask = h.prec_mask;
+    });
+}
+
+h2d_status h2d_export(h2d_t H, const char* path, uint32_t flags)
+{
+    return guarded([&] {
+        if (!H || !path) fail(H2D_EINVAL, "NULL argument");
+        export_handle(H->h, path, flags);
+    });
+}
+
+h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t* out)
+{
+    return guarded([&] {
+        if (!path || !out) fail(H2D_EINVAL, "NULL argument");
+        *out = nullptr;
+        if (prec_mask & ~7u) fail(H2D_EINVAL, "unknown precision bits");
+        hipStream_t s = (hipStream_t)stream;
+        auto t0 = std::chrono::steady_clock::now();
+        auto up_ = std::make_unique<h2d_s>();
+        Handle& H = up_->h;
+        HIPCK(hipGetDevice(&H.device));
+        import_handle(H, path, s);
+        finalize(H, s);
+        make_half_pools(H, prec_mask, s);
+        HIPCK(hipStreamSynchronize(s));
+        H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = up_.release();
+    });
+}
+
+void h2d_destroy(h2d_t H)
+{
+    if (!H) return;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(H->h.device);
+    (void)hipDeviceSynchronize();
+    delete H;
+    (void)hipSetDevice(dev);
+}
+
+}  // extern "C"

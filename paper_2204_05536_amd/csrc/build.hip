@@ -1,0 +1,999 @@
+// Algorithm 1 (InitializeHODLR2D) on gfx950: quadtree, box tables,
+// interaction lists and ACA factors, all computed on the device.
+#include "h2d_impl.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <cstring>
+#include <type_traits>
+
+namespace h2d {
+
+// ---------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------
+
+// Spread the low 16 bits of v to the even bit positions.
+__device__ __forceinline__ uint32_t spread16(uint32_t v)
+{
+    v &= 0xFFFFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t compact16(uint32_t v)
+{
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+    v = (v | (v >> 4)) & 0x00FF00FFu;
+    v = (v | (v >> 8)) & 0x0000FFFFu;
+    return v;
+}
+
+// Morton key of cell (ix, iy): x bits at even, y bits at odd positions, so
+// each base-4 digit is 2*ybit + xbit.
+__device__ __forceinline__ uint32_t morton(uint32_t ix, uint32_t iy) { return spread16(ix) | (spread16(iy) << 1); }
+
+template <typename T>
+__device__ __forceinline__ int64_t lower_bound_dev(const T* a, int64_t n, T v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------
+// Exclusive scan of int32 (3 phases).  Values and totals must fit int32.
+// ---------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ int32_t block_excl_scan(int32_t v, int32_t* lds, int32_t* total)
+{
+    int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        int32_t a = (t >= d) ? lds[t - d] : 0;
+        __syncthreads();
+        lds[t] += a;
+        __syncthreads();
+    }
+    int32_t incl = lds[t];
+    if (total) *total = lds[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_sums(const int32_t* in, int64_t n, int32_t* sums)
+{
+    __shared__ int32_t lds[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t s = 0;
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) s += in[base + i];
+    int32_t tot;
+    block_excl_scan(s, lds, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Single workgroup: exclusive scan of the tile sums in place; total at sums[nb].
+__global__ void k_scan_top(int32_t* sums, int64_t nb)
+{
+    __shared__ int32_t lds[kScanThreads];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        int64_t i = base + threadIdx.x;
+        int32_t v = (i < nb) ? sums[i] : 0;
+        int32_t tot;
+        int32_t ex = block_excl_scan(v, lds, &tot);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ void k_scan_apply(const int32_t* in, int32_t* out, int64_t n, const int32_t* sums)
+{
+    __shared__ int32_t lds[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t s = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        s += v[i];
+    }
+    int32_t ex = block_excl_scan(s, lds, nullptr) + sums[blockIdx.x];
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = ex;
+        ex += v[i];
+    }
+}
+
+// out[i] = sum_{j < i} in[j]; returns the total (synchronises s).
+static int64_t scan_excl(const int32_t* in, int32_t* out, int64_t n, hipStream_t s)
+{
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1) nb = 1;
+    DBuf<int32_t> sums;
+    sums.alloc(nb + 1);
+    k_scan_sums<<<nb, kScanThreads, 0, s>>>(in, n, sums.p);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(sums.p, nb);
+    k_scan_apply<<<nb, kScanThreads, 0, s>>>(in, out, n, sums.p);
+    HIPCK(hipGetLastError());
+    int32_t tot = 0;
+    HIPCK(hipMemcpyAsync(&tot, sums.p + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    return tot;
+}
+
+// ---------------------------------------------------------------------
+// Box B and Morton keys
+// ---------------------------------------------------------------------
+
+// max |coordinate| as the bit pattern of a non-negative double (ordered like
+// the value); bad[0] |= 1 on a non-finite coordinate.
+__global__ void k_maxabs(const double* xy, int64_t n2, unsigned long long* mx, int* bad)
+{
+    __shared__ unsigned long long lds[256];
+    unsigned long long best = 0;
+    int nf = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = xy[i];
+        if (!isfinite(v)) nf = 1;
+        unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
+        best = b > best ? b : best;
+    }
+    lds[threadIdx.x] = best;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) lds[threadIdx.x] = max(lds[threadIdx.x], lds[threadIdx.x + d]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(mx, lds[0]);
+    if (nf) atomicOr(bad, 1);
+}
+
+// Cell of a coordinate at depth 16: v * 2^15 / R is exact (R is a power of
+// two), so floor() gives exactly the half-open cell [lo, mid) / [mid, hi];
+// the top edge v = R is clamped into the last cell.
+__device__ __forceinline__ uint32_t cell16(double v, double scale)
+{
+    double s = floor(v * scale);
+    long long c = (long long)s + 32768;
+    c = c < 0 ? 0 : (c > 65535 ? 65535 : c);
+    return (uint32_t)c;
+}
+
+__global__ void k_keys(const double* xy, int32_t n, double scale, uint32_t* key, int32_t* idx)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = morton(cell16(xy[2 * i], scale), cell16(xy[2 * i + 1], scale));
+    idx[i] = i;
+}
+
+// ---------------------------------------------------------------------
+// Stable LSD radix sort of (key, value) by `bits` low bits, 8 bits a pass.
+// Tile = 256 elements, one per thread; the rank of an element inside its
+// tile counts the earlier tile elements with the same digit.
+// ---------------------------------------------------------------------
+__global__ void k_radix_hist(const uint32_t* key, int32_t n, int shift, int32_t* hist, int32_t ntiles)
+{
+    __shared__ int32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int32_t e = blockIdx.x * 256 + threadIdx.x;
+    if (e < n) atomicAdd(&cnt[(key[e] >> shift) & 255u], 1);
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const uint32_t* kin, const int32_t* vin, int32_t n, int shift, const int32_t* offs,
+                                int32_t ntiles, uint32_t* kout, int32_t* vout)
+{
+    __shared__ int32_t dig[256];
+    int32_t e = blockIdx.x * 256 + threadIdx.x;
+    int32_t d = (e < n) ? (int32_t)((kin[e] >> shift) & 255u) : -1;
+    dig[threadIdx.x] = d;
+    __syncthreads();
+    if (e >= n) return;
+    int32_t r = 0;
+    for (int t = 0; t < (int)threadIdx.x; ++t) r += (dig[t] == d);
+    int32_t pos = offs[(int64_t)d * ntiles + blockIdx.x] + r;
+    kout[pos] = kin[e];
+    vout[pos] = vin[e];
+}
+
+static void radix_sort(DBuf<uint32_t>& key, DBuf<int32_t>& val, int32_t n, int bits, hipStream_t s)
+{
+    if (bits <= 0 || n <= 1) return;
+    int32_t ntiles = (n + 255) / 256;
+    DBuf<int32_t> hist, offs;
+    DBuf<uint32_t> k2;
+    DBuf<int32_t> v2;
+    hist.alloc((size_t)ntiles * 256);
+    offs.alloc((size_t)ntiles * 256);
+    k2.alloc(n);
+    v2.alloc(n);
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_radix_hist<<<ntiles, 256, 0, s>>>(key.p, n, shift, hist.p, ntiles);
+        scan_excl(hist.p, offs.p, (int64_t)ntiles * 256, s);
+        k_radix_scatter<<<ntiles, 256, 0, s>>>(key.p, val.p, n, shift, offs.p, ntiles, k2.p, v2.p);
+        HIPCK(hipGetLastError());
+        std::swap(key, k2);
+        std::swap(val, v2);
+    }
+}
+
+// Largest number of points in one box at every depth 0..16, from keys
+// sorted at depth 16.
+__global__ void k_maxrun(const uint32_t* sk, int32_t n, int32_t* maxrun)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int l = 1; l <= kMaxLevel; ++l) {
+        int sh = 2 * (kMaxLevel - l);
+        uint32_t p = sk[i] >> sh;
+        if (i > 0 && (sk[i - 1] >> sh) == p) continue;
+        // end of the run: first index whose prefix exceeds p
+        int64_t lo = i, hi = n;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((sk[mid] >> sh) <= p) lo = mid + 1; else hi = mid;
+        }
+        atomicMax(&maxrun[l], (int32_t)(lo - i));
+    }
+}
+
+__global__ void k_leafkey(const uint32_t* key16, int32_t n, int sh, uint32_t* out)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = sh >= 32 ? 0u : key16[i] >> sh;   // depth 0: a single box
+}
+
+__global__ void k_gather_xy(const double* xy, const int32_t* perm, int32_t n, double* xyt)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t p = perm[i];
+    xyt[2 * i] = xy[2 * p];
+    xyt[2 * i + 1] = xy[2 * p + 1];
+}
+
+// Box starts of a level: flag[i] = 1 where the level prefix changes.
+__global__ void k_box_flags(const uint32_t* sk, int32_t n, int sh, int32_t* flag)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || (sk[i] >> sh) != (sk[i - 1] >> sh)) ? 1 : 0;
+}
+
+__global__ void k_box_fill(const uint32_t* sk, int32_t n, int sh, const int32_t* flag, const int32_t* ex,
+                           uint32_t* key, int32_t* begin)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    key[ex[i]] = sk[i] >> sh;
+    begin[ex[i]] = i;
+}
+
+__global__ void k_box_count(const int32_t* begin, int32_t nbox, int32_t n, int32_t* count)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    count[b] = ((b + 1 < nbox) ? begin[b + 1] : n) - begin[b];
+}
+
+__global__ void k_box_parent(const uint32_t* key, int32_t nbox, const uint32_t* pkey, int32_t npbox, int32_t* parent)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    parent[b] = (int32_t)lower_bound_dev(pkey, (int64_t)npbox, key[b] >> 2);
+}
+
+// Two distinct points at the same location inside a leaf box.
+__global__ void k_dups(const double* xyt, const int32_t* begin, const int32_t* count, int32_t nbox, int* found)
+{
+    int32_t b = blockIdx.x;
+    if (b >= nbox) return;
+    int32_t c = count[b], p0 = begin[b];
+    for (int32_t e = threadIdx.x; e < c * c; e += blockDim.x) {
+        int32_t i = e / c, j = e % c;
+        if (i < j && xyt[2 * (p0 + i)] == xyt[2 * (p0 + j)] && xyt[2 * (p0 + i) + 1] == xyt[2 * (p0 + j) + 1])
+            atomicOr(found, 1);
+    }
+}
+
+// ---------------------------------------------------------------------
+// Lists
+// ---------------------------------------------------------------------
+
+// Interaction list of box b at level l (Section 4): the clan is the
+// siblings plus the children of the parent's edge sharers; keep the clan
+// members that neither coincide with nor share an edge with b and hold
+// points.  Sources are written in ascending key order.  out == nullptr:
+// count only.
+__global__ void k_il(const uint32_t* key, int32_t nbox, int level, int32_t* cnt, const int32_t* ptr, int32_t* out)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    uint32_t k = key[b];
+    int32_t x = (int32_t)compact16(k), y = (int32_t)compact16(k >> 1);
+    int32_t px = x >> 1, py = y >> 1, pside = 1 << (level - 1);
+    int32_t found[20];
+    int nf = 0;
+    const int dpx[5] = {0, -1, 1, 0, 0};
+    const int dpy[5] = {0, 0, 0, -1, 1};
+    for (int e = 0; e < 5; ++e) {   // parent itself (siblings) and its edge sharers
+        int32_t qx = px + dpx[e], qy = py + dpy[e];
+        if (qx < 0 || qy < 0 || qx >= pside || qy >= pside) continue;
+        for (int d = 0; d < 4; ++d) {
+            int32_t cx = 2 * qx + (d & 1), cy = 2 * qy + (d >> 1);
+            int32_t ax = abs(cx - x), ay = abs(cy - y);
+            if (ax + ay <= 1) continue;   // the box itself or an edge sharer
+            uint32_t ck = morton((uint32_t)cx, (uint32_t)cy);
+            int64_t pos = lower_bound_dev(key, (int64_t)nbox, ck);
+            if (pos < nbox && key[pos] == ck) found[nf++] = (int32_t)pos;
+        }
+    }
+    if (!out) { cnt[b] = nf; return; }
+    for (int i = 1; i < nf; ++i) {   // insertion sort, at most 15 entries
+        int32_t v = found[i];
+        int j = i - 1;
+        while (j >= 0 && found[j] > v) { found[j + 1] = found[j]; --j; }
+        found[j + 1] = v;
+    }
+    int32_t o = ptr[b];
+    for (int i = 0; i < nf; ++i) out[o + i] = found[i];
+}
+
+// Near list of leaf box b: itself and its edge sharers that hold points,
+// in ascending key order.
+__global__ void k_near(const uint32_t* key, int32_t nbox, int level, int32_t* cnt, const int32_t* ptr, int32_t* out)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    uint32_t k = key[b];
+    int32_t x = (int32_t)compact16(k), y = (int32_t)compact16(k >> 1), side = 1 << level;
+    int32_t found[5];
+    int nf = 0;
+    const int dx[5] = {0, -1, 1, 0, 0};
+    const int dy[5] = {0, 0, 0, -1, 1};
+    for (int e = 0; e < 5; ++e) {
+        int32_t cx = x + dx[e], cy = y + dy[e];
+        if (cx < 0 || cy < 0 || cx >= side || cy >= side) continue;
+        uint32_t ck = morton((uint32_t)cx, (uint32_t)cy);
+        int64_t pos = lower_bound_dev(key, (int64_t)nbox, ck);
+        if (pos < nbox && key[pos] == ck) found[nf++] = (int32_t)pos;
+    }
+    if (!out) { cnt[b] = nf; return; }
+    for (int i = 1; i < nf; ++i) {
+        int32_t v = found[i];
+        int j = i - 1;
+        while (j >= 0 && found[j] > v) { found[j + 1] = found[j]; --j; }
+        found[j + 1] = v;
+    }
+    int32_t o = ptr[b];
+    for (int i = 0; i < nf; ++i) out[o + i] = found[i];
+}
+
+template <typename T>
+static std::vector<T> to_host(const T* d, size_t n, hipStream_t s)
+{
+    std::vector<T> h(n);
+    if (n) HIPCK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    return h;
+}
+
+void build_tree_and_lists(Handle& H, hipStream_t s)
+{
+    const int32_t n = (int32_t)H.n;
+    const int T = 256;
+    const int G = (n + T - 1) / T;
+    // box B
+    DBuf<unsigned long long> mx;
+    DBuf<int> bad;
+    mx.alloc(1);
+    bad.alloc(1);
+    HIPCK(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), s));
+    HIPCK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    k_maxabs<<<std::min(G, 1024), 256, 0, s>>>(H.xy.p, 2 * H.n, mx.p, bad.p);
+    unsigned long long mbits = 0;
+    int hbad = 0;
+    HIPCK(hipMemcpyAsync(&mbits, mx.p, sizeof(mbits), hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (hbad) fail(H2D_EINVAL, "non-finite point coordinate");
+    double m;
+    std::memcpy(&m, &mbits, sizeof(m));
+    double R = 1.0;
+    if (m > 0.0) {
+        while (R < m) R *= 2.0;
+        while (R * 0.5 >= m) R *= 0.5;
+    }
+    H.R = R;
+    // keys at depth 16, sort #1 by the full key to find kappa
+    DBuf<uint32_t> key16, skey;
+    DBuf<int32_t> idx, sidx;
+    key16.alloc(n); idx.alloc(n); skey.alloc(n); sidx.alloc(n);
+    k_keys<<<G, T, 0, s>>>(H.xy.p, n, std::ldexp(1.0, 15) / R, key16.p, idx.p);
+    HIPCK(hipMemcpyAsync(skey.p, key16.p, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+    HIPCK(hipMemcpyAsync(sidx.p, idx.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    radix_sort(skey, sidx, n, 32, s);
+    DBuf<int32_t> maxrun;
+    maxrun.alloc(kMaxLevel + 1);
+    HIPCK(hipMemsetAsync(maxrun.p, 0, sizeof(int32_t) * (kMaxLevel + 1), s));
+    k_maxrun<<<G, T, 0, s>>>(skey.p, n, maxrun.p);
+    HIPCK(hipGetLastError());
+    auto hmax = to_host(maxrun.p, kMaxLevel + 1, s);
+    hmax[0] = n;
+    int kappa = -1;
+    for (int l = 0; l <= kMaxLevel; ++l)
+        if (hmax[l] <= H.leaf_max) { kappa = l; break; }
+    if (kappa < 0) fail(H2D_EDEPTH, "more than leaf_max points share a depth-16 box");
+    H.kappa = kappa;
+    // sort #2: stable by leaf key from caller order -> perm
+    DBuf<uint32_t> lkey;
+    lkey.alloc(n);
+    k_leafkey<<<G, T, 0, s>>>(key16.p, n, 2 * (kMaxLevel - kappa), lkey.p);
+    radix_sort(lkey, idx, n, 2 * kappa, s);
+    H.perm = std::move(idx);
+    H.xyt.alloc((size_t)2 * n);
+    k_gather_xy<<<G, T, 0, s>>>(H.xy.p, H.perm.p, n, H.xyt.p);
+    H.h_perm = to_host(H.perm.p, n, s);
+    // level tables
+    DBuf<int32_t> flag, ex;
+    flag.alloc(n); ex.alloc(n);
+    for (int l = 0; l <= kappa; ++l) {
+        Level& L = H.lev[l];
+        int sh = 2 * (kappa - l);
+        k_box_flags<<<G, T, 0, s>>>(lkey.p, n, sh, flag.p);
+        int64_t nb = scan_excl(flag.p, ex.p, n, s);
+        L.nbox = nb;
+        L.key.alloc(nb); L.begin.alloc(nb); L.count.alloc(nb); L.parent.alloc(nb);
+        k_box_fill<<<G, T, 0, s>>>(lkey.p, n, sh, flag.p, ex.p, L.key.p, L.begin.p);
+        int gb = (int)((nb + T - 1) / T);
+        k_box_count<<<gb, T, 0, s>>>(L.begin.p, (int32_t)nb, n, L.count.p);
+        if (l > 0)
+            k_box_parent<<<gb, T, 0, s>>>(L.key.p, (int32_t)nb, H.lev[l - 1].key.p, (int32_t)H.lev[l - 1].nbox,
+                                          L.parent.p);
+        else
+            HIPCK(hipMemsetAsync(L.parent.p, 0xff, sizeof(int32_t) * nb, s));
+        HIPCK(hipGetLastError());
+        L.h_key = to_host(L.key.p, nb, s);
+        L.h_begin = to_host(L.begin.p, nb, s);
+        L.h_count = to_host(L.count.p, nb, s);
+        L.h_parent = to_host(L.parent.p, nb, s);
+    }
+    // duplicates make log and 1/r singular
+    if (H.kern.kind == H2D_K_LOG || H.kern.kind == H2D_K_INVR) {
+        Level& LL = H.lev[kappa];
+        HIPCK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        k_dups<<<(unsigned)LL.nbox, 256, 0, s>>>(H.xyt.p, LL.begin.p, LL.count.p, (int32_t)LL.nbox, bad.p);
+        HIPCK(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        if (hbad) fail(H2D_EDUP, "two distinct points coincide; the kernel is singular at r = 0");
+    }
+    // near lists at the leaf level
+    {
+        Level& LL = H.lev[kappa];
+        int32_t nb = (int32_t)LL.nbox;
+        int gb = (nb + T - 1) / T;
+        DBuf<int32_t> cnt, ptr, src;
+        cnt.alloc(nb); ptr.alloc(nb + 1);
+        k_near<<<gb, T, 0, s>>>(LL.key.p, nb, kappa, cnt.p, nullptr, nullptr);
+        int64_t tot = scan_excl(cnt.p, ptr.p, nb, s);
+        src.alloc(tot);
+        k_near<<<gb, T, 0, s>>>(LL.key.p, nb, kappa, cnt.p, ptr.p, src.p);
+        HIPCK(hipGetLastError());
+        H.h_near_ptr = to_host(ptr.p, nb, s);
+        H.h_near_ptr.push_back((int32_t)tot);
+        H.h_near_src = to_host(src.p, tot, s);
+    }
+    // interaction lists per level, concatenated in (level, target, source) order
+    H.h_il_level.clear(); H.h_il_tgt.clear(); H.h_il_src.clear();
+    H.lev[0].h_il_ptr.assign(H.lev[0].nbox + 1, 0);
+    for (int l = 1; l <= kappa; ++l) {
+        Level& L = H.lev[l];
+        int32_t nb = (int32_t)L.nbox;
+        int gb = (nb + T - 1) / T;
+        DBuf<int32_t> cnt, ptr, src;
+        cnt.alloc(nb); ptr.alloc(nb + 1);
+        k_il<<<gb, T, 0, s>>>(L.key.p, nb, l, cnt.p, nullptr, nullptr);
+        int64_t tot = scan_excl(cnt.p, ptr.p, nb, s);
+        src.alloc(tot);
+        k_il<<<gb, T, 0, s>>>(L.key.p, nb, l, cnt.p, ptr.p, src.p);
+        HIPCK(hipGetLastError());
+        auto hp = to_host(ptr.p, nb, s);
+        auto hs = to_host(src.p, tot, s);
+        int64_t base = (int64_t)H.h_il_tgt.size();
+        L.h_il_ptr.resize(nb + 1);
+        for (int32_t b = 0; b < nb; ++b) {
+            L.h_il_ptr[b] = (int32_t)(base + hp[b]);
+            int32_t e = (b + 1 < nb) ? hp[b + 1] : (int32_t)tot;
+            for (int32_t q = hp[b]; q < e; ++q) {
+                H.h_il_level.push_back(l);
+                H.h_il_tgt.push_back(b);
+                H.h_il_src.push_back(hs[q]);
+            }
+        }
+        L.h_il_ptr[nb] = (int32_t)(base + tot);
+    }
+    H.n_il = (int64_t)H.h_il_tgt.size();
+}
+
+// ---------------------------------------------------------------------
+// Adaptive cross approximation, one workgroup per block
+// ---------------------------------------------------------------------
+constexpr int kAcaThreads = 256;
+
+struct AcaJob {
+    int32_t row0, m, col0, n;
+    int32_t kcap, pad;
+    int64_t uoff, voff, foff;   // scratch: U (m x kcap col-major), V (n x kcap col-major), flags (m + n bytes)
+};
+
+struct ArgMax { double v; int32_t i; };
+
+// larger |value| wins; equal values: lower index wins
+__device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b)
+{
+    if (b.v > a.v || (b.v == a.v && b.i >= 0 && (a.i < 0 || b.i < a.i))) return b;
+    return a;
+}
+
+__device__ ArgMax block_argmax(ArgMax a, double* lv, int32_t* li)
+{
+    int t = threadIdx.x;
+    lv[t] = a.v; li[t] = a.i;
+    __syncthreads();
+    for (int d = kAcaThreads / 2; d > 0; d >>= 1) {
+        if (t < d) {
+            ArgMax x{lv[t], li[t]}, y{lv[t + d], li[t + d]};
+            ArgMax z = better(x, y);
+            lv[t] = z.v; li[t] = z.i;
+        }
+        __syncthreads();
+    }
+    ArgMax r{lv[0], li[0]};
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_sum(double v, double* lv)
+{
+    int t = threadIdx.x;
+    lv[t] = v;
+    __syncthreads();
+    for (int d = kAcaThreads / 2; d > 0; d >>= 1) {
+        if (t < d) lv[t] += lv[t + d];
+        __syncthreads();
+    }
+    double r = lv[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Partial-pivot ACA of K(tree rows row0.., tree cols col0..).  Each step:
+// residual row at pivot row i -> pivot column j* (largest |r|, lowest index
+// on ties, among unused columns) -> v = r / r_j* -> residual column u at
+// j* -> update |S|_F^2 -> stop when |u||v| <= tol |S|_F.  The next pivot row
+// is the unused row with the largest |u|.  A zero residual row is skipped.
+// The block is stored dense once k (m + n) >= m n (smaller and exact).
+// kind_out: 0 low rank, 1 dense, -1 rank cap reached.
+__global__ void __launch_bounds__(kAcaThreads)
+k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double* Uw, double* Vw, uint8_t* flags,
+      int32_t* kind_out, int32_t* rank_out)
+{
+    __shared__ double lv[kAcaThreads];
+    __shared__ int32_t li[kAcaThreads];
+    __shared__ double row[kAcaRankCap];    // U(i, :) or V(j*, :)
+    __shared__ double ab[2][kAcaRankCap];  // cross-term dot products
+    const AcaJob J = jobs[blockIdx.x];
+    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
+    const int32_t m = J.m, n = J.n, kcap = J.kcap;
+    double* U = Uw + J.uoff;
+    double* V = Vw + J.voff;
+    uint8_t* usedR = flags + J.foff;
+    uint8_t* usedC = usedR + m;
+    const double* P = xyt;
+    for (int32_t e = t; e < m + n; e += kAcaThreads) usedR[e] = 0;
+    __syncthreads();
+    int32_t k = 0, i = 0, nusedR = 0, kind = kLowRank;
+    double S2 = 0.0;
+    if (m == 0 || n == 0) { if (t == 0) { kind_out[blockIdx.x] = kLowRank; rank_out[blockIdx.x] = 0; } return; }
+    for (;;) {
+        // U(i, 0..k)
+        for (int q = t; q < k; q += kAcaThreads) row[q] = U[(int64_t)q * m + i];
+        if (t == 0 && !usedR[i]) usedR[i] = 1;
+        __syncthreads();
+        nusedR = 0;   // recount below only when needed
+        const double tx = P[2 * (J.row0 + i)], ty = P[2 * (J.row0 + i) + 1];
+        double* r = V + (int64_t)k * n;   // residual row stored in column k of V
+        ArgMax best{-1.0, -1};
+        for (int32_t j = t; j < n; j += kAcaThreads) {
+            double s = kernel_entry(kp, tx, ty, P[2 * (J.col0 + j)], P[2 * (J.col0 + j) + 1],
+                                    J.row0 + i == J.col0 + j);
+            for (int q = 0; q < k; ++q) s -= row[q] * V[(int64_t)q * n + j];
+            r[j] = s;
+            if (!usedC[j]) best = better(best, ArgMax{fabs(s), j});
+        }
+        best = block_argmax(best, lv, li);
+        const int32_t js = best.i;
+        if (js < 0) break;
+        const double delta = r[js];   // written by the thread owning js; visible after the barrier above
+        if (delta == 0.0) {
+            // zero residual row: mark it used and move to the lowest unused row
+            ArgMax nxt{-1.0, -1};
+            for (int32_t ii = t; ii < m; ii += kAcaThreads)
+                if (!usedR[ii]) nxt = better(nxt, ArgMax{0.0, ii});
+            nxt = block_argmax(nxt, lv, li);
+            if (nxt.i < 0) break;
+            i = nxt.i;
+            continue;
+        }
+        for (int32_t j = t; j < n; j += kAcaThreads) r[j] = r[j] / delta;
+        for (int q = t; q < k; q += kAcaThreads) row[q] = V[(int64_t)q * n + js];
+        __syncthreads();
+        double* u = U + (int64_t)k * m;
+        const double sx = P[2 * (J.col0 + js)], sy = P[2 * (J.col0 + js) + 1];
+        double uu = 0.0, vv = 0.0;
+        for (int32_t ii = t; ii < m; ii += kAcaThreads) {
+            double s = kernel_entry(kp, P[2 * (J.row0 + ii)], P[2 * (J.row0 + ii) + 1], sx, sy,
+                                    J.row0 + ii == J.col0 + js);
+            for (int q = 0; q < k; ++q) s -= U[(int64_t)q * m + ii] * row[q];
+            u[ii] = s;
+            uu += s * s;
+        }
+        for (int32_t j = t; j < n; j += kAcaThreads) vv += r[j] * r[j];
+        if (t == 0) usedC[js] = 1;
+        __syncthreads();
+        uu = block_sum(uu, lv);
+        vv = block_sum(vv, lv);
+        // cross terms (U(:, q) . u) (V(:, q) . v), one wave per q
+        for (int q = wave; q < k; q += kAcaThreads / kWave) {
+            double a = 0.0, b = 0.0;
+            for (int32_t ii = lane; ii < m; ii += kWave) a += U[(int64_t)q * m + ii] * u[ii];
+            for (int32_t j = lane; j < n; j += kWave) b += V[(int64_t)q * n + j] * r[j];
+            a = wave_sum(a);
+            b = wave_sum(b);
+            if (lane == 0) { ab[0][q] = a; ab[1][q] = b; }
+        }
+        __syncthreads();
+        double cross = 0.0;
+        for (int q = 0; q < k; ++q) cross += ab[0][q] * ab[1][q];
+        S2 += 2.0 * cross + uu * vv;
+        ++k;
+        if ((int64_t)k * (m + n) >= (int64_t)m * n) { kind = kDense; break; }
+        if (sqrt(uu) * sqrt(vv) <= tol * sqrt(S2)) break;
+        if (k >= kcap) { kind = -1; break; }
+        ArgMax nxt{-1.0, -1};
+        for (int32_t ii = t; ii < m; ii += kAcaThreads)
+            if (!usedR[ii]) nxt = better(nxt, ArgMax{fabs(u[ii]), ii});
+        nxt = block_argmax(nxt, lv, li);
+        if (nxt.i < 0) break;
+        i = nxt.i;
+    }
+    (void)nusedR;
+    if (t == 0) { kind_out[blockIdx.x] = kind; rank_out[blockIdx.x] = k; }
+}
+
+// Copy converged factors out of the scratch: U (m x k col-major) as is,
+// V transposed to row-major n x k.
+struct PackJob {
+    int64_t su, sv;     // scratch offsets
+    int64_t du, dv;     // destination offsets
+    int32_t m, n, k, pad;
+};
+
+__global__ void k_pack(const PackJob* jobs, const double* Uw, const double* Vw, double* Uo, double* Vo)
+{
+    const PackJob J = jobs[blockIdx.x];
+    for (int64_t e = threadIdx.x; e < (int64_t)J.m * J.k; e += blockDim.x) Uo[J.du + e] = Uw[J.su + e];
+    for (int64_t e = threadIdx.x; e < (int64_t)J.n * J.k; e += blockDim.x) {
+        int64_t j = e / J.k, q = e % J.k;
+        Vo[J.dv + e] = Vw[J.sv + q * J.n + j];
+    }
+}
+
+// Dense blocks: D (m x n column-major) = K(rows, cols) with the diagonal
+// rule where the tree indices coincide.
+struct DenseJob {
+    int64_t off;
+    int32_t row0, m, col0, n;
+};
+
+__global__ void k_dense(const DenseJob* jobs, const double* xyt, KernelParams kp, double* D)
+{
+    const DenseJob J = jobs[blockIdx.x];
+    for (int64_t e = threadIdx.x; e < (int64_t)J.m * J.n; e += blockDim.x) {
+        int32_t j = (int32_t)(e / J.m), i = (int32_t)(e % J.m);
+        D[J.off + e] = kernel_entry(kp, xyt[2 * (J.row0 + i)], xyt[2 * (J.row0 + i) + 1], xyt[2 * (J.col0 + j)],
+                                    xyt[2 * (J.col0 + j) + 1], J.row0 + i == J.col0 + j);
+    }
+}
+
+template <typename T>
+static void upload(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
+{
+    d.alloc(h.size());
+    if (!h.empty()) HIPCK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+void build_factors(Handle& H, hipStream_t s)
+{
+    const int kappa = H.kappa;
+    const int64_t nil = H.n_il;
+    H.h_il_kind.assign(nil, kLowRank);
+    H.h_il_k.assign(nil, 0);
+    std::vector<int32_t> m(nil), n(nil), r0(nil), c0(nil);
+    for (int64_t b = 0; b < nil; ++b) {
+        const Level& L = H.lev[H.h_il_level[b]];
+        m[b] = L.h_count[H.h_il_tgt[b]];
+        n[b] = L.h_count[H.h_il_src[b]];
+        r0[b] = L.h_begin[H.h_il_tgt[b]];
+        c0[b] = L.h_begin[H.h_il_src[b]];
+    }
+    // scratch budget per ACA chunk
+    size_t freeb = 0, totalb = 0;
+    HIPCK(hipMemGetInfo(&freeb, &totalb));
+    const double budget = std::max(1.0e9, std::min(16.0e9, 0.25 * (double)freeb));
+    struct Chunk { int64_t b0, b1; DBuf<double> U, V; int64_t ue = 0, ve = 0; };
+    std::vector<Chunk> chunks;
+    int64_t b = 0;
+    while (b < nil) {
+        std::vector<AcaJob> jobs;
+        int64_t uo = 0, vo = 0, fo = 0;
+        double bytes = 0;
+        int64_t b1 = b;
+        while (b1 < nil) {
+            int64_t mm = m[b1], nn = n[b1];
+            int64_t kc = (mm * nn + mm + nn - 1) / (mm + nn);
+            kc = std::min<int64_t>(kc, kAcaRankCap);
+            double need = 8.0 * (double)(mm + nn) * (double)kc + (double)(mm + nn);
+            if (b1 > b && (bytes + need > budget || jobs.size() >= 200000)) break;
+            AcaJob J{r0[b1], m[b1], c0[b1], n[b1], (int32_t)kc, 0, uo, vo, fo};
+            jobs.push_back(J);
+            uo += mm * kc; vo += nn * kc; fo += mm + nn;
+            bytes += need;
+            ++b1;
+        }
+        DBuf<AcaJob> djobs;
+        DBuf<double> Uw, Vw;
+        DBuf<uint8_t> fl;
+        DBuf<int32_t> kind, rank;
+        upload(djobs, jobs, s);
+        Uw.alloc(std::max<int64_t>(uo, 1)); Vw.alloc(std::max<int64_t>(vo, 1)); fl.alloc(std::max<int64_t>(fo, 1));
+        kind.alloc(jobs.size()); rank.alloc(jobs.size());
+        KernelParams kp = H.kern;
+        k_aca<<<(unsigned)jobs.size(), kAcaThreads, 0, s>>>(djobs.p, H.xyt.p, kp, H.tol, Uw.p, Vw.p, fl.p, kind.p,
+                                                              rank.p);
+        HIPCK(hipGetLastError());
+        auto hk = to_host(kind.p, jobs.size(), s);
+        auto hr = to_host(rank.p, jobs.size(), s);
+        Chunk C;
+        C.b0 = b; C.b1 = b1;
+        std::vector<PackJob> packs;
+        for (size_t q = 0; q < jobs.size(); ++q) {
+            int64_t bb = b + (int64_t)q;
+            if (hk[q] < 0)
+                fail(H2D_ENOCONV, "ACA reached its rank cap of " + std::to_string(kAcaRankCap) + " on a " +
+                                      std::to_string(m[bb]) + " x " + std::to_string(n[bb]) + " block");
+            H.h_il_kind[bb] = hk[q];
+            H.h_il_k[bb] = hr[q];
+            if (hk[q] == kLowRank && hr[q] > 0) {
+                packs.push_back(PackJob{jobs[q].uoff, jobs[q].voff, C.ue, C.ve, m[bb], n[bb], hr[q], 0});
+                C.ue += (int64_t)m[bb] * hr[q];
+                C.ve += (int64_t)n[bb] * hr[q];
+            }
+        }
+        C.U.alloc(std::max<int64_t>(C.ue, 1));
+        C.V.alloc(std::max<int64_t>(C.ve, 1));
+        if (!packs.empty()) {
+            DBuf<PackJob> dp;
+            upload(dp, packs, s);
+            k_pack<<<(unsigned)packs.size(), 256, 0, s>>>(dp.p, Uw.p, Vw.p, C.U.p, C.V.p);
+            HIPCK(hipGetLastError());
+            HIPCK(hipStreamSynchronize(s));
+        }
+        chunks.push_back(std::move(C));
+        b = b1;
+    }
+    // final pools: U, V for low-rank blocks in table order; D for near
+    // blocks (leaf order) then dense IL blocks
+    H.h_il_off.assign(nil, 0);
+    H.h_il_voff.assign(nil, 0);
+    int64_t ue = 0, ve = 0, de = 0;
+    const Level& LL = H.lev[kappa];
+    int64_t nnear = (int64_t)H.h_near_src.size();
+    H.h_near_off.assign(nnear, 0);
+    std::vector<DenseJob> dj;
+    for (int64_t x = 0; x < LL.nbox; ++x)
+        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+            int32_t y = H.h_near_src[q];
+            H.h_near_off[q] = de;
+            dj.push_back(DenseJob{de, LL.h_begin[x], LL.h_count[x], LL.h_begin[y], LL.h_count[y]});
+            de += (int64_t)LL.h_count[x] * LL.h_count[y];
+        }
+    for (int64_t q = 0; q < nil; ++q) {
+        if (H.h_il_kind[q] == kDense) {
+            H.h_il_off[q] = de;
+            dj.push_back(DenseJob{de, r0[q], m[q], c0[q], n[q]});
+            de += (int64_t)m[q] * n[q];
+        } else {
+            H.h_il_off[q] = ue;
+            H.h_il_voff[q] = ve;
+            ue += (int64_t)m[q] * H.h_il_k[q];
+            ve += (int64_t)n[q] * H.h_il_k[q];
+        }
+    }
+    H.u_elems = ue; H.v_elems = ve; H.d_elems = de;
+    H.U64.alloc(std::max<int64_t>(ue, 1));
+    H.V64.alloc(std::max<int64_t>(ve, 1));
+    H.D64.alloc(std::max<int64_t>(de, 1));
+    int64_t uu = 0, vv = 0;
+    for (auto& C : chunks) {
+        if (C.ue) HIPCK(hipMemcpyAsync(H.U64.p + uu, C.U.p, sizeof(double) * C.ue, hipMemcpyDeviceToDevice, s));
+        if (C.ve) HIPCK(hipMemcpyAsync(H.V64.p + vv, C.V.p, sizeof(double) * C.ve, hipMemcpyDeviceToDevice, s));
+        uu += C.ue; vv += C.ve;
+    }
+    if (!dj.empty()) {
+        DBuf<DenseJob> d;
+        upload(d, dj, s);
+        for (size_t o = 0; o < dj.size(); o += 1u << 20) {
+            unsigned cnt = (unsigned)std::min<size_t>(1u << 20, dj.size() - o);
+            k_dense<<<cnt, 256, 0, s>>>(d.p + o, H.xyt.p, H.kern, H.D64.p);
+        }
+        HIPCK(hipGetLastError());
+    }
+    HIPCK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------
+// Half-precision copies: per-block power-of-two scale so that FP16 cannot
+// overflow; V (|v| <= 1 by construction) is stored unscaled; the diagonal
+// of the self blocks is held apart in FP32 (the log kernel's diagonal N can
+// exceed the FP16 range).
+// ---------------------------------------------------------------------
+struct HalfJob {
+    int64_t off;        // pool offset (U or D)
+    int64_t cnt;        // elements
+    int32_t m, self;    // rows (for the diagonal), 1 if a self block
+    int32_t row0, pad;
+};
+
+template <typename T>
+__device__ __forceinline__ T to_half(float v);
+template <>
+__device__ __forceinline__ __half to_half<__half>(float v) { return __float2half_rn(v); }
+template <>
+__device__ __forceinline__ __hip_bfloat16 to_half<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+
+template <typename T>
+__global__ void k_half_blocks(const HalfJob* jobs, const double* src, T* dst, float* scale, float* diag)
+{
+    __shared__ double lv[256];
+    const HalfJob J = jobs[blockIdx.x];
+    double mx = 0.0;
+    for (int64_t e = threadIdx.x; e < J.cnt; e += blockDim.x) {
+        bool d = J.self && (e % J.m) == (e / J.m);
+        if (!d) mx = fmax(mx, fabs(src[J.off + e]));
+    }
+    lv[threadIdx.x] = mx;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) lv[threadIdx.x] = fmax(lv[threadIdx.x], lv[threadIdx.x + d]);
+        __syncthreads();
+    }
+    mx = lv[0];
+    int ex = 0;
+    if (mx > 0.0) frexp(mx, &ex);
+    const double sc = ldexp(1.0, ex);     // mx / sc in [0.5, 1)
+    const double inv = 1.0 / sc;
+    if (threadIdx.x == 0) scale[blockIdx.x] = (float)sc;
+    for (int64_t e = threadIdx.x; e < J.cnt; e += blockDim.x) {
+        int64_t i = e % J.m;
+        bool d = J.self && i == (e / J.m);
+        double v = src[J.off + e];
+        dst[J.off + e] = to_half<T>(d ? 0.0f : (float)(v * inv));
+        if (d) diag[J.row0 + i] = (float)v;
+    }
+}
+
+template <typename T>
+__global__ void k_half_plain(const double* src, T* dst, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = to_half<T>((float)src[e]);
+}
+
+void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
+{
+    const bool f16 = mask & H2D_PREC_BIT(H2D_P_FP16), b16 = mask & H2D_PREC_BIT(H2D_P_BF16);
+    if (!f16 && !b16) return;
+    // jobs: IL blocks (U or D) in table order, then near blocks
+    std::vector<HalfJob> jobs;
+    for (int64_t q = 0; q < H.n_il; ++q) {
+        const Level& L = H.lev[H.h_il_level[q]];
+        int32_t mm = L.h_count[H.h_il_tgt[q]], nn = L.h_count[H.h_il_src[q]];
+        int64_t cnt = H.h_il_kind[q] == kDense ? (int64_t)mm * nn : (int64_t)mm * H.h_il_k[q];
+        jobs.push_back(HalfJob{H.h_il_off[q], cnt, mm, 0, 0, 0});
+    }
+    const Level& LL = H.lev[H.kappa];
+    for (int64_t x = 0; x < LL.nbox; ++x)
+        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+            int32_t y = H.h_near_src[q];
+            jobs.push_back(HalfJob{H.h_near_off[q], (int64_t)LL.h_count[x] * LL.h_count[y], LL.h_count[x],
+                                   y == (int32_t)x ? 1 : 0, LL.h_begin[x], 0});
+        }
+    // U and D pools need per-block scales; split the jobs per pool
+    std::vector<HalfJob> ujobs, djobs;
+    std::vector<int64_t> uidx, didx;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        bool dense = (q >= (size_t)H.n_il) || H.h_il_kind[q] == kDense;
+        (dense ? djobs : ujobs).push_back(jobs[q]);
+        (dense ? didx : uidx).push_back((int64_t)q);
+    }
+    DBuf<HalfJob> du, dd;
+    upload(du, ujobs, s);
+    upload(dd, djobs, s);
+    DBuf<float> su, sd;
+    su.alloc(std::max<size_t>(ujobs.size(), 1));
+    sd.alloc(std::max<size_t>(djobs.size(), 1));
+    H.diag32.alloc(H.n);
+    HIPCK(hipMemsetAsync(H.diag32.p, 0, sizeof(float) * H.n, s));
+    auto run = [&](auto* Up, auto* Vp, auto* Dp) {
+        using T = std::remove_pointer_t<decltype(Up)>;
+        for (size_t o = 0; o < ujobs.size(); o += 1u << 20) {
+            unsigned c = (unsigned)std::min<size_t>(1u << 20, ujobs.size() - o);
+            k_half_blocks<T><<<c, 256, 0, s>>>(du.p + o, H.U64.p, Up, su.p + o, H.diag32.p);
+        }
+        for (size_t o = 0; o < djobs.size(); o += 1u << 20) {
+            unsigned c = (unsigned)std::min<size_t>(1u << 20, djobs.size() - o);
+            k_half_blocks<T><<<c, 256, 0, s>>>(dd.p + o, H.D64.p, Dp, sd.p + o, H.diag32.p);
+        }
+        k_half_plain<T><<<4096, 256, 0, s>>>(H.V64.p, Vp, H.v_elems);
+        HIPCK(hipGetLastError());
+    };
+    if (f16) {
+        H.U16.alloc(std::max<int64_t>(H.u_elems, 1));
+        H.V16.alloc(std::max<int64_t>(H.v_elems, 1));
+        H.D16.alloc(std::max<int64_t>(H.d_elems, 1));
+        run(H.U16.p, H.V16.p, H.D16.p);
+    }
+    if (b16) {
+        H.Ub16.alloc(std::max<int64_t>(H.u_elems, 1));
+        H.Vb16.alloc(std::max<int64_t>(H.v_elems, 1));
+        H.Db16.alloc(std::max<int64_t>(H.d_elems, 1));
+        run(H.Ub16.p, H.Vb16.p, H.Db16.p);
+    }
+    // one scale per IL block then per near block (table order)
+    auto hsu = to_host(su.p, ujobs.size(), s);
+    auto hsd = to_host(sd.p, djobs.size(), s);
+    std::vector<float> sc(jobs.size(), 1.0f);
+    for (size_t q = 0; q < uidx.size(); ++q) sc[uidx[q]] = hsu[q];
+    for (size_t q = 0; q < didx.size(); ++q) sc[didx[q]] = hsd[q];
+    upload(H.scale16, sc, s);
+    HIPCK(hipStreamSynchronize(s));
+    H.prec_mask |= mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16));
+}
+
+}  // namespace h2d

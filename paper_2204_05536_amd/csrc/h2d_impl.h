@@ -1,0 +1,230 @@
+// Internal declarations of the HODLR2D library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/h2d.h"
+
+namespace h2d {
+
+constexpr int kMaxLevel = 16;      // Morton keys are 2 x 16 bits
+constexpr int kWave = 64;
+constexpr int kAcaRankCap = 256;   // ACA scratch columns per block
+constexpr int kPhaseARows = 512;   // V rows per phase-A work item
+
+// Error carried from deep inside the library to the C ABI.
+struct Error {
+    h2d_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(h2d_status code, const std::string& msg);
+void check_hip(hipError_t e, const char* what, const char* file, int line);
+#define HIPCK(x) ::h2d::check_hip((x), #x, __FILE__, __LINE__)
+
+// Block kinds.
+enum : int32_t { kLowRank = 0, kDense = 1 };
+
+// Device buffer with RAII.
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) { reset(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { reset(); }
+    void alloc(size_t count)
+    {
+        reset();
+        if (count == 0) return;
+        hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(H2D_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        n = count;
+    }
+    void reset()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// Per-level box table (tree order).  Device arrays, host mirrors.
+struct Level {
+    int64_t nbox = 0;
+    DBuf<uint32_t> key;       // Morton key, ascending
+    DBuf<int32_t> begin;      // first point (tree order)
+    DBuf<int32_t> count;      // points in the box
+    DBuf<int32_t> parent;     // box index at level - 1
+    DBuf<int32_t> il_ptr;     // CSR into the IL block table (nbox + 1), absolute block index
+    std::vector<uint32_t> h_key;
+    std::vector<int32_t> h_begin, h_count, h_parent, h_il_ptr;
+};
+
+// Phase-B block descriptor: the rows of one target box read as
+// base[q * ld + r] (column-major, ld = target box size), q < |cols|.
+//   cols > 0: low rank, base = U pool + off, the multiplier vector is
+//             t pool + tsrc (k = cols entries)
+//   cols < 0: dense, base = D pool + off, multiplier = x (tree order)
+//             + tsrc (n = -cols entries)
+struct BDesc {
+    int64_t off;
+    int32_t cols;
+    int32_t tsrc;
+};
+
+// Phase-A work item: t(out) = V(rows j0..j1)^T x(col0 + j0 .. col0 + j1).
+// V is row-major n x k starting at V pool + voff.
+struct ADesc {
+    int64_t voff;     // element offset of row 0 of the block's V
+    int32_t j0, j1;   // row range of this item
+    int32_t col0;     // first tree column of the source box
+    int32_t k;        // rank
+    int32_t out;      // t pool offset (whole block) or partial pool offset
+    int32_t pad;
+};
+
+// Blocks whose phase-A work was split: t = sum of consecutive partials.
+struct RDesc {
+    int32_t tout;     // t pool offset
+    int32_t k;
+    int32_t pbeg;     // first partial offset
+    int32_t nparts;   // partials, each k long, stored consecutively
+};
+
+struct KernelParams {
+    int32_t kind;
+    int32_t diag_mode;
+    double c;
+    double diag_value;
+};
+
+struct Handle {
+    int device = 0;
+    int64_t n = 0;
+    int32_t kappa = 0, leaf_max = 0;
+    double R = 1.0, tol = 0.0;
+    KernelParams kern{};
+    uint32_t prec_mask = 1;
+    double build_seconds = 0.0;
+
+    DBuf<double> xy;        // caller order, n x 2
+    DBuf<double> xyt;       // tree order, n x 2
+    DBuf<int32_t> perm;     // tree position -> caller index
+    std::vector<int32_t> h_perm;
+    std::vector<double> h_xy;
+    Level lev[kMaxLevel + 1];
+
+    // near field (leaf level): CSR by target leaf box
+    DBuf<int32_t> near_ptr;
+    std::vector<int32_t> h_near_ptr, h_near_src;
+    std::vector<int64_t> h_near_off;  // D pool offsets
+
+    // interaction-list block table, (level, tgt, src) order
+    int64_t n_il = 0;
+    std::vector<int32_t> h_il_level, h_il_tgt, h_il_src, h_il_kind, h_il_k;
+    std::vector<int64_t> h_il_off;    // U pool offset (low rank) or D pool offset (dense)
+    std::vector<int64_t> h_il_voff;   // V pool offset (low rank)
+    std::vector<int32_t> h_il_toff;   // t pool offset (low rank)
+
+    // factor pools (element offsets are shared by every precision)
+    int64_t u_elems = 0, v_elems = 0, d_elems = 0, t_elems = 0, p_elems = 0;
+    DBuf<double> U64, V64, D64;
+    DBuf<__half> U16, V16, D16;
+    DBuf<__hip_bfloat16> Ub16, Vb16, Db16;
+    DBuf<float> scale16;     // per-block scale of the half pools (IL blocks, then near blocks)
+    DBuf<float> diag32;      // self-block diagonal (tree order) for the half pools
+    int64_t max_rank = 0, sum_rank = 0, n_il_dense = 0;
+
+    // matvec schedule
+    DBuf<BDesc> bnear, bil;  // phase-B descriptors: near blocks, IL blocks
+    DBuf<ADesc> aitems;
+    DBuf<RDesc> ritems;
+    int64_t n_aitems = 0, n_ritems = 0;
+    DBuf<int32_t> leaf_order;   // phase-B tiles: leaf box indices, XCD-aware order
+
+    // work vectors
+    DBuf<double> xs, tpool, ppool;    // FP64: x in tree order, t, partials
+    DBuf<float> xs32, tpool32, ppool32;
+    int64_t ws_nrhs = 0;
+
+    double alg_bytes_fp64 = 0, alg_bytes_half = 0, flops = 0;
+};
+
+// kernels.hip
+void finalize(Handle& H, hipStream_t s);
+void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s);
+void ensure_workspace(Handle& H, int nrhs);
+
+// build.hip
+void build_tree_and_lists(Handle& H, hipStream_t s);
+void build_factors(Handle& H, hipStream_t s);
+void make_half_pools(Handle& H, uint32_t mask, hipStream_t s);
+
+// solve.hip
+h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_solve_opts& o,
+                 h2d_solve_info* info, hipStream_t s);
+
+// ---------------------------------------------------------------------
+// Kernel function on the device (same definitions as the public header).
+// ---------------------------------------------------------------------
+__device__ __forceinline__ double phi_radial(const KernelParams& k, double r)
+{
+    switch (k.kind) {
+    case H2D_K_LOG: return log(r);
+    case H2D_K_INVR: return 1.0 / r;
+    case H2D_K_MQ: { double s = r / k.c; return sqrt(1.0 + s * s); }
+    case H2D_K_GAUSS: { double s = r / k.c; return exp(-(s * s)); }
+    case H2D_K_PHI1: {
+        double a = k.c;
+        if (r >= a) return log(r) / log(a);
+        double rl = (r > 0.0) ? r * log(r) : 0.0;
+        return (rl - 1.0) / (a * log(a) - 1.0);
+    }
+    case H2D_K_PHI2: { double a = k.c; return (r >= a) ? a / r : r / a; }
+    default: return 0.0;
+    }
+}
+
+// Entry between target point (tx, ty) and source point (sx, sy); `same`
+// is true when both are the same point index (the diagonal).
+__device__ __forceinline__ double kernel_entry(const KernelParams& k, double tx, double ty, double sx,
+                                               double sy, bool same)
+{
+    if (k.kind == H2D_K_SEP) {
+        double a = 1.3 * tx + 0.7 * ty, b = 0.9 * sx - 1.1 * sy, v = 0.0;
+        int rank = (int)k.c;
+        for (int q = 0; q < rank; ++q) v += cos(q * a) * cos(q * b);
+        if (same) {
+            if (k.diag_mode == H2D_DIAG_REPLACE) return k.diag_value;
+            if (k.diag_mode == H2D_DIAG_ADD) return v + k.diag_value;
+        }
+        return v;
+    }
+    if (same) {
+        if (k.diag_mode == H2D_DIAG_REPLACE) return k.diag_value;
+        if (k.diag_mode == H2D_DIAG_ADD) return phi_radial(k, 0.0) + k.diag_value;
+        return phi_radial(k, 0.0);
+    }
+    double dx = tx - sx, dy = ty - sy;
+    return phi_radial(k, sqrt(dx * dx + dy * dy));
+}
+
+}  // namespace h2d

@@ -1,0 +1,191 @@
+"""Python binding of the HODLR2D C ABI (include/h2d.h).
+
+Argument marshalling only: every step of build, matvec and solve runs in the
+HIP library ``libh2d.so``.  Device memory and streams come from PyTorch
+(ROCm); tensors are passed to the library as raw device pointers together
+with the current stream.  The library must have been built (``build()`` in
+``__graft_entry__`` or ``python -m paper_2204_05536_amd.build``); there is
+no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # loads the ROCm HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2d.so")
+
+# enums mirrored from include/h2d.h
+H2D_OK, H2D_EINVAL, H2D_ENOMEM, H2D_EDEVICE, H2D_EDUP, H2D_ENOCONV, H2D_EUNSUPPORTED, H2D_EDEPTH = range(8)
+KINDS = {"log": 0, "invr": 1, "mq": 2, "gauss": 3, "phi1": 4, "phi2": 5, "sep": 6}
+DIAG = {"replace": 0, "add": 1, "formula": 2}
+PREC = {"fp64": 0, "fp16": 1, "bf16": 2}
+SOLVE_PLAIN, SOLVE_REFINE = 0, 1
+
+EXPORTED = ["h2d_build", "h2d_matvec", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
+            "h2d_destroy", "h2d_last_error"]
+
+
+class H2DError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"h2d status {code}: {msg}")
+        self.code = code
+
+
+class h2d_kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("diag_mode", C.c_int32), ("c", C.c_double), ("diag_value", C.c_double)]
+
+
+class h2d_solve_opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32), ("inner_prec", C.c_int32),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("pad", C.c_int32)]
+
+
+class h2d_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("relres", C.c_double), ("seconds", C.c_double)]
+
+
+class h2d_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("kappa", C.c_int32), ("leaf_max", C.c_int32), ("R", C.c_double),
+                ("tol", C.c_double), ("n_near", C.c_int64), ("n_il", C.c_int64), ("n_il_dense", C.c_int64),
+                ("max_rank", C.c_int64), ("sum_rank", C.c_int64), ("u_elems", C.c_int64), ("v_elems", C.c_int64),
+                ("d_elems", C.c_int64), ("alg_bytes_fp64", C.c_double), ("alg_bytes_half", C.c_double),
+                ("flops", C.c_double), ("build_seconds", C.c_double), ("prec_mask", C.c_uint32),
+                ("pad", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libh2d.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} missing (run paper_2204_05536_amd/build.py)")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.h2d_build.argtypes = [P, C.c_int64, C.POINTER(h2d_kernel), C.c_int32, C.c_double, C.c_uint32, P,
+                            C.POINTER(P)]
+    L.h2d_build.restype = C.c_int
+    L.h2d_matvec.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, P]
+    L.h2d_matvec.restype = C.c_int
+    L.h2d_solve.argtypes = [P, P, P, C.c_double, C.POINTER(h2d_solve_opts), C.POINTER(h2d_solve_info), P]
+    L.h2d_solve.restype = C.c_int
+    L.h2d_info.argtypes = [P, C.POINTER(h2d_stats)]
+    L.h2d_info.restype = C.c_int
+    L.h2d_export.argtypes = [P, C.c_char_p, C.c_uint32]
+    L.h2d_export.restype = C.c_int
+    L.h2d_import.argtypes = [C.c_char_p, C.c_uint32, P, C.POINTER(P)]
+    L.h2d_import.restype = C.c_int
+    L.h2d_destroy.argtypes = [P]
+    L.h2d_destroy.restype = None
+    L.h2d_last_error.argtypes = []
+    L.h2d_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != H2D_OK:
+        raise H2DError(st, load().h2d_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA/HIP tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def kernel_spec(spec: dict) -> h2d_kernel:
+    return h2d_kernel(KINDS[spec["kind"]], DIAG[spec.get("diag_mode", "formula")], float(spec.get("c", 0.0)),
+                      float(spec.get("diag_value", 0.0)))
+
+
+def prec_mask(*precs):
+    m = 1
+    for p in precs:
+        m |= 1 << PREC[p]
+    return m
+
+
+class HODLR2D:
+    """A built HODLR2D operator on the current GPU.
+
+    ``HODLR2D.build(xy, kernel, leaf_max, tol, precs)``: xy is an (N, 2)
+    float64 tensor on the GPU; kernel a dict (kind, c, diag_mode,
+    diag_value).  ``matvec(x)`` returns A_hat x, ``solve(b, tol)`` returns x.
+    """
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def build(cls, xy, kernel, leaf_max=64, tol=1e-10, precs=()):
+        L = load()
+        xy = xy.contiguous()
+        h = C.c_void_p()
+        k = kernel_spec(kernel)
+        _check(L.h2d_build(_dev_f64(xy, "xy"), xy.shape[0], C.byref(k), int(leaf_max), float(tol),
+                           prec_mask(*precs), _stream(), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def import_file(cls, path, precs=()):
+        L = load()
+        h = C.c_void_p()
+        _check(L.h2d_import(str(path).encode(), prec_mask(*precs), _stream(), C.byref(h)))
+        return cls(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().h2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        s = h2d_stats()
+        _check(load().h2d_info(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in h2d_stats._fields_ if f != "pad"}
+
+    @property
+    def n(self):
+        return self.info()["n"]
+
+    def matvec(self, x, prec="fp64", out=None):
+        """y = A_hat x.  x: (N,) or (nrhs, N) float64 on the GPU (row r is RHS r)."""
+        x = x.contiguous()
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        n = x.shape[-1]
+        y = torch.empty_like(x) if out is None else out
+        _check(load().h2d_matvec(self._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs, n, PREC[prec], _stream()))
+        return y
+
+    def solve(self, b, tol=1e-8, restart=50, max_iter=2500, mode="plain", inner_prec="fp16", inner_tol=1e-4,
+              max_outer=50):
+        b = b.contiguous()
+        x = torch.empty_like(b)
+        o = h2d_solve_opts(SOLVE_PLAIN if mode == "plain" else SOLVE_REFINE, int(restart), int(max_iter),
+                           PREC[inner_prec], float(inner_tol), int(max_outer), 0)
+        info = h2d_solve_info()
+        st = load().h2d_solve(self._h, _dev_f64(b, "b"), _dev_f64(x, "x"), float(tol), C.byref(o), C.byref(info),
+                              _stream())
+        if st not in (H2D_OK, H2D_ENOCONV):
+            _check(st)
+        return x, {"iters": info.iters, "outer": info.outer, "relres": info.relres, "seconds": info.seconds,
+                   "converged": st == H2D_OK}
+
+    def export(self, path, factors=True):
+        _check(load().h2d_export(self._h, str(path).encode(), 1 if factors else 0))

@@ -15,6 +15,8 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def orc():
     import oracle
-    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+    lib = os.path.join(ROOT, "oracle", "liboracle.so")
+    src = os.path.join(ROOT, "oracle", "h2d_oracle.c")
+    if not os.path.exists(lib) or os.path.getmtime(src) > os.path.getmtime(lib):
         oracle.build()
     return oracle

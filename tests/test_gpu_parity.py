@@ -1,0 +1,174 @@
+"""GPU parity: the HIP library against the CPU oracle.
+
+  * tree, permutation, level tables and block lists: bit-exact;
+  * matvec on the oracle's own factors (imported): 1e-12 relative in FP64;
+  * GPU-built factors: the operator within the ACA tolerance of the dense
+    product, ranks close to the oracle's;
+  * bitwise repeatability (no atomics on the hot path).
+"""
+import numpy as np
+import pytest
+
+from paper_2204_05536_amd import inputs
+from tests import h2dfile, npref
+from tests.gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+MQ = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}
+GA = {"kind": "gauss", "c": 0.05, "diag_mode": "add", "diag_value": 1e-4}
+
+
+def _lib():
+    from paper_2204_05536_amd import hodlr2d
+    return hodlr2d
+
+
+def _cases():
+    rng = np.random.default_rng(100)
+    c = []
+    xy, b, k, leaf, tol = inputs.workload("log4096")
+    c.append(("log4096", xy, k, leaf, tol))
+    c.append(("mix3000_leaf16", inputs.gaussian_mixture(3000, rng), MQ, 16, 1e-10))
+    c.append(("disc5000_leaf32", inputs.uniform_disc(5000, rng), GA, 32, 1e-10))
+    c.append(("one_point", np.array([[0.3, -0.2]]), MQ, 64, 1e-10))
+    c.append(("single_leaf_64", rng.uniform(-1, 1, (64, 2)), MQ, 64, 1e-10))
+    c.append(("ragged_1337_leaf7", rng.uniform(-1, 1, (1337, 2)), MQ, 7, 1e-10))
+    # points on cell boundaries, on the top / right edge of B, and at 0
+    g = np.array([[-1.0, -1.0], [1.0, 1.0], [0.0, 0.0], [0.5, -0.5], [-0.5, 0.5], [1.0, -1.0], [-1.0, 1.0],
+                  [0.25, 0.75], [0.0, 1.0], [1.0, 0.0]])
+    c.append(("boundaries", np.concatenate([g, rng.uniform(-1, 1, (300, 2))]), MQ, 4, 1e-10))
+    c.append(("cheb_40x40_leaf25", inputs.chebyshev_grid(40), {"kind": "invr", "diag_mode": "replace",
+                                                                  "diag_value": 0.0}, 25, 1e-12))
+    return c
+
+
+CASES = _cases()
+
+
+def _compare_structure(F, O):
+    assert F["kappa"] == O.kappa
+    assert F["R"] == O.R
+    assert np.array_equal(F["perm"], O.perm())
+    for l in range(O.kappa + 1):
+        L = O.level(l)
+        for f in ("key", "begin", "count", "parent"):
+            assert np.array_equal(F["levels"][l][f].astype(np.int64), L[f].astype(np.int64)), (l, f)
+    t, s = O.near_table()
+    assert np.array_equal(F["near_tgt"], t) and np.array_equal(F["near_src"], s)
+    tab = O.il_table()
+    for f, g in (("il_level", "level"), ("il_tgt", "tgt"), ("il_src", "src")):
+        assert np.array_equal(F[f].astype(np.int64), tab[g].astype(np.int64)), f
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_structure_bit_exact(orc, tmp_path, case):
+    name, xy, k, leaf, tol = case
+    say("structure", name, xy.shape)
+    H = _lib().HODLR2D.build(dev(xy), k, leaf, tol)
+    p = tmp_path / "g.h2dx"
+    H.export(p, factors=False)
+    F = h2dfile.read(p)
+    O = orc.OracleH(xy, k, leaf, tol, factors=False)
+    _compare_structure(F, O)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_matvec_on_oracle_factors(orc, tmp_path, case):
+    """Identical H on both sides: only the summation order differs."""
+    name, xy, k, leaf, tol = case
+    say("import-matvec", name)
+    O = orc.OracleH(xy, k, leaf, tol)
+    p = tmp_path / "o.h2dx"
+    O.export(p)
+    H = _lib().HODLR2D.import_file(p)
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, xy.shape[0])
+    yo = O.matvec(x)
+    yg = host(H.matvec(dev(x)))
+    assert np.linalg.norm(yg - yo) <= 1e-12 * np.linalg.norm(yo)
+    assert np.max(np.abs(yg - yo)) <= 1e-12 * np.max(np.abs(yo))
+
+
+@pytest.mark.parametrize("case", CASES[:3] + CASES[5:], ids=[c[0] for c in CASES[:3] + CASES[5:]])
+def test_gpu_built_operator_accuracy(orc, tmp_path, case):
+    """GPU-built factors: |A_hat x - A x| within 20 tol of |A_off x|, the
+    oracle's own operator within the same bound, kinds equal and ranks
+    within +-3 of the oracle's."""
+    name, xy, k, leaf, tol = case
+    say("gpu-built", name)
+    H = _lib().HODLR2D.build(dev(xy), k, leaf, tol)
+    O = orc.OracleH(xy, k, leaf, tol)
+    x = np.random.default_rng(8).uniform(-1, 1, xy.shape[0])
+    A = npref.kernel_matrix(k, xy)
+    Aoff = A - np.diag(np.diag(A))
+    ref = np.linalg.norm(Aoff @ x)
+    yg = host(H.matvec(dev(x)))
+    yo = O.matvec(x)
+    bound = max(20 * tol, 1e-13) * ref
+    assert np.linalg.norm(yo - A @ x) <= bound
+    assert np.linalg.norm(yg - A @ x) <= bound
+    p = tmp_path / "g.h2dx"
+    H.export(p, factors=False)
+    F = h2dfile.read(p)
+    tab = O.il_table()
+    same_kind = F["il_kind"] == tab["kind"]
+    assert same_kind.mean() >= 0.99
+    lr = same_kind & (tab["kind"] == 0)
+    assert np.all(np.abs(F["il_rank"][lr] - tab["rank"][lr]) <= 3)
+
+
+def test_repeatable_bits():
+    xy, b, k, leaf, tol = inputs.workload("log4096")
+    H = _lib().HODLR2D.build(dev(xy), k, leaf, tol)
+    x = dev(b)
+    y1 = host(H.matvec(x)).copy()
+    y2 = host(H.matvec(x))
+    assert np.array_equal(y1, y2)
+    H2 = _lib().HODLR2D.build(dev(xy), k, leaf, tol)
+    assert np.array_equal(y1, host(H2.matvec(x)))
+
+
+def test_zero_tolerance_is_dense():
+    rng = np.random.default_rng(9)
+    xy = rng.uniform(-1, 1, (1500, 2)); x = rng.uniform(-1, 1, 1500)
+    spec = {"kind": "log", "diag_mode": "replace", "diag_value": 1500.0}
+    H = _lib().HODLR2D.build(dev(xy), spec, 16, 0.0)
+    assert H.info()["n_il_dense"] == H.info()["n_il"]
+    A = npref.kernel_matrix(spec, xy)
+    assert np.linalg.norm(host(H.matvec(dev(x))) - A @ x) <= 1e-13 * np.linalg.norm(A @ x)
+
+
+def test_error_statuses():
+    h = _lib()
+    xy = np.array([[0.1, 0.2], [0.5, 0.5], [0.1, 0.2]])
+    with pytest.raises(h.H2DError) as e:
+        h.HODLR2D.build(dev(xy), {"kind": "log", "diag_mode": "replace", "diag_value": 3.0}, 8, 1e-10)
+    assert e.value.code == h.H2D_EDUP
+    with pytest.raises(h.H2DError) as e:
+        h.HODLR2D.build(dev(np.array([[0.0, np.nan]])), MQ, 8, 1e-10)
+    assert e.value.code == h.H2D_EINVAL
+    with pytest.raises(h.H2DError) as e:
+        h.HODLR2D.build(dev(xy), {"kind": "mq", "c": -1.0, "diag_mode": "add", "diag_value": 0.0}, 8, 1e-10)
+    assert e.value.code == h.H2D_EINVAL
+    H = h.HODLR2D.build(dev(xy), MQ, 8, 1e-10)
+    with pytest.raises(h.H2DError) as e:
+        H.matvec(dev(np.ones(3)), prec="fp16")
+    assert e.value.code == h.H2D_EUNSUPPORTED
+    # 65 coincident points cannot be split by any depth
+    with pytest.raises(h.H2DError) as e:
+        h.HODLR2D.build(dev(np.zeros((65, 2))), MQ, 64, 1e-10)
+    assert e.value.code == h.H2D_EDEPTH
+
+
+def test_solve_plain_log4096(orc):
+    xy, b, k, leaf, tol = inputs.workload("log4096")
+    H = _lib().HODLR2D.build(dev(xy), k, leaf, tol)
+    x, info = H.solve(dev(b), tol=1e-8, restart=50)
+    assert info["converged"] and info["relres"] <= 1e-8
+    O = orc.OracleH(xy, k, leaf, tol)
+    xo, it, rr, st = O.gmres(b, 1e-8, 50, 500)
+    assert abs(info["iters"] - it) <= 1
+    A = npref.kernel_matrix(k, xy)
+    xd = np.linalg.solve(A, b)
+    assert np.linalg.norm(host(x) - xd) <= 1e-7 * np.linalg.norm(xd)
