@@ -165,6 +165,23 @@ h2d_status h2d_export(h2d_t H, const char* path, uint32_t flags);
  * upload it: the resulting handle applies exactly the stored operator. */
 h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t* out);
 
+/* Per-phase timing of the matvec kernels, for roofline reporting.
+ * h2d_profile_enable(H, 1) makes every later single-RHS matvec on H record
+ * HIP events around its four kernels (on the caller's stream, so the
+ * timings cover exactly those kernels); h2d_profile_read() synchronises on
+ * the recorded events, returns the average milliseconds and the
+ * algorithmic bytes of each kernel over the recorded matvecs, and clears
+ * the record.  At most 65536 matvecs are recorded between reads. */
+typedef struct {
+    int32_t count;         /* matvecs averaged */
+    int32_t prec;          /* precision of the last recorded matvec */
+    double ms[4];          /* gather, phase A (V^T x), partial reduce, phase B (U t + near field) */
+    double bytes[4];       /* algorithmic bytes of each kernel per launch */
+} h2d_profile;
+
+h2d_status h2d_profile_enable(h2d_t H, int32_t on);
+h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
+
 /* Free every allocation of H (NULL is a no-op). */
 void h2d_destroy(h2d_t H);
 

@@ -399,6 +399,22 @@ h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t*
     });
 }
 
+h2d_status h2d_profile_enable(h2d_t H, int32_t on)
+{
+    return guarded([&] {
+        if (!H) fail(H2D_EINVAL, "NULL handle");
+        profile_enable(H->h, on != 0);
+    });
+}
+
+h2d_status h2d_profile_read(h2d_t H, h2d_profile* out)
+{
+    return guarded([&] {
+        if (!H || !out) fail(H2D_EINVAL, "NULL argument");
+        profile_read(H->h, out);
+    });
+}
+
 void h2d_destroy(h2d_t H)
 {
     if (!H) return;
@@ -406,6 +422,7 @@ void h2d_destroy(h2d_t H)
     (void)hipGetDevice(&dev);
     (void)hipSetDevice(H->h.device);
     (void)hipDeviceSynchronize();
+    for (hipEvent_t e : H->h.prof_ev) (void)hipEventDestroy(e);
     delete H;
     (void)hipSetDevice(dev);
 }

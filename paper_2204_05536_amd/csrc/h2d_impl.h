@@ -166,12 +166,21 @@ struct Handle {
     int64_t ws_nrhs = 0;
 
     double alg_bytes_fp64 = 0, alg_bytes_half = 0, flops = 0;
+    double phase_bytes[2][4] = {{0}};   // [FP64, half][gather, A, reduce, B]
+
+    // profiling: 5 events per recorded matvec
+    bool prof_on = false;
+    int prof_prec = 0;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
 };
 
 // kernels.hip
 void finalize(Handle& H, hipStream_t s);
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s);
 void ensure_workspace(Handle& H, int nrhs);
+void profile_enable(Handle& H, bool on);
+void profile_read(Handle& H, h2d_profile* out);
 
 // build.hip
 void build_tree_and_lists(Handle& H, hipStream_t s);

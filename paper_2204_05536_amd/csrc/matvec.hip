@@ -16,6 +16,7 @@
 #include "h2d_impl.h"
 
 #include <algorithm>
+#include <cstring>
 
 namespace h2d {
 
@@ -256,6 +257,18 @@ void finalize(Handle& H, hipStream_t s)
     hbytes += nvec * (8 + 4 + 8 + 4 + 4);   // FP32 xs, FP32 diagonal
     H.alg_bytes_fp64 = bytes; H.alg_bytes_half = hbytes; H.flops = flops;
     H.t_elems = toff; H.p_elems = poff;
+    // per-kernel algorithmic bytes: each operand touched once
+    for (int h = 0; h < 2; ++h) {
+        const double s = h ? 2.0 : 8.0, a = h ? 4.0 : 8.0;   // storage, accumulation sizes
+        double vstore = 0, ustore = 0, dstore = 0;
+        vstore = (double)H.v_elems * s;
+        ustore = (double)H.u_elems * s;
+        dstore = (double)H.d_elems * s;
+        H.phase_bytes[h][0] = nvec * (8 + 4 + a);                                   // x, perm -> xs
+        H.phase_bytes[h][1] = vstore + nvec * a + (double)toff * a + (double)poff * a;  // V, xs -> t / partials
+        H.phase_bytes[h][2] = poff ? (double)poff * a + (double)toff * a : 0.0;        // partials -> t
+        H.phase_bytes[h][3] = ustore + dstore + (double)toff * a + nvec * (a + 4 + 8) + (h ? nvec * 4 : 0.0);
+    }
     upload_vec(H.bil, bi, s);
     upload_vec(H.aitems, items, s);
     upload_vec(H.ritems, red, s);
@@ -291,26 +304,75 @@ static LevelPtrs level_ptrs(const Handle& H)
     return P;
 }
 
+constexpr size_t kProfMax = 65536;
+
+// Event slot e (0..4) of the current recorded matvec, or null.
+static hipEvent_t* prof_slot(Handle& H)
+{
+    if (!H.prof_on || H.prof_used >= kProfMax) return nullptr;
+    size_t need = (H.prof_used + 1) * 5;
+    while (H.prof_ev.size() < need) {
+        hipEvent_t e;
+        HIPCK(hipEventCreate(&e));
+        H.prof_ev.push_back(e);
+    }
+    return H.prof_ev.data() + H.prof_used * 5;
+}
+
 template <typename T, typename A, bool kHalf>
 static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp, A* pp, const double* x, double* y,
                     hipStream_t s)
 {
     const int32_t n = (int32_t)H.n;
+    hipEvent_t* ev = prof_slot(H);
+    if (ev) HIPCK(hipEventRecord(ev[0], s));
     k_gather<A><<<(n + 255) / 256, 256, 0, s>>>(x, H.perm.p, n, 0, 0, 1, xs);
+    if (ev) HIPCK(hipEventRecord(ev[1], s));
     if (H.n_aitems)
         k_phaseA<T, A, kHalf><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp, 0,
                                                                             H.scale16.p);
+    if (ev) HIPCK(hipEventRecord(ev[2], s));
     if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 64, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
+    if (ev) HIPCK(hipEventRecord(ev[3], s));
     const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
     k_phaseB<T, A, kHalf><<<(unsigned)((nleaf + 3) / 4), 256, 0, s>>>(
         nleaf, H.kappa, level_ptrs(H), H.near_ptr.p, H.bnear.p, H.bil.p, U, D, tp, xs, H.perm.p, y, H.scale16.p,
         H.diag32.p, H.n_il);
+    if (ev) {
+        HIPCK(hipEventRecord(ev[4], s));
+        H.prof_used++;
+    }
     HIPCK(hipGetLastError());
+}
+
+void profile_enable(Handle& H, bool on)
+{
+    H.prof_on = on;
+}
+
+void profile_read(Handle& H, h2d_profile* out)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->count = (int32_t)H.prof_used;
+    out->prec = H.prof_prec;
+    const int h = H.prof_prec == H2D_P_FP64 ? 0 : 1;
+    for (int p = 0; p < 4; ++p) out->bytes[p] = H.phase_bytes[h][p];
+    if (H.prof_used) HIPCK(hipEventSynchronize(H.prof_ev[H.prof_used * 5 - 1]));
+    for (size_t c = 0; c < H.prof_used; ++c)
+        for (int p = 0; p < 4; ++p) {
+            float ms = 0.f;
+            HIPCK(hipEventElapsedTime(&ms, H.prof_ev[c * 5 + p], H.prof_ev[c * 5 + p + 1]));
+            out->ms[p] += ms;
+        }
+    if (H.prof_used)
+        for (int p = 0; p < 4; ++p) out->ms[p] /= (double)H.prof_used;
+    H.prof_used = 0;
 }
 
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s)
 {
     ensure_workspace(H, 1);
+    H.prof_prec = prec;
     for (int r = 0; r < nrhs; ++r) {
         const double* xr = x + (int64_t)r * ld;
         double* yr = y + (int64_t)r * ld;

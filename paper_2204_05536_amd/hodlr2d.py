@@ -25,7 +25,8 @@ PREC = {"fp64": 0, "fp16": 1, "bf16": 2}
 SOLVE_PLAIN, SOLVE_REFINE = 0, 1
 
 EXPORTED = ["h2d_build", "h2d_matvec", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
-            "h2d_destroy", "h2d_last_error"]
+            "h2d_profile_enable", "h2d_profile_read", "h2d_destroy", "h2d_last_error"]
+PHASES = ["gather", "phaseA", "reduce", "phaseB"]
 
 
 class H2DError(RuntimeError):
@@ -56,6 +57,10 @@ class h2d_stats(C.Structure):
                 ("pad", C.c_int32)]
 
 
+class h2d_profile(C.Structure):
+    _fields_ = [("count", C.c_int32), ("prec", C.c_int32), ("ms", C.c_double * 4), ("bytes", C.c_double * 4)]
+
+
 _lib = None
 
 
@@ -81,6 +86,10 @@ def load():
     L.h2d_export.restype = C.c_int
     L.h2d_import.argtypes = [C.c_char_p, C.c_uint32, P, C.POINTER(P)]
     L.h2d_import.restype = C.c_int
+    L.h2d_profile_enable.argtypes = [P, C.c_int32]
+    L.h2d_profile_enable.restype = C.c_int
+    L.h2d_profile_read.argtypes = [P, C.POINTER(h2d_profile)]
+    L.h2d_profile_read.restype = C.c_int
     L.h2d_destroy.argtypes = [P]
     L.h2d_destroy.restype = None
     L.h2d_last_error.argtypes = []
@@ -186,6 +195,16 @@ class HODLR2D:
             _check(st)
         return x, {"iters": info.iters, "outer": info.outer, "relres": info.relres, "seconds": info.seconds,
                    "converged": st == H2D_OK}
+
+    def profile_enable(self, on=True):
+        _check(load().h2d_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """Average ms and algorithmic bytes per matvec kernel since the last read."""
+        p = h2d_profile()
+        _check(load().h2d_profile_read(self._h, C.byref(p)))
+        return {"count": p.count, "prec": p.prec,
+                "ms": dict(zip(PHASES, list(p.ms))), "bytes": dict(zip(PHASES, list(p.bytes)))}
 
     def export(self, path, factors=True):
         _check(load().h2d_export(self._h, str(path).encode(), 1 if factors else 0))
