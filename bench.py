@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-half", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (a known-size kernel for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the HODLR2D path here is single-GPU.",
@@ -131,6 +133,16 @@ def main():
         return e0.elapsed_time(e1) / steps, prof
 
     ms, prof = timed("fp64", args.steps, args.warmup, True)
+    if args.calibrate_copy:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB (a plain
+        # device copy may run on a DMA engine, which kernel counters miss)
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x (1 GiB read + 1 GiB write) elementwise kernels done")
+        del src, dst
     gbs = info["alg_bytes_fp64"] / (ms * 1e-3) / 1e9
     log(f"FP64 matvec {ms:.3f} ms  {gbs:.0f} GB/s  phases ms={prof['ms']}")
     # dominant kernel's roofline
