@@ -148,7 +148,7 @@ def main():
     # dominant kernel's roofline
     dom = max(prof["ms"], key=lambda k: prof["ms"][k])
     achieved = prof["bytes"][dom] / (prof["ms"][dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"k_phase{dom[-1]}" if dom.startswith("phase") else f"k_{dom}",
+    roofline = {"bound": "hbm", "kernel": f"k_{dom}",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": None, "alg_bytes_per_launch": prof["bytes"][dom], "avg_ms": prof["ms"][dom],
                 "phases_ms": prof["ms"], "phases_alg_bytes": prof["bytes"]}

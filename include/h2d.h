@@ -165,18 +165,22 @@ h2d_status h2d_export(h2d_t H, const char* path, uint32_t flags);
  * upload it: the resulting handle applies exactly the stored operator. */
 h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t* out);
 
-/* Per-phase timing of the matvec kernels, for roofline reporting.
+/* Per-kernel timing of the matvec, for roofline reporting.
  * h2d_profile_enable(H, 1) makes every later single-RHS matvec on H record
- * HIP events around its four kernels (on the caller's stream, so the
+ * HIP events around its five kernels (on the caller's stream, so the
  * timings cover exactly those kernels); h2d_profile_read() synchronises on
  * the recorded events, returns the average milliseconds and the
  * algorithmic bytes of each kernel over the recorded matvecs, and clears
- * the record.  At most 65536 matvecs are recorded between reads. */
+ * the record.  At most 65536 matvecs are recorded between reads.
+ * Kernels: 0 gather x into tree order; 1 phase A, t = V^T x for every
+ * low-rank block; 2 sums of split phase-A partials; 3 phase B1, U t for
+ * the blocks of levels 1..kappa-1; 4 phase B2, leaf-level blocks and near
+ * field, y written in caller order. */
 typedef struct {
     int32_t count;         /* matvecs averaged */
     int32_t prec;          /* precision of the last recorded matvec */
-    double ms[4];          /* gather, phase A (V^T x), partial reduce, phase B (U t + near field) */
-    double bytes[4];       /* algorithmic bytes of each kernel per launch */
+    double ms[5];          /* average milliseconds per kernel */
+    double bytes[5];       /* algorithmic bytes of each kernel per launch */
 } h2d_profile;
 
 h2d_status h2d_profile_enable(h2d_t H, int32_t on);

@@ -17,7 +17,7 @@ namespace h2d {
 constexpr int kMaxLevel = 16;      // Morton keys are 2 x 16 bits
 constexpr int kWave = 64;
 constexpr int kAcaRankCap = 256;   // ACA scratch columns per block
-constexpr int kPhaseARows = 512;   // V rows per phase-A work item
+constexpr int kPhaseARows = 1024;  // V rows per phase-A work item
 
 // Error carried from deep inside the library to the C ABI.
 struct Error {
@@ -158,15 +158,16 @@ struct Handle {
     DBuf<ADesc> aitems;
     DBuf<RDesc> ritems;
     int64_t n_aitems = 0, n_ritems = 0;
-    DBuf<int32_t> leaf_order;   // phase-B tiles: leaf box indices, XCD-aware order
+    DBuf<int2> b1items;         // phase-B1 work: (box at level kappa - 1, first row of a 64-row chunk)
+    int64_t n_b1 = 0;
 
     // work vectors
-    DBuf<double> xs, tpool, ppool;    // FP64: x in tree order, t, partials
-    DBuf<float> xs32, tpool32, ppool32;
+    DBuf<double> xs, tpool, ppool, ypart;    // FP64: x in tree order, t, partials, ancestor sums
+    DBuf<float> xs32, tpool32, ppool32, ypart32;
     int64_t ws_nrhs = 0;
 
     double alg_bytes_fp64 = 0, alg_bytes_half = 0, flops = 0;
-    double phase_bytes[2][4] = {{0}};   // [FP64, half][gather, A, reduce, B]
+    double phase_bytes[2][5] = {{0}};   // [FP64, half][gather, A, reduce, B1, B2]
 
     // profiling: 5 events per recorded matvec
     bool prof_on = false;

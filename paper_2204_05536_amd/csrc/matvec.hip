@@ -28,11 +28,20 @@ struct LevelPtrs {
 };
 
 template <typename T> __device__ __forceinline__ float ldf(const T* p);
-template <> __device__ __forceinline__ float ldf<__half>(const __half* p) { return __half2float(*p); }
-template <> __device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+template <> __device__ __forceinline__ float ldf<__half>(const __half* p)
+{
+    return __half2float(__builtin_nontemporal_load(reinterpret_cast<const _Float16*>(p)));
+}
+template <> __device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfloat16* p)
+{
+    unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
+    return __uint_as_float((unsigned)b << 16);
+}
 
+// Factor values are streamed once per matvec: nontemporal loads keep them
+// from evicting x, t and the descriptors from the caches.
 template <typename T, typename A> __device__ __forceinline__ A ld(const T* p) { return (A)ldf<T>(p); }
-template <> __device__ __forceinline__ double ld<double, double>(const double* p) { return *p; }
+template <> __device__ __forceinline__ double ld<double, double>(const double* p) { return __builtin_nontemporal_load(p); }
 
 template <typename A>
 __global__ void k_gather(const double* x, const int32_t* perm, int32_t n, int64_t ldx, int64_t ldxs, int nrhs, A* xs)
@@ -43,11 +52,22 @@ __global__ void k_gather(const double* x, const int32_t* perm, int32_t n, int64_
     for (int r = 0; r < nrhs; ++r) xs[(int64_t)r * ldxs + i] = (A)x[(int64_t)r * ldx + p];
 }
 
-// Phase A: one wave per work item (rows j0..j1 of one block's V).
+// Workgroup w -> tile index such that each XCD (workgroups are dealt
+// round-robin over the 8 XCDs) walks one contiguous range of tiles, so
+// neighbouring tiles, which share cache lines, share an L2.
+__device__ __forceinline__ int32_t xcd_tile()
+{
+    const int32_t W = gridDim.x, w = blockIdx.x, xcd = w % 8, i8 = w / 8;
+    const int32_t q8 = W / 8, r8 = W % 8;
+    return xcd * q8 + min(xcd, r8) + i8;
+}
+
+// Phase A: one wave per work item (rows j0..j1 of one block's V).  Items
+// are ordered largest first (a static longest-processing-time schedule).
 template <typename T, typename A, bool kScaled>
 __global__ void __launch_bounds__(256)
 k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ V, const A* __restrict__ xs,
-         A* __restrict__ tpool, A* __restrict__ ppool, int64_t nsplit_base, const float* __restrict__ scale)
+         A* __restrict__ tpool, A* __restrict__ ppool, const float* __restrict__ scale)
 {
     __shared__ A red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -60,13 +80,12 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     A* out = (D.out >= 0) ? (tpool + D.out) : (ppool + (-D.out - 1));
     A sc = (A)1;
     if constexpr (kScaled) sc = (A)scale[D.pad];
-    (void)nsplit_base;
     if (k <= kWave) {
         const int G = kWave / k, g = lane / k, q = lane % k;
         A acc = (A)0;
         if (g < G) {
             int32_t j = D.j0 + g;
-#pragma unroll 4
+#pragma unroll 8
             for (; j < D.j1; j += G) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xb[j];
         }
         red[wave][lane] = acc;
@@ -82,7 +101,7 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
             const int32_t q = qc + lane;
             if (q < k) {
                 A acc = (A)0;
-#pragma unroll 4
+#pragma unroll 8
                 for (int32_t j = D.j0; j < D.j1; ++j) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xb[j];
                 out[q] = acc * sc;
             }
@@ -90,85 +109,132 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     }
 }
 
+// t = sum of a split block's partials, in part order.  One workgroup per
+// split block; lanes take parts p = lane, lane + 64, ...; each wave owns
+// columns q = wave, wave + 4, ...; the lane sums are combined by a fixed
+// butterfly.
 template <typename A>
-__global__ void k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ ppool, A* __restrict__ tpool)
+__global__ void __launch_bounds__(256)
+k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ ppool, A* __restrict__ tpool)
 {
     const int64_t r = blockIdx.x;
     if (r >= nr) return;
     const RDesc D = R[r];
-    for (int q = threadIdx.x; q < D.k; q += blockDim.x) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int q = wave; q < D.k; q += 4) {
         A s = (A)0;
-        for (int p = 0; p < D.nparts; ++p) s += ppool[D.pbeg + (int64_t)p * D.k + q];
-        tpool[D.tout + q] = s;
+#pragma unroll 8
+        for (int p = lane; p < D.nparts; p += kWave) s += ppool[D.pbeg + (int64_t)p * D.k + q];
+        for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+        if (lane == 0) tpool[D.tout + q] = s;
     }
 }
 
-// Phase B: one wave per leaf box, 4 leaf boxes (consecutive in tree order)
-// per workgroup; workgroups are mapped to XCDs in contiguous tile ranges so
-// neighbouring boxes share an L2.
+// Phase B1: ancestor levels.  One wave per 64-row chunk of a box at level
+// kappa - 1; lane r owns row r.  For every interaction-list block of that
+// box and of each ancestor, the chunk's rows of every column of U (or D)
+// are 64 consecutive values, read by one coalesced load.
 template <typename T, typename A, bool kHalf>
 __global__ void __launch_bounds__(256)
-k_phaseB(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
-         const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool,
-         const A* __restrict__ xs, const int32_t* __restrict__ perm, double* __restrict__ y,
-         const float* __restrict__ scale, const float* __restrict__ diag, int64_t n_il)
+k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, const BDesc* __restrict__ bil,
+          const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
+          A* __restrict__ ypart, const float* __restrict__ scale)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t it = xcd_tile() * 4 + wave;
+    if (it >= nitems) return;
+    const int2 w = items[it];
+    const int32_t P = w.x, rc = w.y;
+    const int32_t p0 = L.begin[tl][P], cnt = L.count[tl][P];
+    const int32_t rows = min(kWave, cnt - rc);
+    const bool act = lane < rows;
+    A acc = (A)0;
+    int32_t a_box = P;
+    for (int l = tl; l >= 1; --l) {
+        const int32_t ab = L.begin[l][a_box], ld_m = L.count[l][a_box];
+        const int64_t off = (int64_t)(p0 - ab + rc + lane);
+        const int32_t q0 = L.il_ptr[l][a_box], q1 = L.il_ptr[l][a_box + 1];
+        for (int32_t q = q0; q < q1; ++q) {
+            const BDesc d = bil[q];
+            if (d.cols > 0) {
+                const T* base = Up + d.off + off;
+                const A* tv = tpool + d.tsrc;
+                if (act) {
+#pragma unroll 8
+                    for (int32_t c = 0; c < d.cols; ++c) acc += ld<T, A>(base + (int64_t)c * ld_m) * tv[c];
+                }
+            } else if (d.cols < 0) {
+                const T* base = Dp + d.off + off;
+                const A* tv = xs + d.tsrc;
+                A a = (A)0;
+                if (act) {
+#pragma unroll 8
+                    for (int32_t j = 0; j < -d.cols; ++j) a += ld<T, A>(base + (int64_t)j * ld_m) * tv[j];
+                }
+                if constexpr (kHalf) acc += a * (A)scale[q];
+                else acc += a;
+            }
+        }
+        a_box = L.parent[l][a_box];
+    }
+    if (act) ypart[p0 + rc + lane] = acc;
+}
+
+// Phase B2: the leaf level.  One wave per leaf box X: its dense near blocks
+// and its own interaction-list blocks, plus the ancestors' sum from B1;
+// writes y once, in caller order.  A leaf box has at most 64 rows per pass;
+// lane (g, r) takes row r and the columns g, g + G, ... (G = 64 / rows), so
+// a load covers G consecutive columns of the column-major block.
+template <typename T, typename A, bool kHalf>
+__global__ void __launch_bounds__(256)
+k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
+          const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool,
+          const A* __restrict__ xs, const A* __restrict__ ypart, const int32_t* __restrict__ perm, double* __restrict__ y,
+          const float* __restrict__ scale, const float* __restrict__ diag, int64_t n_il)
 {
     __shared__ A red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    // XCD-aware tile order: hardware deals workgroups round-robin over 8 XCDs
-    const int32_t W = gridDim.x, w = blockIdx.x, xcd = w % 8, i8 = w / 8;
-    const int32_t q8 = W / 8, r8 = W % 8;
-    const int32_t tile = xcd * q8 + min(xcd, r8) + i8;
-    const int32_t X = tile * 4 + wave;
+    const int32_t X = xcd_tile() * 4 + wave;
     if (X >= nleaf) return;
     const int32_t r0 = L.begin[kappa][X], cnt = L.count[kappa][X];
+    const int32_t q0 = L.il_ptr[kappa][X], q1 = L.il_ptr[kappa][X + 1];
     for (int32_t rc = 0; rc < cnt; rc += kWave) {
         const int32_t rows = min(kWave, cnt - rc);
         const int G = kWave / rows, g = lane / rows, r = lane % rows;
         const bool act = g < G;
         A acc = (A)0;
-        // dense near blocks of X (self first in key order, then edge sharers)
         for (int32_t q = near_ptr[X]; q < near_ptr[X + 1]; ++q) {
             const BDesc d = bnear[q];
-            const int32_t nn = -d.cols;
             const T* base = Dp + d.off + rc + r;
             const A* tv = xs + d.tsrc;
             A a = (A)0;
             if (act) {
 #pragma unroll 4
-                for (int32_t j = g; j < nn; j += G) a += ld<T, A>(base + (int64_t)j * cnt) * tv[j];
+                for (int32_t j = g; j < -d.cols; j += G) a += ld<T, A>(base + (int64_t)j * cnt) * tv[j];
             }
             if constexpr (kHalf) acc += a * (A)scale[n_il + q];
             else acc += a;
         }
-        // interaction-list blocks of X and of every ancestor
-        int32_t a_box = X;
-        for (int l = kappa; l >= 1; --l) {
-            const int32_t ab = L.begin[l][a_box], ld_m = L.count[l][a_box];
-            const int32_t off = r0 - ab + rc + r;
-            const int32_t q1 = L.il_ptr[l][a_box + 1];
-            for (int32_t q = L.il_ptr[l][a_box]; q < q1; ++q) {
-                const BDesc d = bil[q];
-                if (d.cols > 0) {
-                    const T* base = Up + d.off + off;
-                    const A* tv = tpool + d.tsrc;
-                    if (act) {
+        for (int32_t q = q0; q < q1; ++q) {
+            const BDesc d = bil[q];
+            if (d.cols > 0) {
+                const T* base = Up + d.off + rc + r;
+                const A* tv = tpool + d.tsrc;
+                if (act) {
 #pragma unroll 4
-                        for (int32_t c = g; c < d.cols; c += G) acc += ld<T, A>(base + (int64_t)c * ld_m) * tv[c];
-                    }
-                } else if (d.cols < 0) {
-                    const T* base = Dp + d.off + off;
-                    const A* tv = xs + d.tsrc;
-                    A a = (A)0;
-                    if (act) {
-#pragma unroll 4
-                        for (int32_t j = g; j < -d.cols; j += G) a += ld<T, A>(base + (int64_t)j * ld_m) * tv[j];
-                    }
-                    if constexpr (kHalf) acc += a * (A)scale[q];
-                    else acc += a;
+                    for (int32_t c = g; c < d.cols; c += G) acc += ld<T, A>(base + (int64_t)c * cnt) * tv[c];
                 }
+            } else if (d.cols < 0) {
+                const T* base = Dp + d.off + rc + r;
+                const A* tv = xs + d.tsrc;
+                A a = (A)0;
+                if (act) {
+#pragma unroll 4
+                    for (int32_t j = g; j < -d.cols; j += G) a += ld<T, A>(base + (int64_t)j * cnt) * tv[j];
+                }
+                if constexpr (kHalf) acc += a * (A)scale[q];
+                else acc += a;
             }
-            a_box = L.parent[l][a_box];
         }
         red[wave][lane] = act ? acc : (A)0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -177,6 +243,7 @@ k_phaseB(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ near
             A s = (A)0;
             for (int gg = 0; gg < G; ++gg) s += red[wave][gg * rows + lane];
             const int32_t i = r0 + rc + lane;
+            if (ypart) s += ypart[i];
             if constexpr (kHalf) s += (A)diag[i] * xs[i];
             y[perm[i]] = (double)s;
         }
@@ -216,14 +283,17 @@ void finalize(Handle& H, hipStream_t s)
     H.h_il_toff.assign(nil, -1);
     int64_t toff = 0, poff = 0;
     H.max_rank = 0; H.sum_rank = 0; H.n_il_dense = 0;
-    double bytes = 0, flops = 0, hbytes = 0;
+    double flops = 0;
+    double store_anc = 0, store_leaf = 0, t_leaf = 0;   // stored values read by B1 / B2, t values read by B2
     for (int64_t b = 0; b < nil; ++b) {
         const Level& L = H.lev[H.h_il_level[b]];
+        const bool leaf = H.h_il_level[b] == kappa;
         int32_t m = L.h_count[H.h_il_tgt[b]], n = L.h_count[H.h_il_src[b]], c0 = L.h_begin[H.h_il_src[b]];
         if (H.h_il_kind[b] == kDense) {
             bi[b] = BDesc{H.h_il_off[b], -n, c0};
             H.n_il_dense++;
-            bytes += 8.0 * m * n; hbytes += 2.0 * m * n; flops += 2.0 * m * n;
+            (leaf ? store_leaf : store_anc) += (double)m * n;
+            flops += 2.0 * m * n;
             continue;
         }
         int32_t k = H.h_il_k[b];
@@ -232,7 +302,9 @@ void finalize(Handle& H, hipStream_t s)
         bi[b] = BDesc{H.h_il_off[b], k, (int32_t)toff};
         if (k == 0) continue;
         H.h_il_toff[b] = (int32_t)toff;
-        bytes += 8.0 * k * (double)(m + n); hbytes += 2.0 * k * (double)(m + n); flops += 2.0 * k * (double)(m + n);
+        (leaf ? store_leaf : store_anc) += (double)m * k;
+        if (leaf) t_leaf += k;
+        flops += 2.0 * k * (double)(m + n);
         if (n <= kPhaseARows) {
             items.push_back(ADesc{H.h_il_voff[b], 0, n, c0, k, (int32_t)toff, (int32_t)b});
         } else {
@@ -246,28 +318,44 @@ void finalize(Handle& H, hipStream_t s)
         }
         toff += k;
     }
+    // largest work first (ties keep table order)
+    std::stable_sort(items.begin(), items.end(), [](const ADesc& x, const ADesc& y) {
+        return (int64_t)(x.j1 - x.j0) * x.k > (int64_t)(y.j1 - y.j0) * y.k;
+    });
+    double near_e = 0;
     for (int64_t x = 0; x < LL.nbox; ++x)
-        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
-            double e = (double)LL.h_count[x] * LL.h_count[H.h_near_src[q]];
-            bytes += 8.0 * e; hbytes += 2.0 * e; flops += 2.0 * e;
-        }
-    // vectors: x read (gather), xs written and read, y written, perm read
-    const double nvec = (double)H.n;
-    bytes += nvec * (8 + 8 + 8 + 4);
-    hbytes += nvec * (8 + 4 + 8 + 4 + 4);   // FP32 xs, FP32 diagonal
-    H.alg_bytes_fp64 = bytes; H.alg_bytes_half = hbytes; H.flops = flops;
+        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q)
+            near_e += (double)LL.h_count[x] * LL.h_count[H.h_near_src[q]];
+    flops += 2.0 * near_e;
+    store_leaf += near_e;
+    // phase-B1 work: 64-row chunks of the boxes one level above the leaves
+    std::vector<int2> b1;
+    if (kappa >= 2) {
+        const Level& T = H.lev[kappa - 1];
+        for (int64_t p = 0; p < T.nbox; ++p)
+            for (int32_t rc = 0; rc < T.h_count[p]; rc += kWave) b1.push_back(make_int2((int32_t)p, rc));
+    }
+    H.n_b1 = (int64_t)b1.size();
+    upload_vec(H.b1items, b1, s);
+    H.flops = flops;
     H.t_elems = toff; H.p_elems = poff;
-    // per-kernel algorithmic bytes: each operand touched once
+    // algorithmic bytes per kernel: every stored value and vector touched once
+    const double nvec = (double)H.n;
     for (int h = 0; h < 2; ++h) {
-        const double s = h ? 2.0 : 8.0, a = h ? 4.0 : 8.0;   // storage, accumulation sizes
-        double vstore = 0, ustore = 0, dstore = 0;
-        vstore = (double)H.v_elems * s;
-        ustore = (double)H.u_elems * s;
-        dstore = (double)H.d_elems * s;
-        H.phase_bytes[h][0] = nvec * (8 + 4 + a);                                   // x, perm -> xs
-        H.phase_bytes[h][1] = vstore + nvec * a + (double)toff * a + (double)poff * a;  // V, xs -> t / partials
-        H.phase_bytes[h][2] = poff ? (double)poff * a + (double)toff * a : 0.0;        // partials -> t
-        H.phase_bytes[h][3] = ustore + dstore + (double)toff * a + nvec * (a + 4 + 8) + (h ? nvec * 4 : 0.0);
+        const double sz = h ? 2.0 : 8.0, a = h ? 4.0 : 8.0;   // storage, accumulation sizes
+        const double anc_t = (double)toff - t_leaf;
+        H.phase_bytes[h][0] = nvec * (8 + 4 + a);                                          // x, perm -> xs
+        H.phase_bytes[h][1] = (double)H.v_elems * sz + nvec * a + (double)toff * a + (double)poff * a;
+        H.phase_bytes[h][2] = poff ? (double)poff * a + (double)toff * a : 0.0;           // partials -> t
+        H.phase_bytes[h][3] = H.n_b1 ? store_anc * sz + anc_t * a + nvec * a : 0.0;       // -> ypart
+        H.phase_bytes[h][4] = store_leaf * sz + t_leaf * a + nvec * (a + 4 + 8) + (H.n_b1 ? nvec * a : 0.0) +
+                              (h ? nvec * 4 : 0.0);                                        // -> y
+    }
+    // one matvec: gather + A + (reduce) + B1 + B2 (reduce and B1 intermediates counted once)
+    for (int h = 0; h < 2; ++h) {
+        double t = 0;
+        for (int p = 0; p < 5; ++p) t += H.phase_bytes[h][p];
+        (h ? H.alg_bytes_half : H.alg_bytes_fp64) = t;
     }
     upload_vec(H.bil, bi, s);
     upload_vec(H.aitems, items, s);
@@ -282,10 +370,12 @@ void ensure_workspace(Handle& H, int nrhs)
     if (H.ws_nrhs >= nrhs) return;
     const int64_t n = H.n;
     H.xs.alloc((size_t)n * nrhs);
+    H.ypart.alloc((size_t)n * nrhs);
     H.tpool.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
     H.ppool.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     if (H.prec_mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16))) {
         H.xs32.alloc((size_t)n * nrhs);
+        H.ypart32.alloc((size_t)n * nrhs);
         H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
         H.ppool32.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     }
@@ -305,23 +395,23 @@ static LevelPtrs level_ptrs(const Handle& H)
 }
 
 constexpr size_t kProfMax = 65536;
+constexpr int kEv = 6;   // events per recorded matvec: around gather, A, reduce, B1, B2
 
-// Event slot e (0..4) of the current recorded matvec, or null.
 static hipEvent_t* prof_slot(Handle& H)
 {
     if (!H.prof_on || H.prof_used >= kProfMax) return nullptr;
-    size_t need = (H.prof_used + 1) * 5;
+    size_t need = (H.prof_used + 1) * kEv;
     while (H.prof_ev.size() < need) {
         hipEvent_t e;
         HIPCK(hipEventCreate(&e));
         H.prof_ev.push_back(e);
     }
-    return H.prof_ev.data() + H.prof_used * 5;
+    return H.prof_ev.data() + H.prof_used * kEv;
 }
 
 template <typename T, typename A, bool kHalf>
-static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp, A* pp, const double* x, double* y,
-                    hipStream_t s)
+static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp, A* pp, A* yp, const double* x,
+                    double* y, hipStream_t s)
 {
     const int32_t n = (int32_t)H.n;
     hipEvent_t* ev = prof_slot(H);
@@ -329,17 +419,22 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     k_gather<A><<<(n + 255) / 256, 256, 0, s>>>(x, H.perm.p, n, 0, 0, 1, xs);
     if (ev) HIPCK(hipEventRecord(ev[1], s));
     if (H.n_aitems)
-        k_phaseA<T, A, kHalf><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp, 0,
+        k_phaseA<T, A, kHalf><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp,
                                                                             H.scale16.p);
     if (ev) HIPCK(hipEventRecord(ev[2], s));
-    if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 64, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
+    if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
     if (ev) HIPCK(hipEventRecord(ev[3], s));
+    const LevelPtrs LP = level_ptrs(H);
+    if (H.n_b1)
+        k_phaseB1<T, A, kHalf><<<(unsigned)((H.n_b1 + 3) / 4), 256, 0, s>>>(
+            (int32_t)H.n_b1, H.b1items.p, H.kappa - 1, LP, H.bil.p, U, D, tp, xs, yp, H.scale16.p);
+    if (ev) HIPCK(hipEventRecord(ev[4], s));
     const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
-    k_phaseB<T, A, kHalf><<<(unsigned)((nleaf + 3) / 4), 256, 0, s>>>(
-        nleaf, H.kappa, level_ptrs(H), H.near_ptr.p, H.bnear.p, H.bil.p, U, D, tp, xs, H.perm.p, y, H.scale16.p,
-        H.diag32.p, H.n_il);
+    k_phaseB2<T, A, kHalf><<<(unsigned)((nleaf + 3) / 4), 256, 0, s>>>(
+        nleaf, H.kappa, LP, H.near_ptr.p, H.bnear.p, H.bil.p, U, D, tp, xs, H.n_b1 ? yp : nullptr, H.perm.p, y,
+        H.scale16.p, H.diag32.p, H.n_il);
     if (ev) {
-        HIPCK(hipEventRecord(ev[4], s));
+        HIPCK(hipEventRecord(ev[5], s));
         H.prof_used++;
     }
     HIPCK(hipGetLastError());
@@ -356,16 +451,16 @@ void profile_read(Handle& H, h2d_profile* out)
     out->count = (int32_t)H.prof_used;
     out->prec = H.prof_prec;
     const int h = H.prof_prec == H2D_P_FP64 ? 0 : 1;
-    for (int p = 0; p < 4; ++p) out->bytes[p] = H.phase_bytes[h][p];
-    if (H.prof_used) HIPCK(hipEventSynchronize(H.prof_ev[H.prof_used * 5 - 1]));
+    for (int p = 0; p < 5; ++p) out->bytes[p] = H.phase_bytes[h][p];
+    if (H.prof_used) HIPCK(hipEventSynchronize(H.prof_ev[H.prof_used * kEv - 1]));
     for (size_t c = 0; c < H.prof_used; ++c)
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < 5; ++p) {
             float ms = 0.f;
-            HIPCK(hipEventElapsedTime(&ms, H.prof_ev[c * 5 + p], H.prof_ev[c * 5 + p + 1]));
+            HIPCK(hipEventElapsedTime(&ms, H.prof_ev[c * kEv + p], H.prof_ev[c * kEv + p + 1]));
             out->ms[p] += ms;
         }
     if (H.prof_used)
-        for (int p = 0; p < 4; ++p) out->ms[p] /= (double)H.prof_used;
+        for (int p = 0; p < 5; ++p) out->ms[p] /= (double)H.prof_used;
     H.prof_used = 0;
 }
 
@@ -377,12 +472,14 @@ void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, 
         const double* xr = x + (int64_t)r * ld;
         double* yr = y + (int64_t)r * ld;
         if (prec == H2D_P_FP64)
-            run_one<double, double, false>(H, H.U64.p, H.V64.p, H.D64.p, H.xs.p, H.tpool.p, H.ppool.p, xr, yr, s);
+            run_one<double, double, false>(H, H.U64.p, H.V64.p, H.D64.p, H.xs.p, H.tpool.p, H.ppool.p, H.ypart.p, xr,
+                                           yr, s);
         else if (prec == H2D_P_FP16)
-            run_one<__half, float, true>(H, H.U16.p, H.V16.p, H.D16.p, H.xs32.p, H.tpool32.p, H.ppool32.p, xr, yr, s);
+            run_one<__half, float, true>(H, H.U16.p, H.V16.p, H.D16.p, H.xs32.p, H.tpool32.p, H.ppool32.p, H.ypart32.p,
+                                         xr, yr, s);
         else
             run_one<__hip_bfloat16, float, true>(H, H.Ub16.p, H.Vb16.p, H.Db16.p, H.xs32.p, H.tpool32.p, H.ppool32.p,
-                                                  xr, yr, s);
+                                                  H.ypart32.p, xr, yr, s);
     }
 }
 

@@ -26,7 +26,7 @@ SOLVE_PLAIN, SOLVE_REFINE = 0, 1
 
 EXPORTED = ["h2d_build", "h2d_matvec", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
             "h2d_profile_enable", "h2d_profile_read", "h2d_destroy", "h2d_last_error"]
-PHASES = ["gather", "phaseA", "reduce", "phaseB"]
+PHASES = ["gather", "phaseA", "reduce", "phaseB1", "phaseB2"]
 
 
 class H2DError(RuntimeError):
@@ -58,7 +58,7 @@ class h2d_stats(C.Structure):
 
 
 class h2d_profile(C.Structure):
-    _fields_ = [("count", C.c_int32), ("prec", C.c_int32), ("ms", C.c_double * 4), ("bytes", C.c_double * 4)]
+    _fields_ = [("count", C.c_int32), ("prec", C.c_int32), ("ms", C.c_double * 5), ("bytes", C.c_double * 5)]
 
 
 _lib = None
