@@ -52,6 +52,17 @@ __global__ void k_gather(const double* x, const int32_t* perm, int32_t n, int64_
     for (int r = 0; r < nrhs; ++r) xs[(int64_t)r * ldxs + i] = (A)x[(int64_t)r * ldx + p];
 }
 
+// Wave-uniform values: loaded once per wave, then moved to scalar registers
+// so that the loads they address become scalar-cache loads.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ BDesc uni(const BDesc& d) { return BDesc{uni(d.off), uni(d.cols), uni(d.tsrc)}; }
+
 // Workgroup w -> tile index such that each XCD (workgroups are dealt
 // round-robin over the 8 XCDs) walks one contiguous range of tiles, so
 // neighbouring tiles, which share cache lines, share an L2.
@@ -73,7 +84,9 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t it = (int64_t)blockIdx.x * 4 + wave;
     if (it >= nitems) return;
-    const ADesc D = items[it];
+    ADesc D = items[it];
+    D.voff = uni(D.voff); D.j0 = uni(D.j0); D.j1 = uni(D.j1); D.col0 = uni(D.col0); D.k = uni(D.k);
+    D.out = uni(D.out); D.pad = uni(D.pad);
     const int32_t k = D.k;
     const T* Vb = V + D.voff;
     const A* xb = xs + D.col0;
@@ -119,7 +132,8 @@ k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ pp
 {
     const int64_t r = blockIdx.x;
     if (r >= nr) return;
-    const RDesc D = R[r];
+    RDesc D = R[r];
+    D.tout = uni(D.tout); D.k = uni(D.k); D.pbeg = uni(D.pbeg); D.nparts = uni(D.nparts);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     for (int q = wave; q < D.k; q += 4) {
         A s = (A)0;
@@ -144,18 +158,18 @@ k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, c
     const int32_t it = xcd_tile() * 4 + wave;
     if (it >= nitems) return;
     const int2 w = items[it];
-    const int32_t P = w.x, rc = w.y;
-    const int32_t p0 = L.begin[tl][P], cnt = L.count[tl][P];
+    const int32_t P = uni(w.x), rc = uni(w.y);
+    const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
     const int32_t rows = min(kWave, cnt - rc);
     const bool act = lane < rows;
     A acc = (A)0;
     int32_t a_box = P;
     for (int l = tl; l >= 1; --l) {
-        const int32_t ab = L.begin[l][a_box], ld_m = L.count[l][a_box];
+        const int32_t ab = uni(L.begin[l][a_box]), ld_m = uni(L.count[l][a_box]);
         const int64_t off = (int64_t)(p0 - ab + rc + lane);
-        const int32_t q0 = L.il_ptr[l][a_box], q1 = L.il_ptr[l][a_box + 1];
+        const int32_t q0 = uni(L.il_ptr[l][a_box]), q1 = uni(L.il_ptr[l][a_box + 1]);
         for (int32_t q = q0; q < q1; ++q) {
-            const BDesc d = bil[q];
+            const BDesc d = uni(bil[q]);
             if (d.cols > 0) {
                 const T* base = Up + d.off + off;
                 const A* tv = tpool + d.tsrc;
@@ -175,7 +189,7 @@ k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, c
                 else acc += a;
             }
         }
-        a_box = L.parent[l][a_box];
+        a_box = uni(L.parent[l][a_box]);
     }
     if (act) ypart[p0 + rc + lane] = acc;
 }
@@ -196,15 +210,16 @@ k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ nea
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t X = xcd_tile() * 4 + wave;
     if (X >= nleaf) return;
-    const int32_t r0 = L.begin[kappa][X], cnt = L.count[kappa][X];
-    const int32_t q0 = L.il_ptr[kappa][X], q1 = L.il_ptr[kappa][X + 1];
+    const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
+    const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
+    const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
     for (int32_t rc = 0; rc < cnt; rc += kWave) {
         const int32_t rows = min(kWave, cnt - rc);
         const int G = kWave / rows, g = lane / rows, r = lane % rows;
         const bool act = g < G;
         A acc = (A)0;
-        for (int32_t q = near_ptr[X]; q < near_ptr[X + 1]; ++q) {
-            const BDesc d = bnear[q];
+        for (int32_t q = n0; q < n1; ++q) {
+            const BDesc d = uni(bnear[q]);
             const T* base = Dp + d.off + rc + r;
             const A* tv = xs + d.tsrc;
             A a = (A)0;
@@ -216,7 +231,7 @@ k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ nea
             else acc += a;
         }
         for (int32_t q = q0; q < q1; ++q) {
-            const BDesc d = bil[q];
+            const BDesc d = uni(bil[q]);
             if (d.cols > 0) {
                 const T* base = Up + d.off + rc + r;
                 const A* tv = tpool + d.tsrc;
