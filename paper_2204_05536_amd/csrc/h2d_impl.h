@@ -17,7 +17,7 @@ namespace h2d {
 constexpr int kMaxLevel = 16;      // Morton keys are 2 x 16 bits
 constexpr int kWave = 64;
 constexpr int kAcaRankCap = 256;   // ACA scratch columns per block
-constexpr int kPhaseARows = 1024;  // V rows per phase-A work item
+constexpr int kPhaseARows = 512;   // V rows per phase-A work item (x slice staged in LDS)
 
 // Error carried from deep inside the library to the C ABI.
 struct Error {

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <cstdlib>
 
 namespace h2d {
 
@@ -73,13 +74,18 @@ __device__ __forceinline__ int32_t xcd_tile()
     return xcd * q8 + min(xcd, r8) + i8;
 }
 
-// Phase A: one wave per work item (rows j0..j1 of one block's V).  Items
-// are ordered largest first (a static longest-processing-time schedule).
+// Phase A: one wave per work item (rows j0..j1 of one block's V, at most
+// kPhaseARows rows).  The item's slice of x is staged in LDS first, so the
+// vector-memory pipe carries only V.  Lane (g, q) takes column q of rows
+// j0 + g, j0 + g + G, ... (G = 64 / k): each load covers G whole rows, G k
+// consecutive values.  Items are ordered largest first (a static
+// longest-processing-time schedule).
 template <typename T, typename A, bool kScaled>
 __global__ void __launch_bounds__(256)
 k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ V, const A* __restrict__ xs,
          A* __restrict__ tpool, A* __restrict__ ppool, const float* __restrict__ scale)
 {
+    __shared__ A xw[4][kPhaseARows];
     __shared__ A red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t it = (int64_t)blockIdx.x * 4 + wave;
@@ -87,9 +93,13 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     ADesc D = items[it];
     D.voff = uni(D.voff); D.j0 = uni(D.j0); D.j1 = uni(D.j1); D.col0 = uni(D.col0); D.k = uni(D.k);
     D.out = uni(D.out); D.pad = uni(D.pad);
-    const int32_t k = D.k;
-    const T* Vb = V + D.voff;
-    const A* xb = xs + D.col0;
+    const int32_t k = D.k, rows = D.j1 - D.j0;
+    const T* Vb = V + D.voff + (int64_t)D.j0 * k;
+    const A* xb = xs + D.col0 + D.j0;
+    A* xl = xw[wave];
+    for (int32_t j = lane; j < rows; j += kWave) xl[j] = xb[j];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
     A* out = (D.out >= 0) ? (tpool + D.out) : (ppool + (-D.out - 1));
     A sc = (A)1;
     if constexpr (kScaled) sc = (A)scale[D.pad];
@@ -97,9 +107,8 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
         const int G = kWave / k, g = lane / k, q = lane % k;
         A acc = (A)0;
         if (g < G) {
-            int32_t j = D.j0 + g;
 #pragma unroll 8
-            for (; j < D.j1; j += G) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xb[j];
+            for (int32_t j = g; j < rows; j += G) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xl[j];
         }
         red[wave][lane] = acc;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -115,7 +124,7 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
             if (q < k) {
                 A acc = (A)0;
 #pragma unroll 8
-                for (int32_t j = D.j0; j < D.j1; ++j) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xb[j];
+                for (int32_t j = 0; j < rows; ++j) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xl[j];
                 out[q] = acc * sc;
             }
         }
@@ -335,8 +344,8 @@ void finalize(Handle& H, hipStream_t s)
     }
     // largest work first (ties keep table order)
     std::stable_sort(items.begin(), items.end(), [](const ADesc& x, const ADesc& y) {
-        return (int64_t)(x.j1 - x.j0) * x.k > (int64_t)(y.j1 - y.j0) * y.k;
-    });
+            return (int64_t)(x.j1 - x.j0) * x.k > (int64_t)(y.j1 - y.j0) * y.k;
+        });
     double near_e = 0;
     for (int64_t x = 0; x < LL.nbox; ++x)
         for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q)
