@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <algorithm>
+#include <utility>
 
 namespace h2d {
 
@@ -84,6 +86,29 @@ struct File {
     T r1() { T v; r(&v, 1); return v; }
 };
 
+// U of blocks at levels 1..kappa-1 is stored tiled by the boxes of level
+// kappa - 1 (see the pack kernel).  Convert between that layout and plain
+// column-major m x k; to_tiled selects the direction.
+static void retile_u(const Handle& H, int level, int64_t row0, int64_t m, int64_t k, const double* in, double* out,
+                     bool to_tiled)
+{
+    if (H.kappa < 2 || level > H.kappa - 1) {
+        std::memcpy(out, in, sizeof(double) * (size_t)(m * k));
+        return;
+    }
+    const Level& T = H.lev[H.kappa - 1];
+    auto it = std::lower_bound(T.h_begin.begin(), T.h_begin.end(), (int32_t)row0);
+    for (int64_t p = it - T.h_begin.begin(); p < T.nbox && T.h_begin[p] < row0 + m; ++p) {
+        const int64_t pb = T.h_begin[p] - row0, pc = T.h_count[p];
+        for (int64_t q = 0; q < k; ++q)
+            for (int64_t i = 0; i < pc; ++i) {
+                const int64_t plain = q * m + pb + i, tiled = k * pb + q * pc + i;
+                if (to_tiled) out[tiled] = in[plain];
+                else out[plain] = in[tiled];
+            }
+    }
+}
+
 template <typename T>
 static std::vector<T> dl(const T* d, size_t n)
 {
@@ -134,7 +159,7 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
             if (fac) F.w(D.data() + H.h_near_off[q], (size_t)LL.h_count[x] * LL.h_count[H.h_near_src[q]]);
         }
     F.w1<int64_t>(H.n_il);
-    std::vector<double> Vc;
+    std::vector<double> Vc, Uc;
     for (int64_t b = 0; b < H.n_il; ++b) {
         const Level& L = H.lev[H.h_il_level[b]];
         int64_t m = L.h_count[H.h_il_tgt[b]], n = L.h_count[H.h_il_src[b]], k = H.h_il_k[b];
@@ -147,7 +172,9 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
         if (H.h_il_kind[b] == kDense) {
             F.w(D.data() + H.h_il_off[b], (size_t)(m * n));
         } else {
-            F.w(U.data() + H.h_il_off[b], (size_t)(m * k));
+            Uc.resize((size_t)(m * k));
+            retile_u(H, H.h_il_level[b], L.h_begin[H.h_il_tgt[b]], m, k, U.data() + H.h_il_off[b], Uc.data(), false);
+            F.w(Uc.data(), Uc.size());
             Vc.resize((size_t)(n * k));
             for (int64_t j = 0; j < n; ++j)
                 for (int64_t q = 0; q < k; ++q) Vc[q * n + j] = V[H.h_il_voff[b] + j * k + q];
@@ -223,6 +250,7 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
     H.h_il_k.resize(nil); H.h_il_off.resize(nil); H.h_il_voff.assign(nil, 0);
     std::vector<double> U, V;
     std::vector<double> Vc;
+    std::vector<std::pair<int64_t, int64_t>> pending_tile;   // (block, U offset): retiled once levels are known
     for (int64_t b = 0; b < nil; ++b) {
         int32_t lv = F.r1<int32_t>(), kind = F.r1<int32_t>();
         int64_t t = F.r1<int64_t>(), u = F.r1<int64_t>(), k = F.r1<int64_t>();
@@ -246,6 +274,7 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
             size_t o = U.size();
             U.resize(o + (size_t)(m * k));
             F.r(U.data() + o, (size_t)(m * k));
+            pending_tile.push_back({b, (int64_t)o});
             Vc.resize((size_t)(nc * k));
             F.r(Vc.data(), Vc.size());
             size_t ov = V.size();
@@ -254,6 +283,16 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
                 for (int64_t q = 0; q < k; ++q) V[ov + j * k + q] = Vc[q * nc + j];
         } else {
             fail(H2D_EINVAL, "bad block kind");
+        }
+    }
+    {
+        std::vector<double> tmp;
+        for (auto& pt : pending_tile) {
+            const int64_t b = pt.first, o = pt.second;
+            const Level& L = H.lev[H.h_il_level[b]];
+            const int64_t m = L.h_count[H.h_il_tgt[b]], k = H.h_il_k[b];
+            tmp.assign(U.begin() + o, U.begin() + o + m * k);
+            retile_u(H, H.h_il_level[b], L.h_begin[H.h_il_tgt[b]], m, k, tmp.data(), U.data() + o, true);
         }
     }
     // CSR of IL blocks per level box

@@ -698,16 +698,31 @@ k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double
 
 // Copy converged factors out of the scratch: U (m x k col-major) as is,
 // V transposed to row-major n x k.
+// U of a block above the leaf level is stored tiled by the boxes one level
+// above the leaves (the matvec's row tiles): for each such sub-box P of the
+// target, in tree order, the |P| x k column-major tile U(rows of P, :).
+// Element (i, q) sits at k (begin_P - row0) + q |P| + (i - (begin_P - row0)).
+// tbeg / tcnt give begin_P and |P| for every tree row (null: untiled).
 struct PackJob {
     int64_t su, sv;     // scratch offsets
     int64_t du, dv;     // destination offsets
-    int32_t m, n, k, pad;
+    int32_t m, n, k, tiled;
+    int32_t row0, pad;
 };
 
-__global__ void k_pack(const PackJob* jobs, const double* Uw, const double* Vw, double* Uo, double* Vo)
+__global__ void k_pack(const PackJob* jobs, const double* Uw, const double* Vw, double* Uo, double* Vo,
+                       const int32_t* tbeg, const int32_t* tcnt)
 {
     const PackJob J = jobs[blockIdx.x];
-    for (int64_t e = threadIdx.x; e < (int64_t)J.m * J.k; e += blockDim.x) Uo[J.du + e] = Uw[J.su + e];
+    for (int64_t e = threadIdx.x; e < (int64_t)J.m * J.k; e += blockDim.x) {
+        int64_t dst = e;
+        if (J.tiled) {
+            const int64_t q = e / J.m, i = e % J.m, gi = J.row0 + i;
+            const int64_t pb = tbeg[gi] - J.row0, pc = tcnt[gi];
+            dst = (int64_t)J.k * pb + q * pc + (i - pb);
+        }
+        Uo[J.du + dst] = Uw[J.su + e];
+    }
     for (int64_t e = threadIdx.x; e < (int64_t)J.n * J.k; e += blockDim.x) {
         int64_t j = e / J.k, q = e % J.k;
         Vo[J.dv + e] = Vw[J.sv + q * J.n + j];
@@ -751,6 +766,18 @@ void build_factors(Handle& H, hipStream_t s)
         n[b] = L.h_count[H.h_il_src[b]];
         r0[b] = L.h_begin[H.h_il_tgt[b]];
         c0[b] = L.h_begin[H.h_il_src[b]];
+    }
+    // row -> (begin, size) of its box one level above the leaves
+    DBuf<int32_t> tbeg, tcnt;
+    {
+        std::vector<int32_t> hb(H.n, 0), hc(H.n, 0);
+        if (kappa >= 1) {
+            const Level& T = H.lev[kappa - 1];
+            for (int64_t p = 0; p < T.nbox; ++p)
+                for (int32_t i = T.h_begin[p]; i < T.h_begin[p] + T.h_count[p]; ++i) { hb[i] = T.h_begin[p]; hc[i] = T.h_count[p]; }
+        }
+        upload(tbeg, hb, s);
+        upload(tcnt, hc, s);
     }
     // scratch budget per ACA chunk
     size_t freeb = 0, totalb = 0;
@@ -800,7 +827,8 @@ void build_factors(Handle& H, hipStream_t s)
             H.h_il_kind[bb] = hk[q];
             H.h_il_k[bb] = hr[q];
             if (hk[q] == kLowRank && hr[q] > 0) {
-                packs.push_back(PackJob{jobs[q].uoff, jobs[q].voff, C.ue, C.ve, m[bb], n[bb], hr[q], 0});
+                const int32_t tiled = H.h_il_level[bb] <= kappa - 1 ? 1 : 0;
+                packs.push_back(PackJob{jobs[q].uoff, jobs[q].voff, C.ue, C.ve, m[bb], n[bb], hr[q], tiled, r0[bb], 0});
                 C.ue += (int64_t)m[bb] * hr[q];
                 C.ve += (int64_t)n[bb] * hr[q];
             }
@@ -810,7 +838,7 @@ void build_factors(Handle& H, hipStream_t s)
         if (!packs.empty()) {
             DBuf<PackJob> dp;
             upload(dp, packs, s);
-            k_pack<<<(unsigned)packs.size(), 256, 0, s>>>(dp.p, Uw.p, Vw.p, C.U.p, C.V.p);
+            k_pack<<<(unsigned)packs.size(), 256, 0, s>>>(dp.p, Uw.p, Vw.p, C.U.p, C.V.p, tbeg.p, tcnt.p);
             HIPCK(hipGetLastError());
             HIPCK(hipStreamSynchronize(s));
         }

@@ -180,11 +180,13 @@ k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, c
         for (int32_t q = q0; q < q1; ++q) {
             const BDesc d = uni(bil[q]);
             if (d.cols > 0) {
-                const T* base = Up + d.off + off;
+                // U is tiled by level-(kappa - 1) boxes: this box's tile is
+                // a contiguous cnt x k column-major matrix
+                const T* base = Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + lane;
                 const A* tv = tpool + d.tsrc;
                 if (act) {
 #pragma unroll 8
-                    for (int32_t c = 0; c < d.cols; ++c) acc += ld<T, A>(base + (int64_t)c * ld_m) * tv[c];
+                    for (int32_t c = 0; c < d.cols; ++c) acc += ld<T, A>(base + (int64_t)c * cnt) * tv[c];
                 }
             } else if (d.cols < 0) {
                 const T* base = Dp + d.off + off;
