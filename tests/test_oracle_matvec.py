@@ -111,3 +111,16 @@ def test_gmres_restart_and_cap(orc):
     x, it, rr, st = H.gmres(b, 1e-12, 5, 12)
     assert st == orc.ORC_ENOCONV and it == 12
     assert np.linalg.norm(b - H.matvec(x)) / np.linalg.norm(b) == pytest.approx(rr, rel=1e-9)
+
+
+def test_row_error_bound(orc):
+    """Per-row error of Algorithm 2 stays within 10 tol of the exact row,
+    relative to sum_j |A_ij x_j| (the bound the GPU full-size test uses)."""
+    for name in ("mq1m", "log1m"):
+        xy, b, kern, leaf, tol = inputs.workload(name, n=16384)
+        H = orc.OracleH(xy, kern, leaf, tol)
+        y = H.matvec(b)
+        rows = np.random.default_rng(5).choice(16384, 64, replace=False)
+        ye = orc.dense_rows(kern, xy, b, rows)
+        absrow = np.array([np.sum(np.abs(orc.entries(kern, xy, np.full(16384, i), np.arange(16384)) * b)) for i in rows])
+        assert np.max(np.abs(y[rows] - ye) / absrow) <= 10 * tol
