@@ -112,6 +112,14 @@ typedef enum {
                               on the FP16/BF16 operator (inner_prec) */
 } h2d_solve_mode;
 
+/* Right preconditioners (flexible GMRES: the preconditioned vectors are
+ * kept, so a nonlinear preconditioner such as the MLP is allowed). */
+typedef enum {
+    H2D_PC_NONE = 0,
+    H2D_PC_BLOCK_JACOBI = 1,  /* exact LU of each leaf's self block K(X, X) */
+    H2D_PC_MLP = 2            /* learned per-leaf correction (h2d_mlp_train) */
+} h2d_precond;
+
 typedef struct {
     int32_t mode;          /* h2d_solve_mode */
     int32_t restart;       /* GMRES restart length (e.g. 50) */
@@ -119,7 +127,7 @@ typedef struct {
     int32_t inner_prec;    /* REFINE: H2D_P_FP16 or H2D_P_BF16 */
     double inner_tol;      /* REFINE: relative tolerance of each inner solve */
     int32_t max_outer;     /* REFINE: cap on refinement steps */
-    int32_t pad;
+    int32_t precond;       /* h2d_precond, applied inside every (inner) GMRES */
 } h2d_solve_opts;
 
 typedef struct {
@@ -135,6 +143,69 @@ typedef struct {
  * the last iterate and info->relres its residual). */
 h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d_solve_opts* opts,
                      h2d_solve_info* info, void* stream);
+
+/* Block-Jacobi set-up: LU with partial pivoting of every leaf's self block
+ * (leaf boxes of at most 64 points).  Needed before solving with
+ * H2D_PC_BLOCK_JACOBI.  Errors: EUNSUPPORTED (a leaf above 64 points). */
+h2d_status h2d_bj_setup(h2d_t H, void* stream);
+
+/* z = M r for one of the set-up preconditioners (device FP64 vectors in
+ * caller order).  Asynchronous on `stream`. */
+h2d_status h2d_precond_apply(h2d_t H, int32_t precond, const double* r, double* z, void* stream);
+
+/* Learned per-leaf preconditioner (a shared MLP, 192 -> 256 -> 256 -> 64,
+ * ReLU).  Input of leaf X: box-relative coordinates of its points and the
+ * leaf residual normalised by |r_X| (64 slots each).  The correction on X
+ * is in residual form: z_i = s |r_X| (r_i / |r_X| + out_i), with s the
+ * least-squares scalar z ~ s r fitted on the training solves (so the
+ * untrained network is the preconditioner s I).  Training pairs come from
+ * the library's own solves for n_solves random r (every leaf gives
+ * (r_X, z_X)): leaf-block solves z_X = K(X, X)^{-1} r_X (default), or FP64
+ * GMRES solves A z = r.  The forward pass, backward pass and Adam steps run
+ * in this library's FP32 kernels.  Weights: packed FP32 [W1 (256 x 192), b1, W2 (256 x 256), b2,
+ * W3 (64 x 256), b3], row-major. */
+#define H2D_MLP_PARAMS 131648
+
+typedef enum {
+    H2D_MLP_TARGET_LEAF = 0,    /* z_X = K(X, X)^{-1} r_X: the method's leaf-block solves */
+    H2D_MLP_TARGET_GLOBAL = 1   /* z = A^{-1} r by FP64 GMRES, restricted to each leaf */
+} h2d_mlp_target;
+
+typedef struct {
+    int32_t n_solves;      /* random right-hand sides used for training pairs */
+    int32_t steps;         /* Adam steps */
+    int32_t batch;         /* leaves per step */
+    float lr;              /* Adam learning rate */
+    uint64_t seed;         /* right-hand sides, initial weights, batches */
+    double solve_tol;      /* GLOBAL targets: relative residual of the solves */
+    int32_t target;        /* h2d_mlp_target */
+    int32_t pad;
+} h2d_mlp_train_opts;
+
+typedef struct {
+    double seconds_data;   /* data-generating solves */
+    double seconds_train;  /* Adam steps */
+    float loss_first, loss_last;
+    int32_t n_samples;
+    int32_t solves_converged;
+    double scale;          /* fitted s (z ~ s r over the training solves) */
+} h2d_mlp_train_info;
+
+h2d_status h2d_mlp_train(h2d_t H, const h2d_mlp_train_opts* opts, h2d_mlp_train_info* info, void* stream);
+
+/* Copy the MLP weights out (host, H2D_MLP_PARAMS floats) and/or set them
+ * (host; marks the preconditioner ready).  `scale` (host, may be NULL)
+ * receives the output scale s when reading and sets it when writing.
+ * Any pointer may be NULL. */
+h2d_status h2d_mlp_weights(h2d_t H, float* out, const float* in, double* scale, void* stream);
+
+/* One forward + backward pass of the MLP on a batch, without a handle:
+ * W (H2D_MLP_PARAMS), X (B x 192), T (B x 64 targets), M (B x 64 mask of
+ * valid slots), grad (H2D_MLP_PARAMS): all device FP32, row-major.
+ * *loss (host) = sum M (out - T)^2 / (2 sum M); grad = its gradient.
+ * Synchronises `stream`. */
+h2d_status h2d_mlp_loss_grad(const float* W, const float* X, const float* T, const float* M, int32_t B,
+                             float* loss, float* grad, void* stream);
 
 typedef struct {
     int64_t n;

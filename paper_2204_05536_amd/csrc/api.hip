@@ -454,6 +454,51 @@ h2d_status h2d_profile_read(h2d_t H, h2d_profile* out)
     });
 }
 
+h2d_status h2d_bj_setup(h2d_t H, void* stream)
+{
+    return guarded([&] {
+        if (!H) fail(H2D_EINVAL, "NULL handle");
+        bj_setup(H->h, (hipStream_t)stream);
+    });
+}
+
+h2d_status h2d_precond_apply(h2d_t H, int32_t precond, const double* r, double* z, void* stream)
+{
+    return guarded([&] {
+        if (!H || !r || !z) fail(H2D_EINVAL, "NULL argument");
+        precond_apply(H->h, precond, r, z, (hipStream_t)stream);
+    });
+}
+
+h2d_status h2d_mlp_train(h2d_t H, const h2d_mlp_train_opts* opts, h2d_mlp_train_info* info, void* stream)
+{
+    return guarded([&] {
+        if (!H || !opts) fail(H2D_EINVAL, "NULL argument");
+        if (opts->n_solves < 1 || opts->steps < 0 || opts->batch < 1 || !(opts->lr > 0.f) ||
+            (opts->target == H2D_MLP_TARGET_GLOBAL && !(opts->solve_tol > 0.0)) ||
+            (opts->target != H2D_MLP_TARGET_LEAF && opts->target != H2D_MLP_TARGET_GLOBAL))
+            fail(H2D_EINVAL, "bad training options");
+        mlp_train(H->h, *opts, info, (hipStream_t)stream);
+    });
+}
+
+h2d_status h2d_mlp_weights(h2d_t H, float* out, const float* in, double* scale, void* stream)
+{
+    return guarded([&] {
+        if (!H) fail(H2D_EINVAL, "NULL handle");
+        mlp_weights(H->h, out, in, scale, (hipStream_t)stream);
+    });
+}
+
+h2d_status h2d_mlp_loss_grad(const float* W, const float* X, const float* T, const float* M, int32_t B, float* loss,
+                             float* grad, void* stream)
+{
+    return guarded([&] {
+        if (!W || !X || !T || !M || !loss || !grad || B < 1) fail(H2D_EINVAL, "bad argument");
+        *loss = mlp_loss_grad(W, X, T, M, B, grad, (hipStream_t)stream);
+    });
+}
+
 void h2d_destroy(h2d_t H)
 {
     if (!H) return;

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -116,6 +117,8 @@ struct KernelParams {
     double diag_value;
 };
 
+struct MlpState;
+
 struct Handle {
     int device = 0;
     int64_t n = 0;
@@ -166,6 +169,13 @@ struct Handle {
     DBuf<float> xs32, tpool32, ppool32, ypart32;
     int64_t ws_nrhs = 0;
 
+    // preconditioners
+    DBuf<double> bj_lu;        // per leaf: LU of the self block, m x m column-major
+    DBuf<int32_t> bj_piv;      // per tree row: pivot row chosen at that step of its leaf
+    DBuf<int64_t> bj_off;      // per leaf: offset into bj_lu
+    bool bj_ready = false;
+    std::shared_ptr<MlpState> mlp;
+
     double alg_bytes_fp64 = 0, alg_bytes_half = 0, flops = 0;
     double phase_bytes[2][5] = {{0}};   // [FP64, half][gather, A, reduce, B1, B2]
 
@@ -187,6 +197,15 @@ void profile_read(Handle& H, h2d_profile* out);
 void build_tree_and_lists(Handle& H, hipStream_t s);
 void build_factors(Handle& H, hipStream_t s);
 void make_half_pools(Handle& H, uint32_t mask, hipStream_t s);
+
+// precond.hip, mlp.hip
+void bj_setup(Handle& H, hipStream_t s);
+void precond_apply(Handle& H, int pc, const double* r, double* z, hipStream_t s);
+void mlp_apply(Handle& H, const double* r, double* z, hipStream_t s);
+void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info, hipStream_t s);
+void mlp_weights(Handle& H, float* out, const float* in, double* scale, hipStream_t s);
+float mlp_loss_grad(const float* W, const float* X, const float* T, const float* Mk, int32_t B, float* grad,
+                    hipStream_t s);
 
 // solve.hip
 h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_solve_opts& o,

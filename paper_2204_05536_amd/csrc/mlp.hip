@@ -1,0 +1,500 @@
+// Learned per-leaf preconditioner: a shared 3-layer MLP applied leaf by
+// leaf, used as a right preconditioner inside flexible GMRES.
+//
+// Input of leaf X (64 slots, slot i = the i-th point of X in tree order,
+// empty slots zero): [(x_i - c_x) / h (64), (y_i - c_y) / h (64),
+// r_i / |r_X| (64)], with c the box centre and h its half side.
+// Network: 192 -> 256 (ReLU) -> 256 (ReLU) -> 64, in residual form around
+// a fitted scale s: z_i = s |r_X| (r_i / |r_X| + out_i), so the map is
+// positively homogeneous in r and the untrained network (last layer zero)
+// is the preconditioner s I.  Training targets come from the method
+// itself: for random r, z = K(X, X)^{-1} r(X) leaf by leaf (the method's
+// leaf-block solves; default) or z = A^{-1} r by FP64 GMRES; s is the
+// least-squares scalar with z ~ s r, and every leaf contributes the pair
+// (r_X, z_X / (s |r_X|) - r_X / |r_X|).  Leaf targets are a deterministic
+// function of the leaf's geometry and residual; global targets add the
+// coupling beyond the leaf, which the leaf's input cannot see.
+#include "h2d_impl.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace h2d {
+
+constexpr int kIn = 192, kH = 256, kOut = 64;
+constexpr int64_t kOffW1 = 0, kOffB1 = kOffW1 + (int64_t)kH * kIn, kOffW2 = kOffB1 + kH,
+                  kOffB2 = kOffW2 + (int64_t)kH * kH, kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + (int64_t)kOut * kH,
+                  kParams = kOffB3 + kOut;
+static_assert(kParams == H2D_MLP_PARAMS, "parameter count");
+
+// ---------------------------------------------------------------------
+// FP32 GEMM: C (M x N, row-major, ldc) = alpha op(A) op(B) + beta C, with
+// op(A) M x K and op(B) K x N.  A row-major (lda) or, transA, its
+// transpose; same for B.  64 x 64 tiles, 256 threads, 4 x 4 outputs each,
+// K in steps of 16 through LDS.  Fixed summation order.
+// ---------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, const float* __restrict__ B, int ldb,
+       int transB, float* __restrict__ C, int ldc, float alpha, float beta)
+{
+    __shared__ float As[16][64 + 1];
+    __shared__ float Bs[16][64 + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int kk = e / 64, mm = e % 64;
+            const int gm = m0 + mm, gk = k0 + kk;
+            float a = 0.f;
+            if (gm < M && gk < K) a = transA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+            As[kk][mm] = a;
+            const int gn = n0 + mm;
+            float b = 0.f;
+            if (gn < N && gk < K) b = transB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+            Bs[kk][mm] = b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
+            if (gm < M && gn < N) {
+                float* c = C + (int64_t)gm * ldc + gn;
+                *c = alpha * acc[i][j] + (beta == 0.f ? 0.f : beta * *c);
+            }
+        }
+}
+
+static void gemm(int M, int N, int K, const float* A, int lda, bool tA, const float* B, int ldb, bool tB, float* C,
+                 int ldc, float alpha, float beta, hipStream_t s)
+{
+    dim3 g((N + 63) / 64, (M + 63) / 64);
+    k_gemm<<<g, 256, 0, s>>>(M, N, K, A, lda, tA ? 1 : 0, B, ldb, tB ? 1 : 0, C, ldc, alpha, beta);
+    HIPCK(hipGetLastError());
+}
+
+// Z (M x N) += bias (per column), then optional ReLU.
+__global__ void k_bias_act(int64_t M, int N, const float* __restrict__ bias, float* __restrict__ Z, int relu)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M * N; e += (int64_t)gridDim.x * blockDim.x) {
+        float v = Z[e] + bias[e % N];
+        Z[e] = relu ? fmaxf(v, 0.f) : v;
+    }
+}
+
+// G (M x N) *= [H > 0]  (ReLU derivative, H = the layer's output)
+__global__ void k_relu_back(int64_t M, int N, const float* __restrict__ Hh, float* __restrict__ G)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M * N; e += (int64_t)gridDim.x * blockDim.x)
+        if (!(Hh[e] > 0.f)) G[e] = 0.f;
+}
+
+// db (N) = column sums of G (M x N), fixed order.
+__global__ void k_colsum(int64_t M, int N, const float* __restrict__ G, float* __restrict__ db)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int64_t i = 0; i < M; ++i) s += G[i * N + j];
+    db[j] = s;
+}
+
+// dO = mask (O - T) / count; partial loss sums per block (fixed order).
+__global__ void k_mse(int64_t n, const float* __restrict__ O, const float* __restrict__ T, const float* __restrict__ Mk,
+                      float inv_count, float* __restrict__ dO, float* __restrict__ part)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const float d = (O[e] - T[e]) * Mk[e];
+        dO[e] = d * inv_count;
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m1,
+                       float* __restrict__ m2, float lr, float b1, float b2, float c1, float c2, float eps)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const float gg = g[e];
+        const float a = b1 * m1[e] + (1.f - b1) * gg, v = b2 * m2[e] + (1.f - b2) * gg * gg;
+        m1[e] = a;
+        m2[e] = v;
+        w[e] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------------
+// Forward and backward on a batch (X: B x 192, targets T and mask Mk:
+// B x 64).  Workspace: H1, H2 (B x 256), O (B x 64), G1, G2, GO.
+// ---------------------------------------------------------------------
+struct MlpWork {
+    int64_t cap = 0;
+    DBuf<float> h1, h2, o, g1, g2, go, part;
+    void ensure(int64_t B)
+    {
+        if (B <= cap) return;
+        h1.alloc(B * kH); h2.alloc(B * kH); o.alloc(B * kOut);
+        g1.alloc(B * kH); g2.alloc(B * kH); go.alloc(B * kOut);
+        part.alloc(1024);
+        cap = B;
+    }
+};
+
+static int grid_for(int64_t n) { return (int)std::min<int64_t>(4096, (n + 255) / 256); }
+
+static void forward(const float* W, const float* X, int64_t B, MlpWork& w, hipStream_t s)
+{
+    gemm((int)B, kH, kIn, X, kIn, false, W + kOffW1, kIn, true, w.h1.p, kH, 1.f, 0.f, s);
+    k_bias_act<<<grid_for(B * kH), 256, 0, s>>>(B, kH, W + kOffB1, w.h1.p, 1);
+    gemm((int)B, kH, kH, w.h1.p, kH, false, W + kOffW2, kH, true, w.h2.p, kH, 1.f, 0.f, s);
+    k_bias_act<<<grid_for(B * kH), 256, 0, s>>>(B, kH, W + kOffB2, w.h2.p, 1);
+    gemm((int)B, kOut, kH, w.h2.p, kH, false, W + kOffW3, kH, true, w.o.p, kOut, 1.f, 0.f, s);
+    k_bias_act<<<grid_for(B * kOut), 256, 0, s>>>(B, kOut, W + kOffB3, w.o.p, 0);
+    HIPCK(hipGetLastError());
+}
+
+// loss = sum mask (O - T)^2 / (2 count); grad in the packed layout.  The
+// loss is read back (synchronising) only when want_loss.
+static float loss_grad(const float* W, const float* X, const float* T, const float* Mk, int64_t B, float count,
+                       float* grad, MlpWork& w, hipStream_t s, bool want_loss = true)
+{
+    w.ensure(B);
+    forward(W, X, B, w, s);
+    const int nb = std::min<int64_t>(1024, (B * kOut + 255) / 256);
+    k_mse<<<nb, 256, 0, s>>>(B * kOut, w.o.p, T, Mk, 1.f / count, w.go.p, w.part.p);
+    // layer 3
+    gemm(kOut, kH, (int)B, w.go.p, kOut, true, w.h2.p, kH, false, grad + kOffW3, kH, 1.f, 0.f, s);
+    k_colsum<<<1, kOut, 0, s>>>(B, kOut, w.go.p, grad + kOffB3);
+    gemm((int)B, kH, kOut, w.go.p, kOut, false, W + kOffW3, kH, false, w.g2.p, kH, 1.f, 0.f, s);
+    k_relu_back<<<grid_for(B * kH), 256, 0, s>>>(B, kH, w.h2.p, w.g2.p);
+    // layer 2
+    gemm(kH, kH, (int)B, w.g2.p, kH, true, w.h1.p, kH, false, grad + kOffW2, kH, 1.f, 0.f, s);
+    k_colsum<<<1, kH, 0, s>>>(B, kH, w.g2.p, grad + kOffB2);
+    gemm((int)B, kH, kH, w.g2.p, kH, false, W + kOffW2, kH, false, w.g1.p, kH, 1.f, 0.f, s);
+    k_relu_back<<<grid_for(B * kH), 256, 0, s>>>(B, kH, w.h1.p, w.g1.p);
+    // layer 1
+    gemm(kH, kIn, (int)B, w.g1.p, kH, true, X, kIn, false, grad + kOffW1, kIn, 1.f, 0.f, s);
+    k_colsum<<<1, kH, 0, s>>>(B, kH, w.g1.p, grad + kOffB1);
+    HIPCK(hipGetLastError());
+    if (!want_loss) return 0.f;
+    std::vector<float> part(nb);
+    HIPCK(hipMemcpyAsync(part.data(), w.part.p, sizeof(float) * nb, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    double l = 0;
+    for (float v : part) l += v;
+    return (float)(l / (2.0 * count));
+}
+
+// ---------------------------------------------------------------------
+// Leaf features and corrections
+// ---------------------------------------------------------------------
+__device__ __forceinline__ uint32_t compact_bits(uint32_t v)
+{
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+    v = (v | (v >> 4)) & 0x00FF00FFu;
+    v = (v | (v >> 8)) & 0x0000FFFFu;
+    return v;
+}
+
+// One wave per leaf: features (nleaf x 192) and |r_X|.  Optionally also
+// the normalised target t_i = z_i / |r_X| and the slot mask.
+__global__ void __launch_bounds__(256)
+k_features(int32_t nleaf, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+           const uint32_t* __restrict__ key, int kappa, double R, const double* __restrict__ xyt,
+           const int32_t* __restrict__ perm, const double* __restrict__ r, const double* __restrict__ zt, double zscale,
+           float* __restrict__ F, float* __restrict__ rn, float* __restrict__ T, float* __restrict__ Mk)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t X = blockIdx.x * 4 + wave;
+    if (X >= nleaf) return;
+    const int32_t m = count[X], r0 = begin[X];
+    const bool on = lane < m;
+    const double ri = on ? r[perm[r0 + lane]] : 0.0;
+    double ss = ri * ri;
+    for (int d = 32; d > 0; d >>= 1) ss += __shfl_xor(ss, d, kWave);
+    const double nrm = sqrt(ss), inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    const uint32_t k = key[X];
+    const double h = R / (double)(1u << kappa);
+    const double cx = -R + (2.0 * compact_bits(k) + 1.0) * h, cy = -R + (2.0 * compact_bits(k >> 1) + 1.0) * h;
+    float* f = F + (int64_t)X * kIn;
+    f[lane] = on ? (float)((xyt[2 * (r0 + lane)] - cx) / h) : 0.f;
+    f[64 + lane] = on ? (float)((xyt[2 * (r0 + lane) + 1] - cy) / h) : 0.f;
+    f[128 + lane] = on ? (float)(ri * inv) : 0.f;
+    if (lane == 0) rn[X] = (float)nrm;
+    if (T) {
+        T[(int64_t)X * kOut + lane] = on ? (float)((zt[perm[r0 + lane]] * zscale - ri) * inv) : 0.f;
+        Mk[(int64_t)X * kOut + lane] = (on && nrm > 0.0) ? 1.f : 0.f;
+    }
+}
+
+// z(X) = s (r(X) + |r_X| O(X)) in caller order.
+__global__ void k_correction(int32_t nleaf, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+                             const int32_t* __restrict__ perm, const float* __restrict__ O, const float* __restrict__ rn,
+                             double s, const double* __restrict__ r, double* __restrict__ z)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t X = blockIdx.x * 4 + wave;
+    if (X >= nleaf) return;
+    if (lane < count[X]) {
+        const int32_t p = perm[begin[X] + lane];
+        z[p] = s * (r[p] + (double)O[(int64_t)X * kOut + lane] * (double)rn[X]);
+    }
+}
+
+// Counter-based uniform numbers in [-1, 1): splitmix64 of (seed, index).
+__device__ __forceinline__ double uniform_pm1(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void k_random(int64_t n, uint64_t seed, double* __restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = uniform_pm1(seed, (uint64_t)e);
+}
+
+// Gather rows idx[b] of F (192), T and Mk (64) into a batch.
+__global__ void k_gather_batch(int32_t B, const int32_t* __restrict__ idx, const float* __restrict__ F,
+                               const float* __restrict__ T, const float* __restrict__ Mk, float* __restrict__ Fb,
+                               float* __restrict__ Tb, float* __restrict__ Mb)
+{
+    const int32_t b = blockIdx.x;
+    if (b >= B) return;
+    const int64_t s = idx[b];
+    for (int e = threadIdx.x; e < kIn; e += blockDim.x) Fb[(int64_t)b * kIn + e] = F[s * kIn + e];
+    for (int e = threadIdx.x; e < kOut; e += blockDim.x) {
+        Tb[(int64_t)b * kOut + e] = T[s * kOut + e];
+        Mb[(int64_t)b * kOut + e] = Mk[s * kOut + e];
+    }
+}
+
+struct MlpState {
+    double scale = 1.0;   // s: z ~ s r over the training solves
+    DBuf<float> w, m1, m2, grad;
+    MlpWork work;
+    DBuf<float> feat, rn;
+    int64_t feat_cap = 0;
+    bool ready = false;
+};
+
+MlpState& mlp_state(Handle& H)
+{
+    if (!H.mlp) H.mlp = std::make_shared<MlpState>();
+    return *H.mlp;
+}
+
+void mlp_apply(Handle& H, const double* r, double* z, hipStream_t s)
+{
+    MlpState& S = mlp_state(H);
+    if (!S.ready) fail(H2D_EINVAL, "the MLP preconditioner was not trained (h2d_mlp_train) or loaded");
+    const Level& LL = H.lev[H.kappa];
+    const int32_t nleaf = (int32_t)LL.nbox;
+    if (S.feat_cap < nleaf) {
+        S.feat.alloc((size_t)nleaf * kIn);
+        S.rn.alloc(nleaf);
+        S.feat_cap = nleaf;
+    }
+    S.work.ensure(nleaf);
+    k_features<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, LL.key.p, H.kappa, H.R, H.xyt.p,
+                                               H.perm.p, r, nullptr, 0.0, S.feat.p, S.rn.p, nullptr, nullptr);
+    forward(S.w.p, S.feat.p, nleaf, S.work, s);
+    k_correction<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, H.perm.p, S.work.o.p, S.rn.p, S.scale,
+                                                 r, z);
+    HIPCK(hipGetLastError());
+}
+
+// Xavier-uniform initial weights from the counter-based generator.
+__global__ void k_init_w(float* __restrict__ w, uint64_t seed)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < kParams; e += (int64_t)gridDim.x * blockDim.x) {
+        float lim = 0.f;
+        if (e < kOffB1) lim = sqrtf(6.f / (kIn + kH));
+        else if (e >= kOffW2 && e < kOffB2) lim = sqrtf(6.f / (kH + kH));
+        // the last layer starts at zero: the untrained preconditioner is s I
+        w[e] = lim * (float)uniform_pm1(seed, (uint64_t)e);
+    }
+}
+
+static void ensure_weights(MlpState& S, hipStream_t s)
+{
+    if (S.w.p) return;
+    S.w.alloc(kParams);
+    S.m1.alloc(kParams);
+    S.m2.alloc(kParams);
+    S.grad.alloc(kParams);
+    HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * kParams, s));
+    HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
+}
+
+void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info, hipStream_t s)
+{
+    MlpState& S = mlp_state(H);
+    const Level& LL = H.lev[H.kappa];
+    const int32_t nleaf = (int32_t)LL.nbox;
+    const int64_t n = H.n;
+    const int ns = o.n_solves;
+    auto t0 = std::chrono::steady_clock::now();
+    // training pairs from the method's own FP64 solves
+    const int64_t nsamp = (int64_t)ns * nleaf;
+    DBuf<float> F, T, Mk, rn;
+    F.alloc((size_t)nsamp * kIn);
+    T.alloc((size_t)nsamp * kOut);
+    Mk.alloc((size_t)nsamp * kOut);
+    rn.alloc(nsamp);
+    h2d_solve_opts so{};
+    so.mode = H2D_SOLVE_PLAIN;
+    so.restart = 50;
+    so.max_iter = 500;
+    so.precond = H2D_PC_NONE;
+    int solves_ok = 0;
+    if (o.target == H2D_MLP_TARGET_LEAF && !H.bj_ready) bj_setup(H, s);
+    DBuf<double> R, Z;
+    R.alloc((size_t)n * ns);
+    Z.alloc((size_t)n * ns);
+    double zr = 0.0, rr = 0.0;
+    for (int q = 0; q < ns; ++q) {
+        double* rq = R.p + (int64_t)q * n;
+        double* zq = Z.p + (int64_t)q * n;
+        k_random<<<grid_for(n), 256, 0, s>>>(n, o.seed + 7919ull * (uint64_t)q, rq);
+        if (o.target == H2D_MLP_TARGET_GLOBAL) {
+            h2d_solve_info si{};
+            h2d_status st = solve(H, rq, zq, o.solve_tol, so, &si, s);
+            if (st == H2D_OK) ++solves_ok;
+        } else {
+            precond_apply(H, H2D_PC_BLOCK_JACOBI, rq, zq, s);
+            ++solves_ok;
+        }
+        std::vector<double> hr(n), hz(n);
+        HIPCK(hipMemcpyAsync(hr.data(), rq, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(hz.data(), zq, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < n; ++i) { zr += hz[i] * hr[i]; rr += hr[i] * hr[i]; }
+    }
+    S.scale = rr > 0.0 ? zr / rr : 1.0;
+    if (!(S.scale != 0.0) || !std::isfinite(S.scale)) S.scale = 1.0;
+    for (int q = 0; q < ns; ++q) {
+        k_features<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, LL.key.p, H.kappa, H.R, H.xyt.p,
+                                                   H.perm.p, R.p + (int64_t)q * n, Z.p + (int64_t)q * n,
+                                                   1.0 / S.scale, F.p + (int64_t)q * nleaf * kIn,
+                                                   rn.p + (int64_t)q * nleaf, T.p + (int64_t)q * nleaf * kOut,
+                                                   Mk.p + (int64_t)q * nleaf * kOut);
+        HIPCK(hipGetLastError());
+    }
+    HIPCK(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    // training
+    ensure_weights(S, s);
+    if (!S.ready) {
+        k_init_w<<<256, 256, 0, s>>>(S.w.p, o.seed ^ 0xA5A5A5A5ull);
+        HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * kParams, s));
+        HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
+    }
+    const int B = std::max(1, std::min<int>(o.batch, (int)nsamp));
+    DBuf<float> Fb, Tb, Mb;
+    DBuf<int32_t> idx;
+    Fb.alloc((size_t)B * kIn);
+    Tb.alloc((size_t)B * kOut);
+    Mb.alloc((size_t)B * kOut);
+    idx.alloc(B);
+    std::vector<int32_t> hidx(B);
+    uint64_t st = o.seed * 6364136223846793005ull + 1442695040888963407ull;
+    float first = 0.f, last = 0.f;
+    const float b1 = 0.9f, b2 = 0.999f;
+    for (int it = 0; it < o.steps; ++it) {
+        for (int b = 0; b < B; ++b) {   // host LCG draw of the batch indices
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            hidx[b] = (int32_t)((st >> 33) % (uint64_t)nsamp);
+        }
+        // the previous step's kernels read idx: finish them before reuse
+        HIPCK(hipStreamSynchronize(s));
+        HIPCK(hipMemcpyAsync(idx.p, hidx.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+        k_gather_batch<<<B, 64, 0, s>>>(B, idx.p, F.p, T.p, Mk.p, Fb.p, Tb.p, Mb.p);
+        // valid slots of the batch: the points of each sampled leaf
+        double cnt = 0;
+        for (int b = 0; b < B; ++b) cnt += LL.h_count[hidx[b] % nleaf];
+        const bool report = it == 0 || it + 1 == o.steps;
+        const float L = loss_grad(S.w.p, Fb.p, Tb.p, Mb.p, B, (float)std::max(1.0, cnt), S.grad.p, S.work, s, report);
+        if (it == 0) first = L;
+        if (report) last = L;
+        const float c1 = 1.f - std::pow(b1, (float)(it + 1)), c2 = 1.f - std::pow(b2, (float)(it + 1));
+        k_adam<<<grid_for(kParams), 256, 0, s>>>(kParams, S.w.p, S.grad.p, S.m1.p, S.m2.p, o.lr, b1, b2, c1, c2, 1e-8f);
+        HIPCK(hipGetLastError());
+    }
+    HIPCK(hipStreamSynchronize(s));
+    S.ready = true;
+    auto t2 = std::chrono::steady_clock::now();
+    if (info) {
+        info->seconds_data = std::chrono::duration<double>(t1 - t0).count();
+        info->seconds_train = std::chrono::duration<double>(t2 - t1).count();
+        info->loss_first = first;
+        info->loss_last = last;
+        info->n_samples = (int32_t)nsamp;
+        info->solves_converged = solves_ok;
+        info->scale = S.scale;
+    }
+}
+
+void mlp_weights(Handle& H, float* out, const float* in, double* scale, hipStream_t s)
+{
+    MlpState& S = mlp_state(H);
+    if (in && scale) S.scale = *scale;
+    if (out && scale) *scale = S.scale;
+    if (in) {
+        ensure_weights(S, s);
+        HIPCK(hipMemcpyAsync(S.w.p, in, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
+        HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * kParams, s));
+        HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
+        S.ready = true;
+    }
+    if (out) {
+        if (!S.w.p) fail(H2D_EINVAL, "no MLP weights");
+        HIPCK(hipMemcpyAsync(out, S.w.p, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
+    }
+    HIPCK(hipStreamSynchronize(s));
+}
+
+float mlp_loss_grad(const float* W, const float* X, const float* T, const float* Mk, int32_t B, float* grad,
+                    hipStream_t s)
+{
+    MlpWork w;
+    std::vector<float> hm((size_t)B * kOut);
+    HIPCK(hipMemcpyAsync(hm.data(), Mk, sizeof(float) * hm.size(), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    double cnt = 0;
+    for (float v : hm) cnt += v;
+    return loss_grad(W, X, T, Mk, B, (float)std::max(1.0, cnt), grad, w, s);
+}
+
+}  // namespace h2d

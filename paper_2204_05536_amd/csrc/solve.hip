@@ -136,16 +136,19 @@ struct GmresResult {
     bool converged = false;
 };
 
-// GMRES(restart) for A_prec x = rhs, x0 = 0.  Convergence is judged by the
-// true residual |rhs - A_prec x| / |rhs| <= tol at each restart.
+// GMRES(restart) for A_prec x = rhs, x0 = 0, optionally right-
+// preconditioned in the flexible form (z_j = M v_j kept, x += Z y).
+// Convergence is judged by the true residual |rhs - A_prec x| / |rhs| <= tol
+// at each restart.
 static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, double tol, int restart, int max_iter,
-                         hipStream_t s)
+                         int precond, hipStream_t s)
 {
     const int64_t n = H.n;
     const int m = restart;
     Blas B(s, n, m + 1);
-    DBuf<double> Vb, w, r, yv;
+    DBuf<double> Vb, Zb, w, r, yv;
     Vb.alloc((size_t)n * (m + 1));
+    if (precond != H2D_PC_NONE) Zb.alloc((size_t)n * m);
     w.alloc(n);
     r.alloc(n);
     yv.alloc(m + 1);
@@ -175,7 +178,13 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
         for (; j < m && R.iters < max_iter; ) {
             ++R.iters;
             double* vj1 = Vb.p + (int64_t)(j + 1) * n;
-            launch_matvec(H, Vb.p + (int64_t)j * n, vj1, 1, n, prec, s);
+            if (precond != H2D_PC_NONE) {
+                double* zj = Zb.p + (int64_t)j * n;
+                precond_apply(H, precond, Vb.p + (int64_t)j * n, zj, s);
+                launch_matvec(H, zj, vj1, 1, n, prec, s);
+            } else {
+                launch_matvec(H, Vb.p + (int64_t)j * n, vj1, 1, n, prec, s);
+            }
             // two passes of classical Gram-Schmidt
             std::vector<double> hc(j + 2, 0.0);
             for (int pass = 0; pass < 2; ++pass) {
@@ -210,7 +219,7 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
             y[i] = sum / Hm[(size_t)i * (m + 1) + i];
         }
         HIPCK(hipMemcpyAsync(yv.p, y.data(), sizeof(double) * j, hipMemcpyHostToDevice, s));
-        k_add_comb<<<grid, 256, 0, s>>>(x, Vb.p, n, j, yv.p, n);
+        k_add_comb<<<grid, 256, 0, s>>>(x, precond != H2D_PC_NONE ? Zb.p : Vb.p, n, j, yv.p, n);
         HIPCK(hipGetLastError());
         ++R.restarts;
     }
@@ -225,8 +234,10 @@ h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_s
     const int64_t n = H.n;
     h2d_solve_info I{};
     bool ok = false;
+    if (o.precond == H2D_PC_BLOCK_JACOBI && !H.bj_ready) fail(H2D_EINVAL, "block-Jacobi was not set up (h2d_bj_setup)");
+    if (o.precond < H2D_PC_NONE || o.precond > H2D_PC_MLP) fail(H2D_EINVAL, "unknown preconditioner");
     if (o.mode == H2D_SOLVE_PLAIN) {
-        GmresResult R = gmres(H, H2D_P_FP64, b, x, rtol, o.restart, o.max_iter, s);
+        GmresResult R = gmres(H, H2D_P_FP64, b, x, rtol, o.restart, o.max_iter, o.precond, s);
         I.iters = R.iters; I.outer = R.restarts; I.relres = R.relres;
         ok = R.converged;
     } else if (o.mode == H2D_SOLVE_REFINE) {
@@ -244,7 +255,7 @@ h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_s
         int outer = 0, iters = 0;
         const int max_outer = o.max_outer > 0 ? o.max_outer : 50;
         while (rel > rtol && outer < max_outer && iters < o.max_iter) {
-            GmresResult R = gmres(H, o.inner_prec, r.p, d.p, o.inner_tol, o.restart, o.max_iter - iters, s);
+            GmresResult R = gmres(H, o.inner_prec, r.p, d.p, o.inner_tol, o.restart, o.max_iter - iters, o.precond, s);
             iters += R.iters;
             ++outer;
             k_axpy<<<grid, 256, 0, s>>>(x, d.p, 1.0, n);

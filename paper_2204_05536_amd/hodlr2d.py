@@ -23,9 +23,12 @@ KINDS = {"log": 0, "invr": 1, "mq": 2, "gauss": 3, "phi1": 4, "phi2": 5, "sep": 
 DIAG = {"replace": 0, "add": 1, "formula": 2}
 PREC = {"fp64": 0, "fp16": 1, "bf16": 2}
 SOLVE_PLAIN, SOLVE_REFINE = 0, 1
+PRECOND = {"none": 0, "bj": 1, "mlp": 2}
 
 EXPORTED = ["h2d_build", "h2d_matvec", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
-            "h2d_profile_enable", "h2d_profile_read", "h2d_destroy", "h2d_last_error"]
+            "h2d_profile_enable", "h2d_profile_read", "h2d_bj_setup", "h2d_precond_apply",
+            "h2d_mlp_train", "h2d_mlp_weights", "h2d_mlp_loss_grad", "h2d_destroy", "h2d_last_error"]
+MLP_PARAMS = 131648
 PHASES = ["gather", "phaseA", "reduce", "phaseB1", "phaseB2"]
 
 
@@ -41,7 +44,7 @@ class h2d_kernel(C.Structure):
 
 class h2d_solve_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32), ("inner_prec", C.c_int32),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("pad", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("precond", C.c_int32)]
 
 
 class h2d_solve_info(C.Structure):
@@ -59,6 +62,17 @@ class h2d_stats(C.Structure):
 
 class h2d_profile(C.Structure):
     _fields_ = [("count", C.c_int32), ("prec", C.c_int32), ("ms", C.c_double * 5), ("bytes", C.c_double * 5)]
+
+
+class h2d_mlp_train_opts(C.Structure):
+    _fields_ = [("n_solves", C.c_int32), ("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("seed", C.c_uint64), ("solve_tol", C.c_double), ("target", C.c_int32), ("pad", C.c_int32)]
+
+
+class h2d_mlp_train_info(C.Structure):
+    _fields_ = [("seconds_data", C.c_double), ("seconds_train", C.c_double), ("loss_first", C.c_float),
+                ("loss_last", C.c_float), ("n_samples", C.c_int32), ("solves_converged", C.c_int32),
+                ("scale", C.c_double)]
 
 
 _lib = None
@@ -90,6 +104,16 @@ def load():
     L.h2d_profile_enable.restype = C.c_int
     L.h2d_profile_read.argtypes = [P, C.POINTER(h2d_profile)]
     L.h2d_profile_read.restype = C.c_int
+    L.h2d_bj_setup.argtypes = [P, P]
+    L.h2d_bj_setup.restype = C.c_int
+    L.h2d_precond_apply.argtypes = [P, C.c_int32, P, P, P]
+    L.h2d_precond_apply.restype = C.c_int
+    L.h2d_mlp_train.argtypes = [P, C.POINTER(h2d_mlp_train_opts), C.POINTER(h2d_mlp_train_info), P]
+    L.h2d_mlp_train.restype = C.c_int
+    L.h2d_mlp_weights.argtypes = [P, P, P, C.POINTER(C.c_double), P]
+    L.h2d_mlp_weights.restype = C.c_int
+    L.h2d_mlp_loss_grad.argtypes = [P, P, P, P, C.c_int32, C.POINTER(C.c_float), P, P]
+    L.h2d_mlp_loss_grad.restype = C.c_int
     L.h2d_destroy.argtypes = [P]
     L.h2d_destroy.restype = None
     L.h2d_last_error.argtypes = []
@@ -182,12 +206,21 @@ class HODLR2D:
         _check(load().h2d_matvec(self._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs, n, PREC[prec], _stream()))
         return y
 
+    def bj_setup(self):
+        _check(load().h2d_bj_setup(self._h, _stream()))
+
+    def precond_apply(self, r, precond="bj"):
+        r = r.contiguous()
+        z = torch.empty_like(r)
+        _check(load().h2d_precond_apply(self._h, PRECOND[precond], _dev_f64(r, "r"), _dev_f64(z, "z"), _stream()))
+        return z
+
     def solve(self, b, tol=1e-8, restart=50, max_iter=2500, mode="plain", inner_prec="fp16", inner_tol=1e-4,
-              max_outer=50):
+              max_outer=50, precond="none"):
         b = b.contiguous()
         x = torch.empty_like(b)
         o = h2d_solve_opts(SOLVE_PLAIN if mode == "plain" else SOLVE_REFINE, int(restart), int(max_iter),
-                           PREC[inner_prec], float(inner_tol), int(max_outer), 0)
+                           PREC[inner_prec], float(inner_tol), int(max_outer), PRECOND[precond])
         info = h2d_solve_info()
         st = load().h2d_solve(self._h, _dev_f64(b, "b"), _dev_f64(x, "x"), float(tol), C.byref(o), C.byref(info),
                               _stream())
@@ -206,5 +239,40 @@ class HODLR2D:
         return {"count": p.count, "prec": p.prec,
                 "ms": dict(zip(PHASES, list(p.ms))), "bytes": dict(zip(PHASES, list(p.bytes)))}
 
+    def mlp_train(self, n_solves=16, steps=1500, batch=4096, lr=5e-4, seed=1234, solve_tol=1e-10,
+                  target="leaf") -> dict:
+        o = h2d_mlp_train_opts(int(n_solves), int(steps), int(batch), float(lr), int(seed), float(solve_tol),
+                               {"leaf": 0, "global": 1}[target], 0)
+        info = h2d_mlp_train_info()
+        _check(load().h2d_mlp_train(self._h, C.byref(o), C.byref(info), _stream()))
+        return {f: getattr(info, f) for f, _ in h2d_mlp_train_info._fields_}
+
+    def mlp_weights(self, set_to=None, scale=None):
+        """Return (weights float32, scale); set them first if given."""
+        import numpy as np
+        inp = None
+        if set_to is not None:
+            inp = np.ascontiguousarray(set_to, dtype=np.float32)
+            assert inp.size == MLP_PARAMS
+        sc = C.c_double(1.0 if scale is None else float(scale))
+        if inp is not None:
+            _check(load().h2d_mlp_weights(self._h, None, C.c_void_p(inp.ctypes.data), C.byref(sc), _stream()))
+        out = np.empty(MLP_PARAMS, np.float32)
+        _check(load().h2d_mlp_weights(self._h, C.c_void_p(out.ctypes.data), None, C.byref(sc), _stream()))
+        return out, sc.value
+
     def export(self, path, factors=True):
         _check(load().h2d_export(self._h, str(path).encode(), 1 if factors else 0))
+
+
+def mlp_loss_grad(W, X, T, M):
+    """One MLP forward + backward on device FP32 tensors; returns (loss, grad)."""
+    for t, nm in ((W, "W"), (X, "X"), (T, "T"), (M, "M")):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError(f"{nm} must be a contiguous float32 device tensor")
+    g = torch.empty_like(W)
+    loss = C.c_float()
+    _check(load().h2d_mlp_loss_grad(C.c_void_p(W.data_ptr()), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                    C.c_void_p(M.data_ptr()), int(X.shape[0]), C.byref(loss),
+                                    C.c_void_p(g.data_ptr()), _stream()))
+    return float(loss.value), g

@@ -1,0 +1,119 @@
+"""GPU preconditioners: block-Jacobi (exact leaf LU) against numpy's solve
+on the oracle's self blocks, flexible GMRES with it, the MLP's forward and
+backward kernels against the FP64 oracle, and what the trained network
+gains inside FGMRES, judged by the true FP64 residual of the HODLR2D
+operator."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+from paper_2204_05536_amd import inputs
+from tests.gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2204_05536_amd import hodlr2d
+    return hodlr2d
+
+
+def test_bj_apply_matches_leaf_solves(orc, tmp_path):
+    xy, b, kern, leaf, tol = inputs.workload("log4096")
+    O = orc.OracleH(xy, kern, leaf, tol)
+    p = tmp_path / "o.h2dx"
+    O.export(p)
+    H = _lib().HODLR2D.import_file(p)
+    H.bj_setup()
+    r = np.random.default_rng(3).uniform(-1, 1, xy.shape[0])
+    z = host(H.precond_apply(dev(r), "bj"))
+    perm = O.perm(); L = O.level(O.kappa)
+    t, s = O.near_table()
+    zr = np.empty_like(r)
+    for q in np.nonzero(t == s)[0]:
+        X = t[q]
+        idx = perm[L["begin"][X]:L["begin"][X] + L["count"][X]]
+        zr[idx] = np.linalg.solve(O.near_factor(q), r[idx])
+    assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+
+
+def test_fgmres_block_jacobi_converges():
+    xy, b, kern, leaf, tol = inputs.workload("log4096")
+    H = _lib().HODLR2D.build(dev(xy), kern, leaf, tol)
+    H.bj_setup()
+    x0, i0 = H.solve(dev(b), tol=1e-8)
+    x1, i1 = H.solve(dev(b), tol=1e-8, precond="bj")
+    say("plain", i0, "bj", i1)
+    assert i1["converged"] and i1["relres"] <= 1e-8
+    assert i1["iters"] <= i0["iters"]
+    assert np.linalg.norm(host(x1) - host(x0)) <= 1e-7 * np.linalg.norm(host(x0))
+
+
+@pytest.mark.parametrize("B", [1, 37, 300])
+def test_mlp_loss_grad_matches_oracle(B):
+    rng = np.random.default_rng(B)
+    w = rng.normal(0, 0.08, omlp.NPARAMS)
+    X = rng.normal(size=(B, omlp.IN)); T = rng.normal(size=(B, omlp.OUT))
+    M = (rng.uniform(size=(B, omlp.OUT)) < 0.6).astype(float)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    L, g = _lib().mlp_loss_grad(f32(w), f32(X), f32(T), f32(M))
+    # the oracle on the same FP32-rounded inputs, in FP64
+    r32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    Lr, gr = omlp.loss_grad(r32(w), r32(X), r32(T), r32(M))
+    g = host(g).astype(np.float64)
+    assert abs(L - Lr) <= 1e-5 * abs(Lr)
+    assert np.linalg.norm(g - gr) <= 1e-5 * np.linalg.norm(gr)
+    assert np.max(np.abs(g - gr)) <= 1e-4 * np.max(np.abs(gr))
+
+
+@pytest.fixture(scope="module")
+def trained():
+    xy, b, kern, leaf, tol = inputs.workload("log1m", n=1 << 16)
+    H = _lib().HODLR2D.build(dev(xy), kern, leaf, tol, precs=("fp16",))
+    info = H.mlp_train(n_solves=48, steps=2000, batch=4096, lr=5e-4, seed=11)
+    say("train", info)
+    return H, b, info
+
+
+def test_mlp_training_reduces_loss(trained):
+    """Training lowers the loss, and on a held-out right-hand side the
+    trained network is closer to its training target, the leaf-block solve
+    K(X, X)^{-1} r(X), than its untrained start s I is."""
+    H, b, info = trained
+    assert info["solves_converged"] == 48
+    assert info["loss_last"] < info["loss_first"]
+    H.bj_setup()
+    r = dev(np.random.default_rng(99).uniform(-1, 1, b.shape[0]))
+    zb = host(H.precond_apply(r, "bj"))
+    e_mlp = np.linalg.norm(host(H.precond_apply(r, "mlp")) - zb)
+    e_s = np.linalg.norm(info["scale"] * host(r) - zb)
+    say("held-out |M r - K_XX^-1 r| / |K_XX^-1 r|: s I", e_s / np.linalg.norm(zb), "MLP", e_mlp / np.linalg.norm(zb))
+    assert e_mlp < e_s
+
+
+def test_mlp_preconditioner_gain(trained):
+    """FGMRES with the trained MLP against plain GMRES and block-Jacobi on
+    the same system (log kernel, diagonal N, N = 2^16): every solve must
+    reach 1e-8 in the true FP64 residual; the iteration counts are the gain
+    (printed; the MLP must not need more iterations than plain GMRES)."""
+    H, b, _ = trained
+    H.bj_setup()
+    bb = dev(b)
+    res = {}
+    for pc in ("none", "bj", "mlp"):
+        x, info = H.solve(bb, tol=1e-8, precond=pc)
+        assert info["converged"] and info["relres"] <= 1e-8, (pc, info)
+        r = host(bb - H.matvec(x))
+        assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
+        res[pc] = info["iters"]
+    say("iterations", res)
+    assert res["mlp"] <= res["none"] + 1
+
+
+def test_chosen_form_refine_fp16_mlp(trained):
+    """FP16 factors + FP64 refinement + MLP-preconditioned inner FGMRES."""
+    H, b, _ = trained
+    x, info = H.solve(dev(b), tol=1e-8, mode="refine", inner_prec="fp16", inner_tol=1e-4, precond="mlp")
+    say("chosen form", info)
+    assert info["converged"] and info["relres"] <= 1e-8
