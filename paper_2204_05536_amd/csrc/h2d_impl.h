@@ -164,6 +164,11 @@ struct Handle {
     DBuf<int2> b1items;         // phase-B1 work: (box at level kappa - 1, first row of a 64-row chunk)
     int64_t n_b1 = 0;
 
+    // multi-RHS work (blocks of 16 right-hand sides, point-major)
+    DBuf<double> xs_mr, tp_mr, pp_mr, yp_mr;
+    DBuf<const int32_t*> lvl_ptrs;   // begin, count, parent, il_ptr per level (device copies of the pointers)
+    int mr_cap = 0;
+
     // work vectors
     DBuf<double> xs, tpool, ppool, ypart;    // FP64: x in tree order, t, partials, ancestor sums
     DBuf<float> xs32, tpool32, ppool32, ypart32;
@@ -189,6 +194,7 @@ struct Handle {
 // kernels.hip
 void finalize(Handle& H, hipStream_t s);
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s);
+void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s);
 void ensure_workspace(Handle& H, int nrhs);
 void profile_enable(Handle& H, bool on);
 void profile_read(Handle& H, h2d_profile* out);

@@ -492,6 +492,10 @@ void profile_read(Handle& H, h2d_profile* out)
 
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s)
 {
+    if (nrhs > 1 && prec == H2D_P_FP64) {   // blocks of 16 right-hand sides on the matrix cores
+        launch_matvec_mr(H, x, y, nrhs, ld, s);
+        return;
+    }
     ensure_workspace(H, 1);
     H.prof_prec = prec;
     for (int r = 0; r < nrhs; ++r) {
