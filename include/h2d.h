@@ -259,6 +259,31 @@ typedef struct {
 h2d_status h2d_profile_enable(h2d_t H, int32_t on);
 h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
 
+/* Tile tuning: times FP64 products with nrhs right-hand sides for each
+ * candidate number of V rows per phase-A work item (128, 256, 512) and
+ * keeps the fastest for H.  chosen (host, may be NULL) receives the pick,
+ * ms (host, 3 floats, may be NULL) the measured milliseconds. */
+h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, float* ms);
+
+/* Batched products: the FP64 products y_i = A_i x_i of `count` built
+ * handles (nrhs right-hand sides each, x_i / y_i device column-major with
+ * leading dimension ld[i]) are captured once into a HIP graph and replayed
+ * by h2d_batch_launch with a single graph launch on the caller's stream.
+ * The buffers are bound at creation (hosts arrays x, y, ld of length
+ * count); the handles must outlive the batch, must not be used
+ * concurrently with a launch, and must not be re-tuned (h2d_autotune,
+ * h2d_set_item_rows) while the batch exists: the graph holds their
+ * schedule and work-space addresses. */
+/* Sets the number of V rows per phase-A work item explicitly (16..512)
+ * and rebuilds H's product schedule; H2D_EINVAL outside that range. */
+h2d_status h2d_set_item_rows(h2d_t H, int32_t rows, void* stream);
+
+typedef struct h2d_batch_s* h2d_batch_t;
+h2d_status h2d_batch_create(h2d_t const* handles, int32_t count, int32_t nrhs, double* const* x, double* const* y,
+                            const int64_t* ld, h2d_batch_t* out);
+h2d_status h2d_batch_launch(h2d_batch_t B, void* stream);
+void h2d_batch_destroy(h2d_batch_t B);
+
 /* Free every allocation of H (NULL is a no-op). */
 void h2d_destroy(h2d_t H);
 

@@ -499,6 +499,59 @@ h2d_status h2d_mlp_loss_grad(const float* W, const float* X, const float* T, con
     });
 }
 
+h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, float* ms)
+{
+    return guarded([&] {
+        if (!H || nrhs < 1) fail(H2D_EINVAL, "bad argument");
+        autotune(H->h, nrhs, (hipStream_t)stream, chosen, ms);
+    });
+}
+
+h2d_status h2d_set_item_rows(h2d_t H, int32_t rows, void* stream)
+{
+    return guarded([&] {
+        if (!H || rows < 16 || rows > kPhaseARows) fail(H2D_EINVAL, "item rows must lie in 16..512");
+        H->h.a_rows = rows;
+        finalize(H->h, (hipStream_t)stream);
+    });
+}
+
+struct h2d_batch_s {
+    Batch* b;
+};
+
+h2d_status h2d_batch_create(h2d_t const* handles, int32_t count, int32_t nrhs, double* const* x, double* const* y,
+                            const int64_t* ld, h2d_batch_t* out)
+{
+    return guarded([&] {
+        if (!handles || !x || !y || !ld || !out || count < 1 || nrhs < 1) fail(H2D_EINVAL, "bad argument");
+        *out = nullptr;
+        std::vector<Handle*> hs(count);
+        for (int i = 0; i < count; ++i) {
+            if (!handles[i] || !x[i] || !y[i] || ld[i] < handles[i]->h.n) fail(H2D_EINVAL, "bad batch member");
+            hs[i] = &handles[i]->h;
+        }
+        auto* r = new h2d_batch_s{batch_create(hs.data(), count, nrhs, x, y, ld)};
+        *out = r;
+    });
+}
+
+h2d_status h2d_batch_launch(h2d_batch_t B, void* stream)
+{
+    return guarded([&] {
+        if (!B) fail(H2D_EINVAL, "NULL batch");
+        batch_launch(B->b, (hipStream_t)stream);
+    });
+}
+
+void h2d_batch_destroy(h2d_batch_t B)
+{
+    if (!B) return;
+    (void)hipDeviceSynchronize();
+    batch_destroy(B->b);
+    delete B;
+}
+
 void h2d_destroy(h2d_t H)
 {
     if (!H) return;

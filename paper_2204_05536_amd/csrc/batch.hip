@@ -1,0 +1,129 @@
+// Batched products and tile tuning.
+//
+// A batch is a set of built handles whose products (each with its own
+// right-hand sides) are captured once into a HIP graph and replayed with
+// one launch.  The tuner picks, per handle, the number of V rows per
+// phase-A work item by timing the candidates on the device.
+#include "h2d_impl.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace h2d {
+
+constexpr int kBranches = 4;   // independent graph branches the instances are dealt to
+
+struct Batch {
+    std::vector<Handle*> hs;
+    hipStream_t cap = nullptr;             // capture origin (default priority, like the branches)
+    hipStream_t br[kBranches] = {};
+    hipEvent_t fork = nullptr, join[kBranches] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (int b = 0; b < kBranches; ++b) {
+            if (join[b]) (void)hipEventDestroy(join[b]);
+            if (br[b]) (void)hipStreamDestroy(br[b]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+Batch* batch_create(Handle** hs, int count, int nrhs, double* const* x, double* const* y, const int64_t* ld)
+{
+    auto* B = new Batch();
+    try {
+        B->hs.assign(hs, hs + count);
+        HIPCK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+        HIPCK(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
+        for (int b = 0; b < kBranches; ++b) {
+            HIPCK(hipStreamCreateWithFlags(&B->br[b], hipStreamNonBlocking));
+            HIPCK(hipEventCreateWithFlags(&B->join[b], hipEventDisableTiming));
+        }
+        // one product per handle outside the capture allocates its work space
+        for (int i = 0; i < count; ++i) {
+            hs[i]->prof_on = false;
+            launch_matvec(*hs[i], x[i], y[i], nrhs, ld[i], H2D_P_FP64, B->cap);
+        }
+        HIPCK(hipStreamSynchronize(B->cap));
+        // A handle's work space is shared by its products, so every product
+        // of one handle goes to the same branch; instances are dealt to the
+        // branches by size so that the branches carry similar work.
+        std::vector<int> order(count);
+        for (int i = 0; i < count; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hs[a]->n > hs[b]->n; });
+        std::vector<int> branch(count, -1);
+        int64_t load[kBranches] = {};
+        for (int i : order) {
+            for (int j = 0; j < count; ++j)
+                if (branch[j] >= 0 && hs[j] == hs[i]) branch[i] = branch[j];
+            if (branch[i] < 0) branch[i] = (int)(std::min_element(load, load + kBranches) - load);
+            load[branch[i]] += hs[i]->n;
+        }
+        HIPCK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+        HIPCK(hipEventRecord(B->fork, B->cap));
+        for (int b = 0; b < kBranches; ++b) HIPCK(hipStreamWaitEvent(B->br[b], B->fork, 0));
+        for (int i : order) launch_matvec(*hs[i], x[i], y[i], nrhs, ld[i], H2D_P_FP64, B->br[branch[i]]);
+        for (int b = 0; b < kBranches; ++b) {
+            HIPCK(hipEventRecord(B->join[b], B->br[b]));
+            HIPCK(hipStreamWaitEvent(B->cap, B->join[b], 0));
+        }
+        HIPCK(hipStreamEndCapture(B->cap, &B->graph));
+        HIPCK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(B->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        delete B;
+        throw;
+    }
+    return B;
+}
+
+void batch_launch(Batch* B, hipStream_t s) { HIPCK(hipGraphLaunch(B->exec, s)); }
+
+void batch_destroy(Batch* B) { delete B; }
+
+// Time `reps` products for each candidate item size; keep the fastest.
+void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out)
+{
+    static const int32_t cand[] = {128, 256, 512};
+    const int64_t n = H.n;
+    DBuf<double> x, y;
+    x.alloc((size_t)n * nrhs);
+    y.alloc((size_t)n * nrhs);
+    HIPCK(hipMemsetAsync(x.p, 0, sizeof(double) * n * nrhs, s));
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int32_t arg = H.a_rows;
+    const bool prof = H.prof_on;
+    H.prof_on = false;
+    for (int c = 0; c < 3; ++c) {
+        H.a_rows = cand[c];
+        finalize(H, s);
+        launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);   // warm-up, allocates
+        HIPCK(hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r) launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);
+        HIPCK(hipEventRecord(e1, s));
+        HIPCK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, e0, e1));
+        ms /= 5.f;
+        if (ms_out) ms_out[c] = ms;
+        if (ms < best) { best = ms; arg = cand[c]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    H.a_rows = arg;
+    finalize(H, s);
+    H.prof_on = prof;
+    if (chosen) *chosen = arg;
+}
+
+}  // namespace h2d

@@ -168,6 +168,7 @@ struct Handle {
     DBuf<double> xs_mr, tp_mr, pp_mr, yp_mr;
     DBuf<const int32_t*> lvl_ptrs;   // begin, count, parent, il_ptr per level (device copies of the pointers)
     int mr_cap = 0;
+    int32_t a_rows = kPhaseARows;    // rows per phase-A work item (tuned by h2d_autotune)
 
     // work vectors
     DBuf<double> xs, tpool, ppool, ypart;    // FP64: x in tree order, t, partials, ancestor sums
@@ -212,6 +213,13 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
 void mlp_weights(Handle& H, float* out, const float* in, double* scale, hipStream_t s);
 float mlp_loss_grad(const float* W, const float* X, const float* T, const float* Mk, int32_t B, float* grad,
                     hipStream_t s);
+
+// batch.hip
+struct Batch;
+Batch* batch_create(Handle** hs, int count, int nrhs, double* const* x, double* const* y, const int64_t* ld);
+void batch_launch(Batch* B, hipStream_t s);
+void batch_destroy(Batch* B);
+void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out);
 
 // solve.hip
 h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_solve_opts& o,

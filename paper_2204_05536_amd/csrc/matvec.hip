@@ -331,13 +331,14 @@ void finalize(Handle& H, hipStream_t s)
         (leaf ? store_leaf : store_anc) += (double)m * k;
         if (leaf) t_leaf += k;
         flops += 2.0 * k * (double)(m + n);
-        if (n <= kPhaseARows) {
+        const int32_t ar = std::max(16, std::min<int32_t>(H.a_rows, kPhaseARows));
+        if (n <= ar) {
             items.push_back(ADesc{H.h_il_voff[b], 0, n, c0, k, (int32_t)toff, (int32_t)b});
         } else {
-            int32_t parts = (n + kPhaseARows - 1) / kPhaseARows;
+            int32_t parts = (n + ar - 1) / ar;
             red.push_back(RDesc{(int32_t)toff, k, (int32_t)poff, parts});
             for (int32_t p = 0; p < parts; ++p) {
-                int32_t j0 = p * kPhaseARows, j1 = std::min(n, j0 + kPhaseARows);
+                int32_t j0 = p * ar, j1 = std::min(n, j0 + ar);
                 items.push_back(ADesc{H.h_il_voff[b], j0, j1, c0, k, (int32_t)(-(poff + (int64_t)p * k) - 1), (int32_t)b});
             }
             poff += (int64_t)parts * k;
@@ -388,6 +389,8 @@ void finalize(Handle& H, hipStream_t s)
     upload_vec(H.ritems, red, s);
     H.n_aitems = (int64_t)items.size();
     H.n_ritems = (int64_t)red.size();
+    H.ws_nrhs = 0;   // partial pools depend on the schedule: reallocate on next use
+    H.mr_cap = 0;
     HIPCK(hipStreamSynchronize(s));
 }
 

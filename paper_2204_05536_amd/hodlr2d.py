@@ -27,7 +27,8 @@ PRECOND = {"none": 0, "bj": 1, "mlp": 2}
 
 EXPORTED = ["h2d_build", "h2d_matvec", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
             "h2d_profile_enable", "h2d_profile_read", "h2d_bj_setup", "h2d_precond_apply",
-            "h2d_mlp_train", "h2d_mlp_weights", "h2d_mlp_loss_grad", "h2d_destroy", "h2d_last_error"]
+            "h2d_mlp_train", "h2d_mlp_weights", "h2d_mlp_loss_grad", "h2d_autotune", "h2d_set_item_rows", "h2d_batch_create",
+            "h2d_batch_launch", "h2d_batch_destroy", "h2d_destroy", "h2d_last_error"]
 MLP_PARAMS = 131648
 PHASES = ["gather", "phaseA", "reduce", "phaseB1", "phaseB2"]
 
@@ -114,6 +115,17 @@ def load():
     L.h2d_mlp_weights.restype = C.c_int
     L.h2d_mlp_loss_grad.argtypes = [P, P, P, P, C.c_int32, C.POINTER(C.c_float), P, P]
     L.h2d_mlp_loss_grad.restype = C.c_int
+    L.h2d_autotune.argtypes = [P, C.c_int32, P, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+    L.h2d_autotune.restype = C.c_int
+    L.h2d_set_item_rows.argtypes = [P, C.c_int32, P]
+    L.h2d_set_item_rows.restype = C.c_int
+    L.h2d_batch_create.argtypes = [C.POINTER(P), C.c_int32, C.c_int32, C.POINTER(P), C.POINTER(P),
+                                   C.POINTER(C.c_int64), C.POINTER(P)]
+    L.h2d_batch_create.restype = C.c_int
+    L.h2d_batch_launch.argtypes = [P, P]
+    L.h2d_batch_launch.restype = C.c_int
+    L.h2d_batch_destroy.argtypes = [P]
+    L.h2d_batch_destroy.restype = None
     L.h2d_destroy.argtypes = [P]
     L.h2d_destroy.restype = None
     L.h2d_last_error.argtypes = []
@@ -261,6 +273,15 @@ class HODLR2D:
         _check(load().h2d_mlp_weights(self._h, C.c_void_p(out.ctypes.data), None, C.byref(sc), _stream()))
         return out, sc.value
 
+    def autotune(self, nrhs=16):
+        chosen = C.c_int32()
+        ms = (C.c_float * 3)()
+        _check(load().h2d_autotune(self._h, int(nrhs), _stream(), C.byref(chosen), ms))
+        return int(chosen.value), dict(zip((128, 256, 512), list(ms)))
+
+    def set_item_rows(self, rows):
+        _check(load().h2d_set_item_rows(self._h, int(rows), _stream()))
+
     def export(self, path, factors=True):
         _check(load().h2d_export(self._h, str(path).encode(), 1 if factors else 0))
 
@@ -276,3 +297,35 @@ def mlp_loss_grad(W, X, T, M):
                                     C.c_void_p(M.data_ptr()), int(X.shape[0]), C.byref(loss),
                                     C.c_void_p(g.data_ptr()), _stream()))
     return float(loss.value), g
+
+
+class Batch:
+    """Products of several handles captured into one HIP graph.
+
+    xs[i], ys[i]: (nrhs, N_i) float64 device tensors bound at creation."""
+
+    def __init__(self, handles, xs, ys):
+        n = len(handles)
+        nrhs = 1 if xs[0].dim() == 1 else xs[0].shape[0]
+        P = C.c_void_p
+        hs = (P * n)(*[h._h for h in handles])
+        xp = (P * n)(*[_dev_f64(x, "x") for x in xs])
+        yp = (P * n)(*[_dev_f64(y, "y") for y in ys])
+        ld = (C.c_int64 * n)(*[x.shape[-1] for x in xs])
+        self._b = P()
+        self._keep = (handles, xs, ys)
+        _check(load().h2d_batch_create(hs, n, nrhs, xp, yp, ld, C.byref(self._b)))
+
+    def launch(self):
+        _check(load().h2d_batch_launch(self._b, _stream()))
+
+    def close(self):
+        if getattr(self, "_b", None):
+            load().h2d_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
