@@ -11,9 +11,12 @@ W warm-up and K timed FP64 matvecs run back to back on one stream.
 value = algorithmic bytes of one FP64 matvec (every stored U, V and dense
 value read once, plus the vectors) / measured time per matvec, in GB/s.
 
-Also reported: FP16 / BF16 matvec rates, time-to-1e-8 of plain FP64
-GMRES(50) against FP16 factors + FP64 iterative refinement on the log
-kernel (N = 2^20, diagonal N, seed 2), GMRES on the multiquadric system,
+Also reported: FP16 / BF16 matvec rates, 16 right-hand sides per product
+on the FP64 matrix cores, time-to-1e-8 of plain FP64 GMRES(50) against
+FP16 factors + FP64 iterative refinement, block-Jacobi and learned per-leaf
+(MLP) preconditioned FGMRES on the log kernel (N = 2^20, diagonal N,
+seed 2; MLP training time apart), GMRES on the multiquadric system, a
+batch of 64 Gaussian-kernel systems replayed from one HIP graph,
 the dominant kernel's roofline fraction from HIP events recorded around
 each kernel inside the timed region, and the CPU oracle's matvec rate on a
 bounded sample of the same recipe.
@@ -30,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
 
 
 def log(*a):
@@ -74,6 +78,98 @@ def cpu_baseline(n_sample: int = 65536, min_seconds: float = 5.0):
             "ms_per_matvec": per * 1e3}
 
 
+def mr_bytes(info, nrhs):
+    """Algorithmic bytes of one product with nrhs right-hand sides: the
+    stored factors once, every vector term of the single-RHS count nrhs times."""
+    fac = 8.0 * (info["u_elems"] + info["v_elems"] + info["d_elems"])
+    return fac + nrhs * (info["alg_bytes_fp64"] - fac)
+
+
+def multi_rhs(H, info, n, nrhs=16, reps=10):
+    """16 right-hand sides per product on the FP64 matrix cores."""
+    import numpy as np
+    import torch
+
+    X = torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, (nrhs, n))).cuda()
+    Y = torch.empty_like(X)
+    for _ in range(2):
+        H.matvec(X, out=Y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        H.matvec(X, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    y3 = H.matvec(X[3].contiguous())
+    err = float(torch.linalg.norm(Y[3] - y3) / torch.linalg.norm(y3))
+    tf = nrhs * info["flops"] / (ms * 1e-3) / 1e12
+    r = {"nrhs": nrhs, "ms": ms, "ms_per_rhs": ms / nrhs, "GB/s": mr_bytes(info, nrhs) / (ms * 1e-3) / 1e9,
+         "alg_bytes": mr_bytes(info, nrhs), "TFLOP/s": tf, "fp64_mfma_frac": tf / FP64_MFMA_PEAK_TFS,
+         "rel_diff_vs_single_rhs": err}
+    log(f"multi-RHS x{nrhs}: {ms:.3f} ms ({ms / nrhs:.3f} ms per RHS), {r['GB/s']:.0f} GB/s, {tf:.2f} TFLOP/s")
+    return r
+
+
+def batched(count, nrhs=16, reps=10):
+    """64 independent systems (sizes log-uniform in [1e4, 5e5], disc or
+    4-cluster points, Gaussian RBF c=0.05 + 1e-4 I), 16 right-hand sides
+    each, all products replayed from one captured HIP graph after tuning
+    each handle's phase-A item size."""
+    import numpy as np
+    import torch
+
+    from paper_2204_05536_amd import hodlr2d, inputs
+
+    inst, kern, leaf, tol = inputs.batch_workload(count, nrhs=nrhs)
+    ntot = int(sum(xy.shape[0] for xy, _ in inst))
+    log(f"batched: building {count} instances, {ntot} points in all")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs = [hodlr2d.HODLR2D.build(torch.from_numpy(xy).cuda(), kern, leaf, tol) for xy, _ in inst]
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    picks = [H.autotune(nrhs)[0] for H in hs]
+    t_tune = time.perf_counter() - t0
+    infos = [H.info() for H in hs]
+    byts = sum(mr_bytes(i, nrhs) for i in infos)
+    flops = nrhs * sum(i["flops"] for i in infos)
+    xs = [torch.from_numpy(X).cuda() for _, X in inst]
+    ys = [torch.empty_like(x) for x in xs]
+    B = hodlr2d.Batch(hs, xs, ys)
+    for _ in range(2):
+        B.launch()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        B.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    same = all(torch.equal(ys[i], hs[i].matvec(xs[i])) for i in (0, count // 2, count - 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for H, x, y in zip(hs, xs, ys):
+        H.matvec(x, out=y)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3
+    B.close()
+    for H in hs:
+        H.close()
+    r = {"instances": count, "total_points": ntot, "nrhs": nrhs, "build_seconds": t_build,
+         "autotune_seconds": t_tune, "item_rows_picked": {str(k): picks.count(k) for k in (128, 256, 512)},
+         "graph_ms": ms, "eager_ms": ms_eager, "alg_bytes": byts, "GB/s": byts / (ms * 1e-3) / 1e9,
+         "TFLOP/s": flops / (ms * 1e-3) / 1e12, "rhs_products_per_s": count * nrhs / (ms * 1e-3),
+         "graph_equals_eager": bool(same)}
+    log(f"batched: graph {ms:.2f} ms, eager {ms_eager:.2f} ms, {r['GB/s']:.0f} GB/s, build {t_build:.1f} s")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +179,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-half", action="store_true")
+    ap.add_argument("--no-mrhs", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (a known-size kernel for counter calibration)")
     args = ap.parse_args()
@@ -169,6 +268,8 @@ def main():
                        "rel_err_vs_fp64": err, "phases_ms": ph["ms"]}
             log(f"{p} matvec {mh:.3f} ms  {half[p]['GB/s']:.0f} GB/s  err {err:.2e}")
         extra["half"] = half
+    if not args.no_mrhs:
+        extra["multi_rhs"] = multi_rhs(H, info, x.shape[0])
     if not args.no_solve:
         xs, sinfo = H.solve(x, tol=1e-8, restart=50, max_iter=100)
         extra["gmres_mq_plain"] = {k: sinfo[k] for k in ("iters", "relres", "seconds", "converged")}
@@ -189,8 +290,31 @@ def main():
         sol["refine_fp16"] = {k: ir[k] for k in ("iters", "outer", "relres", "seconds", "converged")}
         sol["refine_fp16"]["rel_diff_vs_plain"] = float(torch.linalg.norm(xr - xp) / torch.linalg.norm(xp))
         log(f"time-to-1e-8 plain {ip} refine {ir}")
+        # block-Jacobi fallback and the learned per-leaf preconditioner
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H2.bj_setup()
+        torch.cuda.synchronize()
+        t_bj = time.perf_counter() - t0
+        xb, ib = H2.solve(bb, tol=1e-8, restart=50, precond="bj")
+        sol["fgmres_bj"] = {k: ib[k] for k in ("iters", "outer", "relres", "seconds", "converged")}
+        sol["fgmres_bj"]["setup_seconds"] = t_bj
+        tinfo = H2.mlp_train(n_solves=16, steps=1500, batch=4096, lr=5e-4, seed=1234)
+        sol["mlp_training"] = {k: tinfo[k] for k in ("seconds_data", "seconds_train", "loss_first", "loss_last",
+                                                     "n_samples")}
+        xm, im = H2.solve(bb, tol=1e-8, restart=50, precond="mlp")
+        sol["fgmres_mlp"] = {k: im[k] for k in ("iters", "outer", "relres", "seconds", "converged")}
+        xc, ic = H2.solve(bb, tol=1e-8, restart=50, mode="refine", inner_prec="fp16", inner_tol=1e-4, precond="mlp")
+        sol["chosen_refine_fp16_mlp"] = {k: ic[k] for k in ("iters", "outer", "relres", "seconds", "converged")}
+        sol["chosen_refine_fp16_mlp"]["rel_diff_vs_plain"] = float(torch.linalg.norm(xc - xp) / torch.linalg.norm(xp))
+        log(f"FGMRES block-Jacobi {ib}; MLP training {tinfo}; FGMRES MLP {im}; refine fp16 + MLP {ic}")
         extra["time_to_1e-8_log1m"] = sol
         H2.close()
+        del H2
+        torch.cuda.synchronize()
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        extra["batched"] = batched(args.batch_count)
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
