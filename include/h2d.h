@@ -260,9 +260,11 @@ h2d_status h2d_profile_enable(h2d_t H, int32_t on);
 h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
 
 /* Tile tuning: times FP64 products with nrhs right-hand sides for each
- * candidate number of V rows per phase-A work item (128, 256, 512) and
- * keeps the fastest for H.  chosen (host, may be NULL) receives the pick,
- * ms (host, 3 floats, may be NULL) the measured milliseconds. */
+ * candidate work-item size and keeps the fastest for H.  nrhs == 1 tunes
+ * the V rows per single-RHS phase-A item (128, 256, 512); nrhs > 1 tunes
+ * the source rows per multi-RHS phase-A item (64, 128, 256).  chosen
+ * (host, may be NULL) receives the pick, ms (host, 3 floats, may be NULL)
+ * the measured milliseconds per product. */
 h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, float* ms);
 
 /* Batched products: the FP64 products y_i = A_i x_i of `count` built
@@ -274,9 +276,11 @@ h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, fl
  * concurrently with a launch, and must not be re-tuned (h2d_autotune,
  * h2d_set_item_rows) while the batch exists: the graph holds their
  * schedule and work-space addresses. */
-/* Sets the number of V rows per phase-A work item explicitly (16..512)
- * and rebuilds H's product schedule; H2D_EINVAL outside that range. */
-h2d_status h2d_set_item_rows(h2d_t H, int32_t rows, void* stream);
+/* Sets a work-item size explicitly: multi == 0, V rows per single-RHS
+ * phase-A item (16..512; the schedule is rebuilt at once); multi != 0,
+ * source rows per multi-RHS phase-A item (16..256, a multiple of 16;
+ * rebuilt at the next multi-RHS product).  H2D_EINVAL outside range. */
+h2d_status h2d_set_item_rows(h2d_t H, int32_t multi, int32_t rows, void* stream);
 
 typedef struct h2d_batch_s* h2d_batch_t;
 h2d_status h2d_batch_create(h2d_t const* handles, int32_t count, int32_t nrhs, double* const* x, double* const* y,

@@ -507,12 +507,13 @@ h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, fl
     });
 }
 
-h2d_status h2d_set_item_rows(h2d_t H, int32_t rows, void* stream)
+h2d_status h2d_set_item_rows(h2d_t H, int32_t multi, int32_t rows, void* stream)
 {
     return guarded([&] {
-        if (!H || rows < 16 || rows > kPhaseARows) fail(H2D_EINVAL, "item rows must lie in 16..512");
-        H->h.a_rows = rows;
-        finalize(H->h, (hipStream_t)stream);
+        if (!H) fail(H2D_EINVAL, "NULL handle");
+        if (!multi && (rows < 16 || rows > kPhaseARows)) fail(H2D_EINVAL, "item rows must lie in 16..512");
+        if (multi && (rows < 16 || rows > 256 || rows % 16)) fail(H2D_EINVAL, "chunk rows must be 16..256, multiple of 16");
+        set_item_rows(H->h, multi != 0, rows, (hipStream_t)stream);
     });
 }
 

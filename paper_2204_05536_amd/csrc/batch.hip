@@ -88,10 +88,26 @@ void batch_launch(Batch* B, hipStream_t s) { HIPCK(hipGraphLaunch(B->exec, s)); 
 
 void batch_destroy(Batch* B) { delete B; }
 
-// Time `reps` products for each candidate item size; keep the fastest.
+// Time 5 products for each candidate item size; keep the fastest.  One
+// right-hand side tunes the single-RHS phase-A item rows (128, 256, 512);
+// several tune the source-chunk rows of the multi-RHS phase A (64, 128, 256).
+static void set_rows(Handle& H, bool multi, int32_t rows, hipStream_t s)
+{
+    if (multi) {
+        H.mr_rows = rows;
+        H.mr_cap = 0;   // rebuilt with the next multi-RHS product
+    } else {
+        H.a_rows = rows;
+        finalize(H, s);
+    }
+}
+
+void set_item_rows(Handle& H, bool multi, int32_t rows, hipStream_t s) { set_rows(H, multi, rows, s); }
+
 void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out)
 {
-    static const int32_t cand[] = {128, 256, 512};
+    const bool multi = nrhs > 1;
+    const int32_t cand[3] = {multi ? 64 : 128, multi ? 128 : 256, multi ? 256 : 512};
     const int64_t n = H.n;
     DBuf<double> x, y;
     x.alloc((size_t)n * nrhs);
@@ -101,12 +117,11 @@ void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
     float best = 1e30f;
-    int32_t arg = H.a_rows;
+    int32_t arg = multi ? H.mr_rows : H.a_rows;
     const bool prof = H.prof_on;
     H.prof_on = false;
     for (int c = 0; c < 3; ++c) {
-        H.a_rows = cand[c];
-        finalize(H, s);
+        set_rows(H, multi, cand[c], s);
         launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);   // warm-up, allocates
         HIPCK(hipEventRecord(e0, s));
         for (int r = 0; r < 5; ++r) launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);
@@ -120,8 +135,7 @@ void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    H.a_rows = arg;
-    finalize(H, s);
+    set_rows(H, multi, arg, s);
     H.prof_on = prof;
     if (chosen) *chosen = arg;
 }

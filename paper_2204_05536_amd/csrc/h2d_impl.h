@@ -110,6 +110,21 @@ struct RDesc {
     int32_t nparts;   // partials, each k long, stored consecutively
 };
 
+// Multi-RHS phase A, grouped by source box: one work item is a row range
+// [j0, j1) of one source box (points col0 + j0 .. col0 + j1 - 1 in tree
+// order) and the blocks b0 .. b1 - 1 of the block list that share it; the
+// item is chunk p of the source's rows.
+struct MRItem {
+    int32_t col0, j0, j1, b0, b1, p;
+};
+// One low-rank block of the list: V offset, rank, and where T goes
+// (out >= 0: t pool offset; out < 0: partial pool offset -out - 1 of chunk 0,
+// chunk p at that + p k).
+struct MRBlk {
+    int64_t voff;
+    int32_t k, out;
+};
+
 struct KernelParams {
     int32_t kind;
     int32_t diag_mode;
@@ -168,6 +183,12 @@ struct Handle {
     DBuf<double> xs_mr, tp_mr, pp_mr, yp_mr;
     DBuf<const int32_t*> lvl_ptrs;   // begin, count, parent, il_ptr per level (device copies of the pointers)
     int mr_cap = 0;
+    DBuf<MRItem> mr_items;           // multi-RHS phase-A items (source-grouped)
+    DBuf<MRBlk> mr_blks;
+    DBuf<RDesc> mr_ritems;           // their split-block reductions
+    DBuf<int32_t> iperm;             // caller index -> tree position
+    int64_t n_mr_items = 0, n_mr_ritems = 0, mr_p_elems = 0;
+    int32_t mr_rows = 256;           // source rows per multi-RHS phase-A item (tuned by h2d_autotune)
     int32_t a_rows = kPhaseARows;    // rows per phase-A work item (tuned by h2d_autotune)
 
     // work vectors
@@ -220,6 +241,7 @@ Batch* batch_create(Handle** hs, int count, int nrhs, double* const* x, double* 
 void batch_launch(Batch* B, hipStream_t s);
 void batch_destroy(Batch* B);
 void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out);
+void set_item_rows(Handle& H, bool multi, int32_t rows, hipStream_t s);
 
 // solve.hip
 h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_solve_opts& o,

@@ -39,87 +39,239 @@ __device__ __forceinline__ int32_t xcd_tile_mr()
     return xcd * q8 + min(xcd, r8) + i8;
 }
 
-// xs[i * 16 + r] = x[(r0 + r) * ldx + perm[i]] for r < nr, 0 beyond.
-__global__ void k_gather_mr(const double* __restrict__ x, int64_t ldx, int32_t nr, const int32_t* __restrict__ perm,
-                            int32_t n, double* __restrict__ xs)
+// xs[iperm[c] * 16 + r] = x[r * ldx + c] for r < nr, 0 beyond.  64
+// caller-order points per workgroup: the right-hand-side rows are read
+// coalesced, transposed through LDS, and each point's 16 values are written
+// as one 128-byte segment at its tree position.
+__global__ void __launch_bounds__(256)
+k_gather_mr(const double* __restrict__ x, int64_t ldx, int32_t nr, const int32_t* __restrict__ iperm, int32_t n,
+            double* __restrict__ xs)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * kR) return;
-    const int32_t i = (int32_t)(e / kR), r = (int32_t)(e % kR);
-    xs[e] = r < nr ? x[(int64_t)r * ldx + perm[i]] : 0.0;
+    __shared__ double tile[kR][kWave + 1];
+    const int32_t c0 = blockIdx.x * kWave;
+    for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
+        const int r = e / kWave, c = e % kWave;
+        tile[r][c] = (r < nr && c0 + c < n) ? x[(int64_t)r * ldx + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
+        const int c = e / kR, r = e % kR;
+        if (c0 + c < n) xs[(int64_t)iperm[c0 + c] * kR + r] = tile[r][c];
+    }
 }
 
-// Phase A: one wave per work item (rows j0..j1 of one block's V).
-// T(k x 16, row-major) = V(rows, :)^T X(rows, :), M tiles of 16 columns q.
+// y[r * ldy + c] = yt[iperm[c] * 16 + r] for r < nr: the inverse of the
+// gather, from the tree-ordered point-major result back to caller order.
 __global__ void __launch_bounds__(256)
-k_phaseA_mr(int64_t nitems, const ADesc* __restrict__ items, const double* __restrict__ V,
-            const double* __restrict__ xs, double* __restrict__ tpool, double* __restrict__ ppool)
+k_scatter_mr(const double* __restrict__ yt, const int32_t* __restrict__ iperm, int32_t n, int32_t nr,
+             double* __restrict__ y, int64_t ldy)
 {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t it = (int64_t)blockIdx.x * 4 + wave;
-    if (it >= nitems) return;
-    const ADesc D = items[it];
-    const int64_t voff = uni_l(D.voff);
-    const int32_t j0 = uni_i(D.j0), j1 = uni_i(D.j1), col0 = uni_i(D.col0), k = uni_i(D.k), out = uni_i(D.out);
-    double* T = out >= 0 ? tpool + (int64_t)out * kR : ppool + (int64_t)(-out - 1) * kR;
+    __shared__ double tile[kR][kWave + 1];
+    const int32_t c0 = blockIdx.x * kWave;
+    for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
+        const int c = e / kR, r = e % kR;
+        if (c0 + c < n) tile[r][c] = yt[(int64_t)iperm[c0 + c] * kR + r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
+        const int r = e / kWave, c = e % kWave;
+        if (r < nr && c0 + c < n) y[(int64_t)r * ldy + c0 + c] = tile[r][c];
+    }
+}
+
+__global__ void k_iperm(const int32_t* __restrict__ perm, int32_t n, int32_t* __restrict__ iperm)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) iperm[perm[i]] = i;
+}
+
+// Every load below is unconditional: addresses are clamped into the
+// operand (rows past the end re-read the last row, and their results are
+// never stored; K indices past the end re-read the last column with the
+// other operand zeroed), so the compiler can issue a whole group of loads
+// before the matrix instructions that consume them.  Loads go through
+// buffer resources: a wave-uniform base and extent in scalar registers,
+// a scalar offset per K-step and a 32-bit per-lane offset that stays fixed
+// over the loop, so a group of 4 K-steps needs no per-lane address math.
+// An offset at or past the extent reads 0 (never the case by construction).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ __forceinline__ rsrc_t rsrc(const double* base, int64_t elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)(elems * 8), 0x00020000);
+}
+
+__device__ __forceinline__ double bld(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+// T rows q0 + 16 t (t < NT) += V(0..rows-1, q)^T X(0..rows-1, :) for one
+// block: V row-major with k columns at Vb, X point-major in LDS at xl,
+// zero-padded to a multiple of 16 rows.
+template <int NT>
+__device__ __forceinline__ void srcA_tiles(d4 (&acc)[4], const double* __restrict__ Vb, int32_t k, int32_t q0,
+                                           const double* xl, int32_t rows, int lane)
+{
     const int li = lane % 16, lk = lane / 16;
-    for (int32_t q0 = 0; q0 < k; q0 += 64) {   // up to 4 M tiles at a time
-        d4 acc[4];
+    uint32_t ao[NT];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
-        for (int32_t j = j0; j < j1; j += 4) {
-            const int32_t jj = j + lk;
-            const bool rowok = jj < j1;
-            const double b = rowok ? xs[(int64_t)(col0 + jj) * kR + li] : 0.0;
+    for (int t = 0; t < NT; ++t) ao[t] = (uint32_t)(lk * k + min(q0 + 16 * t + li, k - 1)) * 8u;
+    const uint32_t sa = (uint32_t)k * 32u;   // 4 rows of V, in bytes
+    int32_t j = 0;
+    for (; j + 16 <= rows; j += 16) {
+        const rsrc_t rv = rsrc(Vb + (int64_t)j * k, 16 * (int64_t)k);
+        double a[4][NT], b[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int32_t q = q0 + 16 * t + li;
-                if (q0 + 16 * t < k) {
-                    const double a = (rowok && q < k) ? V[voff + (int64_t)jj * k + q] : 0.0;
-                    acc[t] = mfma(a, b, acc[t]);
-                }
-            }
+        for (int u = 0; u < 4; ++u) {
+            b[u] = xl[(j + 4 * u + lk) * kR + li];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) a[u][t] = bld(rv, ao[t], u * sa);
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int32_t q = q0 + 16 * t + 4 * v + lk;
-                if (q < k) T[(int64_t)q * kR + li] = acc[t][v];
-            }
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u][t], b[u], acc[t]);
+    }
+    if (j < rows) {   // last group: rows past the end re-read row rows - 1, their X rows are zero
+        double a[4][NT], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t jl = min(j + 4 * u + lk, rows - 1);
+            b[u] = xl[(j + 4 * u + lk) * kR + li];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) a[u][t] = Vb[jl * k + min(q0 + 16 * t + li, k - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u][t], b[u], acc[t]);
     }
 }
 
-__global__ void k_reduce_mr(int64_t nr, const RDesc* __restrict__ R, const double* __restrict__ ppool,
-                            double* __restrict__ tpool)
+// Phase A grouped by source box: one workgroup per item stages the item's
+// rows of X in LDS once; its four waves take the blocks sharing that source
+// in turn, T (k x 16, row-major) = V(rows, :)^T X(rows, :), up to 4 M tiles
+// of 16 columns q per pass.  Dynamic LDS: 16 x 8 bytes per row, rows
+// rounded up to 16.
+__global__ void __launch_bounds__(256)
+k_phaseA_mr(int64_t nitems, const MRItem* __restrict__ items, const MRBlk* __restrict__ blks,
+            const double* __restrict__ V, const double* __restrict__ xs, double* __restrict__ tpool,
+            double* __restrict__ ppool)
 {
-    const RDesc D = R[blockIdx.x];
-    for (int e = threadIdx.x; e < D.k * kR; e += blockDim.x) {
-        double s = 0.0;
-        for (int p = 0; p < D.nparts; ++p) s += ppool[((int64_t)D.pbeg + (int64_t)p * D.k) * kR + e];
-        tpool[(int64_t)D.tout * kR + e] = s;
+    extern __shared__ double xl[];
+    if ((int64_t)blockIdx.x >= nitems) return;
+    const MRItem it = items[blockIdx.x];
+    const int32_t rows = it.j1 - it.j0, rpad = (rows + 15) & ~15;
+    const double* src = xs + (int64_t)(it.col0 + it.j0) * kR;
+    for (int e = threadIdx.x; e < rpad * kR; e += blockDim.x) xl[e] = e < rows * kR ? src[e] : 0.0;
+    __syncthreads();
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int li = lane % 16, lk = lane / 16;
+    for (int32_t b = it.b0 + wave; b < it.b1; b += 4) {
+        const MRBlk B = blks[b];
+        const int64_t voff = uni_l(B.voff);
+        const int32_t k = uni_i(B.k), out = uni_i(B.out);
+        double* T = out >= 0 ? tpool + (int64_t)out * kR : ppool + ((int64_t)(-out - 1) + (int64_t)it.p * k) * kR;
+        const double* Vb = V + voff + (int64_t)it.j0 * k;
+        for (int32_t q0 = 0; q0 < k; q0 += 64) {
+            d4 acc[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
+            const int32_t nt = min(4, (k - q0 + 15) / 16);
+            if (nt == 4) srcA_tiles<4>(acc, Vb, k, q0, xl, rows, lane);
+            else if (nt == 3) srcA_tiles<3>(acc, Vb, k, q0, xl, rows, lane);
+            else if (nt == 2) srcA_tiles<2>(acc, Vb, k, q0, xl, rows, lane);
+            else srcA_tiles<1>(acc, Vb, k, q0, xl, rows, lane);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int32_t q = q0 + 16 * t + 4 * v + lk;
+                    if (t < nt && q < k) T[(int64_t)q * kR + li] = acc[t][v];
+                }
+        }
     }
 }
 
-// Y (rows r0 .. r0 + rows - 1 of a tile, up to 64) += A (rows x K) B (K x 16)
+// t = sum of the partial products of one split block.  Grid (blocks,
+// ceil(max k / 4)): workgroup (b, g) owns elements 64 g .. 64 g + 63 of the
+// k x 16 result, its four waves take every fourth part, and the four wave
+// sums are added in a fixed order.
+__global__ void __launch_bounds__(256)
+k_reduce_mr(int64_t nr, const RDesc* __restrict__ R, const double* __restrict__ ppool, double* __restrict__ tpool)
+{
+    __shared__ double part[4][kWave];
+    const RDesc D = R[blockIdx.x];
+    const int32_t E = D.k * kR;
+    if ((int32_t)blockIdx.y * kWave >= E) return;   // whole workgroup
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t e = blockIdx.y * kWave + lane;
+    const int64_t stride = (int64_t)D.k * kR;
+    const double* base = ppool + (int64_t)D.pbeg * kR + min(e, E - 1);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int32_t p = wave;
+    for (; p + 12 < D.nparts; p += 16) {
+        s0 += base[(int64_t)p * stride];
+        s1 += base[(int64_t)(p + 4) * stride];
+        s2 += base[(int64_t)(p + 8) * stride];
+        s3 += base[(int64_t)(p + 12) * stride];
+    }
+    for (; p < D.nparts; p += 4) s0 += base[(int64_t)p * stride];
+    part[wave][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (wave == 0 && e < E)
+        tpool[(int64_t)D.tout * kR + e] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// acc[t] (rows 16 t .. 16 t + 15 of a tile, t < NT) += A (rows x K) B (K x 16)
 // where A(i, c) = Ab[c * lda + i] and B(c, r) = Bb[c * ldb + r].
+template <int NT>
+__device__ __forceinline__ void mm_tiles(d4 (&acc)[4], const double* __restrict__ Ab, int64_t lda, int32_t rows,
+                                         const double* __restrict__ Bb, int64_t ldb, int32_t K, int lane)
+{
+    const int li = lane % 16, lk = lane / 16;
+    uint32_t ao[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) ao[t] = (uint32_t)(lk * lda + min(16 * t + li, rows - 1)) * 8u;
+    const uint32_t bo = (uint32_t)(lk * ldb + li) * 8u;
+    const uint32_t sa = (uint32_t)lda * 32u, sb = (uint32_t)ldb * 32u;   // 4 columns, in bytes
+    int32_t c = 0;
+    for (; c + 16 <= K; c += 16) {
+        const rsrc_t ra = rsrc(Ab + (int64_t)c * lda, 15 * lda + rows);
+        const rsrc_t rb = rsrc(Bb + (int64_t)c * ldb, 15 * ldb + kR);
+        double a[4][NT], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            b[u] = bld(rb, bo, u * sb);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) a[u][t] = bld(ra, ao[t], u * sa);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u][t], b[u], acc[t]);
+    }
+    for (; c < K; c += 4) {   // tail: columns past K re-read column K - 1 with B zeroed
+        const int32_t cc = c + lk;
+        const int64_t cl = min(cc, K - 1);
+        double b = Bb[cl * ldb + li];
+        b = cc < K ? b : 0.0;
+        double a[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) a[t] = Ab[cl * lda + min(16 * t + li, rows - 1)];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma(a[t], b, acc[t]);
+    }
+}
+
 __device__ __forceinline__ void mm_tile(d4 (&acc)[4], const double* __restrict__ Ab, int64_t lda, int32_t rows,
                                         const double* __restrict__ Bb, int64_t ldb, int32_t K, int lane)
 {
-    const int li = lane % 16, lk = lane / 16;
-    for (int32_t c = 0; c < K; c += 4) {
-        const int32_t cc = c + lk;
-        const bool colok = cc < K;
-        const double b = colok ? Bb[(int64_t)cc * ldb + li] : 0.0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (16 * t < rows) {
-                const int32_t i = 16 * t + li;
-                const double a = (colok && i < rows) ? Ab[(int64_t)cc * lda + i] : 0.0;
-                acc[t] = mfma(a, b, acc[t]);
-            }
-        }
-    }
+    if (rows > 48) mm_tiles<4>(acc, Ab, lda, rows, Bb, ldb, K, lane);
+    else if (rows > 32) mm_tiles<3>(acc, Ab, lda, rows, Bb, ldb, K, lane);
+    else if (rows > 16) mm_tiles<2>(acc, Ab, lda, rows, Bb, ldb, K, lane);
+    else mm_tiles<1>(acc, Ab, lda, rows, Bb, ldb, K, lane);
 }
 
 // Phase B1 (ancestor levels): one wave per 64-row chunk of a box at level
@@ -168,14 +320,13 @@ k_phaseB1_mr(int32_t nitems, const int2* __restrict__ items, int tl, const int32
 }
 
 // Phase B2 (leaf level): one wave per leaf box; near blocks, the leaf's
-// own interaction-list blocks, plus the ancestor sums; y column-major
-// (ldy) in caller order, columns r < nr.
+// own interaction-list blocks, plus the ancestor sums already in yt (when
+// has_anc); the result replaces yt (tree order, point-major).
 __global__ void __launch_bounds__(256)
 k_phaseB2_mr(int32_t nleaf, int kappa, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
              const int32_t* __restrict__ il_ptr, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
              const BDesc* __restrict__ bil, const double* __restrict__ Up, const double* __restrict__ Dp,
-             const double* __restrict__ tpool, const double* __restrict__ xs, const double* __restrict__ ypart,
-             const int32_t* __restrict__ perm, double* __restrict__ y, int64_t ldy, int32_t nr)
+             const double* __restrict__ tpool, const double* __restrict__ xs, int has_anc, double* __restrict__ yt)
 {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t X = xcd_tile_mr() * 4 + wave;
@@ -205,24 +356,96 @@ k_phaseB2_mr(int32_t nleaf, int kappa, const int32_t* __restrict__ begin, const 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int32_t i = 16 * t + 4 * v + lk;
-                if (i < rows && li < nr) {
-                    const int32_t g = r0 + rc + i;
-                    double s = acc[t][v];
-                    if (ypart) s += ypart[(int64_t)g * kR + li];
-                    y[(int64_t)li * ldy + perm[g]] = s;
+                if (i < rows) {
+                    const int64_t g = (int64_t)(r0 + rc + i) * kR + li;
+                    yt[g] = has_anc ? acc[t][v] + yt[g] : acc[t][v];
                 }
             }
     }
 }
 
+// Source-grouped phase-A schedule for the multi-RHS product: low-rank
+// blocks sorted by (level, source box), each source cut into chunks of
+// mr_rows rows; blocks whose source spans several chunks get a partial sum
+// per chunk and a reduction.  Items are ordered largest work first.
+static void build_mr_schedule(Handle& H, hipStream_t s)
+{
+    const int32_t R = std::max(16, std::min<int32_t>(H.mr_rows, 256)) & ~15;
+    std::vector<int64_t> idx;
+    for (int64_t b = 0; b < H.n_il; ++b)
+        if (H.h_il_kind[b] != kDense && H.h_il_k[b] > 0) idx.push_back(b);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        return H.h_il_level[a] != H.h_il_level[b] ? H.h_il_level[a] < H.h_il_level[b] : H.h_il_src[a] < H.h_il_src[b];
+    });
+    std::vector<MRBlk> blks;
+    std::vector<MRItem> items;
+    std::vector<int64_t> work;
+    std::vector<RDesc> red;
+    int64_t poff = 0;
+    for (size_t g0 = 0; g0 < idx.size();) {
+        size_t g1 = g0;
+        const int32_t lv = H.h_il_level[idx[g0]], src = H.h_il_src[idx[g0]];
+        while (g1 < idx.size() && H.h_il_level[idx[g1]] == lv && H.h_il_src[idx[g1]] == src) ++g1;
+        const Level& L = H.lev[lv];
+        const int32_t n = L.h_count[src], c0 = L.h_begin[src];
+        const int32_t parts = (n + R - 1) / R;
+        const int32_t b0 = (int32_t)blks.size();
+        int64_t ksum = 0;
+        for (size_t g = g0; g < g1; ++g) {
+            const int64_t b = idx[g];
+            const int32_t k = H.h_il_k[b];
+            ksum += k;
+            if (parts == 1) {
+                blks.push_back(MRBlk{H.h_il_voff[b], k, H.h_il_toff[b]});
+            } else {
+                blks.push_back(MRBlk{H.h_il_voff[b], k, (int32_t)(-poff - 1)});
+                red.push_back(RDesc{H.h_il_toff[b], k, (int32_t)poff, parts});
+                poff += (int64_t)parts * k;
+            }
+        }
+        const int32_t b1 = (int32_t)blks.size();
+        for (int32_t p = 0; p < parts; ++p) {
+            const int32_t j0 = p * R, j1 = std::min(n, j0 + R);
+            items.push_back(MRItem{c0, j0, j1, b0, b1, p});
+            work.push_back((int64_t)(j1 - j0) * ksum);
+        }
+        g0 = g1;
+    }
+    if (poff > INT32_MAX) fail(H2D_EUNSUPPORTED, "multi-RHS partial pool too large");
+    std::vector<int64_t> ord(items.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int64_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+    std::vector<MRItem> sorted(items.size());
+    for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[ord[i]];
+    H.mr_items.alloc(std::max<size_t>(sorted.size(), 1));
+    H.mr_blks.alloc(std::max<size_t>(blks.size(), 1));
+    H.mr_ritems.alloc(std::max<size_t>(red.size(), 1));
+    if (!sorted.empty())
+        HIPCK(hipMemcpyAsync(H.mr_items.p, sorted.data(), sizeof(MRItem) * sorted.size(), hipMemcpyHostToDevice, s));
+    if (!blks.empty())
+        HIPCK(hipMemcpyAsync(H.mr_blks.p, blks.data(), sizeof(MRBlk) * blks.size(), hipMemcpyHostToDevice, s));
+    if (!red.empty())
+        HIPCK(hipMemcpyAsync(H.mr_ritems.p, red.data(), sizeof(RDesc) * red.size(), hipMemcpyHostToDevice, s));
+    H.n_mr_items = (int64_t)sorted.size();
+    H.n_mr_ritems = (int64_t)red.size();
+    H.mr_p_elems = poff;
+    HIPCK(hipStreamSynchronize(s));
+}
+
 void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s)
 {
     const int32_t n = (int32_t)H.n;
+    // per-group operand extents (16 columns of a box) must stay below 4 GiB
+    if (H.n > (1 << 24)) fail(H2D_EUNSUPPORTED, "multi-RHS products support at most 2^24 points");
     if (H.mr_cap == 0) {
+        build_mr_schedule(H, s);
         H.xs_mr.alloc((size_t)n * kR);
         H.tp_mr.alloc(std::max<int64_t>(H.t_elems, 1) * kR);
-        H.pp_mr.alloc(std::max<int64_t>(H.p_elems, 1) * kR);
+        H.pp_mr.alloc(std::max<int64_t>(H.mr_p_elems, 1) * kR);
         H.yp_mr.alloc((size_t)n * kR);
+        H.iperm.alloc(std::max(n, 1));
+        k_iperm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(H.perm.p, n, H.iperm.p);
+        HIPCK(hipGetLastError());
         std::vector<const int32_t*> ptrs(4 * (kMaxLevel + 1), nullptr);
         for (int l = 0; l <= H.kappa; ++l) {
             ptrs[l] = H.lev[l].begin.p;
@@ -232,6 +455,7 @@ void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t l
         }
         H.lvl_ptrs.alloc(ptrs.size());
         HIPCK(hipMemcpyAsync(H.lvl_ptrs.p, ptrs.data(), sizeof(void*) * ptrs.size(), hipMemcpyHostToDevice, s));
+        HIPCK(hipStreamSynchronize(s));
         H.mr_cap = kR;
     }
     const int32_t* const* Lb = H.lvl_ptrs.p;
@@ -239,22 +463,25 @@ void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t l
     const int32_t* const* Lp = H.lvl_ptrs.p + 2 * (kMaxLevel + 1);
     const int32_t* const* Li = H.lvl_ptrs.p + 3 * (kMaxLevel + 1);
     const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
+    const int32_t R = std::max(16, std::min<int32_t>(H.mr_rows, 256)) & ~15;
+    const unsigned pblocks = (unsigned)((n + kWave - 1) / kWave);
     for (int r0 = 0; r0 < nrhs; r0 += kR) {
         const int32_t nr = std::min(kR, nrhs - r0);
-        k_gather_mr<<<(unsigned)(((int64_t)n * kR + 255) / 256), 256, 0, s>>>(x + (int64_t)r0 * ld, ld, nr, H.perm.p, n,
-                                                                           H.xs_mr.p);
-        if (H.n_aitems)
-            k_phaseA_mr<<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, H.V64.p, H.xs_mr.p,
-                                                                       H.tp_mr.p, H.pp_mr.p);
-        if (H.n_ritems) k_reduce_mr<<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, H.pp_mr.p, H.tp_mr.p);
+        k_gather_mr<<<pblocks, 256, 0, s>>>(x + (int64_t)r0 * ld, ld, nr, H.iperm.p, n, H.xs_mr.p);
+        if (H.n_mr_items)
+            k_phaseA_mr<<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(double), s>>>(
+                H.n_mr_items, H.mr_items.p, H.mr_blks.p, H.V64.p, H.xs_mr.p, H.tp_mr.p, H.pp_mr.p);
+        if (H.n_mr_ritems)
+            k_reduce_mr<<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256, 0,
+                          s>>>(H.n_mr_ritems, H.mr_ritems.p, H.pp_mr.p, H.tp_mr.p);
         if (H.n_b1)
             k_phaseB1_mr<<<(unsigned)((H.n_b1 + 3) / 4), 256, 0, s>>>((int32_t)H.n_b1, H.b1items.p, H.kappa - 1, Lb, Lc,
                                                                      Lp, Li, H.bil.p, H.U64.p, H.D64.p, H.tp_mr.p,
                                                                      H.xs_mr.p, H.yp_mr.p);
         k_phaseB2_mr<<<(unsigned)((nleaf + 3) / 4), 256, 0, s>>>(
             nleaf, H.kappa, H.lev[H.kappa].begin.p, H.lev[H.kappa].count.p, H.lev[H.kappa].il_ptr.p, H.near_ptr.p,
-            H.bnear.p, H.bil.p, H.U64.p, H.D64.p, H.tp_mr.p, H.xs_mr.p, H.n_b1 ? H.yp_mr.p : nullptr, H.perm.p,
-            y + (int64_t)r0 * ld, ld, nr);
+            H.bnear.p, H.bil.p, H.U64.p, H.D64.p, H.tp_mr.p, H.xs_mr.p, H.n_b1 ? 1 : 0, H.yp_mr.p);
+        k_scatter_mr<<<pblocks, 256, 0, s>>>(H.yp_mr.p, H.iperm.p, n, nr, y + (int64_t)r0 * ld, ld);
         HIPCK(hipGetLastError());
     }
 }

@@ -117,7 +117,7 @@ def load():
     L.h2d_mlp_loss_grad.restype = C.c_int
     L.h2d_autotune.argtypes = [P, C.c_int32, P, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     L.h2d_autotune.restype = C.c_int
-    L.h2d_set_item_rows.argtypes = [P, C.c_int32, P]
+    L.h2d_set_item_rows.argtypes = [P, C.c_int32, C.c_int32, P]
     L.h2d_set_item_rows.restype = C.c_int
     L.h2d_batch_create.argtypes = [C.POINTER(P), C.c_int32, C.c_int32, C.POINTER(P), C.POINTER(P),
                                    C.POINTER(C.c_int64), C.POINTER(P)]
@@ -277,10 +277,11 @@ class HODLR2D:
         chosen = C.c_int32()
         ms = (C.c_float * 3)()
         _check(load().h2d_autotune(self._h, int(nrhs), _stream(), C.byref(chosen), ms))
-        return int(chosen.value), dict(zip((128, 256, 512), list(ms)))
+        cand = (64, 128, 256) if nrhs > 1 else (128, 256, 512)
+        return int(chosen.value), dict(zip(cand, list(ms)))
 
-    def set_item_rows(self, rows):
-        _check(load().h2d_set_item_rows(self._h, int(rows), _stream()))
+    def set_item_rows(self, rows, multi=False):
+        _check(load().h2d_set_item_rows(self._h, 1 if multi else 0, int(rows), _stream()))
 
     def export(self, path, factors=True):
         _check(load().h2d_export(self._h, str(path).encode(), 1 if factors else 0))

@@ -70,7 +70,7 @@ def test_autotune_keeps_results(orc, tmp_path):
     X = np.random.default_rng(6).uniform(-1, 1, (16, xy.shape[0]))
     chosen, ms = H.autotune(16)
     say(f"autotune chose {chosen}, ms {ms}")
-    assert chosen in (128, 256, 512)
+    assert chosen in (64, 128, 256)
     assert all(v > 0 for v in ms.values())
     Y = host(H.matvec(dev(X)))
     y1 = host(H.matvec(dev(X[3])))
@@ -80,10 +80,11 @@ def test_autotune_keeps_results(orc, tmp_path):
     assert np.linalg.norm(y1 - O.matvec(X[3])) <= 1e-12 * np.linalg.norm(y1)
 
 
-@pytest.mark.parametrize("rows", [128, 256])
+@pytest.mark.parametrize("rows", [16, 128, 256])
 def test_item_size_changes_schedule_not_result(rows):
     """A smaller phase-A item splits more V blocks into partial sums; the
-    product must agree with the default schedule to rounding."""
+    product (single- and multi-RHS) must agree with the default schedule to
+    rounding."""
     rng = np.random.default_rng(rows)
     xy = inputs.uniform_square(30000, rng)
     spec = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}
@@ -92,6 +93,7 @@ def test_item_size_changes_schedule_not_result(rows):
     y_ref = host(H.matvec(dev(x)))
     y1_ref = host(H.matvec(dev(x[0])))
     H.set_item_rows(rows)
+    H.set_item_rows(max(rows // 2, 16), multi=True)
     y = host(H.matvec(dev(x)))
     y1 = host(H.matvec(dev(x[0])))
     assert np.linalg.norm(y - y_ref) <= 1e-14 * np.linalg.norm(y_ref)
