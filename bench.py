@@ -132,7 +132,7 @@ def batched(count, nrhs=16, reps=10):
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
-    picks = [H.autotune(nrhs)[0] for H in hs]
+    picks = [H.autotune(nrhs)[0]["mr_rows"] for H in hs]
     t_tune = time.perf_counter() - t0
     infos = [H.info() for H in hs]
     byts = sum(mr_bytes(i, nrhs) for i in infos)

@@ -246,9 +246,10 @@ h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t*
  * algorithmic bytes of each kernel over the recorded matvecs, and clears
  * the record.  At most 65536 matvecs are recorded between reads.
  * Kernels: 0 gather x into tree order; 1 phase A, t = V^T x for every
- * low-rank block; 2 sums of split phase-A partials; 3 phase B1, U t for
- * the blocks of levels 1..kappa-1; 4 phase B2, leaf-level blocks and near
- * field, y written in caller order. */
+ * low-rank block; 2 sums of split phase-A partials; 3 phase B, U t (or
+ * D x) for the blocks of levels 1..kappa-1 and, in the same launch, the
+ * leaf-level blocks and near field; 4 combine, the two phase-B sums added
+ * and written in caller order. */
 typedef struct {
     int32_t count;         /* matvecs averaged */
     int32_t prec;          /* precision of the last recorded matvec */
@@ -259,12 +260,19 @@ typedef struct {
 h2d_status h2d_profile_enable(h2d_t H, int32_t on);
 h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
 
-/* Tile tuning: times FP64 products with nrhs right-hand sides for each
- * candidate work-item size and keeps the fastest for H.  nrhs == 1 tunes
- * the V rows per single-RHS phase-A item (128, 256, 512); nrhs > 1 tunes
- * the source rows per multi-RHS phase-A item (64, 128, 256).  chosen
- * (host, may be NULL) receives the pick, ms (host, 3 floats, may be NULL)
- * the measured milliseconds per product. */
+/* Work-item sizes of the product kernels (h2d_set_item_rows, h2d_autotune). */
+typedef enum {
+    H2D_TILE_A_ROWS = 0,   /* V rows per single-RHS phase-A item: 16..512 (default 512) */
+    H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS phase-A item: 16..256, multiple of 16 (default 256) */
+    H2D_TILE_B1_ROWS = 2   /* rows per single-RHS phase-B1 item: 16, 32 or 64 (default 64) */
+} h2d_tile;
+
+/* Tile tuning: times 5 FP64 products with nrhs right-hand sides for each
+ * candidate and keeps the fastest for H.  nrhs == 1 tunes H2D_TILE_A_ROWS
+ * over (128, 256, 512), then H2D_TILE_B1_ROWS over (16, 32, 64); nrhs > 1
+ * tunes H2D_TILE_MR_ROWS over (64, 128, 256).  chosen (host, 2 ints, may be
+ * NULL) receives the picks (second 0 for nrhs > 1); ms (host, 6 floats, may
+ * be NULL) the milliseconds per product of each candidate in that order. */
 h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, float* ms);
 
 /* Batched products: the FP64 products y_i = A_i x_i of `count` built
@@ -276,11 +284,10 @@ h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, fl
  * concurrently with a launch, and must not be re-tuned (h2d_autotune,
  * h2d_set_item_rows) while the batch exists: the graph holds their
  * schedule and work-space addresses. */
-/* Sets a work-item size explicitly: multi == 0, V rows per single-RHS
- * phase-A item (16..512; the schedule is rebuilt at once); multi != 0,
- * source rows per multi-RHS phase-A item (16..256, a multiple of 16;
- * rebuilt at the next multi-RHS product).  H2D_EINVAL outside range. */
-h2d_status h2d_set_item_rows(h2d_t H, int32_t multi, int32_t rows, void* stream);
+/* Sets one work-item size (which: an h2d_tile value) explicitly; the
+ * single-RHS schedule is rebuilt at once, the multi-RHS one at the next
+ * multi-RHS product.  H2D_EINVAL outside the ranges listed at h2d_tile. */
+h2d_status h2d_set_item_rows(h2d_t H, int32_t which, int32_t rows, void* stream);
 
 typedef struct h2d_batch_s* h2d_batch_t;
 h2d_status h2d_batch_create(h2d_t const* handles, int32_t count, int32_t nrhs, double* const* x, double* const* y,

@@ -507,13 +507,20 @@ h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, fl
     });
 }
 
-h2d_status h2d_set_item_rows(h2d_t H, int32_t multi, int32_t rows, void* stream)
+h2d_status h2d_set_item_rows(h2d_t H, int32_t which, int32_t rows, void* stream)
 {
     return guarded([&] {
         if (!H) fail(H2D_EINVAL, "NULL handle");
-        if (!multi && (rows < 16 || rows > kPhaseARows)) fail(H2D_EINVAL, "item rows must lie in 16..512");
-        if (multi && (rows < 16 || rows > 256 || rows % 16)) fail(H2D_EINVAL, "chunk rows must be 16..256, multiple of 16");
-        set_item_rows(H->h, multi != 0, rows, (hipStream_t)stream);
+        if (which == H2D_TILE_A_ROWS) {
+            if (rows < 16 || rows > kPhaseARows) fail(H2D_EINVAL, "phase-A item rows must lie in 16..512");
+        } else if (which == H2D_TILE_MR_ROWS) {
+            if (rows < 16 || rows > 256 || rows % 16) fail(H2D_EINVAL, "chunk rows must be 16..256, multiple of 16");
+        } else if (which == H2D_TILE_B1_ROWS) {
+            if (rows != 16 && rows != 32 && rows != 64) fail(H2D_EINVAL, "phase-B1 slice rows must be 16, 32 or 64");
+        } else {
+            fail(H2D_EINVAL, "unknown tile parameter");
+        }
+        set_item_rows(H->h, which, rows, (hipStream_t)stream);
     });
 }
 

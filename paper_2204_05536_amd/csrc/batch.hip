@@ -88,26 +88,27 @@ void batch_launch(Batch* B, hipStream_t s) { HIPCK(hipGraphLaunch(B->exec, s)); 
 
 void batch_destroy(Batch* B) { delete B; }
 
-// Time 5 products for each candidate item size; keep the fastest.  One
-// right-hand side tunes the single-RHS phase-A item rows (128, 256, 512);
-// several tune the source-chunk rows of the multi-RHS phase A (64, 128, 256).
-static void set_rows(Handle& H, bool multi, int32_t rows, hipStream_t s)
+// which: 0 single-RHS phase-A item rows, 1 multi-RHS phase-A source-chunk
+// rows, 2 single-RHS phase-B1 slice rows.
+static void set_rows(Handle& H, int which, int32_t rows, hipStream_t s)
 {
-    if (multi) {
+    if (which == 1) {
         H.mr_rows = rows;
         H.mr_cap = 0;   // rebuilt with the next multi-RHS product
     } else {
-        H.a_rows = rows;
+        (which == 0 ? H.a_rows : H.b1_rows) = rows;
         finalize(H, s);
     }
 }
 
-void set_item_rows(Handle& H, bool multi, int32_t rows, hipStream_t s) { set_rows(H, multi, rows, s); }
+void set_item_rows(Handle& H, int which, int32_t rows, hipStream_t s) { set_rows(H, which, rows, s); }
 
+// Time 5 products per candidate and keep the fastest; one right-hand side
+// tunes phase A (128, 256, 512) then phase B1 (16, 32, 64), several tune the
+// multi-RHS source chunks (64, 128, 256).
 void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out)
 {
     const bool multi = nrhs > 1;
-    const int32_t cand[3] = {multi ? 64 : 128, multi ? 128 : 256, multi ? 256 : 512};
     const int64_t n = H.n;
     DBuf<double> x, y;
     x.alloc((size_t)n * nrhs);
@@ -116,28 +117,39 @@ void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
-    float best = 1e30f;
-    int32_t arg = multi ? H.mr_rows : H.a_rows;
     const bool prof = H.prof_on;
     H.prof_on = false;
-    for (int c = 0; c < 3; ++c) {
-        set_rows(H, multi, cand[c], s);
-        launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);   // warm-up, allocates
-        HIPCK(hipEventRecord(e0, s));
-        for (int r = 0; r < 5; ++r) launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);
-        HIPCK(hipEventRecord(e1, s));
-        HIPCK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCK(hipEventElapsedTime(&ms, e0, e1));
-        ms /= 5.f;
-        if (ms_out) ms_out[c] = ms;
-        if (ms < best) { best = ms; arg = cand[c]; }
+    struct Knob {
+        int which;
+        int32_t cand[3];
+    };
+    const Knob single[2] = {{0, {128, 256, 512}}, {2, {16, 32, 64}}};
+    const Knob mr[1] = {{1, {64, 128, 256}}};
+    const Knob* knobs = multi ? mr : single;
+    const int nk = multi ? 1 : 2;
+    for (int kb = 0; kb < nk; ++kb) {
+        float best = 1e30f;
+        int32_t arg = knobs[kb].cand[0];
+        for (int c = 0; c < 3; ++c) {
+            set_rows(H, knobs[kb].which, knobs[kb].cand[c], s);
+            launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);   // warm-up, allocates
+            HIPCK(hipEventRecord(e0, s));
+            for (int r = 0; r < 5; ++r) launch_matvec(H, x.p, y.p, nrhs, n, H2D_P_FP64, s);
+            HIPCK(hipEventRecord(e1, s));
+            HIPCK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCK(hipEventElapsedTime(&ms, e0, e1));
+            ms /= 5.f;
+            if (ms_out) ms_out[3 * kb + c] = ms;
+            if (ms < best) { best = ms; arg = knobs[kb].cand[c]; }
+        }
+        set_rows(H, knobs[kb].which, arg, s);
+        if (chosen) chosen[kb] = arg;
     }
+    if (multi && chosen) chosen[1] = 0;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    set_rows(H, multi, arg, s);
     H.prof_on = prof;
-    if (chosen) *chosen = arg;
 }
 
 }  // namespace h2d

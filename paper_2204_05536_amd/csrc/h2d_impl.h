@@ -176,8 +176,11 @@ struct Handle {
     DBuf<ADesc> aitems;
     DBuf<RDesc> ritems;
     int64_t n_aitems = 0, n_ritems = 0;
-    DBuf<int2> b1items;         // phase-B1 work: (box at level kappa - 1, first row of a 64-row chunk)
+    DBuf<int2> b1items;         // multi-RHS phase-B1 work: (box at level kappa - 1, first row of a 64-row chunk)
     int64_t n_b1 = 0;
+    DBuf<int2> b1s_items;       // single-RHS phase-B1 work: (box, first row of a b1_rows-row slice)
+    int64_t n_b1s = 0;
+    int32_t b1_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
 
     // multi-RHS work (blocks of 16 right-hand sides, point-major)
     DBuf<double> xs_mr, tp_mr, pp_mr, yp_mr;
@@ -241,7 +244,7 @@ Batch* batch_create(Handle** hs, int count, int nrhs, double* const* x, double* 
 void batch_launch(Batch* B, hipStream_t s);
 void batch_destroy(Batch* B);
 void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out);
-void set_item_rows(Handle& H, bool multi, int32_t rows, hipStream_t s);
+void set_item_rows(Handle& H, int which, int32_t rows, hipStream_t s);
 
 // solve.hip
 h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_solve_opts& o,

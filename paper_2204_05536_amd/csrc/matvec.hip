@@ -44,6 +44,15 @@ template <> __device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfl
 template <typename T, typename A> __device__ __forceinline__ A ld(const T* p) { return (A)ldf<T>(p); }
 template <> __device__ __forceinline__ double ld<double, double>(const double* p) { return __builtin_nontemporal_load(p); }
 
+// Phase B reads FP64 factors with ordinary loads (measured slightly faster
+// there than nontemporal ones); half factors keep the nontemporal path.
+template <typename T, typename A>
+__device__ __forceinline__ A ldv(const T* p)
+{
+    if constexpr (sizeof(T) == sizeof(A)) return *p;
+    else return ld<T, A>(p);
+}
+
 template <typename A>
 __global__ void k_gather(const double* x, const int32_t* perm, int32_t n, int64_t ldx, int64_t ldxs, int nrhs, A* xs)
 {
@@ -153,40 +162,42 @@ k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ pp
     }
 }
 
-// Phase B1: ancestor levels.  One wave per 64-row chunk of a box at level
-// kappa - 1; lane r owns row r.  For every interaction-list block of that
-// box and of each ancestor, the chunk's rows of every column of U (or D)
-// are 64 consecutive values, read by one coalesced load.
-template <typename T, typename A, bool kHalf>
-__global__ void __launch_bounds__(256)
-k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, const BDesc* __restrict__ bil,
-          const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
-          A* __restrict__ ypart, const float* __restrict__ scale)
+// Phase B1: ancestor levels.  One wave per slice of S rows (S = 16, 32 or
+// 64) of a box at level kappa - 1; lane (g, r) owns row r of the slice and
+// the columns g, g + G, ... (G = 64 / S) of every interaction-list block of
+// that box and of each ancestor, so one load covers G columns of S
+// consecutive values.  The G column-group sums are added in a fixed order.
+// Smaller slices give more, shorter work items (a shorter tail when the
+// items do not fill a whole number of rounds of the machine).
+template <typename T, typename A, bool kHalf, int S>
+__device__ __forceinline__ void
+b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict__ items, int tl, const LevelPtrs& L,
+        const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
+        const A* __restrict__ tpool, const A* __restrict__ xs, A* __restrict__ ypart, const float* __restrict__ scale)
 {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t it = xcd_tile() * 4 + wave;
-    if (it >= nitems) return;
     const int2 w = items[it];
     const int32_t P = uni(w.x), rc = uni(w.y);
     const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
-    const int32_t rows = min(kWave, cnt - rc);
-    const bool act = lane < rows;
+    const int32_t rows = min(S, cnt - rc);
+    constexpr int G = kWave / S;
+    const int g = G == 1 ? 0 : lane / S, r = G == 1 ? lane : lane % S;
+    const bool act = r < rows;
     A acc = (A)0;
     int32_t a_box = P;
     for (int l = tl; l >= 1; --l) {
         const int32_t ab = uni(L.begin[l][a_box]), ld_m = uni(L.count[l][a_box]);
-        const int64_t off = (int64_t)(p0 - ab + rc + lane);
+        const int64_t off = (int64_t)(p0 - ab + rc + r);
         const int32_t q0 = uni(L.il_ptr[l][a_box]), q1 = uni(L.il_ptr[l][a_box + 1]);
         for (int32_t q = q0; q < q1; ++q) {
             const BDesc d = uni(bil[q]);
             if (d.cols > 0) {
                 // U is tiled by level-(kappa - 1) boxes: this box's tile is
                 // a contiguous cnt x k column-major matrix
-                const T* base = Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + lane;
+                const T* base = Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + r;
                 const A* tv = tpool + d.tsrc;
                 if (act) {
 #pragma unroll 8
-                    for (int32_t c = 0; c < d.cols; ++c) acc += ld<T, A>(base + (int64_t)c * cnt) * tv[c];
+                    for (int32_t c = g; c < d.cols; c += G) acc += ldv<T, A>(base + (int64_t)c * cnt) * tv[c];
                 }
             } else if (d.cols < 0) {
                 const T* base = Dp + d.off + off;
@@ -194,7 +205,7 @@ k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, c
                 A a = (A)0;
                 if (act) {
 #pragma unroll 8
-                    for (int32_t j = 0; j < -d.cols; ++j) a += ld<T, A>(base + (int64_t)j * ld_m) * tv[j];
+                    for (int32_t j = g; j < -d.cols; j += G) a += ldv<T, A>(base + (int64_t)j * ld_m) * tv[j];
                 }
                 if constexpr (kHalf) acc += a * (A)scale[q];
                 else acc += a;
@@ -202,7 +213,18 @@ k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, c
         }
         a_box = uni(L.parent[l][a_box]);
     }
-    if (act) ypart[p0 + rc + lane] = acc;
+    if constexpr (G == 1) {
+        if (act) ypart[p0 + rc + r] = acc;
+        return;
+    }
+    red[wave][lane] = act ? acc : (A)0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rows) {
+        A s = (A)0;
+        for (int gg = 0; gg < G; ++gg) s += red[wave][gg * S + lane];
+        ypart[p0 + rc + lane] = s;
+    }
 }
 
 // Phase B2: the leaf level.  One wave per leaf box X: its dense near blocks
@@ -211,16 +233,12 @@ k_phaseB1(int32_t nitems, const int2* __restrict__ items, int tl, LevelPtrs L, c
 // lane (g, r) takes row r and the columns g, g + G, ... (G = 64 / rows), so
 // a load covers G consecutive columns of the column-major block.
 template <typename T, typename A, bool kHalf>
-__global__ void __launch_bounds__(256)
-k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
-          const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool,
-          const A* __restrict__ xs, const A* __restrict__ ypart, const int32_t* __restrict__ perm, double* __restrict__ y,
-          const float* __restrict__ scale, const float* __restrict__ diag, int64_t n_il)
+__device__ __forceinline__ void
+b2_item(int32_t X, int wave, int lane, A (*red)[kWave], int kappa, const LevelPtrs& L,
+        const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
+        const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
+        A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
 {
-    __shared__ A red[4][kWave];
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t X = xcd_tile() * 4 + wave;
-    if (X >= nleaf) return;
     const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
     const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
     const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
@@ -236,7 +254,7 @@ k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ nea
             A a = (A)0;
             if (act) {
 #pragma unroll 4
-                for (int32_t j = g; j < -d.cols; j += G) a += ld<T, A>(base + (int64_t)j * cnt) * tv[j];
+                for (int32_t j = g; j < -d.cols; j += G) a += ldv<T, A>(base + (int64_t)j * cnt) * tv[j];
             }
             if constexpr (kHalf) acc += a * (A)scale[n_il + q];
             else acc += a;
@@ -248,7 +266,7 @@ k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ nea
                 const A* tv = tpool + d.tsrc;
                 if (act) {
 #pragma unroll 4
-                    for (int32_t c = g; c < d.cols; c += G) acc += ld<T, A>(base + (int64_t)c * cnt) * tv[c];
+                    for (int32_t c = g; c < d.cols; c += G) acc += ldv<T, A>(base + (int64_t)c * cnt) * tv[c];
                 }
             } else if (d.cols < 0) {
                 const T* base = Dp + d.off + rc + r;
@@ -256,7 +274,7 @@ k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ nea
                 A a = (A)0;
                 if (act) {
 #pragma unroll 4
-                    for (int32_t j = g; j < -d.cols; j += G) a += ld<T, A>(base + (int64_t)j * cnt) * tv[j];
+                    for (int32_t j = g; j < -d.cols; j += G) a += ldv<T, A>(base + (int64_t)j * cnt) * tv[j];
                 }
                 if constexpr (kHalf) acc += a * (A)scale[q];
                 else acc += a;
@@ -268,14 +286,67 @@ k_phaseB2(int32_t nleaf, int kappa, LevelPtrs L, const int32_t* __restrict__ nea
         if (lane < rows) {
             A s = (A)0;
             for (int gg = 0; gg < G; ++gg) s += red[wave][gg * rows + lane];
-            const int32_t i = r0 + rc + lane;
-            if (ypart) s += ypart[i];
-            if constexpr (kHalf) s += (A)diag[i] * xs[i];
-            y[perm[i]] = (double)s;
+            yleaf[r0 + rc + lane] = s;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+// Workgroups w0 .. w0 + n - 1 of the grid -> tiles 0 .. n - 1 such that
+// the workgroups each XCD receives (workgroup ids are dealt round-robin over
+// the 8 XCDs) take one contiguous range of tiles.
+__device__ __forceinline__ int32_t xcd_sub(int32_t w, int32_t w0, int32_t n)
+{
+    const int32_t x = w % 8;
+    int32_t start = 0;
+    for (int xx = 0; xx < x; ++xx) {
+        const int32_t f = ((xx - w0) % 8 + 8) % 8;   // first local index dealt to XCD xx
+        start += f < n ? (n - f + 7) / 8 : 0;
+    }
+    const int32_t f = ((x - w0) % 8 + 8) % 8;
+    return start + (w - w0 - f) / 8;
+}
+
+// Phase B, both halves in one launch: the first nb1 workgroups do phase-B1
+// slices (ancestor levels, into ypart), the next nb2 do phase-B2 leaf boxes
+// (leaf level and near field, into yleaf).  The two halves write different
+// arrays and do not depend on each other; the latency-bound leaf work is
+// dispatched as the ancestor work drains, filling its tail.
+template <typename T, typename A, bool kHalf, int S>
+__global__ void __launch_bounds__(256)
+k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa, LevelPtrs L,
+         const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
+         const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
+         A* __restrict__ ypart, A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il, int32_t nleaf)
+{
+    __shared__ A red[4][kWave];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t w = blockIdx.x;
+    if (w < nb1) {
+        const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
+        if (it < nitems) b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart,
+                                                 scale);
+    } else {
+        const int32_t X = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
+        if (X < nleaf) b2_item<T, A, kHalf>(X, wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs, yleaf,
+                                            scale, n_il);
+    }
+}
+
+// y (caller order) = ypart + yleaf (+ the FP32 self diagonal times x for
+// the half pools), one thread per tree row.
+template <typename A, bool kHalf>
+__global__ void k_combine(int32_t n, const A* __restrict__ ypart, const A* __restrict__ yleaf,
+                          const int32_t* __restrict__ perm, const float* __restrict__ diag, const A* __restrict__ xs,
+                          double* __restrict__ y)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    A s = yleaf[i];
+    if (ypart) s += ypart[i];
+    if constexpr (kHalf) s += (A)diag[i] * xs[i];
+    y[perm[i]] = (double)s;
 }
 
 template <typename T>
@@ -355,15 +426,21 @@ void finalize(Handle& H, hipStream_t s)
             near_e += (double)LL.h_count[x] * LL.h_count[H.h_near_src[q]];
     flops += 2.0 * near_e;
     store_leaf += near_e;
-    // phase-B1 work: 64-row chunks of the boxes one level above the leaves
-    std::vector<int2> b1;
+    // phase-B1 work: 64-row chunks (multi-RHS) and b1_rows-row slices
+    // (single-RHS) of the boxes one level above the leaves
+    std::vector<int2> b1, b1s;
+    const int32_t S = H.b1_rows;
     if (kappa >= 2) {
         const Level& T = H.lev[kappa - 1];
-        for (int64_t p = 0; p < T.nbox; ++p)
+        for (int64_t p = 0; p < T.nbox; ++p) {
             for (int32_t rc = 0; rc < T.h_count[p]; rc += kWave) b1.push_back(make_int2((int32_t)p, rc));
+            for (int32_t rc = 0; rc < T.h_count[p]; rc += S) b1s.push_back(make_int2((int32_t)p, rc));
+        }
     }
     H.n_b1 = (int64_t)b1.size();
+    H.n_b1s = (int64_t)b1s.size();
     upload_vec(H.b1items, b1, s);
+    upload_vec(H.b1s_items, b1s, s);
     H.flops = flops;
     H.t_elems = toff; H.p_elems = poff;
     // algorithmic bytes per kernel: every stored value and vector touched once
@@ -374,11 +451,13 @@ void finalize(Handle& H, hipStream_t s)
         H.phase_bytes[h][0] = nvec * (8 + 4 + a);                                          // x, perm -> xs
         H.phase_bytes[h][1] = (double)H.v_elems * sz + nvec * a + (double)toff * a + (double)poff * a;
         H.phase_bytes[h][2] = poff ? (double)poff * a + (double)toff * a : 0.0;           // partials -> t
-        H.phase_bytes[h][3] = H.n_b1 ? store_anc * sz + anc_t * a + nvec * a : 0.0;       // -> ypart
-        H.phase_bytes[h][4] = store_leaf * sz + t_leaf * a + nvec * (a + 4 + 8) + (H.n_b1 ? nvec * a : 0.0) +
-                              (h ? nvec * 4 : 0.0);                                        // -> y
+        // phase B: ancestor blocks -> ypart, leaf blocks and near field -> yleaf
+        H.phase_bytes[h][3] = (H.n_b1 ? store_anc * sz + anc_t * a + nvec * a : 0.0) + store_leaf * sz + t_leaf * a +
+                              nvec * a;
+        // combine: ypart + yleaf (+ diagonal and x for half) -> y via perm
+        H.phase_bytes[h][4] = nvec * (a + 4 + 8) + (H.n_b1 ? nvec * a : 0.0) + (h ? nvec * (4 + a) : 0.0);
     }
-    // one matvec: gather + A + (reduce) + B1 + B2 (reduce and B1 intermediates counted once)
+    // one matvec: gather + A + (reduce) + B + combine (intermediate vectors counted once each way)
     for (int h = 0; h < 2; ++h) {
         double t = 0;
         for (int p = 0; p < 5; ++p) t += H.phase_bytes[h][p];
@@ -399,12 +478,12 @@ void ensure_workspace(Handle& H, int nrhs)
     if (H.ws_nrhs >= nrhs) return;
     const int64_t n = H.n;
     H.xs.alloc((size_t)n * nrhs);
-    H.ypart.alloc((size_t)n * nrhs);
+    H.ypart.alloc((size_t)2 * n * nrhs);   // ancestor sums, then leaf-level sums
     H.tpool.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
     H.ppool.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     if (H.prec_mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16))) {
         H.xs32.alloc((size_t)n * nrhs);
-        H.ypart32.alloc((size_t)n * nrhs);
+        H.ypart32.alloc((size_t)2 * n * nrhs);
         H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
         H.ppool32.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     }
@@ -454,14 +533,21 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
     if (ev) HIPCK(hipEventRecord(ev[3], s));
     const LevelPtrs LP = level_ptrs(H);
-    if (H.n_b1)
-        k_phaseB1<T, A, kHalf><<<(unsigned)((H.n_b1 + 3) / 4), 256, 0, s>>>(
-            (int32_t)H.n_b1, H.b1items.p, H.kappa - 1, LP, H.bil.p, U, D, tp, xs, yp, H.scale16.p);
-    if (ev) HIPCK(hipEventRecord(ev[4], s));
     const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
-    k_phaseB2<T, A, kHalf><<<(unsigned)((nleaf + 3) / 4), 256, 0, s>>>(
-        nleaf, H.kappa, LP, H.near_ptr.p, H.bnear.p, H.bil.p, U, D, tp, xs, H.n_b1 ? yp : nullptr, H.perm.p, y,
-        H.scale16.p, H.diag32.p, H.n_il);
+    const int32_t nb1 = (int32_t)((H.n_b1s + 3) / 4), nb2 = (nleaf + 3) / 4;
+    const int32_t ni = (int32_t)H.n_b1s;
+    A* yl = yp + n;   // the work vector holds ypart then yleaf
+#define H2D_PHASE_B(SR)                                                                                              \
+    k_phaseB<T, A, kHalf, SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, \
+                                                                   H.bnear.p, H.bil.p, U, D, tp, xs, yp, yl,         \
+                                                                   H.scale16.p, H.n_il, nleaf)
+    if (H.b1_rows == 16) H2D_PHASE_B(16);
+    else if (H.b1_rows == 32) H2D_PHASE_B(32);
+    else H2D_PHASE_B(64);
+#undef H2D_PHASE_B
+    if (ev) HIPCK(hipEventRecord(ev[4], s));
+    k_combine<A, kHalf><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, ni ? yp : nullptr, yl, H.perm.p, H.diag32.p, xs,
+                                                                   y);
     if (ev) {
         HIPCK(hipEventRecord(ev[5], s));
         H.prof_used++;

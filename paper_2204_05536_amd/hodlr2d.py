@@ -30,7 +30,7 @@ EXPORTED = ["h2d_build", "h2d_matvec", "h2d_solve", "h2d_info", "h2d_export", "h
             "h2d_mlp_train", "h2d_mlp_weights", "h2d_mlp_loss_grad", "h2d_autotune", "h2d_set_item_rows", "h2d_batch_create",
             "h2d_batch_launch", "h2d_batch_destroy", "h2d_destroy", "h2d_last_error"]
 MLP_PARAMS = 131648
-PHASES = ["gather", "phaseA", "reduce", "phaseB1", "phaseB2"]
+PHASES = ["gather", "phaseA", "reduce", "phaseB", "combine"]
 
 
 class H2DError(RuntimeError):
@@ -274,14 +274,21 @@ class HODLR2D:
         return out, sc.value
 
     def autotune(self, nrhs=16):
-        chosen = C.c_int32()
-        ms = (C.c_float * 3)()
-        _check(load().h2d_autotune(self._h, int(nrhs), _stream(), C.byref(chosen), ms))
-        cand = (64, 128, 256) if nrhs > 1 else (128, 256, 512)
-        return int(chosen.value), dict(zip(cand, list(ms)))
+        """Returns (picks, {(knob, candidate): ms}); picks = {knob: rows}."""
+        chosen = (C.c_int32 * 2)()
+        ms = (C.c_float * 6)()
+        _check(load().h2d_autotune(self._h, int(nrhs), _stream(), chosen, ms))
+        if nrhs > 1:
+            return {"mr_rows": chosen[0]}, {("mr_rows", c): ms[i] for i, c in enumerate((64, 128, 256))}
+        times = {("a_rows", c): ms[i] for i, c in enumerate((128, 256, 512))}
+        times.update({("b1_rows", c): ms[3 + i] for i, c in enumerate((16, 32, 64))})
+        return {"a_rows": chosen[0], "b1_rows": chosen[1]}, times
 
-    def set_item_rows(self, rows, multi=False):
-        _check(load().h2d_set_item_rows(self._h, 1 if multi else 0, int(rows), _stream()))
+    def set_item_rows(self, which, rows):
+        """which: "a_rows" (single-RHS phase A), "mr_rows" (multi-RHS phase A)
+        or "b1_rows" (single-RHS phase B1)."""
+        w = {"a_rows": 0, "mr_rows": 1, "b1_rows": 2}[which]
+        _check(load().h2d_set_item_rows(self._h, w, int(rows), _stream()))
 
     def export(self, path, factors=True):
         _check(load().h2d_export(self._h, str(path).encode(), 1 if factors else 0))

@@ -70,8 +70,11 @@ def test_autotune_keeps_results(orc, tmp_path):
     X = np.random.default_rng(6).uniform(-1, 1, (16, xy.shape[0]))
     chosen, ms = H.autotune(16)
     say(f"autotune chose {chosen}, ms {ms}")
-    assert chosen in (64, 128, 256)
+    assert chosen["mr_rows"] in (64, 128, 256)
     assert all(v > 0 for v in ms.values())
+    chosen1, ms1 = H.autotune(1)
+    say(f"autotune (1 RHS) chose {chosen1}, ms {ms1}")
+    assert chosen1["a_rows"] in (128, 256, 512) and chosen1["b1_rows"] in (16, 32, 64)
     Y = host(H.matvec(dev(X)))
     y1 = host(H.matvec(dev(X[3])))
     for r in range(16):
@@ -80,11 +83,11 @@ def test_autotune_keeps_results(orc, tmp_path):
     assert np.linalg.norm(y1 - O.matvec(X[3])) <= 1e-12 * np.linalg.norm(y1)
 
 
-@pytest.mark.parametrize("rows", [16, 128, 256])
-def test_item_size_changes_schedule_not_result(rows):
-    """A smaller phase-A item splits more V blocks into partial sums; the
-    product (single- and multi-RHS) must agree with the default schedule to
-    rounding."""
+@pytest.mark.parametrize("rows,b1", [(16, 16), (128, 32), (256, 64)])
+def test_item_size_changes_schedule_not_result(rows, b1):
+    """Smaller phase-A items split more V blocks into partial sums, smaller
+    phase-B1 slices add column groups; the product (single- and multi-RHS)
+    must agree with the default schedule to rounding."""
     rng = np.random.default_rng(rows)
     xy = inputs.uniform_square(30000, rng)
     spec = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}
@@ -92,8 +95,9 @@ def test_item_size_changes_schedule_not_result(rows):
     x = rng.uniform(-1, 1, (16, 30000))
     y_ref = host(H.matvec(dev(x)))
     y1_ref = host(H.matvec(dev(x[0])))
-    H.set_item_rows(rows)
-    H.set_item_rows(max(rows // 2, 16), multi=True)
+    H.set_item_rows("a_rows", rows)
+    H.set_item_rows("mr_rows", max(rows // 2, 16))
+    H.set_item_rows("b1_rows", b1)
     y = host(H.matvec(dev(x)))
     y1 = host(H.matvec(dev(x[0])))
     assert np.linalg.norm(y - y_ref) <= 1e-14 * np.linalg.norm(y_ref)
