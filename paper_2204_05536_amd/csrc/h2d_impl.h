@@ -183,7 +183,7 @@ struct Handle {
     int32_t b1_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
 
     // multi-RHS work (blocks of 16 right-hand sides, point-major)
-    DBuf<double> xs_mr, tp_mr, pp_mr, yp_mr;
+    DBuf<double> xs_mr, tp_mr, pp_mr, yp_mr, yl_mr;
     DBuf<const int32_t*> lvl_ptrs;   // begin, count, parent, il_ptr per level (device copies of the pointers)
     int mr_cap = 0;
     DBuf<MRItem> mr_items;           // multi-RHS phase-A items (source-grouped)

@@ -32,13 +32,6 @@ __device__ __forceinline__ int64_t uni_l(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ int32_t xcd_tile_mr()
-{
-    const int32_t W = gridDim.x, w = blockIdx.x, xcd = w % 8, i8 = w / 8;
-    const int32_t q8 = W / 8, r8 = W % 8;
-    return xcd * q8 + min(xcd, r8) + i8;
-}
-
 // xs[iperm[c] * 16 + r] = x[r * ldx + c] for r < nr, 0 beyond.  64
 // caller-order points per workgroup: the right-hand-side rows are read
 // coalesced, transposed through LDS, and each point's 16 values are written
@@ -60,17 +53,21 @@ k_gather_mr(const double* __restrict__ x, int64_t ldx, int32_t nr, const int32_t
     }
 }
 
-// y[r * ldy + c] = yt[iperm[c] * 16 + r] for r < nr: the inverse of the
-// gather, from the tree-ordered point-major result back to caller order.
+// y[r * ldy + c] = (yt + ya)[iperm[c] * 16 + r] for r < nr (ya may be
+// NULL): the inverse of the gather, from the tree-ordered point-major leaf
+// and ancestor sums back to caller order.
 __global__ void __launch_bounds__(256)
-k_scatter_mr(const double* __restrict__ yt, const int32_t* __restrict__ iperm, int32_t n, int32_t nr,
-             double* __restrict__ y, int64_t ldy)
+k_scatter_mr(const double* __restrict__ yt, const double* __restrict__ ya, const int32_t* __restrict__ iperm, int32_t n,
+             int32_t nr, double* __restrict__ y, int64_t ldy)
 {
     __shared__ double tile[kR][kWave + 1];
     const int32_t c0 = blockIdx.x * kWave;
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
         const int c = e / kR, r = e % kR;
-        if (c0 + c < n) tile[r][c] = yt[(int64_t)iperm[c0 + c] * kR + r];
+        if (c0 + c < n) {
+            const int64_t g = (int64_t)iperm[c0 + c] * kR + r;
+            tile[r][c] = ya ? yt[g] + ya[g] : yt[g];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
@@ -276,16 +273,13 @@ __device__ __forceinline__ void mm_tile(d4 (&acc)[4], const double* __restrict__
 
 // Phase B1 (ancestor levels): one wave per 64-row chunk of a box at level
 // kappa - 1; U tiles as in the single-RHS path.  ypart is row-major n x 16.
-__global__ void __launch_bounds__(256)
-k_phaseB1_mr(int32_t nitems, const int2* __restrict__ items, int tl, const int32_t* const* __restrict__ Lbegin,
-             const int32_t* const* __restrict__ Lcount, const int32_t* const* __restrict__ Lparent,
-             const int32_t* const* __restrict__ Lil, const BDesc* __restrict__ bil, const double* __restrict__ Up,
-             const double* __restrict__ Dp, const double* __restrict__ tpool, const double* __restrict__ xs,
-             double* __restrict__ ypart)
+__device__ __forceinline__ void
+b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_t* const* __restrict__ Lbegin,
+      const int32_t* const* __restrict__ Lcount, const int32_t* const* __restrict__ Lparent,
+      const int32_t* const* __restrict__ Lil, const BDesc* __restrict__ bil, const double* __restrict__ Up,
+      const double* __restrict__ Dp, const double* __restrict__ tpool, const double* __restrict__ xs,
+      double* __restrict__ ypart)
 {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t it = xcd_tile_mr() * 4 + wave;
-    if (it >= nitems) return;
     const int2 w = items[it];
     const int32_t P = uni_i(w.x), rc = uni_i(w.y);
     const int32_t p0 = uni_i(Lbegin[tl][P]), cnt = uni_i(Lcount[tl][P]);
@@ -319,18 +313,14 @@ k_phaseB1_mr(int32_t nitems, const int2* __restrict__ items, int tl, const int32
         }
 }
 
-// Phase B2 (leaf level): one wave per leaf box; near blocks, the leaf's
-// own interaction-list blocks, plus the ancestor sums already in yt (when
-// has_anc); the result replaces yt (tree order, point-major).
-__global__ void __launch_bounds__(256)
-k_phaseB2_mr(int32_t nleaf, int kappa, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
-             const int32_t* __restrict__ il_ptr, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
-             const BDesc* __restrict__ bil, const double* __restrict__ Up, const double* __restrict__ Dp,
-             const double* __restrict__ tpool, const double* __restrict__ xs, int has_anc, double* __restrict__ yt)
+// Phase B2 (leaf level): one wave per leaf box; near blocks and the leaf's
+// own interaction-list blocks, into yt (tree order, point-major).
+__device__ __forceinline__ void
+b2_mr(int32_t X, int lane, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+      const int32_t* __restrict__ il_ptr, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
+      const BDesc* __restrict__ bil, const double* __restrict__ Up, const double* __restrict__ Dp,
+      const double* __restrict__ tpool, const double* __restrict__ xs, double* __restrict__ yt)
 {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t X = xcd_tile_mr() * 4 + wave;
-    if (X >= nleaf) return;
     const int32_t r0 = uni_i(begin[X]), cnt = uni_i(count[X]);
     const int32_t n0 = uni_i(near_ptr[X]), n1 = uni_i(near_ptr[X + 1]);
     const int32_t q0 = uni_i(il_ptr[X]), q1 = uni_i(il_ptr[X + 1]);
@@ -356,11 +346,46 @@ k_phaseB2_mr(int32_t nleaf, int kappa, const int32_t* __restrict__ begin, const 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int32_t i = 16 * t + 4 * v + lk;
-                if (i < rows) {
-                    const int64_t g = (int64_t)(r0 + rc + i) * kR + li;
-                    yt[g] = has_anc ? acc[t][v] + yt[g] : acc[t][v];
-                }
+                if (i < rows) yt[(int64_t)(r0 + rc + i) * kR + li] = acc[t][v];
             }
+    }
+}
+
+// Workgroups w0 .. w0 + n - 1 -> tiles 0 .. n - 1, each XCD (workgroup ids
+// are dealt round-robin over the 8 XCDs) walking one contiguous range.
+__device__ __forceinline__ int32_t xcd_sub_mr(int32_t w, int32_t w0, int32_t n)
+{
+    const int32_t x = w % 8;
+    int32_t start = 0;
+    for (int xx = 0; xx < x; ++xx) {
+        const int32_t f = ((xx - w0) % 8 + 8) % 8;
+        start += f < n ? (n - f + 7) / 8 : 0;
+    }
+    const int32_t f = ((x - w0) % 8 + 8) % 8;
+    return start + (w - w0 - f) / 8;
+}
+
+// Phase B in one launch: the first nb1 workgroups do 64-row chunks of the
+// level-(kappa-1) boxes (ancestor levels, into ypart), the rest do leaf
+// boxes (into yleaf); the halves are independent and summed by the scatter.
+__global__ void __launch_bounds__(256)
+k_phaseB_mr(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
+            const int32_t* const* __restrict__ Lbegin, const int32_t* const* __restrict__ Lcount,
+            const int32_t* const* __restrict__ Lparent, const int32_t* const* __restrict__ Lil, int32_t nleaf,
+            const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
+            const double* __restrict__ Up, const double* __restrict__ Dp, const double* __restrict__ tpool,
+            const double* __restrict__ xs, double* __restrict__ ypart, double* __restrict__ yleaf)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t w = blockIdx.x;
+    if (w < nb1) {
+        const int32_t it = xcd_sub_mr(w, 0, nb1) * 4 + wave;
+        if (it < nitems)
+            b1_mr(it, lane, items, kappa - 1, Lbegin, Lcount, Lparent, Lil, bil, Up, Dp, tpool, xs, ypart);
+    } else {
+        const int32_t X = xcd_sub_mr(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
+        if (X < nleaf)
+            b2_mr(X, lane, Lbegin[kappa], Lcount[kappa], Lil[kappa], near_ptr, bnear, bil, Up, Dp, tpool, xs, yleaf);
     }
 }
 
@@ -443,6 +468,7 @@ void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t l
         H.tp_mr.alloc(std::max<int64_t>(H.t_elems, 1) * kR);
         H.pp_mr.alloc(std::max<int64_t>(H.mr_p_elems, 1) * kR);
         H.yp_mr.alloc((size_t)n * kR);
+        H.yl_mr.alloc((size_t)n * kR);
         H.iperm.alloc(std::max(n, 1));
         k_iperm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(H.perm.p, n, H.iperm.p);
         HIPCK(hipGetLastError());
@@ -474,14 +500,12 @@ void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t l
         if (H.n_mr_ritems)
             k_reduce_mr<<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256, 0,
                           s>>>(H.n_mr_ritems, H.mr_ritems.p, H.pp_mr.p, H.tp_mr.p);
-        if (H.n_b1)
-            k_phaseB1_mr<<<(unsigned)((H.n_b1 + 3) / 4), 256, 0, s>>>((int32_t)H.n_b1, H.b1items.p, H.kappa - 1, Lb, Lc,
-                                                                     Lp, Li, H.bil.p, H.U64.p, H.D64.p, H.tp_mr.p,
-                                                                     H.xs_mr.p, H.yp_mr.p);
-        k_phaseB2_mr<<<(unsigned)((nleaf + 3) / 4), 256, 0, s>>>(
-            nleaf, H.kappa, H.lev[H.kappa].begin.p, H.lev[H.kappa].count.p, H.lev[H.kappa].il_ptr.p, H.near_ptr.p,
-            H.bnear.p, H.bil.p, H.U64.p, H.D64.p, H.tp_mr.p, H.xs_mr.p, H.n_b1 ? 1 : 0, H.yp_mr.p);
-        k_scatter_mr<<<pblocks, 256, 0, s>>>(H.yp_mr.p, H.iperm.p, n, nr, y + (int64_t)r0 * ld, ld);
+        const int32_t nb1 = (int32_t)((H.n_b1 + 3) / 4), nb2 = (nleaf + 3) / 4;
+        k_phaseB_mr<<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, (int32_t)H.n_b1, H.b1items.p, H.kappa, Lb, Lc, Lp, Li,
+                                                          nleaf, H.near_ptr.p, H.bnear.p, H.bil.p, H.U64.p, H.D64.p,
+                                                          H.tp_mr.p, H.xs_mr.p, H.yp_mr.p, H.yl_mr.p);
+        k_scatter_mr<<<pblocks, 256, 0, s>>>(H.yl_mr.p, H.n_b1 ? H.yp_mr.p : nullptr, H.iperm.p, n, nr,
+                                             y + (int64_t)r0 * ld, ld);
         HIPCK(hipGetLastError());
     }
 }
