@@ -78,6 +78,32 @@ def cpu_baseline(n_sample: int = 65536, min_seconds: float = 5.0):
             "ms_per_matvec": per * 1e3}
 
 
+def kernel_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
+    on a known-size elementwise kernel) from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "matvec_fp64_mq1m_traffic.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_2204_05536_amd/csrc/matvec.hip", "paper_2204_05536_amd/csrc/h2d_impl.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    traffic, sha = {}, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic: "):
+                name, val = line.split()[1:3]
+                traffic[name] = float(val)
+            elif line.startswith("source_sha256: "):
+                sha = line.split()[1]
+    if sha != h.hexdigest():
+        return None
+    return traffic.get(kernel)
+
+
 def mr_bytes(info, nrhs):
     """Algorithmic bytes of one product with nrhs right-hand sides: the
     stored factors once, every vector term of the single-RHS count nrhs times."""
@@ -249,7 +275,8 @@ def main():
     achieved = prof["bytes"][dom] / (prof["ms"][dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": f"k_{dom}",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "alg_bytes_per_launch": prof["bytes"][dom], "avg_ms": prof["ms"][dom],
+                "traffic": kernel_traffic(f"k_{dom}"), "alg_bytes_per_launch": prof["bytes"][dom],
+                "avg_ms": prof["ms"][dom],
                 "phases_ms": prof["ms"], "phases_alg_bytes": prof["bytes"]}
     extra = {"build_seconds": t_build, "kappa": info["kappa"], "n_il_blocks": info["n_il"],
              "n_il_dense": info["n_il_dense"], "max_rank": info["max_rank"],
