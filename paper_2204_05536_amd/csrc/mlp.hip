@@ -212,6 +212,75 @@ static float loss_grad(const float* W, const float* X, const float* T, const flo
 }
 
 // ---------------------------------------------------------------------
+// BF16 inference on the matrix cores: C (M x N) = act(X W^T + b) with
+// v_mfma_f32_16x16x16bf16_1k (FP32 accumulation).  X: M x K row-major,
+// FP32 (the leaf features, rounded to BF16 on load) or BF16 (hidden
+// activations); W: N x K row-major BF16; b FP32.  Lane layout (checked on
+// the device with small integer matrices): A lane l holds
+// A[l % 16][4 (l / 16) + e], B lane l holds B[4 (l / 16) + e][l % 16], and
+// result register v of lane l is D[4 (l / 16) + v][l % 16].  One wave
+// computes 16 rows x N; K is a multiple of 16.
+// ---------------------------------------------------------------------
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf_bits(float x)
+{
+    return __builtin_bit_cast(short, __float2bfloat16(x));
+}
+__device__ __forceinline__ void store_out(float* p, float v) { *p = v; }
+__device__ __forceinline__ void store_out(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+
+template <typename TX, int N, bool kRelu, typename TO>
+__global__ void __launch_bounds__(256)
+k_dense_bf16(int64_t M, int K, const TX* __restrict__ X, const __hip_bfloat16* __restrict__ W,
+             const float* __restrict__ bias, TO* __restrict__ C)
+{
+    constexpr int NT = N / 16;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    if (m0 >= M) return;
+    const int li = lane % 16, lk = lane / 16;
+    const int64_t row = min(m0 + li, M - 1);   // rows past M re-read row M - 1; never stored
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const int kk = k0 + 4 * lk;
+        bf4 a;
+        if constexpr (sizeof(TX) == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(X + row * K + kk);
+            a = bf4{bf_bits(v.x), bf_bits(v.y), bf_bits(v.z), bf_bits(v.w)};
+        } else {
+            a = *reinterpret_cast<const bf4*>(X + row * K + kk);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf4 b = *reinterpret_cast<const bf4*>(W + (int64_t)(16 * t + li) * K + kk);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t m = m0 + 4 * lk + v;
+            const int n = 16 * t + li;
+            if (m < M) {
+                float y = acc[t][v] + bias[n];
+                if (kRelu) y = fmaxf(y, 0.f);
+                store_out(C + m * N + n, y);
+            }
+        }
+}
+
+__global__ void k_to_bf16(int64_t n, const float* __restrict__ src, __hip_bfloat16* __restrict__ dst)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = __float2bfloat16(src[e]);
+}
+
+// ---------------------------------------------------------------------
 // Leaf features and corrections
 // ---------------------------------------------------------------------
 __device__ __forceinline__ uint32_t compact_bits(uint32_t v)
@@ -304,10 +373,33 @@ struct MlpState {
     double scale = 1.0;   // s: z ~ s r over the training solves
     DBuf<float> w, m1, m2, grad;
     MlpWork work;
-    DBuf<float> feat, rn;
+    DBuf<float> feat, rn, out;               // inference: features, |r_X|, network output (FP32)
+    DBuf<__hip_bfloat16> w16, h1b, h2b;      // inference: BF16 weights (W1, W2, W3) and hidden activations
     int64_t feat_cap = 0;
+    bool w16_ok = false;                     // w16 holds the current FP32 weights rounded to BF16
     bool ready = false;
 };
+
+// BF16 forward of nleaf leaves into S.out (FP32 nleaf x 64).
+static void forward_bf16(MlpState& S, int64_t nleaf, hipStream_t s)
+{
+    constexpr int64_t n1 = (int64_t)kH * kIn, n2 = (int64_t)kH * kH, n3 = (int64_t)kOut * kH;
+    if (!S.w16_ok) {
+        S.w16.alloc(n1 + n2 + n3);
+        k_to_bf16<<<256, 256, 0, s>>>(n1, S.w.p + kOffW1, S.w16.p);
+        k_to_bf16<<<256, 256, 0, s>>>(n2, S.w.p + kOffW2, S.w16.p + n1);
+        k_to_bf16<<<64, 256, 0, s>>>(n3, S.w.p + kOffW3, S.w16.p + n1 + n2);
+        S.w16_ok = true;
+    }
+    const unsigned g = (unsigned)((nleaf + 63) / 64);
+    k_dense_bf16<float, kH, true, __hip_bfloat16><<<g, 256, 0, s>>>(nleaf, kIn, S.feat.p, S.w16.p, S.w.p + kOffB1,
+                                                                     S.h1b.p);
+    k_dense_bf16<__hip_bfloat16, kH, true, __hip_bfloat16><<<g, 256, 0, s>>>(nleaf, kH, S.h1b.p, S.w16.p + n1,
+                                                                              S.w.p + kOffB2, S.h2b.p);
+    k_dense_bf16<__hip_bfloat16, kOut, false, float><<<g, 256, 0, s>>>(nleaf, kH, S.h2b.p, S.w16.p + n1 + n2,
+                                                                        S.w.p + kOffB3, S.out.p);
+    HIPCK(hipGetLastError());
+}
 
 MlpState& mlp_state(Handle& H)
 {
@@ -324,13 +416,15 @@ void mlp_apply(Handle& H, const double* r, double* z, hipStream_t s)
     if (S.feat_cap < nleaf) {
         S.feat.alloc((size_t)nleaf * kIn);
         S.rn.alloc(nleaf);
+        S.out.alloc((size_t)nleaf * kOut);
+        S.h1b.alloc((size_t)nleaf * kH);
+        S.h2b.alloc((size_t)nleaf * kH);
         S.feat_cap = nleaf;
     }
-    S.work.ensure(nleaf);
     k_features<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, LL.key.p, H.kappa, H.R, H.xyt.p,
                                                H.perm.p, r, nullptr, 0.0, S.feat.p, S.rn.p, nullptr, nullptr);
-    forward(S.w.p, S.feat.p, nleaf, S.work, s);
-    k_correction<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, H.perm.p, S.work.o.p, S.rn.p, S.scale,
+    forward_bf16(S, nleaf, s);
+    k_correction<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, H.perm.p, S.out.p, S.rn.p, S.scale,
                                                  r, z);
     HIPCK(hipGetLastError());
 }
@@ -454,6 +548,7 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
     }
     HIPCK(hipStreamSynchronize(s));
     S.ready = true;
+    S.w16_ok = false;
     auto t2 = std::chrono::steady_clock::now();
     if (info) {
         info->seconds_data = std::chrono::duration<double>(t1 - t0).count();
@@ -477,6 +572,7 @@ void mlp_weights(Handle& H, float* out, const float* in, double* scale, hipStrea
         HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * kParams, s));
         HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
         S.ready = true;
+        S.w16_ok = false;
     }
     if (out) {
         if (!S.w.p) fail(H2D_EINVAL, "no MLP weights");

@@ -117,3 +117,53 @@ def test_chosen_form_refine_fp16_mlp(trained):
     x, info = H.solve(dev(b), tol=1e-8, mode="refine", inner_prec="fp16", inner_tol=1e-4, precond="mlp")
     say("chosen form", info)
     assert info["converged"] and info["relres"] <= 1e-8
+
+
+def _compact(v):
+    out = 0
+    for bit in range(16):
+        out |= ((v >> (2 * bit)) & 1) << bit
+    return out
+
+
+def test_mlp_apply_bf16_matches_oracle(tmp_path):
+    """The preconditioner runs the network in BF16 on the matrix cores
+    (FP32 accumulation): z against the FP64 oracle forward of the same
+    weights on features built here from the exported tree, within BF16
+    rounding of inputs, weights and activations."""
+    from tests import h2dfile
+    xy, b, kern, leaf, tol = inputs.workload("log4096")
+    H = _lib().HODLR2D.build(dev(xy), kern, leaf, tol)
+    rng = np.random.default_rng(5)
+    w = rng.normal(0, 0.05, omlp.NPARAMS).astype(np.float32)
+    scale = 0.7
+    H.mlp_weights(set_to=w, scale=scale)
+    r = rng.uniform(-1, 1, xy.shape[0])
+    z = host(H.precond_apply(dev(r), "mlp"))
+    p = tmp_path / "s.h2dx"
+    H.export(p, factors=False)
+    F = h2dfile.read(p)
+    kap, R, perm, pts = F["kappa"], F["R"], F["perm"], F["xy"]
+    L = F["levels"][kap]
+    h = R / 2 ** kap
+    nleaf = len(L["key"])
+    feats = np.zeros((nleaf, omlp.IN)); rn = np.zeros(nleaf); leaves = []
+    for X in range(nleaf):
+        b0, c = int(L["begin"][X]), int(L["count"][X])
+        idx = perm[b0:b0 + c]
+        key = int(L["key"][X])
+        cx = -R + (2 * _compact(key) + 1) * h
+        cy = -R + (2 * _compact(key >> 1) + 1) * h
+        rn[X] = np.linalg.norm(r[idx])
+        feats[X, :c] = (pts[idx, 0] - cx) / h
+        feats[X, 64:64 + c] = (pts[idx, 1] - cy) / h
+        feats[X, 128:128 + c] = r[idx] / rn[X]
+        leaves.append(idx)
+    O, _ = omlp.forward(w.astype(np.float64), feats)
+    zref = np.empty_like(r); corr = np.empty_like(r)
+    for X, idx in enumerate(leaves):
+        corr[idx] = scale * rn[X] * O[X, :len(idx)]
+        zref[idx] = scale * r[idx] + corr[idx]
+    err = np.linalg.norm(z - zref) / np.linalg.norm(corr)
+    say(f"BF16 MLP apply: relative error of the correction {err:.2e}")
+    assert err <= 2e-2
