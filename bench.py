@@ -307,7 +307,7 @@ def main():
     if not args.no_solve:
         xy2, b2, kern2, leaf2, tol2 = inputs.workload("log1m", n=args.n)
         log("building log-kernel system for time-to-1e-8")
-        H2 = hodlr2d.HODLR2D.build(torch.from_numpy(xy2).cuda(), kern2, leaf2, tol2, precs=("fp16",))
+        H2 = hodlr2d.HODLR2D.build(torch.from_numpy(xy2).cuda(), kern2, leaf2, tol2, precs=("fp16", "bf16"))
         bb = torch.from_numpy(b2).cuda()
         H2.solve(bb, tol=1e-8, restart=50)  # warm-up
         sol = {}
@@ -317,6 +317,16 @@ def main():
         sol["refine_fp16"] = {k: ir[k] for k in ("iters", "outer", "relres", "seconds", "converged")}
         sol["refine_fp16"]["rel_diff_vs_plain"] = float(torch.linalg.norm(xr - xp) / torch.linalg.norm(xp))
         log(f"time-to-1e-8 plain {ip} refine {ir}")
+        # precision form to 1e-10: FP16 / BF16 factors + FP64 refinement, error against the FP64 solve
+        x10, i10 = H2.solve(bb, tol=1e-10, restart=50)
+        sol["plain_fp64_1e-10"] = {k: i10[k] for k in ("iters", "outer", "relres", "seconds", "converged")}
+        for p in ("fp16", "bf16"):
+            xq, iq = H2.solve(bb, tol=1e-10, restart=50, mode="refine", inner_prec=p, inner_tol=1e-4)
+            d = xq - x10
+            sol[f"refine_{p}_1e-10"] = {k: iq[k] for k in ("iters", "outer", "relres", "seconds", "converged")}
+            sol[f"refine_{p}_1e-10"]["rel_err_vs_fp64_solve"] = float(torch.linalg.norm(d) / torch.linalg.norm(x10))
+            sol[f"refine_{p}_1e-10"]["max_rel_err_vs_fp64_solve"] = float(d.abs().max() / x10.abs().max())
+            log(f"refine {p} to 1e-10: {sol[f'refine_{p}_1e-10']}")
         # block-Jacobi fallback and the learned per-leaf preconditioner
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -114,17 +114,16 @@ def batch_workload(count: int = 64, seed: int = 3, lo: float = 1e4, hi: float = 
 
     Returns (instances, kernel_spec, leaf, tol); instance i is a pair
     (points N_i x 2, right-hand sides nrhs x N_i).  N_i is log-uniform in
-    [lo, hi]; even draws of a fair coin give a uniform disc, odd ones the
+    [lo, hi]; even instances are uniform in the unit disc, odd ones the
     4-cluster Gaussian mixture (sigma 0.05).  Kernel: Gaussian RBF with
     shape 0.05 plus 1e-4 on the diagonal.
     """
     rng = np.random.default_rng(seed)
     sizes = batched_sizes(count, rng, lo, hi)
-    coin = rng.integers(0, 2, size=count)
     inst = []
     for i in range(count):
         n = int(sizes[i])
-        xy = uniform_disc(n, rng) if coin[i] == 0 else gaussian_mixture(n, rng)
+        xy = uniform_disc(n, rng) if i % 2 == 0 else gaussian_mixture(n, rng)
         inst.append((xy, rhs(n, rng, nrhs) if nrhs > 1 else rhs(n, rng)))
     kern = {"kind": "gauss", "c": 0.05, "diag_mode": "add", "diag_value": 1e-4}
     return inst, kern, 64, 1e-10
