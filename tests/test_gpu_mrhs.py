@@ -53,3 +53,29 @@ def test_multi_rhs_deep_tree_big_leaves():
     for r in (0, 7, 15):
         y1 = host(H.matvec(dev(X[r])))
         assert np.linalg.norm(Y[r] - y1) <= 1e-13 * np.linalg.norm(y1)
+
+
+@pytest.mark.parametrize("nrhs", [1, 5, 16])
+def test_leading_dimension_through_abi(nrhs):
+    """Column-major X and Y with leading dimension ld > n, through the C ABI
+    directly: the padding between columns is neither read into the result
+    nor written."""
+    import ctypes as C
+    hd = _lib()
+    rng = np.random.default_rng(31)
+    n, ld = 5000, 5013
+    xy = inputs.uniform_square(n, rng)
+    spec = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}
+    H = hd.HODLR2D.build(dev(xy), spec, 64, 1e-10)
+    Xp = rng.uniform(-1, 1, (nrhs, ld))
+    Xp[:, n:] = np.nan   # padding must never be read
+    Xd = dev(Xp)
+    Yp = torch.full((nrhs, ld), 7.0, dtype=torch.float64, device="cuda")
+    st = hd.load().h2d_matvec(H._h, C.c_void_p(Xd.data_ptr()), C.c_void_p(Yp.data_ptr()), nrhs, ld, 0,
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    Y = host(Yp)
+    assert np.all(Y[:, n:] == 7.0)
+    for r in range(nrhs):
+        y1 = host(H.matvec(dev(np.ascontiguousarray(Xp[r, :n]))))
+        assert np.linalg.norm(Y[r, :n] - y1) <= 1e-13 * np.linalg.norm(y1), r
