@@ -155,6 +155,20 @@ def test_error_statuses():
     with pytest.raises(h.H2DError) as e:
         H.matvec(dev(np.ones(3)), prec="fp16")
     assert e.value.code == h.H2D_EUNSUPPORTED
+    # empty input, no right-hand sides, a leading dimension below n
+    import ctypes as C
+    import torch
+    L = h.load()
+    k = h.kernel_spec(MQ)
+    out = C.c_void_p()
+    strm = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.h2d_build(C.c_void_p(dev(xy).data_ptr()), 0, C.byref(k), 8, 1e-10, 0, strm, C.byref(out)) == h.H2D_EINVAL
+    assert L.h2d_build(None, 3, C.byref(k), 8, 1e-10, 0, strm, C.byref(out)) == h.H2D_EINVAL
+    xd = dev(np.ones(3)); yd = dev(np.zeros(3))
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    assert L.h2d_matvec(H._h, ptr(xd), ptr(yd), 0, 3, 0, strm) == h.H2D_EINVAL
+    assert L.h2d_matvec(H._h, ptr(xd), ptr(yd), 1, 2, 0, strm) == h.H2D_EINVAL
+    assert L.h2d_matvec(H._h, None, ptr(yd), 1, 3, 0, strm) == h.H2D_EINVAL
     # 65 coincident points cannot be split by any depth
     with pytest.raises(h.H2DError) as e:
         h.HODLR2D.build(dev(np.zeros((65, 2))), MQ, 64, 1e-10)
