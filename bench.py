@@ -188,7 +188,7 @@ def batched(count, nrhs=16, reps=10):
     for H in hs:
         H.close()
     r = {"instances": count, "total_points": ntot, "nrhs": nrhs, "build_seconds": t_build,
-         "autotune_seconds": t_tune, "chunk_rows_picked": {str(k): picks.count(k) for k in (64, 128, 256)},
+         "autotune_seconds": t_tune, "chunk_rows_picked": {str(k): picks.count(k) for k in (128, 256, 512)},
          "graph_ms": ms, "eager_ms": ms_eager, "alg_bytes": byts, "GB/s": byts / (ms * 1e-3) / 1e9,
          "TFLOP/s": flops / (ms * 1e-3) / 1e12, "rhs_products_per_s": count * nrhs / (ms * 1e-3),
          "graph_equals_eager": bool(same)}

@@ -263,14 +263,14 @@ h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
 /* Work-item sizes of the product kernels (h2d_set_item_rows, h2d_autotune). */
 typedef enum {
     H2D_TILE_A_ROWS = 0,   /* V rows per single-RHS phase-A item: 16..512 (default 512) */
-    H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS phase-A item: 16..256, multiple of 16 (default 256) */
+    H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS phase-A item: 16..512, multiple of 16 (default 256) */
     H2D_TILE_B1_ROWS = 2   /* rows per single-RHS phase-B1 item: 16, 32 or 64 (default 64) */
 } h2d_tile;
 
 /* Tile tuning: times 5 FP64 products with nrhs right-hand sides for each
  * candidate and keeps the fastest for H.  nrhs == 1 tunes H2D_TILE_A_ROWS
  * over (128, 256, 512), then H2D_TILE_B1_ROWS over (16, 32, 64); nrhs > 1
- * tunes H2D_TILE_MR_ROWS over (64, 128, 256).  chosen (host, 2 ints, may be
+ * tunes H2D_TILE_MR_ROWS over (128, 256, 512).  chosen (host, 2 ints, may be
  * NULL) receives the picks (second 0 for nrhs > 1); ms (host, 6 floats, may
  * be NULL) the milliseconds per product of each candidate in that order. */
 h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, float* ms);

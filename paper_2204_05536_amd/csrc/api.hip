@@ -514,7 +514,8 @@ h2d_status h2d_set_item_rows(h2d_t H, int32_t which, int32_t rows, void* stream)
         if (which == H2D_TILE_A_ROWS) {
             if (rows < 16 || rows > kPhaseARows) fail(H2D_EINVAL, "phase-A item rows must lie in 16..512");
         } else if (which == H2D_TILE_MR_ROWS) {
-            if (rows < 16 || rows > 256 || rows % 16) fail(H2D_EINVAL, "chunk rows must be 16..256, multiple of 16");
+            if (rows < 16 || rows > kMrRowsMax || rows % 16)
+                fail(H2D_EINVAL, "chunk rows must be 16..512, multiple of 16");
         } else if (which == H2D_TILE_B1_ROWS) {
             if (rows != 16 && rows != 32 && rows != 64) fail(H2D_EINVAL, "phase-B1 slice rows must be 16, 32 or 64");
         } else {

@@ -105,7 +105,7 @@ void set_item_rows(Handle& H, int which, int32_t rows, hipStream_t s) { set_rows
 
 // Time 5 products per candidate and keep the fastest; one right-hand side
 // tunes phase A (128, 256, 512) then phase B1 (16, 32, 64), several tune the
-// multi-RHS source chunks (64, 128, 256).
+// multi-RHS source chunks (128, 256, 512).
 void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out)
 {
     const bool multi = nrhs > 1;
@@ -124,7 +124,7 @@ void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out
         int32_t cand[3];
     };
     const Knob single[2] = {{0, {128, 256, 512}}, {2, {16, 32, 64}}};
-    const Knob mr[1] = {{1, {64, 128, 256}}};
+    const Knob mr[1] = {{1, {128, 256, 512}}};
     const Knob* knobs = multi ? mr : single;
     const int nk = multi ? 1 : 2;
     for (int kb = 0; kb < nk; ++kb) {

@@ -395,7 +395,7 @@ k_phaseB_mr(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kap
 // per chunk and a reduction.  Items are ordered largest work first.
 static void build_mr_schedule(Handle& H, hipStream_t s)
 {
-    const int32_t R = std::max(16, std::min<int32_t>(H.mr_rows, 256)) & ~15;
+    const int32_t R = std::max(16, std::min<int32_t>(H.mr_rows, kMrRowsMax)) & ~15;
     std::vector<int64_t> idx;
     for (int64_t b = 0; b < H.n_il; ++b)
         if (H.h_il_kind[b] != kDense && H.h_il_k[b] > 0) idx.push_back(b);
@@ -489,7 +489,7 @@ void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t l
     const int32_t* const* Lp = H.lvl_ptrs.p + 2 * (kMaxLevel + 1);
     const int32_t* const* Li = H.lvl_ptrs.p + 3 * (kMaxLevel + 1);
     const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
-    const int32_t R = std::max(16, std::min<int32_t>(H.mr_rows, 256)) & ~15;
+    const int32_t R = std::max(16, std::min<int32_t>(H.mr_rows, kMrRowsMax)) & ~15;
     const unsigned pblocks = (unsigned)((n + kWave - 1) / kWave);
     for (int r0 = 0; r0 < nrhs; r0 += kR) {
         const int32_t nr = std::min(kR, nrhs - r0);

@@ -279,7 +279,7 @@ class HODLR2D:
         ms = (C.c_float * 6)()
         _check(load().h2d_autotune(self._h, int(nrhs), _stream(), chosen, ms))
         if nrhs > 1:
-            return {"mr_rows": chosen[0]}, {("mr_rows", c): ms[i] for i, c in enumerate((64, 128, 256))}
+            return {"mr_rows": chosen[0]}, {("mr_rows", c): ms[i] for i, c in enumerate((128, 256, 512))}
         times = {("a_rows", c): ms[i] for i, c in enumerate((128, 256, 512))}
         times.update({("b1_rows", c): ms[3 + i] for i, c in enumerate((16, 32, 64))})
         return {"a_rows": chosen[0], "b1_rows": chosen[1]}, times
