@@ -116,19 +116,36 @@ __device__ __forceinline__ void srcA_tiles(d4 (&acc)[4], const double* __restric
     for (int t = 0; t < NT; ++t) ao[t] = (uint32_t)(lk * k + min(q0 + 16 * t + li, k - 1)) * 8u;
     const uint32_t sa = (uint32_t)k * 32u;   // 4 rows of V, in bytes
     int32_t j = 0;
-    for (; j + 16 <= rows; j += 16) {
-        const rsrc_t rv = rsrc(Vb + (int64_t)j * k, 16 * (int64_t)k);
-        double a[4][NT], b[4];
+    // software-pipelined: the loads of the next 16 rows are issued before
+    // the matrix instructions of the current 16
+    auto load = [&](int32_t jj, double (&a)[4][NT], double (&b)[4]) {
+        const rsrc_t rv = rsrc(Vb + (int64_t)jj * k, 16 * (int64_t)k);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            b[u] = xl[(j + 4 * u + lk) * kR + li];
+            b[u] = xl[(jj + 4 * u + lk) * kR + li];
 #pragma unroll
             for (int t = 0; t < NT; ++t) a[u][t] = bld(rv, ao[t], u * sa);
         }
+    };
+    auto compute = [&](const double (&a)[4][NT], const double (&b)[4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u][t], b[u], acc[t]);
+    };
+    if (j + 16 <= rows) {
+        double a0[4][NT], b0[4], a1[4][NT], b1[4];
+        load(j, a0, b0);
+        for (; j + 32 <= rows; j += 32) {
+            load(j + 16, a1, b1);
+            compute(a0, b0);
+            if (j + 48 <= rows) load(j + 32, a0, b0);
+            compute(a1, b1);
+        }
+        if (j + 16 <= rows) {   // one loaded group left in a0
+            compute(a0, b0);
+            j += 16;
+        }
     }
     if (j < rows) {   // last group: rows past the end re-read row rows - 1, their X rows are zero
         double a[4][NT], b[4];
