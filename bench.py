@@ -196,6 +196,48 @@ def batched(count, nrhs=16, reps=10):
     return r
 
 
+def paper_shaped(reps=20):
+    """The paper's serial matvec workload at its largest size: a 500 x 500
+    first-kind Chebyshev grid (N = 250 000), K = 1/r with zero diagonal,
+    tolerance 1e-12, leaf size 500.  The paper reports 1.9681 s per matvec
+    on one core of a Xeon Gold 6248 (13.52 GB of storage) and 0.051 s on 80
+    MPI processes; quoted here as context only."""
+    import numpy as np
+    import torch
+
+    from paper_2204_05536_amd import hodlr2d, inputs
+
+    xy = inputs.chebyshev_grid(500)
+    x = torch.from_numpy(np.random.default_rng(11).uniform(-1, 1, xy.shape[0])).cuda()
+    spec = {"kind": "invr", "diag_mode": "replace", "diag_value": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = hodlr2d.HODLR2D.build(torch.from_numpy(xy).cuda(), spec, 500, 1e-12)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    info = H.info()
+    y = torch.empty_like(x)
+    for _ in range(3):
+        H.matvec(x, out=y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        H.matvec(x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    H.close()
+    r = {"n": int(xy.shape[0]), "kappa": info["kappa"], "max_rank": info["max_rank"], "build_seconds": t_build,
+         "ms_per_matvec": ms, "GB/s": info["alg_bytes_fp64"] / (ms * 1e-3) / 1e9,
+         "factor_GB": 8.0 * (info["u_elems"] + info["v_elems"] + info["d_elems"]) / 1e9,
+         "paper_serial_s": 1.9681, "paper_80proc_s": 0.051, "paper_storage_GB": 13.52}
+    log(f"paper-shaped N=250000 1/r Chebyshev: build {t_build:.1f} s, matvec {ms:.3f} ms, {r['GB/s']:.0f} GB/s, "
+        f"max rank {info['max_rank']}")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +249,7 @@ def main():
     ap.add_argument("--no-half", action="store_true")
     ap.add_argument("--no-mrhs", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's own N=250k 1/r Chebyshev workload")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (a known-size kernel for counter calibration)")
@@ -349,6 +392,8 @@ def main():
         H2.close()
         del H2
         torch.cuda.synchronize()
+    if not args.no_paper:
+        extra["paper_shaped"] = paper_shaped()
     if not args.no_batch:
         torch.cuda.empty_cache()
         extra["batched"] = batched(args.batch_count)

@@ -182,6 +182,8 @@ struct Handle {
     DBuf<int2> b1s_items;       // single-RHS phase-B1 work: (box, first row of a b1_rows-row slice)
     int64_t n_b1s = 0;
     int32_t b1_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
+    DBuf<int2> b2items;         // single-RHS phase-B2 work: (leaf box, first row of a 64-row chunk)
+    int64_t n_b2 = 0;
 
     // multi-RHS work (blocks of 16 right-hand sides, point-major)
     DBuf<double> xs_mr, tp_mr, pp_mr, yp_mr, yl_mr;

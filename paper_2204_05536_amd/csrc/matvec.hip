@@ -227,14 +227,15 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
     }
 }
 
-// Phase B2: the leaf level.  One wave per leaf box X: its dense near blocks
-// and its own interaction-list blocks, plus the ancestors' sum from B1;
-// writes y once, in caller order.  A leaf box has at most 64 rows per pass;
+// Phase B2: the leaf level.  One wave per 64-row chunk of a leaf box X
+// (leaves above 64 points give several items): its dense near blocks and
+// its own interaction-list blocks, into the leaf-level sum.  A chunk has at
+// most 64 rows;
 // lane (g, r) takes row r and the columns g, g + G, ... (G = 64 / rows), so
 // a load covers G consecutive columns of the column-major block.
 template <typename T, typename A, bool kHalf>
 __device__ __forceinline__ void
-b2_item(int32_t X, int wave, int lane, A (*red)[kWave], int kappa, const LevelPtrs& L,
+b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], int kappa, const LevelPtrs& L,
         const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
         const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
         A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
@@ -242,7 +243,7 @@ b2_item(int32_t X, int wave, int lane, A (*red)[kWave], int kappa, const LevelPt
     const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
     const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
     const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
-    for (int32_t rc = 0; rc < cnt; rc += kWave) {
+    {
         const int32_t rows = min(kWave, cnt - rc);
         const int G = kWave / rows, g = lane / rows, r = lane % rows;
         const bool act = g < G;
@@ -318,7 +319,8 @@ __global__ void __launch_bounds__(256)
 k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa, LevelPtrs L,
          const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
          const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
-         A* __restrict__ ypart, A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il, int32_t nleaf)
+         A* __restrict__ ypart, A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il,
+         const int2* __restrict__ b2items, int32_t nb2items)
 {
     __shared__ A red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -328,9 +330,12 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
         if (it < nitems) b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart,
                                                  scale);
     } else {
-        const int32_t X = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
-        if (X < nleaf) b2_item<T, A, kHalf>(X, wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs, yleaf,
-                                            scale, n_il);
+        const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
+        if (it < nb2items) {
+            const int2 c = b2items[it];
+            b2_item<T, A, kHalf>(uni(c.x), uni(c.y), wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs,
+                                 yleaf, scale, n_il);
+        }
     }
 }
 
@@ -437,6 +442,12 @@ void finalize(Handle& H, hipStream_t s)
             for (int32_t rc = 0; rc < T.h_count[p]; rc += S) b1s.push_back(make_int2((int32_t)p, rc));
         }
     }
+    // phase-B2 work: 64-row chunks of the leaf boxes
+    std::vector<int2> b2;
+    for (int64_t x = 0; x < LL.nbox; ++x)
+        for (int32_t rc = 0; rc < LL.h_count[x]; rc += kWave) b2.push_back(make_int2((int32_t)x, rc));
+    H.n_b2 = (int64_t)b2.size();
+    upload_vec(H.b2items, b2, s);
     H.n_b1 = (int64_t)b1.size();
     H.n_b1s = (int64_t)b1s.size();
     upload_vec(H.b1items, b1, s);
@@ -533,14 +544,13 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
     if (ev) HIPCK(hipEventRecord(ev[3], s));
     const LevelPtrs LP = level_ptrs(H);
-    const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
-    const int32_t nb1 = (int32_t)((H.n_b1s + 3) / 4), nb2 = (nleaf + 3) / 4;
+    const int32_t nb1 = (int32_t)((H.n_b1s + 3) / 4), nb2 = (int32_t)((H.n_b2 + 3) / 4);
     const int32_t ni = (int32_t)H.n_b1s;
     A* yl = yp + n;   // the work vector holds ypart then yleaf
 #define H2D_PHASE_B(SR)                                                                                              \
     k_phaseB<T, A, kHalf, SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, \
                                                                    H.bnear.p, H.bil.p, U, D, tp, xs, yp, yl,         \
-                                                                   H.scale16.p, H.n_il, nleaf)
+                                                                   H.scale16.p, H.n_il, H.b2items.p, (int32_t)H.n_b2)
     if (H.b1_rows == 16) H2D_PHASE_B(16);
     else if (H.b1_rows == 32) H2D_PHASE_B(32);
     else H2D_PHASE_B(64);

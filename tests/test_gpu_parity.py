@@ -34,6 +34,8 @@ def _cases():
     c.append(("one_point", np.array([[0.3, -0.2]]), MQ, 64, 1e-10))
     c.append(("single_leaf_64", rng.uniform(-1, 1, (64, 2)), MQ, 64, 1e-10))
     c.append(("ragged_1337_leaf7", rng.uniform(-1, 1, (1337, 2)), MQ, 7, 1e-10))
+    # leaves above 64 points: several 64-row chunks per leaf box
+    c.append(("unif4000_leaf200", rng.uniform(-1, 1, (4000, 2)), MQ, 200, 1e-10))
     # points on cell boundaries, on the top / right edge of B, and at 0
     g = np.array([[-1.0, -1.0], [1.0, 1.0], [0.0, 0.0], [0.5, -0.5], [-0.5, 0.5], [1.0, -1.0], [-1.0, 1.0],
                   [0.25, 0.75], [0.0, 1.0], [1.0, 0.0]])
