@@ -44,6 +44,13 @@ template <> __device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfl
 template <typename T, typename A> __device__ __forceinline__ A ld(const T* p) { return (A)ldf<T>(p); }
 template <> __device__ __forceinline__ double ld<double, double>(const double* p) { return __builtin_nontemporal_load(p); }
 
+// The t and x values of a block are the same for every lane of a phase-B1
+// wave (all lanes walk the same columns): read through the constant address
+// space they become scalar-cache loads (8 values per instruction), so the
+// vector memory pipe carries only the factors.  They are written by earlier
+// kernels only.
+template <typename A> using ConstAS = const __attribute__((address_space(4))) A;
+
 // Phase B reads FP64 factors with ordinary loads (measured slightly faster
 // there than nontemporal ones); half factors keep the nontemporal path.
 template <typename T, typename A>
@@ -175,6 +182,7 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
         const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
         const A* __restrict__ tpool, const A* __restrict__ xs, A* __restrict__ ypart, const float* __restrict__ scale)
 {
+    using cA = ConstAS<A>;
     const int2 w = items[it];
     const int32_t P = uni(w.x), rc = uni(w.y);
     const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
@@ -194,14 +202,14 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
                 // U is tiled by level-(kappa - 1) boxes: this box's tile is
                 // a contiguous cnt x k column-major matrix
                 const T* base = Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + r;
-                const A* tv = tpool + d.tsrc;
+                const cA* tv = (const cA*)(tpool + d.tsrc);
                 if (act) {
 #pragma unroll 8
                     for (int32_t c = g; c < d.cols; c += G) acc += ldv<T, A>(base + (int64_t)c * cnt) * tv[c];
                 }
             } else if (d.cols < 0) {
                 const T* base = Dp + d.off + off;
-                const A* tv = xs + d.tsrc;
+                const cA* tv = (const cA*)(xs + d.tsrc);
                 A a = (A)0;
                 if (act) {
 #pragma unroll 8
