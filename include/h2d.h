@@ -137,6 +137,11 @@ typedef struct {
     int32_t outer;         /* refinement steps (REFINE) or restarts (PLAIN) */
     double relres;         /* true relative residual |b - A_hat x| / |b| in FP64 at exit */
     double seconds;        /* wall time of the call */
+    int32_t fallback_at;   /* H2D_PC_MLP only: total Arnoldi step at which the learned
+                              preconditioner was found stagnating (the estimated residual fell
+                              by less than 10% over 10 steps) and the solve went on with
+                              block-Jacobi (or none if not set up); -1 if it never did */
+    int32_t pad;
 } h2d_solve_info;
 
 /* Solve A_hat x = b to relative residual rtol (GMRES as used in Section 5,

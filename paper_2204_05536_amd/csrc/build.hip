@@ -617,9 +617,43 @@ k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double
     const double* P = xyt;
     for (int32_t e = t; e < m + n; e += kAcaThreads) usedR[e] = 0;
     __syncthreads();
+    __shared__ int32_t first_nz;
     int32_t k = 0, i = 0, nusedR = 0, kind = kLowRank;
     double S2 = 0.0;
     if (m == 0 || n == 0) { if (t == 0) { kind_out[blockIdx.x] = kLowRank; rank_out[blockIdx.x] = 0; } return; }
+    {
+        // Before the first cross the residual row is the kernel row itself,
+        // and every zero row would be tried, marked used and passed over in
+        // index order.  Find the first row with a nonzero entry with the whole
+        // workgroup, chunks of rows at a time, and mark the rows before it
+        // used: the same pivot and the same used set, without one pass and
+        // two reductions per zero row (blocks of a fast-decaying kernel can
+        // be exactly zero).
+        const int32_t per = max(1, min(64, 16384 / n));
+        int32_t found = -1;
+        for (int32_t r0 = 0; r0 < m && found < 0; r0 += per) {
+            const int32_t nr = min(per, m - r0);
+            if (t == 0) first_nz = INT32_MAX;
+            __syncthreads();
+            for (int64_t e = t; e < (int64_t)nr * n; e += kAcaThreads) {
+                const int32_t ii = r0 + (int32_t)(e / n), j = (int32_t)(e % n);
+                const double v = kernel_entry(kp, P[2 * (J.row0 + ii)], P[2 * (J.row0 + ii) + 1], P[2 * (J.col0 + j)],
+                                              P[2 * (J.col0 + j) + 1], J.row0 + ii == J.col0 + j);
+                if (v != 0.0) atomicMin(&first_nz, ii);
+            }
+            __syncthreads();
+            if (first_nz != INT32_MAX) found = first_nz;
+            __syncthreads();
+        }
+        const int32_t stop = found >= 0 ? found : m;
+        for (int32_t ii = t; ii < stop; ii += kAcaThreads) usedR[ii] = 1;
+        __syncthreads();
+        if (found < 0) {   // the block is exactly zero: rank 0
+            if (t == 0) { kind_out[blockIdx.x] = kLowRank; rank_out[blockIdx.x] = 0; }
+            return;
+        }
+        i = found;
+    }
     for (;;) {
         // U(i, 0..k)
         for (int q = t; q < k; q += kAcaThreads) row[q] = U[(int64_t)q * m + i];

@@ -474,14 +474,29 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
     so.precond = H2D_PC_NONE;
     int solves_ok = 0;
     if (o.target == H2D_MLP_TARGET_LEAF && !H.bj_ready) bj_setup(H, s);
-    DBuf<double> R, Z;
+    DBuf<double> R, Z, W;
     R.alloc((size_t)n * ns);
     Z.alloc((size_t)n * ns);
+    W.alloc((size_t)n);
     double zr = 0.0, rr = 0.0;
+    std::vector<double> hw(n);
     for (int q = 0; q < ns; ++q) {
         double* rq = R.p + (int64_t)q * n;
         double* zq = Z.p + (int64_t)q * n;
         k_random<<<grid_for(n), 256, 0, s>>>(n, o.seed + 7919ull * (uint64_t)q, rq);
+        // Residuals met inside a Krylov solve are not white noise: sample q
+        // is A^p r for p = q mod 4 (random r, rescaled to unit RMS after each
+        // product), so the pairs cover the smoother vectors as well.
+        for (int p = 0; p < q % 4; ++p) {
+            launch_matvec(H, rq, W.p, 1, n, H2D_P_FP64, s);
+            HIPCK(hipMemcpyAsync(hw.data(), W.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            double nn = 0.0;
+            for (int64_t i = 0; i < n; ++i) nn += hw[i] * hw[i];
+            const double f = nn > 0.0 ? std::sqrt((double)n / nn) : 1.0;
+            for (int64_t i = 0; i < n; ++i) hw[i] *= f;
+            HIPCK(hipMemcpyAsync(rq, hw.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+        }
         if (o.target == H2D_MLP_TARGET_GLOBAL) {
             h2d_solve_info si{};
             h2d_status st = solve(H, rq, zq, o.solve_tol, so, &si, s);

@@ -134,14 +134,23 @@ struct GmresResult {
     int restarts = 0;
     double relres = 1.0;   // true residual of the operator used, relative to |rhs|
     bool converged = false;
+    int fallback_at = -1;  // Arnoldi step at which the learned preconditioner was dropped
 };
+
+// The learned preconditioner is not a fixed linear map and can be a poor
+// one: when the Arnoldi residual estimate falls by less than 10% over 10
+// steps with it, the cycle is closed and the solve goes on with the exact
+// block-Jacobi fallback (or without a preconditioner if that was not set
+// up).
+constexpr int kStallSteps = 10;
+constexpr double kStallRatio = 0.9;
 
 // GMRES(restart) for A_prec x = rhs, x0 = 0, optionally right-
 // preconditioned in the flexible form (z_j = M v_j kept, x += Z y).
 // Convergence is judged by the true residual |rhs - A_prec x| / |rhs| <= tol
 // at each restart.
 static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, double tol, int restart, int max_iter,
-                         int precond, hipStream_t s)
+                         int& precond, hipStream_t s)
 {
     const int64_t n = H.n;
     const int m = restart;
@@ -174,7 +183,9 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
         k_scale<<<grid, 256, 0, s>>>(Vb.p, r.p, 1.0 / beta, n);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        int j = 0;
+        int j = 0, j_mark = 0;
+        double g_mark = beta;
+        bool stalled = false;
         for (; j < m && R.iters < max_iter; ) {
             ++R.iters;
             double* vj1 = Vb.p + (int64_t)(j + 1) * n;
@@ -212,6 +223,11 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
             g[j] = cs[j] * g[j];
             ++j;
             if (std::fabs(g[j]) / bn <= tol || hn == 0.0) break;
+            if (precond == H2D_PC_MLP && j - j_mark >= kStallSteps) {
+                if (std::fabs(g[j]) > kStallRatio * g_mark) { stalled = true; break; }
+                g_mark = std::fabs(g[j]);
+                j_mark = j;
+            }
         }
         for (int i = j - 1; i >= 0; --i) {
             double sum = g[i];
@@ -222,6 +238,10 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
         k_add_comb<<<grid, 256, 0, s>>>(x, precond != H2D_PC_NONE ? Zb.p : Vb.p, n, j, yv.p, n);
         HIPCK(hipGetLastError());
         ++R.restarts;
+        if (stalled) {
+            precond = H.bj_ready ? H2D_PC_BLOCK_JACOBI : H2D_PC_NONE;
+            if (R.fallback_at < 0) R.fallback_at = R.iters;
+        }
     }
     HIPCK(hipStreamSynchronize(s));
     return R;
@@ -236,9 +256,12 @@ h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_s
     bool ok = false;
     if (o.precond == H2D_PC_BLOCK_JACOBI && !H.bj_ready) fail(H2D_EINVAL, "block-Jacobi was not set up (h2d_bj_setup)");
     if (o.precond < H2D_PC_NONE || o.precond > H2D_PC_MLP) fail(H2D_EINVAL, "unknown preconditioner");
+    I.fallback_at = -1;
+    int pc = o.precond;   // the learned preconditioner may hand over to block-Jacobi
     if (o.mode == H2D_SOLVE_PLAIN) {
-        GmresResult R = gmres(H, H2D_P_FP64, b, x, rtol, o.restart, o.max_iter, o.precond, s);
+        GmresResult R = gmres(H, H2D_P_FP64, b, x, rtol, o.restart, o.max_iter, pc, s);
         I.iters = R.iters; I.outer = R.restarts; I.relres = R.relres;
+        I.fallback_at = R.fallback_at;
         ok = R.converged;
     } else if (o.mode == H2D_SOLVE_REFINE) {
         if (o.inner_prec != H2D_P_FP16 && o.inner_prec != H2D_P_BF16) fail(H2D_EINVAL, "inner_prec must be FP16 or BF16");
@@ -255,7 +278,8 @@ h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_s
         int outer = 0, iters = 0;
         const int max_outer = o.max_outer > 0 ? o.max_outer : 50;
         while (rel > rtol && outer < max_outer && iters < o.max_iter) {
-            GmresResult R = gmres(H, o.inner_prec, r.p, d.p, o.inner_tol, o.restart, o.max_iter - iters, o.precond, s);
+            GmresResult R = gmres(H, o.inner_prec, r.p, d.p, o.inner_tol, o.restart, o.max_iter - iters, pc, s);
+            if (R.fallback_at >= 0 && I.fallback_at < 0) I.fallback_at = iters + R.fallback_at;
             iters += R.iters;
             ++outer;
             k_axpy<<<grid, 256, 0, s>>>(x, d.p, 1.0, n);

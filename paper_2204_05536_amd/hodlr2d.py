@@ -49,7 +49,8 @@ class h2d_solve_opts(C.Structure):
 
 
 class h2d_solve_info(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("relres", C.c_double), ("seconds", C.c_double)]
+    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("relres", C.c_double), ("seconds", C.c_double),
+                ("fallback_at", C.c_int32), ("pad", C.c_int32)]
 
 
 class h2d_stats(C.Structure):
@@ -239,7 +240,7 @@ class HODLR2D:
         if st not in (H2D_OK, H2D_ENOCONV):
             _check(st)
         return x, {"iters": info.iters, "outer": info.outer, "relres": info.relres, "seconds": info.seconds,
-                   "converged": st == H2D_OK}
+                   "converged": st == H2D_OK, "fallback_at": info.fallback_at}
 
     def profile_enable(self, on=True):
         _check(load().h2d_profile_enable(self._h, 1 if on else 0))

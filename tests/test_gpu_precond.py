@@ -167,3 +167,30 @@ def test_mlp_apply_bf16_matches_oracle(tmp_path):
     err = np.linalg.norm(z - zref) / np.linalg.norm(corr)
     say(f"BF16 MLP apply: relative error of the correction {err:.2e}")
     assert err <= 2e-2
+
+
+def test_mlp_stagnation_falls_back_to_block_jacobi():
+    """On a local Gaussian system (c = 0.02 + 0.3 I, N = 2^16) block-Jacobi
+    cuts the GMRES iterations; the network trained on leaf solves does not
+    learn the leaf inverse well enough and FGMRES with it alone stagnates.
+    The solve detects the stagnation, goes on with block-Jacobi, and still
+    reaches 1e-8 in the true FP64 residual in about the iterations of the
+    unpreconditioned solve."""
+    n = 1 << 16
+    rng = np.random.default_rng(3)
+    xy = inputs.uniform_square(n, rng)
+    b = inputs.rhs(n, rng)
+    spec = {"kind": "gauss", "c": 0.02, "diag_mode": "add", "diag_value": 0.3}
+    H = _lib().HODLR2D.build(dev(xy), spec, 64, 1e-10)
+    H.bj_setup()
+    bb = dev(b)
+    _, i0 = H.solve(bb, tol=1e-8, restart=50, max_iter=600)
+    _, ib = H.solve(bb, tol=1e-8, restart=50, max_iter=600, precond="bj")
+    H.mlp_train(n_solves=32, steps=1500, batch=4096, lr=5e-4, seed=7)
+    x, im = H.solve(bb, tol=1e-8, restart=50, max_iter=600, precond="mlp")
+    say("plain", i0, "bj", ib, "mlp with fallback", im)
+    assert i0["converged"] and ib["converged"] and ib["iters"] < i0["iters"]
+    assert im["converged"] and im["relres"] <= 1e-8
+    r = host(bb - H.matvec(x))
+    assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
+    assert im["iters"] <= i0["iters"] + 2 * 10
