@@ -238,6 +238,41 @@ def paper_shaped(reps=20):
     return r
 
 
+def precond_local_gauss(n=1 << 16):
+    """Where a leaf preconditioner matters: Gaussian RBF c = 0.02 + 0.3 I on
+    N = 2^16 uniform points (leaf boxes comparable to c).  Plain GMRES,
+    block-Jacobi FGMRES, FGMRES with the trained MLP (which hands over to
+    block-Jacobi when it stagnates), and the chosen form with FP16
+    refinement; every solve judged by the true FP64 residual."""
+    import numpy as np
+    import torch
+
+    from paper_2204_05536_amd import hodlr2d, inputs
+
+    rng = np.random.default_rng(3)
+    xy = inputs.uniform_square(n, rng)
+    b = torch.from_numpy(inputs.rhs(n, rng)).cuda()
+    spec = {"kind": "gauss", "c": 0.02, "diag_mode": "add", "diag_value": 0.3}
+    H = hodlr2d.HODLR2D.build(torch.from_numpy(xy).cuda(), spec, 64, 1e-10, precs=("fp16",))
+    H.bj_setup()
+    keys = ("iters", "outer", "relres", "seconds", "converged", "fallback_at")
+    r = {"n": n, "kernel": "gauss c=0.02 + 0.3 I"}
+    for name, kw in (("plain_fp64", {}), ("fgmres_bj", {"precond": "bj"})):
+        _, info = H.solve(b, tol=1e-8, restart=50, max_iter=600, **kw)
+        r[name] = {k: info[k] for k in keys}
+    t = H.mlp_train(n_solves=32, steps=1500, batch=4096, lr=5e-4, seed=7)
+    r["mlp_training"] = {k: t[k] for k in ("seconds_train", "loss_first", "loss_last")}
+    _, info = H.solve(b, tol=1e-8, restart=50, max_iter=600, precond="mlp")
+    r["fgmres_mlp"] = {k: info[k] for k in keys}
+    _, info = H.solve(b, tol=1e-8, restart=50, max_iter=600, mode="refine", inner_prec="fp16", inner_tol=1e-4,
+                      precond="mlp")
+    r["chosen_refine_fp16_mlp"] = {k: info[k] for k in keys}
+    H.close()
+    log(f"local Gaussian N={n}: " + ", ".join(f"{k} {v['iters']} its" for k, v in r.items()
+                                               if isinstance(v, dict) and "iters" in v))
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +427,7 @@ def main():
         H2.close()
         del H2
         torch.cuda.synchronize()
+        extra["precond_local_gauss"] = precond_local_gauss()
     if not args.no_paper:
         extra["paper_shaped"] = paper_shaped()
     if not args.no_batch:
