@@ -284,6 +284,11 @@ h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, fl
  * handles (nrhs right-hand sides each, x_i / y_i device column-major with
  * leading dimension ld[i]) are captured once into a HIP graph and replayed
  * by h2d_batch_launch with a single graph launch on the caller's stream.
+ * With nrhs > 1 each block of 16 right-hand sides is one launch per phase
+ * (gather, V^T X, reduction, U T and near field, scatter) covering every
+ * instance; a handle listed more than once is served by further such
+ * rounds.  With nrhs == 1 the instances' products run on parallel graph
+ * branches.
  * The buffers are bound at creation (hosts arrays x, y, ld of length
  * count); the handles must outlive the batch, must not be used
  * concurrently with a launch, and must not be re-tuned (h2d_autotune,

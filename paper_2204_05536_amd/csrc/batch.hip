@@ -2,11 +2,20 @@
 //
 // A batch is a set of built handles whose products (each with its own
 // right-hand sides) are captured once into a HIP graph and replayed with
-// one launch.  The tuner picks, per handle, the number of V rows per
-// phase-A work item by timing the candidates on the device.
+// one launch.  With several right-hand sides the graph holds, per block of
+// 16, one gather, phase-A, reduction, phase-B and scatter launch for all
+// instances together (table-driven kernels over a work list of (instance,
+// item) pairs, phase-A items of every instance ordered largest first), so
+// small instances do not leave the machine idle; a handle listed twice
+// goes to a second such round, since its work space is shared.  With one
+// right-hand side the instances' own products are dealt to parallel graph
+// branches.  The tuner picks, per handle, the work-item sizes by timing
+// the candidates on the device.
 #include "h2d_impl.h"
 
 #include <algorithm>
+#include <map>
+#include <memory>
 #include <vector>
 
 namespace h2d {
@@ -18,6 +27,7 @@ struct Batch {
     hipStream_t cap = nullptr;             // capture origin (default priority, like the branches)
     hipStream_t br[kBranches] = {};
     hipEvent_t fork = nullptr, join[kBranches] = {};
+    std::vector<std::unique_ptr<MRBatchPlan>> plans;   // multi-RHS: one per round
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~Batch()
@@ -50,6 +60,66 @@ Batch* batch_create(Handle** hs, int count, int nrhs, double* const* x, double* 
             launch_matvec(*hs[i], x[i], y[i], nrhs, ld[i], H2D_P_FP64, B->cap);
         }
         HIPCK(hipStreamSynchronize(B->cap));
+        if (nrhs > 1) {
+            // rounds: a handle listed k times appears in k rounds; handles
+            // are dealt, largest first, to kBranches groups of similar total
+            // size, each group of a round one table-driven plan on its
+            // group's graph branch
+            std::map<const Handle*, int> seen;
+            std::vector<std::vector<int>> rounds;
+            for (int i = 0; i < count; ++i) {
+                const int r = seen[hs[i]]++;
+                if ((int)rounds.size() <= r) rounds.emplace_back();
+                rounds[r].push_back(i);
+            }
+            // every occurrence of a handle goes to the branch of its first
+            // one (its work space is shared; a branch runs in order)
+            std::map<const Handle*, int> branch_of;
+            {
+                std::vector<int> order(count);
+                for (int i = 0; i < count; ++i) order[i] = i;
+                std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hs[a]->n > hs[b]->n; });
+                int64_t load[kBranches] = {};
+                for (int i : order) {
+                    if (branch_of.count(hs[i])) continue;
+                    const int g = (int)(std::min_element(load, load + kBranches) - load);
+                    branch_of[hs[i]] = g;
+                    load[g] += hs[i]->n;
+                }
+            }
+            std::vector<int> plan_branch;
+            for (const auto& members : rounds) {
+                std::vector<std::vector<int>> groups(kBranches);
+                for (int i : members) groups[branch_of[hs[i]]].push_back(i);
+                for (int g = 0; g < kBranches; ++g) {
+                    if (groups[g].empty()) continue;
+                    std::vector<Handle*> h;
+                    std::vector<MRIo> io;
+                    for (int i : groups[g]) {
+                        h.push_back(hs[i]);
+                        io.push_back(MRIo{(uint64_t)(uintptr_t)x[i], (uint64_t)(uintptr_t)y[i], ld[i]});
+                    }
+                    B->plans.push_back(std::make_unique<MRBatchPlan>());
+                    mr_plan(*B->plans.back(), h.data(), io.data(), (int)h.size(), B->cap);
+                    plan_branch.push_back(g);
+                }
+            }
+            // a later round of a group follows the earlier one on the same
+            // branch (stream order)
+            HIPCK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+            HIPCK(hipEventRecord(B->fork, B->cap));
+            for (int b = 0; b < kBranches; ++b) HIPCK(hipStreamWaitEvent(B->br[b], B->fork, 0));
+            for (size_t p = 0; p < B->plans.size(); ++p)
+                for (int r0 = 0; r0 < nrhs; r0 += 16)
+                    mr_plan_launch(*B->plans[p], r0, std::min(16, nrhs - r0), B->br[plan_branch[p]]);
+            for (int b = 0; b < kBranches; ++b) {
+                HIPCK(hipEventRecord(B->join[b], B->br[b]));
+                HIPCK(hipStreamWaitEvent(B->cap, B->join[b], 0));
+            }
+            HIPCK(hipStreamEndCapture(B->cap, &B->graph));
+            HIPCK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+            return B;
+        }
         // A handle's work space is shared by its products, so every product
         // of one handle goes to the same branch; instances are dealt to the
         // branches by size so that the branches carry similar work.

@@ -126,6 +126,25 @@ struct MRBlk {
     int32_t k, out;
 };
 
+// Static data of one instance for the table-driven multi-RHS kernels (a
+// single product uses a table of one; a batch, one entry per instance).
+// Device addresses are stored as integers: the kernels turn them back into
+// global-memory pointers (a pointer read from memory would be a generic one
+// to the compiler, with flat loads and per-lane address arithmetic).
+struct MRInst {
+    uint64_t U, V, D;                 // const double*
+    uint64_t xs, tp, pp, yp, yl;      // double*
+    uint64_t items, blks, ritems, b1items, bil, bnear;
+    uint64_t near_ptr, iperm;         // const int32_t*
+    uint64_t lvl;                     // const int32_t* const*: begin, count, parent, il_ptr (kMaxLevel + 1 each)
+    int32_t n, kappa, has_b1, pad;
+};
+// Right-hand sides of one instance: x and y column-major, leading dimension ld.
+struct MRIo {
+    uint64_t x, y;
+    int64_t ld;
+};
+
 struct KernelParams {
     int32_t kind;
     int32_t diag_mode;
@@ -194,6 +213,8 @@ struct Handle {
     DBuf<RDesc> mr_ritems;           // their split-block reductions
     DBuf<int32_t> iperm;             // caller index -> tree position
     int64_t n_mr_items = 0, n_mr_ritems = 0, mr_p_elems = 0;
+    std::vector<int64_t> h_mr_work;  // work of each multi-RHS phase-A item, in schedule order
+    DBuf<MRInst> mr_inst;            // this handle's entry for the table-driven kernels
     int32_t mr_rows = 256;           // source rows per multi-RHS phase-A item (tuned by h2d_autotune)
     int32_t a_rows = kPhaseARows;    // rows per phase-A work item (tuned by h2d_autotune)
 
@@ -223,6 +244,22 @@ struct Handle {
 void finalize(Handle& H, hipStream_t s);
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s);
 void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s);
+// Multi-RHS state of H (schedule, work space, instance entry), built once.
+void ensure_mr(Handle& H, hipStream_t s);
+MRInst mr_inst_of(const Handle& H);
+// Table-driven multi-RHS product of several instances at once (each
+// instance at most once): the gather, phase A, reduction, phase B and
+// scatter of every instance run as one launch each.
+struct MRBatchPlan {
+    DBuf<MRInst> insts;
+    DBuf<MRIo> io;
+    DBuf<int2> wg, wa, wr, wb1, wb2;   // work lists: (instance, item)
+    int32_t ng = 0, nr = 0, nb1 = 0, nb2 = 0;
+    std::vector<int32_t> a_rows, a_beg, a_cnt;   // phase A: one launch per source-chunk size (LDS need)
+    int32_t red_y = 1;
+};
+void mr_plan(MRBatchPlan& P, Handle* const* hs, const MRIo* io, int count, hipStream_t s);
+void mr_plan_launch(const MRBatchPlan& P, int32_t r0, int32_t nr, hipStream_t s);
 void ensure_workspace(Handle& H, int nrhs);
 void profile_enable(Handle& H, bool on);
 void profile_read(Handle& H, h2d_profile* out);

@@ -32,19 +32,41 @@ __device__ __forceinline__ int64_t uni_l(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// xs[iperm[c] * 16 + r] = x[r * ldx + c] for r < nr, 0 beyond.  64
-// caller-order points per workgroup: the right-hand-side rows are read
-// coalesced, transposed through LDS, and each point's 16 values are written
-// as one 128-byte segment at its tree position.
+// A device address from an instance table as a global-memory pointer.
+template <typename T> __device__ __forceinline__ T* gp(uint64_t a)
+{
+    return (T*)(__attribute__((address_space(1))) T*)a;
+}
+
+// Work item i of a table-driven kernel: (instance, item); without a list,
+// instance 0 and item i.
+__device__ __forceinline__ int2 work_at(const int2* __restrict__ work, int32_t i)
+{
+    const int2 w = work ? work[i] : make_int2(0, i);
+    // wave-uniform: the instance's fields then load through the scalar cache
+    return make_int2(__builtin_amdgcn_readfirstlane(w.x), __builtin_amdgcn_readfirstlane(w.y));
+}
+
+// xs[iperm[c] * 16 + r] = x[(r0 + r) * ld + c] for r < nr, 0 beyond.  One
+// workgroup per 64 caller-order points of an instance: the right-hand-side
+// rows are read coalesced, transposed through LDS, and each point's 16
+// values are written as one 128-byte segment at its tree position.
 __global__ void __launch_bounds__(256)
-k_gather_mr(const double* __restrict__ x, int64_t ldx, int32_t nr, const int32_t* __restrict__ iperm, int32_t n,
-            double* __restrict__ xs)
+k_gather_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork, MRIo io0,
+            const MRIo* __restrict__ iot, int32_t r0, int32_t nr)
 {
     __shared__ double tile[kR][kWave + 1];
-    const int32_t c0 = blockIdx.x * kWave;
+    if ((int32_t)blockIdx.x >= nwork) return;
+    const int2 wk = work_at(work, blockIdx.x);
+    const MRInst& I = insts[wk.x];
+    const MRIo io = iot ? iot[wk.x] : io0;
+    const int32_t n = I.n, c0 = wk.y * kWave;
+    const double* x = gp<const double>(io.x) + (int64_t)r0 * io.ld;
+    double* xs = gp<double>(I.xs);
+    const int32_t* iperm = gp<const int32_t>(I.iperm);
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
         const int r = e / kWave, c = e % kWave;
-        tile[r][c] = (r < nr && c0 + c < n) ? x[(int64_t)r * ldx + c0 + c] : 0.0;
+        tile[r][c] = (r < nr && c0 + c < n) ? x[(int64_t)r * io.ld + c0 + c] : 0.0;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
@@ -53,15 +75,22 @@ k_gather_mr(const double* __restrict__ x, int64_t ldx, int32_t nr, const int32_t
     }
 }
 
-// y[r * ldy + c] = (yt + ya)[iperm[c] * 16 + r] for r < nr (ya may be
-// NULL): the inverse of the gather, from the tree-ordered point-major leaf
-// and ancestor sums back to caller order.
+// y[(r0 + r) * ld + c] = (yleaf + yanc)[iperm[c] * 16 + r] for r < nr: the
+// inverse of the gather, from the tree-ordered point-major leaf and
+// ancestor sums back to caller order.
 __global__ void __launch_bounds__(256)
-k_scatter_mr(const double* __restrict__ yt, const double* __restrict__ ya, const int32_t* __restrict__ iperm, int32_t n,
-             int32_t nr, double* __restrict__ y, int64_t ldy)
+k_scatter_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork, MRIo io0,
+             const MRIo* __restrict__ iot, int32_t r0, int32_t nr)
 {
     __shared__ double tile[kR][kWave + 1];
-    const int32_t c0 = blockIdx.x * kWave;
+    if ((int32_t)blockIdx.x >= nwork) return;
+    const int2 wk = work_at(work, blockIdx.x);
+    const MRInst& I = insts[wk.x];
+    const MRIo io = iot ? iot[wk.x] : io0;
+    const int32_t n = I.n, c0 = wk.y * kWave;
+    const double* yt = gp<const double>(I.yl);
+    const double* ya = I.has_b1 ? gp<const double>(I.yp) : nullptr;
+    const int32_t* iperm = gp<const int32_t>(I.iperm);
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
         const int c = e / kR, r = e % kR;
         if (c0 + c < n) {
@@ -70,9 +99,10 @@ k_scatter_mr(const double* __restrict__ yt, const double* __restrict__ ya, const
         }
     }
     __syncthreads();
+    double* y = gp<double>(io.y) + (int64_t)r0 * io.ld;
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
         const int r = e / kWave, c = e % kWave;
-        if (r < nr && c0 + c < n) y[(int64_t)r * ldy + c0 + c] = tile[r][c];
+        if (r < nr && c0 + c < n) y[(int64_t)r * io.ld + c0 + c] = tile[r][c];
     }
 }
 
@@ -168,14 +198,10 @@ __device__ __forceinline__ void srcA_tiles(d4 (&acc)[4], const double* __restric
 // in turn, T (k x 16, row-major) = V(rows, :)^T X(rows, :), up to 4 M tiles
 // of 16 columns q per pass.  Dynamic LDS: 16 x 8 bytes per row, rows
 // rounded up to 16.
-__global__ void __launch_bounds__(256)
-k_phaseA_mr(int64_t nitems, const MRItem* __restrict__ items, const MRBlk* __restrict__ blks,
-            const double* __restrict__ V, const double* __restrict__ xs, double* __restrict__ tpool,
-            double* __restrict__ ppool)
+__device__ __forceinline__ void
+phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const double* __restrict__ V, const double* __restrict__ xs,
+            double* __restrict__ tpool, double* __restrict__ ppool, double* xl)
 {
-    extern __shared__ double xl[];
-    if ((int64_t)blockIdx.x >= nitems) return;
-    const MRItem it = items[blockIdx.x];
     const int32_t rows = it.j1 - it.j0, rpad = (rows + 15) & ~15;
     const double* src = xs + (int64_t)(it.col0 + it.j0) * kR;
     for (int e = threadIdx.x; e < rpad * kR; e += blockDim.x) xl[e] = e < rows * kR ? src[e] : 0.0;
@@ -208,15 +234,31 @@ k_phaseA_mr(int64_t nitems, const MRItem* __restrict__ items, const MRBlk* __res
     }
 }
 
-// t = sum of the partial products of one split block.  Grid (blocks,
+__global__ void __launch_bounds__(256)
+k_phaseA_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork)
+{
+    extern __shared__ double xl[];
+    if ((int32_t)blockIdx.x >= nwork) return;
+    const int2 wk = work_at(work, blockIdx.x);
+    const MRInst& I = insts[wk.x];
+    phaseA_item(gp<const MRItem>(I.items)[wk.y], gp<const MRBlk>(I.blks), gp<const double>(I.V),
+                gp<const double>(I.xs), gp<double>(I.tp), gp<double>(I.pp), xl);
+}
+
+// t = sum of the partial products of one split block.  Grid (split blocks,
 // ceil(max k / 4)): workgroup (b, g) owns elements 64 g .. 64 g + 63 of the
 // k x 16 result, its four waves take every fourth part, and the four wave
 // sums are added in a fixed order.
 __global__ void __launch_bounds__(256)
-k_reduce_mr(int64_t nr, const RDesc* __restrict__ R, const double* __restrict__ ppool, double* __restrict__ tpool)
+k_reduce_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork)
 {
     __shared__ double part[4][kWave];
-    const RDesc D = R[blockIdx.x];
+    if ((int32_t)blockIdx.x >= nwork) return;
+    const int2 wk = work_at(work, blockIdx.x);
+    const MRInst& I = insts[wk.x];
+    const double* __restrict__ ppool = gp<const double>(I.pp);
+    double* __restrict__ tpool = gp<double>(I.tp);
+    const RDesc D = gp<const RDesc>(I.ritems)[wk.y];
     const int32_t E = D.k * kR;
     if ((int32_t)blockIdx.y * kWave >= E) return;   // whole workgroup
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -299,15 +341,15 @@ b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_
 {
     const int2 w = items[it];
     const int32_t P = uni_i(w.x), rc = uni_i(w.y);
-    const int32_t p0 = uni_i(Lbegin[tl][P]), cnt = uni_i(Lcount[tl][P]);
+    const int32_t p0 = uni_i(gp<const int32_t>((uint64_t)Lbegin[tl])[P]), cnt = uni_i(gp<const int32_t>((uint64_t)Lcount[tl])[P]);
     const int32_t rows = min(kWave, cnt - rc);
     d4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
     int32_t a_box = P;
     for (int l = tl; l >= 1; --l) {
-        const int32_t ab = uni_i(Lbegin[l][a_box]), ld_m = uni_i(Lcount[l][a_box]);
-        const int32_t q0 = uni_i(Lil[l][a_box]), q1 = uni_i(Lil[l][a_box + 1]);
+        const int32_t ab = uni_i(gp<const int32_t>((uint64_t)Lbegin[l])[a_box]), ld_m = uni_i(gp<const int32_t>((uint64_t)Lcount[l])[a_box]);
+        const int32_t q0 = uni_i(gp<const int32_t>((uint64_t)Lil[l])[a_box]), q1 = uni_i(gp<const int32_t>((uint64_t)Lil[l])[a_box + 1]);
         for (int32_t q = q0; q < q1; ++q) {
             const BDesc d = bil[q];
             const int64_t off = uni_l(d.off);
@@ -318,7 +360,7 @@ b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_
             else if (cols < 0)
                 mm_tile(acc, Dp + off + (p0 - ab) + rc, ld_m, rows, xs + (int64_t)tsrc * kR, kR, -cols, lane);
         }
-        a_box = uni_i(Lparent[l][a_box]);
+        a_box = uni_i(gp<const int32_t>((uint64_t)Lparent[l])[a_box]);
     }
     const int li = lane % 16, lk = lane / 16;
 #pragma unroll
@@ -386,23 +428,31 @@ __device__ __forceinline__ int32_t xcd_sub_mr(int32_t w, int32_t w0, int32_t n)
 // level-(kappa-1) boxes (ancestor levels, into ypart), the rest do leaf
 // boxes (into yleaf); the halves are independent and summed by the scatter.
 __global__ void __launch_bounds__(256)
-k_phaseB_mr(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
-            const int32_t* const* __restrict__ Lbegin, const int32_t* const* __restrict__ Lcount,
-            const int32_t* const* __restrict__ Lparent, const int32_t* const* __restrict__ Lil, int32_t nleaf,
-            const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
-            const double* __restrict__ Up, const double* __restrict__ Dp, const double* __restrict__ tpool,
-            const double* __restrict__ xs, double* __restrict__ ypart, double* __restrict__ yleaf)
+k_phaseB_mr(const MRInst* __restrict__ insts, int32_t nb1, const int2* __restrict__ work1, int32_t n1,
+            const int2* __restrict__ work2, int32_t n2)
 {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t w = blockIdx.x;
     if (w < nb1) {
         const int32_t it = xcd_sub_mr(w, 0, nb1) * 4 + wave;
-        if (it < nitems)
-            b1_mr(it, lane, items, kappa - 1, Lbegin, Lcount, Lparent, Lil, bil, Up, Dp, tpool, xs, ypart);
+        if (it >= n1) return;
+        const int2 wk = work_at(work1, it);
+        const MRInst& I = insts[wk.x];
+        const int32_t* const* L = gp<const int32_t* const>(I.lvl);
+        b1_mr(wk.y, lane, gp<const int2>(I.b1items), I.kappa - 1, L, L + (kMaxLevel + 1), L + 2 * (kMaxLevel + 1),
+              L + 3 * (kMaxLevel + 1), gp<const BDesc>(I.bil), gp<const double>(I.U), gp<const double>(I.D),
+              gp<const double>(I.tp), gp<const double>(I.xs), gp<double>(I.yp));
     } else {
-        const int32_t X = xcd_sub_mr(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
-        if (X < nleaf)
-            b2_mr(X, lane, Lbegin[kappa], Lcount[kappa], Lil[kappa], near_ptr, bnear, bil, Up, Dp, tpool, xs, yleaf);
+        const int32_t it = xcd_sub_mr(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
+        if (it >= n2) return;
+        const int2 wk = work_at(work2, it);
+        const MRInst& I = insts[wk.x];
+        const int32_t* const* L = gp<const int32_t* const>(I.lvl);
+        const int kp = I.kappa;
+        b2_mr(wk.y, lane, gp<const int32_t>((uint64_t)L[kp]), gp<const int32_t>((uint64_t)L[(kMaxLevel + 1) + kp]),
+              gp<const int32_t>((uint64_t)L[3 * (kMaxLevel + 1) + kp]), gp<const int32_t>(I.near_ptr),
+              gp<const BDesc>(I.bnear), gp<const BDesc>(I.bil), gp<const double>(I.U), gp<const double>(I.D),
+              gp<const double>(I.tp), gp<const double>(I.xs), gp<double>(I.yl));
     }
 }
 
@@ -458,7 +508,11 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
     for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int64_t)i;
     std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
     std::vector<MRItem> sorted(items.size());
-    for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[ord[i]];
+    H.h_mr_work.resize(items.size());
+    for (size_t i = 0; i < ord.size(); ++i) {
+        sorted[i] = items[ord[i]];
+        H.h_mr_work[i] = work[ord[i]];
+    }
     H.mr_items.alloc(std::max<size_t>(sorted.size(), 1));
     H.mr_blks.alloc(std::max<size_t>(blks.size(), 1));
     H.mr_ritems.alloc(std::max<size_t>(red.size(), 1));
@@ -474,57 +528,163 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
     HIPCK(hipStreamSynchronize(s));
 }
 
-void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s)
+static uint64_t addr(const void* p) { return (uint64_t)(uintptr_t)p; }
+
+MRInst mr_inst_of(const Handle& H)
+{
+    MRInst I{};
+    I.U = addr(H.U64.p); I.V = addr(H.V64.p); I.D = addr(H.D64.p);
+    I.xs = addr(H.xs_mr.p); I.tp = addr(H.tp_mr.p); I.pp = addr(H.pp_mr.p);
+    I.yp = addr(H.yp_mr.p); I.yl = addr(H.yl_mr.p);
+    I.items = addr(H.mr_items.p); I.blks = addr(H.mr_blks.p); I.ritems = addr(H.mr_ritems.p);
+    I.b1items = addr(H.b1items.p); I.bil = addr(H.bil.p); I.bnear = addr(H.bnear.p);
+    I.near_ptr = addr(H.near_ptr.p); I.iperm = addr(H.iperm.p); I.lvl = addr(H.lvl_ptrs.p);
+    I.n = (int32_t)H.n; I.kappa = H.kappa; I.has_b1 = H.n_b1 ? 1 : 0;
+    return I;
+}
+
+void ensure_mr(Handle& H, hipStream_t s)
 {
     const int32_t n = (int32_t)H.n;
     // per-group operand extents (16 columns of a box) must stay below 4 GiB
     if (H.n > (1 << 24)) fail(H2D_EUNSUPPORTED, "multi-RHS products support at most 2^24 points");
-    if (H.mr_cap == 0) {
-        build_mr_schedule(H, s);
-        H.xs_mr.alloc((size_t)n * kR);
-        H.tp_mr.alloc(std::max<int64_t>(H.t_elems, 1) * kR);
-        H.pp_mr.alloc(std::max<int64_t>(H.mr_p_elems, 1) * kR);
-        H.yp_mr.alloc((size_t)n * kR);
-        H.yl_mr.alloc((size_t)n * kR);
-        H.iperm.alloc(std::max(n, 1));
-        k_iperm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(H.perm.p, n, H.iperm.p);
-        HIPCK(hipGetLastError());
-        std::vector<const int32_t*> ptrs(4 * (kMaxLevel + 1), nullptr);
-        for (int l = 0; l <= H.kappa; ++l) {
-            ptrs[l] = H.lev[l].begin.p;
-            ptrs[kMaxLevel + 1 + l] = H.lev[l].count.p;
-            ptrs[2 * (kMaxLevel + 1) + l] = H.lev[l].parent.p;
-            ptrs[3 * (kMaxLevel + 1) + l] = H.lev[l].il_ptr.p;
-        }
-        H.lvl_ptrs.alloc(ptrs.size());
-        HIPCK(hipMemcpyAsync(H.lvl_ptrs.p, ptrs.data(), sizeof(void*) * ptrs.size(), hipMemcpyHostToDevice, s));
-        HIPCK(hipStreamSynchronize(s));
-        H.mr_cap = kR;
+    if (H.mr_cap != 0) return;
+    build_mr_schedule(H, s);
+    H.xs_mr.alloc((size_t)n * kR);
+    H.tp_mr.alloc(std::max<int64_t>(H.t_elems, 1) * kR);
+    H.pp_mr.alloc(std::max<int64_t>(H.mr_p_elems, 1) * kR);
+    H.yp_mr.alloc((size_t)n * kR);
+    H.yl_mr.alloc((size_t)n * kR);
+    H.iperm.alloc(std::max(n, 1));
+    k_iperm<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(H.perm.p, n, H.iperm.p);
+    HIPCK(hipGetLastError());
+    std::vector<const int32_t*> ptrs(4 * (kMaxLevel + 1), nullptr);
+    for (int l = 0; l <= H.kappa; ++l) {
+        ptrs[l] = H.lev[l].begin.p;
+        ptrs[kMaxLevel + 1 + l] = H.lev[l].count.p;
+        ptrs[2 * (kMaxLevel + 1) + l] = H.lev[l].parent.p;
+        ptrs[3 * (kMaxLevel + 1) + l] = H.lev[l].il_ptr.p;
     }
-    const int32_t* const* Lb = H.lvl_ptrs.p;
-    const int32_t* const* Lc = H.lvl_ptrs.p + (kMaxLevel + 1);
-    const int32_t* const* Lp = H.lvl_ptrs.p + 2 * (kMaxLevel + 1);
-    const int32_t* const* Li = H.lvl_ptrs.p + 3 * (kMaxLevel + 1);
+    H.lvl_ptrs.alloc(ptrs.size());
+    HIPCK(hipMemcpyAsync(H.lvl_ptrs.p, ptrs.data(), sizeof(void*) * ptrs.size(), hipMemcpyHostToDevice, s));
+    const MRInst I = mr_inst_of(H);
+    H.mr_inst.alloc(1);
+    HIPCK(hipMemcpyAsync(H.mr_inst.p, &I, sizeof(MRInst), hipMemcpyHostToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
+    H.mr_cap = kR;
+}
+
+static int32_t mr_rows_of(const Handle& H) { return std::max(16, std::min<int32_t>(H.mr_rows, kMrRowsMax)) & ~15; }
+
+void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s)
+{
+    ensure_mr(H, s);
+    const int32_t n = (int32_t)H.n;
     const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
-    const int32_t R = std::max(16, std::min<int32_t>(H.mr_rows, kMrRowsMax)) & ~15;
-    const unsigned pblocks = (unsigned)((n + kWave - 1) / kWave);
+    const int32_t R = mr_rows_of(H);
+    const int32_t pblocks = (n + kWave - 1) / kWave;
+    const MRIo io{addr(x), addr(y), ld};
+    const MRInst* I = H.mr_inst.p;
     for (int r0 = 0; r0 < nrhs; r0 += kR) {
         const int32_t nr = std::min(kR, nrhs - r0);
-        k_gather_mr<<<pblocks, 256, 0, s>>>(x + (int64_t)r0 * ld, ld, nr, H.iperm.p, n, H.xs_mr.p);
+        k_gather_mr<<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
         if (H.n_mr_items)
-            k_phaseA_mr<<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(double), s>>>(
-                H.n_mr_items, H.mr_items.p, H.mr_blks.p, H.V64.p, H.xs_mr.p, H.tp_mr.p, H.pp_mr.p);
+            k_phaseA_mr<<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(double), s>>>(I, nullptr,
+                                                                                        (int32_t)H.n_mr_items);
         if (H.n_mr_ritems)
             k_reduce_mr<<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256, 0,
-                          s>>>(H.n_mr_ritems, H.mr_ritems.p, H.pp_mr.p, H.tp_mr.p);
+                          s>>>(I, nullptr, (int32_t)H.n_mr_ritems);
         const int32_t nb1 = (int32_t)((H.n_b1 + 3) / 4), nb2 = (nleaf + 3) / 4;
-        k_phaseB_mr<<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, (int32_t)H.n_b1, H.b1items.p, H.kappa, Lb, Lc, Lp, Li,
-                                                          nleaf, H.near_ptr.p, H.bnear.p, H.bil.p, H.U64.p, H.D64.p,
-                                                          H.tp_mr.p, H.xs_mr.p, H.yp_mr.p, H.yl_mr.p);
-        k_scatter_mr<<<pblocks, 256, 0, s>>>(H.yl_mr.p, H.n_b1 ? H.yp_mr.p : nullptr, H.iperm.p, n, nr,
-                                             y + (int64_t)r0 * ld, ld);
+        k_phaseB_mr<<<(unsigned)(nb1 + nb2), 256, 0, s>>>(I, nb1, nullptr, (int32_t)H.n_b1, nullptr, nleaf);
+        k_scatter_mr<<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
         HIPCK(hipGetLastError());
     }
+}
+
+template <typename T>
+static void upload(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
+{
+    d.alloc(std::max<size_t>(h.size(), 1));
+    if (!h.empty()) HIPCK(hipMemcpyAsync(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
+}
+
+void mr_plan(MRBatchPlan& P, Handle* const* hs, const MRIo* io, int count, hipStream_t s)
+{
+    constexpr int kXcd = 8;
+    std::vector<MRInst> insts(count);
+    std::vector<MRIo> ios(io, io + count);
+    std::vector<int2> wg, wr;
+    std::vector<std::pair<int64_t, int2>> wa;
+    std::vector<int32_t> rows(count);
+    P.red_y = 1;
+    for (int i = 0; i < count; ++i) {
+        Handle& H = *hs[i];
+        ensure_mr(H, s);
+        insts[i] = mr_inst_of(H);
+        rows[i] = mr_rows_of(H);
+        const int32_t n = (int32_t)H.n;
+        for (int32_t b = 0; b < (n + kWave - 1) / kWave; ++b) wg.push_back(make_int2(i, b));
+        for (int32_t a = 0; a < (int32_t)H.n_mr_items; ++a) wa.push_back({H.h_mr_work[a], make_int2(i, a)});
+        for (int32_t r = 0; r < (int32_t)H.n_mr_ritems; ++r) wr.push_back(make_int2(i, r));
+        P.red_y = std::max<int32_t>(P.red_y, (int32_t)((H.max_rank * kR + kWave - 1) / kWave));
+    }
+    // phase B: the XCD-aware mapping gives each XCD one eighth of the list;
+    // deal every instance's items over the eighths (contiguous inside each)
+    // so that each XCD gets a share of every instance
+    auto dealt = [&](auto count_of) {
+        std::vector<int2> w;
+        for (int x = 0; x < kXcd; ++x)
+            for (int i = 0; i < count; ++i) {
+                const int32_t m = count_of(*hs[i]);
+                for (int32_t q = (int32_t)((int64_t)m * x / kXcd); q < (int32_t)((int64_t)m * (x + 1) / kXcd); ++q)
+                    w.push_back(make_int2(i, q));
+            }
+        return w;
+    };
+    const std::vector<int2> wb1 = dealt([](const Handle& H) { return (int32_t)H.n_b1; });
+    const std::vector<int2> wb2 = dealt([](const Handle& H) { return (int32_t)H.lev[H.kappa].nbox; });
+    // phase A: one launch per source-chunk size (its LDS need), items of all
+    // instances largest work first inside each (a static LPT schedule)
+    std::stable_sort(wa.begin(), wa.end(), [&](const auto& a, const auto& b) {
+        const int32_t ra = rows[a.second.x], rb = rows[b.second.x];
+        return ra != rb ? ra > rb : a.first > b.first;
+    });
+    std::vector<int2> wav(wa.size());
+    P.a_rows.clear(); P.a_beg.clear(); P.a_cnt.clear();
+    for (size_t q = 0; q < wa.size(); ++q) {
+        wav[q] = wa[q].second;
+        const int32_t r = rows[wa[q].second.x];
+        if (P.a_rows.empty() || P.a_rows.back() != r) {
+            P.a_rows.push_back(r);
+            P.a_beg.push_back((int32_t)q);
+            P.a_cnt.push_back(0);
+        }
+        ++P.a_cnt.back();
+    }
+    upload(P.insts, insts, s);
+    upload(P.io, ios, s);
+    upload(P.wg, wg, s);
+    upload(P.wa, wav, s);
+    upload(P.wr, wr, s);
+    upload(P.wb1, wb1, s);
+    upload(P.wb2, wb2, s);
+    P.ng = (int32_t)wg.size(); P.nr = (int32_t)wr.size();
+    P.nb1 = (int32_t)wb1.size(); P.nb2 = (int32_t)wb2.size();
+    HIPCK(hipStreamSynchronize(s));
+}
+
+void mr_plan_launch(const MRBatchPlan& P, int32_t r0, int32_t nr, hipStream_t s)
+{
+    const MRIo none{0, 0, 0};
+    k_gather_mr<<<(unsigned)P.ng, 256, 0, s>>>(P.insts.p, P.wg.p, P.ng, none, P.io.p, r0, nr);
+    for (size_t g = 0; g < P.a_rows.size(); ++g)
+        k_phaseA_mr<<<(unsigned)P.a_cnt[g], 256, (size_t)P.a_rows[g] * kR * sizeof(double), s>>>(
+            P.insts.p, P.wa.p + P.a_beg[g], P.a_cnt[g]);
+    if (P.nr) k_reduce_mr<<<dim3((unsigned)P.nr, (unsigned)P.red_y), 256, 0, s>>>(P.insts.p, P.wr.p, P.nr);
+    const int32_t g1 = (P.nb1 + 3) / 4, g2 = (P.nb2 + 3) / 4;
+    k_phaseB_mr<<<(unsigned)(g1 + g2), 256, 0, s>>>(P.insts.p, g1, P.wb1.p, P.nb1, P.wb2.p, P.nb2);
+    k_scatter_mr<<<(unsigned)P.ng, 256, 0, s>>>(P.insts.p, P.wg.p, P.ng, none, P.io.p, r0, nr);
+    HIPCK(hipGetLastError());
 }
 
 }  // namespace h2d
