@@ -538,6 +538,7 @@ void build_tree_and_lists(Handle& H, hipStream_t s)
 // Adaptive cross approximation, one workgroup per block
 // ---------------------------------------------------------------------
 constexpr int kAcaThreads = 256;
+static_assert(kAcaThreads == 4 * kWave, "the ACA cross-term sums combine exactly 4 waves");
 
 struct AcaJob {
     int32_t row0, m, col0, n;
@@ -607,6 +608,7 @@ k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double
     __shared__ int32_t li[kAcaThreads];
     __shared__ double row[kAcaRankCap];    // U(i, :) or V(j*, :)
     __shared__ double ab[2][kAcaRankCap];  // cross-term dot products
+    __shared__ double cw[kAcaThreads / kWave][16];   // per-wave partial cross terms
     const AcaJob J = jobs[blockIdx.x];
     const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
     const int32_t m = J.m, n = J.n, kcap = J.kcap;
@@ -702,14 +704,39 @@ k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double
         __syncthreads();
         uu = block_sum(uu, lv);
         vv = block_sum(vv, lv);
-        // cross terms (U(:, q) . u) (V(:, q) . v), one wave per q
-        for (int q = wave; q < k; q += kAcaThreads / kWave) {
-            double a = 0.0, b = 0.0;
-            for (int32_t ii = lane; ii < m; ii += kWave) a += U[(int64_t)q * m + ii] * u[ii];
-            for (int32_t j = lane; j < n; j += kWave) b += V[(int64_t)q * n + j] * r[j];
-            a = wave_sum(a);
-            b = wave_sum(b);
-            if (lane == 0) { ab[0][q] = a; ab[1][q] = b; }
+        // cross terms (U(:, q) . u) (V(:, q) . v) for q < k: every thread
+        // takes rows t, t + 256, ... for 8 columns q at a time (8 loads in
+        // flight; columns past k - 1 re-read column k - 1 and are dropped),
+        // then shuffle sums per wave and a fixed-order sum of the 4 waves
+        for (int q0 = 0; q0 < k; q0 += 8) {
+            double pa[8], pb[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) { pa[c] = 0.0; pb[c] = 0.0; }
+            for (int32_t ii = t; ii < m; ii += kAcaThreads) {
+                const double ui = u[ii];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) pa[c] += U[(int64_t)min(q0 + c, k - 1) * m + ii] * ui;
+            }
+            for (int32_t j = t; j < n; j += kAcaThreads) {
+                const double vj = r[j];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) pb[c] += V[(int64_t)min(q0 + c, k - 1) * n + j] * vj;
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                pa[c] = wave_sum(pa[c]);
+                pb[c] = wave_sum(pb[c]);
+            }
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) { cw[wave][c] = pa[c]; cw[wave][8 + c] = pb[c]; }
+            __syncthreads();
+            if (t < 16) {
+                const double sum = (cw[0][t] + cw[1][t]) + (cw[2][t] + cw[3][t]);
+                const int q = q0 + (t & 7);
+                if (q < k) ab[t >> 3][q] = sum;
+            }
+            __syncthreads();
         }
         __syncthreads();
         double cross = 0.0;
