@@ -3,12 +3,16 @@
 //   gather:   xs = x(perm)                     tree order
 //   phase A:  t_b = V_b^T xs(Y_b)              every low-rank block, all levels
 //   reduce:   t_b = sum of partials            blocks whose V was split over waves
-//   phase B:  y(X) = sum over the leaf box X's dense near blocks, and over
-//             the blocks of X and of each ancestor of X, of U_b(rows of X) t_b
-//             (or D_b(rows of X) xs(Y_b) for dense blocks); written once,
-//             scattered back to caller order.  No atomics: every output row
-//             is owned by one wave, and every sum is taken in a fixed order,
-//             so two runs give identical bits.
+//   phase B:  for every row of a leaf box X, the sum over the blocks of the
+//             ancestors of X of U_b(rows) t_b (or D_b(rows) xs(Y_b) for dense
+//             blocks) -- the "B1" half, per slice of a box one level above
+//             the leaves -- and, in the same launch, the sum over X's dense
+//             near blocks and X's own blocks -- the "B2" half, per leaf
+//             chunk; the two sums go to separate arrays
+//   combine:  y = the two sums (+ the FP32 diagonal term of the half
+//             pools), written once in caller order.
+// No atomics: every output row is owned by one wave in each half, and every
+// sum is taken in a fixed order, so two runs give identical bits.
 //
 // Storage: U column-major m x k (a leaf box's rows are contiguous in every
 // column), V row-major n x k (a wave reads whole rows: G = 64 / k rows per
@@ -394,7 +398,7 @@ void finalize(Handle& H, hipStream_t s)
     int64_t toff = 0, poff = 0;
     H.max_rank = 0; H.sum_rank = 0; H.n_il_dense = 0;
     double flops = 0;
-    double store_anc = 0, store_leaf = 0, t_leaf = 0;   // stored values read by B1 / B2, t values read by B2
+    double store_anc = 0, store_leaf = 0, t_leaf = 0;   // stored values read by the B1 / B2 halves, t values by B2
     for (int64_t b = 0; b < nil; ++b) {
         const Level& L = H.lev[H.h_il_level[b]];
         const bool leaf = H.h_il_level[b] == kappa;
@@ -522,7 +526,7 @@ static LevelPtrs level_ptrs(const Handle& H)
 }
 
 constexpr size_t kProfMax = 65536;
-constexpr int kEv = 6;   // events per recorded matvec: around gather, A, reduce, B1, B2
+constexpr int kEv = 6;   // events per recorded matvec: around gather, A, reduce, B, combine
 
 static hipEvent_t* prof_slot(Handle& H)
 {
