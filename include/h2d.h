@@ -111,7 +111,9 @@ h2d_status h2d_matvec(h2d_t H, const double* x, double* y, int32_t nrhs, int64_t
 typedef enum {
     H2D_SOLVE_PLAIN = 0,   /* restarted GMRES on the FP64 operator */
     H2D_SOLVE_REFINE = 1   /* FP64 iterative refinement around an inner GMRES
-                              on the FP16/BF16 operator (inner_prec) */
+                              on the FP16/BF16 operator (inner_prec); an inner
+                              solve stops on its Arnoldi residual estimate, the
+                              refinement step on the true FP64 residual */
 } h2d_solve_mode;
 
 /* Right preconditioners (flexible GMRES: the preconditioned vectors are
@@ -147,7 +149,9 @@ typedef struct {
 /* Solve A_hat x = b to relative residual rtol (GMRES as used in Section 5,
  * x0 = 0).  b, x: device FP64, n entries, caller order.  The convergence
  * test is always the true FP64 residual.  Returns OK or ENOCONV (x then holds
- * the last iterate and info->relres its residual). */
+ * the last iterate and info->relres its residual).  The Krylov basis and
+ * work vectors (about (2 restart + 6) n doubles with a preconditioner) are
+ * allocated on the first solve and kept by the handle for the next ones. */
 h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d_solve_opts* opts,
                      h2d_solve_info* info, void* stream);
 

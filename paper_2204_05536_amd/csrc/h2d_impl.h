@@ -18,8 +18,8 @@ namespace h2d {
 constexpr int kMaxLevel = 16;      // Morton keys are 2 x 16 bits
 constexpr int kWave = 64;
 constexpr int kAcaRankCap = 256;   // ACA scratch columns per block
-constexpr int kPhaseARows = 512;
-constexpr int kMrRowsMax = 512;   // multi-RHS phase-A source chunk: 512 rows x 16 x 8 bytes = 64 KiB of LDS   // V rows per phase-A work item (x slice staged in LDS)
+constexpr int kPhaseARows = 512;   // V rows per phase-A work item (x slice staged in LDS)
+constexpr int kMrRowsMax = 512;    // multi-RHS phase-A source chunk: 512 rows x 16 x 8 bytes = 64 KiB of LDS
 
 // Error carried from deep inside the library to the C ABI.
 struct Error {
@@ -59,6 +59,11 @@ struct DBuf {
             fail(H2D_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
         }
         n = count;
+    }
+    // keep the buffer when it already holds count elements
+    void reserve(size_t count)
+    {
+        if (n < count) alloc(count);
     }
     void reset()
     {
@@ -228,12 +233,16 @@ struct Handle {
     DBuf<int32_t> bj_piv;      // per tree row: pivot row chosen at that step of its leaf
     DBuf<int64_t> bj_off;      // per leaf: offset into bj_lu
     bool bj_ready = false;
+    // solver work space, kept between solves and grown on demand: Krylov
+    // basis, preconditioned directions, vectors, dot-product partials, and
+    // the refinement loop's residual, correction and product
+    DBuf<double> gm_V, gm_Z, gm_w, gm_r, gm_y, gm_part, gm_dres, rf_r, rf_d, rf_w;
     std::shared_ptr<MlpState> mlp;
 
     double alg_bytes_fp64 = 0, alg_bytes_half = 0, flops = 0;
-    double phase_bytes[2][5] = {{0}};   // [FP64, half][gather, A, reduce, B1, B2]
+    double phase_bytes[2][5] = {{0}};   // [FP64, half][gather, A, reduce, B, combine]
 
-    // profiling: 5 events per recorded matvec
+    // profiling: 6 events per recorded matvec (around its 5 kernels)
     bool prof_on = false;
     int prof_prec = 0;
     std::vector<hipEvent_t> prof_ev;

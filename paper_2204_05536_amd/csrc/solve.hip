@@ -98,15 +98,17 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
         y[i] += a * x[i];
 }
 
+// Dot products and norms on the handle's partial-sum buffers.
 struct Blas {
     hipStream_t s;
     int64_t n;
-    DBuf<double> part, dres;
+    DBuf<double>& part;
+    DBuf<double>& dres;
     std::vector<double> h;
-    Blas(hipStream_t s_, int64_t n_, int maxv) : s(s_), n(n_)
+    Blas(Handle& H, hipStream_t s_, int64_t n_, int maxv) : s(s_), n(n_), part(H.gm_part), dres(H.gm_dres)
     {
-        part.alloc((size_t)kDotBlocks * maxv);
-        dres.alloc(maxv);
+        part.reserve((size_t)kDotBlocks * maxv);
+        dres.reserve(maxv);
         h.resize(maxv);
     }
     int grid() const { return (int)std::min<int64_t>(4096, (n + 255) / 256); }
@@ -148,19 +150,26 @@ constexpr double kStallRatio = 0.9;
 // GMRES(restart) for A_prec x = rhs, x0 = 0, optionally right-
 // preconditioned in the flexible form (z_j = M v_j kept, x += Z y).
 // Convergence is judged by the true residual |rhs - A_prec x| / |rhs| <= tol
-// at each restart.
+// at each restart.  An inner solve of the refinement loop (`inner`) stops
+// on the Arnoldi estimate instead: the loop around it computes the true
+// FP64 residual anyway, so a true residual of the half operator would be a
+// product spent for nothing.
 static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, double tol, int restart, int max_iter,
-                         int& precond, hipStream_t s)
+                         int& precond, bool inner, hipStream_t s)
 {
     const int64_t n = H.n;
     const int m = restart;
-    Blas B(s, n, m + 1);
-    DBuf<double> Vb, Zb, w, r, yv;
-    Vb.alloc((size_t)n * (m + 1));
-    if (precond != H2D_PC_NONE) Zb.alloc((size_t)n * m);
-    w.alloc(n);
-    r.alloc(n);
-    yv.alloc(m + 1);
+    Blas B(H, s, n, m + 1);
+    DBuf<double>& Vb = H.gm_V;
+    DBuf<double>& Zb = H.gm_Z;
+    DBuf<double>& w = H.gm_w;
+    DBuf<double>& r = H.gm_r;
+    DBuf<double>& yv = H.gm_y;
+    Vb.reserve((size_t)n * (m + 1));
+    if (precond != H2D_PC_NONE) Zb.reserve((size_t)n * m);
+    w.reserve(n);
+    r.reserve(n);
+    yv.reserve(m + 1);
     std::vector<double> Hm((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
     const int grid = B.grid();
     GmresResult R;
@@ -186,6 +195,7 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
         int j = 0, j_mark = 0;
         double g_mark = beta;
         bool stalled = false;
+        double hn_last = 1.0;   // norm of the last new Krylov direction (0: exact breakdown)
         for (; j < m && R.iters < max_iter; ) {
             ++R.iters;
             double* vj1 = Vb.p + (int64_t)(j + 1) * n;
@@ -204,6 +214,7 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
                 k_sub_comb<<<grid, 256, 0, s>>>(vj1, Vb.p, n, j + 1, dh, n);
             }
             const double hn = B.nrm2(vj1);
+            hn_last = hn;
             hc[j + 1] = hn;
             if (hn > 0.0) k_scale<<<grid, 256, 0, s>>>(vj1, vj1, 1.0 / hn, n);
             HIPCK(hipGetLastError());
@@ -241,6 +252,10 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
         if (stalled) {
             precond = H.bj_ready ? H2D_PC_BLOCK_JACOBI : H2D_PC_NONE;
             if (R.fallback_at < 0) R.fallback_at = R.iters;
+        } else if (inner && (std::fabs(g[j]) / bn <= tol || hn_last == 0.0)) {
+            R.relres = std::fabs(g[j]) / bn;
+            R.converged = true;
+            break;
         }
     }
     HIPCK(hipStreamSynchronize(s));
@@ -259,7 +274,7 @@ h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_s
     I.fallback_at = -1;
     int pc = o.precond;   // the learned preconditioner may hand over to block-Jacobi
     if (o.mode == H2D_SOLVE_PLAIN) {
-        GmresResult R = gmres(H, H2D_P_FP64, b, x, rtol, o.restart, o.max_iter, pc, s);
+        GmresResult R = gmres(H, H2D_P_FP64, b, x, rtol, o.restart, o.max_iter, pc, false, s);
         I.iters = R.iters; I.outer = R.restarts; I.relres = R.relres;
         I.fallback_at = R.fallback_at;
         ok = R.converged;
@@ -267,9 +282,11 @@ h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_s
         if (o.inner_prec != H2D_P_FP16 && o.inner_prec != H2D_P_BF16) fail(H2D_EINVAL, "inner_prec must be FP16 or BF16");
         if (!(H.prec_mask & H2D_PREC_BIT(o.inner_prec))) fail(H2D_EUNSUPPORTED, "inner precision was not built");
         if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0)) fail(H2D_EINVAL, "inner_tol must be in (0, 1)");
-        Blas B(s, n, 1);
-        DBuf<double> r, d, w;
-        r.alloc(n); d.alloc(n); w.alloc(n);
+        Blas B(H, s, n, 1);
+        DBuf<double>& r = H.rf_r;
+        DBuf<double>& d = H.rf_d;
+        DBuf<double>& w = H.rf_w;
+        r.reserve(n); d.reserve(n); w.reserve(n);
         const int grid = B.grid();
         HIPCK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
         HIPCK(hipMemcpyAsync(r.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -278,7 +295,7 @@ h2d_status solve(Handle& H, const double* b, double* x, double rtol, const h2d_s
         int outer = 0, iters = 0;
         const int max_outer = o.max_outer > 0 ? o.max_outer : 50;
         while (rel > rtol && outer < max_outer && iters < o.max_iter) {
-            GmresResult R = gmres(H, o.inner_prec, r.p, d.p, o.inner_tol, o.restart, o.max_iter - iters, pc, s);
+            GmresResult R = gmres(H, o.inner_prec, r.p, d.p, o.inner_tol, o.restart, o.max_iter - iters, pc, true, s);
             if (R.fallback_at >= 0 && I.fallback_at < 0) I.fallback_at = iters + R.fallback_at;
             iters += R.iters;
             ++outer;
