@@ -1062,16 +1062,24 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         k_half_plain<T><<<4096, 256, 0, s>>>(H.V64.p, Vp, H.v_elems);
         HIPCK(hipGetLastError());
     };
+    // the half kernels read values in pairs and may read one element past
+    // the last block of a pool: every pool carries kHalfSlack zeroed
+    // elements at its end
+    auto alloc_half = [&](auto& buf, int64_t elems) {
+        using T = std::remove_pointer_t<decltype(buf.p)>;
+        buf.alloc((size_t)elems + kHalfSlack);
+        HIPCK(hipMemsetAsync(buf.p + elems, 0, sizeof(T) * kHalfSlack, s));
+    };
     if (f16) {
-        H.U16.alloc(std::max<int64_t>(H.u_elems, 1));
-        H.V16.alloc(std::max<int64_t>(H.v_elems, 1));
-        H.D16.alloc(std::max<int64_t>(H.d_elems, 1));
+        alloc_half(H.U16, H.u_elems);
+        alloc_half(H.V16, H.v_elems);
+        alloc_half(H.D16, H.d_elems);
         run(H.U16.p, H.V16.p, H.D16.p);
     }
     if (b16) {
-        H.Ub16.alloc(std::max<int64_t>(H.u_elems, 1));
-        H.Vb16.alloc(std::max<int64_t>(H.v_elems, 1));
-        H.Db16.alloc(std::max<int64_t>(H.d_elems, 1));
+        alloc_half(H.Ub16, H.u_elems);
+        alloc_half(H.Vb16, H.v_elems);
+        alloc_half(H.Db16, H.d_elems);
         run(H.Ub16.p, H.Vb16.p, H.Db16.p);
     }
     // one scale per IL block then per near block (table order)

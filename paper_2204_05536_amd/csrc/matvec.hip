@@ -64,6 +64,30 @@ __device__ __forceinline__ A ldv(const T* p)
     else return ld<T, A>(p);
 }
 
+// Two consecutive half values from one 4-byte load.  A lane that reads a
+// single 2-byte value per instruction moves 128 bytes per wave load, and
+// such loads stream at about half the rate of 4-byte ones on this chip, so
+// the half kernels read factor values in pairs.  The pair starts at any
+// even byte address: the type below tells the compiler so, and it still
+// emits one dword load, which the GPU serves in its unaligned-access mode
+// (the mode the ROCm runtime sets on this GPU family).  Callers make sure
+// both values lie inside the pool (the half pools carry a few elements of
+// slack at the end); a value past the end of a block is read but its
+// product is dropped.
+typedef uint32_t u32_a2 __attribute__((aligned(2)));
+template <typename T> __device__ __forceinline__ float2 ld2(const T* p);
+template <> __device__ __forceinline__ float2 ld2<__half>(const __half* p)
+{
+    const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const u32_a2*>(p));
+    return make_float2(__half2float(__ushort_as_half((unsigned short)(w & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(w >> 16))));
+}
+template <> __device__ __forceinline__ float2 ld2<__hip_bfloat16>(const __hip_bfloat16* p)
+{
+    const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const u32_a2*>(p));
+    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
 template <typename A>
 __global__ void k_gather(const double* x, const int32_t* perm, int32_t n, int64_t ldx, int64_t ldxs, int nrhs, A* xs)
 {
@@ -123,6 +147,36 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     A* out = (D.out >= 0) ? (tpool + D.out) : (ppool + (-D.out - 1));
     A sc = (A)1;
     if constexpr (kScaled) sc = (A)scale[D.pad];
+    if constexpr (sizeof(T) == 2) {
+        if (k <= 2 * kWave) {
+            // lane (g, qp) takes columns 2 qp, 2 qp + 1 of rows g, g + G, ...
+            // (kp = ceil(k / 2) lanes per row); for odd k the last lane's
+            // second value belongs to the next row and its sum is dropped
+            __shared__ float red2[4][2 * kWave];
+            const int kp = (k + 1) >> 1;
+            const int G = kWave / kp, g = lane / kp, qp = lane % kp;
+            float a0 = 0.f, a1 = 0.f;
+            if (g < G) {
+#pragma unroll 8
+                for (int32_t j = g; j < rows; j += G) {
+                    const float2 v = ld2<T>(Vb + (int64_t)j * k + 2 * qp);
+                    const float xv = xl[j];
+                    a0 += v.x * xv;
+                    a1 += v.y * xv;
+                }
+            }
+            red2[wave][2 * lane] = a0;
+            red2[wave][2 * lane + 1] = a1;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (int32_t q = lane; q < k; q += kWave) {
+                float s = 0.f;
+                for (int gg = 0; gg < G; ++gg) s += red2[wave][2 * (gg * kp + (q >> 1)) + (q & 1)];
+                out[q] = s * sc;
+            }
+            return;
+        }
+    }
     if (k <= kWave) {
         const int G = kWave / k, g = lane / k, q = lane % k;
         A acc = (A)0;
@@ -239,6 +293,66 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
     }
 }
 
+// Phase B1 for the half pools, slices of 64 rows: lane (g, rp) takes rows
+// 2 rp, 2 rp + 1 (one 4-byte load) of the columns of parity g, so a wave
+// load covers two columns.  Both columns' t (or x) values are read through
+// the scalar cache and each lane picks its own; an odd last column leaves
+// the g = 1 lanes re-reading the previous column with a zero multiplier.
+// The two parities are added with one cross-lane exchange.
+template <typename T>
+__device__ __forceinline__ void
+b1_item_h2(int32_t it, int lane, const int2* __restrict__ items, int tl, const LevelPtrs& L,
+           const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
+           const float* __restrict__ tpool, const float* __restrict__ xs, float* __restrict__ ypart,
+           const float* __restrict__ scale)
+{
+    using cA = ConstAS<float>;
+    const int2 w = items[it];
+    const int32_t P = uni(w.x), rc = uni(w.y);
+    const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
+    const int32_t rows = min(kWave, cnt - rc);
+    const int g = lane >> 5, rp = lane & 31;
+    const bool act = 2 * rp < rows;
+    float a0 = 0.f, a1 = 0.f;
+    int32_t a_box = P;
+    for (int l = tl; l >= 1; --l) {
+        const int32_t ab = uni(L.begin[l][a_box]), ld_m = uni(L.count[l][a_box]);
+        const int32_t q0 = uni(L.il_ptr[l][a_box]), q1 = uni(L.il_ptr[l][a_box + 1]);
+        for (int32_t q = q0; q < q1; ++q) {
+            const BDesc d = uni(bil[q]);
+            const bool lowrank = d.cols > 0;
+            const int32_t nc = lowrank ? d.cols : -d.cols;
+            if (nc == 0) continue;
+            // low rank: this box's tile of U (cnt x k, column-major); dense:
+            // this box's rows of the ancestor's block (leading dimension ld_m)
+            const T* base = lowrank ? Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + 2 * rp
+                                    : Dp + d.off + (p0 - ab) + rc + 2 * rp;
+            const int64_t ld = lowrank ? cnt : ld_m;
+            const cA* tv = (const cA*)(lowrank ? tpool + d.tsrc : xs + d.tsrc);
+            float b0 = 0.f, b1 = 0.f;
+            if (act) {
+#pragma unroll 8
+                for (int32_t c = 0; c < nc; c += 2) {
+                    const float t0 = tv[c], t1r = tv[c + 1];
+                    const float t = g ? (c + 1 < nc ? t1r : 0.f) : t0;
+                    const float2 v = ld2<T>(base + (int64_t)min(c + g, nc - 1) * ld);
+                    b0 += v.x * t;
+                    b1 += v.y * t;
+                }
+            }
+            const float sc = lowrank ? 1.f : scale[q];
+            a0 += b0 * sc;
+            a1 += b1 * sc;
+        }
+        a_box = uni(L.parent[l][a_box]);
+    }
+    const float s0 = a0 + __shfl_xor(a0, 32, kWave), s1 = a1 + __shfl_xor(a1, 32, kWave);
+    if (g == 0 && act) {
+        ypart[p0 + rc + 2 * rp] = s0;
+        if (2 * rp + 1 < rows) ypart[p0 + rc + 2 * rp + 1] = s1;
+    }
+}
+
 // Phase B2: the leaf level.  One wave per 64-row chunk of a leaf box X
 // (leaves above 64 points give several items): its dense near blocks and
 // its own interaction-list blocks, into the leaf-level sum.  A chunk has at
@@ -306,6 +420,87 @@ b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], int kappa, c
     }
 }
 
+// Phase B2 for the half pools: lane (g, rp) takes rows 2 rp, 2 rp + 1 of
+// the chunk (one 4-byte load) and the columns g, g + G, ... (G = 64 / row
+// pairs); same sums and order as the FP64 form.
+template <typename T>
+__device__ __forceinline__ void
+b2_item_h2(int32_t X, int32_t rc, int wave, int lane, float (*red2)[2 * kWave], int kappa, const LevelPtrs& L,
+           const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
+           const T* __restrict__ Up, const T* __restrict__ Dp, const float* __restrict__ tpool,
+           const float* __restrict__ xs, float* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
+{
+    const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
+    const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
+    const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
+    const int32_t rows = min(kWave, cnt - rc);
+    const int P = (rows + 1) >> 1;
+    const int G = kWave / P, g = lane / P, rp = lane % P;
+    const bool act = g < G;
+    float a0 = 0.f, a1 = 0.f;
+    for (int32_t q = n0; q < n1; ++q) {
+        const BDesc d = uni(bnear[q]);
+        const T* base = Dp + d.off + rc + 2 * rp;
+        const float* tv = xs + d.tsrc;
+        float b0 = 0.f, b1 = 0.f;
+        if (act) {
+#pragma unroll 4
+            for (int32_t j = g; j < -d.cols; j += G) {
+                const float2 v = ld2<T>(base + (int64_t)j * cnt);
+                const float xv = tv[j];
+                b0 += v.x * xv;
+                b1 += v.y * xv;
+            }
+        }
+        const float sc = scale[n_il + q];
+        a0 += b0 * sc;
+        a1 += b1 * sc;
+    }
+    for (int32_t q = q0; q < q1; ++q) {
+        const BDesc d = uni(bil[q]);
+        if (d.cols > 0) {
+            const T* base = Up + d.off + rc + 2 * rp;
+            const float* tv = tpool + d.tsrc;
+            if (act) {
+#pragma unroll 4
+                for (int32_t c = g; c < d.cols; c += G) {
+                    const float2 v = ld2<T>(base + (int64_t)c * cnt);
+                    const float t = tv[c];
+                    a0 += v.x * t;
+                    a1 += v.y * t;
+                }
+            }
+        } else if (d.cols < 0) {
+            const T* base = Dp + d.off + rc + 2 * rp;
+            const float* tv = xs + d.tsrc;
+            float b0 = 0.f, b1 = 0.f;
+            if (act) {
+#pragma unroll 4
+                for (int32_t j = g; j < -d.cols; j += G) {
+                    const float2 v = ld2<T>(base + (int64_t)j * cnt);
+                    const float xv = tv[j];
+                    b0 += v.x * xv;
+                    b1 += v.y * xv;
+                }
+            }
+            const float sc = scale[q];
+            a0 += b0 * sc;
+            a1 += b1 * sc;
+        }
+    }
+    red2[wave][2 * lane] = act ? a0 : 0.f;
+    red2[wave][2 * lane + 1] = act ? a1 : 0.f;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rows) {
+        float s = 0.f;
+        for (int gg = 0; gg < G; ++gg) s += red2[wave][2 * (gg * P + (lane >> 1)) + (lane & 1)];
+        yleaf[r0 + rc + lane] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Workgroups w0 .. w0 + n - 1 of the grid -> tiles 0 .. n - 1 such that
 // the workgroups each XCD receives (workgroup ids are dealt round-robin over
 // the 8 XCDs) take one contiguous range of tiles.
@@ -339,14 +534,24 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
     const int32_t w = blockIdx.x;
     if (w < nb1) {
         const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
-        if (it < nitems) b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart,
-                                                 scale);
+        if (it < nitems) {
+            if constexpr (kHalf && S == kWave)
+                b1_item_h2<T>(it, lane, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
+            else
+                b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
+        }
     } else {
         const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
         if (it < nb2items) {
             const int2 c = b2items[it];
-            b2_item<T, A, kHalf>(uni(c.x), uni(c.y), wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs,
-                                 yleaf, scale, n_il);
+            if constexpr (kHalf) {
+                __shared__ float red2[4][2 * kWave];
+                b2_item_h2<T>(uni(c.x), uni(c.y), wave, lane, red2, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs,
+                              yleaf, scale, n_il);
+            } else {
+                b2_item<T, A, kHalf>(uni(c.x), uni(c.y), wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool,
+                                     xs, yleaf, scale, n_il);
+            }
         }
     }
 }
@@ -505,9 +710,11 @@ void ensure_workspace(Handle& H, int nrhs)
     H.tpool.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
     H.ppool.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     if (H.prec_mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16))) {
-        H.xs32.alloc((size_t)n * nrhs);
+        // the half phase-B1 form reads one x or t value past a block (and
+        // drops it): slack after the last one
+        H.xs32.alloc((size_t)n * nrhs + kHalfSlack);
         H.ypart32.alloc((size_t)2 * n * nrhs);
-        H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
+        H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs + kHalfSlack);
         H.ppool32.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     }
     H.ws_nrhs = nrhs;

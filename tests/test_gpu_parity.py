@@ -75,21 +75,36 @@ def test_structure_bit_exact(orc, tmp_path, case):
     _compare_structure(F, O)
 
 
+U16 = 2.0 ** -11   # unit roundoff of FP16
+UBF = 2.0 ** -8    # unit roundoff of BF16
+
+
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_matvec_on_oracle_factors(orc, tmp_path, case):
-    """Identical H on both sides: only the summation order differs."""
+    """Identical H on both sides: only the summation order differs in FP64.
+    The FP16 / BF16 pools made from the same factors (values rounded to the
+    half format, FP32 accumulation): every row within 4 u of
+    sum_j |A_ij x_j|.  Odd box sizes, odd ranks and leaves above 64 points
+    in these cases exercise the half kernels' paired loads, whose value past
+    a block's end is read and dropped."""
     name, xy, k, leaf, tol = case
     say("import-matvec", name)
     O = orc.OracleH(xy, k, leaf, tol)
     p = tmp_path / "o.h2dx"
     O.export(p)
-    H = _lib().HODLR2D.import_file(p)
+    H = _lib().HODLR2D.import_file(p, precs=("fp16", "bf16"))
     rng = np.random.default_rng(7)
     x = rng.uniform(-1, 1, xy.shape[0])
     yo = O.matvec(x)
     yg = host(H.matvec(dev(x)))
     assert np.linalg.norm(yg - yo) <= 1e-12 * np.linalg.norm(yo)
     assert np.max(np.abs(yg - yo)) <= 1e-12 * np.max(np.abs(yo))
+    absrow = np.abs(npref.kernel_matrix(k, xy)) @ np.abs(x)
+    for prec, u in (("fp16", U16), ("bf16", UBF)):
+        yh = host(H.matvec(dev(x), prec=prec))
+        err = np.abs(yh - yo) / absrow
+        say(prec, "max row error / sum|A x|", err.max())
+        assert np.all(np.isfinite(yh)) and err.max() <= 4 * u, prec
 
 
 @pytest.mark.parametrize("case", CASES[:3] + CASES[5:], ids=[c[0] for c in CASES[:3] + CASES[5:]])
