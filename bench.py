@@ -78,6 +78,25 @@ def cpu_baseline(n_sample: int = 65536, min_seconds: float = 5.0):
             "ms_per_matvec": per * 1e3}
 
 
+def read_ceiling(torch, reps: int = 5) -> float:
+    """GB/s of a plain streaming read on this GPU, measured live: torch's
+    sum over 4 GiB of float64 (context for `frac`: the fraction of the 8 TB/s
+    peak that a library reduction reaches here)."""
+    t = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    t.sum()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        t.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del t
+    return (1 << 29) * 8 / (ms * 1e-3) / 1e9
+
+
 def kernel_traffic(kernel: str):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
     on a known-size elementwise kernel) from the committed counter summary,
@@ -351,10 +370,13 @@ def main():
     # dominant kernel's roofline
     dom = max(prof["ms"], key=lambda k: prof["ms"][k])
     achieved = prof["bytes"][dom] / (prof["ms"][dom] * 1e-3) / 1e9
+    ceiling = read_ceiling(torch)
+    log(f"streaming-read ceiling (torch.sum over 4 GiB float64): {ceiling:.0f} GB/s")
     roofline = {"bound": "hbm", "kernel": f"k_{dom}",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": kernel_traffic(f"k_{dom}"), "alg_bytes_per_launch": prof["bytes"][dom],
                 "avg_ms": prof["ms"][dom],
+                "read_ceiling_GBs": ceiling, "frac_of_read_ceiling": achieved / ceiling,
                 "phases_ms": prof["ms"], "phases_alg_bytes": prof["bytes"]}
     extra = {"build_seconds": t_build, "kappa": info["kappa"], "n_il_blocks": info["n_il"],
              "n_il_dense": info["n_il_dense"], "max_rank": info["max_rank"],

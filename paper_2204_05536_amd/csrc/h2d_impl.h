@@ -206,6 +206,8 @@ struct Handle {
     int64_t n_b1 = 0;
     DBuf<int2> b1s_items;       // single-RHS phase-B1 work: (box, first row of a b1_rows-row slice)
     int64_t n_b1s = 0;
+    DBuf<int4> b1h_items;       // half-precision phase-B1 work: (first box, first row quad, row quads, 0)
+    int64_t n_b1h = 0;
     int32_t b1_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
     DBuf<int2> b2items;         // single-RHS phase-B2 work: (leaf box, first row of a 64-row chunk)
     int64_t n_b2 = 0;

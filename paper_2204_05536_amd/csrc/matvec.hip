@@ -87,6 +87,25 @@ template <> __device__ __forceinline__ float2 ld2<__hip_bfloat16>(const __hip_bf
     const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const u32_a2*>(p));
     return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
 }
+// Four consecutive half values from one 8-byte load (same alignment rule).
+typedef uint64_t u64_a2 __attribute__((aligned(2)));
+template <typename T> __device__ __forceinline__ float4 ld4(const T* p);
+template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p)
+{
+    const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const u64_a2*>(p));
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    return make_float4(__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
+                       __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(hi >> 16))));
+}
+template <> __device__ __forceinline__ float4 ld4<__hip_bfloat16>(const __hip_bfloat16* p)
+{
+    const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const u64_a2*>(p));
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    return make_float4(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
+                       __uint_as_float(hi & 0xffff0000u));
+}
 
 template <typename A>
 __global__ void k_gather(const double* x, const int32_t* perm, int32_t n, int64_t ldx, int64_t ldxs, int nrhs, A* xs)
@@ -293,63 +312,100 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
     }
 }
 
-// Phase B1 for the half pools, slices of 64 rows: lane (g, rp) takes rows
-// 2 rp, 2 rp + 1 (one 4-byte load) of the columns of parity g, so a wave
-// load covers two columns.  Both columns' t (or x) values are read through
-// the scalar cache and each lane picks its own; an odd last column leaves
-// the g = 1 lanes re-reading the previous column with a zero multiplier.
-// The two parities are added with one cross-lane exchange.
+// Phase B1 for the half pools.  One wave per run of up to 64 row quads of
+// sibling boxes one level above the leaves (boxes with the same parent, in
+// tree order; a box's rows are grouped in fours from its first row).  Lane
+// l takes rows 4 u .. 4 u + 3 of its box (one 8-byte load per column; the
+// values past the box's last row are dropped), so every wave load covers
+// 256 rows of one column -- 512 bytes, as a wave load of the FP64 form --
+// and the column's t (or x) value is one scalar load for the whole wave.
+// The ancestors above the siblings are shared: their blocks are walked
+// once for all the wave's rows, each lane at its own box's tile of U (or
+// rows of D).  The siblings' own blocks are walked box by box with that
+// box's lanes only.  Every lane owns its rows: no cross-lane sum.
 template <typename T>
 __device__ __forceinline__ void
-b1_item_h2(int32_t it, int lane, const int2* __restrict__ items, int tl, const LevelPtrs& L,
+b1_item_h4(int32_t it, int lane, const int4* __restrict__ items, int tl, const LevelPtrs& L,
            const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
            const float* __restrict__ tpool, const float* __restrict__ xs, float* __restrict__ ypart,
            const float* __restrict__ scale)
 {
     using cA = ConstAS<float>;
-    const int2 w = items[it];
-    const int32_t P = uni(w.x), rc = uni(w.y);
-    const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
-    const int32_t rows = min(kWave, cnt - rc);
-    const int g = lane >> 5, rp = lane & 31;
-    const bool act = 2 * rp < rows;
-    float a0 = 0.f, a1 = 0.f;
-    int32_t a_box = P;
-    for (int l = tl; l >= 1; --l) {
+    const int4 w = items[it];
+    const int32_t P0 = uni(w.x), u0 = uni(w.y), nu = uni(w.z);
+    const bool act = lane < nu;
+    int32_t P = P0, u = u0 + lane;
+    if (act) {
+        for (;;) {
+            const int32_t nq = (L.count[tl][P] + 3) >> 2;
+            if (u < nq) break;
+            u -= nq;
+            ++P;
+        }
+    }
+    const int32_t p0 = act ? L.begin[tl][P] : 0, cnt = act ? L.count[tl][P] : 0, r = 4 * u;
+    const int32_t Plast = __builtin_amdgcn_readlane(P, nu - 1);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto column_sweep = [&](const T* base, int64_t stride, const cA* tv, int32_t nc, float4& b) {
+#pragma unroll 8
+        for (int32_t c = 0; c < nc; ++c) {
+            const float4 v = ld4<T>(base + (int64_t)c * stride);
+            const float t = tv[c];
+            b.x += v.x * t;
+            b.y += v.y * t;
+            b.z += v.z * t;
+            b.w += v.w * t;
+        }
+    };
+    auto add_scaled = [&](const float4& b, float sc) {
+        a.x += b.x * sc;
+        a.y += b.y * sc;
+        a.z += b.z * sc;
+        a.w += b.w * sc;
+    };
+    // the siblings' own interaction lists (target = the box itself)
+    for (int32_t B = P0; B <= Plast; ++B) {
+        const int32_t cB = uni(L.count[tl][B]);
+        const int32_t q0 = uni(L.il_ptr[tl][B]), q1 = uni(L.il_ptr[tl][B + 1]);
+        if (!(act && P == B)) continue;
+        for (int32_t q = q0; q < q1; ++q) {
+            const BDesc d = uni(bil[q]);
+            if (d.cols > 0) {
+                column_sweep(Up + d.off + r, cB, (const cA*)(tpool + d.tsrc), d.cols, a);
+            } else if (d.cols < 0) {
+                float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+                column_sweep(Dp + d.off + r, cB, (const cA*)(xs + d.tsrc), -d.cols, b);
+                add_scaled(b, scale[q]);
+            }
+        }
+    }
+    // the shared ancestors
+    int32_t a_box = uni(L.parent[tl][P0]);
+    for (int l = tl - 1; l >= 1; --l) {
         const int32_t ab = uni(L.begin[l][a_box]), ld_m = uni(L.count[l][a_box]);
         const int32_t q0 = uni(L.il_ptr[l][a_box]), q1 = uni(L.il_ptr[l][a_box + 1]);
         for (int32_t q = q0; q < q1; ++q) {
             const BDesc d = uni(bil[q]);
-            const bool lowrank = d.cols > 0;
-            const int32_t nc = lowrank ? d.cols : -d.cols;
-            if (nc == 0) continue;
-            // low rank: this box's tile of U (cnt x k, column-major); dense:
-            // this box's rows of the ancestor's block (leading dimension ld_m)
-            const T* base = lowrank ? Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + 2 * rp
-                                    : Dp + d.off + (p0 - ab) + rc + 2 * rp;
-            const int64_t ld = lowrank ? cnt : ld_m;
-            const cA* tv = (const cA*)(lowrank ? tpool + d.tsrc : xs + d.tsrc);
-            float b0 = 0.f, b1 = 0.f;
-            if (act) {
-#pragma unroll 8
-                for (int32_t c = 0; c < nc; c += 2) {
-                    const float t0 = tv[c], t1r = tv[c + 1];
-                    const float t = g ? (c + 1 < nc ? t1r : 0.f) : t0;
-                    const float2 v = ld2<T>(base + (int64_t)min(c + g, nc - 1) * ld);
-                    b0 += v.x * t;
-                    b1 += v.y * t;
-                }
+            if (!act) continue;
+            if (d.cols > 0) {
+                // U is tiled by the boxes one level above the leaves: this
+                // lane's box has a cnt x k column-major tile
+                column_sweep(Up + d.off + (int64_t)d.cols * (p0 - ab) + r, cnt, (const cA*)(tpool + d.tsrc), d.cols,
+                             a);
+            } else if (d.cols < 0) {
+                float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+                column_sweep(Dp + d.off + (p0 - ab) + r, ld_m, (const cA*)(xs + d.tsrc), -d.cols, b);
+                add_scaled(b, scale[q]);
             }
-            const float sc = lowrank ? 1.f : scale[q];
-            a0 += b0 * sc;
-            a1 += b1 * sc;
         }
         a_box = uni(L.parent[l][a_box]);
     }
-    const float s0 = a0 + __shfl_xor(a0, 32, kWave), s1 = a1 + __shfl_xor(a1, 32, kWave);
-    if (g == 0 && act) {
-        ypart[p0 + rc + 2 * rp] = s0;
-        if (2 * rp + 1 < rows) ypart[p0 + rc + 2 * rp + 1] = s1;
+    if (act) {
+        float* yo = ypart + p0 + r;
+        yo[0] = a.x;
+        if (r + 1 < cnt) yo[1] = a.y;
+        if (r + 2 < cnt) yo[2] = a.z;
+        if (r + 3 < cnt) yo[3] = a.w;
     }
 }
 
@@ -527,7 +583,7 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
          const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
          const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
          A* __restrict__ ypart, A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il,
-         const int2* __restrict__ b2items, int32_t nb2items)
+         const int2* __restrict__ b2items, int32_t nb2items, const int4* __restrict__ h_items)
 {
     __shared__ A red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -536,7 +592,7 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
         const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
         if (it < nitems) {
             if constexpr (kHalf && S == kWave)
-                b1_item_h2<T>(it, lane, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
+                b1_item_h4<T>(it, lane, h_items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
             else
                 b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
         }
@@ -665,10 +721,35 @@ void finalize(Handle& H, hipStream_t s)
         for (int32_t rc = 0; rc < LL.h_count[x]; rc += kWave) b2.push_back(make_int2((int32_t)x, rc));
     H.n_b2 = (int64_t)b2.size();
     upload_vec(H.b2items, b2, s);
+    // half-precision phase-B1 work: runs of up to 64 row quads over the
+    // boxes one level above the leaves that share a parent
+    std::vector<int4> b1h;
+    if (kappa >= 2) {
+        const Level& T = H.lev[kappa - 1];
+        for (int64_t p = 0; p < T.nbox;) {
+            int64_t q = p;
+            while (q < T.nbox && T.h_parent[q] == T.h_parent[p]) ++q;
+            int32_t used = 0, s_box = 0, s_u = 0;
+            for (int64_t bx = p; bx < q; ++bx) {
+                const int32_t nq = (T.h_count[bx] + 3) / 4;
+                for (int32_t u = 0; u < nq;) {
+                    if (used == 0) { s_box = (int32_t)bx; s_u = u; }
+                    const int32_t take = std::min(nq - u, kWave - used);
+                    used += take;
+                    u += take;
+                    if (used == kWave) { b1h.push_back(make_int4(s_box, s_u, used, 0)); used = 0; }
+                }
+            }
+            if (used) b1h.push_back(make_int4(s_box, s_u, used, 0));
+            p = q;
+        }
+    }
     H.n_b1 = (int64_t)b1.size();
     H.n_b1s = (int64_t)b1s.size();
+    H.n_b1h = (int64_t)b1h.size();
     upload_vec(H.b1items, b1, s);
     upload_vec(H.b1s_items, b1s, s);
+    upload_vec(H.b1h_items, b1h, s);
     H.flops = flops;
     H.t_elems = toff; H.p_elems = poff;
     // algorithmic bytes per kernel: every stored value and vector touched once
@@ -763,13 +844,16 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
     if (ev) HIPCK(hipEventRecord(ev[3], s));
     const LevelPtrs LP = level_ptrs(H);
-    const int32_t nb1 = (int32_t)((H.n_b1s + 3) / 4), nb2 = (int32_t)((H.n_b2 + 3) / 4);
-    const int32_t ni = (int32_t)H.n_b1s;
+    // the half pools' 64-row form walks runs of row quads (b1h_items)
+    const bool quads = kHalf && H.b1_rows == kWave;
+    const int32_t ni = (int32_t)(quads ? H.n_b1h : H.n_b1s);
+    const int32_t nb1 = (ni + 3) / 4, nb2 = (int32_t)((H.n_b2 + 3) / 4);
     A* yl = yp + n;   // the work vector holds ypart then yleaf
 #define H2D_PHASE_B(SR)                                                                                              \
     k_phaseB<T, A, kHalf, SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, \
                                                                    H.bnear.p, H.bil.p, U, D, tp, xs, yp, yl,         \
-                                                                   H.scale16.p, H.n_il, H.b2items.p, (int32_t)H.n_b2)
+                                                                   H.scale16.p, H.n_il, H.b2items.p, (int32_t)H.n_b2, \
+                                                                   H.b1h_items.p)
     if (H.b1_rows == 16) H2D_PHASE_B(16);
     else if (H.b1_rows == 32) H2D_PHASE_B(32);
     else H2D_PHASE_B(64);
