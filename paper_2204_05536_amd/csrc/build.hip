@@ -995,7 +995,12 @@ __global__ void k_half_blocks(const HalfJob* jobs, const double* src, T* dst, fl
     mx = lv[0];
     int ex = 0;
     if (mx > 0.0) frexp(mx, &ex);
-    const double sc = ldexp(1.0, ex);     // mx / sc in [0.5, 1)
+    // mx / sc in [0.5, 1).  The scale is stored in FP32: below its smallest
+    // subnormal 2^-149 the block's values are not representable in any
+    // form here and are stored as zeros (a block whose largest entry is a
+    // subnormal double would otherwise give inv = inf and 0 * inf = NaN)
+    ex = max(ex, -149);
+    const double sc = ldexp(1.0, ex);
     const double inv = 1.0 / sc;
     if (threadIdx.x == 0) scale[blockIdx.x] = (float)sc;
     for (int64_t e = threadIdx.x; e < J.cnt; e += blockDim.x) {

@@ -42,6 +42,10 @@ def _cases():
     c.append(("boundaries", np.concatenate([g, rng.uniform(-1, 1, (300, 2))]), MQ, 4, 1e-10))
     c.append(("cheb_40x40_leaf25", inputs.chebyshev_grid(40), {"kind": "invr", "diag_mode": "replace",
                                                                   "diag_value": 0.0}, 25, 1e-12))
+    # a Gaussian so narrow that K underflows to exactly 0 beyond r = 0.14:
+    # blocks with zero rows before the first cross and after the last one
+    c.append(("gauss_c0.005_unif4000_leaf16", rng.uniform(-1, 1, (4000, 2)),
+              {"kind": "gauss", "c": 0.005, "diag_mode": "add", "diag_value": 0.3}, 16, 1e-10))
     return c
 
 
