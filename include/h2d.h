@@ -273,7 +273,9 @@ h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
 typedef enum {
     H2D_TILE_A_ROWS = 0,   /* V rows per single-RHS phase-A item: 16..512 (default 512) */
     H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS phase-A item: 16..512, multiple of 16 (default 256) */
-    H2D_TILE_B1_ROWS = 2   /* rows per single-RHS phase-B1 item: 16, 32 or 64 (default 64) */
+    H2D_TILE_B1_ROWS = 2   /* rows per single-RHS phase-B1 item: 16, 32 or 64 (default 64); with
+                              64 the FP16/BF16 products take runs of up to 256 rows of sibling
+                              boxes instead (four rows per lane) */
 } h2d_tile;
 
 /* Tile tuning: times 5 FP64 products with nrhs right-hand sides for each
