@@ -257,6 +257,83 @@ def paper_shaped(reps=20):
     return r
 
 
+def dense_rbf_product(kind, a, beta, xy, lam, rows=1024):
+    """f = A lam with A the dense RBF matrix of the paper's Section 5.2
+    (phi_1 or phi_2 off the diagonal, beta on it), evaluated entry by entry
+    in FP64 on the GPU with plain torch operations, a block of rows at a
+    time.  This is how the paper makes its right-hand side (an explicit
+    product); it is input preparation, not part of the timed solve."""
+    import math
+
+    import torch
+
+    n = xy.shape[0]
+    f = torch.empty(n, dtype=torch.float64, device=xy.device)
+    la = math.log(a)
+    for r0 in range(0, n, rows):
+        nr = min(rows, n - r0)
+        # r = sqrt(dx^2 + dy^2) written out (torch.cdist returned NaNs at
+        # N = 250 000 on this stack)
+        dx = xy[r0:r0 + nr, 0:1] - xy[None, :, 0]
+        dy = xy[r0:r0 + nr, 1:2] - xy[None, :, 1]
+        r = torch.sqrt(dx * dx + dy * dy)
+        del dx, dy
+        if kind == "phi1":
+            K = torch.where(r >= a, torch.log(r) / la, (r * torch.log(r) - 1.0) / (a * la - 1.0))
+        else:
+            K = torch.where(r >= a, a / r, r / a)
+        K[torch.arange(nr, device=xy.device), torch.arange(r0, r0 + nr, device=xy.device)] = beta
+        f[r0:r0 + nr] = K @ lam
+        del r, K
+    return f
+
+
+def paper_rbf(m=500):
+    """The paper's RBF interpolation solve (Section 5.2) at its largest
+    size: an m x m first-kind Chebyshev grid (N = 250 000 for m = 500),
+    phi_1 and phi_2 with a = 0.001, beta = N on the diagonal, ACA tolerance
+    1e-12, leaves of at most 500 points; a random lam gives f = A lam by an
+    explicit dense product, GMRES(50) solves to a relative residual of
+    1e-10, and the error is |lam - lam_hat| / |lam|.  The paper's serial
+    figures (one laptop core) are quoted as context: r_m, T_I, CR, T_G."""
+    import numpy as np
+    import torch
+
+    from paper_2204_05536_amd import hodlr2d, inputs
+
+    paper = {"phi1": {"r_m": 59, "T_I_s": 105.4, "CR": 0.013, "T_G_s": 12.2752},
+             "phi2": {"r_m": 118, "T_I_s": 147.6, "CR": 0.021, "T_G_s": 8.93127}}
+    xy = inputs.chebyshev_grid(m)
+    n = xy.shape[0]
+    xy_d = torch.from_numpy(xy).cuda()
+    lam = torch.from_numpy(np.random.default_rng(12).uniform(-1, 1, n)).cuda()
+    out = {"n": n}
+    for kind in ("phi1", "phi2"):
+        spec = {"kind": kind, "c": 1e-3, "diag_mode": "replace", "diag_value": float(n)}
+        t0 = time.perf_counter()
+        f = dense_rbf_product(kind, 1e-3, float(n), xy_d, lam)
+        torch.cuda.synchronize()
+        t_rhs = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        H = hodlr2d.HODLR2D.build(xy_d, spec, 500, 1e-12)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        info = H.info()
+        H.solve(f, tol=1e-10, restart=50)   # warm-up: work space, caches
+        lam_hat, si = H.solve(f, tol=1e-10, restart=50)
+        err = float(torch.linalg.norm(lam_hat - lam) / torch.linalg.norm(lam))
+        stored = info["u_elems"] + info["v_elems"] + info["d_elems"]
+        out[kind] = {"kappa": info["kappa"], "r_m": info["max_rank"], "T_I_s": t_build,
+                     "CR": stored / float(n) ** 2, "T_G_s": si["seconds"], "iters": si["iters"],
+                     "relres": si["relres"], "converged": si["converged"], "rel_err_lambda": err,
+                     "rhs_dense_seconds": t_rhs, "paper_serial": paper[kind]}
+        log(f"paper RBF {kind} N={n}: build {t_build:.2f} s, r_m {info['max_rank']}, CR {stored / n ** 2:.4f}, "
+            f"GMRES {si['iters']} its {si['seconds'] * 1e3:.1f} ms, |lam - lam_hat|/|lam| {err:.2e}")
+        H.close()
+        del f
+    return out
+
+
 def precond_local_gauss(n=1 << 16):
     """Where a leaf preconditioner matters: Gaussian RBF c = 0.02 + 0.3 I on
     N = 2^16 uniform points (leaf boxes comparable to c).  Plain GMRES,
@@ -452,6 +529,7 @@ def main():
         extra["precond_local_gauss"] = precond_local_gauss()
     if not args.no_paper:
         extra["paper_shaped"] = paper_shaped()
+        extra["paper_rbf"] = paper_rbf()
     if not args.no_batch:
         torch.cuda.empty_cache()
         extra["batched"] = batched(args.batch_count)

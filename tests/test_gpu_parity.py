@@ -42,6 +42,10 @@ def _cases():
     c.append(("boundaries", np.concatenate([g, rng.uniform(-1, 1, (300, 2))]), MQ, 4, 1e-10))
     c.append(("cheb_40x40_leaf25", inputs.chebyshev_grid(40), {"kind": "invr", "diag_mode": "replace",
                                                                   "diag_value": 0.0}, 25, 1e-12))
+    # the paper's RBF kernels (Section 5.2): a = 0.001, beta = N on the diagonal
+    for kind in ("phi1", "phi2"):
+        c.append((f"cheb_30x30_{kind}_leaf25", inputs.chebyshev_grid(30),
+                  {"kind": kind, "c": 1e-3, "diag_mode": "replace", "diag_value": 900.0}, 25, 1e-12))
     # a Gaussian so narrow that K underflows to exactly 0 beyond r = 0.14:
     # blocks with zero rows before the first cross and after the last one
     c.append(("gauss_c0.005_unif4000_leaf16", rng.uniform(-1, 1, (4000, 2)),
