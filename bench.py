@@ -24,6 +24,7 @@ bounded sample of the same recipe.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -527,12 +528,19 @@ def main():
         del H2
         torch.cuda.synchronize()
         extra["precond_local_gauss"] = precond_local_gauss()
+    if not args.no_batch:
+        # the batch's factors nearly fill the HBM: release every tensor of
+        # the legs above and torch's cached blocks first
+        del x, y
+        if not args.no_solve:
+            del xs, bb, xp, xr, x10, xq, d, xb, xm, xc
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        extra["batched"] = batched(args.batch_count)
     if not args.no_paper:
         extra["paper_shaped"] = paper_shaped()
         extra["paper_rbf"] = paper_rbf()
-    if not args.no_batch:
-        torch.cuda.empty_cache()
-        extra["batched"] = batched(args.batch_count)
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
