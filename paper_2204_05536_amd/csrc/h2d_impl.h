@@ -19,7 +19,7 @@ constexpr int kMaxLevel = 16;      // Morton keys are 2 x 16 bits
 constexpr int kWave = 64;
 constexpr int kAcaRankCap = 256;   // ACA scratch columns per block
 constexpr int kPhaseARows = 512;   // V rows per phase-A work item (x slice staged in LDS)
-constexpr int kHalfSlack = 16;     // zeroed elements after every half-precision pool and vector (pair loads)
+constexpr int kHalfSlack = 16;     // zeroed elements after every half-precision pool: paired loads may read 1-3 past the last block
 constexpr int kMrRowsMax = 512;    // multi-RHS phase-A source chunk: 512 rows x 16 x 8 bytes = 64 KiB of LDS
 
 // Error carried from deep inside the library to the C ABI.

@@ -6,7 +6,8 @@
 //   phase B:  for every row of a leaf box X, the sum over the blocks of the
 //             ancestors of X of U_b(rows) t_b (or D_b(rows) xs(Y_b) for dense
 //             blocks) -- the "B1" half, per slice of a box one level above
-//             the leaves -- and, in the same launch, the sum over X's dense
+//             the leaves (half pools: per run of sibling boxes at that
+//             level) -- and, in the same launch, the sum over X's dense
 //             near blocks and X's own blocks -- the "B2" half, per leaf
 //             chunk; the two sums go to separate arrays
 //   combine:  y = the two sums (+ the FP32 diagonal term of the half
@@ -573,8 +574,10 @@ __device__ __forceinline__ int32_t xcd_sub(int32_t w, int32_t w0, int32_t n)
 }
 
 // Phase B, both halves in one launch: the first nb1 workgroups do phase-B1
-// slices (ancestor levels, into ypart), the next nb2 do phase-B2 leaf boxes
-// (leaf level and near field, into yleaf).  The two halves write different
+// items (ancestor levels, into ypart: slices of a box one level above the
+// leaves, or for the half pools' 64-row form runs of sibling boxes from
+// h_items), the next nb2 do phase-B2 leaf chunks (leaf level and near
+// field, into yleaf).  The two halves write different
 // arrays and do not depend on each other; the latency-bound leaf work is
 // dispatched as the ancestor work drains, filling its tail.
 template <typename T, typename A, bool kHalf, int S>
@@ -791,11 +794,9 @@ void ensure_workspace(Handle& H, int nrhs)
     H.tpool.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
     H.ppool.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     if (H.prec_mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16))) {
-        // the half phase-B1 form reads one x or t value past a block (and
-        // drops it): slack after the last one
-        H.xs32.alloc((size_t)n * nrhs + kHalfSlack);
+        H.xs32.alloc((size_t)n * nrhs);
         H.ypart32.alloc((size_t)2 * n * nrhs);
-        H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs + kHalfSlack);
+        H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
         H.ppool32.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     }
     H.ws_nrhs = nrhs;
