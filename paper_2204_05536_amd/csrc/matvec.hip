@@ -128,6 +128,10 @@ __device__ __forceinline__ int64_t uni(int64_t v)
 }
 __device__ __forceinline__ BDesc uni(const BDesc& d) { return BDesc{uni(d.off), uni(d.cols), uni(d.tsrc)}; }
 
+// Multiplier values (t, or x of a source box) of one block staged in a
+// wave's LDS slice at a time, where lanes take different columns.
+constexpr int kB2Stage = 256;
+
 // Workgroup w -> tile index such that each XCD (workgroups are dealt
 // round-robin over the 8 XCDs) walks one contiguous range of tiles, so
 // neighbouring tiles, which share cache lines, share an L2.
@@ -326,10 +330,10 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
 // box's lanes only.  Every lane owns its rows: no cross-lane sum.
 template <typename T>
 __device__ __forceinline__ void
-b1_item_h4(int32_t it, int lane, const int4* __restrict__ items, int tl, const LevelPtrs& L,
-           const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
-           const float* __restrict__ tpool, const float* __restrict__ xs, float* __restrict__ ypart,
-           const float* __restrict__ scale)
+b1_item_h4(int32_t it, int lane, float* tst, float4* red4, const int4* __restrict__ items, int tl,
+           const LevelPtrs& L, const BDesc* __restrict__ bil, const T* __restrict__ Up,
+           const T* __restrict__ Dp, const float* __restrict__ tpool, const float* __restrict__ xs,
+           float* __restrict__ ypart, const float* __restrict__ scale)
 {
     using cA = ConstAS<float>;
     const int4 w = items[it];
@@ -364,21 +368,63 @@ b1_item_h4(int32_t it, int lane, const int4* __restrict__ items, int tl, const L
         a.z += b.z * sc;
         a.w += b.w * sc;
     };
-    // the siblings' own interaction lists (target = the box itself)
+    // the siblings' own interaction lists (target = the box itself), box by
+    // box with all 64 lanes: the nb lanes of box B own its quads, and every
+    // lane (cg, j) takes quad j of them and the columns cg, cg + G, ...
+    // (G = 64 / nb), with the block's multiplier values staged in LDS; the
+    // G column-group sums of each quad are added into its owner in order
     for (int32_t B = P0; B <= Plast; ++B) {
         const int32_t cB = uni(L.count[tl][B]);
         const int32_t q0 = uni(L.il_ptr[tl][B]), q1 = uni(L.il_ptr[tl][B + 1]);
-        if (!(act && P == B)) continue;
+        const uint64_t own = __ballot(act && P == B);
+        const int32_t lb = __ffsll((long long)own) - 1, nb = __popcll(own);
+        const int32_t rb = 4 * __builtin_amdgcn_readlane(u, lb);
+        const int G = kWave / nb, cg = lane / nb, j = lane % nb;
+        const bool on = cg < G;
+        const int32_t rj = rb + 4 * j;
+        float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
         for (int32_t q = q0; q < q1; ++q) {
             const BDesc d = uni(bil[q]);
-            if (d.cols > 0) {
-                column_sweep(Up + d.off + r, cB, (const cA*)(tpool + d.tsrc), d.cols, a);
-            } else if (d.cols < 0) {
-                float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
-                column_sweep(Dp + d.off + r, cB, (const cA*)(xs + d.tsrc), -d.cols, b);
-                add_scaled(b, scale[q]);
+            if (d.cols == 0) continue;
+            const bool lowrank = d.cols > 0;
+            const int32_t nc = lowrank ? d.cols : -d.cols;
+            const T* base = (lowrank ? Up : Dp) + d.off + rj;
+            const float* tv = lowrank ? tpool + d.tsrc : xs + d.tsrc;
+            float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int32_t c0 = 0; c0 < nc; c0 += kB2Stage) {
+                const int32_t m = min(kB2Stage, nc - c0);
+                for (int32_t jj = lane; jj < m; jj += kWave) tst[jj] = tv[c0 + jj];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                if (on) {
+#pragma unroll 4
+                    for (int32_t c = cg; c < m; c += G) {
+                        const float4 v = ld4<T>(base + (int64_t)(c0 + c) * cB);
+                        const float t = tst[c];
+                        e.x += v.x * t;
+                        e.y += v.y * t;
+                        e.z += v.z * t;
+                        e.w += v.w * t;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
             }
+            const float sc = lowrank ? 1.f : scale[q];
+            b.x += e.x * sc;
+            b.y += e.y * sc;
+            b.z += e.z * sc;
+            b.w += e.w * sc;
         }
+        red4[lane] = on ? b : make_float4(0.f, 0.f, 0.f, 0.f);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (act && P == B) {
+            const int jo = lane - lb;
+            for (int gg = 0; gg < G; ++gg) add_scaled(red4[gg * nb + jo], 1.f);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
     // the shared ancestors
     int32_t a_box = uni(L.parent[tl][P0]);
@@ -418,7 +464,7 @@ b1_item_h4(int32_t it, int lane, const int4* __restrict__ items, int tl, const L
 // a load covers G consecutive columns of the column-major block.
 template <typename T, typename A, bool kHalf>
 __device__ __forceinline__ void
-b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], int kappa, const LevelPtrs& L,
+b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], A* tst, int kappa, const LevelPtrs& L,
         const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
         const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
         A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
@@ -426,55 +472,55 @@ b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], int kappa, c
     const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
     const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
     const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
-    {
-        const int32_t rows = min(kWave, cnt - rc);
-        const int G = kWave / rows, g = lane / rows, r = lane % rows;
-        const bool act = g < G;
-        A acc = (A)0;
-        for (int32_t q = n0; q < n1; ++q) {
-            const BDesc d = uni(bnear[q]);
-            const T* base = Dp + d.off + rc + r;
-            const A* tv = xs + d.tsrc;
-            A a = (A)0;
+    const int32_t rows = min(kWave, cnt - rc);
+    const int G = kWave / rows, g = lane / rows, r = lane % rows;
+    const bool act = g < G;
+    // one block: its multiplier values (t, or x of the source box) are
+    // staged in this wave's LDS slice, kB2Stage at a time, with one load per
+    // lane, instead of one gather load per lane and column group
+    auto sweep = [&](const T* base, const A* tv, int32_t nc) -> A {
+        A a = (A)0;
+        for (int32_t c0 = 0; c0 < nc; c0 += kB2Stage) {
+            const int32_t m = min(kB2Stage, nc - c0);
+            for (int32_t j = lane; j < m; j += kWave) tst[j] = tv[c0 + j];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
             if (act) {
 #pragma unroll 4
-                for (int32_t j = g; j < -d.cols; j += G) a += ldv<T, A>(base + (int64_t)j * cnt) * tv[j];
+                for (int32_t c = g; c < m; c += G) a += ldv<T, A>(base + (int64_t)(c0 + c) * cnt) * tst[c];
             }
-            if constexpr (kHalf) acc += a * (A)scale[n_il + q];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+        return a;
+    };
+    A acc = (A)0;
+    for (int32_t q = n0; q < n1; ++q) {
+        const BDesc d = uni(bnear[q]);
+        const A a = sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
+        if constexpr (kHalf) acc += a * (A)scale[n_il + q];
+        else acc += a;
+    }
+    for (int32_t q = q0; q < q1; ++q) {
+        const BDesc d = uni(bil[q]);
+        if (d.cols > 0) {
+            acc += sweep(Up + d.off + rc + r, tpool + d.tsrc, d.cols);
+        } else if (d.cols < 0) {
+            const A a = sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
+            if constexpr (kHalf) acc += a * (A)scale[q];
             else acc += a;
         }
-        for (int32_t q = q0; q < q1; ++q) {
-            const BDesc d = uni(bil[q]);
-            if (d.cols > 0) {
-                const T* base = Up + d.off + rc + r;
-                const A* tv = tpool + d.tsrc;
-                if (act) {
-#pragma unroll 4
-                    for (int32_t c = g; c < d.cols; c += G) acc += ldv<T, A>(base + (int64_t)c * cnt) * tv[c];
-                }
-            } else if (d.cols < 0) {
-                const T* base = Dp + d.off + rc + r;
-                const A* tv = xs + d.tsrc;
-                A a = (A)0;
-                if (act) {
-#pragma unroll 4
-                    for (int32_t j = g; j < -d.cols; j += G) a += ldv<T, A>(base + (int64_t)j * cnt) * tv[j];
-                }
-                if constexpr (kHalf) acc += a * (A)scale[q];
-                else acc += a;
-            }
-        }
-        red[wave][lane] = act ? acc : (A)0;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        if (lane < rows) {
-            A s = (A)0;
-            for (int gg = 0; gg < G; ++gg) s += red[wave][gg * rows + lane];
-            yleaf[r0 + rc + lane] = s;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
     }
+    red[wave][lane] = act ? acc : (A)0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rows) {
+        A s = (A)0;
+        for (int gg = 0; gg < G; ++gg) s += red[wave][gg * rows + lane];
+        yleaf[r0 + rc + lane] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Phase B2 for the half pools: lane (g, rp) takes rows 2 rp, 2 rp + 1 of
@@ -589,15 +635,19 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
          const int2* __restrict__ b2items, int32_t nb2items, const int4* __restrict__ h_items)
 {
     __shared__ A red[4][kWave];
+    __shared__ A tst[4][kB2Stage];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t w = blockIdx.x;
     if (w < nb1) {
         const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
         if (it < nitems) {
-            if constexpr (kHalf && S == kWave)
-                b1_item_h4<T>(it, lane, h_items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
-            else
+            if constexpr (kHalf && S == kWave) {
+                __shared__ float4 red4[4][kWave];
+                b1_item_h4<T>(it, lane, tst[wave], red4[wave], h_items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart,
+                              scale);
+            } else {
                 b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
+            }
         }
     } else {
         const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
@@ -608,8 +658,8 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
                 b2_item_h2<T>(uni(c.x), uni(c.y), wave, lane, red2, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs,
                               yleaf, scale, n_il);
             } else {
-                b2_item<T, A, kHalf>(uni(c.x), uni(c.y), wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool,
-                                     xs, yleaf, scale, n_il);
+                b2_item<T, A, kHalf>(uni(c.x), uni(c.y), wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up,
+                                     Dp, tpool, xs, yleaf, scale, n_il);
             }
         }
     }
