@@ -147,7 +147,8 @@ typedef struct {
 } h2d_solve_info;
 
 /* Solve A_hat x = b to relative residual rtol (GMRES as used in Section 5,
- * x0 = 0).  b, x: device FP64, n entries, caller order.  The convergence
+ * x0 = 0).  b, x: device FP64, n entries, caller order; they must not
+ * overlap (EINVAL: x is cleared before b is read).  The convergence
  * test is always the true FP64 residual.  Returns OK or ENOCONV (x then holds
  * the last iterate and info->relres its residual).  The Krylov basis and
  * work vectors (about (2 restart + 6) n doubles with a preconditioner) are
@@ -202,6 +203,9 @@ typedef struct {
     double scale;          /* fitted s (z ~ s r over the training solves) */
 } h2d_mlp_train_info;
 
+/* The network has 64 point slots per leaf: training and applying it on a
+ * handle with a leaf above 64 points fail with EUNSUPPORTED (weights can
+ * still be set on such a handle; the preconditioner then refuses to run). */
 h2d_status h2d_mlp_train(h2d_t H, const h2d_mlp_train_opts* opts, h2d_mlp_train_info* info, void* stream);
 
 /* Copy the MLP weights out (host, H2D_MLP_PARAMS floats) and/or set them
@@ -244,7 +248,11 @@ h2d_status h2d_info(h2d_t H, h2d_stats* s);
 h2d_status h2d_export(h2d_t H, const char* path, uint32_t flags);
 
 /* Read a file written by h2d_export (with factors) or by the oracle and
- * upload it: the resulting handle applies exactly the stored operator. */
+ * upload it: the resulting handle applies exactly the stored operator.
+ * The whole file is checked on the host before anything is uploaded: perm
+ * a permutation of [0, n), every level's boxes non-empty, in ascending key
+ * order, tiling [0, n) and nested in their parents, block indices, kinds,
+ * ranks and order; a file that fails any check gives EINVAL. */
 h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t* out);
 
 /* Per-kernel timing of the matvec, for roofline reporting.

@@ -208,6 +208,13 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
     F.r(xy.data(), xy.size());
     std::vector<int64_t> p64((size_t)n);
     F.r(p64.data(), p64.size());
+    {   // perm must be a permutation of [0, n): it drives every gather and scatter
+        std::vector<uint8_t> seen((size_t)n, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            if (p64[i] < 0 || p64[i] >= n || seen[p64[i]]) fail(H2D_EINVAL, "perm is not a permutation of [0, n)");
+            seen[p64[i]] = 1;
+        }
+    }
     H.h_perm.assign(p64.begin(), p64.end());
     for (int l = 0; l <= H.kappa; ++l) {
         Level& L = H.lev[l];
@@ -217,6 +224,22 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
         F.r(L.h_key.data(), L.nbox);
         std::vector<int64_t> b(L.nbox), c(L.nbox), p(L.nbox);
         F.r(b.data(), L.nbox); F.r(c.data(), L.nbox); F.r(p.data(), L.nbox);
+        // the boxes of a level tile [0, n) in key order, each non-empty, and
+        // lie inside their parent (key >> 2 is the parent's key)
+        int64_t next = 0;
+        for (int64_t x = 0; x < L.nbox; ++x) {
+            const bool key_ok = (l == 0 ? L.h_key[x] == 0 : (uint64_t)L.h_key[x] < ((uint64_t)1 << (2 * l))) &&
+                                (x == 0 || L.h_key[x] > L.h_key[x - 1]);
+            if (!key_ok || b[x] != next || c[x] < 1 || c[x] > n - next) fail(H2D_EINVAL, "bad level table");
+            next += c[x];
+            if (l > 0) {
+                const Level& P = H.lev[l - 1];
+                if (p[x] < 0 || p[x] >= P.nbox || P.h_key[p[x]] != (L.h_key[x] >> 2) || b[x] < P.h_begin[p[x]] ||
+                    b[x] + c[x] > (int64_t)P.h_begin[p[x]] + P.h_count[p[x]])
+                    fail(H2D_EINVAL, "bad parent in level table");
+            }
+        }
+        if (next != n) fail(H2D_EINVAL, "level table does not cover the points");
         L.h_begin.assign(b.begin(), b.end());
         L.h_count.assign(c.begin(), c.end());
         L.h_parent.assign(p.begin(), p.end());
@@ -308,7 +331,8 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
             run = L.h_il_ptr[L.nbox];
         }
     }
-    // device copies
+    // device copies (the file is checked in full before the first HIP call)
+    HIPCK(hipGetDevice(&H.device));
     up(H.xy, xy, s);
     std::vector<double> xyt((size_t)(2 * n));
     for (int64_t i = 0; i < n; ++i) { xyt[2 * i] = xy[2 * H.h_perm[i]]; xyt[2 * i + 1] = xy[2 * H.h_perm[i] + 1]; }
@@ -390,6 +414,10 @@ h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d
         if (!H || !b || !x || !opts) fail(H2D_EINVAL, "NULL argument");
         if (!(rtol > 0.0)) fail(H2D_EINVAL, "rtol must be > 0");
         if (opts->restart < 1 || opts->max_iter < 1) fail(H2D_EINVAL, "restart and max_iter must be >= 1");
+        {   // x is zeroed before b is read: the two must not overlap
+            const uintptr_t b0 = (uintptr_t)b, x0 = (uintptr_t)x, len = sizeof(double) * (uintptr_t)H->h.n;
+            if (b0 < x0 + len && x0 < b0 + len) fail(H2D_EINVAL, "b and x overlap");
+        }
         st = solve(H->h, b, x, rtol, *opts, info, (hipStream_t)stream);
     });
     return g != H2D_OK ? g : st;
@@ -428,7 +456,6 @@ h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t*
         auto t0 = std::chrono::steady_clock::now();
         auto up_ = std::make_unique<h2d_s>();
         Handle& H = up_->h;
-        HIPCK(hipGetDevice(&H.device));
         import_handle(H, path, s);
         finalize(H, s);
         make_half_pools(H, prec_mask, s);

@@ -401,6 +401,17 @@ static void forward_bf16(MlpState& S, int64_t nleaf, hipStream_t s)
     HIPCK(hipGetLastError());
 }
 
+// The network has 64 point slots per leaf: leaves above 64 points are
+// refused, as block-Jacobi refuses them.
+static void check_leaf_slots(const Handle& H)
+{
+    const Level& LL = H.lev[H.kappa];
+    for (int64_t x = 0; x < LL.nbox; ++x)
+        if (LL.h_count[x] > kOut)
+            fail(H2D_EUNSUPPORTED, "the MLP preconditioner needs leaves of at most 64 points (a leaf holds " +
+                                       std::to_string(LL.h_count[x]) + ")");
+}
+
 MlpState& mlp_state(Handle& H)
 {
     if (!H.mlp) H.mlp = std::make_shared<MlpState>();
@@ -411,6 +422,7 @@ void mlp_apply(Handle& H, const double* r, double* z, hipStream_t s)
 {
     MlpState& S = mlp_state(H);
     if (!S.ready) fail(H2D_EINVAL, "the MLP preconditioner was not trained (h2d_mlp_train) or loaded");
+    check_leaf_slots(H);
     const Level& LL = H.lev[H.kappa];
     const int32_t nleaf = (int32_t)LL.nbox;
     if (S.feat_cap < nleaf) {
@@ -454,6 +466,7 @@ static void ensure_weights(MlpState& S, hipStream_t s)
 
 void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info, hipStream_t s)
 {
+    check_leaf_slots(H);
     MlpState& S = mlp_state(H);
     const Level& LL = H.lev[H.kappa];
     const int32_t nleaf = (int32_t)LL.nbox;

@@ -194,3 +194,40 @@ def test_mlp_stagnation_falls_back_to_block_jacobi():
     r = host(bb - H.matvec(x))
     assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
     assert im["iters"] <= i0["iters"] + 2 * 10
+
+
+def test_mlp_refuses_leaves_above_64_points():
+    """The network has 64 point slots per leaf: on a tree with 200-point
+    leaves, training and applying it (weights set through h2d_mlp_weights)
+    fail with H2D_EUNSUPPORTED instead of leaving rows of z unwritten."""
+    h = _lib()
+    rng = np.random.default_rng(8)
+    xy = inputs.uniform_square(2000, rng)
+    H = h.HODLR2D.build(dev(xy), {"kind": "log", "diag_mode": "replace", "diag_value": 2000.0}, 200, 1e-8)
+    assert H.info()["leaf_max"] == 200
+    w = rng.normal(0, 0.05, omlp.NPARAMS).astype(np.float32)
+    H.mlp_weights(set_to=w, scale=1.0)
+    with pytest.raises(h.H2DError) as e:
+        H.precond_apply(dev(rng.uniform(-1, 1, 2000)), "mlp")
+    assert e.value.code == h.H2D_EUNSUPPORTED
+    with pytest.raises(h.H2DError) as e:
+        H.mlp_train(n_solves=2, steps=2, batch=8)
+    assert e.value.code == h.H2D_EUNSUPPORTED
+
+
+def test_solve_refuses_overlapping_b_and_x():
+    import ctypes as C
+    h = _lib()
+    xy, b, kern, leaf, tol = inputs.workload("log4096", n=500)
+    H = h.HODLR2D.build(dev(xy), kern, leaf, tol)
+    buf = dev(np.concatenate([b, b]))
+    o = h.h2d_solve_opts(h.SOLVE_PLAIN, 50, 100, 1, 1e-4, 10, 0)
+    info = h.h2d_solve_info()
+    strm = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L = h.load()
+    p = buf.data_ptr()
+    for xoff in (0, 8 * 100):   # the same buffer, and x starting inside b
+        st = L.h2d_solve(H._h, C.c_void_p(p), C.c_void_p(p + xoff), 1e-8, C.byref(o), C.byref(info), strm)
+        assert st == h.H2D_EINVAL
+    st = L.h2d_solve(H._h, C.c_void_p(p), C.c_void_p(p + 8 * 500), 1e-8, C.byref(o), C.byref(info), strm)
+    assert st == h.H2D_OK
