@@ -107,6 +107,28 @@ h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int3
 h2d_status h2d_matvec(h2d_t H, const double* x, double* y, int32_t nrhs, int64_t ld,
                       int32_t prec, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A_hat x
+ * for one right-hand side, as h2d_matvec with nrhs = 1 (same kernels, same
+ * result bit for bit), with no allocation of any kind.  Its work vectors (x
+ * in tree order, the t = V^T x values, the split-block partials, the two
+ * phase-B sums: about (3 n + sum of ranks + partials) values of 8 bytes for
+ * FP64, 4 bytes for FP16/BF16) live in a fixed device array of
+ * H2D_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.
+ *   x, y    device FP64, n entries, caller order (caller-owned)
+ *   prec    storage precision to read (must have been built)
+ * The current device must be the one H was built on.  Errors: EINVAL (NULL
+ * argument, another device, or a handle whose work vectors exceed the
+ * array: the message states the bytes needed), EUNSUPPORTED, EDEVICE.
+ * Calls share their GPU's array, and every kernel writes each work value
+ * before reading it, so nothing carries over from one call to the next;
+ * calls that overlap in time on one GPU (different streams or threads) race
+ * on the array and must be serialised by the caller.  Asynchronous on
+ * `stream`. */
+#define H2D_NOALLOC_SCRATCH_BYTES (256u << 20)
+h2d_status h2d_matvec_noalloc(h2d_t H, const double* x, double* y, int32_t prec, void* stream);
+
 /* Solver modes for h2d_solve. */
 typedef enum {
     H2D_SOLVE_PLAIN = 0,   /* restarted GMRES on the FP64 operator */

@@ -406,6 +406,16 @@ h2d_status h2d_matvec(h2d_t H, const double* x, double* y, int32_t nrhs, int64_t
     });
 }
 
+h2d_status h2d_matvec_noalloc(h2d_t H, const double* x, double* y, int32_t prec, void* stream)
+{
+    return guarded([&] {
+        if (!H || !x || !y) fail(H2D_EINVAL, "NULL argument");
+        if (prec < H2D_P_FP64 || prec > H2D_P_BF16) fail(H2D_EINVAL, "unknown precision");
+        if (!(H->h.prec_mask & H2D_PREC_BIT(prec))) fail(H2D_EUNSUPPORTED, "precision was not built for this handle");
+        launch_matvec_noalloc(H->h, x, y, prec, (hipStream_t)stream);
+    });
+}
+
 h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d_solve_opts* opts,
                      h2d_solve_info* info, void* stream)
 {

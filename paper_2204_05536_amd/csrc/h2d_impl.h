@@ -273,6 +273,9 @@ struct MRBatchPlan {
 void mr_plan(MRBatchPlan& P, Handle* const* hs, const MRIo* io, int count, hipStream_t s);
 void mr_plan_launch(const MRBatchPlan& P, int32_t r0, int32_t nr, hipStream_t s);
 void ensure_workspace(Handle& H, int nrhs);
+// Single-RHS product on the fixed per-GPU work array (no allocation).
+size_t noalloc_bytes(const Handle& H, int prec);
+void launch_matvec_noalloc(Handle& H, const double* x, double* y, int prec, hipStream_t s);
 void profile_enable(Handle& H, bool on);
 void profile_read(Handle& H, h2d_profile* out);
 

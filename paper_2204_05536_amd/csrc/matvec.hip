@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cstring>
 #include <cstdlib>
+#include <mutex>
 
 namespace h2d {
 
@@ -881,10 +882,10 @@ static hipEvent_t* prof_slot(Handle& H)
 
 template <typename T, typename A, bool kHalf>
 static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp, A* pp, A* yp, const double* x,
-                    double* y, hipStream_t s)
+                    double* y, hipStream_t s, bool may_profile = true)
 {
     const int32_t n = (int32_t)H.n;
-    hipEvent_t* ev = prof_slot(H);
+    hipEvent_t* ev = may_profile ? prof_slot(H) : nullptr;
     if (ev) HIPCK(hipEventRecord(ev[0], s));
     k_gather<A><<<(n + 255) / 256, 256, 0, s>>>(x, H.perm.p, n, 0, 0, 1, xs);
     if (ev) HIPCK(hipEventRecord(ev[1], s));
@@ -963,6 +964,80 @@ void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, 
         else
             run_one<__hip_bfloat16, float, true>(H, H.Ub16.p, H.Vb16.p, H.Db16.p, H.xs32.p, H.tpool32.p, H.ppool32.p,
                                                   H.ypart32.p, xr, yr, s);
+    }
+}
+
+// ---------------------------------------------------------------------
+// The same single-RHS product with its work vectors (x in tree order, the
+// t values, the split-block partials, the two phase-B sums) in a fixed
+// device array instead of the handle's buffers, for callers that cannot
+// allocate.  Each GPU the library runs on holds its own copy of the array
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress gives for the current device (the array's name is a
+// host-side stand-in).  Every kernel writes each work value before it is
+// read, so nothing needs clearing between calls.  Calls that overlap in
+// time on one GPU share the array and race.
+// ---------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)H2D_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array, looked up once per device.
+static char* scratch_base(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) fail(H2D_EDEVICE, "device index out of range for the fixed work space");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(H2D_EDEVICE, std::string("hipGetSymbolAddress of the fixed work space failed: ") +
+                                  hipGetErrorString(e));
+        }
+        g_scratch[dev] = p;
+    }
+    return static_cast<char*>(g_scratch[dev]);
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Work-space bytes of one product of H at storage precision prec, laid out
+// as xs (n), the two phase-B sums (2 n), t, partials: each 256-byte aligned.
+size_t noalloc_bytes(const Handle& H, int prec)
+{
+    const size_t a = prec == H2D_P_FP64 ? sizeof(double) : sizeof(float);
+    return align256(a * (size_t)H.n) + align256(a * 2 * (size_t)H.n) +
+           align256(a * (size_t)std::max<int64_t>(H.t_elems, 1)) + align256(a * (size_t)std::max<int64_t>(H.p_elems, 1));
+}
+
+void launch_matvec_noalloc(Handle& H, const double* x, double* y, int prec, hipStream_t s)
+{
+    int dev = 0;
+    HIPCK(hipGetDevice(&dev));
+    if (dev != H.device) fail(H2D_EINVAL, "the handle lives on another device than the current one");
+    const size_t need = noalloc_bytes(H, prec);
+    if (need > kScratchBytes)
+        fail(H2D_EINVAL, "this product needs " + std::to_string(need) + " bytes of work space; the fixed array holds " +
+                             std::to_string(kScratchBytes));
+    char* base = scratch_base(dev);
+    const size_t a = prec == H2D_P_FP64 ? sizeof(double) : sizeof(float);
+    const size_t o_yp = align256(a * (size_t)H.n);
+    const size_t o_tp = o_yp + align256(a * 2 * (size_t)H.n);
+    const size_t o_pp = o_tp + align256(a * (size_t)std::max<int64_t>(H.t_elems, 1));
+    if (prec == H2D_P_FP64) {
+        double* w = reinterpret_cast<double*>(base);
+        run_one<double, double, false>(H, H.U64.p, H.V64.p, H.D64.p, w, (double*)(base + o_tp), (double*)(base + o_pp),
+                                       (double*)(base + o_yp), x, y, s, false);
+    } else if (prec == H2D_P_FP16) {
+        run_one<__half, float, true>(H, H.U16.p, H.V16.p, H.D16.p, (float*)base, (float*)(base + o_tp),
+                                     (float*)(base + o_pp), (float*)(base + o_yp), x, y, s, false);
+    } else {
+        run_one<__hip_bfloat16, float, true>(H, H.Ub16.p, H.Vb16.p, H.Db16.p, (float*)base, (float*)(base + o_tp),
+                                              (float*)(base + o_pp), (float*)(base + o_yp), x, y, s, false);
     }
 }
 

@@ -25,7 +25,7 @@ PREC = {"fp64": 0, "fp16": 1, "bf16": 2}
 SOLVE_PLAIN, SOLVE_REFINE = 0, 1
 PRECOND = {"none": 0, "bj": 1, "mlp": 2}
 
-EXPORTED = ["h2d_build", "h2d_matvec", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
+EXPORTED = ["h2d_build", "h2d_matvec", "h2d_matvec_noalloc", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
             "h2d_profile_enable", "h2d_profile_read", "h2d_bj_setup", "h2d_precond_apply",
             "h2d_mlp_train", "h2d_mlp_weights", "h2d_mlp_loss_grad", "h2d_autotune", "h2d_set_item_rows", "h2d_batch_create",
             "h2d_batch_launch", "h2d_batch_destroy", "h2d_destroy", "h2d_last_error"]
@@ -94,6 +94,8 @@ def load():
     L.h2d_build.restype = C.c_int
     L.h2d_matvec.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, P]
     L.h2d_matvec.restype = C.c_int
+    L.h2d_matvec_noalloc.argtypes = [P, P, P, C.c_int32, P]
+    L.h2d_matvec_noalloc.restype = C.c_int
     L.h2d_solve.argtypes = [P, P, P, C.c_double, C.POINTER(h2d_solve_opts), C.POINTER(h2d_solve_info), P]
     L.h2d_solve.restype = C.c_int
     L.h2d_info.argtypes = [P, C.POINTER(h2d_stats)]
@@ -217,6 +219,13 @@ class HODLR2D:
         n = x.shape[-1]
         y = torch.empty_like(x) if out is None else out
         _check(load().h2d_matvec(self._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs, n, PREC[prec], _stream()))
+        return y
+
+    def matvec_noalloc(self, x, prec="fp64", out=None):
+        """y = A_hat x (one right-hand side) on the library's fixed work array."""
+        x = x.contiguous()
+        y = torch.empty_like(x) if out is None else out
+        _check(load().h2d_matvec_noalloc(self._h, _dev_f64(x, "x"), _dev_f64(y, "y"), PREC[prec], _stream()))
         return y
 
     def bj_setup(self):
