@@ -41,28 +41,73 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample: int = 65536, min_seconds: float = 5.0):
-    """The oracle (single-threaded C, FP64) on the first recipe at N=n_sample."""
+def host_cpu():
+    """Core count and model of the host this runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def _factor_bytes(O, n):
+    """Algorithmic bytes of one oracle matvec: every stored value once plus
+    the vectors (the same count the library reports for its own product)."""
+    import numpy as np
+
+    tab = O.il_table()
+    levels = [O.level(l) for l in range(O.kappa + 1)]
+    byts = 0.0
+    for l, t, s, kd, k in zip(tab["level"], tab["tgt"], tab["src"], tab["kind"], tab["rank"]):
+        m = levels[l]["count"][t]; nn = levels[l]["count"][s]
+        byts += 8.0 * (m * nn if kd == 1 else k * (m + nn))
+    LL = levels[-1]
+    nt, ns = O.near_table()
+    byts += 8.0 * float(np.sum(LL["count"][nt] * LL["count"][ns]))
+    return byts + n * (8 + 8 + 8 + 4)
+
+
+ORACLE_WORKER = r"""
+import sys, time, json
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_2204_05536_amd import inputs
+n, reps = int(sys.argv[2]), int(sys.argv[3])
+xy, b, kern, leaf, tol = inputs.workload("mq1m", n=n)
+O = oracle.OracleH(xy, kern, leaf, tol)
+print("built", flush=True)
+sys.stdin.readline()   # start together
+t0 = time.perf_counter()
+for _ in range(reps):
+    O.matvec(b)
+print(json.dumps({"per_s": (time.perf_counter() - t0) / reps}), flush=True)
+"""
+
+
+def cpu_baseline(n_sample: int = 65536, min_seconds: float = 5.0, max_procs: int = 16):
+    """The oracle (single-threaded C, FP64) on the benchmark recipe at
+    N = n_sample: one process alone, then one process per host core (at most
+    max_procs) each running the same matvecs at once (the oracle as it
+    stands, parallel across processes)."""
+    import subprocess
+
     import numpy as np
 
     import oracle
     from paper_2204_05536_amd import inputs
 
     oracle.build(force=False)
+    host = host_cpu()
     xy, b, kern, leaf, tol = inputs.workload("mq1m", n=n_sample)
     t0 = time.perf_counter()
     O = oracle.OracleH(xy, kern, leaf, tol)
     t_build = time.perf_counter() - t0
-    tab = O.il_table()
-    levels = [O.level(l) for l in range(O.kappa + 1)]
-    byts = 0.0
-    for l, t, s, kd, k in zip(tab["level"], tab["tgt"], tab["src"], tab["kind"], tab["rank"]):
-        m = levels[l]["count"][t]; n = levels[l]["count"][s]
-        byts += 8.0 * (m * n if kd == 1 else k * (m + n))
-    LL = levels[-1]
-    nt, ns = O.near_table()
-    byts += 8.0 * float(np.sum(LL["count"][nt] * LL["count"][ns]))
-    byts += n_sample * (8 + 8 + 8 + 4)
+    byts = _factor_bytes(O, n_sample)
     reps = 0
     t0 = time.perf_counter()
     while True:
@@ -72,30 +117,80 @@ def cpu_baseline(n_sample: int = 65536, min_seconds: float = 5.0):
         if el >= min_seconds and reps >= 3:
             break
     per = el / reps
-    return {"value": byts / per / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FP64 matvec on N={n_sample} points of the same recipe (uniform [-1,1]^2 seed 1, "
-                      f"MQ c=0.1 +1e-6 I, leaf 64, tol 1e-10): {reps} matvecs averaged, {per * 1e3:.1f} ms each; "
-                      f"oracle build {t_build:.1f} s excluded",
-            "ms_per_matvec": per * 1e3}
+    del O
+    # all cores: P processes, each with its own copy of the operator
+    P = max(1, min(max_procs, host["affinity"]))
+    procs = [subprocess.Popen([sys.executable, "-c", ORACLE_WORKER, ROOT, str(n_sample), "3"],
+                              stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True) for _ in range(P)]
+    try:
+        for p in procs:
+            line = p.stdout.readline().strip()
+            if line != "built":
+                raise RuntimeError(f"oracle worker did not start: {line!r}")
+        for p in procs:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        pers = [json.loads(p.stdout.readline())["per_s"] for p in procs]
+    finally:
+        for p in procs:
+            try:
+                p.wait(timeout=600)
+            except subprocess.TimeoutExpired:
+                p.kill()
+    agg = sum(byts / t for t in pers) / 1e9
+    log(f"oracle matvec N={n_sample}: 1 core {byts / per / 1e9:.2f} GB/s, {P} processes {agg:.2f} GB/s")
+    return {"value": agg, "unit": "GB/s", "cores": P, "kind": "oracle",
+            "sample": f"oracle FP64 matvec on N={n_sample} points of the benchmark recipe (uniform [-1,1]^2 seed 1, "
+                      f"MQ c=0.1 +1e-6 I, leaf 64, tol 1e-10): {P} single-threaded oracle processes at once, "
+                      f"3 matvecs each (mean {np.mean(pers) * 1e3:.0f} ms); one process alone {per * 1e3:.1f} ms "
+                      f"per matvec ({byts / per / 1e9:.2f} GB/s); oracle build {t_build:.1f} s excluded",
+            "host": host, "one_core_GBs": byts / per / 1e9, "one_core_ms_per_matvec": per * 1e3,
+            "all_cores_ms_per_matvec": [t * 1e3 for t in pers]}
 
 
-def read_ceiling(torch, reps: int = 5) -> float:
-    """GB/s of a plain streaming read on this GPU, measured live: torch's
-    sum over 4 GiB of float64 (context for `frac`: the fraction of the 8 TB/s
-    peak that a library reduction reaches here)."""
-    t = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
-    t.sum()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        t.sum()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del t
-    return (1 << 29) * 8 / (ms * 1e-3) / 1e9
+def oracle_solve_leg(n_sample: int = 65536):
+    """Time-to-1e-8 of the oracle's GMRES (one core) on the log-kernel recipe
+    at N = n_sample, beside the GPU's solves of the same operator (the
+    oracle's factors imported), and each GPU solution's error against the
+    oracle's solution taken to 1e-12."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2204_05536_amd import hodlr2d, inputs
+
+    xy, b, kern, leaf, tol = inputs.workload("log1m", n=n_sample)
+    O = oracle.OracleH(xy, kern, leaf, tol)
+    t0 = time.perf_counter()
+    x8, it8, rr8, st8 = O.gmres(b, tol=1e-8)
+    t8 = time.perf_counter() - t0
+    xo, it12, rr12, _ = O.gmres(b, tol=1e-12)
+    out = {"n": n_sample, "oracle_gmres_1e-8": {"iters": it8, "relres": rr8, "seconds": t8, "cores": 1},
+           "oracle_reference": {"tol": 1e-12, "iters": it12, "relres": rr12}}
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "o.h2dx")
+        O.export(path)
+        H = hodlr2d.HODLR2D.import_file(path, precs=("fp16", "bf16"))
+    bb = torch.from_numpy(b).cuda()
+    H.solve(bb, tol=1e-8)   # warm-up (work space)
+    H.bj_setup()
+    forms = {"plain_fp64_1e-8": dict(tol=1e-8), "plain_fp64_1e-10": dict(tol=1e-10),
+             "refine_fp16_1e-10": dict(tol=1e-10, mode="refine", inner_prec="fp16", inner_tol=1e-4),
+             "refine_bf16_1e-10": dict(tol=1e-10, mode="refine", inner_prec="bf16", inner_tol=1e-4),
+             "fgmres_bj_1e-8": dict(tol=1e-8, precond="bj")}
+    for name, kw in forms.items():
+        x, info = H.solve(bb, **kw)
+        e = x.cpu().numpy() - xo
+        out[name] = {"iters": info["iters"], "outer": info["outer"], "relres": info["relres"],
+                     "seconds": info["seconds"], "converged": info["converged"],
+                     "rel_err_vs_oracle_solve": float(np.linalg.norm(e) / np.linalg.norm(xo)),
+                     "max_err_vs_oracle_solve": float(np.max(np.abs(e)) / np.max(np.abs(xo)))}
+    H.close()
+    log(f"oracle GMRES N={n_sample} to 1e-8: {it8} its {t8:.2f} s; "
+        f"GPU plain {out['plain_fp64_1e-8']['seconds'] * 1e3:.1f} ms")
+    return out
 
 
 def kernel_traffic(kernel: str):
@@ -221,46 +316,98 @@ def batched(count, nrhs=16, reps=10):
     return r
 
 
-def paper_shaped(reps=20):
-    """The paper's serial matvec workload at its largest size: a 500 x 500
-    first-kind Chebyshev grid (N = 250 000), K = 1/r with zero diagonal,
-    tolerance 1e-12, leaf size 500.  The paper reports 1.9681 s per matvec
-    on one core of a Xeon Gold 6248 (13.52 GB of storage) and 0.051 s on 80
-    MPI processes; quoted here as context only."""
+def dense_invr_product(xy, psi, rows=1024):
+    """B = K Psi for K_ij = 1/|x_i - x_j| (K_ii = 0), the paper's Section 5.1
+    matrix, evaluated entry by entry in FP64 on the GPU with plain torch
+    operations, a block of rows at a time: the exact products the fast
+    product is measured against (not part of any timed region)."""
+    import torch
+
+    n = xy.shape[0]
+    out = torch.empty((n, psi.shape[1]), dtype=torch.float64, device=xy.device)
+    for r0 in range(0, n, rows):
+        nr = min(rows, n - r0)
+        dx = xy[r0:r0 + nr, 0:1] - xy[None, :, 0]
+        dy = xy[r0:r0 + nr, 1:2] - xy[None, :, 1]
+        K = 1.0 / torch.sqrt(dx * dx + dy * dy)
+        del dx, dy
+        K[torch.arange(nr, device=xy.device), torch.arange(r0, r0 + nr, device=xy.device)] = 0.0
+        out[r0:r0 + nr] = K @ psi
+        del K
+    return out
+
+
+# Section 5.1 serial table of the paper (one Xeon Gold 6248 core, FP64,
+# eps = 1e-12, N_max = 500): N -> (r_m, memory GB, T_I s, matvec s, eps_r)
+PAPER_1BYR = {10000: (113, 0.23, 2.4628, 0.0284, 1.5e-13), 22500: (127, 0.69, 8.02592, 0.0903, 1.75e-12),
+              40000: (138, 1.46, 19.8064, 0.1979, 7.23e-12), 62500: (145, 2.53, 31.5305, 0.3208, 5.16e-12),
+              90000: (159, 3.99, 57.6382, 0.557, 3.88e-12), 160000: (165, 7.96, 125.052, 1.2835, 2.049e-11),
+              250000: (180, 13.52, 186.154, 1.9681, 2.588e-11)}
+
+
+def paper_shaped(reps=20, n_psi=10):
+    """The paper's serial matvec workload (Section 5.1) at each of its sizes:
+    m x m first-kind Chebyshev grids, N = m^2 = 10 000 ... 250 000, K = 1/r
+    with zero diagonal, tolerance 1e-12, leaf size 500.  For each size: the
+    build time, the matvec time, the stored bytes, the largest rank, and the
+    paper's error eps_r = max over 10 random psi of max_i |b_hat - b|_i /
+    |b|_i against the exact product (entries of psi uniform in [0, 1], so
+    that b > 0 for this positive kernel and the element-wise ratio is
+    defined; the normwise max_i |b_hat - b|_i / max_i |b|_i beside it).
+    The paper's own figures for the same size are quoted as context."""
     import numpy as np
     import torch
 
     from paper_2204_05536_amd import hodlr2d, inputs
 
-    xy = inputs.chebyshev_grid(500)
-    x = torch.from_numpy(np.random.default_rng(11).uniform(-1, 1, xy.shape[0])).cuda()
     spec = {"kind": "invr", "diag_mode": "replace", "diag_value": 0.0}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    H = hodlr2d.HODLR2D.build(torch.from_numpy(xy).cuda(), spec, 500, 1e-12)
-    torch.cuda.synchronize()
-    t_build = time.perf_counter() - t0
-    info = H.info()
-    y = torch.empty_like(x)
-    for _ in range(3):
-        H.matvec(x, out=y)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        H.matvec(x, out=y)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    H.close()
-    r = {"n": int(xy.shape[0]), "kappa": info["kappa"], "max_rank": info["max_rank"], "build_seconds": t_build,
-         "ms_per_matvec": ms, "GB/s": info["alg_bytes_fp64"] / (ms * 1e-3) / 1e9,
-         "factor_GB": 8.0 * (info["u_elems"] + info["v_elems"] + info["d_elems"]) / 1e9,
-         "paper_serial_s": 1.9681, "paper_80proc_s": 0.051, "paper_storage_GB": 13.52}
-    log(f"paper-shaped N=250000 1/r Chebyshev: build {t_build:.1f} s, matvec {ms:.3f} ms, {r['GB/s']:.0f} GB/s, "
-        f"max rank {info['max_rank']}")
-    return r
+    out = {"sizes": []}
+    for m in (100, 150, 200, 250, 300, 400, 500):
+        xy = inputs.chebyshev_grid(m)
+        n = xy.shape[0]
+        xy_d = torch.from_numpy(xy).cuda()
+        psi = torch.from_numpy(np.random.default_rng(11).uniform(0, 1, (n_psi, n))).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = hodlr2d.HODLR2D.build(xy_d, spec, 500, 1e-12)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        info = H.info()
+        x = psi[0].contiguous()
+        y = torch.empty_like(x)
+        for _ in range(3):
+            H.matvec(x, out=y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            H.matvec(x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        exact = dense_invr_product(xy_d, psi.T.contiguous())
+        eps_r, eps_n = 0.0, 0.0
+        for q in range(n_psi):
+            bh = H.matvec(psi[q].contiguous())
+            d = (bh - exact[:, q]).abs()
+            eps_r = max(eps_r, float((d / exact[:, q].abs()).max()))
+            eps_n = max(eps_n, float(d.max() / exact[:, q].abs().max()))
+        H.close()
+        del exact, psi, xy_d
+        p = PAPER_1BYR[n]
+        r = {"n": n, "kappa": info["kappa"], "r_m": info["max_rank"], "build_seconds": t_build,
+             "ms_per_matvec": ms, "GB/s": info["alg_bytes_fp64"] / (ms * 1e-3) / 1e9,
+             "factor_GB": 8.0 * (info["u_elems"] + info["v_elems"] + info["d_elems"]) / 1e9,
+             "eps_r": eps_r, "eps_normwise": eps_n,
+             "paper_serial": {"r_m": p[0], "memory_GB": p[1], "T_I_s": p[2], "matvec_s": p[3], "eps_r": p[4]}}
+        out["sizes"].append(r)
+        log(f"paper 1/r N={n}: build {t_build:.2f} s, matvec {ms:.3f} ms ({r['GB/s']:.0f} GB/s), r_m {r['r_m']}, "
+            f"eps_r {eps_r:.2e} (paper {p[4]:.2e}), normwise {eps_n:.2e}")
+    last = out["sizes"][-1]
+    out.update({"n": last["n"], "ms_per_matvec": last["ms_per_matvec"], "GB/s": last["GB/s"],
+                "paper_serial_s": 1.9681, "paper_80proc_s": 0.051, "paper_storage_GB": 13.52})
+    return out
 
 
 def dense_rbf_product(kind, a, beta, xy, lam, rows=1024):
@@ -453,13 +600,10 @@ def main():
     # dominant kernel's roofline
     dom = max(prof["ms"], key=lambda k: prof["ms"][k])
     achieved = prof["bytes"][dom] / (prof["ms"][dom] * 1e-3) / 1e9
-    ceiling = read_ceiling(torch)
-    log(f"streaming-read ceiling (torch.sum over 4 GiB float64): {ceiling:.0f} GB/s")
     roofline = {"bound": "hbm", "kernel": f"k_{dom}",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": kernel_traffic(f"k_{dom}"), "alg_bytes_per_launch": prof["bytes"][dom],
                 "avg_ms": prof["ms"][dom],
-                "read_ceiling_GBs": ceiling, "frac_of_read_ceiling": achieved / ceiling,
                 "phases_ms": prof["ms"], "phases_alg_bytes": prof["bytes"]}
     extra = {"build_seconds": t_build, "kappa": info["kappa"], "n_il_blocks": info["n_il"],
              "n_il_dense": info["n_il_dense"], "max_rank": info["max_rank"],
@@ -560,6 +704,7 @@ def main():
     if not args.no_cpu:
         log("CPU oracle baseline")
         cpu = cpu_baseline()
+        cpu["time_to_1e-8"] = oracle_solve_leg()
         log(f"oracle {cpu['value']:.2f} GB/s")
     out = {
         "metric": "matvec GB/s + time-to-1e-8 residual at N=1M, plain FP64 vs chosen form",

@@ -2,7 +2,9 @@
 // lifetime, build orchestration, import / export.
 #include "h2d_impl.h"
 
+#include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -14,6 +16,19 @@ namespace h2d {
 static thread_local std::string g_last_error;
 
 void fail(h2d_status code, const std::string& msg) { throw Error{code, msg}; }
+
+static std::atomic<int64_t> g_alloc_seen{0};
+
+bool forced_alloc_failure()
+{
+    const char* e = std::getenv("H2D_TEST_FAIL_ALLOC");
+    if (!e || !*e) {
+        g_alloc_seen.store(0);
+        return false;
+    }
+    const long long k = std::atoll(e);
+    return k >= 1 && g_alloc_seen.fetch_add(1) + 1 == k;
+}
 
 void check_hip(hipError_t e, const char* what, const char* file, int line)
 {

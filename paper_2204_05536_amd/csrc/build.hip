@@ -1019,10 +1019,59 @@ __global__ void k_half_plain(const double* src, T* dst, int64_t n)
         dst[e] = to_half<T>((float)src[e]);
 }
 
+// The half-precision product kernels read pairs and fours of 2-byte values
+// with one 4- or 8-byte load at any even address, which relies on the
+// GPU's unaligned-access mode (the mode the ROCm runtime sets on this GPU
+// family).  This check reads a known pattern through such loads at every
+// 2-byte offset of one 16-byte line, once per device, before any half pool
+// is built: a device that served them aligned (dropping low address bits)
+// would return the wrong words, and the half pools are then refused.
+__global__ void k_unaligned_probe(const uint16_t* __restrict__ src, uint64_t* __restrict__ out)
+{
+    typedef uint32_t u32_a2 __attribute__((aligned(2)));
+    typedef uint64_t u64_a2 __attribute__((aligned(2)));
+    const int o = threadIdx.x;   // loads at byte offsets 2, 4, 6, 8 of the pattern
+    if (o < 4) {
+        out[o] = *reinterpret_cast<const u32_a2*>(src + 1 + o);
+        out[4 + o] = *reinterpret_cast<const u64_a2*>(src + 1 + o);
+    }
+}
+
+static void check_unaligned_loads(hipStream_t s)
+{
+    static int checked[64] = {0};
+    int dev = 0;
+    HIPCK(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64 && checked[dev]) return;
+    uint16_t pat[16];
+    for (int i = 0; i < 16; ++i) pat[i] = (uint16_t)(0x1111u * (unsigned)(i + 1) + 0x0101u * (unsigned)i);
+    DBuf<uint16_t> src;
+    DBuf<uint64_t> out;
+    src.alloc(16);
+    out.alloc(8);
+    HIPCK(hipMemcpyAsync(src.p, pat, sizeof(pat), hipMemcpyHostToDevice, s));
+    k_unaligned_probe<<<1, 64, 0, s>>>(src.p, out.p);
+    HIPCK(hipGetLastError());
+    uint64_t got[8];
+    HIPCK(hipMemcpyAsync(got, out.p, sizeof(got), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    for (int o = 0; o < 4; ++o) {
+        const int e32 = 1 + o;   // the 4-byte load of thread o starts at element 1 + o
+        const uint64_t w32 = (uint64_t)pat[e32] | ((uint64_t)pat[e32 + 1] << 16);
+        uint64_t w64 = 0;
+        for (int q = 3; q >= 0; --q) w64 = (w64 << 16) | pat[1 + o + q];
+        if (got[o] != w32 || got[4 + o] != w64)
+            fail(H2D_EUNSUPPORTED, "this GPU does not serve 2-byte-aligned 4- and 8-byte loads as unaligned "
+                                   "accesses; the FP16/BF16 pools need them");
+    }
+    if (dev >= 0 && dev < 64) checked[dev] = 1;
+}
+
 void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
 {
     const bool f16 = mask & H2D_PREC_BIT(H2D_P_FP16), b16 = mask & H2D_PREC_BIT(H2D_P_BF16);
     if (!f16 && !b16) return;
+    check_unaligned_loads(s);
     // jobs: IL blocks (U or D) in table order, then near blocks
     std::vector<HalfJob> jobs;
     for (int64_t q = 0; q < H.n_il; ++q) {

@@ -29,6 +29,10 @@ struct Error {
 };
 
 [[noreturn]] void fail(h2d_status code, const std::string& msg);
+// Test hook: while the environment variable H2D_TEST_FAIL_ALLOC holds k >= 1,
+// the k-th device allocation (counted while the variable is set) fails as an
+// out-of-memory would, so the ENOMEM paths can be exercised from the host.
+bool forced_alloc_failure();
 void check_hip(hipError_t e, const char* what, const char* file, int line);
 #define HIPCK(x) ::h2d::check_hip((x), #x, __FILE__, __LINE__)
 
@@ -53,6 +57,8 @@ struct DBuf {
     {
         reset();
         if (count == 0) return;
+        if (forced_alloc_failure())
+            fail(H2D_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed (forced by H2D_TEST_FAIL_ALLOC)");
         hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
         if (e != hipSuccess) {
             (void)hipGetLastError();

@@ -211,3 +211,30 @@ def test_solve_plain_log4096(orc):
     A = npref.kernel_matrix(k, xy)
     xd = np.linalg.solve(A, b)
     assert np.linalg.norm(host(x) - xd) <= 1e-7 * np.linalg.norm(xd)
+
+
+def test_forced_allocation_failures_report_enomem():
+    """H2D_TEST_FAIL_ALLOC=k makes the k-th device allocation fail: every
+    such failure during a build surfaces as H2D_ENOMEM with the handle left
+    unset, nothing stays allocated, and a later build works."""
+    import os
+    import torch
+    h = _lib()
+    xy, b, kern, leaf, tol = inputs.workload("log4096", n=1500)
+    xd, bd = dev(xy), dev(b)
+    ref = host(h.HODLR2D.build(xd, kern, leaf, tol, precs=("fp16",)).matvec(bd))
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    try:
+        for k in (1, 3, 7, 15, 30):
+            os.environ["H2D_TEST_FAIL_ALLOC"] = str(k)
+            with pytest.raises(h.H2DError) as e:
+                h.HODLR2D.build(xd, kern, leaf, tol, precs=("fp16",))
+            assert e.value.code == h.H2D_ENOMEM, (k, e.value)
+            del os.environ["H2D_TEST_FAIL_ALLOC"]
+    finally:
+        os.environ.pop("H2D_TEST_FAIL_ALLOC", None)
+    torch.cuda.synchronize()
+    assert abs(torch.cuda.mem_get_info()[0] - free0) <= 64 << 20
+    y = host(h.HODLR2D.build(xd, kern, leaf, tol, precs=("fp16",)).matvec(bd))
+    assert np.array_equal(y, ref)
