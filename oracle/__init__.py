@@ -78,6 +78,11 @@ def lib():
         L.orc_near_table.argtypes = [P, i64p, i64p]
         L.orc_il_table.argtypes = [P, C.POINTER(C.c_int32), i64p, i64p, C.POINTER(C.c_int32), i64p]
         L.orc_il_factors.argtypes = [P, C.c_int64, dp, dp, dp]
+        i32p = C.POINTER(C.c_int32)
+        L.orc_is_adaptive.argtypes = [P]; L.orc_is_adaptive.restype = C.c_int32
+        L.orc_block_levels.argtypes = [P, i32p, i32p, i32p, i32p]
+        L.orc_admissible.argtypes = [C.c_int, C.c_uint32, C.c_int, C.c_uint32]
+        L.orc_admissible.restype = C.c_int
         L.orc_near_factor.argtypes = [P, C.c_int64, dp]
         L.orc_matvec.argtypes = [P, dp, dp]; L.orc_matvec.restype = C.c_int
         L.orc_gmres.argtypes = [P, dp, dp, C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32), dp]
@@ -175,6 +180,11 @@ def box_relation(ka, kb, level):
     return int(lib().orc_box_relation(ka, kb, level))
 
 
+def admissible(la, ka, lb, kb):
+    """1 when boxes (level la, key ka) and (lb, kb) share at most one point."""
+    return int(lib().orc_admissible(la, ka, lb, kb))
+
+
 def aca(spec, xy, rows, cols, tol):
     """ACA of the block K(xy[rows], xy[cols]); returns (kind, rank, U, V, D)."""
     xy = _f64(xy)
@@ -204,16 +214,19 @@ class OracleH:
     """Algorithm 1 on the CPU: the HODLR2D representation of K(xy, xy).
 
     ``factors=False`` builds the tree and the lists only (no ACA).
+    ``adaptive=True`` builds the adaptive tree (a box is split exactly when
+    it holds more than leaf_max points) and its blocks between boxes of any
+    levels.
     """
 
-    def __init__(self, xy, spec, leaf_max=64, tol=1e-10, factors=True):
+    def __init__(self, xy, spec, leaf_max=64, tol=1e-10, factors=True, adaptive=False):
         self.xy = _f64(xy)
         self.n = self.xy.shape[0]
         self.spec = dict(spec)
         self._k = kernel_struct(spec)
         h = C.c_void_p()
         st = lib().orc_build(_dp(self.xy), self.n, C.byref(self._k), int(leaf_max), float(tol),
-                             1 if factors else 0, C.byref(h))
+                             (1 if factors else 0) | (2 if adaptive else 0), C.byref(h))
         if st != ORC_OK:
             raise OracleError(st, "build")
         self._h = h
@@ -261,12 +274,25 @@ class OracleH:
                            kd.ctypes.data_as(C.POINTER(C.c_int32)), _i64p(rk))
         return {"level": lv, "tgt": t, "src": s, "kind": kd, "rank": rk}
 
+    @property
+    def adaptive(self):
+        return bool(lib().orc_is_adaptive(self._h))
+
+    def block_levels(self):
+        """(near target levels, near source levels, IL target levels, IL source levels)."""
+        nn = lib().orc_n_near(self._h); ni = lib().orc_n_il(self._h)
+        a = [np.empty(max(c, 1), np.int32) for c in (nn, nn, ni, ni)]
+        lib().orc_block_levels(self._h, *[x.ctypes.data_as(C.POINTER(C.c_int32)) for x in a])
+        return a[0][:nn], a[1][:nn], a[2][:ni], a[3][:ni]
+
     def il_factors(self, b):
         """(kind, U, V, D) of interaction-list block b, in tree-ordered rows/cols."""
         tab = self.il_table() if not hasattr(self, "_tab") else self._tab
         self._tab = tab
-        lvl = self.level(int(tab["level"][b]))
-        m = int(lvl["count"][tab["tgt"][b]]); n = int(lvl["count"][tab["src"][b]])
+        if not hasattr(self, "_lv"):
+            self._lv = self.block_levels()
+        lt = self.level(int(tab["level"][b])); ls = self.level(int(self._lv[3][b]))
+        m = int(lt["count"][tab["tgt"][b]]); n = int(ls["count"][tab["src"][b]])
         k = int(tab["rank"][b])
         if tab["kind"][b] == BK_DENSE:
             D = np.empty(m * n)
@@ -278,8 +304,8 @@ class OracleH:
 
     def near_factor(self, b):
         t, s = self.near_table()
-        lvl = self.level(self.kappa)
-        m = int(lvl["count"][t[b]]); n = int(lvl["count"][s[b]])
+        ntl, nsl, _, _ = self.block_levels()
+        m = int(self.level(int(ntl[b]))["count"][t[b]]); n = int(self.level(int(nsl[b]))["count"][s[b]])
         D = np.empty(m * n)
         lib().orc_near_factor(self._h, b, _dp(D))
         return D.reshape(n, m).T

@@ -207,11 +207,14 @@ typedef struct {
     int64_t* begin;   /* first point (tree order) */
     int64_t* count;   /* number of points */
     int64_t* parent;  /* index of the parent box at level-1 (-1 at level 0) */
+    int64_t* child0;  /* first child at level+1 */
+    int64_t* nchild;  /* number of children (0: the box is a leaf) */
 } orc_level_t;
 
 typedef struct {
-    int32_t level, kind;
-    int64_t tgt, src, k;     /* boxes are indices into the level's box table */
+    int32_t level, kind;     /* level of the target box */
+    int32_t slevel, pad;     /* level of the source box (= level in a balanced tree) */
+    int64_t tgt, src, k;     /* boxes are indices into their level's box table */
     double* U;               /* m x k column-major (kind LOWRANK) */
     double* V;               /* n x k column-major (kind LOWRANK) */
     double* D;               /* m x n column-major (kind DENSE) */
@@ -229,12 +232,14 @@ typedef struct {
     orc_block* near;         /* leaf level: self + edge sharers, (tgt, src) order */
     orc_block* il;           /* interaction-list blocks, (level, tgt, src) order */
     int factors;             /* 0 = structure only */
+    int adaptive;            /* 1: adaptive tree (leaves at several levels) */
 } orc_h;
 
 static void orc_free_levels(orc_h* h)
 {
     for (int l = 0; l <= ORC_MAX_LEVEL; ++l) {
         free(h->lev[l].key); free(h->lev[l].begin); free(h->lev[l].count); free(h->lev[l].parent);
+        free(h->lev[l].child0); free(h->lev[l].nchild);
         memset(&h->lev[l], 0, sizeof(h->lev[l]));
     }
 }
@@ -261,6 +266,31 @@ static int64_t orc_find(const orc_level_t* L, uint32_t key)
         if (L->key[mid] < key) lo = mid + 1; else hi = mid - 1;
     }
     return -1;
+}
+
+static int orc_i64_cmp(const void* a, const void* b)
+{
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* child0 / nchild of every box from the parent indices of the level below
+ * (children of a box are consecutive there, in key order). */
+static void orc_child_ranges(orc_h* h)
+{
+    for (int l = 0; l <= h->kappa; ++l) {
+        orc_level_t* L = &h->lev[l];
+        L->child0 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L->nbox + 1));
+        L->nchild = (int64_t*)calloc((size_t)(L->nbox + 1), sizeof(int64_t));
+        for (int64_t b = 0; b < L->nbox; ++b) L->child0[b] = -1;
+        if (l == h->kappa) continue;
+        const orc_level_t* C = &h->lev[l + 1];
+        for (int64_t c = 0; c < C->nbox; ++c) {
+            int64_t p = C->parent[c];
+            if (L->nchild[p] == 0) L->child0[p] = c;
+            L->nchild[p]++;
+        }
+    }
 }
 
 /* Balanced quadtree (Algorithm 1): kappa is the smallest depth at which no
@@ -316,6 +346,85 @@ static int orc_tree(orc_h* h)
             L->parent[b] = (l == 0) ? -1 : orc_find(&h->lev[l - 1], L->key[b] >> 2);
     }
     free(kv);
+    orc_child_ranges(h);
+    return ORC_OK;
+}
+
+/* Adaptive quadtree.  The paper notes (end of Section 4) that the method
+ * carries over to a non-balanced, adaptive tree with small changes; the
+ * reading taken here: a box is subdivided exactly when it holds more than
+ * N_max points, so the leaves are the boxes of at most N_max points whose
+ * parent holds more, at whatever level that happens (the same half-open
+ * cells, depth at most 16).  Points are ordered by (leaf, caller index),
+ * leaves in Morton order of their cells; every level lists its boxes in key
+ * order.  When every box above some depth holds more than N_max points and
+ * every box at it at most N_max, this is the balanced tree of Algorithm 1. */
+static int orc_tree_adaptive(orc_h* h)
+{
+    int64_t n = h->n;
+    orc_kv* kv = (orc_kv*)malloc(sizeof(orc_kv) * (size_t)(n > 0 ? n : 1));
+    if (!kv) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        kv[i].key = orc_morton(orc_cell(h->xy[2 * i], h->R, ORC_MAX_LEVEL),
+                               orc_cell(h->xy[2 * i + 1], h->R, ORC_MAX_LEVEL), ORC_MAX_LEVEL);
+        kv[i].idx = i;
+    }
+    qsort(kv, (size_t)n, sizeof(orc_kv), orc_kv_cmp);
+    /* level 0: the root */
+    orc_level_t* L0 = &h->lev[0];
+    L0->nbox = 1;
+    L0->key = (uint32_t*)calloc(1, sizeof(uint32_t));
+    L0->begin = (int64_t*)calloc(1, sizeof(int64_t));
+    L0->count = (int64_t*)malloc(sizeof(int64_t));
+    L0->parent = (int64_t*)malloc(sizeof(int64_t));
+    L0->count[0] = n; L0->parent[0] = -1;
+    int kappa = 0;
+    for (int l = 0; l < ORC_MAX_LEVEL; ++l) {
+        const orc_level_t* P = &h->lev[l];
+        int shift = 2 * (ORC_MAX_LEVEL - (l + 1));
+        /* children of the boxes above N_max: runs of equal level-(l+1) key */
+        int64_t nb = 0;
+        for (int64_t b = 0; b < P->nbox; ++b) {
+            if (P->count[b] <= h->leaf_max) continue;
+            for (int64_t i = P->begin[b]; i < P->begin[b] + P->count[b]; ++i)
+                if (i == P->begin[b] || (kv[i].key >> shift) != (kv[i - 1].key >> shift)) ++nb;
+        }
+        if (nb == 0) break;
+        orc_level_t* L = &h->lev[l + 1];
+        L->nbox = nb;
+        L->key = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)nb);
+        L->begin = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+        L->count = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+        L->parent = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+        int64_t c = -1;
+        for (int64_t b = 0; b < P->nbox; ++b) {
+            if (P->count[b] <= h->leaf_max) continue;
+            for (int64_t i = P->begin[b]; i < P->begin[b] + P->count[b]; ++i) {
+                uint32_t kk = kv[i].key >> shift;
+                if (i == P->begin[b] || kk != (kv[i - 1].key >> shift)) {
+                    ++c; L->key[c] = kk; L->begin[c] = i; L->count[c] = 0; L->parent[c] = b;
+                }
+                L->count[c]++;
+            }
+        }
+        kappa = l + 1;
+    }
+    /* a box still above N_max at depth 16 cannot be split further */
+    const orc_level_t* D = &h->lev[kappa];
+    for (int64_t b = 0; b < D->nbox; ++b)
+        if (D->count[b] > h->leaf_max && kappa == ORC_MAX_LEVEL) { free(kv); return ORC_EDEPTH; }
+    h->kappa = kappa;
+    h->perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) h->perm[i] = kv[i].idx;
+    free(kv);
+    orc_child_ranges(h);
+    /* inside each leaf, caller order */
+    for (int l = 0; l <= kappa; ++l) {
+        const orc_level_t* L = &h->lev[l];
+        for (int64_t b = 0; b < L->nbox; ++b)
+            if (L->nchild[b] == 0)
+                qsort(h->perm + L->begin[b], (size_t)L->count[b], sizeof(int64_t), orc_i64_cmp);
+    }
     return ORC_OK;
 }
 
@@ -393,6 +502,96 @@ int orc_edge_list(uint32_t key, int level, uint32_t* out)
 
 /* Classify two same-level boxes (exported for tests). */
 int orc_box_relation(uint32_t ka, uint32_t kb, int level) { return orc_relation(ka, kb, level); }
+
+/* Admissibility of two boxes of any levels (adaptive tree): their closed
+ * squares, compared on the grid of the finer level, have at most one point
+ * in common (a shared vertex, or none).  For boxes of one level this is
+ * "vertex sharing or well separated", the compressed pairs of Section 4;
+ * the same box and edge sharers are not admissible. */
+int orc_admissible(int la, uint32_t ka, int lb, uint32_t kb)
+{
+    int L = la > lb ? la : lb;
+    uint32_t ax, ay, bx, by;
+    orc_demorton(ka, la, &ax, &ay);
+    orc_demorton(kb, lb, &bx, &by);
+    int64_t sa = (int64_t)1 << (L - la), sb = (int64_t)1 << (L - lb);
+    int64_t ax0 = ax * sa, ax1 = ax0 + sa, ay0 = ay * sa, ay1 = ay0 + sa;
+    int64_t bx0 = bx * sb, bx1 = bx0 + sb, by0 = by * sb, by1 = by0 + sb;
+    int64_t wx = (ax1 < bx1 ? ax1 : bx1) - (ax0 > bx0 ? ax0 : bx0);
+    int64_t wy = (ay1 < by1 ? ay1 : by1) - (ay0 > by0 ? ay0 : by0);
+    if (wx < 0 || wy < 0) return 1;
+    return wx == 0 && wy == 0;
+}
+
+static int orc_block_cmp(const void* x, const void* y)
+{
+    const orc_block* a = (const orc_block*)x;
+    const orc_block* b = (const orc_block*)y;
+    if (a->level != b->level) return a->level < b->level ? -1 : 1;
+    if (a->tgt != b->tgt) return a->tgt < b->tgt ? -1 : 1;
+    if (a->slevel != b->slevel) return a->slevel < b->slevel ? -1 : 1;
+    if (a->src != b->src) return a->src < b->src ? -1 : 1;
+    return 0;
+}
+
+typedef struct { int32_t la, lb; int64_t a, b; } orc_pair;
+
+static void orc_push_block(orc_block** arr, int64_t* cnt, int64_t* cap, int la, int64_t a, int lb, int64_t b)
+{
+    if (*cnt == *cap) {
+        *cap = *cap ? 2 * *cap : 1024;
+        *arr = (orc_block*)realloc(*arr, sizeof(orc_block) * (size_t)*cap);
+    }
+    orc_block* B = &(*arr)[(*cnt)++];
+    memset(B, 0, sizeof(*B));
+    B->level = la; B->slevel = lb; B->tgt = a; B->src = b; B->kind = BK_DENSE;
+}
+
+/* Blocks of the adaptive tree, found by descending pairs of boxes from
+ * (root, root), the pair form of the Section 4 construction: a pair of
+ * distinct admissible boxes is one compressed block; a pair of leaves
+ * that is not admissible (the same leaf, or leaves sharing a segment) is
+ * a dense near-field block; any other pair is replaced by the pairs of
+ * their children (only the non-leaf side is split when one side is a
+ * leaf).  On a balanced tree this gives exactly the interaction lists of
+ * every level and the self + edge-sharing leaf blocks. */
+static void orc_lists_adaptive(orc_h* h)
+{
+    int64_t nn = 0, ncap = 0, ni = 0, icap = 0, sp = 0, scap = 1024;
+    orc_pair* st = (orc_pair*)malloc(sizeof(orc_pair) * (size_t)scap);
+    h->near = NULL; h->il = NULL;
+    st[sp++] = (orc_pair){0, 0, 0, 0};
+    while (sp > 0) {
+        orc_pair P = st[--sp];
+        const orc_level_t* LA = &h->lev[P.la];
+        const orc_level_t* LB = &h->lev[P.lb];
+        int leafA = LA->nchild[P.a] == 0, leafB = LB->nchild[P.b] == 0;
+        int same = P.la == P.lb && P.a == P.b;
+        if (!same && orc_admissible(P.la, LA->key[P.a], P.lb, LB->key[P.b])) {
+            orc_push_block(&h->il, &ni, &icap, P.la, P.a, P.lb, P.b);
+            continue;
+        }
+        if (leafA && leafB) {
+            orc_push_block(&h->near, &nn, &ncap, P.la, P.a, P.lb, P.b);
+            continue;
+        }
+        int64_t a0 = leafA ? P.a : LA->child0[P.a], na = leafA ? 1 : LA->nchild[P.a];
+        int64_t b0 = leafB ? P.b : LB->child0[P.b], nb = leafB ? 1 : LB->nchild[P.b];
+        int la = leafA ? P.la : P.la + 1, lb = leafB ? P.lb : P.lb + 1;
+        for (int64_t i = 0; i < na; ++i)
+            for (int64_t j = 0; j < nb; ++j) {
+                if (sp == scap) { scap *= 2; st = (orc_pair*)realloc(st, sizeof(orc_pair) * (size_t)scap); }
+                st[sp++] = (orc_pair){la, lb, a0 + i, b0 + j};
+            }
+    }
+    free(st);
+    if (nn) qsort(h->near, (size_t)nn, sizeof(orc_block), orc_block_cmp);
+    if (ni) qsort(h->il, (size_t)ni, sizeof(orc_block), orc_block_cmp);
+    for (int64_t q = 0; q < ni; ++q) h->il[q].kind = BK_LOWRANK;
+    h->n_near = nn; h->n_il = ni;
+    if (!h->near) h->near = (orc_block*)calloc(1, sizeof(orc_block));
+    if (!h->il) h->il = (orc_block*)calloc(1, sizeof(orc_block));
+}
 
 /* ------------------------------------------------------------------ */
 /* Adaptive cross approximation                                         */
@@ -498,18 +697,54 @@ int64_t orc_aca(const orc_kernel* kern, const double* xy, const int64_t* rows, i
 /* Algorithm 1                                                          */
 /* ------------------------------------------------------------------ */
 
+/* Dense near-field blocks by their entries; ACA for the interaction-list
+ * blocks.  Rows are the target box's points, columns the source box's, in
+ * tree order (each box on its own level). */
+static void orc_fill_factors(orc_h* h)
+{
+    const orc_kernel* kern = &h->kern;
+    const double* xy = h->xy;
+    int64_t n = h->n;
+    int64_t* rows = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* cols = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t t = 0; t < h->n_near; ++t) {
+        orc_block* B = &h->near[t];
+        const orc_level_t* LT = &h->lev[B->level];
+        const orc_level_t* LS = &h->lev[B->slevel];
+        int64_t m = LT->count[B->tgt], nn = LS->count[B->src];
+        B->D = (double*)malloc(sizeof(double) * (size_t)(m * nn));
+        for (int64_t j = 0; j < nn; ++j)
+            for (int64_t i = 0; i < m; ++i)
+                B->D[j * m + i] = orc_entry(kern, xy, h->perm[LT->begin[B->tgt] + i], h->perm[LS->begin[B->src] + j]);
+    }
+    for (int64_t t = 0; t < h->n_il; ++t) {
+        orc_block* B = &h->il[t];
+        const orc_level_t* LT = &h->lev[B->level];
+        const orc_level_t* LS = &h->lev[B->slevel];
+        int64_t m = LT->count[B->tgt], nn = LS->count[B->src];
+        for (int64_t i = 0; i < m; ++i) rows[i] = h->perm[LT->begin[B->tgt] + i];
+        for (int64_t j = 0; j < nn; ++j) cols[j] = h->perm[LS->begin[B->src] + j];
+        B->k = orc_aca(kern, xy, rows, m, cols, nn, h->tol, &B->kind, &B->U, &B->V, &B->D);
+    }
+    free(rows); free(cols);
+}
+
 static int orc_has_duplicates(const orc_h* h)
 {
     /* two distinct points at distance 0 make log, 1/r, phi_1, phi_2 singular */
     if (!(h->kern.kind == OK_LOG || h->kern.kind == OK_INVR)) return 0;
-    const orc_level_t* L = &h->lev[h->kappa];
-    for (int64_t b = 0; b < L->nbox; ++b)
-        for (int64_t p = L->begin[b]; p < L->begin[b] + L->count[b]; ++p)
-            for (int64_t q = p + 1; q < L->begin[b] + L->count[b]; ++q) {
-                const double* a = h->xy + 2 * h->perm[p];
-                const double* c = h->xy + 2 * h->perm[q];
-                if (a[0] == c[0] && a[1] == c[1]) return 1;
-            }
+    for (int l = 0; l <= h->kappa; ++l) {
+        const orc_level_t* L = &h->lev[l];
+        for (int64_t b = 0; b < L->nbox; ++b) {
+            if (L->nchild[b] != 0) continue;   /* leaves only: they partition the points */
+            for (int64_t p = L->begin[b]; p < L->begin[b] + L->count[b]; ++p)
+                for (int64_t q = p + 1; q < L->begin[b] + L->count[b]; ++q) {
+                    const double* a = h->xy + 2 * h->perm[p];
+                    const double* c = h->xy + 2 * h->perm[q];
+                    if (a[0] == c[0] && a[1] == c[1]) return 1;
+                }
+        }
+    }
     return 0;
 }
 
@@ -520,13 +755,21 @@ int orc_build(const double* xy, int64_t n, const orc_kernel* kern, int32_t leaf_
     if (n < 1 || leaf_max < 1 || !(tol >= 0.0)) return ORC_EINVAL;
     for (int64_t i = 0; i < 2 * n; ++i) if (!isfinite(xy[i])) return ORC_EINVAL;
     orc_h* h = (orc_h*)calloc(1, sizeof(orc_h));
-    h->n = n; h->leaf_max = leaf_max; h->tol = tol; h->kern = *kern; h->factors = with_factors;
+    h->n = n; h->leaf_max = leaf_max; h->tol = tol; h->kern = *kern;
+    h->factors = with_factors & 1;
+    h->adaptive = (with_factors >> 1) & 1;
     h->xy = (double*)malloc(sizeof(double) * (size_t)(2 * n));
     memcpy(h->xy, xy, sizeof(double) * (size_t)(2 * n));
     h->R = orc_box_radius(xy, n);
-    int st = orc_tree(h);
+    int st = h->adaptive ? orc_tree_adaptive(h) : orc_tree(h);
     if (st) { orc_free(h); return st; }
     if (orc_has_duplicates(h)) { orc_free(h); return ORC_EDUP; }
+    if (h->adaptive) {
+        orc_lists_adaptive(h);
+        if (h->factors) orc_fill_factors(h);
+        *out = h;
+        return ORC_OK;
+    }
     int kappa = h->kappa;
     /* near blocks at the leaf level: self, then edge sharers, in key order */
     const orc_level_t* LL = &h->lev[kappa];
@@ -542,7 +785,7 @@ int orc_build(const double* xy, int64_t n, const orc_kernel* kern, int32_t leaf_
             int64_t s = orc_find(LL, keys[e]);
             if (s < 0) continue;
             orc_block* B = &h->near[h->n_near++];
-            B->level = kappa; B->kind = BK_DENSE; B->tgt = b; B->src = s; B->k = 0;
+            B->level = kappa; B->slevel = kappa; B->kind = BK_DENSE; B->tgt = b; B->src = s; B->k = 0;
         }
     }
     /* interaction-list blocks, levels 1..kappa */
@@ -559,32 +802,11 @@ int orc_build(const double* xy, int64_t n, const orc_kernel* kern, int32_t leaf_
                 int64_t s = orc_find(L, keys[e]);
                 if (s < 0) continue;
                 orc_block* B = &h->il[h->n_il++];
-                B->level = l; B->tgt = b; B->src = s;
+                B->level = l; B->slevel = l; B->tgt = b; B->src = s;
             }
         }
     }
-    if (with_factors) {
-        int64_t* rows = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-        int64_t* cols = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-        for (int64_t t = 0; t < h->n_near; ++t) {
-            orc_block* B = &h->near[t];
-            int64_t m = LL->count[B->tgt], nn = LL->count[B->src];
-            B->D = (double*)malloc(sizeof(double) * (size_t)(m * nn));
-            for (int64_t j = 0; j < nn; ++j)
-                for (int64_t i = 0; i < m; ++i)
-                    B->D[j * m + i] = orc_entry(kern, xy, h->perm[LL->begin[B->tgt] + i],
-                                                h->perm[LL->begin[B->src] + j]);
-        }
-        for (int64_t t = 0; t < h->n_il; ++t) {
-            orc_block* B = &h->il[t];
-            const orc_level_t* L = &h->lev[B->level];
-            int64_t m = L->count[B->tgt], nn = L->count[B->src];
-            for (int64_t i = 0; i < m; ++i) rows[i] = h->perm[L->begin[B->tgt] + i];
-            for (int64_t j = 0; j < nn; ++j) cols[j] = h->perm[L->begin[B->src] + j];
-            B->k = orc_aca(kern, xy, rows, m, cols, nn, tol, &B->kind, &B->U, &B->V, &B->D);
-        }
-        free(rows); free(cols);
-    }
+    if (h->factors) orc_fill_factors(h);
     *out = h;
     return ORC_OK;
 }
@@ -600,12 +822,13 @@ int orc_matvec(const orc_h* h, const double* psi, double* bout)
     double* x = (double*)malloc(sizeof(double) * (size_t)n);   /* psi in tree order */
     double* b = (double*)calloc((size_t)n, sizeof(double));    /* b in tree order */
     for (int64_t i = 0; i < n; ++i) x[i] = psi[h->perm[i]];
-    const orc_level_t* LL = &h->lev[h->kappa];
-    /* full-rank part: self and edge-sharing blocks at the leaf level */
+    /* full-rank part: self and edge-sharing blocks of the leaves */
     for (int64_t t = 0; t < h->n_near; ++t) {
         const orc_block* B = &h->near[t];
-        int64_t r0 = LL->begin[B->tgt], m = LL->count[B->tgt];
-        int64_t c0 = LL->begin[B->src], nn = LL->count[B->src];
+        const orc_level_t* LT = &h->lev[B->level];
+        const orc_level_t* LS = &h->lev[B->slevel];
+        int64_t r0 = LT->begin[B->tgt], m = LT->count[B->tgt];
+        int64_t c0 = LS->begin[B->src], nn = LS->count[B->src];
         for (int64_t i = 0; i < m; ++i) {
             double s = 0.0;
             for (int64_t j = 0; j < nn; ++j) s += B->D[j * m + i] * x[c0 + j];
@@ -616,9 +839,10 @@ int orc_matvec(const orc_h* h, const double* psi, double* bout)
     double* t = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     for (int64_t q = 0; q < h->n_il; ++q) {
         const orc_block* B = &h->il[q];
-        const orc_level_t* L = &h->lev[B->level];
-        int64_t r0 = L->begin[B->tgt], m = L->count[B->tgt];
-        int64_t c0 = L->begin[B->src], nn = L->count[B->src];
+        const orc_level_t* LT = &h->lev[B->level];
+        const orc_level_t* LS = &h->lev[B->slevel];
+        int64_t r0 = LT->begin[B->tgt], m = LT->count[B->tgt];
+        int64_t c0 = LS->begin[B->src], nn = LS->count[B->src];
         if (B->kind == BK_DENSE) {
             for (int64_t i = 0; i < m; ++i) {
                 double s = 0.0;
@@ -752,6 +976,13 @@ void orc_near_table(const orc_h* h, int64_t* tgt, int64_t* src)
 {
     for (int64_t b = 0; b < h->n_near; ++b) { tgt[b] = h->near[b].tgt; src[b] = h->near[b].src; }
 }
+int32_t orc_is_adaptive(const orc_h* h) { return h->adaptive; }
+/* Levels of the target and source boxes of every near and IL block. */
+void orc_block_levels(const orc_h* h, int32_t* near_tl, int32_t* near_sl, int32_t* il_tl, int32_t* il_sl)
+{
+    for (int64_t b = 0; b < h->n_near; ++b) { near_tl[b] = h->near[b].level; near_sl[b] = h->near[b].slevel; }
+    for (int64_t b = 0; b < h->n_il; ++b) { il_tl[b] = h->il[b].level; il_sl[b] = h->il[b].slevel; }
+}
 void orc_il_table(const orc_h* h, int32_t* level, int64_t* tgt, int64_t* src, int32_t* kind, int64_t* rank)
 {
     for (int64_t b = 0; b < h->n_il; ++b) {
@@ -764,8 +995,7 @@ void orc_il_table(const orc_h* h, int32_t* level, int64_t* tgt, int64_t* src, in
 void orc_il_factors(const orc_h* h, int64_t b, double* U, double* V, double* D)
 {
     const orc_block* B = &h->il[b];
-    const orc_level_t* L = &h->lev[B->level];
-    int64_t m = L->count[B->tgt], n = L->count[B->src];
+    int64_t m = h->lev[B->level].count[B->tgt], n = h->lev[B->slevel].count[B->src];
     if (B->kind == BK_DENSE) { if (D) memcpy(D, B->D, sizeof(double) * (size_t)(m * n)); return; }
     if (U) memcpy(U, B->U, sizeof(double) * (size_t)(m * B->k));
     if (V) memcpy(V, B->V, sizeof(double) * (size_t)(n * B->k));
@@ -773,8 +1003,7 @@ void orc_il_factors(const orc_h* h, int64_t b, double* U, double* V, double* D)
 void orc_near_factor(const orc_h* h, int64_t b, double* D)
 {
     const orc_block* B = &h->near[b];
-    const orc_level_t* L = &h->lev[h->kappa];
-    memcpy(D, B->D, sizeof(double) * (size_t)(L->count[B->tgt] * L->count[B->src]));
+    memcpy(D, B->D, sizeof(double) * (size_t)(h->lev[B->level].count[B->tgt] * h->lev[B->slevel].count[B->src]));
 }
 
 /* ------------------------------------------------------------------ */
@@ -787,7 +1016,9 @@ int orc_export(const orc_h* h, const char* path)
     FILE* f = fopen(path, "wb");
     if (!f) return ORC_EINVAL;
     const char magic[4] = {'H', '2', 'D', 'X'};
-    uint32_t version = 1, flags = 1, reserved = 0;   /* flags bit 0: factors present */
+    /* version 2 (adaptive trees): every block also carries the levels of its
+     * boxes; flags bit 0: factors present */
+    uint32_t version = h->adaptive ? 2 : 1, flags = 1, reserved = 0;
     fwrite(magic, 1, 4, f);
     fwrite(&version, 4, 1, f);
     fwrite(&flags, 4, 1, f);
@@ -811,21 +1042,21 @@ int orc_export(const orc_h* h, const char* path)
         fwrite(L->count, 8, (size_t)L->nbox, f);
         fwrite(L->parent, 8, (size_t)L->nbox, f);
     }
-    const orc_level_t* LL = &h->lev[h->kappa];
     fwrite(&h->n_near, 8, 1, f);
     for (int64_t b = 0; b < h->n_near; ++b) {
         const orc_block* B = &h->near[b];
+        if (h->adaptive) { fwrite(&B->level, 4, 1, f); fwrite(&B->slevel, 4, 1, f); }
         fwrite(&B->tgt, 8, 1, f);
         fwrite(&B->src, 8, 1, f);
-        fwrite(B->D, 8, (size_t)(LL->count[B->tgt] * LL->count[B->src]), f);
+        fwrite(B->D, 8, (size_t)(h->lev[B->level].count[B->tgt] * h->lev[B->slevel].count[B->src]), f);
     }
     fwrite(&h->n_il, 8, 1, f);
     for (int64_t b = 0; b < h->n_il; ++b) {
         const orc_block* B = &h->il[b];
-        const orc_level_t* L = &h->lev[B->level];
-        int64_t m = L->count[B->tgt], n = L->count[B->src];
+        int64_t m = h->lev[B->level].count[B->tgt], n = h->lev[B->slevel].count[B->src];
         fwrite(&B->level, 4, 1, f);
         fwrite(&B->kind, 4, 1, f);
+        if (h->adaptive) { fwrite(&B->slevel, 4, 1, f); fwrite(&B->pad, 4, 1, f); }
         fwrite(&B->tgt, 8, 1, f);
         fwrite(&B->src, 8, 1, f);
         fwrite(&B->k, 8, 1, f);
