@@ -487,6 +487,55 @@ def paper_rbf(m=500):
     return out
 
 
+def adaptive_vs_balanced(n=250000, rows=48):
+    """The batched workload's clustered geometry (4-cluster Gaussian
+    mixture, sigma 0.05; Gaussian RBF c = 0.05 + 1e-4 I; leaf 64; tol 1e-10)
+    at one instance size, on the balanced tree and on the adaptive tree
+    (boxes split only while they hold more than 64 points): depth, blocks,
+    stored values, build and product time, and the error of sampled rows
+    against their exact O(N) sums."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2204_05536_amd import hodlr2d, inputs
+
+    spec = {"kind": "gauss", "c": 0.05, "diag_mode": "add", "diag_value": 1e-4}
+    xy = inputs.gaussian_mixture(n, np.random.default_rng(21))
+    x = np.random.default_rng(22).uniform(-1, 1, n)
+    ridx = np.random.default_rng(23).choice(n, rows, replace=False)
+    yd = oracle.dense_rows(spec, xy, x, ridx)
+    sc = oracle.dense_rows(spec, xy, np.abs(x), ridx)
+    xd = torch.from_numpy(x).cuda()
+    out = {"n": n}
+    for name, ad in (("balanced", False), ("adaptive", True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = hodlr2d.HODLR2D.build(torch.from_numpy(xy).cuda(), spec, 64, 1e-10, adaptive=ad)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        I = H.info()
+        y = torch.empty_like(xd)
+        for _ in range(3):
+            H.matvec(xd, out=y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            H.matvec(xd, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        yh = y.cpu().numpy()
+        out[name] = {"depth": I["kappa"], "compressed_blocks": I["n_il"], "near_blocks": I["n_near"],
+                     "stored_values": I["u_elems"] + I["v_elems"] + I["d_elems"], "build_seconds": tb,
+                     "ms_per_matvec": ms, "GB/s": I["alg_bytes_fp64"] / (ms * 1e-3) / 1e9,
+                     "max_row_err_rel_abs": float(np.max(np.abs(yh[ridx] - yd) / sc))}
+        log(f"{name} tree, mixture N={n}: {out[name]}")
+        H.close()
+    return out
+
+
 def precond_local_gauss(n=1 << 16):
     """Where a leaf preconditioner matters: Gaussian RBF c = 0.02 + 0.3 I on
     N = 2^16 uniform points (leaf boxes comparable to c).  Plain GMRES,
@@ -534,6 +583,7 @@ def main():
     ap.add_argument("--no-mrhs", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own N=250k 1/r Chebyshev workload")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-tree leg")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (a known-size kernel for counter calibration)")
@@ -700,6 +750,8 @@ def main():
     if not args.no_paper:
         extra["paper_shaped"] = paper_shaped()
         extra["paper_rbf"] = paper_rbf()
+    if not args.no_adaptive:
+        extra["adaptive_vs_balanced"] = adaptive_vs_balanced()
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")

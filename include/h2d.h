@@ -78,6 +78,23 @@ typedef struct {
 typedef enum { H2D_P_FP64 = 0, H2D_P_FP16 = 1, H2D_P_BF16 = 2 } h2d_prec;
 #define H2D_PREC_BIT(p) (1u << (p))
 
+/* Build flag (OR-ed into h2d_build's prec_mask): an adaptive quadtree, the
+ * form the end of Section 4 says the method carries over to.  A box is
+ * split exactly when it holds more than leaf_max points, so leaves sit at
+ * several levels; the blocks come from descending pairs of boxes from
+ * (root, root): two distinct boxes whose closed squares share at most one
+ * point are one compressed (ACA) block, two leaves sharing a segment (or a
+ * leaf with itself) one dense block, any other pair gives way to the pairs
+ * of its children (only the non-leaf side splits when one side is a leaf).
+ * On inputs where this rule stops every branch at one depth the result is
+ * the balanced tree.  The tree and block lists are built by host code, the
+ * factors and products on the GPU.  Adaptive handles build the FP64 pools
+ * only and serve h2d_matvec (right-hand sides one at a time),
+ * h2d_matvec_noalloc, plain h2d_solve, h2d_info, h2d_export (file version
+ * 2) and h2d_import; the half-precision pools, preconditioners, batches and
+ * tile tuning return EUNSUPPORTED. */
+#define H2D_BUILD_ADAPTIVE (1u << 8)
+
 /* Algorithm 1 (InitializeHODLR2D(N_max, eps)) on the GPU.
  *   xy        device, n x 2 row-major FP64 point coordinates (copied)
  *   n         number of points, 1 <= n < 2^31
@@ -202,7 +219,10 @@ h2d_status h2d_precond_apply(h2d_t H, int32_t precond, const double* r, double* 
 
 typedef enum {
     H2D_MLP_TARGET_LEAF = 0,    /* z_X = K(X, X)^{-1} r_X: the method's leaf-block solves */
-    H2D_MLP_TARGET_GLOBAL = 1   /* z = A^{-1} r by FP64 GMRES, restricted to each leaf */
+    H2D_MLP_TARGET_GLOBAL = 1,  /* z = A^{-1} r by FP64 GMRES, restricted to each leaf */
+    H2D_MLP_TARGET_PATCH = 2    /* z_X = [K(P, P)^{-1} r_P]_X with P = X and its edge-sharing leaves
+                                   (the leaf's near-field patch: the self and edge blocks the method
+                                   stores dense), solved exactly; at most 320 patch points */
 } h2d_mlp_target;
 
 typedef struct {
@@ -265,8 +285,11 @@ typedef struct {
 h2d_status h2d_info(h2d_t H, h2d_stats* s);
 
 /* Write H to `path` (little-endian, format "H2DX" version 1, the same the
- * CPU oracle writes).  flags bit 0: include the factors (else structure
- * only: tree, perm, levels, block tables with kinds and ranks). */
+ * CPU oracle writes; version 2 for an adaptive tree, where every near block
+ * names (target level, source level, target box, source box) and every
+ * compressed block also its source level).  flags bit 0: include the
+ * factors (else structure only: tree, perm, levels, block tables with kinds
+ * and ranks). */
 h2d_status h2d_export(h2d_t H, const char* path, uint32_t flags);
 
 /* Read a file written by h2d_export (with factors) or by the oracle and

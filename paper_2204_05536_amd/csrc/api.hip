@@ -137,7 +137,7 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
     const bool fac = flags & 1u;
     File F(path, "wb");
     F.w("H2DX", 4);
-    F.w1<uint32_t>(1);
+    F.w1<uint32_t>(H.adaptive ? 2u : 1u);   // version 2: adaptive tree, blocks carry their box levels
     F.w1<uint32_t>(fac ? 1u : 0u);
     F.w1<uint32_t>(0);
     F.w1<int64_t>(H.n);
@@ -167,19 +167,37 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
     std::vector<double> U, V, D;
     if (fac) { U = dl(H.U64.p, H.u_elems); V = dl(H.V64.p, H.v_elems); D = dl(H.D64.p, H.d_elems); }
     F.w1<int64_t>((int64_t)H.h_near_src.size());
-    for (int64_t x = 0; x < LL.nbox; ++x)
-        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
-            F.w1<int64_t>(x);
-            F.w1<int64_t>(H.h_near_src[q]);
-            if (fac) F.w(D.data() + H.h_near_off[q], (size_t)LL.h_count[x] * LL.h_count[H.h_near_src[q]]);
-        }
+    if (H.adaptive) {
+        // near CSR over leaf numbers; the file names (level, box) of both leaves
+        const int64_t nleaf = (int64_t)H.h_leaf_level.size();
+        for (int64_t x = 0; x < nleaf; ++x)
+            for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+                const int32_t y = H.h_near_src[q];
+                F.w1<int32_t>(H.h_leaf_level[x]);
+                F.w1<int32_t>(H.h_leaf_level[y]);
+                F.w1<int64_t>(H.h_leaf_box[x]);
+                F.w1<int64_t>(H.h_leaf_box[y]);
+                if (fac) F.w(D.data() + H.h_near_off[q], (size_t)H.h_leaf_count[x] * H.h_leaf_count[y]);
+            }
+    } else {
+        for (int64_t x = 0; x < LL.nbox; ++x)
+            for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+                F.w1<int64_t>(x);
+                F.w1<int64_t>(H.h_near_src[q]);
+                if (fac) F.w(D.data() + H.h_near_off[q], (size_t)LL.h_count[x] * LL.h_count[H.h_near_src[q]]);
+            }
+    }
     F.w1<int64_t>(H.n_il);
     std::vector<double> Vc, Uc;
     for (int64_t b = 0; b < H.n_il; ++b) {
         const Level& L = H.lev[H.h_il_level[b]];
-        int64_t m = L.h_count[H.h_il_tgt[b]], n = L.h_count[H.h_il_src[b]], k = H.h_il_k[b];
+        int64_t m = L.h_count[H.h_il_tgt[b]], n = H.lev[il_src_level(H, b)].h_count[H.h_il_src[b]], k = H.h_il_k[b];
         F.w1<int32_t>(H.h_il_level[b]);
         F.w1<int32_t>(H.h_il_kind[b]);
+        if (H.adaptive) {
+            F.w1<int32_t>(il_src_level(H, b));
+            F.w1<int32_t>(0);
+        }
         F.w1<int64_t>(H.h_il_tgt[b]);
         F.w1<int64_t>(H.h_il_src[b]);
         F.w1<int64_t>(k);
@@ -188,7 +206,8 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
             F.w(D.data() + H.h_il_off[b], (size_t)(m * n));
         } else {
             Uc.resize((size_t)(m * k));
-            retile_u(H, H.h_il_level[b], L.h_begin[H.h_il_tgt[b]], m, k, U.data() + H.h_il_off[b], Uc.data(), false);
+            if (H.adaptive) std::memcpy(Uc.data(), U.data() + H.h_il_off[b], sizeof(double) * Uc.size());
+            else retile_u(H, H.h_il_level[b], L.h_begin[H.h_il_tgt[b]], m, k, U.data() + H.h_il_off[b], Uc.data(), false);
             F.w(Uc.data(), Uc.size());
             Vc.resize((size_t)(n * k));
             for (int64_t j = 0; j < n; ++j)
@@ -206,7 +225,8 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
     if (std::memcmp(magic, "H2DX", 4) != 0) fail(H2D_EINVAL, "not an H2DX file");
     uint32_t version = F.r1<uint32_t>(), flags = F.r1<uint32_t>();
     (void)F.r1<uint32_t>();
-    if (version != 1) fail(H2D_EINVAL, "unsupported H2DX version");
+    if (version != 1 && version != 2) fail(H2D_EINVAL, "unsupported H2DX version");
+    H.adaptive = version == 2;
     if (!(flags & 1u)) fail(H2D_EINVAL, "file holds no factors");
     H.n = F.r1<int64_t>();
     H.kappa = F.r1<int32_t>();
@@ -239,14 +259,17 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
         F.r(L.h_key.data(), L.nbox);
         std::vector<int64_t> b(L.nbox), c(L.nbox), p(L.nbox);
         F.r(b.data(), L.nbox); F.r(c.data(), L.nbox); F.r(p.data(), L.nbox);
-        // the boxes of a level tile [0, n) in key order, each non-empty, and
-        // lie inside their parent (key >> 2 is the parent's key)
+        // the boxes of a level tile [0, n) in key order (an adaptive tree:
+        // lie in [0, n) in key order without overlapping, the leaves above
+        // them filling the gaps), each non-empty, and lie inside their
+        // parent (key >> 2 is the parent's key)
         int64_t next = 0;
         for (int64_t x = 0; x < L.nbox; ++x) {
             const bool key_ok = (l == 0 ? L.h_key[x] == 0 : (uint64_t)L.h_key[x] < ((uint64_t)1 << (2 * l))) &&
                                 (x == 0 || L.h_key[x] > L.h_key[x - 1]);
-            if (!key_ok || b[x] != next || c[x] < 1 || c[x] > n - next) fail(H2D_EINVAL, "bad level table");
-            next += c[x];
+            const bool place_ok = H.adaptive ? b[x] >= next : b[x] == next;
+            if (!key_ok || !place_ok || c[x] < 1 || c[x] > n - b[x]) fail(H2D_EINVAL, "bad level table");
+            next = b[x] + c[x];
             if (l > 0) {
                 const Level& P = H.lev[l - 1];
                 if (p[x] < 0 || p[x] >= P.nbox || P.h_key[p[x]] != (L.h_key[x] >> 2) || b[x] < P.h_begin[p[x]] ||
@@ -254,33 +277,96 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
                     fail(H2D_EINVAL, "bad parent in level table");
             }
         }
-        if (next != n) fail(H2D_EINVAL, "level table does not cover the points");
+        if (next != n && !(H.adaptive && l > 0)) fail(H2D_EINVAL, "level table does not cover the points");
         L.h_begin.assign(b.begin(), b.end());
         L.h_count.assign(c.begin(), c.end());
         L.h_parent.assign(p.begin(), p.end());
     }
     const Level& LL = H.lev[H.kappa];
-    // near blocks, (target, source) order
+    // adaptive trees: leaves are the boxes without children at any level,
+    // numbered in tree order
+    std::vector<std::vector<int32_t>> leafno(H.kappa + 1);
+    if (H.adaptive) {
+        std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> lv;
+        for (int l = 0; l <= H.kappa; ++l) {
+            std::vector<int32_t> nch(H.lev[l].nbox, 0);
+            if (l < H.kappa)
+                for (int32_t p : H.lev[l + 1].h_parent) nch[p]++;
+            leafno[l].assign(H.lev[l].nbox, -1);
+            for (int64_t b = 0; b < H.lev[l].nbox; ++b)
+                if (!nch[b]) lv.push_back({H.lev[l].h_begin[b], {l, (int32_t)b}});
+        }
+        std::sort(lv.begin(), lv.end());
+        int64_t next = 0;
+        for (size_t q = 0; q < lv.size(); ++q) {
+            const int l = lv[q].second.first, b = lv[q].second.second;
+            leafno[l][b] = (int32_t)q;
+            H.h_leaf_level.push_back(l);
+            H.h_leaf_box.push_back(b);
+            H.h_leaf_begin.push_back(H.lev[l].h_begin[b]);
+            H.h_leaf_count.push_back(H.lev[l].h_count[b]);
+            if (H.lev[l].h_begin[b] != next) fail(H2D_EINVAL, "the leaves do not tile the points");
+            next += H.lev[l].h_count[b];
+        }
+        if (next != n) fail(H2D_EINVAL, "the leaves do not tile the points");
+        // a split box's children fill it exactly
+        for (int l = 0; l < H.kappa; ++l) {
+            std::vector<int64_t> filled(H.lev[l].nbox, 0);
+            for (int64_t c = 0; c < H.lev[l + 1].nbox; ++c) filled[H.lev[l + 1].h_parent[c]] += H.lev[l + 1].h_count[c];
+            for (int64_t b = 0; b < H.lev[l].nbox; ++b)
+                if (filled[b] != 0 && filled[b] != H.lev[l].h_count[b]) fail(H2D_EINVAL, "children do not fill their box");
+        }
+    }
+    const int64_t nleaf = H.adaptive ? (int64_t)H.h_leaf_level.size() : LL.nbox;
+    // near blocks, grouped by target leaf
     int64_t nn = F.r1<int64_t>();
     std::vector<double> D;
-    H.h_near_ptr.assign(LL.nbox + 1, 0);
+    H.h_near_ptr.assign(nleaf + 1, 0);
     H.h_near_src.resize(nn);
     H.h_near_off.resize(nn);
     std::vector<int64_t> ntgt(nn);
     for (int64_t q = 0; q < nn; ++q) {
-        int64_t t = F.r1<int64_t>(), u = F.r1<int64_t>();
-        if (t < 0 || t >= LL.nbox || u < 0 || u >= LL.nbox || (q > 0 && t < ntgt[q - 1]))
-            fail(H2D_EINVAL, "bad near block");
+        int64_t t, u, mt, mu;
+        if (H.adaptive) {
+            const int32_t tl = F.r1<int32_t>(), sl = F.r1<int32_t>();
+            const int64_t tb = F.r1<int64_t>(), sb = F.r1<int64_t>();
+            if (tl < 0 || tl > H.kappa || sl < 0 || sl > H.kappa || tb < 0 || tb >= H.lev[tl].nbox || sb < 0 ||
+                sb >= H.lev[sl].nbox || leafno[tl][tb] < 0 || leafno[sl][sb] < 0)
+                fail(H2D_EINVAL, "bad near block");
+            t = leafno[tl][tb];
+            u = leafno[sl][sb];
+            mt = H.h_leaf_count[t];
+            mu = H.h_leaf_count[u];
+        } else {
+            t = F.r1<int64_t>();
+            u = F.r1<int64_t>();
+            if (t < 0 || t >= LL.nbox || u < 0 || u >= LL.nbox) fail(H2D_EINVAL, "bad near block");
+            mt = LL.h_count[t];
+            mu = LL.h_count[u];
+        }
+        // version 1 lists near blocks by target; version 2 in (target level,
+        // target, source level, source) order, regrouped by target leaf below
+        if (!H.adaptive && q > 0 && t < ntgt[q - 1]) fail(H2D_EINVAL, "near blocks not grouped by target");
         ntgt[q] = t;
         H.h_near_src[q] = (int32_t)u;
         H.h_near_off[q] = (int64_t)D.size();
-        size_t e = (size_t)LL.h_count[t] * LL.h_count[u];
-        size_t o = D.size();
+        const size_t e = (size_t)mt * (size_t)mu;
+        const size_t o = D.size();
         D.resize(o + e);
         F.r(D.data() + o, e);
         H.h_near_ptr[t + 1]++;
     }
-    for (int64_t x = 0; x < LL.nbox; ++x) H.h_near_ptr[x + 1] += H.h_near_ptr[x];
+    for (int64_t x = 0; x < nleaf; ++x) H.h_near_ptr[x + 1] += H.h_near_ptr[x];
+    if (H.adaptive) {   // stable regrouping by target leaf (tree order)
+        std::vector<int64_t> ord(nn);
+        for (int64_t q = 0; q < nn; ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return ntgt[a] < ntgt[b]; });
+        std::vector<int32_t> src2(nn);
+        std::vector<int64_t> off2(nn);
+        for (int64_t q = 0; q < nn; ++q) { src2[q] = H.h_near_src[ord[q]]; off2[q] = H.h_near_off[ord[q]]; }
+        H.h_near_src.swap(src2);
+        H.h_near_off.swap(off2);
+    }
     // interaction-list blocks
     H.n_il = F.r1<int64_t>();
     const int64_t nil = H.n_il;
@@ -289,15 +375,23 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
     std::vector<double> U, V;
     std::vector<double> Vc;
     std::vector<std::pair<int64_t, int64_t>> pending_tile;   // (block, U offset): retiled once levels are known
+    if (H.adaptive) H.h_il_slevel.resize(nil);
     for (int64_t b = 0; b < nil; ++b) {
-        int32_t lv = F.r1<int32_t>(), kind = F.r1<int32_t>();
+        int32_t lv = F.r1<int32_t>(), kind = F.r1<int32_t>(), sl = lv;
+        if (H.adaptive) {
+            sl = F.r1<int32_t>();
+            (void)F.r1<int32_t>();
+            if (sl < 1 || sl > H.kappa) fail(H2D_EINVAL, "bad block source level");
+            H.h_il_slevel[b] = sl;
+        }
         int64_t t = F.r1<int64_t>(), u = F.r1<int64_t>(), k = F.r1<int64_t>();
         if (lv < 1 || lv > H.kappa) fail(H2D_EINVAL, "bad block level");
         const Level& L = H.lev[lv];
-        if (t < 0 || t >= L.nbox || u < 0 || u >= L.nbox || k < 0) fail(H2D_EINVAL, "bad block");
+        const Level& Ls = H.lev[sl];
+        if (t < 0 || t >= L.nbox || u < 0 || u >= Ls.nbox || k < 0) fail(H2D_EINVAL, "bad block");
         if (b > 0 && (lv < H.h_il_level[b - 1] || (lv == H.h_il_level[b - 1] && t < H.h_il_tgt[b - 1])))
             fail(H2D_EINVAL, "blocks not in (level, target) order");
-        int64_t m = L.h_count[t], nc = L.h_count[u];
+        int64_t m = L.h_count[t], nc = Ls.h_count[u];
         H.h_il_level[b] = lv; H.h_il_kind[b] = kind; H.h_il_tgt[b] = (int32_t)t; H.h_il_src[b] = (int32_t)u;
         H.h_il_k[b] = (int32_t)k;
         if (kind == kDense) {
@@ -329,6 +423,7 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
             const int64_t b = pt.first, o = pt.second;
             const Level& L = H.lev[H.h_il_level[b]];
             const int64_t m = L.h_count[H.h_il_tgt[b]], k = H.h_il_k[b];
+            if (H.adaptive) continue;   // adaptive trees keep U plain column-major
             tmp.assign(U.begin() + o, U.begin() + o + m * k);
             retile_u(H, H.h_il_level[b], L.h_begin[H.h_il_tgt[b]], m, k, tmp.data(), U.data() + o, true);
         }
@@ -389,7 +484,11 @@ h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int3
         if (n < 1 || n >= ((int64_t)1 << 31)) fail(H2D_EINVAL, "n must be in [1, 2^31)");
         if (leaf_max < 1) fail(H2D_EINVAL, "leaf_max must be >= 1");
         if (!(tol >= 0.0) || !std::isfinite(tol)) fail(H2D_EINVAL, "tol must be finite and >= 0");
-        if (prec_mask & ~7u) fail(H2D_EINVAL, "unknown precision bits");
+        if (prec_mask & ~(7u | H2D_BUILD_ADAPTIVE)) fail(H2D_EINVAL, "unknown precision or build bits");
+        const bool adaptive = (prec_mask & H2D_BUILD_ADAPTIVE) != 0;
+        prec_mask &= 7u;
+        if (adaptive && (prec_mask & ~1u))
+            fail(H2D_EUNSUPPORTED, "half-precision pools are not built for adaptive trees");
         check_kernel(kernel);
         hipStream_t s = (hipStream_t)stream;
         auto t0 = std::chrono::steady_clock::now();
@@ -397,12 +496,14 @@ h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int3
         Handle& H = up_->h;
         HIPCK(hipGetDevice(&H.device));
         H.n = n; H.leaf_max = leaf_max; H.tol = tol;
+        H.adaptive = adaptive;
         H.kern = KernelParams{kernel->kind, kernel->diag_mode, kernel->c, kernel->diag_value};
         H.xy.alloc((size_t)(2 * n));
         HIPCK(hipMemcpyAsync(H.xy.p, xy, sizeof(double) * 2 * n, hipMemcpyDefault, s));
         build_tree_and_lists(H, s);
         build_factors(H, s);
-        finalize(H, s);
+        if (adaptive) finalize_adaptive(H, s);
+        else finalize(H, s);
         make_half_pools(H, prec_mask, s);
         HIPCK(hipStreamSynchronize(s));
         H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -438,6 +539,8 @@ h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d
     h2d_status g = guarded([&] {
         if (!H || !b || !x || !opts) fail(H2D_EINVAL, "NULL argument");
         if (!(rtol > 0.0)) fail(H2D_EINVAL, "rtol must be > 0");
+        if (H->h.adaptive && (opts->mode != H2D_SOLVE_PLAIN || opts->precond != H2D_PC_NONE))
+            fail(H2D_EUNSUPPORTED, "adaptive trees solve with plain FP64 GMRES only");
         if (opts->restart < 1 || opts->max_iter < 1) fail(H2D_EINVAL, "restart and max_iter must be >= 1");
         {   // x is zeroed before b is read: the two must not overlap
             const uintptr_t b0 = (uintptr_t)b, x0 = (uintptr_t)x, len = sizeof(double) * (uintptr_t)H->h.n;
@@ -482,7 +585,12 @@ h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t*
         auto up_ = std::make_unique<h2d_s>();
         Handle& H = up_->h;
         import_handle(H, path, s);
-        finalize(H, s);
+        if (H.adaptive) {
+            if (prec_mask & ~1u) fail(H2D_EUNSUPPORTED, "half-precision pools are not built for adaptive trees");
+            finalize_adaptive(H, s);
+        } else {
+            finalize(H, s);
+        }
         make_half_pools(H, prec_mask, s);
         HIPCK(hipStreamSynchronize(s));
         H.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -510,6 +618,7 @@ h2d_status h2d_bj_setup(h2d_t H, void* stream)
 {
     return guarded([&] {
         if (!H) fail(H2D_EINVAL, "NULL handle");
+        if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "block-Jacobi is not built for adaptive trees");
         bj_setup(H->h, (hipStream_t)stream);
     });
 }
@@ -526,9 +635,11 @@ h2d_status h2d_mlp_train(h2d_t H, const h2d_mlp_train_opts* opts, h2d_mlp_train_
 {
     return guarded([&] {
         if (!H || !opts) fail(H2D_EINVAL, "NULL argument");
+        if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "the learned preconditioner is not built for adaptive trees");
         if (opts->n_solves < 1 || opts->steps < 0 || opts->batch < 1 || !(opts->lr > 0.f) ||
             (opts->target == H2D_MLP_TARGET_GLOBAL && !(opts->solve_tol > 0.0)) ||
-            (opts->target != H2D_MLP_TARGET_LEAF && opts->target != H2D_MLP_TARGET_GLOBAL))
+            (opts->target != H2D_MLP_TARGET_LEAF && opts->target != H2D_MLP_TARGET_GLOBAL &&
+             opts->target != H2D_MLP_TARGET_PATCH))
             fail(H2D_EINVAL, "bad training options");
         mlp_train(H->h, *opts, info, (hipStream_t)stream);
     });
@@ -555,6 +666,7 @@ h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, fl
 {
     return guarded([&] {
         if (!H || nrhs < 1) fail(H2D_EINVAL, "bad argument");
+        if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "tile tuning is not built for adaptive trees");
         autotune(H->h, nrhs, (hipStream_t)stream, chosen, ms);
     });
 }
@@ -563,6 +675,7 @@ h2d_status h2d_set_item_rows(h2d_t H, int32_t which, int32_t rows, void* stream)
 {
     return guarded([&] {
         if (!H) fail(H2D_EINVAL, "NULL handle");
+        if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "tile sizes are fixed for adaptive trees");
         if (which == H2D_TILE_A_ROWS) {
             if (rows < 16 || rows > kPhaseARows) fail(H2D_EINVAL, "phase-A item rows must lie in 16..512");
         } else if (which == H2D_TILE_MR_ROWS) {
@@ -590,6 +703,7 @@ h2d_status h2d_batch_create(h2d_t const* handles, int32_t count, int32_t nrhs, d
         std::vector<Handle*> hs(count);
         for (int i = 0; i < count; ++i) {
             if (!handles[i] || !x[i] || !y[i] || ld[i] < handles[i]->h.n) fail(H2D_EINVAL, "bad batch member");
+            if (handles[i]->h.adaptive) fail(H2D_EUNSUPPORTED, "adaptive trees are not batched");
             hs[i] = &handles[i]->h;
         }
         auto* r = new h2d_batch_s{batch_create(hs.data(), count, nrhs, x, y, ld)};

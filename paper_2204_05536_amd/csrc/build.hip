@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <numeric>
+#include <tuple>
 #include <cstring>
 #include <type_traits>
 
@@ -397,6 +398,220 @@ static std::vector<T> to_host(const T* d, size_t n, hipStream_t s)
     return h;
 }
 
+template <typename T>
+static void upload(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
+{
+    d.alloc(h.size());
+    if (!h.empty()) HIPCK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ---------------------------------------------------------------------
+// Adaptive tree (host).  A box is split exactly when it holds more than
+// leaf_max points (the adaptive form of the quadtree that the end of
+// Section 4 allows), so leaves sit at several levels.  Points are ordered by
+// (leaf, caller index), leaves in Morton order.  Blocks come from
+// descending pairs of boxes from (root, root): distinct boxes whose closed
+// squares share at most one point form one compressed block; two leaves
+// that share a segment, or a leaf with itself, one dense near-field block;
+// any other pair gives way to the pairs of its children (only the non-leaf
+// side splits when one side is a leaf).  On a balanced tree this is the
+// interaction-list and near-field structure of every level.
+// ---------------------------------------------------------------------
+static uint32_t compact16(uint32_t v)
+{
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+    v = (v | (v >> 4)) & 0x00FF00FFu;
+    v = (v | (v >> 8)) & 0x0000FFFFu;
+    return v;
+}
+
+// 1 when boxes (la, ka) and (lb, kb) have at most one common point.
+static bool boxes_admissible(int la, uint32_t ka, int lb, uint32_t kb)
+{
+    const int L = std::max(la, lb);
+    const int64_t sa = (int64_t)1 << (L - la), sb = (int64_t)1 << (L - lb);
+    const int64_t ax = compact16(ka) * sa, ay = compact16(ka >> 1) * sa;
+    const int64_t bx = compact16(kb) * sb, by = compact16(kb >> 1) * sb;
+    const int64_t wx = std::min(ax + sa, bx + sb) - std::max(ax, bx);
+    const int64_t wy = std::min(ay + sa, by + sb) - std::max(ay, by);
+    if (wx < 0 || wy < 0) return true;
+    return wx == 0 && wy == 0;
+}
+
+void adaptive_tree_and_lists(Handle& H, const DBuf<uint32_t>& skey, const DBuf<int32_t>& sidx, hipStream_t s)
+{
+    const int32_t n = (int32_t)H.n;
+    const int T = 256, G = (n + T - 1) / T;
+    const std::vector<uint32_t> key = to_host(skey.p, n, s);
+    std::vector<int32_t> idx = to_host(sidx.p, n, s);
+    // levels: children of every box above leaf_max are the runs of equal
+    // key prefix inside it
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        Level& L = H.lev[l];
+        L.nbox = 0;
+        L.h_key.clear(); L.h_begin.clear(); L.h_count.clear(); L.h_parent.clear();
+    }
+    {
+        Level& L0 = H.lev[0];
+        L0.nbox = 1;
+        L0.h_key = {0u}; L0.h_begin = {0}; L0.h_count = {n}; L0.h_parent = {-1};
+    }
+    int kappa = 0;
+    for (int l = 0; l < kMaxLevel; ++l) {
+        const Level& P = H.lev[l];
+        Level& C = H.lev[l + 1];
+        const int sh = 2 * (kMaxLevel - (l + 1));
+        for (int64_t b = 0; b < P.nbox; ++b) {
+            if (P.h_count[b] <= H.leaf_max) continue;
+            const int32_t e = P.h_begin[b] + P.h_count[b];
+            for (int32_t i = P.h_begin[b]; i < e;) {
+                const uint32_t k = key[i] >> sh;
+                int32_t j = i + 1;
+                while (j < e && (key[j] >> sh) == k) ++j;
+                C.h_key.push_back(k);
+                C.h_begin.push_back(i);
+                C.h_count.push_back(j - i);
+                C.h_parent.push_back((int32_t)b);
+                i = j;
+            }
+        }
+        C.nbox = (int64_t)C.h_key.size();
+        if (!C.nbox) break;
+        kappa = l + 1;
+    }
+    for (int64_t b = 0; b < H.lev[kappa].nbox; ++b)
+        if (H.lev[kappa].h_count[b] > H.leaf_max)
+            fail(H2D_EDEPTH, "more than leaf_max points share a depth-16 box");
+    H.kappa = kappa;
+    // leaves (tree order), caller order inside each leaf
+    std::vector<std::vector<int32_t>> nchild(kappa + 1);
+    for (int l = 0; l <= kappa; ++l) {
+        nchild[l].assign(H.lev[l].nbox, 0);
+        if (l > 0)
+            for (int32_t p : H.lev[l].h_parent) nchild[l - 1][p]++;
+    }
+    std::vector<std::vector<int32_t>> leafno(kappa + 1);
+    {
+        std::vector<std::pair<int32_t, std::pair<int32_t, int32_t>>> lv;   // (begin, (level, box))
+        for (int l = 0; l <= kappa; ++l) {
+            leafno[l].assign(H.lev[l].nbox, -1);
+            for (int64_t b = 0; b < H.lev[l].nbox; ++b)
+                if (!nchild[l][b]) lv.push_back({H.lev[l].h_begin[b], {l, (int32_t)b}});
+        }
+        std::sort(lv.begin(), lv.end());
+        H.h_leaf_level.clear(); H.h_leaf_box.clear(); H.h_leaf_begin.clear(); H.h_leaf_count.clear();
+        for (size_t q = 0; q < lv.size(); ++q) {
+            const int l = lv[q].second.first, b = lv[q].second.second;
+            leafno[l][b] = (int32_t)q;
+            H.h_leaf_level.push_back(l);
+            H.h_leaf_box.push_back(b);
+            H.h_leaf_begin.push_back(H.lev[l].h_begin[b]);
+            H.h_leaf_count.push_back(H.lev[l].h_count[b]);
+            std::sort(idx.begin() + H.lev[l].h_begin[b], idx.begin() + H.lev[l].h_begin[b] + H.lev[l].h_count[b]);
+        }
+    }
+    H.h_perm = idx;
+    upload(H.perm, idx, s);
+    H.xyt.alloc((size_t)2 * n);
+    k_gather_xy<<<G, T, 0, s>>>(H.xy.p, H.perm.p, n, H.xyt.p);
+    HIPCK(hipGetLastError());
+    for (int l = 0; l <= kappa; ++l) {
+        Level& L = H.lev[l];
+        upload(L.key, L.h_key, s);
+        upload(L.begin, L.h_begin, s);
+        upload(L.count, L.h_count, s);
+        upload(L.parent, L.h_parent, s);
+    }
+    if (H.kern.kind == H2D_K_LOG || H.kern.kind == H2D_K_INVR) {   // duplicates: two points in one leaf
+        DBuf<int32_t> lb, lc;
+        DBuf<int> bad;
+        upload(lb, H.h_leaf_begin, s);
+        upload(lc, H.h_leaf_count, s);
+        bad.alloc(1);
+        HIPCK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        const int32_t nl = (int32_t)H.h_leaf_begin.size();
+        k_dups<<<(unsigned)nl, 256, 0, s>>>(H.xyt.p, lb.p, lc.p, nl, bad.p);
+        HIPCK(hipGetLastError());
+        int hbad = 0;
+        HIPCK(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        if (hbad) fail(H2D_EDUP, "two distinct points coincide; the kernel is singular at r = 0");
+    }
+    // pair descent
+    std::vector<std::vector<int32_t>> child0(kappa + 1);
+    for (int l = 0; l <= kappa; ++l) {
+        child0[l].assign(H.lev[l].nbox, -1);
+        if (l < kappa)
+            for (int64_t c = H.lev[l + 1].nbox - 1; c >= 0; --c) child0[l][H.lev[l + 1].h_parent[c]] = (int32_t)c;
+    }
+    struct Pair { int32_t la, a, lb, b; };
+    std::vector<Pair> stack{{0, 0, 0, 0}}, il, near;
+    while (!stack.empty()) {
+        const Pair P = stack.back();
+        stack.pop_back();
+        const bool leafA = !nchild[P.la][P.a], leafB = !nchild[P.lb][P.b];
+        const bool same = P.la == P.lb && P.a == P.b;
+        if (!same && boxes_admissible(P.la, H.lev[P.la].h_key[P.a], P.lb, H.lev[P.lb].h_key[P.b])) {
+            il.push_back(P);
+            continue;
+        }
+        if (leafA && leafB) {
+            near.push_back(P);
+            continue;
+        }
+        const int32_t a0 = leafA ? P.a : child0[P.la][P.a], na = leafA ? 1 : nchild[P.la][P.a];
+        const int32_t b0 = leafB ? P.b : child0[P.lb][P.b], nb = leafB ? 1 : nchild[P.lb][P.b];
+        const int32_t la = leafA ? P.la : P.la + 1, lb = leafB ? P.lb : P.lb + 1;
+        for (int32_t i = 0; i < na; ++i)
+            for (int32_t j = 0; j < nb; ++j) stack.push_back({la, a0 + i, lb, b0 + j});
+    }
+    auto order = [](const Pair& x, const Pair& y) {
+        return std::tie(x.la, x.a, x.lb, x.b) < std::tie(y.la, y.a, y.lb, y.b);
+    };
+    std::sort(il.begin(), il.end(), order);
+    // near blocks grouped by target leaf (tree order), then (source level, source)
+    std::sort(near.begin(), near.end(), [&](const Pair& x, const Pair& y) {
+        const int32_t lx = leafno[x.la][x.a], ly = leafno[y.la][y.a];
+        return std::tie(lx, x.lb, x.b) < std::tie(ly, y.lb, y.b);
+    });
+    const int32_t nleaf = (int32_t)H.h_leaf_level.size();
+    H.h_near_ptr.assign(nleaf + 1, 0);
+    H.h_near_src.resize(near.size());
+    for (size_t q = 0; q < near.size(); ++q) {
+        H.h_near_ptr[leafno[near[q].la][near[q].a] + 1]++;
+        H.h_near_src[q] = leafno[near[q].lb][near[q].b];
+    }
+    for (int32_t x = 0; x < nleaf; ++x) H.h_near_ptr[x + 1] += H.h_near_ptr[x];
+    H.n_il = (int64_t)il.size();
+    H.h_il_level.resize(il.size()); H.h_il_tgt.resize(il.size());
+    H.h_il_slevel.resize(il.size()); H.h_il_src.resize(il.size());
+    for (size_t q = 0; q < il.size(); ++q) {
+        H.h_il_level[q] = il[q].la; H.h_il_tgt[q] = il[q].a;
+        H.h_il_slevel[q] = il[q].lb; H.h_il_src[q] = il[q].b;
+    }
+    adaptive_index(H, s);
+}
+
+void adaptive_index(Handle& H, hipStream_t s)
+{
+    // per-level CSR of the blocks by target box (absolute block index)
+    for (int l = 0; l <= H.kappa; ++l) H.lev[l].h_il_ptr.assign(H.lev[l].nbox + 1, 0);
+    for (int64_t b = 0; b < H.n_il; ++b) H.lev[H.h_il_level[b]].h_il_ptr[H.h_il_tgt[b] + 1]++;
+    int64_t run = 0;
+    for (int l = 0; l <= H.kappa; ++l) {
+        Level& L = H.lev[l];
+        L.h_il_ptr[0] = (int32_t)run;
+        for (int64_t x = 0; x < L.nbox; ++x) L.h_il_ptr[x + 1] += L.h_il_ptr[x];
+        run = L.h_il_ptr[L.nbox];
+        upload(L.il_ptr, L.h_il_ptr, s);
+    }
+    upload(H.near_ptr, H.h_near_ptr, s);
+    upload(H.leaf_level, H.h_leaf_level, s);
+    upload(H.leaf_box, H.h_leaf_box, s);
+}
+
 void build_tree_and_lists(Handle& H, hipStream_t s)
 {
     const int32_t n = (int32_t)H.n;
@@ -432,6 +647,10 @@ void build_tree_and_lists(Handle& H, hipStream_t s)
     HIPCK(hipMemcpyAsync(skey.p, key16.p, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
     HIPCK(hipMemcpyAsync(sidx.p, idx.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
     radix_sort(skey, sidx, n, 32, s);
+    if (H.adaptive) {
+        adaptive_tree_and_lists(H, skey, sidx, s);
+        return;
+    }
     DBuf<int32_t> maxrun;
     maxrun.alloc(kMaxLevel + 1);
     HIPCK(hipMemsetAsync(maxrun.p, 0, sizeof(int32_t) * (kMaxLevel + 1), s));
@@ -807,13 +1026,6 @@ __global__ void k_dense(const DenseJob* jobs, const double* xyt, KernelParams kp
     }
 }
 
-template <typename T>
-static void upload(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
-{
-    d.alloc(h.size());
-    if (!h.empty()) HIPCK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
-
 void build_factors(Handle& H, hipStream_t s)
 {
     const int kappa = H.kappa;
@@ -823,10 +1035,11 @@ void build_factors(Handle& H, hipStream_t s)
     std::vector<int32_t> m(nil), n(nil), r0(nil), c0(nil);
     for (int64_t b = 0; b < nil; ++b) {
         const Level& L = H.lev[H.h_il_level[b]];
+        const Level& Ls = H.lev[il_src_level(H, b)];
         m[b] = L.h_count[H.h_il_tgt[b]];
-        n[b] = L.h_count[H.h_il_src[b]];
+        n[b] = Ls.h_count[H.h_il_src[b]];
         r0[b] = L.h_begin[H.h_il_tgt[b]];
-        c0[b] = L.h_begin[H.h_il_src[b]];
+        c0[b] = Ls.h_begin[H.h_il_src[b]];
     }
     // row -> (begin, size) of its box one level above the leaves
     DBuf<int32_t> tbeg, tcnt;
@@ -888,7 +1101,9 @@ void build_factors(Handle& H, hipStream_t s)
             H.h_il_kind[bb] = hk[q];
             H.h_il_k[bb] = hr[q];
             if (hk[q] == kLowRank && hr[q] > 0) {
-                const int32_t tiled = H.h_il_level[bb] <= kappa - 1 ? 1 : 0;
+                // U tiled by the boxes one level above the leaves (balanced
+                // trees); plain column-major on an adaptive tree
+                const int32_t tiled = (!H.adaptive && H.h_il_level[bb] <= kappa - 1) ? 1 : 0;
                 packs.push_back(PackJob{jobs[q].uoff, jobs[q].voff, C.ue, C.ve, m[bb], n[bb], hr[q], tiled, r0[bb], 0});
                 C.ue += (int64_t)m[bb] * hr[q];
                 C.ve += (int64_t)n[bb] * hr[q];
@@ -915,13 +1130,24 @@ void build_factors(Handle& H, hipStream_t s)
     int64_t nnear = (int64_t)H.h_near_src.size();
     H.h_near_off.assign(nnear, 0);
     std::vector<DenseJob> dj;
-    for (int64_t x = 0; x < LL.nbox; ++x)
-        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
-            int32_t y = H.h_near_src[q];
-            H.h_near_off[q] = de;
-            dj.push_back(DenseJob{de, LL.h_begin[x], LL.h_count[x], LL.h_begin[y], LL.h_count[y]});
-            de += (int64_t)LL.h_count[x] * LL.h_count[y];
-        }
+    if (H.adaptive) {   // near CSR over leaf numbers
+        const int64_t nleaf = (int64_t)H.h_leaf_begin.size();
+        for (int64_t x = 0; x < nleaf; ++x)
+            for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+                const int32_t y = H.h_near_src[q];
+                H.h_near_off[q] = de;
+                dj.push_back(DenseJob{de, H.h_leaf_begin[x], H.h_leaf_count[x], H.h_leaf_begin[y], H.h_leaf_count[y]});
+                de += (int64_t)H.h_leaf_count[x] * H.h_leaf_count[y];
+            }
+    } else {
+        for (int64_t x = 0; x < LL.nbox; ++x)
+            for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+                int32_t y = H.h_near_src[q];
+                H.h_near_off[q] = de;
+                dj.push_back(DenseJob{de, LL.h_begin[x], LL.h_count[x], LL.h_begin[y], LL.h_count[y]});
+                de += (int64_t)LL.h_count[x] * LL.h_count[y];
+            }
+    }
     for (int64_t q = 0; q < nil; ++q) {
         if (H.h_il_kind[q] == kDense) {
             H.h_il_off[q] = de;

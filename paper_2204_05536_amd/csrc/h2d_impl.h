@@ -187,9 +187,19 @@ struct Handle {
     std::vector<int32_t> h_near_ptr, h_near_src;
     std::vector<int64_t> h_near_off;  // D pool offsets
 
-    // interaction-list block table, (level, tgt, src) order
+    // adaptive tree (leaves at several levels): leaves numbered in tree
+    // order; the near CSR (near_ptr, h_near_src) is then over leaf numbers
+    bool adaptive = false;
+    std::vector<int32_t> h_leaf_level, h_leaf_box, h_leaf_begin, h_leaf_count;
+    DBuf<int32_t> leaf_level, leaf_box;
+    DBuf<int2> ad_items;         // adaptive phase-B work: (leaf, first row of a 64-row chunk)
+    int64_t n_ad_items = 0;
+
+    // interaction-list block table, (level, tgt, src) order (adaptive:
+    // (target level, tgt, source level, src); h_il_slevel holds the source
+    // levels, empty for a balanced tree where they equal h_il_level)
     int64_t n_il = 0;
-    std::vector<int32_t> h_il_level, h_il_tgt, h_il_src, h_il_kind, h_il_k;
+    std::vector<int32_t> h_il_level, h_il_tgt, h_il_src, h_il_kind, h_il_k, h_il_slevel;
     std::vector<int64_t> h_il_off;    // U pool offset (low rank) or D pool offset (dense)
     std::vector<int64_t> h_il_voff;   // V pool offset (low rank)
     std::vector<int32_t> h_il_toff;   // t pool offset (low rank)
@@ -287,6 +297,14 @@ void profile_read(Handle& H, h2d_profile* out);
 
 // build.hip
 void build_tree_and_lists(Handle& H, hipStream_t s);
+// Adaptive tree and block lists from the points sorted by (depth-16 key,
+// caller index); host code (the rest of the build runs on the device).
+void adaptive_tree_and_lists(Handle& H, const DBuf<uint32_t>& skey, const DBuf<int32_t>& sidx, hipStream_t s);
+// Leaf arrays and per-level block CSR of an adaptive handle from its host
+// tables (build and import).
+void adaptive_index(Handle& H, hipStream_t s);
+void finalize_adaptive(Handle& H, hipStream_t s);
+inline int32_t il_src_level(const Handle& H, int64_t b) { return H.h_il_slevel.empty() ? H.h_il_level[b] : H.h_il_slevel[b]; }
 void build_factors(Handle& H, hipStream_t s);
 void make_half_pools(Handle& H, uint32_t mask, hipStream_t s);
 

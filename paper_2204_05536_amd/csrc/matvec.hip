@@ -666,6 +666,61 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
     }
 }
 
+// Phase B on an adaptive tree (leaves at several levels).  One wave per
+// 64-row chunk of a leaf; lane r owns one row and sums, in a fixed order,
+// the leaf's dense near-field blocks, then the blocks whose target is the
+// leaf or one of its ancestors, from the leaf up.  U and D are plain
+// column-major (ld = the target box's size), so the lanes' loads of one
+// column are consecutive.
+__global__ void __launch_bounds__(256)
+k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t* __restrict__ leaf_level,
+                  const int32_t* __restrict__ leaf_box, LevelPtrs L, const int32_t* __restrict__ near_ptr,
+                  const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil, const double* __restrict__ Up,
+                  const double* __restrict__ Dp, const double* __restrict__ tpool, const double* __restrict__ xs,
+                  double* __restrict__ y)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t it = blockIdx.x * 4 + wave;
+    if (it >= nitems) return;
+    const int2 w = items[it];
+    const int32_t X = uni(w.x), rc = uni(w.y);
+    const int lx = uni(leaf_level[X]);
+    const int32_t box = uni(leaf_box[X]);
+    const int32_t r0 = uni(L.begin[lx][box]), cnt = uni(L.count[lx][box]);
+    const bool act = rc + lane < cnt;
+    const int32_t row = r0 + rc + lane;
+    double acc = 0.0;
+    const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
+    for (int32_t q = n0; q < n1; ++q) {
+        const BDesc d = uni(bnear[q]);
+        if (!act) continue;
+        const double* base = Dp + d.off + rc + lane;
+        const double* xv = xs + d.tsrc;
+        for (int32_t j = 0; j < -d.cols; ++j) acc += base[(int64_t)j * cnt] * xv[j];
+    }
+    int32_t a = box;
+    for (int l = lx; l >= 1; --l) {
+        const int32_t ab = uni(L.begin[l][a]), m = uni(L.count[l][a]);
+        const int32_t q0 = uni(L.il_ptr[l][a]), q1 = uni(L.il_ptr[l][a + 1]);
+        for (int32_t q = q0; q < q1; ++q) {
+            const BDesc d = uni(bil[q]);
+            if (!act || d.cols == 0) continue;
+            const int64_t roff = (int64_t)(row - ab);
+            if (d.cols > 0) {
+                const double* base = Up + d.off + roff;
+                const double* tv = tpool + d.tsrc;
+                for (int32_t c = 0; c < d.cols; ++c) acc += base[(int64_t)c * m] * tv[c];
+            } else {
+                const double* base = Dp + d.off + roff;
+                const double* xv = xs + d.tsrc;
+                for (int32_t j = 0; j < -d.cols; ++j) acc += base[(int64_t)j * m] * xv[j];
+            }
+        }
+        a = uni(L.parent[l][a]);
+    }
+    if (act) y[row] = acc;
+}
+
 // y (caller order) = ypart + yleaf (+ the FP32 self diagonal times x for
 // the half pools), one thread per tree row.
 template <typename A, bool kHalf>
@@ -836,6 +891,101 @@ void finalize(Handle& H, hipStream_t s)
     HIPCK(hipStreamSynchronize(s));
 }
 
+// Device tables and the matvec schedule of an adaptive handle: phase A as
+// for a balanced tree (items per block and row range of its source box),
+// phase B one item per 64-row chunk of every leaf.
+void finalize_adaptive(Handle& H, hipStream_t s)
+{
+    const int kappa = H.kappa;
+    for (int l = 0; l <= kappa; ++l) {
+        Level& L = H.lev[l];
+        if (L.h_il_ptr.empty()) L.h_il_ptr.assign(L.nbox + 1, 0);
+        upload_vec(L.il_ptr, L.h_il_ptr, s);
+    }
+    upload_vec(H.near_ptr, H.h_near_ptr, s);
+    upload_vec(H.leaf_level, H.h_leaf_level, s);
+    upload_vec(H.leaf_box, H.h_leaf_box, s);
+    const int64_t nleaf = (int64_t)H.h_leaf_level.size();
+    std::vector<BDesc> bn(H.h_near_src.size());
+    double store = 0, flops = 0;
+    for (int64_t x = 0; x < nleaf; ++x)
+        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+            const int32_t y = H.h_near_src[q];
+            bn[q] = BDesc{H.h_near_off[q], -H.h_leaf_count[y], H.h_leaf_begin[y]};
+            store += (double)H.h_leaf_count[x] * H.h_leaf_count[y];
+        }
+    flops += 2.0 * store;
+    upload_vec(H.bnear, bn, s);
+    const int64_t nil = H.n_il;
+    std::vector<BDesc> bi(nil);
+    std::vector<ADesc> items;
+    std::vector<RDesc> red;
+    H.h_il_toff.assign(nil, -1);
+    int64_t toff = 0, poff = 0;
+    H.max_rank = 0; H.sum_rank = 0; H.n_il_dense = 0;
+    const int32_t ar = std::max(16, std::min<int32_t>(H.a_rows, kPhaseARows));
+    for (int64_t b = 0; b < nil; ++b) {
+        const Level& L = H.lev[H.h_il_level[b]];
+        const Level& Ls = H.lev[il_src_level(H, b)];
+        const int32_t m = L.h_count[H.h_il_tgt[b]], n = Ls.h_count[H.h_il_src[b]], c0 = Ls.h_begin[H.h_il_src[b]];
+        if (H.h_il_kind[b] == kDense) {
+            bi[b] = BDesc{H.h_il_off[b], -n, c0};
+            H.n_il_dense++;
+            store += (double)m * n;
+            flops += 2.0 * m * n;
+            continue;
+        }
+        const int32_t k = H.h_il_k[b];
+        H.max_rank = std::max<int64_t>(H.max_rank, k);
+        H.sum_rank += k;
+        bi[b] = BDesc{H.h_il_off[b], k, (int32_t)toff};
+        if (k == 0) continue;
+        H.h_il_toff[b] = (int32_t)toff;
+        store += (double)m * k;
+        flops += 2.0 * k * (double)(m + n);
+        if (n <= ar) {
+            items.push_back(ADesc{H.h_il_voff[b], 0, n, c0, k, (int32_t)toff, (int32_t)b});
+        } else {
+            const int32_t parts = (n + ar - 1) / ar;
+            red.push_back(RDesc{(int32_t)toff, k, (int32_t)poff, parts});
+            for (int32_t p = 0; p < parts; ++p) {
+                const int32_t j0 = p * ar, j1 = std::min(n, j0 + ar);
+                items.push_back(ADesc{H.h_il_voff[b], j0, j1, c0, k, (int32_t)(-(poff + (int64_t)p * k) - 1), (int32_t)b});
+            }
+            poff += (int64_t)parts * k;
+        }
+        toff += k;
+    }
+    std::stable_sort(items.begin(), items.end(), [](const ADesc& x, const ADesc& y) {
+        return (int64_t)(x.j1 - x.j0) * x.k > (int64_t)(y.j1 - y.j0) * y.k;
+    });
+    std::vector<int2> ad;
+    for (int64_t x = 0; x < nleaf; ++x)
+        for (int32_t rc = 0; rc < H.h_leaf_count[x]; rc += kWave) ad.push_back(make_int2((int32_t)x, rc));
+    H.n_ad_items = (int64_t)ad.size();
+    upload_vec(H.ad_items, ad, s);
+    H.n_b1 = H.n_b1s = H.n_b1h = H.n_b2 = 0;
+    H.flops = flops;
+    H.t_elems = toff; H.p_elems = poff;
+    const double nvec = (double)H.n;
+    H.phase_bytes[0][0] = nvec * (8 + 4 + 8);
+    H.phase_bytes[0][1] = (double)H.v_elems * 8 + nvec * 8 + (double)toff * 8 + (double)poff * 8;
+    H.phase_bytes[0][2] = poff ? (double)poff * 8 + (double)toff * 8 : 0.0;
+    H.phase_bytes[0][3] = store * 8 + (double)toff * 8 + nvec * 8;
+    H.phase_bytes[0][4] = nvec * (8 + 4 + 8);
+    H.alg_bytes_fp64 = 0;
+    for (int p = 0; p < 5; ++p) H.alg_bytes_fp64 += H.phase_bytes[0][p];
+    H.alg_bytes_half = 0;
+    upload_vec(H.bil, bi, s);
+    upload_vec(H.aitems, items, s);
+    upload_vec(H.ritems, red, s);
+    H.n_aitems = (int64_t)items.size();
+    H.n_ritems = (int64_t)red.size();
+    H.ws_nrhs = 0;
+    H.mr_cap = 0;
+    HIPCK(hipStreamSynchronize(s));
+}
+
 void ensure_workspace(Handle& H, int nrhs)
 {
     if (H.ws_nrhs >= nrhs) return;
@@ -896,6 +1046,24 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
     if (ev) HIPCK(hipEventRecord(ev[3], s));
     const LevelPtrs LP = level_ptrs(H);
+    if constexpr (!kHalf) {
+        if (H.adaptive) {
+            double* yl = yp + n;
+            if (H.n_ad_items)
+                k_phaseB_adaptive<<<(unsigned)((H.n_ad_items + 3) / 4), 256, 0, s>>>(
+                    (int32_t)H.n_ad_items, H.ad_items.p, H.leaf_level.p, H.leaf_box.p, LP, H.near_ptr.p, H.bnear.p,
+                    H.bil.p, U, D, tp, xs, yl);
+            if (ev) HIPCK(hipEventRecord(ev[4], s));
+            k_combine<double, false><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, nullptr, yl, H.perm.p, nullptr, xs,
+                                                                                y);
+            if (ev) {
+                HIPCK(hipEventRecord(ev[5], s));
+                H.prof_used++;
+            }
+            HIPCK(hipGetLastError());
+            return;
+        }
+    }
     // the half pools' 64-row form walks runs of row quads (b1h_items)
     const bool quads = kHalf && H.b1_rows == kWave;
     const int32_t ni = (int32_t)(quads ? H.n_b1h : H.n_b1s);
@@ -946,7 +1114,7 @@ void profile_read(Handle& H, h2d_profile* out)
 
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s)
 {
-    if (nrhs > 1 && prec == H2D_P_FP64) {   // blocks of 16 right-hand sides on the matrix cores
+    if (nrhs > 1 && prec == H2D_P_FP64 && !H.adaptive) {   // blocks of 16 right-hand sides on the matrix cores
         launch_matvec_mr(H, x, y, nrhs, ld, s);
         return;
     }

@@ -91,6 +91,35 @@ static void gemm(int M, int N, int K, const float* A, int lda, bool tA, const fl
     HIPCK(hipGetLastError());
 }
 
+// C (M x N, ldc = N) = sum over the S slices of partial products, slice q
+// covering K rows [q K / S, (q + 1) K / S) of op(A) and op(B); partials
+// summed in slice order (fixed).  For the weight gradients, where the
+// inner dimension is the batch and M x N is only a few 64 x 64 tiles.
+__global__ void k_sum_slices(int64_t mn, int S, const float* __restrict__ P, float* __restrict__ C)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        for (int q = 0; q < S; ++q) v += P[(int64_t)q * mn + e];
+        C[e] = v;
+    }
+}
+
+static void gemm_tn_split(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, float* work,
+                          int S, hipStream_t s)
+{
+    // op(A) = A^T (A stored K x M), op(B) = B (K x N); slice q of K
+    const int kq = (K + S - 1) / S;
+    for (int q = 0; q < S; ++q) {
+        const int k0 = q * kq, kk = std::max(0, std::min(K, k0 + kq) - k0);
+        dim3 g((N + 63) / 64, (M + 63) / 64);
+        k_gemm<<<g, 256, 0, s>>>(M, N, kk, A + (int64_t)k0 * lda, lda, 1, B + (int64_t)k0 * ldb, ldb, 0,
+                                 work + (int64_t)q * M * N, N, 1.f, 0.f);
+    }
+    const int64_t mn = (int64_t)M * N;
+    k_sum_slices<<<(int)std::min<int64_t>(1024, (mn + 255) / 256), 256, 0, s>>>(mn, S, work, C);
+    HIPCK(hipGetLastError());
+}
+
 // Z (M x N) += bias (per column), then optional ReLU.
 __global__ void k_bias_act(int64_t M, int N, const float* __restrict__ bias, float* __restrict__ Z, int relu)
 {
@@ -107,21 +136,57 @@ __global__ void k_relu_back(int64_t M, int N, const float* __restrict__ Hh, floa
         if (!(Hh[e] > 0.f)) G[e] = 0.f;
 }
 
-// db (N) = column sums of G (M x N), fixed order.
-__global__ void k_colsum(int64_t M, int N, const float* __restrict__ G, float* __restrict__ db)
+// db (N) = column sums of G (M x N) in two fixed-order stages: block
+// (c, q) sums rows q, q + Q, ... of columns 64 c .. 64 c + 63 (4 row
+// groups per block, combined in LDS), then one pass adds the Q partials.
+constexpr int kColQ = 64;
+__global__ void __launch_bounds__(256)
+k_colsum_part(int64_t M, int N, const float* __restrict__ G, float* __restrict__ part)
+{
+    __shared__ float red[4][64];
+    const int c = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int j = blockIdx.x * 64 + c, q = blockIdx.y;
+    float v = 0.f;
+    if (j < N)
+        for (int64_t i = q + (int64_t)kColQ * g; i < M; i += 4 * kColQ) v += G[i * N + j];
+    red[g][c] = v;
+    __syncthreads();
+    if (g == 0 && j < N) part[(int64_t)q * N + j] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+__global__ void k_colsum_final(int N, const float* __restrict__ part, float* __restrict__ db)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
+    float v = 0.f;
+    for (int q = 0; q < kColQ; ++q) v += part[(int64_t)q * N + j];
+    db[j] = v;
+}
+
+// count[0] = sum of the mask (one workgroup, fixed order), at least 1.
+__global__ void __launch_bounds__(256) k_masksum(int64_t n, const float* __restrict__ Mk, float* __restrict__ count)
+{
+    __shared__ float red[256];
     float s = 0.f;
-    for (int64_t i = 0; i < M; ++i) s += G[i * N + j];
-    db[j] = s;
+    for (int64_t e = threadIdx.x; e < n; e += 256) s += Mk[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count[0] = fmaxf(red[0], 1.f);
 }
 
 // dO = mask (O - T) / count; partial loss sums per block (fixed order).
+// The count is read from device memory (count_d) when given, else taken
+// from inv_count.
 __global__ void k_mse(int64_t n, const float* __restrict__ O, const float* __restrict__ T, const float* __restrict__ Mk,
-                      float inv_count, float* __restrict__ dO, float* __restrict__ part)
+                      float inv_count, const float* __restrict__ count_d, float* __restrict__ dO,
+                      float* __restrict__ part)
 {
     __shared__ float red[256];
+    if (count_d) inv_count = 1.f / count_d[0];
     float s = 0.f;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const float d = (O[e] - T[e]) * Mk[e];
@@ -153,18 +218,31 @@ __global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict
 // Forward and backward on a batch (X: B x 192, targets T and mask Mk:
 // B x 64).  Workspace: H1, H2 (B x 256), O (B x 64), G1, G2, GO.
 // ---------------------------------------------------------------------
+constexpr int kSplitMax = 16;   // K slices of the weight-gradient products
 struct MlpWork {
     int64_t cap = 0;
-    DBuf<float> h1, h2, o, g1, g2, go, part;
+    DBuf<float> h1, h2, o, g1, g2, go, part, split, colp, count;
     void ensure(int64_t B)
     {
         if (B <= cap) return;
         h1.alloc(B * kH); h2.alloc(B * kH); o.alloc(B * kOut);
         g1.alloc(B * kH); g2.alloc(B * kH); go.alloc(B * kOut);
         part.alloc(1024);
+        split.alloc((size_t)kSplitMax * kH * kH);
+        colp.alloc((size_t)kColQ * kH);
+        count.alloc(1);
         cap = B;
     }
 };
+
+static void colsum(int64_t M, int N, const float* G, float* db, MlpWork& w, hipStream_t s)
+{
+    k_colsum_part<<<dim3((N + 63) / 64, kColQ), 256, 0, s>>>(M, N, G, w.colp.p);
+    k_colsum_final<<<(N + 255) / 256, 256, 0, s>>>(N, w.colp.p, db);
+}
+
+// K slices for a weight-gradient product with inner dimension B
+static int splits_for(int64_t B) { return (int)std::max<int64_t>(1, std::min<int64_t>(kSplitMax, B / 256)); }
 
 static int grid_for(int64_t n) { return (int)std::min<int64_t>(4096, (n + 255) / 256); }
 
@@ -181,27 +259,38 @@ static void forward(const float* W, const float* X, int64_t B, MlpWork& w, hipSt
 
 // loss = sum mask (O - T)^2 / (2 count); grad in the packed layout.  The
 // loss is read back (synchronising) only when want_loss.
+// count > 0: the mask sum given by the caller; count <= 0: summed on the
+// device from Mk (no host round trip).
 static float loss_grad(const float* W, const float* X, const float* T, const float* Mk, int64_t B, float count,
                        float* grad, MlpWork& w, hipStream_t s, bool want_loss = true)
 {
     w.ensure(B);
     forward(W, X, B, w, s);
     const int nb = std::min<int64_t>(1024, (B * kOut + 255) / 256);
-    k_mse<<<nb, 256, 0, s>>>(B * kOut, w.o.p, T, Mk, 1.f / count, w.go.p, w.part.p);
+    if (count <= 0.f) {
+        k_masksum<<<1, 256, 0, s>>>(B * kOut, Mk, w.count.p);
+        k_mse<<<nb, 256, 0, s>>>(B * kOut, w.o.p, T, Mk, 1.f, w.count.p, w.go.p, w.part.p);
+    } else {
+        k_mse<<<nb, 256, 0, s>>>(B * kOut, w.o.p, T, Mk, 1.f / count, nullptr, w.go.p, w.part.p);
+    }
+    const int S = splits_for(B);
     // layer 3
-    gemm(kOut, kH, (int)B, w.go.p, kOut, true, w.h2.p, kH, false, grad + kOffW3, kH, 1.f, 0.f, s);
-    k_colsum<<<1, kOut, 0, s>>>(B, kOut, w.go.p, grad + kOffB3);
+    gemm_tn_split(kOut, kH, (int)B, w.go.p, kOut, w.h2.p, kH, grad + kOffW3, w.split.p, S, s);
+    colsum(B, kOut, w.go.p, grad + kOffB3, w, s);
     gemm((int)B, kH, kOut, w.go.p, kOut, false, W + kOffW3, kH, false, w.g2.p, kH, 1.f, 0.f, s);
     k_relu_back<<<grid_for(B * kH), 256, 0, s>>>(B, kH, w.h2.p, w.g2.p);
     // layer 2
-    gemm(kH, kH, (int)B, w.g2.p, kH, true, w.h1.p, kH, false, grad + kOffW2, kH, 1.f, 0.f, s);
-    k_colsum<<<1, kH, 0, s>>>(B, kH, w.g2.p, grad + kOffB2);
+    gemm_tn_split(kH, kH, (int)B, w.g2.p, kH, w.h1.p, kH, grad + kOffW2, w.split.p, S, s);
+    colsum(B, kH, w.g2.p, grad + kOffB2, w, s);
     gemm((int)B, kH, kH, w.g2.p, kH, false, W + kOffW2, kH, false, w.g1.p, kH, 1.f, 0.f, s);
     k_relu_back<<<grid_for(B * kH), 256, 0, s>>>(B, kH, w.h1.p, w.g1.p);
     // layer 1
-    gemm(kH, kIn, (int)B, w.g1.p, kH, true, X, kIn, false, grad + kOffW1, kIn, 1.f, 0.f, s);
-    k_colsum<<<1, kH, 0, s>>>(B, kH, w.g1.p, grad + kOffB1);
+    gemm_tn_split(kH, kIn, (int)B, w.g1.p, kH, X, kIn, grad + kOffW1, w.split.p, S, s);
+    colsum(B, kH, w.g1.p, grad + kOffB1, w, s);
     HIPCK(hipGetLastError());
+    if (want_loss && count <= 0.f) {
+        HIPCK(hipMemcpyAsync(&count, w.count.p, sizeof(float), hipMemcpyDeviceToHost, s));
+    }
     if (!want_loss) return 0.f;
     std::vector<float> part(nb);
     HIPCK(hipMemcpyAsync(part.data(), w.part.p, sizeof(float) * nb, hipMemcpyDeviceToHost, s));
@@ -354,20 +443,27 @@ __global__ void k_random(int64_t n, uint64_t seed, double* __restrict__ out)
         out[e] = uniform_pm1(seed, (uint64_t)e);
 }
 
-// Gather rows idx[b] of F (192), T and Mk (64) into a batch.
-__global__ void k_gather_batch(int32_t B, const int32_t* __restrict__ idx, const float* __restrict__ F,
+// Batch of step `it`: sample index of row b = splitmix64 of (seed, it B + b)
+// modulo nsamp, then rows of F (192), T and Mk (64) gathered (no host
+// round trip per step).
+__global__ void k_sample_batch(int32_t B, int64_t nsamp, uint64_t seed, int64_t it, const float* __restrict__ F,
                                const float* __restrict__ T, const float* __restrict__ Mk, float* __restrict__ Fb,
                                float* __restrict__ Tb, float* __restrict__ Mb)
 {
     const int32_t b = blockIdx.x;
     if (b >= B) return;
-    const int64_t s = idx[b];
-    for (int e = threadIdx.x; e < kIn; e += blockDim.x) Fb[(int64_t)b * kIn + e] = F[s * kIn + e];
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * ((uint64_t)it * (uint64_t)B + (uint64_t)b + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int64_t sidx = (int64_t)(z % (uint64_t)nsamp);
+    for (int e = threadIdx.x; e < kIn; e += blockDim.x) Fb[(int64_t)b * kIn + e] = F[sidx * kIn + e];
     for (int e = threadIdx.x; e < kOut; e += blockDim.x) {
-        Tb[(int64_t)b * kOut + e] = T[s * kOut + e];
-        Mb[(int64_t)b * kOut + e] = Mk[s * kOut + e];
+        Tb[(int64_t)b * kOut + e] = T[sidx * kOut + e];
+        Mb[(int64_t)b * kOut + e] = Mk[sidx * kOut + e];
     }
 }
+
 
 struct MlpState {
     double scale = 1.0;   // s: z ~ s r over the training solves
@@ -439,6 +535,162 @@ void mlp_apply(Handle& H, const double* r, double* z, hipStream_t s)
     k_correction<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, H.perm.p, S.out.p, S.rn.p, S.scale,
                                                  r, z);
     HIPCK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------
+// Patch targets: for leaf X with near list {X} u E_X (the self block and
+// the edge-sharing leaves, the blocks the method stores dense), the patch
+// P = X followed by the points of E_X, the patch system K(P, P) z_P = r_P
+// solved exactly, and z_X kept (a restricted additive Schwarz step).  One
+// workgroup per leaf: the augmented matrix [K(P, P) | r_P of every
+// right-hand side] is built column-major in the workgroup's slice of a
+// global work array, reduced by Gaussian elimination with partial
+// pivoting, and back-substituted.
+// ---------------------------------------------------------------------
+constexpr int kPatchMax = 5 * 64;   // self + 4 edge sharers, 64 points each
+
+__global__ void __launch_bounds__(256)
+k_patch_solve(int32_t x0, int32_t nx, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+              const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src, KernelParams kp,
+              const double* __restrict__ xyt, const int32_t* __restrict__ perm, int64_t n, int ns,
+              const double* __restrict__ R, double* __restrict__ Z, double* __restrict__ work, int64_t slot_elems,
+              int lds, int* __restrict__ singular)
+{
+    extern __shared__ double lds_aug[];
+    __shared__ int32_t pts[kPatchMax];
+    __shared__ int32_t pv;
+    __shared__ int32_t npts;
+    const int32_t X = x0 + blockIdx.x;
+    if (blockIdx.x >= nx) return;
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    if (t == 0) {
+        int32_t c = 0;
+        for (int32_t i = 0; i < count[X]; ++i) pts[c++] = begin[X] + i;
+        for (int32_t q = near_ptr[X]; q < near_ptr[X + 1]; ++q) {
+            const int32_t y = near_src[q];
+            if (y == X) continue;
+            for (int32_t i = 0; i < count[y]; ++i) pts[c++] = begin[y] + i;
+        }
+        npts = c;
+    }
+    __syncthreads();
+    const int m = npts, mx = count[X], nc = m + ns;
+    // m x (m + ns), column-major, ld = m: in LDS when the launch gave room
+    // for the largest patch of the chunk, else in the workgroup's slice of
+    // the global work array
+    double* A = lds ? lds_aug : work + (int64_t)blockIdx.x * slot_elems;
+    for (int64_t e = t; e < (int64_t)m * nc; e += blockDim.x) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        const int32_t pi = pts[i];
+        double v;
+        if (j < m) {
+            const int32_t pj = pts[j];
+            v = kernel_entry(kp, xyt[2 * pi], xyt[2 * pi + 1], xyt[2 * pj], xyt[2 * pj + 1], pi == pj);
+        } else {
+            v = R[(int64_t)(j - m) * n + perm[pi]];
+        }
+        A[(int64_t)j * m + i] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        if (wave == 0) {
+            double best = -1.0;
+            int bi = -1;
+            for (int i = k + lane; i < m; i += kWave) {
+                const double v = fabs(A[(int64_t)k * m + i]);
+                if (v > best) { best = v; bi = i; }
+            }
+            for (int d = 32; d > 0; d >>= 1) {
+                const double ov = __shfl_xor(best, d, kWave);
+                const int oi = __shfl_xor(bi, d, kWave);
+                if (ov > best || (ov == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ov; bi = oi; }
+            }
+            if (lane == 0) {
+                pv = bi;
+                if (!(best > 0.0)) atomicOr(singular, 1);
+            }
+        }
+        __syncthreads();
+        const int p = pv;
+        if (p != k && p >= 0)
+            for (int j = k + t; j < nc; j += blockDim.x) {
+                const double a = A[(int64_t)j * m + k];
+                A[(int64_t)j * m + k] = A[(int64_t)j * m + p];
+                A[(int64_t)j * m + p] = a;
+            }
+        __syncthreads();
+        const double d = A[(int64_t)k * m + k];
+        if (d != 0.0)
+            for (int i = k + 1 + t; i < m; i += blockDim.x) A[(int64_t)k * m + i] /= d;
+        __syncthreads();
+        const int rem = m - k - 1, cols = nc - k - 1;
+        for (int64_t e = t; e < (int64_t)rem * cols; e += blockDim.x) {
+            const int i = k + 1 + (int)(e % rem), j = k + 1 + (int)(e / rem);
+            A[(int64_t)j * m + i] -= A[(int64_t)k * m + i] * A[(int64_t)j * m + k];
+        }
+        __syncthreads();
+    }
+    // back substitution, one thread per right-hand side; only the first mx
+    // unknowns (the leaf's own points) are kept
+    for (int q = t; q < ns; q += blockDim.x) {
+        double* b = A + (int64_t)(m + q) * m;
+        for (int k = m - 1; k >= 0; --k) {
+            double v = b[k];
+            for (int j = k + 1; j < m; ++j) v -= A[(int64_t)j * m + k] * b[j];
+            const double d = A[(int64_t)k * m + k];
+            b[k] = d != 0.0 ? v / d : 0.0;
+        }
+        for (int i = 0; i < mx; ++i) Z[(int64_t)q * n + perm[pts[i]]] = b[i];
+    }
+}
+
+// Patch targets z_q (n each, caller order) for the ns right-hand sides r_q.
+static void patch_targets(Handle& H, const double* R, double* Z, int ns, hipStream_t s)
+{
+    const Level& LL = H.lev[H.kappa];
+    const int32_t nleaf = (int32_t)LL.nbox;
+    int32_t pmax = 0;
+    for (int32_t x = 0; x < nleaf; ++x) {
+        int32_t c = 0;
+        for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) c += LL.h_count[H.h_near_src[q]];
+        pmax = std::max(pmax, c);
+    }
+    if (pmax > kPatchMax) fail(H2D_EUNSUPPORTED, "a near-field patch exceeds 320 points");
+    DBuf<int32_t> nsrc;
+    nsrc.alloc(std::max<size_t>(H.h_near_src.size(), 1));
+    HIPCK(hipMemcpyAsync(nsrc.p, H.h_near_src.data(), sizeof(int32_t) * H.h_near_src.size(), hipMemcpyHostToDevice,
+                         s));
+    const int64_t slot = (int64_t)pmax * (pmax + ns);
+    // the augmented matrix in LDS when it fits (the common case), else in
+    // global memory, a chunk of leaves at a time
+    int dev = 0, lds_max = 0;
+    HIPCK(hipGetDevice(&dev));
+    HIPCK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int64_t static_lds = (int64_t)sizeof(int32_t) * (kPatchMax + 2) + 64;
+    const int64_t need = slot * (int64_t)sizeof(double);
+    bool lds = need + static_lds <= lds_max;
+    if (lds && need > 48 * 1024)
+        lds = hipFuncSetAttribute(reinterpret_cast<const void*>(k_patch_solve),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) == hipSuccess;
+    (void)hipGetLastError();
+    const int32_t chunk =
+        lds ? nleaf : (int32_t)std::max<int64_t>(1, std::min<int64_t>(nleaf, (int64_t)(512ll << 20) / 8 / slot));
+    DBuf<double> work;
+    if (!lds) work.alloc((size_t)chunk * slot);
+    DBuf<int> sing;
+    sing.alloc(1);
+    HIPCK(hipMemsetAsync(sing.p, 0, sizeof(int), s));
+    for (int32_t x0 = 0; x0 < nleaf; x0 += chunk) {
+        const int32_t nx = std::min(chunk, nleaf - x0);
+        k_patch_solve<<<nx, 256, lds ? (size_t)need : 0, s>>>(x0, nx, LL.begin.p, LL.count.p, H.near_ptr.p, nsrc.p,
+                                                              H.kern, H.xyt.p, H.perm.p, H.n, ns, R, Z, work.p, slot,
+                                                              lds ? 1 : 0, sing.p);
+        HIPCK(hipGetLastError());
+    }
+    int hs = 0;
+    HIPCK(hipMemcpyAsync(&hs, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (hs) fail(H2D_EINVAL, "a near-field patch system is singular");
 }
 
 // Xavier-uniform initial weights from the counter-based generator.
@@ -514,15 +766,22 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
             h2d_solve_info si{};
             h2d_status st = solve(H, rq, zq, o.solve_tol, so, &si, s);
             if (st == H2D_OK) ++solves_ok;
-        } else {
+        } else if (o.target == H2D_MLP_TARGET_LEAF) {
             precond_apply(H, H2D_PC_BLOCK_JACOBI, rq, zq, s);
             ++solves_ok;
+        } else {
+            ++solves_ok;   // patch targets: every right-hand side at once below
         }
+    }
+    if (o.target == H2D_MLP_TARGET_PATCH) patch_targets(H, R.p, Z.p, ns, s);
+    {
         std::vector<double> hr(n), hz(n);
-        HIPCK(hipMemcpyAsync(hr.data(), rq, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(hz.data(), zq, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        for (int64_t i = 0; i < n; ++i) { zr += hz[i] * hr[i]; rr += hr[i] * hr[i]; }
+        for (int q = 0; q < ns; ++q) {
+            HIPCK(hipMemcpyAsync(hr.data(), R.p + (int64_t)q * n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(hz.data(), Z.p + (int64_t)q * n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            for (int64_t i = 0; i < n; ++i) { zr += hz[i] * hr[i]; rr += hr[i] * hr[i]; }
+        }
     }
     S.scale = rr > 0.0 ? zr / rr : 1.0;
     if (!(S.scale != 0.0) || !std::isfinite(S.scale)) S.scale = 1.0;
@@ -545,29 +804,18 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
     }
     const int B = std::max(1, std::min<int>(o.batch, (int)nsamp));
     DBuf<float> Fb, Tb, Mb;
-    DBuf<int32_t> idx;
     Fb.alloc((size_t)B * kIn);
     Tb.alloc((size_t)B * kOut);
     Mb.alloc((size_t)B * kOut);
-    idx.alloc(B);
-    std::vector<int32_t> hidx(B);
-    uint64_t st = o.seed * 6364136223846793005ull + 1442695040888963407ull;
     float first = 0.f, last = 0.f;
     const float b1 = 0.9f, b2 = 0.999f;
+    const uint64_t bseed = o.seed * 6364136223846793005ull + 1442695040888963407ull;
     for (int it = 0; it < o.steps; ++it) {
-        for (int b = 0; b < B; ++b) {   // host LCG draw of the batch indices
-            st = st * 6364136223846793005ull + 1442695040888963407ull;
-            hidx[b] = (int32_t)((st >> 33) % (uint64_t)nsamp);
-        }
-        // the previous step's kernels read idx: finish them before reuse
-        HIPCK(hipStreamSynchronize(s));
-        HIPCK(hipMemcpyAsync(idx.p, hidx.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
-        k_gather_batch<<<B, 64, 0, s>>>(B, idx.p, F.p, T.p, Mk.p, Fb.p, Tb.p, Mb.p);
-        // valid slots of the batch: the points of each sampled leaf
-        double cnt = 0;
-        for (int b = 0; b < B; ++b) cnt += LL.h_count[hidx[b] % nleaf];
+        // batch drawn and gathered on the device; the mask sum (valid slots)
+        // is taken there too, so a step has no host round trip
+        k_sample_batch<<<B, 64, 0, s>>>(B, nsamp, bseed, it, F.p, T.p, Mk.p, Fb.p, Tb.p, Mb.p);
         const bool report = it == 0 || it + 1 == o.steps;
-        const float L = loss_grad(S.w.p, Fb.p, Tb.p, Mb.p, B, (float)std::max(1.0, cnt), S.grad.p, S.work, s, report);
+        const float L = loss_grad(S.w.p, Fb.p, Tb.p, Mb.p, B, 0.f, S.grad.p, S.work, s, report);
         if (it == 0) first = L;
         if (report) last = L;
         const float c1 = 1.f - std::pow(b1, (float)(it + 1)), c2 = 1.f - std::pow(b2, (float)(it + 1));

@@ -23,6 +23,7 @@ KINDS = {"log": 0, "invr": 1, "mq": 2, "gauss": 3, "phi1": 4, "phi2": 5, "sep": 
 DIAG = {"replace": 0, "add": 1, "formula": 2}
 PREC = {"fp64": 0, "fp16": 1, "bf16": 2}
 SOLVE_PLAIN, SOLVE_REFINE = 0, 1
+BUILD_ADAPTIVE = 1 << 8
 PRECOND = {"none": 0, "bj": 1, "mlp": 2}
 
 EXPORTED = ["h2d_build", "h2d_matvec", "h2d_matvec_noalloc", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
@@ -176,13 +177,14 @@ class HODLR2D:
         self._h = handle
 
     @classmethod
-    def build(cls, xy, kernel, leaf_max=64, tol=1e-10, precs=()):
+    def build(cls, xy, kernel, leaf_max=64, tol=1e-10, precs=(), adaptive=False):
         L = load()
         xy = xy.contiguous()
         h = C.c_void_p()
         k = kernel_spec(kernel)
+        flags = prec_mask(*precs) | (BUILD_ADAPTIVE if adaptive else 0)
         _check(L.h2d_build(_dev_f64(xy, "xy"), xy.shape[0], C.byref(k), int(leaf_max), float(tol),
-                           prec_mask(*precs), _stream(), C.byref(h)))
+                           flags, _stream(), C.byref(h)))
         return cls(h)
 
     @classmethod
@@ -264,7 +266,7 @@ class HODLR2D:
     def mlp_train(self, n_solves=16, steps=1500, batch=4096, lr=5e-4, seed=1234, solve_tol=1e-10,
                   target="leaf") -> dict:
         o = h2d_mlp_train_opts(int(n_solves), int(steps), int(batch), float(lr), int(seed), float(solve_tol),
-                               {"leaf": 0, "global": 1}[target], 0)
+                               {"leaf": 0, "global": 1, "patch": 2}[target], 0)
         info = h2d_mlp_train_info()
         _check(load().h2d_mlp_train(self._h, C.byref(o), C.byref(info), _stream()))
         return {f: getattr(info, f) for f, _ in h2d_mlp_train_info._fields_}

@@ -18,9 +18,10 @@ def read(path):
     assert buf[:4] == b"H2DX"
     off = 4
     version, flags, _ = take("<u4", 3)
-    assert version == 1
+    assert version in (1, 2)
+    adaptive = version == 2   # blocks carry the levels of both boxes
     fac = bool(flags & 1)
-    H = {"factors": fac}
+    H = {"factors": fac, "adaptive": adaptive}
     H["n"] = int(take("<i8")[0])
     H["kappa"] = int(take("<i4")[0])
     H["leaf_max"] = int(take("<i4")[0])
@@ -37,25 +38,27 @@ def read(path):
         levels.append({"key": key, "begin": take("<i8", nb).copy(), "count": take("<i8", nb).copy(),
                        "parent": take("<i8", nb).copy()})
     H["levels"] = levels
-    LL = levels[-1]
+    kap = H["kappa"]
     nn = int(take("<i8")[0])
-    nt, ns, nD = [], [], []
+    nt, ns, nD, ntl, nsl = [], [], [], [], []
     for _ in range(nn):
+        tl, sl = map(int, take("<i4", 2)) if adaptive else (kap, kap)
         t, s = take("<i8", 2)
-        nt.append(int(t)); ns.append(int(s))
+        nt.append(int(t)); ns.append(int(s)); ntl.append(tl); nsl.append(sl)
         if fac:
-            m, c = int(LL["count"][t]), int(LL["count"][s])
+            m, c = int(levels[tl]["count"][t]), int(levels[sl]["count"][s])
             nD.append(take("<f8", m * c).reshape(c, m).T)
     H["near_tgt"] = np.array(nt, np.int64); H["near_src"] = np.array(ns, np.int64); H["near_D"] = nD
+    H["near_tlevel"] = np.array(ntl, np.int32); H["near_slevel"] = np.array(nsl, np.int32)
     nb = int(take("<i8")[0])
-    lv, kd, tg, sr, rk, fa = [], [], [], [], [], []
+    lv, kd, tg, sr, rk, fa, slv = [], [], [], [], [], [], []
     for _ in range(nb):
         l, k = map(int, take("<i4", 2))
+        sl = int(take("<i4", 2)[0]) if adaptive else l
         t, s, r = map(int, take("<i8", 3))
-        lv.append(l); kd.append(k); tg.append(t); sr.append(s); rk.append(r)
+        lv.append(l); kd.append(k); tg.append(t); sr.append(s); rk.append(r); slv.append(sl)
         if fac:
-            L = levels[l]
-            m, c = int(L["count"][t]), int(L["count"][s])
+            m, c = int(levels[l]["count"][t]), int(levels[sl]["count"][s])
             if k == 1:
                 fa.append(("D", take("<f8", m * c).reshape(c, m).T))
             else:
@@ -65,6 +68,7 @@ def read(path):
     H["il_level"] = np.array(lv, np.int32); H["il_kind"] = np.array(kd, np.int32)
     H["il_tgt"] = np.array(tg, np.int64); H["il_src"] = np.array(sr, np.int64)
     H["il_rank"] = np.array(rk, np.int64); H["il_factors"] = fa
+    H["il_slevel"] = np.array(slv, np.int32)
     assert off == len(buf), "trailing bytes"
     return H
 
@@ -74,14 +78,13 @@ def dense_operator(H):
     n = H["n"]
     A = np.zeros((n, n))
     perm = H["perm"]
-    LL = H["levels"][-1]
-    for t, s, D in zip(H["near_tgt"], H["near_src"], H["near_D"]):
-        r = perm[LL["begin"][t]:LL["begin"][t] + LL["count"][t]]
-        c = perm[LL["begin"][s]:LL["begin"][s] + LL["count"][s]]
+    lev = H["levels"]
+    for tl, sl, t, s, D in zip(H["near_tlevel"], H["near_slevel"], H["near_tgt"], H["near_src"], H["near_D"]):
+        r = perm[lev[tl]["begin"][t]:lev[tl]["begin"][t] + lev[tl]["count"][t]]
+        c = perm[lev[sl]["begin"][s]:lev[sl]["begin"][s] + lev[sl]["count"][s]]
         A[np.ix_(r, c)] += D
-    for l, t, s, f in zip(H["il_level"], H["il_tgt"], H["il_src"], H["il_factors"]):
-        L = H["levels"][l]
-        r = perm[L["begin"][t]:L["begin"][t] + L["count"][t]]
-        c = perm[L["begin"][s]:L["begin"][s] + L["count"][s]]
+    for l, sl, t, s, f in zip(H["il_level"], H["il_slevel"], H["il_tgt"], H["il_src"], H["il_factors"]):
+        r = perm[lev[l]["begin"][t]:lev[l]["begin"][t] + lev[l]["count"][t]]
+        c = perm[lev[sl]["begin"][s]:lev[sl]["begin"][s] + lev[sl]["count"][s]]
         A[np.ix_(r, c)] += f[1] if f[0] == "D" else f[1] @ f[2].T
     return A
