@@ -1238,11 +1238,23 @@ __global__ void k_half_blocks(const HalfJob* jobs, const double* src, T* dst, fl
     }
 }
 
+// V of one low-rank block, FP64 row-major n x k at src_off, to the half
+// pool at dst_off as row-major n x kp4 (kp4 = k rounded up to 4, zeros in
+// the padding columns).
+struct HalfVJob {
+    int64_t src_off, dst_off;
+    int32_t n, k;
+};
+
 template <typename T>
-__global__ void k_half_plain(const double* src, T* dst, int64_t n)
+__global__ void k_half_v4(const HalfVJob* jobs, const double* src, T* dst)
 {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        dst[e] = to_half<T>((float)src[e]);
+    const HalfVJob J = jobs[blockIdx.x];
+    const int32_t kp4 = (J.k + 3) & ~3;
+    for (int64_t e = threadIdx.x; e < (int64_t)J.n * kp4; e += blockDim.x) {
+        const int32_t j = (int32_t)(e / kp4), q = (int32_t)(e % kp4);
+        dst[J.dst_off + e] = to_half<T>(q < J.k ? (float)src[J.src_off + (int64_t)j * J.k + q] : 0.0f);
+    }
 }
 
 // The half-precision product kernels read pairs and fours of 2-byte values
@@ -1324,6 +1336,14 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     DBuf<HalfJob> du, dd;
     upload(du, ujobs, s);
     upload(dd, djobs, s);
+    std::vector<HalfVJob> vjobs;
+    for (int64_t q = 0; q < H.n_il; ++q) {
+        if (H.h_il_kind[q] == kDense || H.h_il_k[q] == 0) continue;
+        const int32_t nn = H.lev[il_src_level(H, q)].h_count[H.h_il_src[q]];
+        vjobs.push_back(HalfVJob{H.h_il_voff[q], H.h_il_voff16[q], nn, H.h_il_k[q]});
+    }
+    DBuf<HalfVJob> dv;
+    upload(dv, vjobs, s);
     DBuf<float> su, sd;
     su.alloc(std::max<size_t>(ujobs.size(), 1));
     sd.alloc(std::max<size_t>(djobs.size(), 1));
@@ -1339,7 +1359,10 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
             unsigned c = (unsigned)std::min<size_t>(1u << 20, djobs.size() - o);
             k_half_blocks<T><<<c, 256, 0, s>>>(dd.p + o, H.D64.p, Dp, sd.p + o, H.diag32.p);
         }
-        k_half_plain<T><<<4096, 256, 0, s>>>(H.V64.p, Vp, H.v_elems);
+        for (size_t o = 0; o < vjobs.size(); o += 1u << 20) {
+            unsigned c = (unsigned)std::min<size_t>(1u << 20, vjobs.size() - o);
+            k_half_v4<T><<<c, 256, 0, s>>>(dv.p + o, H.V64.p, Vp);
+        }
         HIPCK(hipGetLastError());
     };
     // the half kernels read values in pairs and may read one element past
@@ -1352,13 +1375,13 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     };
     if (f16) {
         alloc_half(H.U16, H.u_elems);
-        alloc_half(H.V16, H.v_elems);
+        alloc_half(H.V16, H.v16_elems);
         alloc_half(H.D16, H.d_elems);
         run(H.U16.p, H.V16.p, H.D16.p);
     }
     if (b16) {
         alloc_half(H.Ub16, H.u_elems);
-        alloc_half(H.Vb16, H.v_elems);
+        alloc_half(H.Vb16, H.v16_elems);
         alloc_half(H.Db16, H.d_elems);
         run(H.Ub16.p, H.Vb16.p, H.Db16.p);
     }

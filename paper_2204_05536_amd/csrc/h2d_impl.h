@@ -216,6 +216,13 @@ struct Handle {
     // matvec schedule
     DBuf<BDesc> bnear, bil;  // phase-B descriptors: near blocks, IL blocks
     DBuf<ADesc> aitems;
+    // FP16/BF16 V pools: each low-rank block's V row-major with its rows
+    // padded to a multiple of 4 values (zeros), so that every 4-value group
+    // is one aligned 8-byte load; offsets of their own (h_il_voff16) and the
+    // phase-A items pointing there (aitems16, same order as aitems)
+    std::vector<int64_t> h_il_voff16;
+    int64_t v16_elems = 0;
+    DBuf<ADesc> aitems16;
     DBuf<RDesc> ritems;
     int64_t n_aitems = 0, n_ritems = 0;
     DBuf<int2> b1items;         // multi-RHS phase-B1 work: (box at level kappa - 1, first row of a 64-row chunk)

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 
 namespace h2d {
 
@@ -109,6 +110,22 @@ template <> __device__ __forceinline__ float4 ld4<__hip_bfloat16>(const __hip_bf
                        __uint_as_float(hi & 0xffff0000u));
 }
 
+// Four consecutive half values at an 8-byte-aligned address: one aligned
+// 8-byte load (the padded V pools).
+template <typename T> __device__ __forceinline__ float4 ld4v(const T* p)
+{
+    const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(p));
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    if constexpr (std::is_same<T, __half>::value)
+        return make_float4(__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
+                           __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(hi >> 16))));
+    else
+        return make_float4(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
+                           __uint_as_float(hi & 0xffff0000u));
+}
+
 template <typename A>
 __global__ void k_gather(const double* x, const int32_t* perm, int32_t n, int64_t ldx, int64_t ldxs, int nrhs, A* xs)
 {
@@ -173,34 +190,41 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     A sc = (A)1;
     if constexpr (kScaled) sc = (A)scale[D.pad];
     if constexpr (sizeof(T) == 2) {
-        if (k <= 2 * kWave) {
-            // lane (g, qp) takes columns 2 qp, 2 qp + 1 of rows g, g + G, ...
-            // (kp = ceil(k / 2) lanes per row); for odd k the last lane's
-            // second value belongs to the next row and its sum is dropped
-            __shared__ float red2[4][2 * kWave];
-            const int kp = (k + 1) >> 1;
-            const int G = kWave / kp, g = lane / kp, qp = lane % kp;
-            float a0 = 0.f, a1 = 0.f;
-            if (g < G) {
+        // half pools: rows padded to kp4 = k rounded up to 4 (zeros past
+        // column k), the block 8-byte aligned.  Lane (g, c) takes columns
+        // 4 c .. 4 c + 3 of rows g, g + G, ... (nc = kp4 / 4 lanes per row,
+        // G = 64 / nc rows per load): one aligned 8-byte load per lane,
+        // whole rows per wave load.  kp4 <= 256 (the ACA rank cap), so
+        // nc <= 64.
+        const int kp4 = (k + 3) & ~3, nc = kp4 >> 2;
+        const T* Vh = V + D.voff + (int64_t)D.j0 * kp4;
+        const int G = kWave / nc, g = lane / nc, c = lane % nc;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        if (g < G) {
 #pragma unroll 8
-                for (int32_t j = g; j < rows; j += G) {
-                    const float2 v = ld2<T>(Vb + (int64_t)j * k + 2 * qp);
-                    const float xv = xl[j];
-                    a0 += v.x * xv;
-                    a1 += v.y * xv;
-                }
+            for (int32_t j = g; j < rows; j += G) {
+                const float4 v = ld4v<T>(Vh + (int64_t)j * kp4 + 4 * c);
+                const float xv = xl[j];
+                a0 += v.x * xv;
+                a1 += v.y * xv;
+                a2 += v.z * xv;
+                a3 += v.w * xv;
             }
-            red2[wave][2 * lane] = a0;
-            red2[wave][2 * lane + 1] = a1;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            for (int32_t q = lane; q < k; q += kWave) {
-                float s = 0.f;
-                for (int gg = 0; gg < G; ++gg) s += red2[wave][2 * (gg * kp + (q >> 1)) + (q & 1)];
-                out[q] = s * sc;
-            }
-            return;
         }
+        __shared__ float red4[4][4 * kWave];
+        float* rw = red4[wave];
+        rw[4 * lane] = a0;
+        rw[4 * lane + 1] = a1;
+        rw[4 * lane + 2] = a2;
+        rw[4 * lane + 3] = a3;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t q = lane; q < k; q += kWave) {
+            float acc = 0.f;
+            for (int gg = 0; gg < G; ++gg) acc += rw[4 * (gg * nc + (q >> 2)) + (q & 3)];
+            out[q] = acc * sc;
+        }
+        return;
     }
     if (k <= kWave) {
         const int G = kWave / k, g = lane / k, q = lane % k;
@@ -765,7 +789,8 @@ void finalize(Handle& H, hipStream_t s)
     std::vector<ADesc> items;
     std::vector<RDesc> red;
     H.h_il_toff.assign(nil, -1);
-    int64_t toff = 0, poff = 0;
+    H.h_il_voff16.assign(nil, 0);
+    int64_t toff = 0, poff = 0, v16 = 0;
     H.max_rank = 0; H.sum_rank = 0; H.n_il_dense = 0;
     double flops = 0;
     double store_anc = 0, store_leaf = 0, t_leaf = 0;   // stored values read by the B1 / B2 halves, t values by B2
@@ -786,6 +811,8 @@ void finalize(Handle& H, hipStream_t s)
         bi[b] = BDesc{H.h_il_off[b], k, (int32_t)toff};
         if (k == 0) continue;
         H.h_il_toff[b] = (int32_t)toff;
+        H.h_il_voff16[b] = v16;
+        v16 += (int64_t)n * ((k + 3) & ~3);
         (leaf ? store_leaf : store_anc) += (double)m * k;
         if (leaf) t_leaf += k;
         flops += 2.0 * k * (double)(m + n);
@@ -883,6 +910,12 @@ void finalize(Handle& H, hipStream_t s)
     }
     upload_vec(H.bil, bi, s);
     upload_vec(H.aitems, items, s);
+    H.v16_elems = v16;
+    {   // the same items on the padded half V pools (ADesc.pad is the block)
+        std::vector<ADesc> i16(items);
+        for (ADesc& d : i16) d.voff = H.h_il_voff16[d.pad];
+        upload_vec(H.aitems16, i16, s);
+    }
     upload_vec(H.ritems, red, s);
     H.n_aitems = (int64_t)items.size();
     H.n_ritems = (int64_t)red.size();
@@ -1040,7 +1073,9 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     k_gather<A><<<(n + 255) / 256, 256, 0, s>>>(x, H.perm.p, n, 0, 0, 1, xs);
     if (ev) HIPCK(hipEventRecord(ev[1], s));
     if (H.n_aitems)
-        k_phaseA<T, A, kHalf><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp,
+        k_phaseA<T, A, kHalf><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems,
+                                                                            kHalf ? H.aitems16.p : H.aitems.p, V, xs,
+                                                                            tp, pp,
                                                                             H.scale16.p);
     if (ev) HIPCK(hipEventRecord(ev[2], s));
     if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);

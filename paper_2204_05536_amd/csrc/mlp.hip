@@ -35,12 +35,23 @@ static_assert(kParams == H2D_MLP_PARAMS, "parameter count");
 // transpose; same for B.  64 x 64 tiles, 256 threads, 4 x 4 outputs each,
 // K in steps of 16 through LDS.  Fixed summation order.
 // ---------------------------------------------------------------------
+// With gridDim.z > 1 the inner dimension is cut into slices of kslice
+// (slice z covers rows [z kslice, (z + 1) kslice) of op(A)'s columns and
+// op(B)'s rows) and slice z writes its own C at C + z cstride: the partial
+// products of a split-K product, all in one launch.
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, const float* __restrict__ B, int ldb,
-       int transB, float* __restrict__ C, int ldc, float alpha, float beta)
+       int transB, float* __restrict__ C, int ldc, float alpha, float beta, int kslice, int64_t cstride)
 {
     __shared__ float As[16][64 + 1];
     __shared__ float Bs[16][64 + 1];
+    if (gridDim.z > 1) {
+        const int k0 = blockIdx.z * kslice;
+        K = max(0, min(K, k0 + kslice) - k0);
+        A += transA ? (int64_t)k0 * lda : k0;
+        B += transB ? k0 : (int64_t)k0 * ldb;
+        C += blockIdx.z * cstride;
+    }
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     float acc[4][4] = {};
@@ -87,7 +98,7 @@ static void gemm(int M, int N, int K, const float* A, int lda, bool tA, const fl
                  int ldc, float alpha, float beta, hipStream_t s)
 {
     dim3 g((N + 63) / 64, (M + 63) / 64);
-    k_gemm<<<g, 256, 0, s>>>(M, N, K, A, lda, tA ? 1 : 0, B, ldb, tB ? 1 : 0, C, ldc, alpha, beta);
+    k_gemm<<<g, 256, 0, s>>>(M, N, K, A, lda, tA ? 1 : 0, B, ldb, tB ? 1 : 0, C, ldc, alpha, beta, K, 0);
     HIPCK(hipGetLastError());
 }
 
@@ -107,14 +118,11 @@ __global__ void k_sum_slices(int64_t mn, int S, const float* __restrict__ P, flo
 static void gemm_tn_split(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, float* work,
                           int S, hipStream_t s)
 {
-    // op(A) = A^T (A stored K x M), op(B) = B (K x N); slice q of K
+    // op(A) = A^T (A stored K x M), op(B) = B (K x N); slice z of K in
+    // grid plane z
     const int kq = (K + S - 1) / S;
-    for (int q = 0; q < S; ++q) {
-        const int k0 = q * kq, kk = std::max(0, std::min(K, k0 + kq) - k0);
-        dim3 g((N + 63) / 64, (M + 63) / 64);
-        k_gemm<<<g, 256, 0, s>>>(M, N, kk, A + (int64_t)k0 * lda, lda, 1, B + (int64_t)k0 * ldb, ldb, 0,
-                                 work + (int64_t)q * M * N, N, 1.f, 0.f);
-    }
+    dim3 g((N + 63) / 64, (M + 63) / 64, S);
+    k_gemm<<<g, 256, 0, s>>>(M, N, K, A, lda, 1, B, ldb, 0, work, N, 1.f, 0.f, kq, (int64_t)M * N);
     const int64_t mn = (int64_t)M * N;
     k_sum_slices<<<(int)std::min<int64_t>(1024, (mn + 255) / 256), 256, 0, s>>>(mn, S, work, C);
     HIPCK(hipGetLastError());
@@ -163,7 +171,8 @@ __global__ void k_colsum_final(int N, const float* __restrict__ part, float* __r
     db[j] = v;
 }
 
-// count[0] = sum of the mask (one workgroup, fixed order), at least 1.
+// count[0] = sum of the n values (one workgroup, fixed order), at least 1:
+// the mask's valid slots, from the per-row counts of a batch.
 __global__ void __launch_bounds__(256) k_masksum(int64_t n, const float* __restrict__ Mk, float* __restrict__ count)
 {
     __shared__ float red[256];
@@ -262,13 +271,14 @@ static void forward(const float* W, const float* X, int64_t B, MlpWork& w, hipSt
 // count > 0: the mask sum given by the caller; count <= 0: summed on the
 // device from Mk (no host round trip).
 static float loss_grad(const float* W, const float* X, const float* T, const float* Mk, int64_t B, float count,
-                       float* grad, MlpWork& w, hipStream_t s, bool want_loss = true)
+                       float* grad, MlpWork& w, hipStream_t s, bool want_loss = true, const float* rowcnt = nullptr)
 {
     w.ensure(B);
     forward(W, X, B, w, s);
     const int nb = std::min<int64_t>(1024, (B * kOut + 255) / 256);
     if (count <= 0.f) {
-        k_masksum<<<1, 256, 0, s>>>(B * kOut, Mk, w.count.p);
+        if (rowcnt) k_masksum<<<1, 256, 0, s>>>(B, rowcnt, w.count.p);
+        else k_masksum<<<1, 256, 0, s>>>(B * kOut, Mk, w.count.p);
         k_mse<<<nb, 256, 0, s>>>(B * kOut, w.o.p, T, Mk, 1.f, w.count.p, w.go.p, w.part.p);
     } else {
         k_mse<<<nb, 256, 0, s>>>(B * kOut, w.o.p, T, Mk, 1.f / count, nullptr, w.go.p, w.part.p);
@@ -448,7 +458,7 @@ __global__ void k_random(int64_t n, uint64_t seed, double* __restrict__ out)
 // round trip per step).
 __global__ void k_sample_batch(int32_t B, int64_t nsamp, uint64_t seed, int64_t it, const float* __restrict__ F,
                                const float* __restrict__ T, const float* __restrict__ Mk, float* __restrict__ Fb,
-                               float* __restrict__ Tb, float* __restrict__ Mb)
+                               float* __restrict__ Tb, float* __restrict__ Mb, float* __restrict__ rowcnt)
 {
     const int32_t b = blockIdx.x;
     if (b >= B) return;
@@ -458,10 +468,16 @@ __global__ void k_sample_batch(int32_t B, int64_t nsamp, uint64_t seed, int64_t 
     z ^= z >> 31;
     const int64_t sidx = (int64_t)(z % (uint64_t)nsamp);
     for (int e = threadIdx.x; e < kIn; e += blockDim.x) Fb[(int64_t)b * kIn + e] = F[sidx * kIn + e];
+    float c = 0.f;
     for (int e = threadIdx.x; e < kOut; e += blockDim.x) {
         Tb[(int64_t)b * kOut + e] = T[sidx * kOut + e];
-        Mb[(int64_t)b * kOut + e] = Mk[sidx * kOut + e];
+        const float mv = Mk[sidx * kOut + e];
+        Mb[(int64_t)b * kOut + e] = mv;
+        c += mv;
     }
+    // the block is one wave (64 threads): its valid-slot count
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
+    if (threadIdx.x == 0) rowcnt[b] = c;
 }
 
 
@@ -803,19 +819,20 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
         HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
     }
     const int B = std::max(1, std::min<int>(o.batch, (int)nsamp));
-    DBuf<float> Fb, Tb, Mb;
+    DBuf<float> Fb, Tb, Mb, rc;
     Fb.alloc((size_t)B * kIn);
     Tb.alloc((size_t)B * kOut);
     Mb.alloc((size_t)B * kOut);
+    rc.alloc(B);
     float first = 0.f, last = 0.f;
     const float b1 = 0.9f, b2 = 0.999f;
     const uint64_t bseed = o.seed * 6364136223846793005ull + 1442695040888963407ull;
     for (int it = 0; it < o.steps; ++it) {
         // batch drawn and gathered on the device; the mask sum (valid slots)
         // is taken there too, so a step has no host round trip
-        k_sample_batch<<<B, 64, 0, s>>>(B, nsamp, bseed, it, F.p, T.p, Mk.p, Fb.p, Tb.p, Mb.p);
+        k_sample_batch<<<B, 64, 0, s>>>(B, nsamp, bseed, it, F.p, T.p, Mk.p, Fb.p, Tb.p, Mb.p, rc.p);
         const bool report = it == 0 || it + 1 == o.steps;
-        const float L = loss_grad(S.w.p, Fb.p, Tb.p, Mb.p, B, 0.f, S.grad.p, S.work, s, report);
+        const float L = loss_grad(S.w.p, Fb.p, Tb.p, Mb.p, B, 0.f, S.grad.p, S.work, s, report, rc.p);
         if (it == 0) first = L;
         if (report) last = L;
         const float c1 = 1.f - std::pow(b1, (float)(it + 1)), c2 = 1.f - std::pow(b2, (float)(it + 1));
