@@ -93,10 +93,10 @@ def test_mlp_training_reduces_loss(trained):
 
 
 def test_mlp_preconditioner_gain(trained):
-    """FGMRES with the trained MLP against plain GMRES and block-Jacobi on
-    the same system (log kernel, diagonal N, N = 2^16): every solve must
-    reach 1e-8 in the true FP64 residual; the iteration counts are the gain
-    (printed; the MLP must not need more iterations than plain GMRES)."""
+    """The log system with diagonal N (N = 2^16) leaves no room to any leaf
+    preconditioner: GMRES needs 7 steps with none, with block-Jacobi and
+    with the trained MLP alike.  Every solve must reach 1e-8 in the true
+    FP64 residual, and the learned one must cost no extra iteration."""
     H, b, _ = trained
     H.bj_setup()
     bb = dev(b)
@@ -108,7 +108,48 @@ def test_mlp_preconditioner_gain(trained):
         assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
         res[pc] = info["iters"]
     say("iterations", res)
-    assert res["mlp"] <= res["none"] + 1
+    assert res["bj"] == res["none"] and res["mlp"] == res["none"]
+
+
+def test_learned_targets_on_a_local_system():
+    """Where a leaf preconditioner matters (Gaussian c = 0.02 + 0.3 I,
+    N = 2^16: block-Jacobi cuts plain GMRES's iterations), the network is
+    trained on each of its targets -- the leaf solve K(X,X)^-1 r(X), the
+    leaf-restricted solve of the near-field patch (self + edge sharers),
+    the leaf-restricted global solve -- and used in FGMRES.  Its input is
+    the leaf's own points and residual: the best map of that input is the
+    patch solve restricted to the leaf with the neighbours' residual
+    unseen, which barely beats block-Jacobi (CPU test
+    test_precond_ceiling); measured here, no target beats block-Jacobi and
+    the stagnation test hands every solve to block-Jacobi.  Asserted: every
+    solve converges in the true residual, block-Jacobi gains, and the
+    hand-over keeps the learned form within 20 steps of plain GMRES."""
+    n = 1 << 16
+    rng = np.random.default_rng(3)
+    xy = inputs.uniform_square(n, rng)
+    b = inputs.rhs(n, rng)
+    spec = {"kind": "gauss", "c": 0.02, "diag_mode": "add", "diag_value": 0.3}
+    bb = dev(b)
+    res = {}
+    for target in ("leaf", "patch", "global"):
+        H = _lib().HODLR2D.build(dev(xy), spec, 64, 1e-10)
+        H.bj_setup()
+        if not res:
+            for pc in ("none", "bj"):
+                _, i = H.solve(bb, tol=1e-8, max_iter=600, precond=pc)
+                assert i["converged"], (pc, i)
+                res[pc] = i["iters"]
+        t = H.mlp_train(n_solves=32, steps=1500, batch=4096, lr=5e-4, seed=7, target=target)
+        x, i = H.solve(bb, tol=1e-8, max_iter=600, precond="mlp")
+        assert i["converged"] and i["relres"] <= 1e-8, (target, i)
+        r = host(bb - H.matvec(x))
+        assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
+        res["mlp_" + target] = (i["iters"], i["fallback_at"], round(t["seconds_train"], 2))
+        H.close()
+    say("iterations (mlp: iterations, hand-over step, training s):", res)
+    assert res["bj"] < res["none"]
+    for target in ("leaf", "patch", "global"):
+        assert res["mlp_" + target][0] <= res["none"] + 20
 
 
 def test_chosen_form_refine_fp16_mlp(trained):
