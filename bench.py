@@ -199,7 +199,7 @@ def kernel_traffic(kernel: str):
     or None when the kernel sources changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "matvec_fp64_mq1m_traffic.md")
+    path = os.path.join(ROOT, "profiles", "matvec_mq1m_traffic.md")
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
@@ -226,6 +226,24 @@ def mr_bytes(info, nrhs):
     return fac + nrhs * (info["alg_bytes_fp64"] - fac)
 
 
+def mr_phase_bytes(H, info, nrhs):
+    """Algorithmic bytes of the multi-RHS phase kernels: phase A reads every
+    V value once and nrhs times the vector terms of the single-RHS phase A;
+    phase B every U and D value once and nrhs times its vector terms."""
+    H.profile_read()
+    H.profile_enable(True)
+    import torch
+    x = torch.zeros(info["n"], dtype=torch.float64, device="cuda")
+    H.matvec(x)
+    torch.cuda.synchronize()
+    H.profile_enable(False)
+    b = H.profile_read()["bytes"]
+    v = 8.0 * info["v_elems"]
+    ud = 8.0 * (info["u_elems"] + info["d_elems"])
+    return {"phaseA_mr": v + nrhs * (b["phaseA"] - v), "phaseB_mr": ud + nrhs * (b["phaseB"] - ud),
+            "reduce_mr": nrhs * b["reduce"], "gather_mr": nrhs * b["gather"], "scatter_mr": nrhs * b["combine"]}
+
+
 def multi_rhs(H, info, n, nrhs=16, reps=10):
     """16 right-hand sides per product on the FP64 matrix cores."""
     import numpy as np
@@ -249,7 +267,7 @@ def multi_rhs(H, info, n, nrhs=16, reps=10):
     tf = nrhs * info["flops"] / (ms * 1e-3) / 1e12
     r = {"nrhs": nrhs, "ms": ms, "ms_per_rhs": ms / nrhs, "GB/s": mr_bytes(info, nrhs) / (ms * 1e-3) / 1e9,
          "alg_bytes": mr_bytes(info, nrhs), "TFLOP/s": tf, "fp64_mfma_frac": tf / FP64_MFMA_PEAK_TFS,
-         "rel_diff_vs_single_rhs": err}
+         "rel_diff_vs_single_rhs": err, "phases_alg_bytes": mr_phase_bytes(H, info, nrhs)}
     log(f"multi-RHS x{nrhs}: {ms:.3f} ms ({ms / nrhs:.3f} ms per RHS), {r['GB/s']:.0f} GB/s, {tf:.2f} TFLOP/s")
     return r
 
@@ -669,7 +687,7 @@ def main():
             yh = H.matvec(x, prec=p)
             err = float(torch.linalg.norm(yh - y1) / torch.linalg.norm(y1))
             half[p] = {"ms": mh, "GB/s": info["alg_bytes_half"] / (mh * 1e-3) / 1e9,
-                       "rel_err_vs_fp64": err, "phases_ms": ph["ms"]}
+                       "rel_err_vs_fp64": err, "phases_ms": ph["ms"], "phases_alg_bytes": ph["bytes"]}
             log(f"{p} matvec {mh:.3f} ms  {half[p]['GB/s']:.0f} GB/s  err {err:.2e}")
         extra["half"] = half
     if not args.no_mrhs:
