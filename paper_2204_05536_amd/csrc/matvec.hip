@@ -81,13 +81,13 @@ typedef uint32_t u32_a2 __attribute__((aligned(2)));
 template <typename T> __device__ __forceinline__ float2 ld2(const T* p);
 template <> __device__ __forceinline__ float2 ld2<__half>(const __half* p)
 {
-    const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const u32_a2*>(p));
+    const uint32_t w = *reinterpret_cast<const u32_a2*>(p);
     return make_float2(__half2float(__ushort_as_half((unsigned short)(w & 0xffffu))),
                        __half2float(__ushort_as_half((unsigned short)(w >> 16))));
 }
 template <> __device__ __forceinline__ float2 ld2<__hip_bfloat16>(const __hip_bfloat16* p)
 {
-    const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const u32_a2*>(p));
+    const uint32_t w = *reinterpret_cast<const u32_a2*>(p);
     return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
 }
 // Four consecutive half values from one 8-byte load (same alignment rule).
@@ -95,7 +95,7 @@ typedef uint64_t u64_a2 __attribute__((aligned(2)));
 template <typename T> __device__ __forceinline__ float4 ld4(const T* p);
 template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p)
 {
-    const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const u64_a2*>(p));
+    const uint64_t w = *reinterpret_cast<const u64_a2*>(p);
     const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
     return make_float4(__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
                        __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
@@ -104,7 +104,7 @@ template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p)
 }
 template <> __device__ __forceinline__ float4 ld4<__hip_bfloat16>(const __hip_bfloat16* p)
 {
-    const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const u64_a2*>(p));
+    const uint64_t w = *reinterpret_cast<const u64_a2*>(p);
     const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
     return make_float4(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
                        __uint_as_float(hi & 0xffff0000u));
