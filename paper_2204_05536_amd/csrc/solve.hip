@@ -92,6 +92,23 @@ __global__ void k_sub(double* __restrict__ out, const double* __restrict__ a, co
         out[i] = a[i] - b[i];
 }
 
+// v *= 1 / |v| with |v|^2 read from device memory (no host round trip);
+// a zero norm leaves v unchanged (exact breakdown, handled on the host).
+__global__ void k_scale_by_norm(double* __restrict__ v, const double* __restrict__ nrm2, int64_t n)
+{
+    const double s2 = nrm2[0];
+    if (!(s2 > 0.0)) return;
+    const double a = 1.0 / sqrt(s2);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] *= a;
+}
+
+// out[0..nv) = a[0..nv) + b[0..nv) (the two Gram-Schmidt passes' coefficients)
+__global__ void k_add_small(const double* __restrict__ a, const double* __restrict__ b, int nv, double* __restrict__ out)
+{
+    for (int c = threadIdx.x; c < nv; c += blockDim.x) out[c] = a[c] + b[c];
+}
+
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -108,21 +125,21 @@ struct Blas {
     Blas(Handle& H, hipStream_t s_, int64_t n_, int maxv) : s(s_), n(n_), part(H.gm_part), dres(H.gm_dres)
     {
         part.reserve((size_t)kDotBlocks * maxv);
-        dres.reserve(maxv);
-        h.resize(maxv);
+        dres.reserve(4 * (size_t)maxv + 4);
+        h.resize(4 * (size_t)maxv + 4);
     }
     int grid() const { return (int)std::min<int64_t>(4096, (n + 255) / 256); }
-    // device result in dres[0..nv), copied to host h
-    const double* dots(const double* V, int nv, const double* w, bool to_host)
+    // device result in dres[at .. at + nv), copied to host h when asked
+    const double* dots(const double* V, int nv, const double* w, bool to_host, int at = 0)
     {
         k_dots<<<kDotBlocks, kDotThreads, 0, s>>>(V, n, nv, w, n, part.p);
-        k_dots_final<<<1, 64, 0, s>>>(part.p, kDotBlocks, nv, dres.p);
+        k_dots_final<<<1, 64, 0, s>>>(part.p, kDotBlocks, nv, dres.p + at);
         HIPCK(hipGetLastError());
         if (to_host) {
-            HIPCK(hipMemcpyAsync(h.data(), dres.p, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(h.data(), dres.p + at, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
             HIPCK(hipStreamSynchronize(s));
         }
-        return dres.p;
+        return dres.p + at;
     }
     double nrm2(const double* w)
     {
@@ -206,18 +223,26 @@ static GmresResult gmres(Handle& H, int prec, const double* rhs, double* x, doub
             } else {
                 launch_matvec(H, Vb.p + (int64_t)j * n, vj1, 1, n, prec, s);
             }
-            // two passes of classical Gram-Schmidt
+            // two passes of classical Gram-Schmidt, the norm and the
+            // normalisation on the device; one read-back per step: the
+            // j + 1 summed coefficients and the squared norm
             std::vector<double> hc(j + 2, 0.0);
-            for (int pass = 0; pass < 2; ++pass) {
-                const double* dh = B.dots(Vb.p, j + 1, vj1, true);
-                for (int i = 0; i <= j; ++i) hc[i] += B.h[i];
-                k_sub_comb<<<grid, 256, 0, s>>>(vj1, Vb.p, n, j + 1, dh, n);
-            }
-            const double hn = B.nrm2(vj1);
+            const int nv = j + 1, o1 = 0, o2 = nv, o3 = 2 * nv;
+            const double* d1 = B.dots(Vb.p, nv, vj1, false, o1);
+            k_sub_comb<<<grid, 256, 0, s>>>(vj1, Vb.p, n, nv, d1, n);
+            const double* d2 = B.dots(Vb.p, nv, vj1, false, o2);
+            k_sub_comb<<<grid, 256, 0, s>>>(vj1, Vb.p, n, nv, d2, n);
+            double* hsum = B.dres.p + o3;
+            k_add_small<<<1, 64, 0, s>>>(d1, d2, nv, hsum);
+            const double* dn = B.dots(vj1, 1, vj1, false, o3 + nv);
+            k_scale_by_norm<<<grid, 256, 0, s>>>(vj1, dn, n);
+            HIPCK(hipGetLastError());
+            HIPCK(hipMemcpyAsync(B.h.data(), hsum, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) hc[i] = B.h[i];
+            const double hn = std::sqrt(std::max(B.h[nv], 0.0));
             hn_last = hn;
             hc[j + 1] = hn;
-            if (hn > 0.0) k_scale<<<grid, 256, 0, s>>>(vj1, vj1, 1.0 / hn, n);
-            HIPCK(hipGetLastError());
             double* col = Hm.data() + (size_t)j * (m + 1);
             for (int i = 0; i <= j + 1; ++i) col[i] = hc[i];
             for (int i = 0; i < j; ++i) {
