@@ -217,6 +217,20 @@ h2d_status h2d_precond_apply(h2d_t H, int32_t precond, const double* r, double* 
  * W3 (64 x 256), b3], row-major. */
 #define H2D_MLP_PARAMS 131648
 
+/* Network input.  LEAF: the leaf's own points and residual (192 values;
+ * correction z_X = s |r_X| (r_X / |r_X| + out), H2D_MLP_PARAMS weights).
+ * PATCH: the near-field patch -- the leaf and its edge-sharing leaves to the
+ * left, right, below and above, 5 x 64 slots of (x offset, y offset from
+ * the leaf's centre in half sides, r_i / |r_P|), 960 values -- and the
+ * correction added to the block-Jacobi step: z_X = K(X, X)^{-1} r_X +
+ * s |r_P| out, trained on what the target solve adds to the block-Jacobi
+ * step (target PATCH: the restricted additive Schwarz step over the patch);
+ * H2D_MLP_PARAMS_PATCH weights, block-Jacobi set up on the way.  A leaf-input
+ * network cannot see the neighbours' residual, which is where restricted
+ * Schwarz gains over block-Jacobi. */
+typedef enum { H2D_MLP_INPUT_LEAF = 0, H2D_MLP_INPUT_PATCH = 1 } h2d_mlp_input;
+#define H2D_MLP_PARAMS_PATCH 328256
+
 typedef enum {
     H2D_MLP_TARGET_LEAF = 0,    /* z_X = K(X, X)^{-1} r_X: the method's leaf-block solves */
     H2D_MLP_TARGET_GLOBAL = 1,  /* z = A^{-1} r by FP64 GMRES, restricted to each leaf */
@@ -233,7 +247,7 @@ typedef struct {
     uint64_t seed;         /* right-hand sides, initial weights, batches */
     double solve_tol;      /* GLOBAL targets: relative residual of the solves */
     int32_t target;        /* h2d_mlp_target */
-    int32_t pad;
+    int32_t input;         /* h2d_mlp_input */
 } h2d_mlp_train_opts;
 
 typedef struct {
@@ -250,7 +264,9 @@ typedef struct {
  * still be set on such a handle; the preconditioner then refuses to run). */
 h2d_status h2d_mlp_train(h2d_t H, const h2d_mlp_train_opts* opts, h2d_mlp_train_info* info, void* stream);
 
-/* Copy the MLP weights out (host, H2D_MLP_PARAMS floats) and/or set them
+/* Copy the MLP weights out (host, H2D_MLP_PARAMS floats, or
+ * H2D_MLP_PARAMS_PATCH for a network trained with the patch input) and/or
+ * set those of a leaf-input network (H2D_MLP_PARAMS floats); setting them
  * (host; marks the preconditioner ready).  `scale` (host, may be NULL)
  * receives the output scale s when reading and sets it when writing.
  * Any pointer may be NULL. */

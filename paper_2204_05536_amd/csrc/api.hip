@@ -639,7 +639,9 @@ h2d_status h2d_mlp_train(h2d_t H, const h2d_mlp_train_opts* opts, h2d_mlp_train_
         if (opts->n_solves < 1 || opts->steps < 0 || opts->batch < 1 || !(opts->lr > 0.f) ||
             (opts->target == H2D_MLP_TARGET_GLOBAL && !(opts->solve_tol > 0.0)) ||
             (opts->target != H2D_MLP_TARGET_LEAF && opts->target != H2D_MLP_TARGET_GLOBAL &&
-             opts->target != H2D_MLP_TARGET_PATCH))
+             opts->target != H2D_MLP_TARGET_PATCH) ||
+            (opts->input != H2D_MLP_INPUT_LEAF && opts->input != H2D_MLP_INPUT_PATCH) ||
+            (opts->input == H2D_MLP_INPUT_PATCH && opts->target == H2D_MLP_TARGET_LEAF))
             fail(H2D_EINVAL, "bad training options");
         mlp_train(H->h, *opts, info, (hipStream_t)stream);
     });

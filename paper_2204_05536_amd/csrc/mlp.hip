@@ -24,10 +24,28 @@
 namespace h2d {
 
 constexpr int kIn = 192, kH = 256, kOut = 64;
-constexpr int64_t kOffW1 = 0, kOffB1 = kOffW1 + (int64_t)kH * kIn, kOffW2 = kOffB1 + kH,
-                  kOffB2 = kOffW2 + (int64_t)kH * kH, kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + (int64_t)kOut * kH,
-                  kParams = kOffB3 + kOut;
-static_assert(kParams == H2D_MLP_PARAMS, "parameter count");
+constexpr int kInPatch = 5 * kIn;   // the leaf and its 4 edge sharers, 64 slots x 3 features each
+
+// Packed parameter layout of a network with `in` inputs:
+// W1 (256 x in), b1, W2 (256 x 256), b2, W3 (64 x 256), b3.
+struct Dims {
+    int in;
+    int64_t w1, b1, w2, b2, w3, b3, params;
+};
+constexpr Dims make_dims(int in)
+{
+    return Dims{in,
+                0,
+                (int64_t)kH * in,
+                (int64_t)kH * in + kH,
+                (int64_t)kH * in + kH + (int64_t)kH * kH,
+                (int64_t)kH * in + 2 * kH + (int64_t)kH * kH,
+                (int64_t)kH * in + 2 * kH + (int64_t)kH * kH + (int64_t)kOut * kH,
+                (int64_t)kH * in + 2 * kH + (int64_t)kH * kH + (int64_t)kOut * kH + kOut};
+}
+constexpr Dims kLeafDims = make_dims(kIn), kPatchDims = make_dims(kInPatch);
+static_assert(kLeafDims.params == H2D_MLP_PARAMS, "parameter count");
+static_assert(kPatchDims.params == H2D_MLP_PARAMS_PATCH, "parameter count (patch input)");
 
 // ---------------------------------------------------------------------
 // FP32 GEMM: C (M x N, row-major, ldc) = alpha op(A) op(B) + beta C, with
@@ -237,7 +255,7 @@ struct MlpWork {
         h1.alloc(B * kH); h2.alloc(B * kH); o.alloc(B * kOut);
         g1.alloc(B * kH); g2.alloc(B * kH); go.alloc(B * kOut);
         part.alloc(1024);
-        split.alloc((size_t)kSplitMax * kH * kH);
+        split.alloc((size_t)kSplitMax * kH * kInPatch);
         colp.alloc((size_t)kColQ * kH);
         count.alloc(1);
         cap = B;
@@ -255,14 +273,14 @@ static int splits_for(int64_t B) { return (int)std::max<int64_t>(1, std::min<int
 
 static int grid_for(int64_t n) { return (int)std::min<int64_t>(4096, (n + 255) / 256); }
 
-static void forward(const float* W, const float* X, int64_t B, MlpWork& w, hipStream_t s)
+static void forward(const Dims& d, const float* W, const float* X, int64_t B, MlpWork& w, hipStream_t s)
 {
-    gemm((int)B, kH, kIn, X, kIn, false, W + kOffW1, kIn, true, w.h1.p, kH, 1.f, 0.f, s);
-    k_bias_act<<<grid_for(B * kH), 256, 0, s>>>(B, kH, W + kOffB1, w.h1.p, 1);
-    gemm((int)B, kH, kH, w.h1.p, kH, false, W + kOffW2, kH, true, w.h2.p, kH, 1.f, 0.f, s);
-    k_bias_act<<<grid_for(B * kH), 256, 0, s>>>(B, kH, W + kOffB2, w.h2.p, 1);
-    gemm((int)B, kOut, kH, w.h2.p, kH, false, W + kOffW3, kH, true, w.o.p, kOut, 1.f, 0.f, s);
-    k_bias_act<<<grid_for(B * kOut), 256, 0, s>>>(B, kOut, W + kOffB3, w.o.p, 0);
+    gemm((int)B, kH, d.in, X, d.in, false, W + d.w1, d.in, true, w.h1.p, kH, 1.f, 0.f, s);
+    k_bias_act<<<grid_for(B * kH), 256, 0, s>>>(B, kH, W + d.b1, w.h1.p, 1);
+    gemm((int)B, kH, kH, w.h1.p, kH, false, W + d.w2, kH, true, w.h2.p, kH, 1.f, 0.f, s);
+    k_bias_act<<<grid_for(B * kH), 256, 0, s>>>(B, kH, W + d.b2, w.h2.p, 1);
+    gemm((int)B, kOut, kH, w.h2.p, kH, false, W + d.w3, kH, true, w.o.p, kOut, 1.f, 0.f, s);
+    k_bias_act<<<grid_for(B * kOut), 256, 0, s>>>(B, kOut, W + d.b3, w.o.p, 0);
     HIPCK(hipGetLastError());
 }
 
@@ -270,11 +288,12 @@ static void forward(const float* W, const float* X, int64_t B, MlpWork& w, hipSt
 // loss is read back (synchronising) only when want_loss.
 // count > 0: the mask sum given by the caller; count <= 0: summed on the
 // device from Mk (no host round trip).
-static float loss_grad(const float* W, const float* X, const float* T, const float* Mk, int64_t B, float count,
-                       float* grad, MlpWork& w, hipStream_t s, bool want_loss = true, const float* rowcnt = nullptr)
+static float loss_grad(const Dims& d, const float* W, const float* X, const float* T, const float* Mk, int64_t B,
+                       float count, float* grad, MlpWork& w, hipStream_t s, bool want_loss = true,
+                       const float* rowcnt = nullptr)
 {
     w.ensure(B);
-    forward(W, X, B, w, s);
+    forward(d, W, X, B, w, s);
     const int nb = std::min<int64_t>(1024, (B * kOut + 255) / 256);
     if (count <= 0.f) {
         if (rowcnt) k_masksum<<<1, 256, 0, s>>>(B, rowcnt, w.count.p);
@@ -285,18 +304,18 @@ static float loss_grad(const float* W, const float* X, const float* T, const flo
     }
     const int S = splits_for(B);
     // layer 3
-    gemm_tn_split(kOut, kH, (int)B, w.go.p, kOut, w.h2.p, kH, grad + kOffW3, w.split.p, S, s);
-    colsum(B, kOut, w.go.p, grad + kOffB3, w, s);
-    gemm((int)B, kH, kOut, w.go.p, kOut, false, W + kOffW3, kH, false, w.g2.p, kH, 1.f, 0.f, s);
+    gemm_tn_split(kOut, kH, (int)B, w.go.p, kOut, w.h2.p, kH, grad + d.w3, w.split.p, S, s);
+    colsum(B, kOut, w.go.p, grad + d.b3, w, s);
+    gemm((int)B, kH, kOut, w.go.p, kOut, false, W + d.w3, kH, false, w.g2.p, kH, 1.f, 0.f, s);
     k_relu_back<<<grid_for(B * kH), 256, 0, s>>>(B, kH, w.h2.p, w.g2.p);
     // layer 2
-    gemm_tn_split(kH, kH, (int)B, w.g2.p, kH, w.h1.p, kH, grad + kOffW2, w.split.p, S, s);
-    colsum(B, kH, w.g2.p, grad + kOffB2, w, s);
-    gemm((int)B, kH, kH, w.g2.p, kH, false, W + kOffW2, kH, false, w.g1.p, kH, 1.f, 0.f, s);
+    gemm_tn_split(kH, kH, (int)B, w.g2.p, kH, w.h1.p, kH, grad + d.w2, w.split.p, S, s);
+    colsum(B, kH, w.g2.p, grad + d.b2, w, s);
+    gemm((int)B, kH, kH, w.g2.p, kH, false, W + d.w2, kH, false, w.g1.p, kH, 1.f, 0.f, s);
     k_relu_back<<<grid_for(B * kH), 256, 0, s>>>(B, kH, w.h1.p, w.g1.p);
     // layer 1
-    gemm_tn_split(kH, kIn, (int)B, w.g1.p, kH, X, kIn, grad + kOffW1, w.split.p, S, s);
-    colsum(B, kH, w.g1.p, grad + kOffB1, w, s);
+    gemm_tn_split(kH, d.in, (int)B, w.g1.p, kH, X, d.in, grad + d.w1, w.split.p, S, s);
+    colsum(B, kH, w.g1.p, grad + d.b1, w, s);
     HIPCK(hipGetLastError());
     if (want_loss && count <= 0.f) {
         HIPCK(hipMemcpyAsync(&count, w.count.p, sizeof(float), hipMemcpyDeviceToHost, s));
@@ -437,6 +456,79 @@ __global__ void k_correction(int32_t nleaf, const int32_t* __restrict__ begin, c
     }
 }
 
+// Patch input (one wave per leaf X): 5 groups of 64 slots -- X, then its
+// edge-sharing leaves to the left, right, below and above (a missing one
+// leaves its group zero) -- each group (x offset / h, y offset / h,
+// r_i / |r_P|) with offsets from the centre of X, h its half side, and
+// |r_P| the residual norm over the whole patch.  Optionally the target
+// t_i = zd_i zscale / |r_P| on X's slots and their mask.
+__global__ void __launch_bounds__(256)
+k_patch_features(int32_t nleaf, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+                 const uint32_t* __restrict__ key, const int32_t* __restrict__ near_ptr,
+                 const int32_t* __restrict__ near_src, int kappa, double R, const double* __restrict__ xyt,
+                 const int32_t* __restrict__ perm, const double* __restrict__ r, const double* __restrict__ zd,
+                 double zscale, float* __restrict__ F, float* __restrict__ rn, float* __restrict__ T,
+                 float* __restrict__ Mk)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t X = blockIdx.x * 4 + wave;
+    if (X >= nleaf) return;
+    const uint32_t kx = key[X];
+    const int32_t ix = (int32_t)compact_bits(kx), iy = (int32_t)compact_bits(kx >> 1);
+    const double h = R / (double)(1u << kappa);
+    const double cx = -R + (2.0 * ix + 1.0) * h, cy = -R + (2.0 * iy + 1.0) * h;
+    // group of each near block: 0 self, 1 left, 2 right, 3 below, 4 above
+    int32_t box[5] = {-1, -1, -1, -1, -1};
+    for (int32_t q = near_ptr[X]; q < near_ptr[X + 1]; ++q) {
+        const int32_t Y = near_src[q];
+        const uint32_t ky = key[Y];
+        const int32_t dx = (int32_t)compact_bits(ky) - ix, dy = (int32_t)compact_bits(ky >> 1) - iy;
+        const int gidx = Y == X ? 0 : dx < 0 ? 1 : dx > 0 ? 2 : dy < 0 ? 3 : 4;
+        box[gidx] = Y;
+    }
+    double ss = 0.0;
+    double rv[5];
+    for (int gi = 0; gi < 5; ++gi) {
+        rv[gi] = 0.0;
+        if (box[gi] >= 0 && lane < count[box[gi]]) rv[gi] = r[perm[begin[box[gi]] + lane]];
+        ss += rv[gi] * rv[gi];
+    }
+    for (int d = 32; d > 0; d >>= 1) ss += __shfl_xor(ss, d, kWave);
+    const double nrm = sqrt(ss), inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    float* f = F + (int64_t)X * kInPatch;
+    for (int gi = 0; gi < 5; ++gi) {
+        const bool on = box[gi] >= 0 && lane < count[box[gi]];
+        const int32_t t = on ? begin[box[gi]] + lane : 0;
+        f[gi * kIn + lane] = on ? (float)((xyt[2 * t] - cx) / h) : 0.f;
+        f[gi * kIn + 64 + lane] = on ? (float)((xyt[2 * t + 1] - cy) / h) : 0.f;
+        f[gi * kIn + 128 + lane] = on ? (float)(rv[gi] * inv) : 0.f;
+    }
+    if (lane == 0) rn[X] = (float)nrm;
+    if (T) {
+        const bool on = lane < count[X];
+        T[(int64_t)X * kOut + lane] = on ? (float)(zd[perm[begin[X] + lane]] * zscale * inv) : 0.f;
+        Mk[(int64_t)X * kOut + lane] = (on && nrm > 0.0) ? 1.f : 0.f;
+    }
+}
+
+// z(X) += s |r_P| O(X) in caller order (z holds the block-Jacobi step).
+__global__ void k_patch_correction(int32_t nleaf, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+                                   const int32_t* __restrict__ perm, const float* __restrict__ O,
+                                   const float* __restrict__ rn, double s, double* __restrict__ z)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t X = blockIdx.x * 4 + wave;
+    if (X >= nleaf) return;
+    if (lane < count[X]) z[perm[begin[X] + lane]] += s * (double)O[(int64_t)X * kOut + lane] * (double)rn[X];
+}
+
+// out = a - b
+__global__ void k_diff(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = a[e] - b[e];
+}
+
 // Counter-based uniform numbers in [-1, 1): splitmix64 of (seed, index).
 __device__ __forceinline__ double uniform_pm1(uint64_t seed, uint64_t i)
 {
@@ -456,7 +548,7 @@ __global__ void k_random(int64_t n, uint64_t seed, double* __restrict__ out)
 // Batch of step `it`: sample index of row b = splitmix64 of (seed, it B + b)
 // modulo nsamp, then rows of F (192), T and Mk (64) gathered (no host
 // round trip per step).
-__global__ void k_sample_batch(int32_t B, int64_t nsamp, uint64_t seed, int64_t it, const float* __restrict__ F,
+__global__ void k_sample_batch(int32_t B, int in, int64_t nsamp, uint64_t seed, int64_t it, const float* __restrict__ F,
                                const float* __restrict__ T, const float* __restrict__ Mk, float* __restrict__ Fb,
                                float* __restrict__ Tb, float* __restrict__ Mb, float* __restrict__ rowcnt)
 {
@@ -467,7 +559,7 @@ __global__ void k_sample_batch(int32_t B, int64_t nsamp, uint64_t seed, int64_t 
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     const int64_t sidx = (int64_t)(z % (uint64_t)nsamp);
-    for (int e = threadIdx.x; e < kIn; e += blockDim.x) Fb[(int64_t)b * kIn + e] = F[sidx * kIn + e];
+    for (int e = threadIdx.x; e < in; e += blockDim.x) Fb[(int64_t)b * in + e] = F[sidx * in + e];
     float c = 0.f;
     for (int e = threadIdx.x; e < kOut; e += blockDim.x) {
         Tb[(int64_t)b * kOut + e] = T[sidx * kOut + e];
@@ -482,6 +574,8 @@ __global__ void k_sample_batch(int32_t B, int64_t nsamp, uint64_t seed, int64_t 
 
 
 struct MlpState {
+    Dims d = kLeafDims;   // parameter layout of the current network
+    int input = H2D_MLP_INPUT_LEAF;
     double scale = 1.0;   // s: z ~ s r over the training solves
     DBuf<float> w, m1, m2, grad;
     MlpWork work;
@@ -490,26 +584,28 @@ struct MlpState {
     int64_t feat_cap = 0;
     bool w16_ok = false;                     // w16 holds the current FP32 weights rounded to BF16
     bool ready = false;
+    DBuf<int32_t> nsrc;                      // device copy of the near-list sources (patch input)
 };
 
 // BF16 forward of nleaf leaves into S.out (FP32 nleaf x 64).
 static void forward_bf16(MlpState& S, int64_t nleaf, hipStream_t s)
 {
-    constexpr int64_t n1 = (int64_t)kH * kIn, n2 = (int64_t)kH * kH, n3 = (int64_t)kOut * kH;
+    const Dims& d = S.d;
+    const int64_t n1 = (int64_t)kH * d.in, n2 = (int64_t)kH * kH, n3 = (int64_t)kOut * kH;
     if (!S.w16_ok) {
         S.w16.alloc(n1 + n2 + n3);
-        k_to_bf16<<<256, 256, 0, s>>>(n1, S.w.p + kOffW1, S.w16.p);
-        k_to_bf16<<<256, 256, 0, s>>>(n2, S.w.p + kOffW2, S.w16.p + n1);
-        k_to_bf16<<<64, 256, 0, s>>>(n3, S.w.p + kOffW3, S.w16.p + n1 + n2);
+        k_to_bf16<<<256, 256, 0, s>>>(n1, S.w.p + d.w1, S.w16.p);
+        k_to_bf16<<<256, 256, 0, s>>>(n2, S.w.p + d.w2, S.w16.p + n1);
+        k_to_bf16<<<64, 256, 0, s>>>(n3, S.w.p + d.w3, S.w16.p + n1 + n2);
         S.w16_ok = true;
     }
     const unsigned g = (unsigned)((nleaf + 63) / 64);
-    k_dense_bf16<float, kH, true, __hip_bfloat16><<<g, 256, 0, s>>>(nleaf, kIn, S.feat.p, S.w16.p, S.w.p + kOffB1,
+    k_dense_bf16<float, kH, true, __hip_bfloat16><<<g, 256, 0, s>>>(nleaf, d.in, S.feat.p, S.w16.p, S.w.p + d.b1,
                                                                      S.h1b.p);
     k_dense_bf16<__hip_bfloat16, kH, true, __hip_bfloat16><<<g, 256, 0, s>>>(nleaf, kH, S.h1b.p, S.w16.p + n1,
-                                                                              S.w.p + kOffB2, S.h2b.p);
+                                                                              S.w.p + d.b2, S.h2b.p);
     k_dense_bf16<__hip_bfloat16, kOut, false, float><<<g, 256, 0, s>>>(nleaf, kH, S.h2b.p, S.w16.p + n1 + n2,
-                                                                        S.w.p + kOffB3, S.out.p);
+                                                                        S.w.p + d.b3, S.out.p);
     HIPCK(hipGetLastError());
 }
 
@@ -537,13 +633,26 @@ void mlp_apply(Handle& H, const double* r, double* z, hipStream_t s)
     check_leaf_slots(H);
     const Level& LL = H.lev[H.kappa];
     const int32_t nleaf = (int32_t)LL.nbox;
-    if (S.feat_cap < nleaf) {
-        S.feat.alloc((size_t)nleaf * kIn);
+    if (S.feat_cap < nleaf || (int64_t)S.feat.n < (int64_t)nleaf * S.d.in) {
+        S.feat.alloc((size_t)nleaf * S.d.in);
         S.rn.alloc(nleaf);
         S.out.alloc((size_t)nleaf * kOut);
         S.h1b.alloc((size_t)nleaf * kH);
         S.h2b.alloc((size_t)nleaf * kH);
         S.feat_cap = nleaf;
+    }
+    if (S.input == H2D_MLP_INPUT_PATCH) {
+        // block-Jacobi step, then the learned correction from the patch
+        if (!H.bj_ready) fail(H2D_EINVAL, "the patch-input MLP needs block-Jacobi (h2d_bj_setup)");
+        precond_apply(H, H2D_PC_BLOCK_JACOBI, r, z, s);
+        k_patch_features<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, LL.key.p, H.near_ptr.p,
+                                                         S.nsrc.p, H.kappa, H.R, H.xyt.p, H.perm.p, r, nullptr, 0.0,
+                                                         S.feat.p, S.rn.p, nullptr, nullptr);
+        forward_bf16(S, nleaf, s);
+        k_patch_correction<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, H.perm.p, S.out.p, S.rn.p,
+                                                           S.scale, z);
+        HIPCK(hipGetLastError());
+        return;
     }
     k_features<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, LL.key.p, H.kappa, H.R, H.xyt.p,
                                                H.perm.p, r, nullptr, 0.0, S.feat.p, S.rn.p, nullptr, nullptr);
@@ -710,12 +819,12 @@ static void patch_targets(Handle& H, const double* R, double* Z, int ns, hipStre
 }
 
 // Xavier-uniform initial weights from the counter-based generator.
-__global__ void k_init_w(float* __restrict__ w, uint64_t seed)
+__global__ void k_init_w(float* __restrict__ w, uint64_t seed, Dims d)
 {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < kParams; e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.params; e += (int64_t)gridDim.x * blockDim.x) {
         float lim = 0.f;
-        if (e < kOffB1) lim = sqrtf(6.f / (kIn + kH));
-        else if (e >= kOffW2 && e < kOffB2) lim = sqrtf(6.f / (kH + kH));
+        if (e < d.b1) lim = sqrtf(6.f / (d.in + kH));
+        else if (e >= d.w2 && e < d.b2) lim = sqrtf(6.f / (kH + kH));
         // the last layer starts at zero: the untrained preconditioner is s I
         w[e] = lim * (float)uniform_pm1(seed, (uint64_t)e);
     }
@@ -723,19 +832,25 @@ __global__ void k_init_w(float* __restrict__ w, uint64_t seed)
 
 static void ensure_weights(MlpState& S, hipStream_t s)
 {
-    if (S.w.p) return;
-    S.w.alloc(kParams);
-    S.m1.alloc(kParams);
-    S.m2.alloc(kParams);
-    S.grad.alloc(kParams);
-    HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * kParams, s));
-    HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
+    if (S.w.p && (int64_t)S.w.n == S.d.params) return;
+    S.w.alloc(S.d.params);
+    S.m1.alloc(S.d.params);
+    S.m2.alloc(S.d.params);
+    S.grad.alloc(S.d.params);
+    HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * S.d.params, s));
+    HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * S.d.params, s));
+    S.ready = false;
 }
 
 void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info, hipStream_t s)
 {
     check_leaf_slots(H);
     MlpState& S = mlp_state(H);
+    const bool patch_in = o.input == H2D_MLP_INPUT_PATCH;
+    const Dims d = patch_in ? kPatchDims : kLeafDims;
+    if (S.d.in != d.in) S.ready = false;   // another network: start from fresh weights
+    S.d = d;
+    S.input = patch_in ? H2D_MLP_INPUT_PATCH : H2D_MLP_INPUT_LEAF;
     const Level& LL = H.lev[H.kappa];
     const int32_t nleaf = (int32_t)LL.nbox;
     const int64_t n = H.n;
@@ -744,7 +859,7 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
     // training pairs from the method's own FP64 solves
     const int64_t nsamp = (int64_t)ns * nleaf;
     DBuf<float> F, T, Mk, rn;
-    F.alloc((size_t)nsamp * kIn);
+    F.alloc((size_t)nsamp * d.in);
     T.alloc((size_t)nsamp * kOut);
     Mk.alloc((size_t)nsamp * kOut);
     rn.alloc(nsamp);
@@ -754,11 +869,12 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
     so.max_iter = 500;
     so.precond = H2D_PC_NONE;
     int solves_ok = 0;
-    if (o.target == H2D_MLP_TARGET_LEAF && !H.bj_ready) bj_setup(H, s);
-    DBuf<double> R, Z, W;
+    if ((o.target == H2D_MLP_TARGET_LEAF || patch_in) && !H.bj_ready) bj_setup(H, s);
+    DBuf<double> R, Z, W, Zb;
     R.alloc((size_t)n * ns);
     Z.alloc((size_t)n * ns);
     W.alloc((size_t)n);
+    if (patch_in) Zb.alloc((size_t)n * ns);
     double zr = 0.0, rr = 0.0;
     std::vector<double> hw(n);
     for (int q = 0; q < ns; ++q) {
@@ -778,6 +894,7 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
             for (int64_t i = 0; i < n; ++i) hw[i] *= f;
             HIPCK(hipMemcpyAsync(rq, hw.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
         }
+        if (patch_in) precond_apply(H, H2D_PC_BLOCK_JACOBI, rq, Zb.p + (int64_t)q * n, s);
         if (o.target == H2D_MLP_TARGET_GLOBAL) {
             h2d_solve_info si{};
             h2d_status st = solve(H, rq, zq, o.solve_tol, so, &si, s);
@@ -790,23 +907,39 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
         }
     }
     if (o.target == H2D_MLP_TARGET_PATCH) patch_targets(H, R.p, Z.p, ns, s);
+    // s: the least-squares scalar z ~ s r of the targets (leaf input) or of
+    // the block-Jacobi steps the patch-input correction is added to
     {
+        const DBuf<double>& Zs = patch_in ? Zb : Z;
         std::vector<double> hr(n), hz(n);
         for (int q = 0; q < ns; ++q) {
             HIPCK(hipMemcpyAsync(hr.data(), R.p + (int64_t)q * n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(hz.data(), Z.p + (int64_t)q * n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(hz.data(), Zs.p + (int64_t)q * n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
             HIPCK(hipStreamSynchronize(s));
             for (int64_t i = 0; i < n; ++i) { zr += hz[i] * hr[i]; rr += hr[i] * hr[i]; }
         }
     }
     S.scale = rr > 0.0 ? zr / rr : 1.0;
     if (!(S.scale != 0.0) || !std::isfinite(S.scale)) S.scale = 1.0;
+    if (patch_in) {
+        // target: what the target solve adds to the block-Jacobi step
+        k_diff<<<grid_for(n * ns), 256, 0, s>>>(n * ns, Z.p, Zb.p, Z.p);
+        S.nsrc.alloc(std::max<size_t>(H.h_near_src.size(), 1));
+        HIPCK(hipMemcpyAsync(S.nsrc.p, H.h_near_src.data(), sizeof(int32_t) * H.h_near_src.size(),
+                             hipMemcpyHostToDevice, s));
+    }
     for (int q = 0; q < ns; ++q) {
-        k_features<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, LL.key.p, H.kappa, H.R, H.xyt.p,
-                                                   H.perm.p, R.p + (int64_t)q * n, Z.p + (int64_t)q * n,
-                                                   1.0 / S.scale, F.p + (int64_t)q * nleaf * kIn,
-                                                   rn.p + (int64_t)q * nleaf, T.p + (int64_t)q * nleaf * kOut,
-                                                   Mk.p + (int64_t)q * nleaf * kOut);
+        if (patch_in)
+            k_patch_features<<<(nleaf + 3) / 4, 256, 0, s>>>(
+                nleaf, LL.begin.p, LL.count.p, LL.key.p, H.near_ptr.p, S.nsrc.p, H.kappa, H.R, H.xyt.p, H.perm.p,
+                R.p + (int64_t)q * n, Z.p + (int64_t)q * n, 1.0 / S.scale, F.p + (int64_t)q * nleaf * d.in,
+                rn.p + (int64_t)q * nleaf, T.p + (int64_t)q * nleaf * kOut, Mk.p + (int64_t)q * nleaf * kOut);
+        else
+            k_features<<<(nleaf + 3) / 4, 256, 0, s>>>(nleaf, LL.begin.p, LL.count.p, LL.key.p, H.kappa, H.R, H.xyt.p,
+                                                       H.perm.p, R.p + (int64_t)q * n, Z.p + (int64_t)q * n,
+                                                       1.0 / S.scale, F.p + (int64_t)q * nleaf * d.in,
+                                                       rn.p + (int64_t)q * nleaf, T.p + (int64_t)q * nleaf * kOut,
+                                                       Mk.p + (int64_t)q * nleaf * kOut);
         HIPCK(hipGetLastError());
     }
     HIPCK(hipStreamSynchronize(s));
@@ -814,13 +947,13 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
     // training
     ensure_weights(S, s);
     if (!S.ready) {
-        k_init_w<<<256, 256, 0, s>>>(S.w.p, o.seed ^ 0xA5A5A5A5ull);
-        HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * kParams, s));
-        HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
+        k_init_w<<<256, 256, 0, s>>>(S.w.p, o.seed ^ 0xA5A5A5A5ull, d);
+        HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * d.params, s));
+        HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * d.params, s));
     }
     const int B = std::max(1, std::min<int>(o.batch, (int)nsamp));
     DBuf<float> Fb, Tb, Mb, rc;
-    Fb.alloc((size_t)B * kIn);
+    Fb.alloc((size_t)B * d.in);
     Tb.alloc((size_t)B * kOut);
     Mb.alloc((size_t)B * kOut);
     rc.alloc(B);
@@ -830,13 +963,14 @@ void mlp_train(Handle& H, const h2d_mlp_train_opts& o, h2d_mlp_train_info* info,
     for (int it = 0; it < o.steps; ++it) {
         // batch drawn and gathered on the device; the mask sum (valid slots)
         // is taken there too, so a step has no host round trip
-        k_sample_batch<<<B, 64, 0, s>>>(B, nsamp, bseed, it, F.p, T.p, Mk.p, Fb.p, Tb.p, Mb.p, rc.p);
+        k_sample_batch<<<B, 64, 0, s>>>(B, d.in, nsamp, bseed, it, F.p, T.p, Mk.p, Fb.p, Tb.p, Mb.p, rc.p);
         const bool report = it == 0 || it + 1 == o.steps;
-        const float L = loss_grad(S.w.p, Fb.p, Tb.p, Mb.p, B, 0.f, S.grad.p, S.work, s, report, rc.p);
+        const float L = loss_grad(d, S.w.p, Fb.p, Tb.p, Mb.p, B, 0.f, S.grad.p, S.work, s, report, rc.p);
         if (it == 0) first = L;
         if (report) last = L;
         const float c1 = 1.f - std::pow(b1, (float)(it + 1)), c2 = 1.f - std::pow(b2, (float)(it + 1));
-        k_adam<<<grid_for(kParams), 256, 0, s>>>(kParams, S.w.p, S.grad.p, S.m1.p, S.m2.p, o.lr, b1, b2, c1, c2, 1e-8f);
+        k_adam<<<grid_for(d.params), 256, 0, s>>>(d.params, S.w.p, S.grad.p, S.m1.p, S.m2.p, o.lr, b1, b2, c1, c2,
+                                                  1e-8f);
         HIPCK(hipGetLastError());
     }
     HIPCK(hipStreamSynchronize(s));
@@ -860,16 +994,19 @@ void mlp_weights(Handle& H, float* out, const float* in, double* scale, hipStrea
     if (in && scale) S.scale = *scale;
     if (out && scale) *scale = S.scale;
     if (in) {
+        // weights set from the host are always a leaf-input network
+        S.d = kLeafDims;
+        S.input = H2D_MLP_INPUT_LEAF;
         ensure_weights(S, s);
-        HIPCK(hipMemcpyAsync(S.w.p, in, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
-        HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * kParams, s));
-        HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * kParams, s));
+        HIPCK(hipMemcpyAsync(S.w.p, in, sizeof(float) * S.d.params, hipMemcpyHostToDevice, s));
+        HIPCK(hipMemsetAsync(S.m1.p, 0, sizeof(float) * S.d.params, s));
+        HIPCK(hipMemsetAsync(S.m2.p, 0, sizeof(float) * S.d.params, s));
         S.ready = true;
         S.w16_ok = false;
     }
     if (out) {
         if (!S.w.p) fail(H2D_EINVAL, "no MLP weights");
-        HIPCK(hipMemcpyAsync(out, S.w.p, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(out, S.w.p, sizeof(float) * S.d.params, hipMemcpyDeviceToHost, s));
     }
     HIPCK(hipStreamSynchronize(s));
 }
@@ -883,7 +1020,7 @@ float mlp_loss_grad(const float* W, const float* X, const float* T, const float*
     HIPCK(hipStreamSynchronize(s));
     double cnt = 0;
     for (float v : hm) cnt += v;
-    return loss_grad(W, X, T, Mk, B, (float)std::max(1.0, cnt), grad, w, s);
+    return loss_grad(kLeafDims, W, X, T, Mk, B, (float)std::max(1.0, cnt), grad, w, s);
 }
 
 }  // namespace h2d

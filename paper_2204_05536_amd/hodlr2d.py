@@ -31,6 +31,7 @@ EXPORTED = ["h2d_build", "h2d_matvec", "h2d_matvec_noalloc", "h2d_solve", "h2d_i
             "h2d_mlp_train", "h2d_mlp_weights", "h2d_mlp_loss_grad", "h2d_autotune", "h2d_set_item_rows", "h2d_batch_create",
             "h2d_batch_launch", "h2d_batch_destroy", "h2d_destroy", "h2d_last_error"]
 MLP_PARAMS = 131648
+MLP_PARAMS_PATCH = 328256
 PHASES = ["gather", "phaseA", "reduce", "phaseB", "combine"]
 
 
@@ -69,7 +70,7 @@ class h2d_profile(C.Structure):
 
 class h2d_mlp_train_opts(C.Structure):
     _fields_ = [("n_solves", C.c_int32), ("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
-                ("seed", C.c_uint64), ("solve_tol", C.c_double), ("target", C.c_int32), ("pad", C.c_int32)]
+                ("seed", C.c_uint64), ("solve_tol", C.c_double), ("target", C.c_int32), ("input", C.c_int32)]
 
 
 class h2d_mlp_train_info(C.Structure):
@@ -264,16 +265,19 @@ class HODLR2D:
                 "ms": dict(zip(PHASES, list(p.ms))), "bytes": dict(zip(PHASES, list(p.bytes)))}
 
     def mlp_train(self, n_solves=16, steps=1500, batch=4096, lr=5e-4, seed=1234, solve_tol=1e-10,
-                  target="leaf") -> dict:
+                  target="leaf", input="leaf") -> dict:
         o = h2d_mlp_train_opts(int(n_solves), int(steps), int(batch), float(lr), int(seed), float(solve_tol),
-                               {"leaf": 0, "global": 1, "patch": 2}[target], 0)
+                               {"leaf": 0, "global": 1, "patch": 2}[target], {"leaf": 0, "patch": 1}[input])
         info = h2d_mlp_train_info()
         _check(load().h2d_mlp_train(self._h, C.byref(o), C.byref(info), _stream()))
         return {f: getattr(info, f) for f, _ in h2d_mlp_train_info._fields_}
 
-    def mlp_weights(self, set_to=None, scale=None):
-        """Return (weights float32, scale); set them first if given."""
+    def mlp_weights(self, set_to=None, scale=None, patch=False):
+        """Return (weights float32, scale); set them first if given.  patch:
+        the handle's network was trained with the patch input (its weights
+        are MLP_PARAMS_PATCH floats)."""
         import numpy as np
+        size = MLP_PARAMS_PATCH if patch else MLP_PARAMS
         inp = None
         if set_to is not None:
             inp = np.ascontiguousarray(set_to, dtype=np.float32)
@@ -281,7 +285,7 @@ class HODLR2D:
         sc = C.c_double(1.0 if scale is None else float(scale))
         if inp is not None:
             _check(load().h2d_mlp_weights(self._h, None, C.c_void_p(inp.ctypes.data), C.byref(sc), _stream()))
-        out = np.empty(MLP_PARAMS, np.float32)
+        out = np.empty(size, np.float32)
         _check(load().h2d_mlp_weights(self._h, C.c_void_p(out.ctypes.data), None, C.byref(sc), _stream()))
         return out, sc.value
 
