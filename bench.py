@@ -544,8 +544,15 @@ def adaptive_vs_balanced(n=250000, rows=48):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 10
+        H.profile_read()
+        H.profile_enable(True)
+        for _ in range(5):
+            H.matvec(xd, out=y)
+        torch.cuda.synchronize()
+        H.profile_enable(False)
+        phases = H.profile_read()["ms"]
         yh = y.cpu().numpy()
-        out[name] = {"depth": I["kappa"], "compressed_blocks": I["n_il"], "near_blocks": I["n_near"],
+        out[name] = {"depth": I["kappa"], "compressed_blocks": I["n_il"], "near_blocks": I["n_near"], "phases_ms": phases,
                      "stored_values": I["u_elems"] + I["v_elems"] + I["d_elems"], "build_seconds": tb,
                      "ms_per_matvec": ms, "GB/s": I["alg_bytes_fp64"] / (ms * 1e-3) / 1e9,
                      "max_row_err_rel_abs": float(np.max(np.abs(yh[ridx] - yd) / sc))}

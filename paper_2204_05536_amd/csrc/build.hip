@@ -806,6 +806,21 @@ __device__ double block_sum(double v, double* lv)
     return r;
 }
 
+// Largest value over the workgroup (fixed order).
+__device__ double block_sum_max(double v, double* lv)
+{
+    int t = threadIdx.x;
+    lv[t] = v;
+    __syncthreads();
+    for (int d = kAcaThreads / 2; d > 0; d >>= 1) {
+        if (t < d) lv[t] = fmax(lv[t], lv[t + d]);
+        __syncthreads();
+    }
+    double r = lv[0];
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
@@ -838,6 +853,29 @@ k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double
     const double* P = xyt;
     for (int32_t e = t; e < m + n; e += kAcaThreads) usedR[e] = 0;
     __syncthreads();
+    if (kp.kind == H2D_K_GAUSS && m > 0 && n > 0) {
+        // Rows of a Gaussian block that are exactly zero: exp(-(r / c)^2)
+        // is +0 in FP64 once (r / c)^2 > 746, so a row whose point lies
+        // farther than c sqrt(760) from the bounding rectangle of the
+        // column points has no nonzero entry.  Marking such rows used up
+        // front gives the same pivots and crosses as meeting them one by
+        // one (a zero residual row is only ever marked used and passed
+        // over), without evaluating them.
+        double bx0 = 1e300, by0 = 1e300, bx1 = -1e300, by1 = -1e300;
+        for (int32_t j = t; j < n; j += kAcaThreads) {
+            const double x = P[2 * (J.col0 + j)], y = P[2 * (J.col0 + j) + 1];
+            bx0 = fmin(bx0, x); bx1 = fmax(bx1, x); by0 = fmin(by0, y); by1 = fmax(by1, y);
+        }
+        bx0 = -block_sum_max(-bx0, lv); bx1 = block_sum_max(bx1, lv);
+        by0 = -block_sum_max(-by0, lv); by1 = block_sum_max(by1, lv);
+        const double lim = 760.0 * kp.c * kp.c;
+        for (int32_t ii = t; ii < m; ii += kAcaThreads) {
+            const double px = P[2 * (J.row0 + ii)], py = P[2 * (J.row0 + ii) + 1];
+            const double dx = fmax(0.0, fmax(bx0 - px, px - bx1)), dy = fmax(0.0, fmax(by0 - py, py - by1));
+            if (dx * dx + dy * dy > lim) usedR[ii] = 1;
+        }
+        __syncthreads();
+    }
     __shared__ int32_t first_nz;
     int32_t k = 0, i = 0, nusedR = 0, kind = kLowRank;
     double S2 = 0.0;
@@ -858,6 +896,7 @@ k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double
             __syncthreads();
             for (int64_t e = t; e < (int64_t)nr * n; e += kAcaThreads) {
                 const int32_t ii = r0 + (int32_t)(e / n), j = (int32_t)(e % n);
+                if (usedR[ii]) continue;   // known zero row
                 const double v = kernel_entry(kp, P[2 * (J.row0 + ii)], P[2 * (J.row0 + ii) + 1], P[2 * (J.col0 + j)],
                                               P[2 * (J.col0 + j) + 1], J.row0 + ii == J.col0 + j);
                 if (v != 0.0) atomicMin(&first_nz, ii);

@@ -691,11 +691,13 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
 }
 
 // Phase B on an adaptive tree (leaves at several levels).  One wave per
-// 64-row chunk of a leaf; lane r owns one row and sums, in a fixed order,
-// the leaf's dense near-field blocks, then the blocks whose target is the
-// leaf or one of its ancestors, from the leaf up.  U and D are plain
-// column-major (ld = the target box's size), so the lanes' loads of one
-// column are consecutive.
+// 64-row chunk of a leaf; the chunk's rows are rounded up to S = 16, 32 or
+// 64 and lane (g, r) owns row r and the columns g, g + G, ... (G = 64 / S)
+// of every block, so small leaves still keep every lane loading.  The
+// wave sums, in a fixed order, the leaf's dense near-field blocks, then
+// the blocks whose target is the leaf or one of its ancestors, from the
+// leaf up; the G column-group sums of a row are added in order at the end.
+// U and D are plain column-major (ld = the target box's size).
 __global__ void __launch_bounds__(256)
 k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t* __restrict__ leaf_level,
                   const int32_t* __restrict__ leaf_box, LevelPtrs L, const int32_t* __restrict__ near_ptr,
@@ -703,6 +705,7 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
                   const double* __restrict__ Dp, const double* __restrict__ tpool, const double* __restrict__ xs,
                   double* __restrict__ y)
 {
+    __shared__ double red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t it = blockIdx.x * 4 + wave;
     if (it >= nitems) return;
@@ -711,16 +714,19 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
     const int lx = uni(leaf_level[X]);
     const int32_t box = uni(leaf_box[X]);
     const int32_t r0 = uni(L.begin[lx][box]), cnt = uni(L.count[lx][box]);
-    const bool act = rc + lane < cnt;
-    const int32_t row = r0 + rc + lane;
+    const int32_t rows = min(kWave, cnt - rc);
+    const int S = rows <= 16 ? 16 : rows <= 32 ? 32 : 64, G = kWave / S;
+    const int g = lane / S, r = lane % S;
+    const bool act = r < rows;
+    const int32_t row = r0 + rc + r;
     double acc = 0.0;
     const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
     for (int32_t q = n0; q < n1; ++q) {
         const BDesc d = uni(bnear[q]);
         if (!act) continue;
-        const double* base = Dp + d.off + rc + lane;
+        const double* base = Dp + d.off + rc + r;
         const double* xv = xs + d.tsrc;
-        for (int32_t j = 0; j < -d.cols; ++j) acc += base[(int64_t)j * cnt] * xv[j];
+        for (int32_t j = g; j < -d.cols; j += G) acc += base[(int64_t)j * cnt] * xv[j];
     }
     int32_t a = box;
     for (int l = lx; l >= 1; --l) {
@@ -733,16 +739,25 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
             if (d.cols > 0) {
                 const double* base = Up + d.off + roff;
                 const double* tv = tpool + d.tsrc;
-                for (int32_t c = 0; c < d.cols; ++c) acc += base[(int64_t)c * m] * tv[c];
+#pragma unroll 4
+                for (int32_t c = g; c < d.cols; c += G) acc += base[(int64_t)c * m] * tv[c];
             } else {
                 const double* base = Dp + d.off + roff;
                 const double* xv = xs + d.tsrc;
-                for (int32_t j = 0; j < -d.cols; ++j) acc += base[(int64_t)j * m] * xv[j];
+#pragma unroll 4
+                for (int32_t j = g; j < -d.cols; j += G) acc += base[(int64_t)j * m] * xv[j];
             }
         }
         a = uni(L.parent[l][a]);
     }
-    if (act) y[row] = acc;
+    red[wave][lane] = act ? acc : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rows) {
+        double s = 0.0;
+        for (int gg = 0; gg < G; ++gg) s += red[wave][gg * S + lane];
+        y[r0 + rc + lane] = s;
+    }
 }
 
 // y (caller order) = ypart + yleaf (+ the FP32 self diagonal times x for
