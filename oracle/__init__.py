@@ -80,6 +80,7 @@ def lib():
         L.orc_il_factors.argtypes = [P, C.c_int64, dp, dp, dp]
         i32p = C.POINTER(C.c_int32)
         L.orc_is_adaptive.argtypes = [P]; L.orc_is_adaptive.restype = C.c_int32
+        L.orc_is_symmetric.argtypes = [P]; L.orc_is_symmetric.restype = C.c_int32
         L.orc_block_levels.argtypes = [P, i32p, i32p, i32p, i32p]
         L.orc_admissible.argtypes = [C.c_int, C.c_uint32, C.c_int, C.c_uint32]
         L.orc_admissible.restype = C.c_int
@@ -217,16 +218,20 @@ class OracleH:
     ``adaptive=True`` builds the adaptive tree (a box is split exactly when
     it holds more than leaf_max points) and its blocks between boxes of any
     levels.
+    ``symmetric=True`` (symmetric kernels, balanced tree) compresses only the
+    block of each interaction-list pair whose target box has the smaller
+    index; the mirror block is its exact transpose.
     """
 
-    def __init__(self, xy, spec, leaf_max=64, tol=1e-10, factors=True, adaptive=False):
+    def __init__(self, xy, spec, leaf_max=64, tol=1e-10, factors=True, adaptive=False, symmetric=False):
         self.xy = _f64(xy)
         self.n = self.xy.shape[0]
         self.spec = dict(spec)
         self._k = kernel_struct(spec)
         h = C.c_void_p()
         st = lib().orc_build(_dp(self.xy), self.n, C.byref(self._k), int(leaf_max), float(tol),
-                             (1 if factors else 0) | (2 if adaptive else 0), C.byref(h))
+                             (1 if factors else 0) | (2 if adaptive else 0) | (4 if symmetric else 0),
+                             C.byref(h))
         if st != ORC_OK:
             raise OracleError(st, "build")
         self._h = h
@@ -277,6 +282,10 @@ class OracleH:
     @property
     def adaptive(self):
         return bool(lib().orc_is_adaptive(self._h))
+
+    @property
+    def symmetric(self):
+        return bool(lib().orc_is_symmetric(self._h))
 
     def block_levels(self):
         """(near target levels, near source levels, IL target levels, IL source levels)."""

@@ -25,6 +25,12 @@
  *                           cross approximation without details, the
  *                           variant used is written out in orc_aca().
  *   matvec ................ Algorithm 2 (near field, then levels 1..kappa).
+ *   symmetric sharing ..... Section 2.1 (Notations: the matrix is taken
+ *                           symmetric): with a symmetric kernel the block
+ *                           of (C', C) is the transpose of the block of
+ *                           (C, C'); in that mode only the block whose
+ *                           target box has the smaller index is compressed
+ *                           and its mirror is its exact transpose.
  *   GMRES ................. Section 5 (restarted GMRES on the fast matvec).
  *
  * Parity pins for every function here live in tests/test_oracle_*.py.
@@ -233,6 +239,7 @@ typedef struct {
     orc_block* il;           /* interaction-list blocks, (level, tgt, src) order */
     int factors;             /* 0 = structure only */
     int adaptive;            /* 1: adaptive tree (leaves at several levels) */
+    int symmetric;           /* 1: the block of (s, t), t > s, is the transpose of (t, s) */
 } orc_h;
 
 static void orc_free_levels(orc_h* h)
@@ -697,10 +704,51 @@ int64_t orc_aca(const orc_kernel* kern, const double* xy, const int64_t* rows, i
 /* Algorithm 1                                                          */
 /* ------------------------------------------------------------------ */
 
+/* Index of the IL block (level, tgt, src) in the (level, tgt, src)-sorted
+ * table of a balanced tree, or -1. */
+static int64_t orc_find_block(const orc_h* h, int32_t level, int64_t tgt, int64_t src)
+{
+    int64_t lo = 0, hi = h->n_il;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        const orc_block* B = &h->il[mid];
+        int less = B->level != level ? B->level < level : (B->tgt != tgt ? B->tgt < tgt : B->src < src);
+        if (less) lo = mid + 1; else hi = mid;
+    }
+    if (lo < h->n_il && h->il[lo].level == level && h->il[lo].tgt == tgt && h->il[lo].src == src) return lo;
+    return -1;
+}
+
+/* Symmetric mode: the block (level, t, s) with t > s takes the transpose of
+ * the block (level, s, t): U and V swapped for low rank, D transposed for
+ * dense (kind and rank from the owner). */
+static int orc_mirror_block(orc_h* h, orc_block* B)
+{
+    int64_t o = orc_find_block(h, B->level, B->src, B->tgt);
+    if (o < 0) return ORC_EINVAL;
+    const orc_block* O = &h->il[o];
+    int64_t m = h->lev[B->level].count[B->tgt], n = h->lev[B->level].count[B->src];
+    B->kind = O->kind;
+    B->k = O->k;
+    if (O->kind == BK_DENSE) {
+        /* owner D is n x m (rows of src) */
+        B->D = (double*)malloc(sizeof(double) * (size_t)(m * n));
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < m; ++i) B->D[j * m + i] = O->D[i * n + j];
+        return ORC_OK;
+    }
+    B->U = (double*)malloc(sizeof(double) * (size_t)(m * O->k > 0 ? m * O->k : 1));
+    B->V = (double*)malloc(sizeof(double) * (size_t)(n * O->k > 0 ? n * O->k : 1));
+    memcpy(B->U, O->V, sizeof(double) * (size_t)(m * O->k));
+    memcpy(B->V, O->U, sizeof(double) * (size_t)(n * O->k));
+    return ORC_OK;
+}
+
 /* Dense near-field blocks by their entries; ACA for the interaction-list
  * blocks.  Rows are the target box's points, columns the source box's, in
- * tree order (each box on its own level). */
-static void orc_fill_factors(orc_h* h)
+ * tree order (each box on its own level).  In symmetric mode the blocks
+ * with tgt > src are filled last, as transposes. */
+static int orc_fill_factors(orc_h* h)
 {
     const orc_kernel* kern = &h->kern;
     const double* xy = h->xy;
@@ -719,6 +767,7 @@ static void orc_fill_factors(orc_h* h)
     }
     for (int64_t t = 0; t < h->n_il; ++t) {
         orc_block* B = &h->il[t];
+        if (h->symmetric && B->tgt > B->src) continue;
         const orc_level_t* LT = &h->lev[B->level];
         const orc_level_t* LS = &h->lev[B->slevel];
         int64_t m = LT->count[B->tgt], nn = LS->count[B->src];
@@ -727,6 +776,10 @@ static void orc_fill_factors(orc_h* h)
         B->k = orc_aca(kern, xy, rows, m, cols, nn, h->tol, &B->kind, &B->U, &B->V, &B->D);
     }
     free(rows); free(cols);
+    if (h->symmetric)
+        for (int64_t t = 0; t < h->n_il; ++t)
+            if (h->il[t].tgt > h->il[t].src && orc_mirror_block(h, &h->il[t]) != ORC_OK) return ORC_EINVAL;
+    return ORC_OK;
 }
 
 static int orc_has_duplicates(const orc_h* h)
@@ -758,6 +811,9 @@ int orc_build(const double* xy, int64_t n, const orc_kernel* kern, int32_t leaf_
     h->n = n; h->leaf_max = leaf_max; h->tol = tol; h->kern = *kern;
     h->factors = with_factors & 1;
     h->adaptive = (with_factors >> 1) & 1;
+    h->symmetric = (with_factors >> 2) & 1;
+    /* sharing needs a symmetric kernel and same-level pairs */
+    if (h->symmetric && (h->adaptive || kern->kind == OK_SEP)) { free(h->xy); free(h); return ORC_EINVAL; }
     h->xy = (double*)malloc(sizeof(double) * (size_t)(2 * n));
     memcpy(h->xy, xy, sizeof(double) * (size_t)(2 * n));
     h->R = orc_box_radius(xy, n);
@@ -806,7 +862,7 @@ int orc_build(const double* xy, int64_t n, const orc_kernel* kern, int32_t leaf_
             }
         }
     }
-    if (h->factors) orc_fill_factors(h);
+    if (h->factors && orc_fill_factors(h) != ORC_OK) { orc_free(h); return ORC_EINVAL; }
     *out = h;
     return ORC_OK;
 }
@@ -977,6 +1033,7 @@ void orc_near_table(const orc_h* h, int64_t* tgt, int64_t* src)
     for (int64_t b = 0; b < h->n_near; ++b) { tgt[b] = h->near[b].tgt; src[b] = h->near[b].src; }
 }
 int32_t orc_is_adaptive(const orc_h* h) { return h->adaptive; }
+int32_t orc_is_symmetric(const orc_h* h) { return h->symmetric; }
 /* Levels of the target and source boxes of every near and IL block. */
 void orc_block_levels(const orc_h* h, int32_t* near_tl, int32_t* near_sl, int32_t* il_tl, int32_t* il_sl)
 {
