@@ -95,6 +95,27 @@ typedef enum { H2D_P_FP64 = 0, H2D_P_FP16 = 1, H2D_P_BF16 = 2 } h2d_prec;
  * tile tuning return EUNSUPPORTED. */
 #define H2D_BUILD_ADAPTIVE (1u << 8)
 
+/* Build flag (OR-ed into h2d_build's prec_mask, or h2d_import's): one
+ * factor pair per interaction-list pair.  Section 2.1 takes the matrix
+ * symmetric; for a symmetric kernel the block of (C', C) is the transpose
+ * of the block of (C, C').  Only the block whose target box has the smaller
+ * index is compressed, (X, Y) ~ F_X F_Y^T, and the mirror applies F_Y F_X^T;
+ * dense and edge-sharing blocks are stored once too.  Factor
+ * storage is about half the ordered form's, and the product reads the
+ * factors above the leaf level 1.5 times and the leaf-level pairs once
+ * (the ordered product: 2 and 2 per pair).  Needs a symmetric kernel (every
+ * kind but H2D_K_SEP), the balanced tree, leaves of at most 64 points, and
+ * FP64 pools only (else EUNSUPPORTED).  h2d_import with this flag takes an
+ * ordered file whose mirror blocks are exact transposes of their owners
+ * (the oracle's symmetric build writes such files; else EINVAL).
+ * Symmetric handles serve h2d_matvec (right-hand sides one at a time),
+ * plain h2d_solve, h2d_info, h2d_export (ordered, mirrors written as the
+ * transposes) and h2d_profile_*; the fixed-array product, preconditioners,
+ * batches and tile tuning return EUNSUPPORTED.  Profile phases of a
+ * symmetric product: gather, walk 1 + its reduction, walk 2 + the leaf
+ * pairs, the second reduction + walk 3 + the slot sums, combine. */
+#define H2D_BUILD_SYMMETRIC (1u << 9)
+
 /* Algorithm 1 (InitializeHODLR2D(N_max, eps)) on the GPU.
  *   xy        device, n x 2 row-major FP64 point coordinates (copied)
  *   n         number of points, 1 <= n < 2^31

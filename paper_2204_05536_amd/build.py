@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libh2d.so")
-SOURCES = ["api.hip", "build.hip", "matvec.hip", "solve.hip", "precond.hip", "mlp.hip", "mrhs.hip", "batch.hip"]
+SOURCES = ["api.hip", "build.hip", "matvec.hip", "solve.hip", "precond.hip", "mlp.hip", "mrhs.hip", "batch.hip",
+           "symmetric.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -81,6 +81,15 @@ static void check_kernel(const h2d_kernel* k)
     if (!std::isfinite(k->c) || !std::isfinite(k->diag_value)) fail(H2D_EINVAL, "non-finite kernel parameter");
 }
 
+// Symmetric sharing needs a symmetric kernel, a balanced tree and FP64
+// factors only.
+static void check_symmetric(int32_t kind, bool adaptive, uint32_t prec_mask)
+{
+    if (kind == H2D_K_SEP) fail(H2D_EUNSUPPORTED, "the separable test kernel is not symmetric");
+    if (adaptive) fail(H2D_EUNSUPPORTED, "symmetric sharing needs a balanced tree");
+    if (prec_mask & ~1u) fail(H2D_EUNSUPPORTED, "symmetric handles keep FP64 factors only");
+}
+
 // ---------------------------------------------------------------------
 // Export / import ("H2DX" version 1)
 // ---------------------------------------------------------------------
@@ -180,11 +189,22 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
                 if (fac) F.w(D.data() + H.h_near_off[q], (size_t)H.h_leaf_count[x] * H.h_leaf_count[y]);
             }
     } else {
+        std::vector<double> Dt;
         for (int64_t x = 0; x < LL.nbox; ++x)
             for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+                const int32_t y = H.h_near_src[q];
                 F.w1<int64_t>(x);
-                F.w1<int64_t>(H.h_near_src[q]);
-                if (fac) F.w(D.data() + H.h_near_off[q], (size_t)LL.h_count[x] * LL.h_count[H.h_near_src[q]]);
+                F.w1<int64_t>(y);
+                if (!fac) continue;
+                const int64_t mx = LL.h_count[x], my = LL.h_count[y];
+                if (H.symmetric && y < x) {   // the owner's block (rows of y), transposed
+                    Dt.resize((size_t)(mx * my));
+                    for (int64_t j = 0; j < my; ++j)
+                        for (int64_t i = 0; i < mx; ++i) Dt[j * mx + i] = D[H.h_near_off[q] + i * my + j];
+                    F.w(Dt.data(), Dt.size());
+                } else {
+                    F.w(D.data() + H.h_near_off[q], (size_t)(mx * my));
+                }
             }
     }
     F.w1<int64_t>(H.n_il);
@@ -203,7 +223,23 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
         F.w1<int64_t>(k);
         if (!fac) continue;
         if (H.h_il_kind[b] == kDense) {
-            F.w(D.data() + H.h_il_off[b], (size_t)(m * n));
+            if (H.symmetric && H.h_il_tgt[b] > H.h_il_src[b]) {
+                Uc.resize((size_t)(m * n));   // the owner's block (n x m), transposed
+                for (int64_t j = 0; j < n; ++j)
+                    for (int64_t i = 0; i < m; ++i) Uc[j * m + i] = D[H.h_il_off[b] + i * n + j];
+                F.w(Uc.data(), Uc.size());
+            } else {
+                F.w(D.data() + H.h_il_off[b], (size_t)(m * n));
+            }
+        } else if (H.symmetric) {
+            // both factors in the U pool, each laid out by its own box
+            const Level& Ls = H.lev[il_src_level(H, b)];
+            Uc.resize((size_t)(m * k));
+            retile_u(H, H.h_il_level[b], L.h_begin[H.h_il_tgt[b]], m, k, U.data() + H.h_il_off[b], Uc.data(), false);
+            F.w(Uc.data(), Uc.size());
+            Vc.resize((size_t)(n * k));
+            retile_u(H, H.h_il_level[b], Ls.h_begin[H.h_il_src[b]], n, k, U.data() + H.h_il_voff[b], Vc.data(), false);
+            F.w(Vc.data(), Vc.size());
         } else {
             Uc.resize((size_t)(m * k));
             if (H.adaptive) std::memcpy(Uc.data(), U.data() + H.h_il_off[b], sizeof(double) * Uc.size());
@@ -217,7 +253,7 @@ static void export_handle(Handle& H, const char* path, uint32_t flags)
     }
 }
 
-static void import_handle(Handle& H, const char* path, hipStream_t s)
+static void import_handle(Handle& H, const char* path, hipStream_t s, uint32_t prec_mask)
 {
     File F(path, "rb");
     char magic[4];
@@ -441,6 +477,11 @@ static void import_handle(Handle& H, const char* path, hipStream_t s)
             run = L.h_il_ptr[L.nbox];
         }
     }
+    if (H.symmetric) {
+        if (H.adaptive) fail(H2D_EUNSUPPORTED, "symmetric sharing needs a balanced tree");
+        check_symmetric(H.kern.kind, false, prec_mask);
+        symmetrize_import(H, U, V, D);
+    }
     // device copies (the file is checked in full before the first HIP call)
     HIPCK(hipGetDevice(&H.device));
     up(H.xy, xy, s);
@@ -484,12 +525,15 @@ h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int3
         if (n < 1 || n >= ((int64_t)1 << 31)) fail(H2D_EINVAL, "n must be in [1, 2^31)");
         if (leaf_max < 1) fail(H2D_EINVAL, "leaf_max must be >= 1");
         if (!(tol >= 0.0) || !std::isfinite(tol)) fail(H2D_EINVAL, "tol must be finite and >= 0");
-        if (prec_mask & ~(7u | H2D_BUILD_ADAPTIVE)) fail(H2D_EINVAL, "unknown precision or build bits");
+        if (prec_mask & ~(7u | H2D_BUILD_ADAPTIVE | H2D_BUILD_SYMMETRIC))
+            fail(H2D_EINVAL, "unknown precision or build bits");
         const bool adaptive = (prec_mask & H2D_BUILD_ADAPTIVE) != 0;
+        const bool symmetric = (prec_mask & H2D_BUILD_SYMMETRIC) != 0;
         prec_mask &= 7u;
         if (adaptive && (prec_mask & ~1u))
             fail(H2D_EUNSUPPORTED, "half-precision pools are not built for adaptive trees");
         check_kernel(kernel);
+        if (symmetric) check_symmetric(kernel->kind, adaptive, prec_mask);
         hipStream_t s = (hipStream_t)stream;
         auto t0 = std::chrono::steady_clock::now();
         auto up_ = std::make_unique<h2d_s>();
@@ -497,12 +541,14 @@ h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int3
         HIPCK(hipGetDevice(&H.device));
         H.n = n; H.leaf_max = leaf_max; H.tol = tol;
         H.adaptive = adaptive;
+        H.symmetric = symmetric;
         H.kern = KernelParams{kernel->kind, kernel->diag_mode, kernel->c, kernel->diag_value};
         H.xy.alloc((size_t)(2 * n));
         HIPCK(hipMemcpyAsync(H.xy.p, xy, sizeof(double) * 2 * n, hipMemcpyDefault, s));
         build_tree_and_lists(H, s);
         build_factors(H, s);
         if (adaptive) finalize_adaptive(H, s);
+        else if (symmetric) finalize_symmetric(H, s);
         else finalize(H, s);
         make_half_pools(H, prec_mask, s);
         HIPCK(hipStreamSynchronize(s));
@@ -528,6 +574,7 @@ h2d_status h2d_matvec_noalloc(h2d_t H, const double* x, double* y, int32_t prec,
         if (!H || !x || !y) fail(H2D_EINVAL, "NULL argument");
         if (prec < H2D_P_FP64 || prec > H2D_P_BF16) fail(H2D_EINVAL, "unknown precision");
         if (!(H->h.prec_mask & H2D_PREC_BIT(prec))) fail(H2D_EUNSUPPORTED, "precision was not built for this handle");
+        if (H->h.symmetric) fail(H2D_EUNSUPPORTED, "symmetric handles have no fixed-array product");
         launch_matvec_noalloc(H->h, x, y, prec, (hipStream_t)stream);
     });
 }
@@ -541,6 +588,8 @@ h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d
         if (!(rtol > 0.0)) fail(H2D_EINVAL, "rtol must be > 0");
         if (H->h.adaptive && (opts->mode != H2D_SOLVE_PLAIN || opts->precond != H2D_PC_NONE))
             fail(H2D_EUNSUPPORTED, "adaptive trees solve with plain FP64 GMRES only");
+        if (H->h.symmetric && (opts->mode != H2D_SOLVE_PLAIN || opts->precond != H2D_PC_NONE))
+            fail(H2D_EUNSUPPORTED, "symmetric handles solve with plain FP64 GMRES only");
         if (opts->restart < 1 || opts->max_iter < 1) fail(H2D_EINVAL, "restart and max_iter must be >= 1");
         {   // x is zeroed before b is read: the two must not overlap
             const uintptr_t b0 = (uintptr_t)b, x0 = (uintptr_t)x, len = sizeof(double) * (uintptr_t)H->h.n;
@@ -579,15 +628,20 @@ h2d_status h2d_import(const char* path, uint32_t prec_mask, void* stream, h2d_t*
     return guarded([&] {
         if (!path || !out) fail(H2D_EINVAL, "NULL argument");
         *out = nullptr;
-        if (prec_mask & ~7u) fail(H2D_EINVAL, "unknown precision bits");
+        if (prec_mask & ~(7u | H2D_BUILD_SYMMETRIC)) fail(H2D_EINVAL, "unknown precision bits");
+        const bool symmetric = (prec_mask & H2D_BUILD_SYMMETRIC) != 0;
+        prec_mask &= 7u;
         hipStream_t s = (hipStream_t)stream;
         auto t0 = std::chrono::steady_clock::now();
         auto up_ = std::make_unique<h2d_s>();
         Handle& H = up_->h;
-        import_handle(H, path, s);
+        H.symmetric = symmetric;
+        import_handle(H, path, s, prec_mask);
         if (H.adaptive) {
             if (prec_mask & ~1u) fail(H2D_EUNSUPPORTED, "half-precision pools are not built for adaptive trees");
             finalize_adaptive(H, s);
+        } else if (symmetric) {
+            finalize_symmetric(H, s);
         } else {
             finalize(H, s);
         }
@@ -619,6 +673,7 @@ h2d_status h2d_bj_setup(h2d_t H, void* stream)
     return guarded([&] {
         if (!H) fail(H2D_EINVAL, "NULL handle");
         if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "block-Jacobi is not built for adaptive trees");
+        if (H->h.symmetric) fail(H2D_EUNSUPPORTED, "block-Jacobi is not built for symmetric handles");
         bj_setup(H->h, (hipStream_t)stream);
     });
 }
@@ -636,6 +691,7 @@ h2d_status h2d_mlp_train(h2d_t H, const h2d_mlp_train_opts* opts, h2d_mlp_train_
     return guarded([&] {
         if (!H || !opts) fail(H2D_EINVAL, "NULL argument");
         if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "the learned preconditioner is not built for adaptive trees");
+        if (H->h.symmetric) fail(H2D_EUNSUPPORTED, "the learned preconditioner is not built for symmetric handles");
         if (opts->n_solves < 1 || opts->steps < 0 || opts->batch < 1 || !(opts->lr > 0.f) ||
             (opts->target == H2D_MLP_TARGET_GLOBAL && !(opts->solve_tol > 0.0)) ||
             (opts->target != H2D_MLP_TARGET_LEAF && opts->target != H2D_MLP_TARGET_GLOBAL &&
@@ -669,6 +725,7 @@ h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, fl
     return guarded([&] {
         if (!H || nrhs < 1) fail(H2D_EINVAL, "bad argument");
         if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "tile tuning is not built for adaptive trees");
+        if (H->h.symmetric) fail(H2D_EUNSUPPORTED, "tile tuning is not built for symmetric handles");
         autotune(H->h, nrhs, (hipStream_t)stream, chosen, ms);
     });
 }
@@ -678,6 +735,7 @@ h2d_status h2d_set_item_rows(h2d_t H, int32_t which, int32_t rows, void* stream)
     return guarded([&] {
         if (!H) fail(H2D_EINVAL, "NULL handle");
         if (H->h.adaptive) fail(H2D_EUNSUPPORTED, "tile sizes are fixed for adaptive trees");
+        if (H->h.symmetric) fail(H2D_EUNSUPPORTED, "tile sizes are fixed for symmetric handles");
         if (which == H2D_TILE_A_ROWS) {
             if (rows < 16 || rows > kPhaseARows) fail(H2D_EINVAL, "phase-A item rows must lie in 16..512");
         } else if (which == H2D_TILE_MR_ROWS) {
@@ -706,6 +764,7 @@ h2d_status h2d_batch_create(h2d_t const* handles, int32_t count, int32_t nrhs, d
         for (int i = 0; i < count; ++i) {
             if (!handles[i] || !x[i] || !y[i] || ld[i] < handles[i]->h.n) fail(H2D_EINVAL, "bad batch member");
             if (handles[i]->h.adaptive) fail(H2D_EUNSUPPORTED, "adaptive trees are not batched");
+            if (handles[i]->h.symmetric) fail(H2D_EUNSUPPORTED, "symmetric handles are not batched");
             hs[i] = &handles[i]->h;
         }
         auto* r = new h2d_batch_s{batch_create(hs.data(), count, nrhs, x, y, ld)};

@@ -1022,11 +1022,13 @@ k_aca(const AcaJob* jobs, const double* xyt, KernelParams kp, double tol, double
 // target, in tree order, the |P| x k column-major tile U(rows of P, :).
 // Element (i, q) sits at k (begin_P - row0) + q |P| + (i - (begin_P - row0)).
 // tbeg / tcnt give begin_P and |P| for every tree row (null: untiled).
+// V is stored row-major (n x k), except on symmetric handles (vcm), where it
+// is laid out as U is, by the source box's rows starting at col0.
 struct PackJob {
     int64_t su, sv;     // scratch offsets
     int64_t du, dv;     // destination offsets
     int32_t m, n, k, tiled;
-    int32_t row0, pad;
+    int32_t row0, col0, vcm, pad;
 };
 
 __global__ void k_pack(const PackJob* jobs, const double* Uw, const double* Vw, double* Uo, double* Vo,
@@ -1043,8 +1045,18 @@ __global__ void k_pack(const PackJob* jobs, const double* Uw, const double* Vw, 
         Uo[J.du + dst] = Uw[J.su + e];
     }
     for (int64_t e = threadIdx.x; e < (int64_t)J.n * J.k; e += blockDim.x) {
-        int64_t j = e / J.k, q = e % J.k;
-        Vo[J.dv + e] = Vw[J.sv + q * J.n + j];
+        if (J.vcm) {
+            int64_t dst = e;
+            if (J.tiled) {
+                const int64_t q = e / J.n, j = e % J.n, gj = J.col0 + j;
+                const int64_t pb = tbeg[gj] - J.col0, pc = tcnt[gj];
+                dst = (int64_t)J.k * pb + q * pc + (j - pb);
+            }
+            Vo[J.dv + dst] = Vw[J.sv + e];
+        } else {
+            int64_t j = e / J.k, q = e % J.k;
+            Vo[J.dv + e] = Vw[J.sv + q * J.n + j];
+        }
     }
 }
 
@@ -1069,8 +1081,17 @@ void build_factors(Handle& H, hipStream_t s)
 {
     const int kappa = H.kappa;
     const int64_t nil = H.n_il;
+    const bool sym = H.symmetric;
+    if (sym) symmetric_partners(H);
     H.h_il_kind.assign(nil, kLowRank);
     H.h_il_k.assign(nil, 0);
+    // blocks compressed here: all, or on a symmetric handle the owners
+    // (target index below source index); mirrors take their owner's factors
+    std::vector<int64_t> todo;
+    todo.reserve(nil);
+    for (int64_t b = 0; b < nil; ++b)
+        if (!sym || H.h_il_tgt[b] < H.h_il_src[b]) todo.push_back(b);
+    const int64_t ntodo = (int64_t)todo.size();
     std::vector<int32_t> m(nil), n(nil), r0(nil), c0(nil);
     for (int64_t b = 0; b < nil; ++b) {
         const Level& L = H.lev[H.h_il_level[b]];
@@ -1099,18 +1120,19 @@ void build_factors(Handle& H, hipStream_t s)
     struct Chunk { int64_t b0, b1; DBuf<double> U, V; int64_t ue = 0, ve = 0; };
     std::vector<Chunk> chunks;
     int64_t b = 0;
-    while (b < nil) {
+    while (b < ntodo) {
         std::vector<AcaJob> jobs;
         int64_t uo = 0, vo = 0, fo = 0;
         double bytes = 0;
         int64_t b1 = b;
-        while (b1 < nil) {
-            int64_t mm = m[b1], nn = n[b1];
+        while (b1 < ntodo) {
+            const int64_t bb = todo[b1];
+            int64_t mm = m[bb], nn = n[bb];
             int64_t kc = (mm * nn + mm + nn - 1) / (mm + nn);
             kc = std::min<int64_t>(kc, kAcaRankCap);
             double need = 8.0 * (double)(mm + nn) * (double)kc + (double)(mm + nn);
             if (b1 > b && (bytes + need > budget || jobs.size() >= 200000)) break;
-            AcaJob J{r0[b1], m[b1], c0[b1], n[b1], (int32_t)kc, 0, uo, vo, fo};
+            AcaJob J{r0[bb], m[bb], c0[bb], n[bb], (int32_t)kc, 0, uo, vo, fo};
             jobs.push_back(J);
             uo += mm * kc; vo += nn * kc; fo += mm + nn;
             bytes += need;
@@ -1133,7 +1155,7 @@ void build_factors(Handle& H, hipStream_t s)
         C.b0 = b; C.b1 = b1;
         std::vector<PackJob> packs;
         for (size_t q = 0; q < jobs.size(); ++q) {
-            int64_t bb = b + (int64_t)q;
+            const int64_t bb = todo[b + (int64_t)q];
             if (hk[q] < 0)
                 fail(H2D_ENOCONV, "ACA reached its rank cap of " + std::to_string(kAcaRankCap) + " on a " +
                                       std::to_string(m[bb]) + " x " + std::to_string(n[bb]) + " block");
@@ -1143,9 +1165,16 @@ void build_factors(Handle& H, hipStream_t s)
                 // U tiled by the boxes one level above the leaves (balanced
                 // trees); plain column-major on an adaptive tree
                 const int32_t tiled = (!H.adaptive && H.h_il_level[bb] <= kappa - 1) ? 1 : 0;
-                packs.push_back(PackJob{jobs[q].uoff, jobs[q].voff, C.ue, C.ve, m[bb], n[bb], hr[q], tiled, r0[bb], 0});
-                C.ue += (int64_t)m[bb] * hr[q];
-                C.ve += (int64_t)n[bb] * hr[q];
+                if (sym) {   // both factors in the U pool: F_X, then F_Y
+                    packs.push_back(PackJob{jobs[q].uoff, jobs[q].voff, C.ue, C.ue + (int64_t)m[bb] * hr[q], m[bb], n[bb],
+                                            hr[q], tiled, r0[bb], c0[bb], 1, 0});
+                    C.ue += (int64_t)(m[bb] + n[bb]) * hr[q];
+                } else {
+                    packs.push_back(PackJob{jobs[q].uoff, jobs[q].voff, C.ue, C.ve, m[bb], n[bb], hr[q], tiled, r0[bb], 0,
+                                            0, 0});
+                    C.ue += (int64_t)m[bb] * hr[q];
+                    C.ve += (int64_t)n[bb] * hr[q];
+                }
             }
         }
         C.U.alloc(std::max<int64_t>(C.ue, 1));
@@ -1153,7 +1182,8 @@ void build_factors(Handle& H, hipStream_t s)
         if (!packs.empty()) {
             DBuf<PackJob> dp;
             upload(dp, packs, s);
-            k_pack<<<(unsigned)packs.size(), 256, 0, s>>>(dp.p, Uw.p, Vw.p, C.U.p, C.V.p, tbeg.p, tcnt.p);
+            k_pack<<<(unsigned)packs.size(), 256, 0, s>>>(dp.p, Uw.p, Vw.p, C.U.p, sym ? C.U.p : C.V.p, tbeg.p,
+                                                           tcnt.p);
             HIPCK(hipGetLastError());
             HIPCK(hipStreamSynchronize(s));
         }
@@ -1169,7 +1199,29 @@ void build_factors(Handle& H, hipStream_t s)
     int64_t nnear = (int64_t)H.h_near_src.size();
     H.h_near_off.assign(nnear, 0);
     std::vector<DenseJob> dj;
-    if (H.adaptive) {   // near CSR over leaf numbers
+    if (sym) {
+        // mirrors take the owner's kind and rank
+        for (int64_t q = 0; q < nil; ++q)
+            if (H.h_il_tgt[q] > H.h_il_src[q]) {
+                H.h_il_kind[q] = H.h_il_kind[H.h_il_partner[q]];
+                H.h_il_k[q] = H.h_il_k[H.h_il_partner[q]];
+            }
+    }
+    if (sym) {   // self and owner near blocks stored; a mirror shares its owner's (transposed)
+        for (int64_t x = 0; x < LL.nbox; ++x)
+            for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
+                const int32_t y = H.h_near_src[q];
+                if (y < x) {
+                    int32_t o = H.h_near_ptr[y];
+                    while (H.h_near_src[o] != x) ++o;
+                    H.h_near_off[q] = H.h_near_off[o];
+                    continue;
+                }
+                H.h_near_off[q] = de;
+                dj.push_back(DenseJob{de, LL.h_begin[x], LL.h_count[x], LL.h_begin[y], LL.h_count[y]});
+                de += (int64_t)LL.h_count[x] * LL.h_count[y];
+            }
+    } else if (H.adaptive) {   // near CSR over leaf numbers
         const int64_t nleaf = (int64_t)H.h_leaf_begin.size();
         for (int64_t x = 0; x < nleaf; ++x)
             for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
@@ -1188,10 +1240,26 @@ void build_factors(Handle& H, hipStream_t s)
             }
     }
     for (int64_t q = 0; q < nil; ++q) {
+        const bool mirror = sym && H.h_il_tgt[q] > H.h_il_src[q];
+        if (mirror) {
+            const int64_t o = H.h_il_partner[q];   // earlier in table order
+            if (H.h_il_kind[q] == kDense) {
+                H.h_il_off[q] = H.h_il_off[o];
+            } else {
+                H.h_il_off[q] = H.h_il_voff[o];
+                H.h_il_voff[q] = H.h_il_off[o];
+            }
+            continue;
+        }
         if (H.h_il_kind[q] == kDense) {
             H.h_il_off[q] = de;
             dj.push_back(DenseJob{de, r0[q], m[q], c0[q], n[q]});
             de += (int64_t)m[q] * n[q];
+        } else if (sym) {
+            H.h_il_off[q] = ue;
+            ue += (int64_t)m[q] * H.h_il_k[q];
+            H.h_il_voff[q] = ue;
+            ue += (int64_t)n[q] * H.h_il_k[q];
         } else {
             H.h_il_off[q] = ue;
             H.h_il_voff[q] = ve;

@@ -157,6 +157,35 @@ struct MRIo {
     int64_t ld;
 };
 
+// Symmetric handles (one factor pair per interaction-list pair): one
+// descriptor per interaction-list block, read by the slice walks above the
+// leaf level.
+//   cols > 0: low rank; the block's target-side factor at U pool + off,
+//             column-major and tiled by the boxes one level above the
+//             leaves; tsrc: this block's t; part: partial pool offset of
+//             the partner block's t (slice s of the target box at
+//             part + s cols)
+//   cols < 0: dense, D pool + off, multiplier xs + tsrc; part = 0: the
+//             block itself, column-major (ld = target box size); part = 1:
+//             a mirror, its owner's block read transposed (row-major, ld =
+//             source box size)
+//   cols = 0: rank 0, nothing to do
+struct SDesc {
+    int64_t off;
+    int32_t cols, tsrc;
+    int64_t part;
+};
+// A leaf-level pair {X, Y}, X < Y, applied in both directions from one read
+// by the wave of leaf Y.  k > 0: low rank, F_X (|X| x k) at U pool + a and
+// F_Y (|Y| x k) at U pool + b, column-major; k < 0: dense, D (|X| x |Y|,
+// column-major) at D pool + a.  X's rows of the product go to the slot
+// pool at slot.
+struct LPair {
+    int64_t a, b;
+    int32_t x, k;
+    int64_t slot;
+};
+
 struct KernelParams {
     int32_t kind;
     int32_t diag_mode;
@@ -265,6 +294,24 @@ struct Handle {
     DBuf<double> gm_V, gm_Z, gm_w, gm_r, gm_y, gm_part, gm_dres, rf_r, rf_d, rf_w;
     std::shared_ptr<MlpState> mlp;
 
+    // symmetric sharing (one factor pair per interaction-list pair): both
+    // factors of a pair in the U pool (h_il_off: the block's target side,
+    // h_il_voff: its source side); a mirror block (target index > source
+    // index) points at its owner's factors with the roles swapped, and a
+    // mirror leaf-level dense or near block at its owner's D
+    bool symmetric = false;
+    std::vector<int64_t> h_il_partner;          // block (level, src, tgt) of block (level, tgt, src)
+    DBuf<SDesc> sdesc;
+    DBuf<int32_t> s_mid[kMaxLevel + 1];         // per box: first block of its list with src > tgt
+    DBuf<int32_t> s_first[kMaxLevel + 1];       // per box (+1): its first slice item
+    DBuf<int2> s_items;                         // (box one level above the leaves, first row of a 64-row slice)
+    DBuf<RDesc> s_red1, s_red2;                 // partial sums of the mirrors' t (first walk), owners' t (second)
+    DBuf<int32_t> s_lp_ptr, s_nslot;            // per leaf: its pairs {X < leaf}; its slot count
+    DBuf<LPair> s_lp;
+    DBuf<int64_t> s_self, s_slot_base;          // per leaf: self block offset; first slot
+    DBuf<double> s_y, s_slots;                  // work: walk sums (2 n), leaf sums (2 n); slot pool
+    int64_t n_s_items = 0, n_s_red1 = 0, n_s_red2 = 0, s_slot_elems = 0;
+
     double alg_bytes_fp64 = 0, alg_bytes_half = 0, flops = 0;
     double phase_bytes[2][5] = {{0}};   // [FP64, half][gather, A, reduce, B, combine]
 
@@ -311,6 +358,17 @@ void adaptive_tree_and_lists(Handle& H, const DBuf<uint32_t>& skey, const DBuf<i
 // tables (build and import).
 void adaptive_index(Handle& H, hipStream_t s);
 void finalize_adaptive(Handle& H, hipStream_t s);
+// symmetric.hip
+constexpr int kSymLeafMax = 64;   // leaf points a symmetric handle allows (one wave per leaf)
+void symmetric_partners(Handle& H);
+void finalize_symmetric(Handle& H, hipStream_t s);
+void launch_matvec_symmetric(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s);
+// Host factor arrays of an imported ordered file (U tiled, V row-major, D)
+// -> the symmetric layout; EINVAL unless every mirror is the exact
+// transpose of its owner.
+void symmetrize_import(Handle& H, std::vector<double>& U, std::vector<double>& V, std::vector<double>& D);
+// Row -> (first row, size) of its box one level above the leaves.
+void tile_map(const Handle& H, std::vector<int32_t>& tbeg, std::vector<int32_t>& tcnt);
 inline int32_t il_src_level(const Handle& H, int64_t b) { return H.h_il_slevel.empty() ? H.h_il_level[b] : H.h_il_slevel[b]; }
 void build_factors(Handle& H, hipStream_t s);
 void make_half_pools(Handle& H, uint32_t mask, hipStream_t s);

@@ -1164,6 +1164,10 @@ void profile_read(Handle& H, h2d_profile* out)
 
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s)
 {
+    if (H.symmetric) {   // one factor pair per pair: its own three-walk product (FP64)
+        launch_matvec_symmetric(H, x, y, nrhs, ld, s);
+        return;
+    }
     if (nrhs > 1 && prec == H2D_P_FP64 && !H.adaptive) {   // blocks of 16 right-hand sides on the matrix cores
         launch_matvec_mr(H, x, y, nrhs, ld, s);
         return;

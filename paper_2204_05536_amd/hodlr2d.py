@@ -24,6 +24,7 @@ DIAG = {"replace": 0, "add": 1, "formula": 2}
 PREC = {"fp64": 0, "fp16": 1, "bf16": 2}
 SOLVE_PLAIN, SOLVE_REFINE = 0, 1
 BUILD_ADAPTIVE = 1 << 8
+BUILD_SYMMETRIC = 1 << 9
 PRECOND = {"none": 0, "bj": 1, "mlp": 2}
 
 EXPORTED = ["h2d_build", "h2d_matvec", "h2d_matvec_noalloc", "h2d_solve", "h2d_info", "h2d_export", "h2d_import",
@@ -178,21 +179,22 @@ class HODLR2D:
         self._h = handle
 
     @classmethod
-    def build(cls, xy, kernel, leaf_max=64, tol=1e-10, precs=(), adaptive=False):
+    def build(cls, xy, kernel, leaf_max=64, tol=1e-10, precs=(), adaptive=False, symmetric=False):
         L = load()
         xy = xy.contiguous()
         h = C.c_void_p()
         k = kernel_spec(kernel)
-        flags = prec_mask(*precs) | (BUILD_ADAPTIVE if adaptive else 0)
+        flags = prec_mask(*precs) | (BUILD_ADAPTIVE if adaptive else 0) | (BUILD_SYMMETRIC if symmetric else 0)
         _check(L.h2d_build(_dev_f64(xy, "xy"), xy.shape[0], C.byref(k), int(leaf_max), float(tol),
                            flags, _stream(), C.byref(h)))
         return cls(h)
 
     @classmethod
-    def import_file(cls, path, precs=()):
+    def import_file(cls, path, precs=(), symmetric=False):
         L = load()
         h = C.c_void_p()
-        _check(L.h2d_import(str(path).encode(), prec_mask(*precs), _stream(), C.byref(h)))
+        flags = prec_mask(*precs) | (BUILD_SYMMETRIC if symmetric else 0)
+        _check(L.h2d_import(str(path).encode(), flags, _stream(), C.byref(h)))
         return cls(h)
 
     def close(self):
