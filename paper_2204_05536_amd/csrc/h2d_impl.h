@@ -178,12 +178,11 @@ struct SDesc {
 // A leaf-level pair {X, Y}, X < Y, applied in both directions from one read
 // by the wave of leaf Y.  k > 0: low rank, F_X (|X| x k) at U pool + a and
 // F_Y (|Y| x k) at U pool + b, column-major; k < 0: dense, D (|X| x |Y|,
-// column-major) at D pool + a.  X's rows of the product go to the slot
-// pool at slot.
+// column-major) at D pool + a.  X's rows (first tree row x0, mx of them)
+// of the product go to the slot pool at slot.
 struct LPair {
-    int64_t a, b;
-    int32_t x, k;
-    int64_t slot;
+    int64_t a, b, slot;
+    int32_t x0, mx, k, pad;
 };
 
 struct KernelParams {
@@ -305,12 +304,12 @@ struct Handle {
     DBuf<int32_t> s_mid[kMaxLevel + 1];         // per box: first block of its list with src > tgt
     DBuf<int32_t> s_first[kMaxLevel + 1];       // per box (+1): its first slice item
     DBuf<int2> s_items;                         // (box one level above the leaves, first row of a 64-row slice)
-    DBuf<RDesc> s_red1, s_red2;                 // partial sums of the mirrors' t (first walk), owners' t (second)
+    DBuf<RDesc> s_red[4];                       // partial sums: mirrors' t (first walk; runs, then run sums), owners' t (second walk; same)
     DBuf<int32_t> s_lp_ptr, s_nslot;            // per leaf: its pairs {X < leaf}; its slot count
     DBuf<LPair> s_lp;
     DBuf<int64_t> s_self, s_slot_base;          // per leaf: self block offset; first slot
     DBuf<double> s_y, s_slots;                  // work: walk sums (2 n), leaf sums (2 n); slot pool
-    int64_t n_s_items = 0, n_s_red1 = 0, n_s_red2 = 0, s_slot_elems = 0;
+    int64_t n_s_items = 0, n_s_red[4] = {0, 0, 0, 0}, s_slot_elems = 0;
 
     double alg_bytes_fp64 = 0, alg_bytes_half = 0, flops = 0;
     double phase_bytes[2][5] = {{0}};   // [FP64, half][gather, A, reduce, B, combine]

@@ -43,7 +43,8 @@ namespace h2d {
 namespace {
 
 constexpr int kSymS = 64;      // rows per walk slice (one per lane)
-constexpr int kSymChunk = 16;  // factor columns per cross-lane partial sum
+constexpr int kSymChunk = 8;   // factor columns per cross-lane partial sum
+constexpr int kSymSeg = 32;    // slice partials one reduction wave sums at most
 
 struct SymLevels {
     const int32_t* begin[kMaxLevel + 1];
@@ -74,9 +75,10 @@ __device__ __forceinline__ void wave_sync()
 // the owner blocks (kOwner) or the mirror blocks of that box's list,
 // applies the block's target-side factor to its t (kApply) and/or sums the
 // slice's part of F^T xs for the partner block (kReduce).  The partial sums
-// go through LDS 16 columns at a time: lane (c, h) adds the 16 products of
-// lanes 16 h .. 16 h + 15 for column c, then two butterfly steps finish the
-// 64-row sum.
+// go through LDS 8 columns at a time (4 KB per wave, so LDS does not cap
+// the waves per CU below what the registers allow): lane (c, h) adds the 8
+// products of lanes 8 h .. 8 h + 7 for column c, then three butterfly steps
+// finish the 64-row sum.
 template <bool kApply, bool kReduce, bool kOwner>
 __device__ __forceinline__ void sym_walk(int32_t it, int lane, double* red, const int2* __restrict__ items, int tl,
                                          const SymLevels& L, const SDesc* __restrict__ sd,
@@ -118,25 +120,34 @@ __device__ __forceinline__ void sym_walk(int32_t it, int lane, double* red, cons
                     double* pout = ppool + su(d.part) + (int64_t)sl * cols;
                     for (int32_t c0 = 0; c0 < cols; c0 += kSymChunk) {
                         const int32_t nc = min(kSymChunk, cols - c0);
+                        // the chunk's t values: one vector load, then lane
+                        // reads (scalar-cache loads would share a wait
+                        // counter with the LDS traffic below)
+                        double tc = 0.0;
+                        if constexpr (kApply) tc = lane < nc ? tpool[tsrc + c0 + lane] : 0.0;
                         double pr[kSymChunk];
 #pragma unroll
                         for (int cc = 0; cc < kSymChunk; ++cc) {
                             double v = 0.0;
                             if (cc < nc && act) v = base[(int64_t)(c0 + cc) * cnt];
                             if constexpr (kApply) {
-                                if (cc < nc) acc += v * tv[c0 + cc];
+                                const uint64_t tb = __double_as_longlong(tc);
+                                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)tb, cc);
+                                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(tb >> 32), cc);
+                                acc += v * __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
                             }
                             pr[cc] = v * xr;
                         }
 #pragma unroll
                         for (int cc = 0; cc < kSymChunk; ++cc) red[cc * kWave + lane] = pr[cc];
                         wave_sync();
-                        const int cc = lane >> 2, h = lane & 3;
+                        constexpr int kPer = kWave / kSymChunk;   // lanes per column
+                        const int cc = lane / kPer, h = lane % kPer;
                         double sum = 0.0;
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) sum += red[cc * kWave + h * 16 + i];
-                        sum += __shfl_xor(sum, 1, kWave);
-                        sum += __shfl_xor(sum, 2, kWave);
+                        for (int i = 0; i < kSymChunk; ++i) sum += red[cc * kWave + h * kSymChunk + i];
+#pragma unroll
+                        for (int dd = 1; dd < kPer; dd <<= 1) sum += __shfl_xor(sum, dd, kWave);
                         if (h == 0 && cc < nc) pout[c0 + cc] = sum;
                         wave_sync();
                     }
@@ -182,53 +193,80 @@ __device__ __forceinline__ double group_sum(double v, int lane, int m, int G, do
 
 // One wave per leaf Y (at most 64 points): lane (g, r) owns row r of Y and
 // the columns g, g + G, ... (G = 64 / |Y|) of every block applied to Y's
-// rows; for X's rows the same layout with |X|.  Per pair {X, Y}:
-//   dense D (|X| x |Y|): X's rows D xs(Y) (coalesced read), then Y's rows
-//     D^T xs(X) (the same block again, now from the cache);
+// rows; for X's rows the same layout with |X|.  xs of Y, and of each
+// partner X in turn, sit in LDS.  Per pair {X, Y}:
+//   dense D (|X| x |Y|): X's rows D xs(Y) (coalesced read) and Y's rows
+//     D^T xs(X) (the same block again, from the cache);
 //   low rank: t1 = F_X^T xs(X), t2 = F_Y^T xs(Y) (lane (g, q) sums rows
 //     g, g + G', ... of column q, G' = 64 / k), then Y's rows F_Y t1 and
-//     X's rows F_X t2 (both again from the cache).
+//     X's rows F_X t2 (again from the cache).
+// X's rows are summed over their column groups in order into the pair's
+// slot; Y's rows accumulate over all pairs and are summed once at the end.
 __device__ __forceinline__ void sym_leaf(int32_t Y, int lane, double* lds, int kappa, const SymLevels& L,
                                          const int32_t* __restrict__ lp_ptr, const LPair* __restrict__ lp,
                                          const int64_t* __restrict__ self_off, const double* __restrict__ Fp,
                                          const double* __restrict__ Dp, const double* __restrict__ xs,
                                          double* __restrict__ yown, double* __restrict__ slots)
 {
-    double* red = lds;            // 64
-    double* red2 = lds + kWave;   // 64
-    double* tv = lds + 2 * kWave; // 128: t1, then t2 at +64
+    double* xY = lds;                 // 64
+    double* xX = lds + kWave;         // 64
+    double* red = lds + 2 * kWave;    // 64
+    double* red2 = lds + 3 * kWave;   // 64
+    double* tv = lds + 4 * kWave;     // 128: t1, then t2 at +64
     const int32_t r0 = su(L.begin[kappa][Y]), m = su(L.count[kappa][Y]);
     const int G = kWave / m, g = lane / m, r = lane % m;
     const bool act = g < G;
+    const int32_t e0 = su(lp_ptr[Y]), e1 = su(lp_ptr[Y + 1]);
+    LPair nx{};
+    if (e0 < e1) nx = lp[e0];
+    if (lane < m) xY[lane] = xs[r0 + lane];
+    wave_sync();
     double acc = 0.0;
     {
-        const double* D = Dp + su(self_off[Y]);
-        if (act)
-            for (int32_t j = g; j < m; j += G) acc += D[r + (int64_t)j * m] * xs[r0 + j];
+        const double* D = Dp + su(self_off[Y]) + r;
+        if (act) {
+#pragma unroll 4
+            for (int32_t j = g; j < m; j += G) acc += D[(int64_t)j * m] * xY[j];
+        }
     }
-    const int32_t e0 = su(lp_ptr[Y]), e1 = su(lp_ptr[Y + 1]);
     for (int32_t e = e0; e < e1; ++e) {
-        const LPair Pq = lp[e];
-        const int64_t pa = su(Pq.a), pb = su(Pq.b), slot = su(Pq.slot);
-        const int32_t X = su(Pq.x), k = su(Pq.k);
-        const int32_t x0 = su(L.begin[kappa][X]), mx = su(L.count[kappa][X]);
+        const int64_t pa = su(nx.a), pb = su(nx.b), slot = su(nx.slot);
+        const int32_t x0 = su(nx.x0), mx = su(nx.mx), k = su(nx.k);
+        if (e + 1 < e1) nx = lp[e + 1];   // the next descriptor, in flight during this pair
+        // X's x values, in flight while the parts that need only xs(Y) run
+        const double xv = lane < mx ? xs[x0 + lane] : 0.0;
         const int Gx = kWave / mx, gx = lane / mx, ix = lane % mx;
         const bool actx = gx < Gx;
         double sx = 0.0;
         if (k < 0) {
-            const double* D = Dp + pa;
-            if (actx)
-                for (int32_t j = gx; j < m; j += Gx) sx += D[ix + (int64_t)j * mx] * xs[r0 + j];
-            if (act)
-                for (int32_t i = g; i < mx; i += G) acc += D[i + (int64_t)r * mx] * xs[x0 + i];
+            const double* Dr = Dp + pa + ix;
+            if (actx) {
+#pragma unroll 4
+                for (int32_t j = gx; j < m; j += Gx) sx += Dr[(int64_t)j * mx] * xY[j];
+            }
+            if (lane < mx) xX[lane] = xv;
+            wave_sync();
+            const double* Dc = Dp + pa + (int64_t)r * mx;
+            if (act) {
+#pragma unroll 4
+                for (int32_t i = g; i < mx; i += G) acc += Dc[i] * xX[i];
+            }
         } else {
             const double* FX = Fp + pa;
             const double* FY = Fp + pb;
             const int Gq = kWave / k, gq = lane / k, qq = lane % k;
             double s1 = 0.0, s2 = 0.0;
             if (gq < Gq) {
-                for (int32_t i = gq; i < mx; i += Gq) s1 += FX[i + (int64_t)qq * mx] * xs[x0 + i];
-                for (int32_t j = gq; j < m; j += Gq) s2 += FY[j + (int64_t)qq * m] * xs[r0 + j];
+                const double* fy = FY + (int64_t)qq * m;
+#pragma unroll 4
+                for (int32_t j = gq; j < m; j += Gq) s2 += fy[j] * xY[j];
+            }
+            if (lane < mx) xX[lane] = xv;
+            wave_sync();
+            if (gq < Gq) {
+                const double* fx = FX + (int64_t)qq * mx;
+#pragma unroll 4
+                for (int32_t i = gq; i < mx; i += Gq) s1 += fx[i] * xX[i];
             }
             red[lane] = s1;
             red2[lane] = s2;
@@ -243,11 +281,14 @@ __device__ __forceinline__ void sym_leaf(int32_t Y, int lane, double* lds, int k
                 tv[kWave + lane] = a2;
             }
             wave_sync();
-            if (act)
+            if (act) {
+#pragma unroll 4
                 for (int32_t c = g; c < k; c += G) acc += FY[r + (int64_t)c * m] * tv[c];
-            if (actx)
+            }
+            if (actx) {
+#pragma unroll 4
                 for (int32_t c = gx; c < k; c += Gx) sx += FX[ix + (int64_t)c * mx] * tv[kWave + c];
-            wave_sync();
+            }
         }
         const double t = group_sum(actx ? sx : 0.0, lane, mx, Gx, red);
         if (lane < mx) slots[slot + lane] = t;
@@ -276,27 +317,30 @@ k_sym_walk1(int32_t nitems, const int2* __restrict__ items, int tl, SymLevels L,
                                 nullptr);
 }
 
-// Walk 2 (first nw workgroups) and the leaf pairs (the rest).
+// Walk 2: the mirrors' F_Y t into y2 and the owners' t partials.
 __global__ void __launch_bounds__(256)
-k_sym_walk2(int32_t nw, int32_t nitems, const int2* __restrict__ items, int tl, SymLevels L,
-            const SDesc* __restrict__ sd, const double* __restrict__ Fp, const double* __restrict__ Dp,
-            const double* __restrict__ tpool, const double* __restrict__ xs, double* __restrict__ ppool,
-            double* __restrict__ y2, int32_t nleaf, int kappa, const int32_t* __restrict__ lp_ptr,
-            const LPair* __restrict__ lp, const int64_t* __restrict__ self_off, double* __restrict__ yown,
-            double* __restrict__ slots)
+k_sym_walk2(int32_t nitems, const int2* __restrict__ items, int tl, SymLevels L, const SDesc* __restrict__ sd,
+            const double* __restrict__ Fp, const double* __restrict__ Dp, const double* __restrict__ tpool,
+            const double* __restrict__ xs, double* __restrict__ ppool, double* __restrict__ y2)
 {
     __shared__ double lds[4][kSymChunk * kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t w = blockIdx.x;
-    if (w < nw) {
-        const int32_t it = w * 4 + wave;
-        if (it < nitems)
-            sym_walk<true, true, false>(it, lane, lds[wave], items, tl, L, sd, Fp, Dp, tpool, xs, ppool, y2,
-                                        nullptr);
-    } else {
-        const int32_t Y = (w - nw) * 4 + wave;
-        if (Y < nleaf) sym_leaf(Y, lane, lds[wave], kappa, L, lp_ptr, lp, self_off, Fp, Dp, xs, yown, slots);
-    }
+    const int32_t it = blockIdx.x * 4 + wave;
+    if (it >= nitems) return;
+    sym_walk<true, true, false>(it, lane, lds[wave], items, tl, L, sd, Fp, Dp, tpool, xs, ppool, y2, nullptr);
+}
+
+// The leaf-level pairs, one wave per leaf.
+__global__ void __launch_bounds__(256)
+k_sym_leaf(int32_t nleaf, int kappa, SymLevels L, const int32_t* __restrict__ lp_ptr, const LPair* __restrict__ lp,
+           const int64_t* __restrict__ self_off, const double* __restrict__ Fp, const double* __restrict__ Dp,
+           const double* __restrict__ xs, double* __restrict__ yown, double* __restrict__ slots)
+{
+    __shared__ double lds[4][6 * kWave];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t Y = blockIdx.x * 4 + wave;
+    if (Y >= nleaf) return;
+    sym_leaf(Y, lane, lds[wave], kappa, L, lp_ptr, lp, self_off, Fp, Dp, xs, yown, slots);
 }
 
 // Walk 3 (first nw workgroups) and the slot sums per leaf (the rest).
@@ -328,21 +372,44 @@ k_sym_walk3(int32_t nw, int32_t nitems, const int2* __restrict__ items, int tl, 
     }
 }
 
-// t = sum of a block's slice partials, in slice order (one workgroup per
-// block; lanes take slices p = lane, lane + 64, ..., waves take columns).
+// Sums of consecutive k-value partials (slice-major, in the t pool):
+// out = sum of the nparts rows at pbeg, one wave per descriptor.  Lane
+// (g, q), G = 64 / k (k <= 64), sums column q over the rows g, g + G, ...
+// and the G sums are added in order; for k > 64 lane q, q + 64, ... sums
+// its columns over all rows.  Blocks with many slices are summed in two
+// launches (runs of at most kSymSeg slices, then the runs), so no wave
+// sums a long chain.
 __global__ void __launch_bounds__(256)
-k_sym_reduce(int64_t nr, const RDesc* __restrict__ R, const double* __restrict__ ppool, double* __restrict__ tpool)
+k_sym_reduce(int64_t nr, const RDesc* __restrict__ R, double* __restrict__ tpool)
 {
-    const int64_t b = blockIdx.x;
+    __shared__ double red[4][kWave];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t b = (int64_t)blockIdx.x * 4 + wave;
     if (b >= nr) return;
     const RDesc D = R[b];
     const int32_t tout = su(D.tout), k = su(D.k), pbeg = su(D.pbeg), np = su(D.nparts);
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    for (int q = wave; q < k; q += 4) {
-        double s = 0.0;
-        for (int p = lane; p < np; p += kWave) s += ppool[pbeg + (int64_t)p * k + q];
-        for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
-        if (lane == 0) tpool[tout + q] = s;
+    if (k > kWave) {
+        for (int q = lane; q < k; q += kWave) {
+            double s = 0.0;
+#pragma unroll 4
+            for (int32_t i = 0; i < np; ++i) s += tpool[pbeg + (int64_t)i * k + q];
+            tpool[tout + q] = s;
+        }
+        return;
+    }
+    const int G = kWave / k, g = lane / k, q = lane % k;
+    double s = 0.0;
+    if (g < G) {
+        const double* p = tpool + pbeg + q;
+#pragma unroll 4
+        for (int32_t i = g; i < np; i += G) s += p[(int64_t)i * k];
+    }
+    red[wave][lane] = s;
+    wave_sync();
+    if (lane < k) {
+        double a = 0.0;
+        for (int gg = 0; gg < G; ++gg) a += red[wave][gg * k + lane];
+        tpool[tout + lane] = a;
     }
 }
 
@@ -496,8 +563,19 @@ void finalize_symmetric(Handle& H, hipStream_t s)
     H.h_il_toff = toff;
     auto nslices = [&](int l, int32_t a) -> int32_t { return first[l][a + 1] - first[l][a]; };
     std::vector<SDesc> sd(nil);
-    std::vector<RDesc> r1, r2;
+    std::vector<RDesc> r1, r2, r1b, r2b;
     int64_t poff = 0, p1 = 0, p2 = 0;
+    // slice partials (past the t values), then the run sums of long partial
+    // chains (past the partials): sizes first
+    int64_t ptot = 0, nsegv = 0;
+    for (int64_t b = 0; b < nil; ++b) {
+        const int l = H.h_il_level[b];
+        if (H.h_il_kind[b] == kDense || H.h_il_k[b] == 0 || l == kappa) continue;
+        const int32_t ns = first[l][H.h_il_tgt[b] + 1] - first[l][H.h_il_tgt[b]];
+        if (ns > 1) ptot += (int64_t)ns * H.h_il_k[b];
+        if (ns > kSymSeg) nsegv += (int64_t)((ns + kSymSeg - 1) / kSymSeg) * H.h_il_k[b];
+    }
+    int64_t segoff = t_el + ptot;
     double anc_fx = 0, anc_fy = 0, anc_dense_own = 0, anc_dense_mir = 0, t_anc = 0;
     for (int64_t b = 0; b < nil; ++b) {
         const int l = H.h_il_level[b];
@@ -512,22 +590,43 @@ void finalize_symmetric(Handle& H, hipStream_t s)
         sd[b] = SDesc{H.h_il_off[b], k, std::max(toff[b], 0), 0};
         if (k == 0 || l == kappa) continue;
         const int32_t ns = nslices(l, tg);
-        sd[b].part = poff;
-        // partial sums of the partner's t, from this block's target-side factor
-        RDesc R{toff[H.h_il_partner[b]], k, (int32_t)poff, ns};
-        if (tg < sr) { r1.push_back(R); anc_fx += (double)m * k; p1 += (int64_t)ns * k; }
-        else { r2.push_back(R); anc_fy += (double)m * k; p2 += (int64_t)ns * k; }
+        (tg < sr ? anc_fx : anc_fy) += (double)m * k;
         t_anc += k;
+        if (ns == 1) {   // one slice: the walk writes the partner's t itself
+            sd[b].part = toff[H.h_il_partner[b]];
+            continue;
+        }
+        // partial sums of the partner's t, from this block's target-side
+        // factor, in the t pool past the t values
+        sd[b].part = t_el + poff;
+        const int32_t tp = toff[H.h_il_partner[b]];
+        std::vector<RDesc>& ra = (tg < sr) ? r1 : r2;
+        std::vector<RDesc>& rb = (tg < sr) ? r1b : r2b;
+        ((tg < sr) ? p1 : p2) += (int64_t)ns * k;
+        if (ns <= kSymSeg) {
+            ra.push_back(RDesc{tp, k, (int32_t)(t_el + poff), ns});
+        } else {   // runs of kSymSeg slices into run sums (past all partials), then the runs
+            const int32_t nseg = (ns + kSymSeg - 1) / kSymSeg;
+            for (int32_t g = 0; g < nseg; ++g)
+                ra.push_back(RDesc{(int32_t)(segoff + (int64_t)g * k), k,
+                                   (int32_t)(t_el + poff + (int64_t)g * kSymSeg * k),
+                                   std::min(kSymSeg, ns - g * kSymSeg)});
+            rb.push_back(RDesc{tp, k, (int32_t)segoff, nseg});
+            segoff += (int64_t)nseg * k;
+        }
         poff += (int64_t)ns * k;
     }
-    if (poff >= ((int64_t)1 << 31)) fail(H2D_EUNSUPPORTED, "partial pool exceeds 2^31 values");
-    H.t_elems = t_el;
-    H.p_elems = poff;
+    if (t_el + ptot + nsegv >= ((int64_t)1 << 31)) fail(H2D_EUNSUPPORTED, "t and partial pool exceeds 2^31 values");
+    H.t_elems = t_el + ptot + nsegv;   // t values, slice partials, run sums
+    H.p_elems = 0;
     up(H.sdesc, sd, s);
-    up(H.s_red1, r1, s);
-    up(H.s_red2, r2, s);
-    H.n_s_red1 = (int64_t)r1.size();
-    H.n_s_red2 = (int64_t)r2.size();
+    {
+        std::vector<RDesc>* lists[4] = {&r1, &r1b, &r2, &r2b};
+        for (int i = 0; i < 4; ++i) {
+            up(H.s_red[i], *lists[i], s);
+            H.n_s_red[i] = (int64_t)lists[i]->size();
+        }
+    }
     // leaf pairs: for leaf X, its partners Y > X (near, then leaf-level IL)
     // in ascending order take its slots 0, 1, ...
     const int64_t nleaf = LL.nbox;
@@ -577,7 +676,7 @@ void finalize_symmetric(Handle& H, hipStream_t s)
             const int32_t x = H.h_near_src[q];
             if (x >= y) continue;
             const int64_t own = find_near(H, x, (int32_t)y);
-            lps.push_back(LPair{H.h_near_off[own], 0, x, -1, slot_of_near[own]});
+            lps.push_back(LPair{H.h_near_off[own], 0, slot_of_near[own], LL.h_begin[x], LL.h_count[x], -1, 0});
             leaf_pair_vals += (double)LL.h_count[x] * my;
         }
         for (int32_t q = LL.h_il_ptr[y]; q < LL.h_il_ptr[y + 1]; ++q) {
@@ -586,10 +685,11 @@ void finalize_symmetric(Handle& H, hipStream_t s)
             const int64_t own = H.h_il_partner[q];
             if (!pair_used(own)) continue;
             if (H.h_il_kind[own] == kDense) {
-                lps.push_back(LPair{H.h_il_off[own], 0, x, -1, slot_of_il[own]});
+                lps.push_back(LPair{H.h_il_off[own], 0, slot_of_il[own], LL.h_begin[x], LL.h_count[x], -1, 0});
                 leaf_pair_vals += (double)LL.h_count[x] * my;
             } else {
-                lps.push_back(LPair{H.h_il_off[own], H.h_il_voff[own], x, H.h_il_k[own], slot_of_il[own]});
+                lps.push_back(LPair{H.h_il_off[own], H.h_il_voff[own], slot_of_il[own], LL.h_begin[x], LL.h_count[x],
+                                    H.h_il_k[own], 0});
                 leaf_pair_vals += (double)(LL.h_count[x] + my) * H.h_il_k[own];
             }
         }
@@ -672,7 +772,6 @@ void launch_matvec_symmetric(Handle& H, const double* x, double* y, int nrhs, in
     if (H.ws_nrhs < 1 || H.s_y.n < (size_t)(4 * n)) {
         H.xs.alloc((size_t)n);
         H.tpool.alloc(std::max<int64_t>(H.t_elems, 1));
-        H.ppool.alloc(std::max<int64_t>(H.p_elems, 1));
         H.s_y.alloc((size_t)4 * n);
         H.s_slots.alloc(std::max<int64_t>(H.s_slot_elems, 1));
         H.ws_nrhs = 1;
@@ -693,18 +792,26 @@ void launch_matvec_symmetric(Handle& H, const double* x, double* y, int nrhs, in
         if (ev) HIPCK(hipEventRecord(ev[0], s));
         k_sym_gather<<<(n + 255) / 256, 256, 0, s>>>(xr, H.perm.p, n, H.xs.p);
         if (ev) HIPCK(hipEventRecord(ev[1], s));
+        auto reduce = [&](int i) {
+            if (H.n_s_red[i])
+                k_sym_reduce<<<(unsigned)((H.n_s_red[i] + 3) / 4), 256, 0, s>>>(H.n_s_red[i], H.s_red[i].p, H.tpool.p);
+        };
         if (ni) {
-            k_sym_walk1<<<(unsigned)nw, 256, 0, s>>>(ni, H.s_items.p, tl, L, H.sdesc.p, H.U64.p, H.xs.p, H.ppool.p);
-            if (H.n_s_red1)
-                k_sym_reduce<<<(unsigned)H.n_s_red1, 256, 0, s>>>(H.n_s_red1, H.s_red1.p, H.ppool.p, H.tpool.p);
+            k_sym_walk1<<<(unsigned)nw, 256, 0, s>>>(ni, H.s_items.p, tl, L, H.sdesc.p, H.U64.p, H.xs.p, H.tpool.p);
+            reduce(0);
+            reduce(1);
         }
         if (ev) HIPCK(hipEventRecord(ev[2], s));
-        k_sym_walk2<<<(unsigned)(nw + nlw), 256, 0, s>>>(nw, ni, H.s_items.p, tl, L, H.sdesc.p, H.U64.p, H.D64.p,
-                                                          H.tpool.p, H.xs.p, H.ppool.p, y2, nleaf, kappa,
-                                                          H.s_lp_ptr.p, H.s_lp.p, H.s_self.p, yown, H.s_slots.p);
+        if (ni)
+            k_sym_walk2<<<(unsigned)nw, 256, 0, s>>>(ni, H.s_items.p, tl, L, H.sdesc.p, H.U64.p, H.D64.p, H.tpool.p,
+                                                      H.xs.p, H.tpool.p, y2);
+        k_sym_leaf<<<(unsigned)nlw, 256, 0, s>>>(nleaf, kappa, L, H.s_lp_ptr.p, H.s_lp.p, H.s_self.p, H.U64.p,
+                                                  H.D64.p, H.xs.p, yown, H.s_slots.p);
         if (ev) HIPCK(hipEventRecord(ev[3], s));
-        if (ni && H.n_s_red2)
-            k_sym_reduce<<<(unsigned)H.n_s_red2, 256, 0, s>>>(H.n_s_red2, H.s_red2.p, H.ppool.p, H.tpool.p);
+        if (ni) {
+            reduce(2);
+            reduce(3);
+        }
         k_sym_walk3<<<(unsigned)(nw + nlw), 256, 0, s>>>(nw, ni, H.s_items.p, tl, L, H.sdesc.p, H.U64.p, H.D64.p,
                                                           H.tpool.p, H.xs.p, y2, y3, nleaf, kappa, H.s_slot_base.p,
                                                           H.s_nslot.p, yown, H.s_slots.p, yleaf);
