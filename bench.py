@@ -561,6 +561,56 @@ def adaptive_vs_balanced(n=250000, rows=48):
     return out
 
 
+def symmetric_leg(xy, b, kern, leaf, tol, ms_ordered, y_ordered, info_ordered, reps=20):
+    """The same N = 2^20 multiquadric system with one factor pair per
+    interaction-list pair (Section 2.1 takes the matrix symmetric): storage,
+    build, the product's time and bytes, and its difference from the
+    ordered product (both approximate A x to the ACA tolerance)."""
+    import torch
+
+    from paper_2204_05536_amd import hodlr2d
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = hodlr2d.HODLR2D.build(torch.from_numpy(xy).cuda(), kern, leaf, tol, symmetric=True)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    I = S.info()
+    x = torch.from_numpy(b).cuda()
+    y = torch.empty_like(x)
+    for _ in range(3):
+        S.matvec(x, out=y)
+    S.profile_read()
+    S.profile_enable(True)
+    for _ in range(3):
+        S.matvec(x, out=y)
+    torch.cuda.synchronize()
+    S.profile_enable(False)
+    prof = S.profile_read()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        S.matvec(x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    y2 = S.matvec(x)
+    rel = float(torch.linalg.norm(y2 - y_ordered) / torch.linalg.norm(y_ordered))
+    stored = 8.0 * (I["u_elems"] + I["v_elems"] + I["d_elems"])
+    stored_o = 8.0 * (info_ordered["u_elems"] + info_ordered["v_elems"] + info_ordered["d_elems"])
+    out = {"build_seconds": tb, "stored_GB": stored / 1e9, "stored_GB_ordered": stored_o / 1e9,
+           "alg_bytes_per_product": I["alg_bytes_fp64"], "ms": ms, "ms_ordered": ms_ordered,
+           "speedup_vs_ordered": ms_ordered / ms, "GB/s": I["alg_bytes_fp64"] / (ms * 1e-3) / 1e9,
+           "matvecs_per_s": 1e3 / ms, "rel_diff_vs_ordered_product": rel,
+           "bitwise_repeatable": bool(torch.equal(y2, S.matvec(x))),
+           "phases": ["gather", "walk 1 + reduce", "walk 2 + leaf pairs", "reduce + walk 3 + slots", "combine"],
+           "phases_ms": prof["ms"], "phases_alg_bytes": prof["bytes"]}
+    log(f"symmetric: {out['stored_GB']:.2f} GB stored (ordered {out['stored_GB_ordered']:.2f}), {ms:.3f} ms "
+        f"(ordered {ms_ordered:.3f}), {out['GB/s']:.0f} GB/s, rel diff {rel:.1e}, build {tb:.1f} s")
+    S.close()
+    return out
+
+
 def precond_local_gauss(n=1 << 16):
     """Where a leaf preconditioner matters: Gaussian RBF c = 0.02 + 0.3 I on
     N = 2^16 uniform points (leaf boxes comparable to c).  Plain GMRES,
@@ -609,6 +659,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own N=250k 1/r Chebyshev workload")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-tree leg")
+    ap.add_argument("--no-symmetric", action="store_true", help="skip the one-factor-pair-per-pair leg")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (a known-size kernel for counter calibration)")
@@ -699,6 +750,8 @@ def main():
         extra["half"] = half
     if not args.no_mrhs:
         extra["multi_rhs"] = multi_rhs(H, info, x.shape[0])
+    if not args.no_symmetric:
+        extra["symmetric"] = symmetric_leg(xy, b, kern, leaf, tol, ms, y1, info)
     if not args.no_solve:
         xs, sinfo = H.solve(x, tol=1e-8, restart=50, max_iter=100)
         extra["gmres_mq_plain"] = {k: sinfo[k] for k in ("iters", "relres", "seconds", "converged")}
