@@ -67,6 +67,31 @@ __device__ __forceinline__ A ldv(const T* p)
     else return ld<T, A>(p);
 }
 
+// acc += sum over c = g, g + G, ... < n of base[c ld] w[c], eight columns
+// per lane loaded before any is multiplied: the loads of a chunk are in
+// flight together, and a short tail is padded with zero products instead of
+// running one load (and one memory latency) at a time.  The products are
+// added in increasing c, as the plain loop adds them.
+template <typename T, typename A, typename W>
+__device__ __forceinline__ void dot_cols(A& acc, const T* base, int64_t ld, const W* w, int32_t n, int g, int G)
+{
+    for (int32_t c0 = 0; c0 < n; c0 += 8 * G) {
+        A v[8], t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t c = c0 + u * G + g;
+            v[u] = (A)0;
+            t[u] = (A)0;
+            if (c < n) {
+                v[u] = ldv<T, A>(base + (int64_t)c * ld);
+                t[u] = (A)w[c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u] * t[u];
+    }
+}
+
 // Two consecutive half values from one 4-byte load.  A lane that reads a
 // single 2-byte value per instruction moves 128 bytes per wave load, and
 // such loads stream at about half the rate of 4-byte ones on this chip, so
@@ -310,18 +335,12 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
                 // a contiguous cnt x k column-major matrix
                 const T* base = Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + r;
                 const cA* tv = (const cA*)(tpool + d.tsrc);
-                if (act) {
-#pragma unroll 8
-                    for (int32_t c = g; c < d.cols; c += G) acc += ldv<T, A>(base + (int64_t)c * cnt) * tv[c];
-                }
+                if (act) dot_cols<T, A>(acc, base, cnt, tv, d.cols, g, G);
             } else if (d.cols < 0) {
                 const T* base = Dp + d.off + off;
                 const cA* tv = (const cA*)(xs + d.tsrc);
                 A a = (A)0;
-                if (act) {
-#pragma unroll 8
-                    for (int32_t j = g; j < -d.cols; j += G) a += ldv<T, A>(base + (int64_t)j * ld_m) * tv[j];
-                }
+                if (act) dot_cols<T, A>(a, base, ld_m, tv, -d.cols, g, G);
                 if constexpr (kHalf) acc += a * (A)scale[q];
                 else acc += a;
             }
@@ -510,10 +529,7 @@ b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], A* tst, int 
             for (int32_t j = lane; j < m; j += kWave) tst[j] = tv[c0 + j];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
-            if (act) {
-#pragma unroll 4
-                for (int32_t c = g; c < m; c += G) a += ldv<T, A>(base + (int64_t)(c0 + c) * cnt) * tst[c];
-            }
+            if (act) dot_cols<T, A>(a, base + (int64_t)c0 * cnt, cnt, tst, m, g, G);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
@@ -726,7 +742,7 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
         if (!act) continue;
         const double* base = Dp + d.off + rc + r;
         const double* xv = xs + d.tsrc;
-        for (int32_t j = g; j < -d.cols; j += G) acc += base[(int64_t)j * cnt] * xv[j];
+        dot_cols<double, double>(acc, base, cnt, xv, -d.cols, g, G);
     }
     int32_t a = box;
     for (int l = lx; l >= 1; --l) {
@@ -739,13 +755,11 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
             if (d.cols > 0) {
                 const double* base = Up + d.off + roff;
                 const double* tv = tpool + d.tsrc;
-#pragma unroll 4
-                for (int32_t c = g; c < d.cols; c += G) acc += base[(int64_t)c * m] * tv[c];
+                dot_cols<double, double>(acc, base, m, tv, d.cols, g, G);
             } else {
                 const double* base = Dp + d.off + roff;
                 const double* xv = xs + d.tsrc;
-#pragma unroll 4
-                for (int32_t j = g; j < -d.cols; j += G) acc += base[(int64_t)j * m] * xv[j];
+                dot_cols<double, double>(acc, base, m, xv, -d.cols, g, G);
             }
         }
         a = uni(L.parent[l][a]);

@@ -64,6 +64,30 @@ __device__ __forceinline__ int64_t su(int64_t v)
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+// acc += sum over c = g, g + G, ... < n of base[c ld] w[c], eight columns
+// per lane loaded before any is multiplied (a short tail is padded with
+// zero products instead of running one memory latency per column); the
+// products are added in increasing c.
+template <typename W>
+__device__ __forceinline__ void dot8(double& acc, const double* base, int64_t ld, const W* w, int32_t n, int g, int G)
+{
+    for (int32_t c0 = 0; c0 < n; c0 += 8 * G) {
+        double v[8], t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t c = c0 + u * G + g;
+            v[u] = 0.0;
+            t[u] = 0.0;
+            if (c < n) {
+                v[u] = base[(int64_t)c * ld];
+                t[u] = w[c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u] * t[u];
+    }
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -112,10 +136,7 @@ __device__ __forceinline__ void sym_walk(int32_t it, int lane, double* red, cons
                 const double* base = Fp + off + (int64_t)cols * (p0 - ab) + rc + r;
                 const cdouble* tv = (const cdouble*)(tpool + tsrc);
                 if constexpr (!kReduce) {
-                    if (act) {
-#pragma unroll 8
-                        for (int32_t c = 0; c < cols; ++c) acc += base[(int64_t)c * cnt] * tv[c];
-                    }
+                    if (act) dot8(acc, base, cnt, tv, cols, 0, 1);
                 } else {
                     double* pout = ppool + su(d.part) + (int64_t)sl * cols;
                     for (int32_t c0 = 0; c0 < cols; c0 += kSymChunk) {
@@ -157,16 +178,10 @@ __device__ __forceinline__ void sym_walk(int32_t it, int lane, double* red, cons
                     const cdouble* xv = (const cdouble*)(xs + tsrc);
                     if (su(d.part) == 0) {
                         const double* base = Dp + off + (p0 - ab + rc + r);
-                        if (act) {
-#pragma unroll 8
-                            for (int32_t j = 0; j < -cols; ++j) acc += base[(int64_t)j * ld_m] * xv[j];
-                        }
+                        if (act) dot8(acc, base, ld_m, xv, -cols, 0, 1);
                     } else {   // the owner's block, this row of the mirror is its column
                         const double* base = Dp + off + (int64_t)(p0 - ab + rc + r) * (-cols);
-                        if (act) {
-#pragma unroll 8
-                            for (int32_t j = 0; j < -cols; ++j) acc += base[j] * xv[j];
-                        }
+                        if (act) dot8(acc, base, 1, xv, -cols, 0, 1);
                     }
                 }
             }
@@ -224,10 +239,7 @@ __device__ __forceinline__ void sym_leaf(int32_t Y, int lane, double* lds, int k
     double acc = 0.0;
     {
         const double* D = Dp + su(self_off[Y]) + r;
-        if (act) {
-#pragma unroll 4
-            for (int32_t j = g; j < m; j += G) acc += D[(int64_t)j * m] * xY[j];
-        }
+        if (act) dot8(acc, D, m, xY, m, g, G);
     }
     for (int32_t e = e0; e < e1; ++e) {
         const int64_t pa = su(nx.a), pb = su(nx.b), slot = su(nx.slot);
@@ -240,34 +252,20 @@ __device__ __forceinline__ void sym_leaf(int32_t Y, int lane, double* lds, int k
         double sx = 0.0;
         if (k < 0) {
             const double* Dr = Dp + pa + ix;
-            if (actx) {
-#pragma unroll 4
-                for (int32_t j = gx; j < m; j += Gx) sx += Dr[(int64_t)j * mx] * xY[j];
-            }
+            if (actx) dot8(sx, Dr, mx, xY, m, gx, Gx);
             if (lane < mx) xX[lane] = xv;
             wave_sync();
             const double* Dc = Dp + pa + (int64_t)r * mx;
-            if (act) {
-#pragma unroll 4
-                for (int32_t i = g; i < mx; i += G) acc += Dc[i] * xX[i];
-            }
+            if (act) dot8(acc, Dc, 1, xX, mx, g, G);
         } else {
             const double* FX = Fp + pa;
             const double* FY = Fp + pb;
             const int Gq = kWave / k, gq = lane / k, qq = lane % k;
             double s1 = 0.0, s2 = 0.0;
-            if (gq < Gq) {
-                const double* fy = FY + (int64_t)qq * m;
-#pragma unroll 4
-                for (int32_t j = gq; j < m; j += Gq) s2 += fy[j] * xY[j];
-            }
+            if (gq < Gq) dot8(s2, FY + (int64_t)qq * m, 1, xY, m, gq, Gq);
             if (lane < mx) xX[lane] = xv;
             wave_sync();
-            if (gq < Gq) {
-                const double* fx = FX + (int64_t)qq * mx;
-#pragma unroll 4
-                for (int32_t i = gq; i < mx; i += Gq) s1 += fx[i] * xX[i];
-            }
+            if (gq < Gq) dot8(s1, FX + (int64_t)qq * mx, 1, xX, mx, gq, Gq);
             red[lane] = s1;
             red2[lane] = s2;
             wave_sync();
@@ -281,14 +279,8 @@ __device__ __forceinline__ void sym_leaf(int32_t Y, int lane, double* lds, int k
                 tv[kWave + lane] = a2;
             }
             wave_sync();
-            if (act) {
-#pragma unroll 4
-                for (int32_t c = g; c < k; c += G) acc += FY[r + (int64_t)c * m] * tv[c];
-            }
-            if (actx) {
-#pragma unroll 4
-                for (int32_t c = gx; c < k; c += Gx) sx += FX[ix + (int64_t)c * mx] * tv[kWave + c];
-            }
+            if (act) dot8(acc, FY + r, m, tv, k, g, G);
+            if (actx) dot8(sx, FX + ix, mx, tv + kWave, k, gx, Gx);
         }
         const double t = group_sum(actx ? sx : 0.0, lane, mx, Gx, red);
         if (lane < mx) slots[slot + lane] = t;
