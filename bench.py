@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
+FP32_MFMA_PEAK_TFS = 157.3
 
 
 def log(*a):
@@ -219,6 +220,11 @@ def kernel_traffic(kernel: str):
     return traffic.get(kernel)
 
 
+def hodlr_prec(name):
+    from paper_2204_05536_amd import hodlr2d
+    return hodlr2d.PREC[name]
+
+
 def mr_bytes(info, nrhs):
     """Algorithmic bytes of one product with nrhs right-hand sides: the
     stored factors once, every vector term of the single-RHS count nrhs times."""
@@ -269,6 +275,31 @@ def multi_rhs(H, info, n, nrhs=16, reps=10):
          "alg_bytes": mr_bytes(info, nrhs), "TFLOP/s": tf, "fp64_mfma_frac": tf / FP64_MFMA_PEAK_TFS,
          "rel_diff_vs_single_rhs": err, "phases_alg_bytes": mr_phase_bytes(H, info, nrhs)}
     log(f"multi-RHS x{nrhs}: {ms:.3f} ms ({ms / nrhs:.3f} ms per RHS), {r['GB/s']:.0f} GB/s, {tf:.2f} TFLOP/s")
+    # the FP16 / BF16 pools: values widened to FP32 on load, FP32 matrix cores
+    half = {}
+    hfac = 2.0 * (info["u_elems"] + info["v_elems"] + info["d_elems"])
+    hbytes = hfac + nrhs * (info["alg_bytes_half"] - hfac)
+    for p in ("fp16", "bf16"):
+        if not info["prec_mask"] & (1 << hodlr_prec(p)):
+            continue
+        for _ in range(2):
+            H.matvec(X, prec=p, out=Y)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            H.matvec(X, prec=p, out=Y)
+        e1.record()
+        torch.cuda.synchronize()
+        mh = e0.elapsed_time(e1) / reps
+        yh3 = H.matvec(X[3].contiguous(), prec=p)
+        tfh = nrhs * info["flops"] / (mh * 1e-3) / 1e12
+        half[p] = {"ms": mh, "ms_per_rhs": mh / nrhs, "GB/s": hbytes / (mh * 1e-3) / 1e9, "alg_bytes": hbytes,
+                   "TFLOP/s": tfh, "fp32_mfma_frac": tfh / FP32_MFMA_PEAK_TFS,
+                   "rel_diff_vs_single_rhs_same_prec": float(torch.linalg.norm(Y[3] - yh3) / torch.linalg.norm(yh3)),
+                   "rel_diff_vs_fp64": float(torch.linalg.norm(Y[3] - y3) / torch.linalg.norm(y3))}
+        log(f"multi-RHS x{nrhs} {p}: {mh:.3f} ms ({mh / nrhs:.3f} ms per RHS), {half[p]['GB/s']:.0f} GB/s, "
+            f"{tfh:.2f} TFLOP/s, diff vs FP64 {half[p]['rel_diff_vs_fp64']:.1e}")
+    r["half"] = half
     return r
 
 

@@ -136,6 +136,7 @@ struct MRItem {
 struct MRBlk {
     int64_t voff;
     int32_t k, out;
+    int32_t blk, pad;   // the block (its scale in the half pools)
 };
 
 // Static data of one instance for the table-driven multi-RHS kernels (a
@@ -144,12 +145,14 @@ struct MRBlk {
 // global-memory pointers (a pointer read from memory would be a generic one
 // to the compiler, with flat loads and per-lane address arithmetic).
 struct MRInst {
-    uint64_t U, V, D;                 // const double*
-    uint64_t xs, tp, pp, yp, yl;      // double*
+    uint64_t U, V, D;                 // factor pools: const double*, or the FP16/BF16 pools
+    uint64_t xs, tp, pp, yp, yl;      // work vectors: double*, or float* with the half pools
     uint64_t items, blks, ritems, b1items, bil, bnear;
     uint64_t near_ptr, iperm;         // const int32_t*
     uint64_t lvl;                     // const int32_t* const*: begin, count, parent, il_ptr (kMaxLevel + 1 each)
-    int32_t n, kappa, has_b1, pad;
+    uint64_t scale, diag;             // half pools: const float* block scales (IL blocks, then near blocks) and
+                                      // self-block diagonal (tree order); unused in FP64
+    int32_t n, kappa, has_b1, n_il;
 };
 // Right-hand sides of one instance: x and y column-major, leading dimension ld.
 struct MRIo {
@@ -274,6 +277,12 @@ struct Handle {
     int64_t n_mr_items = 0, n_mr_ritems = 0, mr_p_elems = 0;
     std::vector<int64_t> h_mr_work;  // work of each multi-RHS phase-A item, in schedule order
     DBuf<MRInst> mr_inst;            // this handle's entry for the table-driven kernels
+    // the same schedule on the half pools (FP32 work vectors, V offsets of
+    // the padded half V pools), built on the first half-precision product
+    DBuf<float> xs_mr32, tp_mr32, pp_mr32, yp_mr32, yl_mr32;
+    DBuf<MRBlk> mr_blks16;
+    DBuf<MRInst> mr_inst16;          // [FP16, BF16]
+    int mr16_cap = 0;
     int32_t mr_rows = 256;           // source rows per multi-RHS phase-A item (tuned by h2d_autotune)
     int32_t a_rows = kPhaseARows;    // rows per phase-A work item (tuned by h2d_autotune)
 
@@ -324,7 +333,7 @@ struct Handle {
 // kernels.hip
 void finalize(Handle& H, hipStream_t s);
 void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s);
-void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s);
+void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s);
 // Multi-RHS state of H (schedule, work space, instance entry), built once.
 void ensure_mr(Handle& H, hipStream_t s);
 MRInst mr_inst_of(const Handle& H);

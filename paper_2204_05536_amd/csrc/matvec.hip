@@ -1182,8 +1182,8 @@ void launch_matvec(Handle& H, const double* x, double* y, int nrhs, int64_t ld, 
         launch_matvec_symmetric(H, x, y, nrhs, ld, s);
         return;
     }
-    if (nrhs > 1 && prec == H2D_P_FP64 && !H.adaptive) {   // blocks of 16 right-hand sides on the matrix cores
-        launch_matvec_mr(H, x, y, nrhs, ld, s);
+    if (nrhs > 1 && !H.adaptive) {   // blocks of 16 right-hand sides on the matrix cores
+        launch_matvec_mr(H, x, y, nrhs, ld, prec, s);
         return;
     }
     ensure_workspace(H, 1);

@@ -1,13 +1,23 @@
-// Multi-RHS form of Algorithm 2 on FP64 matrix cores: Y = A_hat X for
+// Multi-RHS form of Algorithm 2 on the matrix cores: Y = A_hat X for
 // blocks of 16 right-hand sides.  With 16 columns the products become real
 // contractions, T_b = V_b^T X(Y_b) (k x 16) and Y(X) += U_b T_b, computed
-// with v_mfma_f64_16x16x4f64.  Schedule, storage and the tree are those of
-// the single-RHS path (matvec.hip); only the inner products differ.
+// with v_mfma_f64_16x16x4f64 on the FP64 pools and, on the FP16 / BF16
+// pools, with v_mfma_f32_16x16x4f32: each stored value is widened to FP32
+// as it is loaded, right-hand sides, T and the sums stay FP32, and the
+// products accumulate in FP32 (the accuracy of the single-RHS half path).
+// Schedule, storage and the tree are those of the single-RHS path
+// (matvec.hip); only the inner products differ.  The half pools keep their
+// per-block scales: T_b carries the scale of U_b (as t does in the
+// single-RHS path), dense blocks scale the x values they multiply, and the
+// self-block diagonal held apart in FP32 is added when the result is
+// scattered back.
 //
 // MFMA operand layout (16 x 16 output, K = 4 per instruction), lane l:
 //   A (16 x 4):  A[l % 16][l / 16]
 //   B (4 x 16):  B[l / 16][l % 16]
-//   D (16 x 16): register v holds D[4 v + l / 16][l % 16]
+//   D (16 x 16): register v holds D[4 v + l / 16][l % 16] for the FP64
+//                instruction, D[4 (l / 16) + v][l % 16] for the FP32 one
+//                (checked on the device)
 // Right-hand sides are kept point-major inside the kernels (16 consecutive
 // values per point), so a B fragment is 64 consecutive doubles.
 #include "h2d_impl.h"
@@ -18,10 +28,57 @@ namespace h2d {
 
 constexpr int kR = 16;
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+// Storage type T -> arithmetic type A, accumulator tile V4, the matrix
+// instruction, and loads of one stored value (through a buffer resource at
+// a byte offset, or through a pointer) widened to A.
+template <typename T> struct MrT;
+template <> struct MrT<double> {
+    using A = double;
+    using V4 = d4;
+    static __device__ __forceinline__ V4 mma(A a, A b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ A load(rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    }
+    static __device__ __forceinline__ A get(const double* p) { return *p; }
+    // output row of accumulator register v in lane group lk = lane / 16
+    static __device__ __forceinline__ int row(int v, int lk) { return 4 * v + lk; }
+};
+template <> struct MrT<__half> {
+    using A = float;
+    using V4 = f4;
+    static __device__ __forceinline__ V4 mma(A a, A b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ A load(rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+    }
+    static __device__ __forceinline__ A get(const __half* p) { return __half2float(*p); }
+    static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
+template <> struct MrT<__hip_bfloat16> {
+    using A = float;
+    using V4 = f4;
+    static __device__ __forceinline__ V4 mma(A a, A b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ A load(rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+        return __builtin_bit_cast(float, h << 16);
+    }
+    static __device__ __forceinline__ A get(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+    static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
+// Work-vector values (x, T) through a buffer resource.
+template <typename A> __device__ __forceinline__ A vload(rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ double vload<double>(rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ float vload<float>(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
 __device__ __forceinline__ int32_t uni_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -50,7 +107,8 @@ __device__ __forceinline__ int2 work_at(const int2* __restrict__ work, int32_t i
 // xs[iperm[c] * 16 + r] = x[(r0 + r) * ld + c] for r < nr, 0 beyond.  One
 // workgroup per 64 caller-order points of an instance: the right-hand-side
 // rows are read coalesced, transposed through LDS, and each point's 16
-// values are written as one 128-byte segment at its tree position.
+// values are written as one segment at its tree position.
+template <typename A>
 __global__ void __launch_bounds__(256)
 k_gather_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork, MRIo io0,
             const MRIo* __restrict__ iot, int32_t r0, int32_t nr)
@@ -62,7 +120,7 @@ k_gather_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int
     const MRIo io = iot ? iot[wk.x] : io0;
     const int32_t n = I.n, c0 = wk.y * kWave;
     const double* x = gp<const double>(io.x) + (int64_t)r0 * io.ld;
-    double* xs = gp<double>(I.xs);
+    A* xs = gp<A>(I.xs);
     const int32_t* iperm = gp<const int32_t>(I.iperm);
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
         const int r = e / kWave, c = e % kWave;
@@ -71,13 +129,15 @@ k_gather_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int
     __syncthreads();
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
         const int c = e / kR, r = e % kR;
-        if (c0 + c < n) xs[(int64_t)iperm[c0 + c] * kR + r] = tile[r][c];
+        if (c0 + c < n) xs[(int64_t)iperm[c0 + c] * kR + r] = (A)tile[r][c];
     }
 }
 
 // y[(r0 + r) * ld + c] = (yleaf + yanc)[iperm[c] * 16 + r] for r < nr: the
 // inverse of the gather, from the tree-ordered point-major leaf and
-// ancestor sums back to caller order.
+// ancestor sums back to caller order (half pools: plus the FP32 self
+// diagonal times x).
+template <typename A>
 __global__ void __launch_bounds__(256)
 k_scatter_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork, MRIo io0,
              const MRIo* __restrict__ iot, int32_t r0, int32_t nr)
@@ -88,14 +148,19 @@ k_scatter_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, in
     const MRInst& I = insts[wk.x];
     const MRIo io = iot ? iot[wk.x] : io0;
     const int32_t n = I.n, c0 = wk.y * kWave;
-    const double* yt = gp<const double>(I.yl);
-    const double* ya = I.has_b1 ? gp<const double>(I.yp) : nullptr;
+    const A* yt = gp<const A>(I.yl);
+    const A* ya = I.has_b1 ? gp<const A>(I.yp) : nullptr;
+    const float* diag = I.diag ? gp<const float>(I.diag) : nullptr;
+    const A* xs = gp<const A>(I.xs);
     const int32_t* iperm = gp<const int32_t>(I.iperm);
     for (int e = threadIdx.x; e < kR * kWave; e += blockDim.x) {
         const int c = e / kR, r = e % kR;
         if (c0 + c < n) {
-            const int64_t g = (int64_t)iperm[c0 + c] * kR + r;
-            tile[r][c] = ya ? yt[g] + ya[g] : yt[g];
+            const int32_t i = iperm[c0 + c];
+            const int64_t g = (int64_t)i * kR + r;
+            A v = ya ? yt[g] + ya[g] : yt[g];
+            if (diag) v += (A)diag[i] * xs[g];
+            tile[r][c] = (double)v;
         }
     }
     __syncthreads();
@@ -121,50 +186,48 @@ __global__ void k_iperm(const int32_t* __restrict__ perm, int32_t n, int32_t* __
 // a scalar offset per K-step and a 32-bit per-lane offset that stays fixed
 // over the loop, so a group of 4 K-steps needs no per-lane address math.
 // An offset at or past the extent reads 0 (never the case by construction).
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-
-__device__ __forceinline__ rsrc_t rsrc(const double* base, int64_t elems)
+template <typename T>
+__device__ __forceinline__ rsrc_t rsrc(const T* base, int64_t elems)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)(elems * 8), 0x00020000);
-}
-
-__device__ __forceinline__ double bld(rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)(elems * (int64_t)sizeof(T)),
+                                             0x00020000);
 }
 
 // T rows q0 + 16 t (t < NT) += V(0..rows-1, q)^T X(0..rows-1, :) for one
-// block: V row-major with k columns at Vb, X point-major in LDS at xl,
-// zero-padded to a multiple of 16 rows.
-template <int NT>
-__device__ __forceinline__ void srcA_tiles(d4 (&acc)[4], const double* __restrict__ Vb, int32_t k, int32_t q0,
-                                           const double* xl, int32_t rows, int lane)
+// block: V row-major with k columns and row stride ldv at Vb, X point-major
+// in LDS at xl, zero-padded to a multiple of 16 rows.
+template <typename T, int NT>
+__device__ __forceinline__ void srcA_tiles(typename MrT<T>::V4 (&acc)[4], const T* __restrict__ Vb, int32_t k,
+                                           int32_t ldv, int32_t q0, const typename MrT<T>::A* xl, int32_t rows,
+                                           int lane)
 {
+    using A = typename MrT<T>::A;
+    constexpr uint32_t es = sizeof(T);
     const int li = lane % 16, lk = lane / 16;
     uint32_t ao[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) ao[t] = (uint32_t)(lk * k + min(q0 + 16 * t + li, k - 1)) * 8u;
-    const uint32_t sa = (uint32_t)k * 32u;   // 4 rows of V, in bytes
+    for (int t = 0; t < NT; ++t) ao[t] = (uint32_t)(lk * ldv + min(q0 + 16 * t + li, k - 1)) * es;
+    const uint32_t sa = (uint32_t)ldv * 4u * es;   // 4 rows of V, in bytes
     int32_t j = 0;
     // software-pipelined: the loads of the next 16 rows are issued before
     // the matrix instructions of the current 16
-    auto load = [&](int32_t jj, double (&a)[4][NT], double (&b)[4]) {
-        const rsrc_t rv = rsrc(Vb + (int64_t)jj * k, 16 * (int64_t)k);
+    auto load = [&](int32_t jj, A (&a)[4][NT], A (&b)[4]) {
+        const rsrc_t rv = rsrc(Vb + (int64_t)jj * ldv, 16 * (int64_t)ldv);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             b[u] = xl[(jj + 4 * u + lk) * kR + li];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) a[u][t] = bld(rv, ao[t], u * sa);
+            for (int t = 0; t < NT; ++t) a[u][t] = MrT<T>::load(rv, ao[t], u * sa);
         }
     };
-    auto compute = [&](const double (&a)[4][NT], const double (&b)[4]) {
+    auto compute = [&](const A (&a)[4][NT], const A (&b)[4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u][t], b[u], acc[t]);
+            for (int t = 0; t < NT; ++t) acc[t] = MrT<T>::mma(a[u][t], b[u], acc[t]);
     };
     if (j + 16 <= rows) {
-        double a0[4][NT], b0[4], a1[4][NT], b1[4];
+        A a0[4][NT], b0[4], a1[4][NT], b1[4];
         load(j, a0, b0);
         for (; j + 32 <= rows; j += 32) {
             load(j + 16, a1, b1);
@@ -178,33 +241,37 @@ __device__ __forceinline__ void srcA_tiles(d4 (&acc)[4], const double* __restric
         }
     }
     if (j < rows) {   // last group: rows past the end re-read row rows - 1, their X rows are zero
-        double a[4][NT], b[4];
+        A a[4][NT], b[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t jl = min(j + 4 * u + lk, rows - 1);
             b[u] = xl[(j + 4 * u + lk) * kR + li];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) a[u][t] = Vb[jl * k + min(q0 + 16 * t + li, k - 1)];
+            for (int t = 0; t < NT; ++t) a[u][t] = MrT<T>::get(Vb + jl * ldv + min(q0 + 16 * t + li, k - 1));
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u][t], b[u], acc[t]);
+            for (int t = 0; t < NT; ++t) acc[t] = MrT<T>::mma(a[u][t], b[u], acc[t]);
     }
 }
 
 // Phase A grouped by source box: one workgroup per item stages the item's
 // rows of X in LDS once; its four waves take the blocks sharing that source
 // in turn, T (k x 16, row-major) = V(rows, :)^T X(rows, :), up to 4 M tiles
-// of 16 columns q per pass.  Dynamic LDS: 16 x 8 bytes per row, rows
-// rounded up to 16.
+// of 16 columns q per pass (half pools: times the block's U scale).
+// Dynamic LDS: 16 values per row, rows rounded up to 16.
+template <typename T>
 __device__ __forceinline__ void
-phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const double* __restrict__ V, const double* __restrict__ xs,
-            double* __restrict__ tpool, double* __restrict__ ppool, double* xl)
+phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restrict__ V,
+            const typename MrT<T>::A* __restrict__ xs, typename MrT<T>::A* __restrict__ tpool,
+            typename MrT<T>::A* __restrict__ ppool, typename MrT<T>::A* xl, const float* __restrict__ scale)
 {
+    using A = typename MrT<T>::A;
+    using V4 = typename MrT<T>::V4;
     const int32_t rows = it.j1 - it.j0, rpad = (rows + 15) & ~15;
-    const double* src = xs + (int64_t)(it.col0 + it.j0) * kR;
-    for (int e = threadIdx.x; e < rpad * kR; e += blockDim.x) xl[e] = e < rows * kR ? src[e] : 0.0;
+    const A* src = xs + (int64_t)(it.col0 + it.j0) * kR;
+    for (int e = threadIdx.x; e < rpad * kR; e += blockDim.x) xl[e] = e < rows * kR ? src[e] : (A)0;
     __syncthreads();
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int li = lane % 16, lk = lane / 16;
@@ -212,60 +279,67 @@ phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const double* __re
         const MRBlk B = blks[b];
         const int64_t voff = uni_l(B.voff);
         const int32_t k = uni_i(B.k), out = uni_i(B.out);
-        double* T = out >= 0 ? tpool + (int64_t)out * kR : ppool + ((int64_t)(-out - 1) + (int64_t)it.p * k) * kR;
-        const double* Vb = V + voff + (int64_t)it.j0 * k;
+        // FP64 V rows hold k values; the half pools pad each row to a multiple of 4
+        const int32_t ldv = sizeof(T) == 8 ? k : ((k + 3) & ~3);
+        A sc = (A)1;
+        if constexpr (sizeof(T) != 8) sc = (A)scale[uni_i(B.blk)];
+        A* Tt = out >= 0 ? tpool + (int64_t)out * kR : ppool + ((int64_t)(-out - 1) + (int64_t)it.p * k) * kR;
+        const T* Vb = V + voff + (int64_t)it.j0 * ldv;
         for (int32_t q0 = 0; q0 < k; q0 += 64) {
-            d4 acc[4];
+            V4 acc[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
+            for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
             const int32_t nt = min(4, (k - q0 + 15) / 16);
-            if (nt == 4) srcA_tiles<4>(acc, Vb, k, q0, xl, rows, lane);
-            else if (nt == 3) srcA_tiles<3>(acc, Vb, k, q0, xl, rows, lane);
-            else if (nt == 2) srcA_tiles<2>(acc, Vb, k, q0, xl, rows, lane);
-            else srcA_tiles<1>(acc, Vb, k, q0, xl, rows, lane);
+            if (nt == 4) srcA_tiles<T, 4>(acc, Vb, k, ldv, q0, xl, rows, lane);
+            else if (nt == 3) srcA_tiles<T, 3>(acc, Vb, k, ldv, q0, xl, rows, lane);
+            else if (nt == 2) srcA_tiles<T, 2>(acc, Vb, k, ldv, q0, xl, rows, lane);
+            else srcA_tiles<T, 1>(acc, Vb, k, ldv, q0, xl, rows, lane);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int32_t q = q0 + 16 * t + 4 * v + lk;
-                    if (t < nt && q < k) T[(int64_t)q * kR + li] = acc[t][v];
+                    const int32_t q = q0 + 16 * t + MrT<T>::row(v, lk);
+                    if (t < nt && q < k) Tt[(int64_t)q * kR + li] = acc[t][v] * sc;
                 }
         }
     }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256)
 k_phaseA_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork)
 {
-    extern __shared__ double xl[];
+    using A = typename MrT<T>::A;
+    extern __shared__ double xl_raw[];
     if ((int32_t)blockIdx.x >= nwork) return;
     const int2 wk = work_at(work, blockIdx.x);
     const MRInst& I = insts[wk.x];
-    phaseA_item(gp<const MRItem>(I.items)[wk.y], gp<const MRBlk>(I.blks), gp<const double>(I.V),
-                gp<const double>(I.xs), gp<double>(I.tp), gp<double>(I.pp), xl);
+    phaseA_item<T>(gp<const MRItem>(I.items)[wk.y], gp<const MRBlk>(I.blks), gp<const T>(I.V), gp<const A>(I.xs),
+                   gp<A>(I.tp), gp<A>(I.pp), (A*)xl_raw, I.scale ? gp<const float>(I.scale) : nullptr);
 }
 
 // t = sum of the partial products of one split block.  Grid (split blocks,
 // ceil(max k / 4)): workgroup (b, g) owns elements 64 g .. 64 g + 63 of the
 // k x 16 result, its four waves take every fourth part, and the four wave
 // sums are added in a fixed order.
+template <typename A>
 __global__ void __launch_bounds__(256)
 k_reduce_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork)
 {
-    __shared__ double part[4][kWave];
+    __shared__ A part[4][kWave];
     if ((int32_t)blockIdx.x >= nwork) return;
     const int2 wk = work_at(work, blockIdx.x);
     const MRInst& I = insts[wk.x];
-    const double* __restrict__ ppool = gp<const double>(I.pp);
-    double* __restrict__ tpool = gp<double>(I.tp);
+    const A* __restrict__ ppool = gp<const A>(I.pp);
+    A* __restrict__ tpool = gp<A>(I.tp);
     const RDesc D = gp<const RDesc>(I.ritems)[wk.y];
     const int32_t E = D.k * kR;
     if ((int32_t)blockIdx.y * kWave >= E) return;   // whole workgroup
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t e = blockIdx.y * kWave + lane;
     const int64_t stride = (int64_t)D.k * kR;
-    const double* base = ppool + (int64_t)D.pbeg * kR + min(e, E - 1);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const A* base = ppool + (int64_t)D.pbeg * kR + min(e, E - 1);
+    A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     int32_t p = wave;
     for (; p + 12 < D.nparts; p += 16) {
         s0 += base[(int64_t)p * stride];
@@ -281,71 +355,89 @@ k_reduce_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int
 }
 
 // acc[t] (rows 16 t .. 16 t + 15 of a tile, t < NT) += A (rows x K) B (K x 16)
-// where A(i, c) = Ab[c * lda + i] and B(c, r) = Bb[c * ldb + r].
-template <int NT>
-__device__ __forceinline__ void mm_tiles(d4 (&acc)[4], const double* __restrict__ Ab, int64_t lda, int32_t rows,
-                                         const double* __restrict__ Bb, int64_t ldb, int32_t K, int lane)
+// where A(i, c) = Ab[c * lda + i] (stored values) and B(c, r) = bs Bb[c * ldb + r]
+// (work values, times the dense block's scale bs on the half pools).
+template <typename T, int NT>
+__device__ __forceinline__ void mm_tiles(typename MrT<T>::V4 (&acc)[4], const T* __restrict__ Ab, int64_t lda,
+                                         int32_t rows, const typename MrT<T>::A* __restrict__ Bb, int64_t ldb, int32_t K,
+                                         typename MrT<T>::A bs, int lane)
 {
+    using A = typename MrT<T>::A;
+    constexpr uint32_t ea = sizeof(T), eb = sizeof(A);
     const int li = lane % 16, lk = lane / 16;
     uint32_t ao[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) ao[t] = (uint32_t)(lk * lda + min(16 * t + li, rows - 1)) * 8u;
-    const uint32_t bo = (uint32_t)(lk * ldb + li) * 8u;
-    const uint32_t sa = (uint32_t)lda * 32u, sb = (uint32_t)ldb * 32u;   // 4 columns, in bytes
+    for (int t = 0; t < NT; ++t) ao[t] = (uint32_t)(lk * lda + min(16 * t + li, rows - 1)) * ea;
+    const uint32_t bo = (uint32_t)(lk * ldb + li) * eb;
+    const uint32_t sa = (uint32_t)lda * 4u * ea, sb = (uint32_t)ldb * 4u * eb;   // 4 columns, in bytes
     int32_t c = 0;
     for (; c + 16 <= K; c += 16) {
         const rsrc_t ra = rsrc(Ab + (int64_t)c * lda, 15 * lda + rows);
         const rsrc_t rb = rsrc(Bb + (int64_t)c * ldb, 15 * ldb + kR);
-        double a[4][NT], b[4];
+        A a[4][NT], b[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            b[u] = bld(rb, bo, u * sb);
+            b[u] = vload<A>(rb, bo, u * sb) * bs;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) a[u][t] = bld(ra, ao[t], u * sa);
+            for (int t = 0; t < NT; ++t) a[u][t] = MrT<T>::load(ra, ao[t], u * sa);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u][t], b[u], acc[t]);
+            for (int t = 0; t < NT; ++t) acc[t] = MrT<T>::mma(a[u][t], b[u], acc[t]);
     }
     for (; c < K; c += 4) {   // tail: columns past K re-read column K - 1 with B zeroed
         const int32_t cc = c + lk;
         const int64_t cl = min(cc, K - 1);
-        double b = Bb[cl * ldb + li];
-        b = cc < K ? b : 0.0;
-        double a[NT];
+        A b = Bb[cl * ldb + li] * bs;
+        b = cc < K ? b : (A)0;
+        A a[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) a[t] = Ab[cl * lda + min(16 * t + li, rows - 1)];
+        for (int t = 0; t < NT; ++t) a[t] = MrT<T>::get(Ab + cl * lda + min(16 * t + li, rows - 1));
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = mfma(a[t], b, acc[t]);
+        for (int t = 0; t < NT; ++t) acc[t] = MrT<T>::mma(a[t], b, acc[t]);
     }
 }
 
-__device__ __forceinline__ void mm_tile(d4 (&acc)[4], const double* __restrict__ Ab, int64_t lda, int32_t rows,
-                                        const double* __restrict__ Bb, int64_t ldb, int32_t K, int lane)
+template <typename T>
+__device__ __forceinline__ void mm_tile(typename MrT<T>::V4 (&acc)[4], const T* __restrict__ Ab, int64_t lda,
+                                        int32_t rows, const typename MrT<T>::A* __restrict__ Bb, int64_t ldb, int32_t K,
+                                        typename MrT<T>::A bs, int lane)
 {
-    if (rows > 48) mm_tiles<4>(acc, Ab, lda, rows, Bb, ldb, K, lane);
-    else if (rows > 32) mm_tiles<3>(acc, Ab, lda, rows, Bb, ldb, K, lane);
-    else if (rows > 16) mm_tiles<2>(acc, Ab, lda, rows, Bb, ldb, K, lane);
-    else mm_tiles<1>(acc, Ab, lda, rows, Bb, ldb, K, lane);
+    if (rows > 48) mm_tiles<T, 4>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
+    else if (rows > 32) mm_tiles<T, 3>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
+    else if (rows > 16) mm_tiles<T, 2>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
+    else mm_tiles<T, 1>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
+}
+
+// Scale of a dense block of the half pools (index into the scale table).
+template <typename T>
+__device__ __forceinline__ typename MrT<T>::A dense_scale(const float* __restrict__ scale, int64_t i)
+{
+    if constexpr (sizeof(T) == 8) return 1.0;
+    else return scale[i];
 }
 
 // Phase B1 (ancestor levels): one wave per 64-row chunk of a box at level
 // kappa - 1; U tiles as in the single-RHS path.  ypart is row-major n x 16.
+template <typename T>
 __device__ __forceinline__ void
 b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_t* const* __restrict__ Lbegin,
       const int32_t* const* __restrict__ Lcount, const int32_t* const* __restrict__ Lparent,
-      const int32_t* const* __restrict__ Lil, const BDesc* __restrict__ bil, const double* __restrict__ Up,
-      const double* __restrict__ Dp, const double* __restrict__ tpool, const double* __restrict__ xs,
-      double* __restrict__ ypart)
+      const int32_t* const* __restrict__ Lil, const BDesc* __restrict__ bil, const T* __restrict__ Up,
+      const T* __restrict__ Dp, const typename MrT<T>::A* __restrict__ tpool,
+      const typename MrT<T>::A* __restrict__ xs, typename MrT<T>::A* __restrict__ ypart,
+      const float* __restrict__ scale)
 {
+    using A = typename MrT<T>::A;
+    using V4 = typename MrT<T>::V4;
     const int2 w = items[it];
     const int32_t P = uni_i(w.x), rc = uni_i(w.y);
     const int32_t p0 = uni_i(gp<const int32_t>((uint64_t)Lbegin[tl])[P]), cnt = uni_i(gp<const int32_t>((uint64_t)Lcount[tl])[P]);
     const int32_t rows = min(kWave, cnt - rc);
-    d4 acc[4];
+    V4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
+    for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
     int32_t a_box = P;
     for (int l = tl; l >= 1; --l) {
         const int32_t ab = uni_i(gp<const int32_t>((uint64_t)Lbegin[l])[a_box]), ld_m = uni_i(gp<const int32_t>((uint64_t)Lcount[l])[a_box]);
@@ -355,10 +447,11 @@ b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_
             const int64_t off = uni_l(d.off);
             const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
             if (cols > 0)
-                mm_tile(acc, Up + off + (int64_t)cols * (p0 - ab) + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR, cols,
-                        lane);
+                mm_tile<T>(acc, Up + off + (int64_t)cols * (p0 - ab) + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR,
+                           cols, (A)1, lane);
             else if (cols < 0)
-                mm_tile(acc, Dp + off + (p0 - ab) + rc, ld_m, rows, xs + (int64_t)tsrc * kR, kR, -cols, lane);
+                mm_tile<T>(acc, Dp + off + (p0 - ab) + rc, ld_m, rows, xs + (int64_t)tsrc * kR, kR, -cols,
+                           dense_scale<T>(scale, q), lane);
         }
         a_box = uni_i(gp<const int32_t>((uint64_t)Lparent[l])[a_box]);
     }
@@ -367,44 +460,52 @@ b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int32_t i = 16 * t + 4 * v + lk;
+            const int32_t i = 16 * t + MrT<T>::row(v, lk);
             if (i < rows) ypart[(int64_t)(p0 + rc + i) * kR + li] = acc[t][v];
         }
 }
 
 // Phase B2 (leaf level): one wave per leaf box; near blocks and the leaf's
 // own interaction-list blocks, into yt (tree order, point-major).
+template <typename T>
 __device__ __forceinline__ void
 b2_mr(int32_t X, int lane, const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
       const int32_t* __restrict__ il_ptr, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
-      const BDesc* __restrict__ bil, const double* __restrict__ Up, const double* __restrict__ Dp,
-      const double* __restrict__ tpool, const double* __restrict__ xs, double* __restrict__ yt)
+      const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
+      const typename MrT<T>::A* __restrict__ tpool, const typename MrT<T>::A* __restrict__ xs,
+      typename MrT<T>::A* __restrict__ yt, const float* __restrict__ scale, int32_t n_il)
 {
+    using A = typename MrT<T>::A;
+    using V4 = typename MrT<T>::V4;
     const int32_t r0 = uni_i(begin[X]), cnt = uni_i(count[X]);
     const int32_t n0 = uni_i(near_ptr[X]), n1 = uni_i(near_ptr[X + 1]);
     const int32_t q0 = uni_i(il_ptr[X]), q1 = uni_i(il_ptr[X + 1]);
     const int li = lane % 16, lk = lane / 16;
     for (int32_t rc = 0; rc < cnt; rc += kWave) {
         const int32_t rows = min(kWave, cnt - rc);
-        d4 acc[4];
+        V4 acc[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
+        for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
         for (int32_t q = n0; q < n1; ++q) {
             const BDesc d = bnear[q];
-            mm_tile(acc, Dp + uni_l(d.off) + rc, cnt, rows, xs + (int64_t)uni_i(d.tsrc) * kR, kR, -uni_i(d.cols), lane);
+            mm_tile<T>(acc, Dp + uni_l(d.off) + rc, cnt, rows, xs + (int64_t)uni_i(d.tsrc) * kR, kR, -uni_i(d.cols),
+                       dense_scale<T>(scale, (int64_t)n_il + q), lane);
         }
         for (int32_t q = q0; q < q1; ++q) {
             const BDesc d = bil[q];
             const int64_t off = uni_l(d.off);
             const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
-            if (cols > 0) mm_tile(acc, Up + off + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR, cols, lane);
-            else if (cols < 0) mm_tile(acc, Dp + off + rc, cnt, rows, xs + (int64_t)tsrc * kR, kR, -cols, lane);
+            if (cols > 0)
+                mm_tile<T>(acc, Up + off + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR, cols, (A)1, lane);
+            else if (cols < 0)
+                mm_tile<T>(acc, Dp + off + rc, cnt, rows, xs + (int64_t)tsrc * kR, kR, -cols, dense_scale<T>(scale, q),
+                           lane);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int32_t i = 16 * t + 4 * v + lk;
+                const int32_t i = 16 * t + MrT<T>::row(v, lk);
                 if (i < rows) yt[(int64_t)(r0 + rc + i) * kR + li] = acc[t][v];
             }
     }
@@ -427,10 +528,12 @@ __device__ __forceinline__ int32_t xcd_sub_mr(int32_t w, int32_t w0, int32_t n)
 // Phase B in one launch: the first nb1 workgroups do 64-row chunks of the
 // level-(kappa-1) boxes (ancestor levels, into ypart), the rest do leaf
 // boxes (into yleaf); the halves are independent and summed by the scatter.
+template <typename T>
 __global__ void __launch_bounds__(256)
 k_phaseB_mr(const MRInst* __restrict__ insts, int32_t nb1, const int2* __restrict__ work1, int32_t n1,
             const int2* __restrict__ work2, int32_t n2)
 {
+    using A = typename MrT<T>::A;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t w = blockIdx.x;
     if (w < nb1) {
@@ -439,9 +542,9 @@ k_phaseB_mr(const MRInst* __restrict__ insts, int32_t nb1, const int2* __restric
         const int2 wk = work_at(work1, it);
         const MRInst& I = insts[wk.x];
         const int32_t* const* L = gp<const int32_t* const>(I.lvl);
-        b1_mr(wk.y, lane, gp<const int2>(I.b1items), I.kappa - 1, L, L + (kMaxLevel + 1), L + 2 * (kMaxLevel + 1),
-              L + 3 * (kMaxLevel + 1), gp<const BDesc>(I.bil), gp<const double>(I.U), gp<const double>(I.D),
-              gp<const double>(I.tp), gp<const double>(I.xs), gp<double>(I.yp));
+        b1_mr<T>(wk.y, lane, gp<const int2>(I.b1items), I.kappa - 1, L, L + (kMaxLevel + 1), L + 2 * (kMaxLevel + 1),
+                 L + 3 * (kMaxLevel + 1), gp<const BDesc>(I.bil), gp<const T>(I.U), gp<const T>(I.D),
+                 gp<const A>(I.tp), gp<const A>(I.xs), gp<A>(I.yp), I.scale ? gp<const float>(I.scale) : nullptr);
     } else {
         const int32_t it = xcd_sub_mr(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
         if (it >= n2) return;
@@ -449,10 +552,11 @@ k_phaseB_mr(const MRInst* __restrict__ insts, int32_t nb1, const int2* __restric
         const MRInst& I = insts[wk.x];
         const int32_t* const* L = gp<const int32_t* const>(I.lvl);
         const int kp = I.kappa;
-        b2_mr(wk.y, lane, gp<const int32_t>((uint64_t)L[kp]), gp<const int32_t>((uint64_t)L[(kMaxLevel + 1) + kp]),
-              gp<const int32_t>((uint64_t)L[3 * (kMaxLevel + 1) + kp]), gp<const int32_t>(I.near_ptr),
-              gp<const BDesc>(I.bnear), gp<const BDesc>(I.bil), gp<const double>(I.U), gp<const double>(I.D),
-              gp<const double>(I.tp), gp<const double>(I.xs), gp<double>(I.yl));
+        b2_mr<T>(wk.y, lane, gp<const int32_t>((uint64_t)L[kp]), gp<const int32_t>((uint64_t)L[(kMaxLevel + 1) + kp]),
+                 gp<const int32_t>((uint64_t)L[3 * (kMaxLevel + 1) + kp]), gp<const int32_t>(I.near_ptr),
+                 gp<const BDesc>(I.bnear), gp<const BDesc>(I.bil), gp<const T>(I.U), gp<const T>(I.D),
+                 gp<const A>(I.tp), gp<const A>(I.xs), gp<A>(I.yl), I.scale ? gp<const float>(I.scale) : nullptr,
+                 I.n_il);
     }
 }
 
@@ -488,9 +592,9 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
             const int32_t k = H.h_il_k[b];
             ksum += k;
             if (parts == 1) {
-                blks.push_back(MRBlk{H.h_il_voff[b], k, H.h_il_toff[b]});
+                blks.push_back(MRBlk{H.h_il_voff[b], k, H.h_il_toff[b], (int32_t)b, 0});
             } else {
-                blks.push_back(MRBlk{H.h_il_voff[b], k, (int32_t)(-poff - 1)});
+                blks.push_back(MRBlk{H.h_il_voff[b], k, (int32_t)(-poff - 1), (int32_t)b, 0});
                 red.push_back(RDesc{H.h_il_toff[b], k, (int32_t)poff, parts});
                 poff += (int64_t)parts * k;
             }
@@ -522,6 +626,13 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
         HIPCK(hipMemcpyAsync(H.mr_blks.p, blks.data(), sizeof(MRBlk) * blks.size(), hipMemcpyHostToDevice, s));
     if (!red.empty())
         HIPCK(hipMemcpyAsync(H.mr_ritems.p, red.data(), sizeof(RDesc) * red.size(), hipMemcpyHostToDevice, s));
+    if (H.v16_elems > 0) {   // the same blocks on the padded half V pools
+        std::vector<MRBlk> b16(blks);
+        for (MRBlk& B : b16) B.voff = H.h_il_voff16[B.blk];
+        H.mr_blks16.alloc(std::max<size_t>(b16.size(), 1));
+        if (!b16.empty())
+            HIPCK(hipMemcpyAsync(H.mr_blks16.p, b16.data(), sizeof(MRBlk) * b16.size(), hipMemcpyHostToDevice, s));
+    }
     H.n_mr_items = (int64_t)sorted.size();
     H.n_mr_ritems = (int64_t)red.size();
     H.mr_p_elems = poff;
@@ -539,7 +650,8 @@ MRInst mr_inst_of(const Handle& H)
     I.items = addr(H.mr_items.p); I.blks = addr(H.mr_blks.p); I.ritems = addr(H.mr_ritems.p);
     I.b1items = addr(H.b1items.p); I.bil = addr(H.bil.p); I.bnear = addr(H.bnear.p);
     I.near_ptr = addr(H.near_ptr.p); I.iperm = addr(H.iperm.p); I.lvl = addr(H.lvl_ptrs.p);
-    I.n = (int32_t)H.n; I.kappa = H.kappa; I.has_b1 = H.n_b1 ? 1 : 0;
+    I.scale = 0; I.diag = 0;
+    I.n = (int32_t)H.n; I.kappa = H.kappa; I.has_b1 = H.n_b1 ? 1 : 0; I.n_il = (int32_t)H.n_il;
     return I;
 }
 
@@ -572,32 +684,75 @@ void ensure_mr(Handle& H, hipStream_t s)
     HIPCK(hipMemcpyAsync(H.mr_inst.p, &I, sizeof(MRInst), hipMemcpyHostToDevice, s));
     HIPCK(hipStreamSynchronize(s));
     H.mr_cap = kR;
+    H.mr16_cap = 0;   // the half-pool entries follow the schedule
+}
+
+// The half-pool entries (FP16, then BF16) of the multi-RHS product: the
+// FP64 schedule with the padded half V offsets, FP32 work vectors.
+static void ensure_mr16(Handle& H, hipStream_t s)
+{
+    ensure_mr(H, s);
+    if (H.mr16_cap) return;
+    const int32_t n = (int32_t)H.n;
+    H.xs_mr32.alloc((size_t)n * kR);
+    H.tp_mr32.alloc(std::max<int64_t>(H.t_elems, 1) * kR);
+    H.pp_mr32.alloc(std::max<int64_t>(H.mr_p_elems, 1) * kR);
+    H.yp_mr32.alloc((size_t)n * kR);
+    H.yl_mr32.alloc((size_t)n * kR);
+    MRInst I[2];
+    for (int h = 0; h < 2; ++h) {
+        I[h] = mr_inst_of(H);
+        I[h].U = addr(h ? (const void*)H.Ub16.p : (const void*)H.U16.p);
+        I[h].V = addr(h ? (const void*)H.Vb16.p : (const void*)H.V16.p);
+        I[h].D = addr(h ? (const void*)H.Db16.p : (const void*)H.D16.p);
+        I[h].xs = addr(H.xs_mr32.p); I[h].tp = addr(H.tp_mr32.p); I[h].pp = addr(H.pp_mr32.p);
+        I[h].yp = addr(H.yp_mr32.p); I[h].yl = addr(H.yl_mr32.p);
+        I[h].blks = addr(H.mr_blks16.p);
+        I[h].scale = addr(H.scale16.p);
+        I[h].diag = addr(H.diag32.p);
+    }
+    H.mr_inst16.alloc(2);
+    HIPCK(hipMemcpyAsync(H.mr_inst16.p, I, sizeof(I), hipMemcpyHostToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
+    H.mr16_cap = 1;
 }
 
 static int32_t mr_rows_of(const Handle& H) { return std::max(16, std::min<int32_t>(H.mr_rows, kMrRowsMax)) & ~15; }
 
-void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s)
+template <typename T>
+static void run_mr(Handle& H, const MRInst* I, const double* x, double* y, int nrhs, int64_t ld, hipStream_t s)
 {
-    ensure_mr(H, s);
+    using A = typename MrT<T>::A;
     const int32_t n = (int32_t)H.n;
     const int32_t nleaf = (int32_t)H.lev[H.kappa].nbox;
     const int32_t R = mr_rows_of(H);
     const int32_t pblocks = (n + kWave - 1) / kWave;
     const MRIo io{addr(x), addr(y), ld};
-    const MRInst* I = H.mr_inst.p;
     for (int r0 = 0; r0 < nrhs; r0 += kR) {
         const int32_t nr = std::min(kR, nrhs - r0);
-        k_gather_mr<<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
+        k_gather_mr<A><<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
         if (H.n_mr_items)
-            k_phaseA_mr<<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(double), s>>>(I, nullptr,
-                                                                                        (int32_t)H.n_mr_items);
+            k_phaseA_mr<T><<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(A), s>>>(I, nullptr,
+                                                                                         (int32_t)H.n_mr_items);
         if (H.n_mr_ritems)
-            k_reduce_mr<<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256, 0,
-                          s>>>(I, nullptr, (int32_t)H.n_mr_ritems);
+            k_reduce_mr<A><<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256, 0,
+                             s>>>(I, nullptr, (int32_t)H.n_mr_ritems);
         const int32_t nb1 = (int32_t)((H.n_b1 + 3) / 4), nb2 = (nleaf + 3) / 4;
-        k_phaseB_mr<<<(unsigned)(nb1 + nb2), 256, 0, s>>>(I, nb1, nullptr, (int32_t)H.n_b1, nullptr, nleaf);
-        k_scatter_mr<<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
+        k_phaseB_mr<T><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(I, nb1, nullptr, (int32_t)H.n_b1, nullptr, nleaf);
+        k_scatter_mr<A><<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
         HIPCK(hipGetLastError());
+    }
+}
+
+void launch_matvec_mr(Handle& H, const double* x, double* y, int nrhs, int64_t ld, int prec, hipStream_t s)
+{
+    if (prec == H2D_P_FP64) {
+        ensure_mr(H, s);
+        run_mr<double>(H, H.mr_inst.p, x, y, nrhs, ld, s);
+    } else {
+        ensure_mr16(H, s);
+        if (prec == H2D_P_FP16) run_mr<__half>(H, H.mr_inst16.p, x, y, nrhs, ld, s);
+        else run_mr<__hip_bfloat16>(H, H.mr_inst16.p + 1, x, y, nrhs, ld, s);
     }
 }
 
@@ -676,14 +831,14 @@ void mr_plan(MRBatchPlan& P, Handle* const* hs, const MRIo* io, int count, hipSt
 void mr_plan_launch(const MRBatchPlan& P, int32_t r0, int32_t nr, hipStream_t s)
 {
     const MRIo none{0, 0, 0};
-    k_gather_mr<<<(unsigned)P.ng, 256, 0, s>>>(P.insts.p, P.wg.p, P.ng, none, P.io.p, r0, nr);
+    k_gather_mr<double><<<(unsigned)P.ng, 256, 0, s>>>(P.insts.p, P.wg.p, P.ng, none, P.io.p, r0, nr);
     for (size_t g = 0; g < P.a_rows.size(); ++g)
-        k_phaseA_mr<<<(unsigned)P.a_cnt[g], 256, (size_t)P.a_rows[g] * kR * sizeof(double), s>>>(
+        k_phaseA_mr<double><<<(unsigned)P.a_cnt[g], 256, (size_t)P.a_rows[g] * kR * sizeof(double), s>>>(
             P.insts.p, P.wa.p + P.a_beg[g], P.a_cnt[g]);
-    if (P.nr) k_reduce_mr<<<dim3((unsigned)P.nr, (unsigned)P.red_y), 256, 0, s>>>(P.insts.p, P.wr.p, P.nr);
+    if (P.nr) k_reduce_mr<double><<<dim3((unsigned)P.nr, (unsigned)P.red_y), 256, 0, s>>>(P.insts.p, P.wr.p, P.nr);
     const int32_t g1 = (P.nb1 + 3) / 4, g2 = (P.nb2 + 3) / 4;
-    k_phaseB_mr<<<(unsigned)(g1 + g2), 256, 0, s>>>(P.insts.p, g1, P.wb1.p, P.nb1, P.wb2.p, P.nb2);
-    k_scatter_mr<<<(unsigned)P.ng, 256, 0, s>>>(P.insts.p, P.wg.p, P.ng, none, P.io.p, r0, nr);
+    k_phaseB_mr<double><<<(unsigned)(g1 + g2), 256, 0, s>>>(P.insts.p, g1, P.wb1.p, P.nb1, P.wb2.p, P.nb2);
+    k_scatter_mr<double><<<(unsigned)P.ng, 256, 0, s>>>(P.insts.p, P.wg.p, P.ng, none, P.io.p, r0, nr);
     HIPCK(hipGetLastError());
 }
 

@@ -1,6 +1,6 @@
-"""Multi-RHS matvec (FP64 matrix cores, 16 right-hand sides per pass)
-against the single-RHS path and against the oracle's Algorithm 2 on
-identical factors."""
+"""Multi-RHS matvec (16 right-hand sides per pass on the matrix cores: FP64,
+and FP32 for the FP16 / BF16 pools) against the single-RHS path and against
+the oracle's Algorithm 2 on identical factors."""
 import numpy as np
 import pytest
 import torch
@@ -79,3 +79,43 @@ def test_leading_dimension_through_abi(nrhs):
     for r in range(nrhs):
         y1 = host(H.matvec(dev(np.ascontiguousarray(Xp[r, :n]))))
         assert np.linalg.norm(Y[r, :n] - y1) <= 1e-13 * np.linalg.norm(y1), r
+
+
+U16 = 2.0 ** -11   # unit roundoff of FP16
+UBF = 2.0 ** -8    # unit roundoff of BF16
+
+
+@pytest.mark.parametrize("prec,u", [("fp16", U16), ("bf16", UBF)])
+@pytest.mark.parametrize("name", ["log4096", "mq5120_leaf100"])
+def test_half_multi_rhs_on_oracle_factors(orc, tmp_path, prec, u, name):
+    """FP16 / BF16 pools made from the oracle's factors, 21 right-hand sides
+    (a pass of 16 and a pass of 5): every row of every column within 4 u of
+    sum_j |A_ij x_j| of the oracle's FP64 product (the bound of the
+    single-RHS half path), and within FP32 rounding of the single-RHS half
+    product of the same column (same stored values, FP32 sums in another
+    order)."""
+    from tests import npref
+    if name == "log4096":
+        xy, _, kern, leaf, tol = inputs.workload("log4096")
+    else:   # leaves of about 80 points: two 64-row passes per leaf
+        xy = np.random.default_rng(12).uniform(-1, 1, (5120, 2))
+        kern, leaf, tol = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}, 100, 1e-10
+    n = xy.shape[0]
+    O = orc.OracleH(xy, kern, leaf, tol)
+    p = tmp_path / "o.h2dx"
+    O.export(p)
+    H = _lib().HODLR2D.import_file(p, precs=(prec,))
+    X = np.random.default_rng(13).uniform(-1, 1, (21, n))
+    Y = host(H.matvec(dev(X), prec=prec))
+    Aabs = np.abs(npref.kernel_matrix(kern, xy))
+    worst = 0.0
+    for r in range(21):
+        absrow = Aabs @ np.abs(X[r])
+        yo = O.matvec(X[r])
+        err = np.abs(Y[r] - yo) / absrow
+        worst = max(worst, float(err.max()))
+        assert np.all(np.isfinite(Y[r])) and err.max() <= 4 * u, (r, err.max())
+        if r in (0, 15, 16, 20):
+            y1 = host(H.matvec(dev(X[r]), prec=prec))
+            assert np.max(np.abs(Y[r] - y1) / absrow) <= 1e-5, r
+    say(f"{name} {prec} x21: max row error / sum|A x| = {worst:.2e} (4u = {4 * u:.1e})")
