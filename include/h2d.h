@@ -138,8 +138,11 @@ h2d_status h2d_build(const double* xy, int64_t n, const h2d_kernel* kernel, int3
  *   x, y    device, FP64, column-major n x nrhs with leading dimension ld >= n
  *   prec    storage precision to read (must have been built); FP16/BF16
  *           accumulate in FP32 and round the result to FP64
- * FP64 with nrhs > 1 runs the right-hand sides 16 at a time through FP64
- * matrix-core (MFMA) kernels; otherwise right-hand sides run one by one.
+ * nrhs > 1 runs the right-hand sides 16 at a time through matrix-core
+ * (MFMA) kernels: FP64 ones on the FP64 pools, FP32 ones on the FP16/BF16
+ * pools (each stored value widened to FP32 as it is loaded, right-hand
+ * sides and sums in FP32); adaptive and symmetric handles run them one by
+ * one.
  * Asynchronous on `stream`.  Errors: EINVAL, EUNSUPPORTED (precision not
  * built), EDEVICE. */
 h2d_status h2d_matvec(h2d_t H, const double* x, double* y, int32_t nrhs, int64_t ld,
