@@ -88,6 +88,27 @@ __device__ __forceinline__ void dot8(double& acc, const double* base, int64_t ld
     }
 }
 
+// A double moved between lanes by a DPP pattern (two 32-bit moves).
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over each aligned group of 8 lanes, in every lane of the group: the
+// pairs (l, l ^ 1) and (l, l ^ 2) of a quad, then the two quads of the
+// group (row_half_mirror pairs lane j with 7 - j).
+__device__ __forceinline__ double sum8(double s)
+{
+    s += dpp_f64<0xB1>(s);    // quad_perm [1, 0, 3, 2]
+    s += dpp_f64<0x4E>(s);    // quad_perm [2, 3, 0, 1]
+    s += dpp_f64<0x141>(s);   // row_half_mirror
+    return s;
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -101,7 +122,7 @@ __device__ __forceinline__ void wave_sync()
 // slice's part of F^T xs for the partner block (kReduce).  The partial sums
 // go through LDS 8 columns at a time (4 KB per wave, so LDS does not cap
 // the waves per CU below what the registers allow): lane (c, h) adds the 8
-// products of lanes 8 h .. 8 h + 7 for column c, then three butterfly steps
+// products of lanes 8 h .. 8 h + 7 for column c, then three DPP steps
 // finish the 64-row sum.
 template <bool kApply, bool kReduce, bool kOwner>
 __device__ __forceinline__ void sym_walk(int32_t it, int lane, double* red, const int2* __restrict__ items, int tl,
@@ -167,8 +188,8 @@ __device__ __forceinline__ void sym_walk(int32_t it, int lane, double* red, cons
                         double sum = 0.0;
 #pragma unroll
                         for (int i = 0; i < kSymChunk; ++i) sum += red[cc * kWave + h * kSymChunk + i];
-#pragma unroll
-                        for (int dd = 1; dd < kPer; dd <<= 1) sum += __shfl_xor(sum, dd, kWave);
+                        static_assert(kPer == 8, "the butterfly below sums groups of 8 lanes");
+                        sum = sum8(sum);
                         if (h == 0 && cc < nc) pout[c0 + cc] = sum;
                         wave_sync();
                     }
