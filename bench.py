@@ -398,7 +398,8 @@ def paper_shaped(reps=20, n_psi=10):
     """The paper's serial matvec workload (Section 5.1) at each of its sizes:
     m x m first-kind Chebyshev grids, N = m^2 = 10 000 ... 250 000, K = 1/r
     with zero diagonal, tolerance 1e-12, leaf size 500.  For each size: the
-    build time, the matvec time, the stored bytes, the largest rank, and the
+    build time, the matvec time (work-item sizes picked by h2d_autotune),
+    the stored bytes, the largest rank, and the
     paper's error eps_r = max over 10 random psi of max_i |b_hat - b|_i /
     |b|_i against the exact product (entries of psi uniform in [0, 1], so
     that b > 0 for this positive kernel and the element-wise ratio is
@@ -422,6 +423,10 @@ def paper_shaped(reps=20, n_psi=10):
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t0
         info = H.info()
+        # leaves of up to 500 points: the tuner picks the work-item sizes
+        t0 = time.perf_counter()
+        tiles, _ = H.autotune(1)
+        t_tune = time.perf_counter() - t0
         x = psi[0].contiguous()
         y = torch.empty_like(x)
         for _ in range(3):
@@ -446,6 +451,7 @@ def paper_shaped(reps=20, n_psi=10):
         del exact, psi, xy_d
         p = PAPER_1BYR[n]
         r = {"n": n, "kappa": info["kappa"], "r_m": info["max_rank"], "build_seconds": t_build,
+             "tiles": tiles, "tune_seconds": t_tune,
              "ms_per_matvec": ms, "GB/s": info["alg_bytes_fp64"] / (ms * 1e-3) / 1e9,
              "factor_GB": 8.0 * (info["u_elems"] + info["v_elems"] + info["d_elems"]) / 1e9,
              "eps_r": eps_r, "eps_normwise": eps_n,

@@ -366,17 +366,21 @@ h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
 typedef enum {
     H2D_TILE_A_ROWS = 0,   /* V rows per single-RHS phase-A item: 16..512 (default 512) */
     H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS phase-A item: 16..512, multiple of 16 (default 256) */
-    H2D_TILE_B1_ROWS = 2   /* rows per single-RHS phase-B1 item: 16, 32 or 64 (default 64); with
+    H2D_TILE_B1_ROWS = 2,  /* rows per single-RHS phase-B1 item: 16, 32 or 64 (default 64); with
                               64 the FP16/BF16 products take runs of up to 256 rows of sibling
                               boxes instead (four rows per lane) */
+    H2D_TILE_B2_ROWS = 3   /* rows per single-RHS phase-B2 item (a chunk of a leaf box): 16, 32 or
+                              64 (default 64); chunks of fewer rows take several column groups
+                              per wave, so big leaves spread over more waves */
 } h2d_tile;
 
 /* Tile tuning: times 5 FP64 products with nrhs right-hand sides for each
  * candidate and keeps the fastest for H.  nrhs == 1 tunes H2D_TILE_A_ROWS
- * over (128, 256, 512), then H2D_TILE_B1_ROWS over (16, 32, 64); nrhs > 1
- * tunes H2D_TILE_MR_ROWS over (128, 256, 512).  chosen (host, 2 ints, may be
- * NULL) receives the picks (second 0 for nrhs > 1); ms (host, 6 floats, may
- * be NULL) the milliseconds per product of each candidate in that order. */
+ * over (128, 256, 512), then H2D_TILE_B1_ROWS over (16, 32, 64), then
+ * H2D_TILE_B2_ROWS over (16, 32, 64); nrhs > 1 tunes H2D_TILE_MR_ROWS over
+ * (128, 256, 512).  chosen (host, 3 ints, may be NULL) receives the picks
+ * (0 past the first for nrhs > 1); ms (host, 9 floats, may be NULL) the
+ * milliseconds per product of each candidate in that order. */
 h2d_status h2d_autotune(h2d_t H, int32_t nrhs, void* stream, int32_t* chosen, float* ms);
 
 /* Batched products: the FP64 products y_i = A_i x_i of `count` built

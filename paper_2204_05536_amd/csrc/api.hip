@@ -743,6 +743,8 @@ h2d_status h2d_set_item_rows(h2d_t H, int32_t which, int32_t rows, void* stream)
                 fail(H2D_EINVAL, "chunk rows must be 16..512, multiple of 16");
         } else if (which == H2D_TILE_B1_ROWS) {
             if (rows != 16 && rows != 32 && rows != 64) fail(H2D_EINVAL, "phase-B1 slice rows must be 16, 32 or 64");
+        } else if (which == H2D_TILE_B2_ROWS) {
+            if (rows != 16 && rows != 32 && rows != 64) fail(H2D_EINVAL, "phase-B2 chunk rows must be 16, 32 or 64");
         } else {
             fail(H2D_EINVAL, "unknown tile parameter");
         }

@@ -159,14 +159,15 @@ void batch_launch(Batch* B, hipStream_t s) { HIPCK(hipGraphLaunch(B->exec, s)); 
 void batch_destroy(Batch* B) { delete B; }
 
 // which: 0 single-RHS phase-A item rows, 1 multi-RHS phase-A source-chunk
-// rows, 2 single-RHS phase-B1 slice rows.
+// rows, 2 single-RHS phase-B1 slice rows, 3 single-RHS phase-B2 leaf-chunk
+// rows.
 static void set_rows(Handle& H, int which, int32_t rows, hipStream_t s)
 {
     if (which == 1) {
         H.mr_rows = rows;
         H.mr_cap = 0;   // rebuilt with the next multi-RHS product
     } else {
-        (which == 0 ? H.a_rows : H.b1_rows) = rows;
+        (which == 0 ? H.a_rows : which == 2 ? H.b1_rows : H.b2_rows) = rows;
         finalize(H, s);
     }
 }
@@ -174,8 +175,8 @@ static void set_rows(Handle& H, int which, int32_t rows, hipStream_t s)
 void set_item_rows(Handle& H, int which, int32_t rows, hipStream_t s) { set_rows(H, which, rows, s); }
 
 // Time 5 products per candidate and keep the fastest; one right-hand side
-// tunes phase A (128, 256, 512) then phase B1 (16, 32, 64), several tune the
-// multi-RHS source chunks (128, 256, 512).
+// tunes phase A (128, 256, 512), then phase B1 (16, 32, 64), then phase B2
+// (16, 32, 64); several tune the multi-RHS source chunks (128, 256, 512).
 void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out)
 {
     const bool multi = nrhs > 1;
@@ -193,10 +194,10 @@ void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out
         int which;
         int32_t cand[3];
     };
-    const Knob single[2] = {{0, {128, 256, 512}}, {2, {16, 32, 64}}};
+    const Knob single[3] = {{0, {128, 256, 512}}, {2, {16, 32, 64}}, {3, {16, 32, 64}}};
     const Knob mr[1] = {{1, {128, 256, 512}}};
     const Knob* knobs = multi ? mr : single;
-    const int nk = multi ? 1 : 2;
+    const int nk = multi ? 1 : 3;
     for (int kb = 0; kb < nk; ++kb) {
         float best = 1e30f;
         int32_t arg = knobs[kb].cand[0];
@@ -216,7 +217,7 @@ void autotune(Handle& H, int nrhs, hipStream_t s, int32_t* chosen, float* ms_out
         set_rows(H, knobs[kb].which, arg, s);
         if (chosen) chosen[kb] = arg;
     }
-    if (multi && chosen) chosen[1] = 0;
+    if (multi && chosen) chosen[1] = chosen[2] = 0;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     H.prof_on = prof;

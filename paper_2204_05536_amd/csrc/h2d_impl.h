@@ -263,7 +263,8 @@ struct Handle {
     DBuf<int4> b1h_items;       // half-precision phase-B1 work: (first box, first row quad, row quads, 0)
     int64_t n_b1h = 0;
     int32_t b1_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
-    DBuf<int2> b2items;         // single-RHS phase-B2 work: (leaf box, first row of a 64-row chunk)
+    DBuf<int2> b2items;         // single-RHS phase-B2 work: (leaf box, first row of a b2_rows-row chunk)
+    int32_t b2_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
     int64_t n_b2 = 0;
 
     // multi-RHS work (blocks of 16 right-hand sides, point-major)

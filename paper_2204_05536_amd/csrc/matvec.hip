@@ -508,7 +508,7 @@ b1_item_h4(int32_t it, int lane, float* tst, float4* red4, const int4* __restric
 // a load covers G consecutive columns of the column-major block.
 template <typename T, typename A, bool kHalf>
 __device__ __forceinline__ void
-b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], A* tst, int kappa, const LevelPtrs& L,
+b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, A (*red)[kWave], A* tst, int kappa, const LevelPtrs& L,
         const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
         const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
         A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
@@ -516,7 +516,7 @@ b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], A* tst, int 
     const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
     const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
     const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
-    const int32_t rows = min(kWave, cnt - rc);
+    const int32_t rows = min(S2, cnt - rc);
     const int G = kWave / rows, g = lane / rows, r = lane % rows;
     const bool act = g < G;
     // one block: its multiplier values (t, or x of the source box) are
@@ -569,7 +569,8 @@ b2_item(int32_t X, int32_t rc, int wave, int lane, A (*red)[kWave], A* tst, int 
 // pairs); same sums and order as the FP64 form.
 template <typename T>
 __device__ __forceinline__ void
-b2_item_h2(int32_t X, int32_t rc, int wave, int lane, float (*red2)[2 * kWave], int kappa, const LevelPtrs& L,
+b2_item_h2(int32_t X, int32_t rc, int32_t S2, int wave, int lane, float (*red2)[2 * kWave], int kappa,
+           const LevelPtrs& L,
            const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
            const T* __restrict__ Up, const T* __restrict__ Dp, const float* __restrict__ tpool,
            const float* __restrict__ xs, float* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
@@ -577,7 +578,7 @@ b2_item_h2(int32_t X, int32_t rc, int wave, int lane, float (*red2)[2 * kWave], 
     const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
     const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
     const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
-    const int32_t rows = min(kWave, cnt - rc);
+    const int32_t rows = min(S2, cnt - rc);
     const int P = (rows + 1) >> 1;
     const int G = kWave / P, g = lane / P, rp = lane % P;
     const bool act = g < G;
@@ -673,7 +674,7 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
          const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
          const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
          A* __restrict__ ypart, A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il,
-         const int2* __restrict__ b2items, int32_t nb2items, const int4* __restrict__ h_items)
+         const int2* __restrict__ b2items, int32_t nb2items, int32_t b2_rows, const int4* __restrict__ h_items)
 {
     __shared__ A red[4][kWave];
     __shared__ A tst[4][kB2Stage];
@@ -696,10 +697,10 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
             const int2 c = b2items[it];
             if constexpr (kHalf) {
                 __shared__ float red2[4][2 * kWave];
-                b2_item_h2<T>(uni(c.x), uni(c.y), wave, lane, red2, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs,
+                b2_item_h2<T>(uni(c.x), uni(c.y), b2_rows, wave, lane, red2, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs,
                               yleaf, scale, n_il);
             } else {
-                b2_item<T, A, kHalf>(uni(c.x), uni(c.y), wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up,
+                b2_item<T, A, kHalf>(uni(c.x), uni(c.y), b2_rows, wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up,
                                      Dp, tpool, xs, yleaf, scale, n_il);
             }
         }
@@ -880,10 +881,11 @@ void finalize(Handle& H, hipStream_t s)
             for (int32_t rc = 0; rc < T.h_count[p]; rc += S) b1s.push_back(make_int2((int32_t)p, rc));
         }
     }
-    // phase-B2 work: 64-row chunks of the leaf boxes
+    // phase-B2 work: b2_rows-row chunks of the leaf boxes
     std::vector<int2> b2;
+    const int32_t S2 = H.b2_rows;
     for (int64_t x = 0; x < LL.nbox; ++x)
-        for (int32_t rc = 0; rc < LL.h_count[x]; rc += kWave) b2.push_back(make_int2((int32_t)x, rc));
+        for (int32_t rc = 0; rc < LL.h_count[x]; rc += S2) b2.push_back(make_int2((int32_t)x, rc));
     H.n_b2 = (int64_t)b2.size();
     upload_vec(H.b2items, b2, s);
     // half-precision phase-B1 work: runs of up to 64 row quads over the
@@ -1137,7 +1139,7 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     k_phaseB<T, A, kHalf, SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, \
                                                                    H.bnear.p, H.bil.p, U, D, tp, xs, yp, yl,         \
                                                                    H.scale16.p, H.n_il, H.b2items.p, (int32_t)H.n_b2, \
-                                                                   H.b1h_items.p)
+                                                                   H.b2_rows, H.b1h_items.p)
     if (H.b1_rows == 16) H2D_PHASE_B(16);
     else if (H.b1_rows == 32) H2D_PHASE_B(32);
     else H2D_PHASE_B(64);

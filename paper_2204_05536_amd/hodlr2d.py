@@ -293,19 +293,20 @@ class HODLR2D:
 
     def autotune(self, nrhs=16):
         """Returns (picks, {(knob, candidate): ms}); picks = {knob: rows}."""
-        chosen = (C.c_int32 * 2)()
-        ms = (C.c_float * 6)()
+        chosen = (C.c_int32 * 3)()
+        ms = (C.c_float * 9)()
         _check(load().h2d_autotune(self._h, int(nrhs), _stream(), chosen, ms))
         if nrhs > 1:
             return {"mr_rows": chosen[0]}, {("mr_rows", c): ms[i] for i, c in enumerate((128, 256, 512))}
         times = {("a_rows", c): ms[i] for i, c in enumerate((128, 256, 512))}
         times.update({("b1_rows", c): ms[3 + i] for i, c in enumerate((16, 32, 64))})
-        return {"a_rows": chosen[0], "b1_rows": chosen[1]}, times
+        times.update({("b2_rows", c): ms[6 + i] for i, c in enumerate((16, 32, 64))})
+        return {"a_rows": chosen[0], "b1_rows": chosen[1], "b2_rows": chosen[2]}, times
 
     def set_item_rows(self, which, rows):
-        """which: "a_rows" (single-RHS phase A), "mr_rows" (multi-RHS phase A)
-        or "b1_rows" (single-RHS phase B1)."""
-        w = {"a_rows": 0, "mr_rows": 1, "b1_rows": 2}[which]
+        """which: "a_rows" (single-RHS phase A), "mr_rows" (multi-RHS phase A),
+        "b1_rows" (single-RHS phase B1) or "b2_rows" (single-RHS phase B2)."""
+        w = {"a_rows": 0, "mr_rows": 1, "b1_rows": 2, "b2_rows": 3}[which]
         _check(load().h2d_set_item_rows(self._h, w, int(rows), _stream()))
 
     def export(self, path, factors=True):

@@ -75,6 +75,7 @@ def test_autotune_keeps_results(orc, tmp_path):
     chosen1, ms1 = H.autotune(1)
     say(f"autotune (1 RHS) chose {chosen1}, ms {ms1}")
     assert chosen1["a_rows"] in (128, 256, 512) and chosen1["b1_rows"] in (16, 32, 64)
+    assert chosen1["b2_rows"] in (16, 32, 64)
     Y = host(H.matvec(dev(X)))
     y1 = host(H.matvec(dev(X[3])))
     for r in range(16):
@@ -102,3 +103,22 @@ def test_item_size_changes_schedule_not_result(rows, b1):
     y1 = host(H.matvec(dev(x[0])))
     assert np.linalg.norm(y - y_ref) <= 1e-14 * np.linalg.norm(y_ref)
     assert np.linalg.norm(y1 - y1_ref) <= 1e-14 * np.linalg.norm(y1_ref)
+
+
+@pytest.mark.parametrize("b2", [16, 32])
+def test_leaf_chunk_rows_change_schedule_not_result(b2):
+    """Leaves of up to 200 points split into chunks of 16 or 32 rows (several
+    column groups per wave) instead of 64: the FP64 product agrees with the
+    default schedule to rounding, the FP16 one to FP32 rounding."""
+    rng = np.random.default_rng(40 + b2)
+    xy = inputs.uniform_square(20000, rng)
+    spec = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}
+    H = _lib().HODLR2D.build(dev(xy), spec, 200, 1e-10, precs=("fp16",))
+    x = dev(rng.uniform(-1, 1, 20000))
+    y_ref, yh_ref = host(H.matvec(x)), host(H.matvec(x, prec="fp16"))
+    H.set_item_rows("b2_rows", b2)
+    y, yh = host(H.matvec(x)), host(H.matvec(x, prec="fp16"))
+    assert np.linalg.norm(y - y_ref) <= 1e-14 * np.linalg.norm(y_ref)
+    assert np.linalg.norm(yh - yh_ref) <= 1e-6 * np.linalg.norm(yh_ref)
+    # the no-allocation product runs the same schedule
+    assert np.array_equal(host(H.matvec_noalloc(x)), y)
