@@ -1295,11 +1295,19 @@ void build_factors(Handle& H, hipStream_t s)
 // of the self blocks is held apart in FP32 (the log kernel's diagonal N can
 // exceed the FP16 range).
 // ---------------------------------------------------------------------
+// U and D tiles of the half pools are stored in a quad layout: a tile (the
+// U of a block above the leaf level is tiled by the boxes one level above
+// the leaves, as in the FP64 pool; any other block is one tile) is laid out
+// as [column quads][rows][4], so the 4 values of one row in 4 consecutive
+// columns form one aligned 8-byte group; the columns are padded with zeros
+// to a multiple of 4.  Element (i, c) of a p-row tile sits at
+// (floor(c / 4) p + i) 4 + c mod 4, and the tile of a k-column block whose
+// first row is row b of the block starts at k4 b (k4 = k rounded up to 4).
 struct HalfJob {
-    int64_t off;        // pool offset (U or D)
-    int64_t cnt;        // elements
-    int32_t m, self;    // rows (for the diagonal), 1 if a self block
-    int32_t row0, pad;
+    int64_t src, dst;     // FP64 offset, half offset (a multiple of 4)
+    int32_t m, n;         // rows, columns (the rank for U)
+    int32_t tiled, self;  // U tiled as above; 1 if a self block
+    int32_t row0, pad;    // first tree row of the block
 };
 
 template <typename T>
@@ -1310,14 +1318,16 @@ template <>
 __device__ __forceinline__ __hip_bfloat16 to_half<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
 
 template <typename T>
-__global__ void k_half_blocks(const HalfJob* jobs, const double* src, T* dst, float* scale, float* diag)
+__global__ void k_half_q(const HalfJob* jobs, const double* src, T* dst, float* scale, float* diag,
+                         const int32_t* tbeg, const int32_t* tcnt)
 {
     __shared__ double lv[256];
     const HalfJob J = jobs[blockIdx.x];
+    const int64_t cnt = (int64_t)J.m * J.n;
     double mx = 0.0;
-    for (int64_t e = threadIdx.x; e < J.cnt; e += blockDim.x) {
+    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
         bool d = J.self && (e % J.m) == (e / J.m);
-        if (!d) mx = fmax(mx, fabs(src[J.off + e]));
+        if (!d) mx = fmax(mx, fabs(src[J.src + e]));
     }
     lv[threadIdx.x] = mx;
     __syncthreads();
@@ -1336,11 +1346,18 @@ __global__ void k_half_blocks(const HalfJob* jobs, const double* src, T* dst, fl
     const double sc = ldexp(1.0, ex);
     const double inv = 1.0 / sc;
     if (threadIdx.x == 0) scale[blockIdx.x] = (float)sc;
-    for (int64_t e = threadIdx.x; e < J.cnt; e += blockDim.x) {
-        int64_t i = e % J.m;
-        bool d = J.self && i == (e / J.m);
-        double v = src[J.off + e];
-        dst[J.off + e] = to_half<T>(d ? 0.0f : (float)(v * inv));
+    const int64_t n4 = (J.n + 3) & ~3;
+    for (int64_t e = threadIdx.x; e < (int64_t)J.m * n4; e += blockDim.x) {
+        const int64_t c = e / J.m, i = e % J.m;
+        int64_t pb = 0, pc = J.m;   // the tile holding row i: its first row (in the block), its rows
+        if (J.tiled) {
+            pb = tbeg[J.row0 + i] - J.row0;
+            pc = tcnt[J.row0 + i];
+        }
+        const bool d = J.self && i == c;
+        double v = 0.0;
+        if (c < J.n) v = src[J.src + (J.tiled ? (int64_t)J.n * pb + c * pc + (i - pb) : c * J.m + i)];
+        dst[J.dst + n4 * pb + ((c >> 2) * pc + (i - pb)) * 4 + (c & 3)] = to_half<T>(d ? 0.0f : (float)(v * inv));
         if (d) diag[J.row0 + i] = (float)v;
     }
 }
@@ -1364,74 +1381,52 @@ __global__ void k_half_v4(const HalfVJob* jobs, const double* src, T* dst)
     }
 }
 
-// The half-precision product kernels read pairs and fours of 2-byte values
-// with one 4- or 8-byte load at any even address, which relies on the
-// GPU's unaligned-access mode (the mode the ROCm runtime sets on this GPU
-// family).  This check reads a known pattern through such loads at every
-// 2-byte offset of one 16-byte line, once per device, before any half pool
-// is built: a device that served them aligned (dropping low address bits)
-// would return the wrong words, and the half pools are then refused.
-__global__ void k_unaligned_probe(const uint16_t* __restrict__ src, uint64_t* __restrict__ out)
-{
-    typedef uint32_t u32_a2 __attribute__((aligned(2)));
-    typedef uint64_t u64_a2 __attribute__((aligned(2)));
-    const int o = threadIdx.x;   // loads at byte offsets 2, 4, 6, 8 of the pattern
-    if (o < 4) {
-        out[o] = *reinterpret_cast<const u32_a2*>(src + 1 + o);
-        out[4 + o] = *reinterpret_cast<const u64_a2*>(src + 1 + o);
-    }
-}
-
-static void check_unaligned_loads(hipStream_t s)
-{
-    static int checked[64] = {0};
-    int dev = 0;
-    HIPCK(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 64 && checked[dev]) return;
-    uint16_t pat[16];
-    for (int i = 0; i < 16; ++i) pat[i] = (uint16_t)(0x1111u * (unsigned)(i + 1) + 0x0101u * (unsigned)i);
-    DBuf<uint16_t> src;
-    DBuf<uint64_t> out;
-    src.alloc(16);
-    out.alloc(8);
-    HIPCK(hipMemcpyAsync(src.p, pat, sizeof(pat), hipMemcpyHostToDevice, s));
-    k_unaligned_probe<<<1, 64, 0, s>>>(src.p, out.p);
-    HIPCK(hipGetLastError());
-    uint64_t got[8];
-    HIPCK(hipMemcpyAsync(got, out.p, sizeof(got), hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
-    for (int o = 0; o < 4; ++o) {
-        const int e32 = 1 + o;   // the 4-byte load of thread o starts at element 1 + o
-        const uint64_t w32 = (uint64_t)pat[e32] | ((uint64_t)pat[e32 + 1] << 16);
-        uint64_t w64 = 0;
-        for (int q = 3; q >= 0; --q) w64 = (w64 << 16) | pat[1 + o + q];
-        if (got[o] != w32 || got[4 + o] != w64)
-            fail(H2D_EUNSUPPORTED, "this GPU does not serve 2-byte-aligned 4- and 8-byte loads as unaligned "
-                                   "accesses; the FP16/BF16 pools need them");
-    }
-    if (dev >= 0 && dev < 64) checked[dev] = 1;
-}
-
 void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
 {
     const bool f16 = mask & H2D_PREC_BIT(H2D_P_FP16), b16 = mask & H2D_PREC_BIT(H2D_P_BF16);
     if (!f16 && !b16) return;
-    check_unaligned_loads(s);
-    // jobs: IL blocks (U or D) in table order, then near blocks
+    const int kappa = H.kappa;
+    // jobs: IL blocks (U or D) in table order, then near blocks; each pool
+    // gets quad-layout offsets of its own, and the descriptors the half
+    // product kernels read
     std::vector<HalfJob> jobs;
+    std::vector<BDesc> bi(H.n_il);
+    H.h_il_off16.assign(H.n_il, 0);
+    int64_t uo = 0, dof = 0;
     for (int64_t q = 0; q < H.n_il; ++q) {
         const Level& L = H.lev[H.h_il_level[q]];
-        int32_t mm = L.h_count[H.h_il_tgt[q]], nn = L.h_count[H.h_il_src[q]];
-        int64_t cnt = H.h_il_kind[q] == kDense ? (int64_t)mm * nn : (int64_t)mm * H.h_il_k[q];
-        jobs.push_back(HalfJob{H.h_il_off[q], cnt, mm, 0, 0, 0});
+        const int32_t mm = L.h_count[H.h_il_tgt[q]], nn = L.h_count[H.h_il_src[q]];
+        const int32_t row0 = L.h_begin[H.h_il_tgt[q]];
+        if (H.h_il_kind[q] == kDense) {
+            H.h_il_off16[q] = dof;
+            jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, 0});
+            bi[q] = BDesc{dof, -nn, L.h_begin[H.h_il_src[q]]};
+            dof += (int64_t)mm * ((nn + 3) & ~3);
+        } else {
+            const int32_t k = H.h_il_k[q];
+            const int32_t tiled = H.h_il_level[q] <= kappa - 1 ? 1 : 0;
+            H.h_il_off16[q] = uo;
+            jobs.push_back(HalfJob{H.h_il_off[q], uo, mm, k, tiled, 0, row0, 0});
+            bi[q] = BDesc{uo, k, std::max(H.h_il_toff[q], 0)};
+            uo += (int64_t)mm * ((k + 3) & ~3);
+        }
     }
-    const Level& LL = H.lev[H.kappa];
+    const Level& LL = H.lev[kappa];
+    std::vector<BDesc> bn(H.h_near_src.size());
+    H.h_near_off16.assign(H.h_near_src.size(), 0);
     for (int64_t x = 0; x < LL.nbox; ++x)
         for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
-            int32_t y = H.h_near_src[q];
-            jobs.push_back(HalfJob{H.h_near_off[q], (int64_t)LL.h_count[x] * LL.h_count[y], LL.h_count[x],
-                                   y == (int32_t)x ? 1 : 0, LL.h_begin[x], 0});
+            const int32_t y = H.h_near_src[q];
+            H.h_near_off16[q] = dof;
+            jobs.push_back(HalfJob{H.h_near_off[q], dof, LL.h_count[x], LL.h_count[y], 0, y == (int32_t)x ? 1 : 0,
+                                   LL.h_begin[x], 0});
+            bn[q] = BDesc{dof, -LL.h_count[y], LL.h_begin[y]};
+            dof += (int64_t)LL.h_count[x] * ((LL.h_count[y] + 3) & ~3);
         }
+    H.u16_elems = uo;
+    H.d16_elems = dof;
+    upload(H.bil16, bi, s);
+    upload(H.bnear16, bn, s);
     // U and D pools need per-block scales; split the jobs per pool
     std::vector<HalfJob> ujobs, djobs;
     std::vector<int64_t> uidx, didx;
@@ -1451,6 +1446,21 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     }
     DBuf<HalfVJob> dv;
     upload(dv, vjobs, s);
+    // tree row -> first row and size of its box one level above the leaves
+    DBuf<int32_t> tbeg, tcnt;
+    {
+        std::vector<int32_t> hb(std::max<int64_t>(H.n, 1), 0), hc(std::max<int64_t>(H.n, 1), 0);
+        if (kappa >= 1) {
+            const Level& T = H.lev[kappa - 1];
+            for (int64_t p = 0; p < T.nbox; ++p)
+                for (int32_t i = T.h_begin[p]; i < T.h_begin[p] + T.h_count[p]; ++i) {
+                    hb[i] = T.h_begin[p];
+                    hc[i] = T.h_count[p];
+                }
+        }
+        upload(tbeg, hb, s);
+        upload(tcnt, hc, s);
+    }
     DBuf<float> su, sd;
     su.alloc(std::max<size_t>(ujobs.size(), 1));
     sd.alloc(std::max<size_t>(djobs.size(), 1));
@@ -1460,11 +1470,11 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         using T = std::remove_pointer_t<decltype(Up)>;
         for (size_t o = 0; o < ujobs.size(); o += 1u << 20) {
             unsigned c = (unsigned)std::min<size_t>(1u << 20, ujobs.size() - o);
-            k_half_blocks<T><<<c, 256, 0, s>>>(du.p + o, H.U64.p, Up, su.p + o, H.diag32.p);
+            k_half_q<T><<<c, 256, 0, s>>>(du.p + o, H.U64.p, Up, su.p + o, H.diag32.p, tbeg.p, tcnt.p);
         }
         for (size_t o = 0; o < djobs.size(); o += 1u << 20) {
             unsigned c = (unsigned)std::min<size_t>(1u << 20, djobs.size() - o);
-            k_half_blocks<T><<<c, 256, 0, s>>>(dd.p + o, H.D64.p, Dp, sd.p + o, H.diag32.p);
+            k_half_q<T><<<c, 256, 0, s>>>(dd.p + o, H.D64.p, Dp, sd.p + o, H.diag32.p, tbeg.p, tcnt.p);
         }
         for (size_t o = 0; o < vjobs.size(); o += 1u << 20) {
             unsigned c = (unsigned)std::min<size_t>(1u << 20, vjobs.size() - o);
@@ -1472,24 +1482,23 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         }
         HIPCK(hipGetLastError());
     };
-    // the half kernels read values in pairs and may read one element past
-    // the last block of a pool: every pool carries kHalfSlack zeroed
-    // elements at its end
+    // every pool carries kHalfSlack zeroed elements at its end (the
+    // multi-RHS tiles may read a few elements past the last block)
     auto alloc_half = [&](auto& buf, int64_t elems) {
         using T = std::remove_pointer_t<decltype(buf.p)>;
         buf.alloc((size_t)elems + kHalfSlack);
         HIPCK(hipMemsetAsync(buf.p + elems, 0, sizeof(T) * kHalfSlack, s));
     };
     if (f16) {
-        alloc_half(H.U16, H.u_elems);
+        alloc_half(H.U16, H.u16_elems);
         alloc_half(H.V16, H.v16_elems);
-        alloc_half(H.D16, H.d_elems);
+        alloc_half(H.D16, H.d16_elems);
         run(H.U16.p, H.V16.p, H.D16.p);
     }
     if (b16) {
-        alloc_half(H.Ub16, H.u_elems);
+        alloc_half(H.Ub16, H.u16_elems);
         alloc_half(H.Vb16, H.v16_elems);
-        alloc_half(H.Db16, H.d_elems);
+        alloc_half(H.Db16, H.d16_elems);
         run(H.Ub16.p, H.Vb16.p, H.Db16.p);
     }
     // one scale per IL block then per near block (table order)

@@ -19,7 +19,7 @@ constexpr int kMaxLevel = 16;      // Morton keys are 2 x 16 bits
 constexpr int kWave = 64;
 constexpr int kAcaRankCap = 256;   // ACA scratch columns per block
 constexpr int kPhaseARows = 512;   // V rows per phase-A work item (x slice staged in LDS)
-constexpr int kHalfSlack = 16;     // zeroed elements after every half-precision pool: paired loads may read 1-3 past the last block
+constexpr int kHalfSlack = 16;     // zeroed elements after every half-precision pool
 constexpr int kMrRowsMax = 512;    // multi-RHS phase-A source chunk: 512 rows x 16 x 8 bytes = 64 KiB of LDS
 
 // Error carried from deep inside the library to the C ABI.
@@ -235,11 +235,19 @@ struct Handle {
     std::vector<int64_t> h_il_voff;   // V pool offset (low rank)
     std::vector<int32_t> h_il_toff;   // t pool offset (low rank)
 
-    // factor pools (element offsets are shared by every precision)
+    // factor pools: FP64 offsets as in the block table; the half V pools are
+    // padded row-major (h_il_voff16), the half U and D pools have a layout and
+    // offsets of their own (below)
     int64_t u_elems = 0, v_elems = 0, d_elems = 0, t_elems = 0, p_elems = 0;
     DBuf<double> U64, V64, D64;
     DBuf<__half> U16, V16, D16;
     DBuf<__hip_bfloat16> Ub16, Vb16, Db16;
+    // half U and D pools in the quad layout (every tile [column quads][rows][4],
+    // columns padded to a multiple of 4): offsets of their own, and the
+    // descriptors of the half phase-B kernels pointing there
+    std::vector<int64_t> h_il_off16, h_near_off16;
+    int64_t u16_elems = 0, d16_elems = 0;
+    DBuf<BDesc> bil16, bnear16;
     DBuf<float> scale16;     // per-block scale of the half pools (IL blocks, then near blocks)
     DBuf<float> diag32;      // self-block diagonal (tree order) for the half pools
     int64_t max_rank = 0, sum_rank = 0, n_il_dense = 0;
@@ -260,8 +268,6 @@ struct Handle {
     int64_t n_b1 = 0;
     DBuf<int2> b1s_items;       // single-RHS phase-B1 work: (box, first row of a b1_rows-row slice)
     int64_t n_b1s = 0;
-    DBuf<int4> b1h_items;       // half-precision phase-B1 work: (first box, first row quad, row quads, 0)
-    int64_t n_b1h = 0;
     int32_t b1_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
     DBuf<int2> b2items;         // single-RHS phase-B2 work: (leaf box, first row of a b2_rows-row chunk)
     int32_t b2_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)

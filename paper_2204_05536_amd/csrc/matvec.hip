@@ -92,49 +92,6 @@ __device__ __forceinline__ void dot_cols(A& acc, const T* base, int64_t ld, cons
     }
 }
 
-// Two consecutive half values from one 4-byte load.  A lane that reads a
-// single 2-byte value per instruction moves 128 bytes per wave load, and
-// such loads stream at about half the rate of 4-byte ones on this chip, so
-// the half kernels read factor values in pairs.  The pair starts at any
-// even byte address: the type below tells the compiler so, and it still
-// emits one dword load, which the GPU serves in its unaligned-access mode
-// (the mode the ROCm runtime sets on this GPU family).  Callers make sure
-// both values lie inside the pool (the half pools carry a few elements of
-// slack at the end); a value past the end of a block is read but its
-// product is dropped.
-typedef uint32_t u32_a2 __attribute__((aligned(2)));
-template <typename T> __device__ __forceinline__ float2 ld2(const T* p);
-template <> __device__ __forceinline__ float2 ld2<__half>(const __half* p)
-{
-    const uint32_t w = *reinterpret_cast<const u32_a2*>(p);
-    return make_float2(__half2float(__ushort_as_half((unsigned short)(w & 0xffffu))),
-                       __half2float(__ushort_as_half((unsigned short)(w >> 16))));
-}
-template <> __device__ __forceinline__ float2 ld2<__hip_bfloat16>(const __hip_bfloat16* p)
-{
-    const uint32_t w = *reinterpret_cast<const u32_a2*>(p);
-    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
-}
-// Four consecutive half values from one 8-byte load (same alignment rule).
-typedef uint64_t u64_a2 __attribute__((aligned(2)));
-template <typename T> __device__ __forceinline__ float4 ld4(const T* p);
-template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p)
-{
-    const uint64_t w = *reinterpret_cast<const u64_a2*>(p);
-    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    return make_float4(__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
-                       __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
-                       __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu))),
-                       __half2float(__ushort_as_half((unsigned short)(hi >> 16))));
-}
-template <> __device__ __forceinline__ float4 ld4<__hip_bfloat16>(const __hip_bfloat16* p)
-{
-    const uint64_t w = *reinterpret_cast<const u64_a2*>(p);
-    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    return make_float4(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
-                       __uint_as_float(hi & 0xffff0000u));
-}
-
 // Four consecutive half values at an 8-byte-aligned address: one aligned
 // 8-byte load (the padded V pools).
 template <typename T> __device__ __forceinline__ float4 ld4v(const T* p)
@@ -361,142 +318,96 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
     }
 }
 
-// Phase B1 for the half pools.  One wave per run of up to 64 row quads of
-// sibling boxes one level above the leaves (boxes with the same parent, in
-// tree order; a box's rows are grouped in fours from its first row).  Lane
-// l takes rows 4 u .. 4 u + 3 of its box (one 8-byte load per column; the
-// values past the box's last row are dropped), so every wave load covers
-// 256 rows of one column -- 512 bytes, as a wave load of the FP64 form --
-// and the column's t (or x) value is one scalar load for the whole wave.
-// The ancestors above the siblings are shared: their blocks are walked
-// once for all the wave's rows, each lane at its own box's tile of U (or
-// rows of D).  The siblings' own blocks are walked box by box with that
-// box's lanes only.  Every lane owns its rows: no cross-lane sum.
-template <typename T>
+// The half pools' U and D tiles are stored as [column quads][rows][4]: the
+// 4 values of one row in 4 consecutive columns form one aligned 8-byte
+// group (columns padded with zeros to a multiple of 4).
+// acc += sum over quads u = g, g + G, ... < ceil(n / 4) of the 4 values at
+// base + u qstride times w[4 u .. 4 u + 3] (w past n taken as 0: those
+// belong to other blocks or lie past the vector's end).  The loads of 4
+// quads are issued before any is used; columns are added in increasing
+// order.
+template <typename T, typename W>
+__device__ __forceinline__ void quad_dot(float& acc, const T* base, int64_t qstride, const W* w, int32_t n, int g,
+                                         int G)
+{
+    const int32_t nq = (n + 3) >> 2;
+    for (int32_t u0 = 0; u0 < nq; u0 += 4 * G) {
+        float4 v[4], t[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t u = u0 + j * G + g, c = 4 * u;
+            v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            t[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (u < nq) {
+                v[j] = ld4v<T>(base + (int64_t)u * qstride);
+                t[j].x = w[c];
+                t[j].y = c + 1 < n ? (float)w[c + 1] : 0.f;
+                t[j].z = c + 2 < n ? (float)w[c + 2] : 0.f;
+                t[j].w = c + 3 < n ? (float)w[c + 3] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc += v[j].x * t[j].x;
+            acc += v[j].y * t[j].y;
+            acc += v[j].z * t[j].z;
+            acc += v[j].w * t[j].w;
+        }
+    }
+}
+
+// Phase B1 on the half pools: lane (g, r) owns row r of an S-row slice of a
+// box one level above the leaves and the column quads g, g + G, ... (G =
+// 64 / S) of every block of that box and of its ancestors: each load is
+// one row's 4 columns, a wave load 64 rows x 4 columns (512 bytes, as in
+// the FP64 form).  The G column-group sums are added in a fixed order.
+template <typename T, int S>
 __device__ __forceinline__ void
-b1_item_h4(int32_t it, int lane, float* tst, float4* red4, const int4* __restrict__ items, int tl,
-           const LevelPtrs& L, const BDesc* __restrict__ bil, const T* __restrict__ Up,
-           const T* __restrict__ Dp, const float* __restrict__ tpool, const float* __restrict__ xs,
-           float* __restrict__ ypart, const float* __restrict__ scale)
+b1_item_q(int32_t it, int wave, int lane, float (*red)[kWave], const int2* __restrict__ items, int tl,
+          const LevelPtrs& L, const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
+          const float* __restrict__ tpool, const float* __restrict__ xs, float* __restrict__ ypart,
+          const float* __restrict__ scale)
 {
     using cA = ConstAS<float>;
-    const int4 w = items[it];
-    const int32_t P0 = uni(w.x), u0 = uni(w.y), nu = uni(w.z);
-    const bool act = lane < nu;
-    int32_t P = P0, u = u0 + lane;
-    if (act) {
-        for (;;) {
-            const int32_t nq = (L.count[tl][P] + 3) >> 2;
-            if (u < nq) break;
-            u -= nq;
-            ++P;
-        }
-    }
-    const int32_t p0 = act ? L.begin[tl][P] : 0, cnt = act ? L.count[tl][P] : 0, r = 4 * u;
-    const int32_t Plast = __builtin_amdgcn_readlane(P, nu - 1);
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    auto column_sweep = [&](const T* base, int64_t stride, const cA* tv, int32_t nc, float4& b) {
-#pragma unroll 8
-        for (int32_t c = 0; c < nc; ++c) {
-            const float4 v = ld4<T>(base + (int64_t)c * stride);
-            const float t = tv[c];
-            b.x += v.x * t;
-            b.y += v.y * t;
-            b.z += v.z * t;
-            b.w += v.w * t;
-        }
-    };
-    auto add_scaled = [&](const float4& b, float sc) {
-        a.x += b.x * sc;
-        a.y += b.y * sc;
-        a.z += b.z * sc;
-        a.w += b.w * sc;
-    };
-    // the siblings' own interaction lists (target = the box itself), box by
-    // box with all 64 lanes: the nb lanes of box B own its quads, and every
-    // lane (cg, j) takes quad j of them and the columns cg, cg + G, ...
-    // (G = 64 / nb), with the block's multiplier values staged in LDS; the
-    // G column-group sums of each quad are added into its owner in order
-    for (int32_t B = P0; B <= Plast; ++B) {
-        const int32_t cB = uni(L.count[tl][B]);
-        const int32_t q0 = uni(L.il_ptr[tl][B]), q1 = uni(L.il_ptr[tl][B + 1]);
-        const uint64_t own = __ballot(act && P == B);
-        const int32_t lb = __ffsll((long long)own) - 1, nb = __popcll(own);
-        const int32_t rb = 4 * __builtin_amdgcn_readlane(u, lb);
-        const int G = kWave / nb, cg = lane / nb, j = lane % nb;
-        const bool on = cg < G;
-        const int32_t rj = rb + 4 * j;
-        float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int32_t q = q0; q < q1; ++q) {
-            const BDesc d = uni(bil[q]);
-            if (d.cols == 0) continue;
-            const bool lowrank = d.cols > 0;
-            const int32_t nc = lowrank ? d.cols : -d.cols;
-            const T* base = (lowrank ? Up : Dp) + d.off + rj;
-            const float* tv = lowrank ? tpool + d.tsrc : xs + d.tsrc;
-            float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-            for (int32_t c0 = 0; c0 < nc; c0 += kB2Stage) {
-                const int32_t m = min(kB2Stage, nc - c0);
-                for (int32_t jj = lane; jj < m; jj += kWave) tst[jj] = tv[c0 + jj];
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                if (on) {
-#pragma unroll 4
-                    for (int32_t c = cg; c < m; c += G) {
-                        const float4 v = ld4<T>(base + (int64_t)(c0 + c) * cB);
-                        const float t = tst[c];
-                        e.x += v.x * t;
-                        e.y += v.y * t;
-                        e.z += v.z * t;
-                        e.w += v.w * t;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-            }
-            const float sc = lowrank ? 1.f : scale[q];
-            b.x += e.x * sc;
-            b.y += e.y * sc;
-            b.z += e.z * sc;
-            b.w += e.w * sc;
-        }
-        red4[lane] = on ? b : make_float4(0.f, 0.f, 0.f, 0.f);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        if (act && P == B) {
-            const int jo = lane - lb;
-            for (int gg = 0; gg < G; ++gg) add_scaled(red4[gg * nb + jo], 1.f);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-    }
-    // the shared ancestors
-    int32_t a_box = uni(L.parent[tl][P0]);
-    for (int l = tl - 1; l >= 1; --l) {
+    const int2 w = items[it];
+    const int32_t P = uni(w.x), rc = uni(w.y);
+    const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
+    const int32_t rows = min(S, cnt - rc);
+    constexpr int G = kWave / S;
+    const int g = G == 1 ? 0 : lane / S, r = G == 1 ? lane : lane % S;
+    const bool act = r < rows;
+    float acc = 0.f;
+    int32_t a_box = P;
+    for (int l = tl; l >= 1; --l) {
         const int32_t ab = uni(L.begin[l][a_box]), ld_m = uni(L.count[l][a_box]);
         const int32_t q0 = uni(L.il_ptr[l][a_box]), q1 = uni(L.il_ptr[l][a_box + 1]);
         for (int32_t q = q0; q < q1; ++q) {
             const BDesc d = uni(bil[q]);
-            if (!act) continue;
             if (d.cols > 0) {
-                // U is tiled by the boxes one level above the leaves: this
-                // lane's box has a cnt x k column-major tile
-                column_sweep(Up + d.off + (int64_t)d.cols * (p0 - ab) + r, cnt, (const cA*)(tpool + d.tsrc), d.cols,
-                             a);
+                // this box's tile of U: [k4 / 4 quads][cnt rows][4]
+                const int32_t k4 = (d.cols + 3) & ~3;
+                const T* base = Up + d.off + (int64_t)k4 * (p0 - ab) + (int64_t)(rc + r) * 4;
+                if (act) quad_dot<T>(acc, base, (int64_t)cnt * 4, (const cA*)(tpool + d.tsrc), d.cols, g, G);
             } else if (d.cols < 0) {
-                float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
-                column_sweep(Dp + d.off + (p0 - ab) + r, ld_m, (const cA*)(xs + d.tsrc), -d.cols, b);
-                add_scaled(b, scale[q]);
+                const T* base = Dp + d.off + (int64_t)(p0 - ab + rc + r) * 4;
+                float a = 0.f;
+                if (act) quad_dot<T>(a, base, (int64_t)ld_m * 4, (const cA*)(xs + d.tsrc), -d.cols, g, G);
+                acc += a * scale[q];
             }
         }
         a_box = uni(L.parent[l][a_box]);
     }
-    if (act) {
-        float* yo = ypart + p0 + r;
-        yo[0] = a.x;
-        if (r + 1 < cnt) yo[1] = a.y;
-        if (r + 2 < cnt) yo[2] = a.z;
-        if (r + 3 < cnt) yo[3] = a.w;
+    if constexpr (G == 1) {
+        if (act) ypart[p0 + rc + r] = acc;
+        return;
+    }
+    red[wave][lane] = act ? acc : 0.f;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rows) {
+        float sum = 0.f;
+        for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * S + lane];
+        ypart[p0 + rc + lane] = sum;
     }
 }
 
@@ -564,83 +475,48 @@ b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, A (*red)[kWave], 
     __builtin_amdgcn_wave_barrier();
 }
 
-// Phase B2 for the half pools: lane (g, rp) takes rows 2 rp, 2 rp + 1 of
-// the chunk (one 4-byte load) and the columns g, g + G, ... (G = 64 / row
-// pairs); same sums and order as the FP64 form.
+// Phase B2 on the half pools: one wave per chunk of at most S2 rows of a
+// leaf box; lane (g, r) owns row r and the column quads g, g + G, ... (G =
+// 64 / rows) of the leaf's near blocks and its own interaction-list blocks
+// (each one tile of cnt rows); same sums and order as the FP64 form.
 template <typename T>
 __device__ __forceinline__ void
-b2_item_h2(int32_t X, int32_t rc, int32_t S2, int wave, int lane, float (*red2)[2 * kWave], int kappa,
-           const LevelPtrs& L,
-           const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
-           const T* __restrict__ Up, const T* __restrict__ Dp, const float* __restrict__ tpool,
-           const float* __restrict__ xs, float* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
+b2_item_q(int32_t X, int32_t rc, int32_t S2, int wave, int lane, float (*red)[kWave], int kappa, const LevelPtrs& L,
+          const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
+          const T* __restrict__ Up, const T* __restrict__ Dp, const float* __restrict__ tpool,
+          const float* __restrict__ xs, float* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
 {
     const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
     const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
     const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
     const int32_t rows = min(S2, cnt - rc);
-    const int P = (rows + 1) >> 1;
-    const int G = kWave / P, g = lane / P, rp = lane % P;
+    const int G = kWave / rows, g = lane / rows, r = lane % rows;
     const bool act = g < G;
-    float a0 = 0.f, a1 = 0.f;
+    const int64_t qs = (int64_t)cnt * 4, ro = (int64_t)(rc + r) * 4;
+    float acc = 0.f;
     for (int32_t q = n0; q < n1; ++q) {
         const BDesc d = uni(bnear[q]);
-        const T* base = Dp + d.off + rc + 2 * rp;
-        const float* tv = xs + d.tsrc;
-        float b0 = 0.f, b1 = 0.f;
-        if (act) {
-#pragma unroll 4
-            for (int32_t j = g; j < -d.cols; j += G) {
-                const float2 v = ld2<T>(base + (int64_t)j * cnt);
-                const float xv = tv[j];
-                b0 += v.x * xv;
-                b1 += v.y * xv;
-            }
-        }
-        const float sc = scale[n_il + q];
-        a0 += b0 * sc;
-        a1 += b1 * sc;
+        float a = 0.f;
+        if (act) quad_dot<T>(a, Dp + d.off + ro, qs, xs + d.tsrc, -d.cols, g, G);
+        acc += a * scale[n_il + q];
     }
     for (int32_t q = q0; q < q1; ++q) {
         const BDesc d = uni(bil[q]);
         if (d.cols > 0) {
-            const T* base = Up + d.off + rc + 2 * rp;
-            const float* tv = tpool + d.tsrc;
-            if (act) {
-#pragma unroll 4
-                for (int32_t c = g; c < d.cols; c += G) {
-                    const float2 v = ld2<T>(base + (int64_t)c * cnt);
-                    const float t = tv[c];
-                    a0 += v.x * t;
-                    a1 += v.y * t;
-                }
-            }
+            if (act) quad_dot<T>(acc, Up + d.off + ro, qs, tpool + d.tsrc, d.cols, g, G);
         } else if (d.cols < 0) {
-            const T* base = Dp + d.off + rc + 2 * rp;
-            const float* tv = xs + d.tsrc;
-            float b0 = 0.f, b1 = 0.f;
-            if (act) {
-#pragma unroll 4
-                for (int32_t j = g; j < -d.cols; j += G) {
-                    const float2 v = ld2<T>(base + (int64_t)j * cnt);
-                    const float xv = tv[j];
-                    b0 += v.x * xv;
-                    b1 += v.y * xv;
-                }
-            }
-            const float sc = scale[q];
-            a0 += b0 * sc;
-            a1 += b1 * sc;
+            float a = 0.f;
+            if (act) quad_dot<T>(a, Dp + d.off + ro, qs, xs + d.tsrc, -d.cols, g, G);
+            acc += a * scale[q];
         }
     }
-    red2[wave][2 * lane] = act ? a0 : 0.f;
-    red2[wave][2 * lane + 1] = act ? a1 : 0.f;
+    red[wave][lane] = act ? acc : 0.f;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
     if (lane < rows) {
-        float s = 0.f;
-        for (int gg = 0; gg < G; ++gg) s += red2[wave][2 * (gg * P + (lane >> 1)) + (lane & 1)];
-        yleaf[r0 + rc + lane] = s;
+        float sum = 0.f;
+        for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * rows + lane];
+        yleaf[r0 + rc + lane] = sum;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -663,8 +539,7 @@ __device__ __forceinline__ int32_t xcd_sub(int32_t w, int32_t w0, int32_t n)
 
 // Phase B, both halves in one launch: the first nb1 workgroups do phase-B1
 // items (ancestor levels, into ypart: slices of a box one level above the
-// leaves, or for the half pools' 64-row form runs of sibling boxes from
-// h_items), the next nb2 do phase-B2 leaf chunks (leaf level and near
+// leaves), the next nb2 do phase-B2 leaf chunks (leaf level and near
 // field, into yleaf).  The two halves write different
 // arrays and do not depend on each other; the latency-bound leaf work is
 // dispatched as the ancestor work drains, filling its tail.
@@ -674,31 +549,27 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
          const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
          const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
          A* __restrict__ ypart, A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il,
-         const int2* __restrict__ b2items, int32_t nb2items, int32_t b2_rows, const int4* __restrict__ h_items)
+         const int2* __restrict__ b2items, int32_t nb2items, int32_t b2_rows)
 {
     __shared__ A red[4][kWave];
-    __shared__ A tst[4][kB2Stage];
+    __shared__ A tst[4][kHalf ? 1 : kB2Stage];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t w = blockIdx.x;
     if (w < nb1) {
         const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
         if (it < nitems) {
-            if constexpr (kHalf && S == kWave) {
-                __shared__ float4 red4[4][kWave];
-                b1_item_h4<T>(it, lane, tst[wave], red4[wave], h_items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart,
-                              scale);
-            } else {
+            if constexpr (kHalf)
+                b1_item_q<T, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
+            else
                 b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
-            }
         }
     } else {
         const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
         if (it < nb2items) {
             const int2 c = b2items[it];
             if constexpr (kHalf) {
-                __shared__ float red2[4][2 * kWave];
-                b2_item_h2<T>(uni(c.x), uni(c.y), b2_rows, wave, lane, red2, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool, xs,
-                              yleaf, scale, n_il);
+                b2_item_q<T>(uni(c.x), uni(c.y), b2_rows, wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool,
+                             xs, yleaf, scale, n_il);
             } else {
                 b2_item<T, A, kHalf>(uni(c.x), uni(c.y), b2_rows, wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up,
                                      Dp, tpool, xs, yleaf, scale, n_il);
@@ -888,35 +759,10 @@ void finalize(Handle& H, hipStream_t s)
         for (int32_t rc = 0; rc < LL.h_count[x]; rc += S2) b2.push_back(make_int2((int32_t)x, rc));
     H.n_b2 = (int64_t)b2.size();
     upload_vec(H.b2items, b2, s);
-    // half-precision phase-B1 work: runs of up to 64 row quads over the
-    // boxes one level above the leaves that share a parent
-    std::vector<int4> b1h;
-    if (kappa >= 2) {
-        const Level& T = H.lev[kappa - 1];
-        for (int64_t p = 0; p < T.nbox;) {
-            int64_t q = p;
-            while (q < T.nbox && T.h_parent[q] == T.h_parent[p]) ++q;
-            int32_t used = 0, s_box = 0, s_u = 0;
-            for (int64_t bx = p; bx < q; ++bx) {
-                const int32_t nq = (T.h_count[bx] + 3) / 4;
-                for (int32_t u = 0; u < nq;) {
-                    if (used == 0) { s_box = (int32_t)bx; s_u = u; }
-                    const int32_t take = std::min(nq - u, kWave - used);
-                    used += take;
-                    u += take;
-                    if (used == kWave) { b1h.push_back(make_int4(s_box, s_u, used, 0)); used = 0; }
-                }
-            }
-            if (used) b1h.push_back(make_int4(s_box, s_u, used, 0));
-            p = q;
-        }
-    }
     H.n_b1 = (int64_t)b1.size();
     H.n_b1s = (int64_t)b1s.size();
-    H.n_b1h = (int64_t)b1h.size();
     upload_vec(H.b1items, b1, s);
     upload_vec(H.b1s_items, b1s, s);
-    upload_vec(H.b1h_items, b1h, s);
     H.flops = flops;
     H.t_elems = toff; H.p_elems = poff;
     // algorithmic bytes per kernel: every stored value and vector touched once
@@ -1028,7 +874,7 @@ void finalize_adaptive(Handle& H, hipStream_t s)
         for (int32_t rc = 0; rc < H.h_leaf_count[x]; rc += kWave) ad.push_back(make_int2((int32_t)x, rc));
     H.n_ad_items = (int64_t)ad.size();
     upload_vec(H.ad_items, ad, s);
-    H.n_b1 = H.n_b1s = H.n_b1h = H.n_b2 = 0;
+    H.n_b1 = H.n_b1s = H.n_b2 = 0;
     H.flops = flops;
     H.t_elems = toff; H.p_elems = poff;
     const double nvec = (double)H.n;
@@ -1130,16 +976,17 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
             return;
         }
     }
-    // the half pools' 64-row form walks runs of row quads (b1h_items)
-    const bool quads = kHalf && H.b1_rows == kWave;
-    const int32_t ni = (int32_t)(quads ? H.n_b1h : H.n_b1s);
+    // the half pools have descriptors of their own (quad-layout offsets)
+    const BDesc* bil = kHalf ? H.bil16.p : H.bil.p;
+    const BDesc* bnear = kHalf ? H.bnear16.p : H.bnear.p;
+    const int32_t ni = (int32_t)H.n_b1s;
     const int32_t nb1 = (ni + 3) / 4, nb2 = (int32_t)((H.n_b2 + 3) / 4);
     A* yl = yp + n;   // the work vector holds ypart then yleaf
 #define H2D_PHASE_B(SR)                                                                                              \
     k_phaseB<T, A, kHalf, SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, \
-                                                                   H.bnear.p, H.bil.p, U, D, tp, xs, yp, yl,         \
+                                                                   bnear, bil, U, D, tp, xs, yp, yl,                 \
                                                                    H.scale16.p, H.n_il, H.b2items.p, (int32_t)H.n_b2, \
-                                                                   H.b2_rows, H.b1h_items.p)
+                                                                   H.b2_rows)
     if (H.b1_rows == 16) H2D_PHASE_B(16);
     else if (H.b1_rows == 32) H2D_PHASE_B(32);
     else H2D_PHASE_B(64);

@@ -23,6 +23,7 @@
 #include "h2d_impl.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace h2d {
 
@@ -410,6 +411,70 @@ __device__ __forceinline__ void mm_tile(typename MrT<T>::V4 (&acc)[4], const T* 
     else mm_tiles<T, 1>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
 }
 
+// The 4 half values of one aligned 8-byte group, widened to FP32.
+template <typename T>
+__device__ __forceinline__ f4 quad_f32(uint64_t w)
+{
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    if constexpr (std::is_same<T, __half>::value)
+        return f4{__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
+                  __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
+                  __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu))),
+                  __half2float(__ushort_as_half((unsigned short)(hi >> 16)))};
+    else
+        return f4{__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
+                  __uint_as_float(hi & 0xffff0000u)};
+}
+
+// The half pools' tiles are stored as [column quads][rows][4] (the 4 values
+// of one row in 4 consecutive columns form one aligned 8-byte group,
+// columns padded with zeros to a multiple of 4).  acc[t] (rows 16 t .. 16 t
+// + 15, t < NT) += A (rows x K) B (K x 16), A(i, c) = Ab[(c / 4) qs + 4 i +
+// c % 4] (qs = 4 x the tile's rows), B(c, r) = bs Bb[c ldb + r].  A step
+// takes 16 columns: lane group lk loads the group of columns c0 + 4 lk ..
+// c0 + 4 lk + 3 of its row, and instruction u = 0..3 takes column c0 + 4 lk
+// + u as its k index lk.  Groups past the last one re-read the last (their
+// B values are zero), rows past the tile's end re-read its last row.
+template <typename T, int NT>
+__device__ __forceinline__ void mm_tiles_q(f4 (&acc)[4], const T* __restrict__ Ab, int64_t qs, int32_t rows,
+                                           const float* __restrict__ Bb, int64_t ldb, int32_t K, float bs, int lane)
+{
+    const int li = lane % 16, lk = lane / 16;
+    const int32_t nq = (K + 3) >> 2;
+    int64_t ro[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) ro[t] = (int64_t)min(16 * t + li, rows - 1) * 4;
+    for (int32_t c0 = 0; c0 < K; c0 += 16) {
+        const T* qa = Ab + (int64_t)min((c0 >> 2) + lk, nq - 1) * qs;
+        uint64_t w[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) w[t] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(qa + ro[t]));
+        float b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t c = c0 + 4 * lk + u;
+            b[u] = c < K ? Bb[(int64_t)c * ldb + li] * bs : 0.f;
+        }
+        f4 a[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) a[t] = quad_f32<T>(w[t]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[u], acc[t], 0, 0, 0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void mm_tile_q(f4 (&acc)[4], const T* __restrict__ Ab, int64_t qs, int32_t rows,
+                                          const float* __restrict__ Bb, int64_t ldb, int32_t K, float bs, int lane)
+{
+    if (rows > 48) mm_tiles_q<T, 4>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
+    else if (rows > 32) mm_tiles_q<T, 3>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
+    else if (rows > 16) mm_tiles_q<T, 2>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
+    else mm_tiles_q<T, 1>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
+}
+
 // Scale of a dense block of the half pools (index into the scale table).
 template <typename T>
 __device__ __forceinline__ typename MrT<T>::A dense_scale(const float* __restrict__ scale, int64_t i)
@@ -446,12 +511,23 @@ b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_
             const BDesc d = bil[q];
             const int64_t off = uni_l(d.off);
             const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
-            if (cols > 0)
-                mm_tile<T>(acc, Up + off + (int64_t)cols * (p0 - ab) + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR,
-                           cols, (A)1, lane);
-            else if (cols < 0)
-                mm_tile<T>(acc, Dp + off + (p0 - ab) + rc, ld_m, rows, xs + (int64_t)tsrc * kR, kR, -cols,
-                           dense_scale<T>(scale, q), lane);
+            if constexpr (sizeof(T) == 2) {
+                // this box's tile of U: k4 / 4 groups of cnt rows; a dense
+                // block: one tile of ld_m rows
+                if (cols > 0)
+                    mm_tile_q<T>(acc, Up + off + (int64_t)((cols + 3) & ~3) * (p0 - ab) + (int64_t)rc * 4,
+                                 (int64_t)cnt * 4, rows, tpool + (int64_t)tsrc * kR, kR, cols, 1.f, lane);
+                else if (cols < 0)
+                    mm_tile_q<T>(acc, Dp + off + (int64_t)(p0 - ab + rc) * 4, (int64_t)ld_m * 4, rows,
+                                 xs + (int64_t)tsrc * kR, kR, -cols, scale[q], lane);
+            } else {
+                if (cols > 0)
+                    mm_tile<T>(acc, Up + off + (int64_t)cols * (p0 - ab) + rc, cnt, rows, tpool + (int64_t)tsrc * kR,
+                               kR, cols, (A)1, lane);
+                else if (cols < 0)
+                    mm_tile<T>(acc, Dp + off + (p0 - ab) + rc, ld_m, rows, xs + (int64_t)tsrc * kR, kR, -cols,
+                               dense_scale<T>(scale, q), lane);
+            }
         }
         a_box = uni_i(gp<const int32_t>((uint64_t)Lparent[l])[a_box]);
     }
@@ -486,20 +562,38 @@ b2_mr(int32_t X, int lane, const int32_t* __restrict__ begin, const int32_t* __r
         V4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
-        for (int32_t q = n0; q < n1; ++q) {
-            const BDesc d = bnear[q];
-            mm_tile<T>(acc, Dp + uni_l(d.off) + rc, cnt, rows, xs + (int64_t)uni_i(d.tsrc) * kR, kR, -uni_i(d.cols),
-                       dense_scale<T>(scale, (int64_t)n_il + q), lane);
-        }
-        for (int32_t q = q0; q < q1; ++q) {
-            const BDesc d = bil[q];
-            const int64_t off = uni_l(d.off);
-            const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
-            if (cols > 0)
-                mm_tile<T>(acc, Up + off + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR, cols, (A)1, lane);
-            else if (cols < 0)
-                mm_tile<T>(acc, Dp + off + rc, cnt, rows, xs + (int64_t)tsrc * kR, kR, -cols, dense_scale<T>(scale, q),
-                           lane);
+        if constexpr (sizeof(T) == 2) {
+            // every block here is one tile of cnt rows
+            auto blk = [&](const T* P, const A* Bb, int32_t K, A bs) {
+                mm_tile_q<T>(acc, P + (int64_t)rc * 4, (int64_t)cnt * 4, rows, Bb, kR, K, bs, lane);
+            };
+            for (int32_t q = n0; q < n1; ++q) {
+                const BDesc d = bnear[q];
+                blk(Dp + uni_l(d.off), xs + (int64_t)uni_i(d.tsrc) * kR, -uni_i(d.cols), scale[(int64_t)n_il + q]);
+            }
+            for (int32_t q = q0; q < q1; ++q) {
+                const BDesc d = bil[q];
+                const int64_t off = uni_l(d.off);
+                const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
+                if (cols > 0) blk(Up + off, tpool + (int64_t)tsrc * kR, cols, 1.f);
+                else if (cols < 0) blk(Dp + off, xs + (int64_t)tsrc * kR, -cols, scale[q]);
+            }
+        } else {
+            for (int32_t q = n0; q < n1; ++q) {
+                const BDesc d = bnear[q];
+                mm_tile<T>(acc, Dp + uni_l(d.off) + rc, cnt, rows, xs + (int64_t)uni_i(d.tsrc) * kR, kR, -uni_i(d.cols),
+                           dense_scale<T>(scale, (int64_t)n_il + q), lane);
+            }
+            for (int32_t q = q0; q < q1; ++q) {
+                const BDesc d = bil[q];
+                const int64_t off = uni_l(d.off);
+                const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
+                if (cols > 0)
+                    mm_tile<T>(acc, Up + off + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR, cols, (A)1, lane);
+                else if (cols < 0)
+                    mm_tile<T>(acc, Dp + off + rc, cnt, rows, xs + (int64_t)tsrc * kR, kR, -cols,
+                               dense_scale<T>(scale, q), lane);
+            }
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -708,6 +802,8 @@ static void ensure_mr16(Handle& H, hipStream_t s)
         I[h].xs = addr(H.xs_mr32.p); I[h].tp = addr(H.tp_mr32.p); I[h].pp = addr(H.pp_mr32.p);
         I[h].yp = addr(H.yp_mr32.p); I[h].yl = addr(H.yl_mr32.p);
         I[h].blks = addr(H.mr_blks16.p);
+        I[h].bil = addr(H.bil16.p);
+        I[h].bnear = addr(H.bnear16.p);
         I[h].scale = addr(H.scale16.p);
         I[h].diag = addr(H.diag32.p);
     }
