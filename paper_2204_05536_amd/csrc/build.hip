@@ -1381,6 +1381,78 @@ __global__ void k_half_v4(const HalfVJob* jobs, const double* src, T* dst)
     }
 }
 
+// The phase-B tables of the half pools.  Table 1, per box P one level
+// above the leaves: the 4-column groups of P's tile of every block whose
+// target is P or one of its ancestors, level by level from P up, blocks in
+// table order.  Table 2, per leaf X: its near blocks, then its own
+// interaction-list blocks.  A row slice of the box sums its table's groups
+// in order.
+static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16, const std::vector<float>& sc,
+                              hipStream_t s)
+{
+    const int kappa = H.kappa;
+    std::vector<QEnt> t1, t2;
+    std::vector<int32_t> p1(1, 0), p2(1, 0);
+    // the groups of one tile: row 0 of its slice at e0 (elements), groups qs
+    // elements apart, ncols columns whose multiplier values start at src0
+    auto put = [&](std::vector<QEnt>& t, int64_t e0, int64_t qs, int32_t ncols, int32_t src0, bool dense, float scale) {
+        for (int32_t u = 0; 4 * u < ncols; ++u) {
+            const int64_t e = e0 + (int64_t)u * qs;
+            t.push_back(QEnt{(uint32_t)(e >> 2), dense ? ~(src0 + 4 * u) : src0 + 4 * u, dense ? scale : 1.0f,
+                             std::min(4, ncols - 4 * u)});
+        }
+    };
+    auto close = [&](std::vector<int32_t>& p, const std::vector<QEnt>& t) {
+        if (t.size() > (size_t)INT32_MAX) fail(H2D_EUNSUPPORTED, "phase-B table above 2^31 entries");
+        p.push_back((int32_t)t.size());
+    };
+    if (kappa >= 2) {
+        const Level& T = H.lev[kappa - 1];
+        for (int64_t P = 0; P < T.nbox; ++P) {
+            const int32_t p0 = T.h_begin[P], cnt = T.h_count[P];
+            int32_t a_box = (int32_t)P;
+            for (int l = kappa - 1; l >= 1; --l) {
+                const Level& L = H.lev[l];
+                const int32_t ab = L.h_begin[a_box], ldm = L.h_count[a_box];
+                for (int32_t q = L.h_il_ptr[a_box]; q < L.h_il_ptr[a_box + 1]; ++q) {
+                    if (H.h_il_kind[q] == kDense) {
+                        const int32_t sb = H.h_il_src[q];
+                        put(t1, H.h_il_off16[q] + (int64_t)(p0 - ab) * 4, (int64_t)ldm * 4, L.h_count[sb], L.h_begin[sb],
+                            true, sc[q]);
+                    } else if (H.h_il_k[q] > 0) {
+                        const int32_t k = H.h_il_k[q];
+                        put(t1, H.h_il_off16[q] + (int64_t)((k + 3) & ~3) * (p0 - ab), (int64_t)cnt * 4, k,
+                            H.h_il_toff[q], false, 1.0f);
+                    }
+                }
+                a_box = L.h_parent[a_box];
+            }
+            close(p1, t1);
+        }
+    }
+    const Level& LL = H.lev[kappa];
+    for (int64_t X = 0; X < LL.nbox; ++X) {
+        const int64_t qs = (int64_t)LL.h_count[X] * 4;
+        for (int32_t q = H.h_near_ptr[X]; q < H.h_near_ptr[X + 1]; ++q) {
+            const int32_t y = H.h_near_src[q];
+            put(t2, near_off16[q], qs, LL.h_count[y], LL.h_begin[y], true, sc[H.n_il + q]);
+        }
+        for (int32_t q = LL.h_il_ptr[X]; q < LL.h_il_ptr[X + 1]; ++q) {
+            if (H.h_il_kind[q] == kDense) {
+                const int32_t sb = H.h_il_src[q];
+                put(t2, H.h_il_off16[q], qs, LL.h_count[sb], LL.h_begin[sb], true, sc[q]);
+            } else if (H.h_il_k[q] > 0) {
+                put(t2, H.h_il_off16[q], qs, H.h_il_k[q], H.h_il_toff[q], false, 1.0f);
+            }
+        }
+        close(p2, t2);
+    }
+    upload(H.qp1, p1, s);
+    upload(H.qt1, t1, s);
+    upload(H.qp2, p2, s);
+    upload(H.qt2, t2, s);
+}
+
 void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
 {
     const bool f16 = mask & H2D_PREC_BIT(H2D_P_FP16), b16 = mask & H2D_PREC_BIT(H2D_P_BF16);
@@ -1390,7 +1462,6 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     // gets quad-layout offsets of its own, and the descriptors the half
     // product kernels read
     std::vector<HalfJob> jobs;
-    std::vector<BDesc> bi(H.n_il);
     H.h_il_off16.assign(H.n_il, 0);
     int64_t uo = 0, dof = 0;
     for (int64_t q = 0; q < H.n_il; ++q) {
@@ -1400,33 +1471,29 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         if (H.h_il_kind[q] == kDense) {
             H.h_il_off16[q] = dof;
             jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, 0});
-            bi[q] = BDesc{dof, -nn, L.h_begin[H.h_il_src[q]]};
             dof += (int64_t)mm * ((nn + 3) & ~3);
         } else {
             const int32_t k = H.h_il_k[q];
             const int32_t tiled = H.h_il_level[q] <= kappa - 1 ? 1 : 0;
             H.h_il_off16[q] = uo;
             jobs.push_back(HalfJob{H.h_il_off[q], uo, mm, k, tiled, 0, row0, 0});
-            bi[q] = BDesc{uo, k, std::max(H.h_il_toff[q], 0)};
             uo += (int64_t)mm * ((k + 3) & ~3);
         }
     }
     const Level& LL = H.lev[kappa];
-    std::vector<BDesc> bn(H.h_near_src.size());
-    H.h_near_off16.assign(H.h_near_src.size(), 0);
+    std::vector<int64_t> near_off16(H.h_near_src.size(), 0);
     for (int64_t x = 0; x < LL.nbox; ++x)
         for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q) {
             const int32_t y = H.h_near_src[q];
-            H.h_near_off16[q] = dof;
+            near_off16[q] = dof;
             jobs.push_back(HalfJob{H.h_near_off[q], dof, LL.h_count[x], LL.h_count[y], 0, y == (int32_t)x ? 1 : 0,
                                    LL.h_begin[x], 0});
-            bn[q] = BDesc{dof, -LL.h_count[y], LL.h_begin[y]};
             dof += (int64_t)LL.h_count[x] * ((LL.h_count[y] + 3) & ~3);
         }
     H.u16_elems = uo;
     H.d16_elems = dof;
-    upload(H.bil16, bi, s);
-    upload(H.bnear16, bn, s);
+    if (((uo + kHalfSlack) >> 2) > (int64_t)UINT32_MAX || ((dof + kHalfSlack) >> 2) > (int64_t)UINT32_MAX)
+        fail(H2D_EUNSUPPORTED, "half-precision pools above 2^34 values are not supported");
     // U and D pools need per-block scales; split the jobs per pool
     std::vector<HalfJob> ujobs, djobs;
     std::vector<int64_t> uidx, didx;
@@ -1508,6 +1575,7 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     for (size_t q = 0; q < uidx.size(); ++q) sc[uidx[q]] = hsu[q];
     for (size_t q = 0; q < didx.size(); ++q) sc[didx[q]] = hsd[q];
     upload(H.scale16, sc, s);
+    build_quad_tables(H, near_off16, sc, s);
     HIPCK(hipStreamSynchronize(s));
     H.prec_mask |= mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16));
 }

@@ -104,6 +104,21 @@ struct BDesc {
     int32_t tsrc;
 };
 
+// One entry of a phase-B table of the half pools: a 4-column group of one
+// tile (half U and D tiles are stored as [column quads][rows][4]), as one
+// row slice of a box multiplies it.  Row i of the slice's box reads the
+// group's 4 values at pool + 4 q + 4 i.
+//   src >= 0: low rank; U pool, multiplier values t pool + src ..
+//   src < 0:  dense; D pool, multiplier values x (tree order) + ~src ..
+//   sc:       the dense block's scale (1 for low rank)
+//   nv:       columns of the group inside the block, 1 .. 4
+struct QEnt {
+    uint32_t q;
+    int32_t src;
+    float sc;
+    int32_t nv;
+};
+
 // Phase-A work item: t(out) = V(rows j0..j1)^T x(col0 + j0 .. col0 + j1).
 // V is row-major n x k starting at V pool + voff.
 struct ADesc {
@@ -152,6 +167,7 @@ struct MRInst {
     uint64_t lvl;                     // const int32_t* const*: begin, count, parent, il_ptr (kMaxLevel + 1 each)
     uint64_t scale, diag;             // half pools: const float* block scales (IL blocks, then near blocks) and
                                       // self-block diagonal (tree order); unused in FP64
+    uint64_t qp1, qt1, qp2, qt2;      // half pools: phase-B tables (CSR pointers, entries); unused in FP64
     int32_t n, kappa, has_b1, n_il;
 };
 // Right-hand sides of one instance: x and y column-major, leading dimension ld.
@@ -243,11 +259,13 @@ struct Handle {
     DBuf<__half> U16, V16, D16;
     DBuf<__hip_bfloat16> Ub16, Vb16, Db16;
     // half U and D pools in the quad layout (every tile [column quads][rows][4],
-    // columns padded to a multiple of 4): offsets of their own, and the
-    // descriptors of the half phase-B kernels pointing there
-    std::vector<int64_t> h_il_off16, h_near_off16;
+    // columns padded to a multiple of 4) at offsets of their own, and the
+    // phase-B tables: per box one level above the leaves (qt1) and per leaf
+    // (qt2), every 4-column group its row slices multiply, in summation order
+    std::vector<int64_t> h_il_off16;
     int64_t u16_elems = 0, d16_elems = 0;
-    DBuf<BDesc> bil16, bnear16;
+    DBuf<int32_t> qp1, qp2;
+    DBuf<QEnt> qt1, qt2;
     DBuf<float> scale16;     // per-block scale of the half pools (IL blocks, then near blocks)
     DBuf<float> diag32;      // self-block diagonal (tree order) for the half pools
     int64_t max_rank = 0, sum_rank = 0, n_il_dense = 0;

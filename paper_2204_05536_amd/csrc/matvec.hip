@@ -318,99 +318,6 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
     }
 }
 
-// The half pools' U and D tiles are stored as [column quads][rows][4]: the
-// 4 values of one row in 4 consecutive columns form one aligned 8-byte
-// group (columns padded with zeros to a multiple of 4).
-// acc += sum over quads u = g, g + G, ... < ceil(n / 4) of the 4 values at
-// base + u qstride times w[4 u .. 4 u + 3] (w past n taken as 0: those
-// belong to other blocks or lie past the vector's end).  The loads of 4
-// quads are issued before any is used; columns are added in increasing
-// order.
-template <typename T, typename W>
-__device__ __forceinline__ void quad_dot(float& acc, const T* base, int64_t qstride, const W* w, int32_t n, int g,
-                                         int G)
-{
-    const int32_t nq = (n + 3) >> 2;
-    for (int32_t u0 = 0; u0 < nq; u0 += 4 * G) {
-        float4 v[4], t[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int32_t u = u0 + j * G + g, c = 4 * u;
-            v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-            t[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (u < nq) {
-                v[j] = ld4v<T>(base + (int64_t)u * qstride);
-                t[j].x = w[c];
-                t[j].y = c + 1 < n ? (float)w[c + 1] : 0.f;
-                t[j].z = c + 2 < n ? (float)w[c + 2] : 0.f;
-                t[j].w = c + 3 < n ? (float)w[c + 3] : 0.f;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc += v[j].x * t[j].x;
-            acc += v[j].y * t[j].y;
-            acc += v[j].z * t[j].z;
-            acc += v[j].w * t[j].w;
-        }
-    }
-}
-
-// Phase B1 on the half pools: lane (g, r) owns row r of an S-row slice of a
-// box one level above the leaves and the column quads g, g + G, ... (G =
-// 64 / S) of every block of that box and of its ancestors: each load is
-// one row's 4 columns, a wave load 64 rows x 4 columns (512 bytes, as in
-// the FP64 form).  The G column-group sums are added in a fixed order.
-template <typename T, int S>
-__device__ __forceinline__ void
-b1_item_q(int32_t it, int wave, int lane, float (*red)[kWave], const int2* __restrict__ items, int tl,
-          const LevelPtrs& L, const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
-          const float* __restrict__ tpool, const float* __restrict__ xs, float* __restrict__ ypart,
-          const float* __restrict__ scale)
-{
-    using cA = ConstAS<float>;
-    const int2 w = items[it];
-    const int32_t P = uni(w.x), rc = uni(w.y);
-    const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
-    const int32_t rows = min(S, cnt - rc);
-    constexpr int G = kWave / S;
-    const int g = G == 1 ? 0 : lane / S, r = G == 1 ? lane : lane % S;
-    const bool act = r < rows;
-    float acc = 0.f;
-    int32_t a_box = P;
-    for (int l = tl; l >= 1; --l) {
-        const int32_t ab = uni(L.begin[l][a_box]), ld_m = uni(L.count[l][a_box]);
-        const int32_t q0 = uni(L.il_ptr[l][a_box]), q1 = uni(L.il_ptr[l][a_box + 1]);
-        for (int32_t q = q0; q < q1; ++q) {
-            const BDesc d = uni(bil[q]);
-            if (d.cols > 0) {
-                // this box's tile of U: [k4 / 4 quads][cnt rows][4]
-                const int32_t k4 = (d.cols + 3) & ~3;
-                const T* base = Up + d.off + (int64_t)k4 * (p0 - ab) + (int64_t)(rc + r) * 4;
-                if (act) quad_dot<T>(acc, base, (int64_t)cnt * 4, (const cA*)(tpool + d.tsrc), d.cols, g, G);
-            } else if (d.cols < 0) {
-                const T* base = Dp + d.off + (int64_t)(p0 - ab + rc + r) * 4;
-                float a = 0.f;
-                if (act) quad_dot<T>(a, base, (int64_t)ld_m * 4, (const cA*)(xs + d.tsrc), -d.cols, g, G);
-                acc += a * scale[q];
-            }
-        }
-        a_box = uni(L.parent[l][a_box]);
-    }
-    if constexpr (G == 1) {
-        if (act) ypart[p0 + rc + r] = acc;
-        return;
-    }
-    red[wave][lane] = act ? acc : 0.f;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    if (lane < rows) {
-        float sum = 0.f;
-        for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * S + lane];
-        ypart[p0 + rc + lane] = sum;
-    }
-}
-
 // Phase B2: the leaf level.  One wave per 64-row chunk of a leaf box X
 // (leaves above 64 points give several items): its dense near blocks and
 // its own interaction-list blocks, into the leaf-level sum.  A chunk has at
@@ -475,53 +382,6 @@ b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, A (*red)[kWave], 
     __builtin_amdgcn_wave_barrier();
 }
 
-// Phase B2 on the half pools: one wave per chunk of at most S2 rows of a
-// leaf box; lane (g, r) owns row r and the column quads g, g + G, ... (G =
-// 64 / rows) of the leaf's near blocks and its own interaction-list blocks
-// (each one tile of cnt rows); same sums and order as the FP64 form.
-template <typename T>
-__device__ __forceinline__ void
-b2_item_q(int32_t X, int32_t rc, int32_t S2, int wave, int lane, float (*red)[kWave], int kappa, const LevelPtrs& L,
-          const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
-          const T* __restrict__ Up, const T* __restrict__ Dp, const float* __restrict__ tpool,
-          const float* __restrict__ xs, float* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
-{
-    const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
-    const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
-    const int32_t n0 = uni(near_ptr[X]), n1 = uni(near_ptr[X + 1]);
-    const int32_t rows = min(S2, cnt - rc);
-    const int G = kWave / rows, g = lane / rows, r = lane % rows;
-    const bool act = g < G;
-    const int64_t qs = (int64_t)cnt * 4, ro = (int64_t)(rc + r) * 4;
-    float acc = 0.f;
-    for (int32_t q = n0; q < n1; ++q) {
-        const BDesc d = uni(bnear[q]);
-        float a = 0.f;
-        if (act) quad_dot<T>(a, Dp + d.off + ro, qs, xs + d.tsrc, -d.cols, g, G);
-        acc += a * scale[n_il + q];
-    }
-    for (int32_t q = q0; q < q1; ++q) {
-        const BDesc d = uni(bil[q]);
-        if (d.cols > 0) {
-            if (act) quad_dot<T>(acc, Up + d.off + ro, qs, tpool + d.tsrc, d.cols, g, G);
-        } else if (d.cols < 0) {
-            float a = 0.f;
-            if (act) quad_dot<T>(a, Dp + d.off + ro, qs, xs + d.tsrc, -d.cols, g, G);
-            acc += a * scale[q];
-        }
-    }
-    red[wave][lane] = act ? acc : 0.f;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    if (lane < rows) {
-        float sum = 0.f;
-        for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * rows + lane];
-        yleaf[r0 + rc + lane] = sum;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-}
-
 // Workgroups w0 .. w0 + n - 1 of the grid -> tiles 0 .. n - 1 such that
 // the workgroups each XCD receives (workgroup ids are dealt round-robin over
 // the 8 XCDs) take one contiguous range of tiles.
@@ -552,29 +412,139 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
          const int2* __restrict__ b2items, int32_t nb2items, int32_t b2_rows)
 {
     __shared__ A red[4][kWave];
-    __shared__ A tst[4][kHalf ? 1 : kB2Stage];
+    __shared__ A tst[4][kB2Stage];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t w = blockIdx.x;
     if (w < nb1) {
         const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
-        if (it < nitems) {
-            if constexpr (kHalf)
-                b1_item_q<T, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
-            else
-                b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
-        }
+        if (it < nitems)
+            b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
     } else {
         const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
         if (it < nb2items) {
             const int2 c = b2items[it];
-            if constexpr (kHalf) {
-                b2_item_q<T>(uni(c.x), uni(c.y), b2_rows, wave, lane, red, kappa, L, near_ptr, bnear, bil, Up, Dp, tpool,
-                             xs, yleaf, scale, n_il);
-            } else {
-                b2_item<T, A, kHalf>(uni(c.x), uni(c.y), b2_rows, wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up,
-                                     Dp, tpool, xs, yleaf, scale, n_il);
-            }
+            b2_item<T, A, kHalf>(uni(c.x), uni(c.y), b2_rows, wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up,
+                                 Dp, tpool, xs, yleaf, scale, n_il);
         }
+    }
+}
+
+// The dot product of one row's 4-value group (half, widened to FP32) with
+// 4 multiplier values.
+template <typename T>
+__device__ __forceinline__ float quad_dot4(uint64_t w, float t0, float t1, float t2, float t3)
+{
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    float v0, v1, v2, v3;
+    if constexpr (std::is_same<T, __half>::value) {
+        v0 = __half2float(__ushort_as_half((unsigned short)(lo & 0xffffu)));
+        v1 = __half2float(__ushort_as_half((unsigned short)(lo >> 16)));
+        v2 = __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu)));
+        v3 = __half2float(__ushort_as_half((unsigned short)(hi >> 16)));
+    } else {
+        v0 = __uint_as_float(lo << 16);
+        v1 = __uint_as_float(lo & 0xffff0000u);
+        v2 = __uint_as_float(hi << 16);
+        v3 = __uint_as_float(hi & 0xffff0000u);
+    }
+    return v0 * t0 + v1 * t1 + v2 * t2 + v3 * t3;
+}
+
+// acc += the sum over table entries j = j0 + g, j0 + g + G, ... < j1 of the
+// entry's scale times the dot product of this lane's row of the entry's
+// 4-column group (at pool + 4 q + ro) with its multiplier values.  Eight
+// entries are loaded before any is used, so the groups of several blocks
+// are in flight together; slots past j1 re-read entry j1 - 1 and add
+// nothing.  kUni: G = 1, g = 0, every lane takes every entry (the entries
+// and multiplier values are then wave-uniform loads).  The multiplier
+// values of columns past the group's nv are taken as zero; the work
+// vectors carry slack past their ends for these reads.
+template <typename T, bool kUni>
+__device__ __forceinline__ void qt_sweep(float& acc, const QEnt* __restrict__ qt, int32_t j0, int32_t j1, int g, int G,
+                                         int64_t ro, const T* __restrict__ Up, const T* __restrict__ Dp,
+                                         const float* __restrict__ tpool, const float* __restrict__ xs)
+{
+    constexpr int NF = 8;
+    if constexpr (kUni) {
+        g = 0;
+        G = 1;
+    }
+    for (int32_t jb = j0; jb < j1; jb += NF * G) {
+        QEnt e[NF];
+        uint64_t w[NF];
+#pragma unroll
+        for (int u = 0; u < NF; ++u) e[u] = qt[min(jb + u * G + g, j1 - 1)];
+#pragma unroll
+        for (int u = 0; u < NF; ++u) {
+            const T* pool = e[u].src >= 0 ? Up : Dp;
+            w[u] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(pool + ((int64_t)e[u].q << 2) + ro));
+        }
+#pragma unroll
+        for (int u = 0; u < NF; ++u) {
+            const float* tb = e[u].src >= 0 ? tpool + e[u].src : xs + ~e[u].src;
+            const int32_t nv = e[u].nv;
+            const float t0 = tb[0], t1 = tb[1], t2 = tb[2], t3 = tb[3];
+            const float d = quad_dot4<T>(w[u], t0, nv > 1 ? t1 : 0.f, nv > 2 ? t2 : 0.f, nv > 3 ? t3 : 0.f);
+            // a slot past j1 adds d * 0 (d is computed either way, so the
+            // slot's loads are not moved behind a branch)
+            acc = fmaf(d, jb + u * G + g < j1 ? e[u].sc : 0.f, acc);
+        }
+    }
+}
+
+// Phase B on the half pools, both halves in one launch.  B1: one wave per
+// 64-row slice of a box P one level above the leaves; lane r owns row r and
+// walks P's table (the groups of every block of P and its ancestors).  B2:
+// one wave per chunk of at most S2 rows of a leaf X; lane (g, r) owns row r
+// and the table entries g, g + G, ... (G = 64 / rows) of X's table (near
+// blocks, then X's own interaction-list blocks); the G sums of a row are
+// added in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_phaseB_half(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa, LevelPtrs L,
+              const int32_t* __restrict__ qp1, const QEnt* __restrict__ qt1, const int32_t* __restrict__ qp2,
+              const QEnt* __restrict__ qt2, const T* __restrict__ Up, const T* __restrict__ Dp,
+              const float* __restrict__ tpool, const float* __restrict__ xs, float* __restrict__ ypart,
+              float* __restrict__ yleaf, const int2* __restrict__ b2items, int32_t nb2items, int32_t S2)
+{
+    __shared__ float red[4][kWave];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t w = blockIdx.x;
+    if (w < nb1) {
+        const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
+        if (it >= nitems) return;
+        const int2 wi = items[it];
+        const int32_t P = uni(wi.x), rc = uni(wi.y);
+        const int32_t p0 = uni(L.begin[kappa - 1][P]), cnt = uni(L.count[kappa - 1][P]);
+        const int32_t rows = min(kWave, cnt - rc);
+        float acc = 0.f;
+        qt_sweep<T, true>(acc, qt1, uni(qp1[P]), uni(qp1[P + 1]), 0, 1, (int64_t)(rc + min(lane, rows - 1)) * 4, Up, Dp,
+                          tpool, xs);
+        if (lane < rows) ypart[p0 + rc + lane] = acc;
+        return;
+    }
+    const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
+    if (it >= nb2items) return;
+    const int2 c = b2items[it];
+    const int32_t X = uni(c.x), rc = uni(c.y);
+    const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
+    const int32_t rows = min(S2, cnt - rc);
+    const int32_t j0 = uni(qp2[X]), j1 = uni(qp2[X + 1]);
+    float acc = 0.f;
+    if (rows > kWave / 2) {
+        qt_sweep<T, true>(acc, qt2, j0, j1, 0, 1, (int64_t)(rc + min(lane, rows - 1)) * 4, Up, Dp, tpool, xs);
+        if (lane < rows) yleaf[r0 + rc + lane] = acc;
+        return;
+    }
+    const int G = kWave / rows, g = lane / rows, r = lane % rows;
+    if (g < G) qt_sweep<T, false>(acc, qt2, j0, j1, g, G, (int64_t)(rc + r) * 4, Up, Dp, tpool, xs);
+    red[wave][lane] = g < G ? acc : 0.f;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rows) {
+        float sum = 0.f;
+        for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * rows + lane];
+        yleaf[r0 + rc + lane] = sum;
     }
 }
 
@@ -905,9 +875,11 @@ void ensure_workspace(Handle& H, int nrhs)
     H.tpool.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
     H.ppool.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     if (H.prec_mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16))) {
-        H.xs32.alloc((size_t)n * nrhs);
+        // x and t carry 4 values of slack: the half phase-B walks read
+        // multiplier values in fours and drop those past a block's columns
+        H.xs32.alloc((size_t)n * nrhs + 4);
         H.ypart32.alloc((size_t)2 * n * nrhs);
-        H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs);
+        H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs + 4);
         H.ppool32.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
     }
     H.ws_nrhs = nrhs;
@@ -976,21 +948,28 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
             return;
         }
     }
-    // the half pools have descriptors of their own (quad-layout offsets)
-    const BDesc* bil = kHalf ? H.bil16.p : H.bil.p;
-    const BDesc* bnear = kHalf ? H.bnear16.p : H.bnear.p;
-    const int32_t ni = (int32_t)H.n_b1s;
-    const int32_t nb1 = (ni + 3) / 4, nb2 = (int32_t)((H.n_b2 + 3) / 4);
     A* yl = yp + n;   // the work vector holds ypart then yleaf
+    int32_t ni = 0;
+    if constexpr (kHalf) {
+        // the half pools: table-driven walks, 64-row slices above the leaves
+        ni = (int32_t)H.n_b1;
+        const int32_t nb1 = (ni + 3) / 4, nb2 = (int32_t)((H.n_b2 + 3) / 4);
+        k_phaseB_half<T><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1items.p, H.kappa, LP, H.qp1.p, H.qt1.p,
+                                                                H.qp2.p, H.qt2.p, U, D, tp, xs, yp, yl, H.b2items.p,
+                                                                (int32_t)H.n_b2, H.b2_rows);
+    } else {
+        ni = (int32_t)H.n_b1s;
+        const int32_t nb1 = (ni + 3) / 4, nb2 = (int32_t)((H.n_b2 + 3) / 4);
 #define H2D_PHASE_B(SR)                                                                                              \
     k_phaseB<T, A, kHalf, SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, \
-                                                                   bnear, bil, U, D, tp, xs, yp, yl,                 \
+                                                                   H.bnear.p, H.bil.p, U, D, tp, xs, yp, yl,         \
                                                                    H.scale16.p, H.n_il, H.b2items.p, (int32_t)H.n_b2, \
                                                                    H.b2_rows)
-    if (H.b1_rows == 16) H2D_PHASE_B(16);
-    else if (H.b1_rows == 32) H2D_PHASE_B(32);
-    else H2D_PHASE_B(64);
+        if (H.b1_rows == 16) H2D_PHASE_B(16);
+        else if (H.b1_rows == 32) H2D_PHASE_B(32);
+        else H2D_PHASE_B(64);
 #undef H2D_PHASE_B
+    }
     if (ev) HIPCK(hipEventRecord(ev[4], s));
     k_combine<A, kHalf><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, ni ? yp : nullptr, yl, H.perm.p, H.diag32.p, xs,
                                                                    y);
@@ -1095,8 +1074,11 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t noalloc_bytes(const Handle& H, int prec)
 {
     const size_t a = prec == H2D_P_FP64 ? sizeof(double) : sizeof(float);
-    return align256(a * (size_t)H.n) + align256(a * 2 * (size_t)H.n) +
-           align256(a * (size_t)std::max<int64_t>(H.t_elems, 1)) + align256(a * (size_t)std::max<int64_t>(H.p_elems, 1));
+    // x and t with 4 values of slack (the half phase-B walks read
+    // multiplier values in fours)
+    return align256(a * ((size_t)H.n + 4)) + align256(a * 2 * (size_t)H.n) +
+           align256(a * ((size_t)std::max<int64_t>(H.t_elems, 1) + 4)) +
+           align256(a * (size_t)std::max<int64_t>(H.p_elems, 1));
 }
 
 void launch_matvec_noalloc(Handle& H, const double* x, double* y, int prec, hipStream_t s)
@@ -1110,9 +1092,9 @@ void launch_matvec_noalloc(Handle& H, const double* x, double* y, int prec, hipS
                              std::to_string(kScratchBytes));
     char* base = scratch_base(dev);
     const size_t a = prec == H2D_P_FP64 ? sizeof(double) : sizeof(float);
-    const size_t o_yp = align256(a * (size_t)H.n);
+    const size_t o_yp = align256(a * ((size_t)H.n + 4));
     const size_t o_tp = o_yp + align256(a * 2 * (size_t)H.n);
-    const size_t o_pp = o_tp + align256(a * (size_t)std::max<int64_t>(H.t_elems, 1));
+    const size_t o_pp = o_tp + align256(a * ((size_t)std::max<int64_t>(H.t_elems, 1) + 4));
     if (prec == H2D_P_FP64) {
         double* w = reinterpret_cast<double*>(base);
         run_one<double, double, false>(H, H.U64.p, H.V64.p, H.D64.p, w, (double*)(base + o_tp), (double*)(base + o_pp),

@@ -426,53 +426,64 @@ __device__ __forceinline__ f4 quad_f32(uint64_t w)
                   __uint_as_float(hi & 0xffff0000u)};
 }
 
-// The half pools' tiles are stored as [column quads][rows][4] (the 4 values
-// of one row in 4 consecutive columns form one aligned 8-byte group,
-// columns padded with zeros to a multiple of 4).  acc[t] (rows 16 t .. 16 t
-// + 15, t < NT) += A (rows x K) B (K x 16), A(i, c) = Ab[(c / 4) qs + 4 i +
-// c % 4] (qs = 4 x the tile's rows), B(c, r) = bs Bb[c ldb + r].  A step
-// takes 16 columns: lane group lk loads the group of columns c0 + 4 lk ..
-// c0 + 4 lk + 3 of its row, and instruction u = 0..3 takes column c0 + 4 lk
-// + u as its k index lk.  Groups past the last one re-read the last (their
-// B values are zero), rows past the tile's end re-read its last row.
+// acc[t] (rows 16 t .. 16 t + 15 of a slice, t < NT) += the products of
+// the slice's rows of the 4-column groups of table entries j0 .. j1 - 1 (a
+// phase-B table of the half pools) with their multiplier rows, times the
+// entries' scales.  A step takes 4 entries: lane group lk loads its row's
+// 4 values of entry jb + lk, and instruction u = 0..3 takes column u of
+// that group as its k index lk; two steps are loaded before either is
+// used.  Entries past j1 re-read the last one with their multiplier values
+// zeroed, as are columns past an entry's nv; rows past the slice re-read
+// its last row.
 template <typename T, int NT>
-__device__ __forceinline__ void mm_tiles_q(f4 (&acc)[4], const T* __restrict__ Ab, int64_t qs, int32_t rows,
-                                           const float* __restrict__ Bb, int64_t ldb, int32_t K, float bs, int lane)
+__device__ __forceinline__ void mm_qt_tiles(f4 (&acc)[4], const QEnt* __restrict__ qt, int32_t j0, int32_t j1,
+                                            int32_t rc, int32_t rows, const T* __restrict__ Up,
+                                            const T* __restrict__ Dp, const float* __restrict__ tp,
+                                            const float* __restrict__ xs, int lane)
 {
+    constexpr int US = 2;
     const int li = lane % 16, lk = lane / 16;
-    const int32_t nq = (K + 3) >> 2;
     int64_t ro[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) ro[t] = (int64_t)min(16 * t + li, rows - 1) * 4;
-    for (int32_t c0 = 0; c0 < K; c0 += 16) {
-        const T* qa = Ab + (int64_t)min((c0 >> 2) + lk, nq - 1) * qs;
-        uint64_t w[NT];
+    for (int t = 0; t < NT; ++t) ro[t] = (int64_t)(rc + min(16 * t + li, rows - 1)) * 4;
+    for (int32_t jb = j0; jb < j1; jb += 4 * US) {
+        uint64_t w[US][NT];
+        float b[US][4];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) w[t] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(qa + ro[t]));
-        float b[4];
+        for (int st = 0; st < US; ++st) {
+            const int32_t j = jb + 4 * st + lk;
+            const QEnt e = qt[min(j, j1 - 1)];
+            const T* qa = (e.src >= 0 ? Up : Dp) + ((int64_t)e.q << 2);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int32_t c = c0 + 4 * lk + u;
-            b[u] = c < K ? Bb[(int64_t)c * ldb + li] * bs : 0.f;
+            for (int t = 0; t < NT; ++t) w[st][t] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(qa + ro[t]));
+            const float* tb = e.src >= 0 ? tp + (int64_t)e.src * kR : xs + (int64_t)(~e.src) * kR;
+            const int32_t nv = j < j1 ? e.nv : 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) b[st][u] = u < nv ? tb[u * kR + li] * e.sc : 0.f;
         }
-        f4 a[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) a[t] = quad_f32<T>(w[t]);
+        for (int st = 0; st < US; ++st) {
+            f4 a[NT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int t = 0; t < NT; ++t) a[t] = quad_f32<T>(w[st][t]);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[u], acc[t], 0, 0, 0);
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[st][u], acc[t], 0, 0, 0);
+        }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void mm_tile_q(f4 (&acc)[4], const T* __restrict__ Ab, int64_t qs, int32_t rows,
-                                          const float* __restrict__ Bb, int64_t ldb, int32_t K, float bs, int lane)
+__device__ __forceinline__ void mm_qt(f4 (&acc)[4], const QEnt* __restrict__ qt, int32_t j0, int32_t j1, int32_t rc,
+                                      int32_t rows, const T* __restrict__ Up, const T* __restrict__ Dp,
+                                      const float* __restrict__ tp, const float* __restrict__ xs, int lane)
 {
-    if (rows > 48) mm_tiles_q<T, 4>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
-    else if (rows > 32) mm_tiles_q<T, 3>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
-    else if (rows > 16) mm_tiles_q<T, 2>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
-    else mm_tiles_q<T, 1>(acc, Ab, qs, rows, Bb, ldb, K, bs, lane);
+    if (rows > 48) mm_qt_tiles<T, 4>(acc, qt, j0, j1, rc, rows, Up, Dp, tp, xs, lane);
+    else if (rows > 32) mm_qt_tiles<T, 3>(acc, qt, j0, j1, rc, rows, Up, Dp, tp, xs, lane);
+    else if (rows > 16) mm_qt_tiles<T, 2>(acc, qt, j0, j1, rc, rows, Up, Dp, tp, xs, lane);
+    else mm_qt_tiles<T, 1>(acc, qt, j0, j1, rc, rows, Up, Dp, tp, xs, lane);
 }
 
 // Scale of a dense block of the half pools (index into the scale table).
@@ -511,23 +522,12 @@ b1_mr(int32_t it, int lane, const int2* __restrict__ items, int tl, const int32_
             const BDesc d = bil[q];
             const int64_t off = uni_l(d.off);
             const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
-            if constexpr (sizeof(T) == 2) {
-                // this box's tile of U: k4 / 4 groups of cnt rows; a dense
-                // block: one tile of ld_m rows
-                if (cols > 0)
-                    mm_tile_q<T>(acc, Up + off + (int64_t)((cols + 3) & ~3) * (p0 - ab) + (int64_t)rc * 4,
-                                 (int64_t)cnt * 4, rows, tpool + (int64_t)tsrc * kR, kR, cols, 1.f, lane);
-                else if (cols < 0)
-                    mm_tile_q<T>(acc, Dp + off + (int64_t)(p0 - ab + rc) * 4, (int64_t)ld_m * 4, rows,
-                                 xs + (int64_t)tsrc * kR, kR, -cols, scale[q], lane);
-            } else {
-                if (cols > 0)
-                    mm_tile<T>(acc, Up + off + (int64_t)cols * (p0 - ab) + rc, cnt, rows, tpool + (int64_t)tsrc * kR,
-                               kR, cols, (A)1, lane);
-                else if (cols < 0)
-                    mm_tile<T>(acc, Dp + off + (p0 - ab) + rc, ld_m, rows, xs + (int64_t)tsrc * kR, kR, -cols,
-                               dense_scale<T>(scale, q), lane);
-            }
+            if (cols > 0)
+                mm_tile<T>(acc, Up + off + (int64_t)cols * (p0 - ab) + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR,
+                           cols, (A)1, lane);
+            else if (cols < 0)
+                mm_tile<T>(acc, Dp + off + (p0 - ab) + rc, ld_m, rows, xs + (int64_t)tsrc * kR, kR, -cols,
+                           dense_scale<T>(scale, q), lane);
         }
         a_box = uni_i(gp<const int32_t>((uint64_t)Lparent[l])[a_box]);
     }
@@ -562,38 +562,20 @@ b2_mr(int32_t X, int lane, const int32_t* __restrict__ begin, const int32_t* __r
         V4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
-        if constexpr (sizeof(T) == 2) {
-            // every block here is one tile of cnt rows
-            auto blk = [&](const T* P, const A* Bb, int32_t K, A bs) {
-                mm_tile_q<T>(acc, P + (int64_t)rc * 4, (int64_t)cnt * 4, rows, Bb, kR, K, bs, lane);
-            };
-            for (int32_t q = n0; q < n1; ++q) {
-                const BDesc d = bnear[q];
-                blk(Dp + uni_l(d.off), xs + (int64_t)uni_i(d.tsrc) * kR, -uni_i(d.cols), scale[(int64_t)n_il + q]);
-            }
-            for (int32_t q = q0; q < q1; ++q) {
-                const BDesc d = bil[q];
-                const int64_t off = uni_l(d.off);
-                const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
-                if (cols > 0) blk(Up + off, tpool + (int64_t)tsrc * kR, cols, 1.f);
-                else if (cols < 0) blk(Dp + off, xs + (int64_t)tsrc * kR, -cols, scale[q]);
-            }
-        } else {
-            for (int32_t q = n0; q < n1; ++q) {
-                const BDesc d = bnear[q];
-                mm_tile<T>(acc, Dp + uni_l(d.off) + rc, cnt, rows, xs + (int64_t)uni_i(d.tsrc) * kR, kR, -uni_i(d.cols),
-                           dense_scale<T>(scale, (int64_t)n_il + q), lane);
-            }
-            for (int32_t q = q0; q < q1; ++q) {
-                const BDesc d = bil[q];
-                const int64_t off = uni_l(d.off);
-                const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
-                if (cols > 0)
-                    mm_tile<T>(acc, Up + off + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR, cols, (A)1, lane);
-                else if (cols < 0)
-                    mm_tile<T>(acc, Dp + off + rc, cnt, rows, xs + (int64_t)tsrc * kR, kR, -cols,
-                               dense_scale<T>(scale, q), lane);
-            }
+        for (int32_t q = n0; q < n1; ++q) {
+            const BDesc d = bnear[q];
+            mm_tile<T>(acc, Dp + uni_l(d.off) + rc, cnt, rows, xs + (int64_t)uni_i(d.tsrc) * kR, kR, -uni_i(d.cols),
+                       dense_scale<T>(scale, (int64_t)n_il + q), lane);
+        }
+        for (int32_t q = q0; q < q1; ++q) {
+            const BDesc d = bil[q];
+            const int64_t off = uni_l(d.off);
+            const int32_t cols = uni_i(d.cols), tsrc = uni_i(d.tsrc);
+            if (cols > 0)
+                mm_tile<T>(acc, Up + off + rc, cnt, rows, tpool + (int64_t)tsrc * kR, kR, cols, (A)1, lane);
+            else if (cols < 0)
+                mm_tile<T>(acc, Dp + off + rc, cnt, rows, xs + (int64_t)tsrc * kR, kR, -cols, dense_scale<T>(scale, q),
+                           lane);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -603,6 +585,30 @@ b2_mr(int32_t X, int lane, const int32_t* __restrict__ begin, const int32_t* __r
                 if (i < rows) yt[(int64_t)(r0 + rc + i) * kR + li] = acc[t][v];
             }
     }
+}
+
+// Phase B on the half pools: rows rc .. rc + rows - 1 of a box whose first
+// row is r0 (one level above the leaves: its table-1 entries; a leaf: its
+// table-2 entries j0 .. j1 - 1), into out (tree order, point-major).
+template <typename T>
+__device__ __forceinline__ void mr_half_slice(int lane, int32_t r0, int32_t rc, int32_t rows,
+                                              const QEnt* __restrict__ qt, int32_t j0, int32_t j1,
+                                              const T* __restrict__ Up, const T* __restrict__ Dp,
+                                              const float* __restrict__ tp, const float* __restrict__ xs,
+                                              float* __restrict__ out)
+{
+    f4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    mm_qt<T>(acc, qt, j0, j1, rc, rows, Up, Dp, tp, xs, lane);
+    const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int32_t i = 16 * t + MrT<T>::row(v, lk);
+            if (i < rows) out[(int64_t)(r0 + rc + i) * kR + li] = acc[t][v];
+        }
 }
 
 // Workgroups w0 .. w0 + n - 1 -> tiles 0 .. n - 1, each XCD (workgroup ids
@@ -636,6 +642,16 @@ k_phaseB_mr(const MRInst* __restrict__ insts, int32_t nb1, const int2* __restric
         const int2 wk = work_at(work1, it);
         const MRInst& I = insts[wk.x];
         const int32_t* const* L = gp<const int32_t* const>(I.lvl);
+        if constexpr (sizeof(T) == 2) {
+            const int2 wi = gp<const int2>(I.b1items)[wk.y];
+            const int32_t P = uni_i(wi.x), rc = uni_i(wi.y), tl = I.kappa - 1;
+            const int32_t p0 = uni_i(gp<const int32_t>((uint64_t)L[tl])[P]);
+            const int32_t cnt = uni_i(gp<const int32_t>((uint64_t)L[(kMaxLevel + 1) + tl])[P]);
+            const int32_t* qp = gp<const int32_t>(I.qp1);
+            mr_half_slice<T>(lane, p0, rc, min(kWave, cnt - rc), gp<const QEnt>(I.qt1), uni_i(qp[P]), uni_i(qp[P + 1]),
+                             gp<const T>(I.U), gp<const T>(I.D), gp<const A>(I.tp), gp<const A>(I.xs), gp<A>(I.yp));
+            return;
+        }
         b1_mr<T>(wk.y, lane, gp<const int2>(I.b1items), I.kappa - 1, L, L + (kMaxLevel + 1), L + 2 * (kMaxLevel + 1),
                  L + 3 * (kMaxLevel + 1), gp<const BDesc>(I.bil), gp<const T>(I.U), gp<const T>(I.D),
                  gp<const A>(I.tp), gp<const A>(I.xs), gp<A>(I.yp), I.scale ? gp<const float>(I.scale) : nullptr);
@@ -646,6 +662,17 @@ k_phaseB_mr(const MRInst* __restrict__ insts, int32_t nb1, const int2* __restric
         const MRInst& I = insts[wk.x];
         const int32_t* const* L = gp<const int32_t* const>(I.lvl);
         const int kp = I.kappa;
+        if constexpr (sizeof(T) == 2) {
+            const int32_t X = wk.y;
+            const int32_t r0 = uni_i(gp<const int32_t>((uint64_t)L[kp])[X]);
+            const int32_t cnt = uni_i(gp<const int32_t>((uint64_t)L[(kMaxLevel + 1) + kp])[X]);
+            const int32_t* qp = gp<const int32_t>(I.qp2);
+            const int32_t j0 = uni_i(qp[X]), j1 = uni_i(qp[X + 1]);
+            for (int32_t rc = 0; rc < cnt; rc += kWave)
+                mr_half_slice<T>(lane, r0, rc, min(kWave, cnt - rc), gp<const QEnt>(I.qt2), j0, j1, gp<const T>(I.U),
+                                 gp<const T>(I.D), gp<const A>(I.tp), gp<const A>(I.xs), gp<A>(I.yl));
+            return;
+        }
         b2_mr<T>(wk.y, lane, gp<const int32_t>((uint64_t)L[kp]), gp<const int32_t>((uint64_t)L[(kMaxLevel + 1) + kp]),
                  gp<const int32_t>((uint64_t)L[3 * (kMaxLevel + 1) + kp]), gp<const int32_t>(I.near_ptr),
                  gp<const BDesc>(I.bnear), gp<const BDesc>(I.bil), gp<const T>(I.U), gp<const T>(I.D),
@@ -802,8 +829,8 @@ static void ensure_mr16(Handle& H, hipStream_t s)
         I[h].xs = addr(H.xs_mr32.p); I[h].tp = addr(H.tp_mr32.p); I[h].pp = addr(H.pp_mr32.p);
         I[h].yp = addr(H.yp_mr32.p); I[h].yl = addr(H.yl_mr32.p);
         I[h].blks = addr(H.mr_blks16.p);
-        I[h].bil = addr(H.bil16.p);
-        I[h].bnear = addr(H.bnear16.p);
+        I[h].qp1 = addr(H.qp1.p); I[h].qt1 = addr(H.qt1.p);
+        I[h].qp2 = addr(H.qp2.p); I[h].qt2 = addr(H.qt2.p);
         I[h].scale = addr(H.scale16.p);
         I[h].diag = addr(H.diag32.p);
     }
