@@ -452,10 +452,10 @@ __device__ __forceinline__ float quad_dot4(uint64_t w, float t0, float t1, float
 
 // acc += the sum over table entries j = j0 + g, j0 + g + G, ... < j1 of the
 // entry's scale times the dot product of this lane's row of the entry's
-// 4-column group (at pool + 4 q + ro) with its multiplier values.  Eight
+// 4-column group (at pool + 4 q + ro) with its multiplier values.  Four
 // entries are loaded before any is used, so the groups of several blocks
-// are in flight together; slots past j1 re-read entry j1 - 1 and add
-// nothing.  kUni: G = 1, g = 0, every lane takes every entry (the entries
+// are in flight together, and the next four entries are fetched while
+// their groups load; slots past j1 re-read entry j1 - 1 and add nothing.  kUni: G = 1, g = 0, every lane takes every entry (the entries
 // and multiplier values are then wave-uniform loads).  The multiplier
 // values of columns past the group's nv are taken as zero; the work
 // vectors carry slack past their ends for these reads.
@@ -464,16 +464,18 @@ __device__ __forceinline__ void qt_sweep(float& acc, const QEnt* __restrict__ qt
                                          int64_t ro, const T* __restrict__ Up, const T* __restrict__ Dp,
                                          const float* __restrict__ tpool, const float* __restrict__ xs)
 {
-    constexpr int NF = 8;
+    constexpr int NF = 4;
     if constexpr (kUni) {
         g = 0;
         G = 1;
     }
-    for (int32_t jb = j0; jb < j1; jb += NF * G) {
-        QEnt e[NF];
-        uint64_t w[NF];
+    if (j0 >= j1) return;
+    QEnt e[NF];
 #pragma unroll
-        for (int u = 0; u < NF; ++u) e[u] = qt[min(jb + u * G + g, j1 - 1)];
+    for (int u = 0; u < NF; ++u) e[u] = qt[min(j0 + u * G + g, j1 - 1)];
+    for (int32_t jb = j0; jb < j1; jb += NF * G) {
+        uint64_t w[NF];
+        float t[NF][4];
 #pragma unroll
         for (int u = 0; u < NF; ++u) {
             const T* pool = e[u].src >= 0 ? Up : Dp;
@@ -482,13 +484,25 @@ __device__ __forceinline__ void qt_sweep(float& acc, const QEnt* __restrict__ qt
 #pragma unroll
         for (int u = 0; u < NF; ++u) {
             const float* tb = e[u].src >= 0 ? tpool + e[u].src : xs + ~e[u].src;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) t[u][c] = tb[c];
+        }
+        // the next entries are loaded while this step's groups are in flight
+        // (past j1 they re-read entry j1 - 1)
+        QEnt en[NF];
+#pragma unroll
+        for (int u = 0; u < NF; ++u) en[u] = qt[min(jb + (NF + u) * G + g, j1 - 1)];
+#pragma unroll
+        for (int u = 0; u < NF; ++u) {
             const int32_t nv = e[u].nv;
-            const float t0 = tb[0], t1 = tb[1], t2 = tb[2], t3 = tb[3];
-            const float d = quad_dot4<T>(w[u], t0, nv > 1 ? t1 : 0.f, nv > 2 ? t2 : 0.f, nv > 3 ? t3 : 0.f);
+            const float d = quad_dot4<T>(w[u], t[u][0], nv > 1 ? t[u][1] : 0.f, nv > 2 ? t[u][2] : 0.f,
+                                         nv > 3 ? t[u][3] : 0.f);
             // a slot past j1 adds d * 0 (d is computed either way, so the
             // slot's loads are not moved behind a branch)
             acc = fmaf(d, jb + u * G + g < j1 ? e[u].sc : 0.f, acc);
         }
+#pragma unroll
+        for (int u = 0; u < NF; ++u) e[u] = en[u];
     }
 }
 

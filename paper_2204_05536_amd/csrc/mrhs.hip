@@ -432,7 +432,7 @@ __device__ __forceinline__ f4 quad_f32(uint64_t w)
 // entries' scales.  A step takes 4 entries: lane group lk loads its row's
 // 4 values of entry jb + lk, and instruction u = 0..3 takes column u of
 // that group as its k index lk; two steps are loaded before either is
-// used.  Entries past j1 re-read the last one with their multiplier values
+// used, and the next two steps' entries are fetched meanwhile.  Entries past j1 re-read the last one with their multiplier values
 // zeroed, as are columns past an entry's nv; rows past the slice re-read
 // its last row.
 template <typename T, int NT>
@@ -446,21 +446,27 @@ __device__ __forceinline__ void mm_qt_tiles(f4 (&acc)[4], const QEnt* __restrict
     int64_t ro[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) ro[t] = (int64_t)(rc + min(16 * t + li, rows - 1)) * 4;
+    if (j0 >= j1) return;
+    QEnt e[US];
+#pragma unroll
+    for (int st = 0; st < US; ++st) e[st] = qt[min(j0 + 4 * st + lk, j1 - 1)];
     for (int32_t jb = j0; jb < j1; jb += 4 * US) {
         uint64_t w[US][NT];
         float b[US][4];
 #pragma unroll
         for (int st = 0; st < US; ++st) {
             const int32_t j = jb + 4 * st + lk;
-            const QEnt e = qt[min(j, j1 - 1)];
-            const T* qa = (e.src >= 0 ? Up : Dp) + ((int64_t)e.q << 2);
+            const T* qa = (e[st].src >= 0 ? Up : Dp) + ((int64_t)e[st].q << 2);
 #pragma unroll
             for (int t = 0; t < NT; ++t) w[st][t] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(qa + ro[t]));
-            const float* tb = e.src >= 0 ? tp + (int64_t)e.src * kR : xs + (int64_t)(~e.src) * kR;
-            const int32_t nv = j < j1 ? e.nv : 0;
+            const float* tb = e[st].src >= 0 ? tp + (int64_t)e[st].src * kR : xs + (int64_t)(~e[st].src) * kR;
+            const int32_t nv = j < j1 ? e[st].nv : 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) b[st][u] = u < nv ? tb[u * kR + li] * e.sc : 0.f;
+            for (int u = 0; u < 4; ++u) b[st][u] = u < nv ? tb[u * kR + li] * e[st].sc : 0.f;
         }
+        // the next entries are loaded while this step's values are in flight
+#pragma unroll
+        for (int st = 0; st < US; ++st) e[st] = qt[min(jb + 4 * (US + st) + lk, j1 - 1)];
 #pragma unroll
         for (int st = 0; st < US; ++st) {
             f4 a[NT];
