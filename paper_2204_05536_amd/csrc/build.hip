@@ -1363,22 +1363,91 @@ __global__ void k_half_q(const HalfJob* jobs, const double* src, T* dst, float* 
 }
 
 // V of one low-rank block, FP64 row-major n x k at src_off, to the half
-// pool at dst_off as row-major n x kp4 (kp4 = k rounded up to 4, zeros in
-// the padding columns).
+// pool at dst_off with row stride ld (its place in its source box's wide
+// rows; the pool is zeroed beforehand, which covers the padding).
 struct HalfVJob {
     int64_t src_off, dst_off;
-    int32_t n, k;
+    int32_t n, k, ld, pad;
 };
 
 template <typename T>
-__global__ void k_half_v4(const HalfVJob* jobs, const double* src, T* dst)
+__global__ void k_half_v(const HalfVJob* jobs, const double* src, T* dst)
 {
     const HalfVJob J = jobs[blockIdx.x];
-    const int32_t kp4 = (J.k + 3) & ~3;
-    for (int64_t e = threadIdx.x; e < (int64_t)J.n * kp4; e += blockDim.x) {
-        const int32_t j = (int32_t)(e / kp4), q = (int32_t)(e % kp4);
-        dst[J.dst_off + e] = to_half<T>(q < J.k ? (float)src[J.src_off + (int64_t)j * J.k + q] : 0.0f);
+    for (int64_t e = threadIdx.x; e < (int64_t)J.n * J.k; e += blockDim.x) {
+        const int32_t j = (int32_t)(e / J.k), q = (int32_t)(e % J.k);
+        dst[J.dst_off + (int64_t)j * J.ld + q] = to_half<T>((float)src[J.src_off + e]);
     }
+}
+
+// The half V pools grouped by source box: for every source box (per
+// level) the V of its low-rank blocks side by side, row j holding each
+// block's row j in table order, padded with zeros to a multiple of 4
+// values.  Sets the blocks' offsets and row strides, the phase-A items
+// (at most kPhaseARows rows of one source box each, largest first), the
+// column maps to the t pool and the reductions of split source boxes;
+// returns the conversion jobs.
+static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
+{
+    std::vector<int64_t> order;
+    for (int64_t q = 0; q < H.n_il; ++q)
+        if (H.h_il_kind[q] != kDense && H.h_il_k[q] > 0) order.push_back(q);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return H.h_il_level[a] != H.h_il_level[b] ? H.h_il_level[a] < H.h_il_level[b] : H.h_il_src[a] < H.h_il_src[b];
+    });
+    H.h_il_voff16.assign(H.n_il, 0);
+    H.h_il_vld16.assign(H.n_il, 0);
+    std::vector<HalfVJob> jobs;
+    std::vector<AWDesc> items;
+    std::vector<AWRed> red;
+    std::vector<int32_t> map;
+    int64_t vo = 0, po = 0;
+    for (size_t i = 0; i < order.size();) {
+        size_t e = i;
+        int32_t w = 0;
+        while (e < order.size() && H.h_il_level[order[e]] == H.h_il_level[order[i]] &&
+               H.h_il_src[order[e]] == H.h_il_src[order[i]])
+            w += H.h_il_k[order[e++]];
+        const int32_t w4 = (w + 3) & ~3;
+        const Level& L = H.lev[H.h_il_level[order[i]]];
+        const int32_t ny = L.h_count[H.h_il_src[order[i]]], y0 = L.h_begin[H.h_il_src[order[i]]];
+        const int32_t mo = (int32_t)map.size();
+        int32_t c0 = 0;
+        for (size_t b = i; b < e; ++b) {
+            const int64_t q = order[b];
+            const int32_t k = H.h_il_k[q];
+            H.h_il_voff16[q] = vo + c0;
+            H.h_il_vld16[q] = w4;
+            jobs.push_back(HalfVJob{H.h_il_voff[q], vo + c0, ny, k, w4, 0});
+            for (int32_t c = 0; c < k; ++c) map.push_back(H.h_il_toff[q] + c);
+            c0 += k;
+        }
+        for (int32_t c = w; c < w4; ++c) map.push_back(-1);
+        const int32_t parts = (ny + kPhaseARows - 1) / kPhaseARows;
+        for (int32_t p = 0; p < parts; ++p) {
+            const int32_t j0 = p * kPhaseARows, rows = std::min(kPhaseARows, ny - j0);
+            items.push_back(AWDesc{vo + (int64_t)j0 * w4, rows, w4, y0 + j0, mo, parts > 1 ? (int32_t)(po + (int64_t)p * w4) : -1, 0});
+        }
+        if (parts > 1) {
+            red.push_back(AWRed{(int32_t)po, parts, w4, mo});
+            po += (int64_t)parts * w4;
+        }
+        vo += (int64_t)ny * w4;
+        i = e;
+    }
+    if (po > INT32_MAX || map.size() > (size_t)INT32_MAX)
+        fail(H2D_EUNSUPPORTED, "half-precision phase-A tables above 2^31 entries");
+    std::stable_sort(items.begin(), items.end(),
+                     [](const AWDesc& a, const AWDesc& b) { return (int64_t)a.rows * a.w4 > (int64_t)b.rows * b.w4; });
+    H.v16_elems = vo;
+    H.p16_elems = po;
+    upload(H.aw_items, items, s);
+    upload(H.aw_map, map, s);
+    upload(H.aw_red, red, s);
+    H.n_aw_items = (int64_t)items.size();
+    H.n_aw_red = (int64_t)red.size();
+    H.ws_nrhs = 0;   // the half partial rows are sized here: reallocate on next use
+    return jobs;
 }
 
 // The phase-B tables of the half pools.  Table 1, per box P one level
@@ -1398,7 +1467,7 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
     auto put = [&](std::vector<QEnt>& t, int64_t e0, int64_t qs, int32_t ncols, int32_t src0, bool dense, float scale) {
         for (int32_t u = 0; 4 * u < ncols; ++u) {
             const int64_t e = e0 + (int64_t)u * qs;
-            t.push_back(QEnt{(uint32_t)(e >> 2), dense ? ~(src0 + 4 * u) : src0 + 4 * u, dense ? scale : 1.0f,
+            t.push_back(QEnt{(uint32_t)(e >> 2), dense ? ~(src0 + 4 * u) : src0 + 4 * u, scale,
                              std::min(4, ncols - 4 * u)});
         }
     };
@@ -1422,7 +1491,7 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
                     } else if (H.h_il_k[q] > 0) {
                         const int32_t k = H.h_il_k[q];
                         put(t1, H.h_il_off16[q] + (int64_t)((k + 3) & ~3) * (p0 - ab), (int64_t)cnt * 4, k,
-                            H.h_il_toff[q], false, 1.0f);
+                            H.h_il_toff[q], false, sc[q]);
                     }
                 }
                 a_box = L.h_parent[a_box];
@@ -1442,7 +1511,7 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
                 const int32_t sb = H.h_il_src[q];
                 put(t2, H.h_il_off16[q], qs, LL.h_count[sb], LL.h_begin[sb], true, sc[q]);
             } else if (H.h_il_k[q] > 0) {
-                put(t2, H.h_il_off16[q], qs, H.h_il_k[q], H.h_il_toff[q], false, 1.0f);
+                put(t2, H.h_il_off16[q], qs, H.h_il_k[q], H.h_il_toff[q], false, sc[q]);
             }
         }
         close(p2, t2);
@@ -1505,12 +1574,7 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     DBuf<HalfJob> du, dd;
     upload(du, ujobs, s);
     upload(dd, djobs, s);
-    std::vector<HalfVJob> vjobs;
-    for (int64_t q = 0; q < H.n_il; ++q) {
-        if (H.h_il_kind[q] == kDense || H.h_il_k[q] == 0) continue;
-        const int32_t nn = H.lev[il_src_level(H, q)].h_count[H.h_il_src[q]];
-        vjobs.push_back(HalfVJob{H.h_il_voff[q], H.h_il_voff16[q], nn, H.h_il_k[q]});
-    }
+    std::vector<HalfVJob> vjobs = wide_v_layout(H, s);
     DBuf<HalfVJob> dv;
     upload(dv, vjobs, s);
     // tree row -> first row and size of its box one level above the leaves
@@ -1545,7 +1609,7 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         }
         for (size_t o = 0; o < vjobs.size(); o += 1u << 20) {
             unsigned c = (unsigned)std::min<size_t>(1u << 20, vjobs.size() - o);
-            k_half_v4<T><<<c, 256, 0, s>>>(dv.p + o, H.V64.p, Vp);
+            k_half_v<T><<<c, 256, 0, s>>>(dv.p + o, H.V64.p, Vp);
         }
         HIPCK(hipGetLastError());
     };
@@ -1559,12 +1623,14 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     if (f16) {
         alloc_half(H.U16, H.u16_elems);
         alloc_half(H.V16, H.v16_elems);
+        HIPCK(hipMemsetAsync(H.V16.p, 0, sizeof(__half) * H.v16_elems, s));
         alloc_half(H.D16, H.d16_elems);
         run(H.U16.p, H.V16.p, H.D16.p);
     }
     if (b16) {
         alloc_half(H.Ub16, H.u16_elems);
         alloc_half(H.Vb16, H.v16_elems);
+        HIPCK(hipMemsetAsync(H.Vb16.p, 0, sizeof(__hip_bfloat16) * H.v16_elems, s));
         alloc_half(H.Db16, H.d16_elems);
         run(H.Ub16.p, H.Vb16.p, H.Db16.p);
     }

@@ -130,6 +130,22 @@ struct ADesc {
     int32_t pad;
 };
 
+// Phase A on the half pools, grouped by source box: rows of one source
+// box's wide V (the V of all its low-rank blocks side by side).
+struct AWDesc {
+    int64_t voff;     // element offset of the item's first row
+    int32_t rows, w4; // rows (at most kPhaseARows), width (a multiple of 4)
+    int32_t x0;       // tree index of the item's first row
+    int32_t map;      // offset of the source box's column map (t index of each column, -1 for padding)
+    int32_t part;     // -1: t written through the map; else offset of the item's partial row
+    int32_t pad;
+};
+// A source box whose phase-A rows were split: t[map[c]] = sum of the
+// nparts partial rows (w4 values each, consecutive from pbeg).
+struct AWRed {
+    int32_t pbeg, nparts, w4, map;
+};
+
 // Blocks whose phase-A work was split: t = sum of consecutive partials.
 struct RDesc {
     int32_t tout;     // t pool offset
@@ -151,7 +167,7 @@ struct MRItem {
 struct MRBlk {
     int64_t voff;
     int32_t k, out;
-    int32_t blk, pad;   // the block (its scale in the half pools)
+    int32_t blk, pad;   // the block; pad: the half pools' V row stride
 };
 
 // Static data of one instance for the table-driven multi-RHS kernels (a
@@ -251,9 +267,8 @@ struct Handle {
     std::vector<int64_t> h_il_voff;   // V pool offset (low rank)
     std::vector<int32_t> h_il_toff;   // t pool offset (low rank)
 
-    // factor pools: FP64 offsets as in the block table; the half V pools are
-    // padded row-major (h_il_voff16), the half U and D pools have a layout and
-    // offsets of their own (below)
+    // factor pools: FP64 offsets as in the block table; the half pools have
+    // layouts and offsets of their own (below)
     int64_t u_elems = 0, v_elems = 0, d_elems = 0, t_elems = 0, p_elems = 0;
     DBuf<double> U64, V64, D64;
     DBuf<__half> U16, V16, D16;
@@ -273,13 +288,20 @@ struct Handle {
     // matvec schedule
     DBuf<BDesc> bnear, bil;  // phase-B descriptors: near blocks, IL blocks
     DBuf<ADesc> aitems;
-    // FP16/BF16 V pools: each low-rank block's V row-major with its rows
-    // padded to a multiple of 4 values (zeros), so that every 4-value group
-    // is one aligned 8-byte load; offsets of their own (h_il_voff16) and the
-    // phase-A items pointing there (aitems16, same order as aitems)
+    // FP16/BF16 V pools, grouped by source box: for every source box (per
+    // level) the V of its low-rank blocks side by side, row j of the box
+    // holding each block's row j in table order, padded with zeros to w4 (a
+    // multiple of 4) values; block b's V starts at h_il_voff16[b] with row
+    // stride h_il_vld16[b].  Phase-A items over these rows (aw_items), the
+    // column maps to the t pool (aw_map), the reductions of split source
+    // boxes (aw_red) and their partial rows (p16_elems values).
     std::vector<int64_t> h_il_voff16;
-    int64_t v16_elems = 0;
-    DBuf<ADesc> aitems16;
+    std::vector<int32_t> h_il_vld16;
+    int64_t v16_elems = 0, p16_elems = 0;
+    DBuf<AWDesc> aw_items;
+    DBuf<int32_t> aw_map;
+    DBuf<AWRed> aw_red;
+    int64_t n_aw_items = 0, n_aw_red = 0;
     DBuf<RDesc> ritems;
     int64_t n_aitems = 0, n_ritems = 0;
     DBuf<int2> b1items;         // multi-RHS phase-B1 work: (box at level kappa - 1, first row of a 64-row chunk)

@@ -171,43 +171,6 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     A* out = (D.out >= 0) ? (tpool + D.out) : (ppool + (-D.out - 1));
     A sc = (A)1;
     if constexpr (kScaled) sc = (A)scale[D.pad];
-    if constexpr (sizeof(T) == 2) {
-        // half pools: rows padded to kp4 = k rounded up to 4 (zeros past
-        // column k), the block 8-byte aligned.  Lane (g, c) takes columns
-        // 4 c .. 4 c + 3 of rows g, g + G, ... (nc = kp4 / 4 lanes per row,
-        // G = 64 / nc rows per load): one aligned 8-byte load per lane,
-        // whole rows per wave load.  kp4 <= 256 (the ACA rank cap), so
-        // nc <= 64.
-        const int kp4 = (k + 3) & ~3, nc = kp4 >> 2;
-        const T* Vh = V + D.voff + (int64_t)D.j0 * kp4;
-        const int G = kWave / nc, g = lane / nc, c = lane % nc;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        if (g < G) {
-#pragma unroll 8
-            for (int32_t j = g; j < rows; j += G) {
-                const float4 v = ld4v<T>(Vh + (int64_t)j * kp4 + 4 * c);
-                const float xv = xl[j];
-                a0 += v.x * xv;
-                a1 += v.y * xv;
-                a2 += v.z * xv;
-                a3 += v.w * xv;
-            }
-        }
-        __shared__ float red4[4][4 * kWave];
-        float* rw = red4[wave];
-        rw[4 * lane] = a0;
-        rw[4 * lane + 1] = a1;
-        rw[4 * lane + 2] = a2;
-        rw[4 * lane + 3] = a3;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        for (int32_t q = lane; q < k; q += kWave) {
-            float acc = 0.f;
-            for (int gg = 0; gg < G; ++gg) acc += rw[4 * (gg * nc + (q >> 2)) + (q & 3)];
-            out[q] = acc * sc;
-        }
-        return;
-    }
     if (k <= kWave) {
         const int G = kWave / k, g = lane / k, q = lane % k;
         A acc = (A)0;
@@ -255,6 +218,109 @@ k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ pp
         for (int p = lane; p < D.nparts; p += kWave) s += ppool[D.pbeg + (int64_t)p * D.k + q];
         for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
         if (lane == 0) tpool[D.tout + q] = s;
+    }
+}
+
+// Phase A on the half pools, grouped by source box: one wave per item (at
+// most kPhaseARows rows of a source box's wide V, w4 values per row: the V
+// of every low-rank block with that source side by side).  The item's x
+// rows are staged in LDS.  With nc = w4 / 4 column groups per row, lane
+// (g, c) takes group c of rows g, g + G, ... (G = 64 / nc rows per load:
+// one aligned 8-byte load per lane, G whole rows per wave load) and the G
+// row-group sums of each column are added in a fixed order; wider rows
+// (nc > 64) are taken 64 groups per pass.  Each column's sum goes to its t
+// entry through the source box's column map, or to the item's partial row.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_phaseA_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t* __restrict__ map,
+              const T* __restrict__ V, const float* __restrict__ xs, float* __restrict__ tpool,
+              float* __restrict__ ppool)
+{
+    __shared__ float xw[4][kPhaseARows];
+    __shared__ float red4[4][4 * kWave];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+    if (it >= nitems) return;
+    const AWDesc D = items[it];
+    const int64_t voff = uni(D.voff);
+    const int32_t rows = uni(D.rows), w4 = uni(D.w4), x0 = uni(D.x0), mo = uni(D.map), part = uni(D.part);
+    float* xl = xw[wave];
+    for (int32_t j = lane; j < rows; j += kWave) xl[j] = xs[x0 + j];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    auto put = [&](int32_t q, float v) {
+        if (part >= 0) {
+            ppool[part + q] = v;
+        } else {
+            const int32_t m = map[mo + q];
+            if (m >= 0) tpool[m] = v;
+        }
+    };
+    const int32_t nc = w4 >> 2;
+    const T* Vb = V + voff;
+    if (nc <= kWave) {
+        const int G = kWave / nc, g = lane / nc, c = lane % nc;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        if (g < G) {
+#pragma unroll 8
+            for (int32_t j = g; j < rows; j += G) {
+                const float4 v = ld4v<T>(Vb + (int64_t)j * w4 + 4 * c);
+                const float xv = xl[j];
+                a0 += v.x * xv;
+                a1 += v.y * xv;
+                a2 += v.z * xv;
+                a3 += v.w * xv;
+            }
+        }
+        float* rw = red4[wave];
+        rw[4 * lane] = a0;
+        rw[4 * lane + 1] = a1;
+        rw[4 * lane + 2] = a2;
+        rw[4 * lane + 3] = a3;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t q = lane; q < w4; q += kWave) {
+            float acc = 0.f;
+            for (int gg = 0; gg < G; ++gg) acc += rw[4 * (gg * nc + (q >> 2)) + (q & 3)];
+            put(q, acc);
+        }
+        return;
+    }
+    for (int32_t c = lane; c < nc; c += kWave) {
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll 8
+        for (int32_t j = 0; j < rows; ++j) {
+            const float4 v = ld4v<T>(Vb + (int64_t)j * w4 + 4 * c);
+            const float xv = xl[j];
+            a0 += v.x * xv;
+            a1 += v.y * xv;
+            a2 += v.z * xv;
+            a3 += v.w * xv;
+        }
+        put(4 * c, a0);
+        put(4 * c + 1, a1);
+        put(4 * c + 2, a2);
+        put(4 * c + 3, a3);
+    }
+}
+
+// t of the columns of source boxes whose phase-A rows were split: the sum
+// of the partial rows in part order.  One workgroup per source box, one
+// thread per column.
+__global__ void __launch_bounds__(256)
+k_reduce_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict__ map,
+              const float* __restrict__ ppool, float* __restrict__ tpool)
+{
+    const int64_t r = blockIdx.x;
+    if (r >= nr) return;
+    const AWRed D = R[r];
+    for (int32_t q = threadIdx.x; q < D.w4; q += blockDim.x) {
+        const int32_t m = map[D.map + q];
+        if (m < 0) continue;
+        float s = 0.f;
+#pragma unroll 8
+        for (int32_t p = 0; p < D.nparts; ++p) s += ppool[D.pbeg + (int64_t)p * D.w4 + q];
+        tpool[m] = s;
     }
 }
 
@@ -674,8 +740,7 @@ void finalize(Handle& H, hipStream_t s)
     std::vector<ADesc> items;
     std::vector<RDesc> red;
     H.h_il_toff.assign(nil, -1);
-    H.h_il_voff16.assign(nil, 0);
-    int64_t toff = 0, poff = 0, v16 = 0;
+    int64_t toff = 0, poff = 0;
     H.max_rank = 0; H.sum_rank = 0; H.n_il_dense = 0;
     double flops = 0;
     double store_anc = 0, store_leaf = 0, t_leaf = 0;   // stored values read by the B1 / B2 halves, t values by B2
@@ -696,8 +761,6 @@ void finalize(Handle& H, hipStream_t s)
         bi[b] = BDesc{H.h_il_off[b], k, (int32_t)toff};
         if (k == 0) continue;
         H.h_il_toff[b] = (int32_t)toff;
-        H.h_il_voff16[b] = v16;
-        v16 += (int64_t)n * ((k + 3) & ~3);
         (leaf ? store_leaf : store_anc) += (double)m * k;
         if (leaf) t_leaf += k;
         flops += 2.0 * k * (double)(m + n);
@@ -771,12 +834,6 @@ void finalize(Handle& H, hipStream_t s)
     }
     upload_vec(H.bil, bi, s);
     upload_vec(H.aitems, items, s);
-    H.v16_elems = v16;
-    {   // the same items on the padded half V pools (ADesc.pad is the block)
-        std::vector<ADesc> i16(items);
-        for (ADesc& d : i16) d.voff = H.h_il_voff16[d.pad];
-        upload_vec(H.aitems16, i16, s);
-    }
     upload_vec(H.ritems, red, s);
     H.n_aitems = (int64_t)items.size();
     H.n_ritems = (int64_t)red.size();
@@ -894,7 +951,7 @@ void ensure_workspace(Handle& H, int nrhs)
         H.xs32.alloc((size_t)n * nrhs + 4);
         H.ypart32.alloc((size_t)2 * n * nrhs);
         H.tpool32.alloc(std::max<int64_t>(H.t_elems, 1) * nrhs + 4);
-        H.ppool32.alloc(std::max<int64_t>(H.p_elems, 1) * nrhs);
+        H.ppool32.alloc(std::max<int64_t>(H.p16_elems, 1) * nrhs);
     }
     H.ws_nrhs = nrhs;
 }
@@ -935,13 +992,19 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
     if (ev) HIPCK(hipEventRecord(ev[0], s));
     k_gather<A><<<(n + 255) / 256, 256, 0, s>>>(x, H.perm.p, n, 0, 0, 1, xs);
     if (ev) HIPCK(hipEventRecord(ev[1], s));
-    if (H.n_aitems)
-        k_phaseA<T, A, kHalf><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems,
-                                                                            kHalf ? H.aitems16.p : H.aitems.p, V, xs,
-                                                                            tp, pp,
-                                                                            H.scale16.p);
-    if (ev) HIPCK(hipEventRecord(ev[2], s));
-    if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
+    if constexpr (kHalf) {
+        if (H.n_aw_items)
+            k_phaseA_wide<T><<<(unsigned)((H.n_aw_items + 3) / 4), 256, 0, s>>>(H.n_aw_items, H.aw_items.p, H.aw_map.p, V,
+                                                                               xs, tp, pp);
+        if (ev) HIPCK(hipEventRecord(ev[2], s));
+        if (H.n_aw_red) k_reduce_wide<<<(unsigned)H.n_aw_red, 256, 0, s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, pp, tp);
+    } else {
+        if (H.n_aitems)
+            k_phaseA<T, A, false><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp,
+                                                                                nullptr);
+        if (ev) HIPCK(hipEventRecord(ev[2], s));
+        if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
+    }
     if (ev) HIPCK(hipEventRecord(ev[3], s));
     const LevelPtrs LP = level_ptrs(H);
     if constexpr (!kHalf) {
@@ -1090,9 +1153,10 @@ size_t noalloc_bytes(const Handle& H, int prec)
     const size_t a = prec == H2D_P_FP64 ? sizeof(double) : sizeof(float);
     // x and t with 4 values of slack (the half phase-B walks read
     // multiplier values in fours)
+    // (the half pools have partial rows of their own)
+    const int64_t pe = prec == H2D_P_FP64 ? H.p_elems : H.p16_elems;
     return align256(a * ((size_t)H.n + 4)) + align256(a * 2 * (size_t)H.n) +
-           align256(a * ((size_t)std::max<int64_t>(H.t_elems, 1) + 4)) +
-           align256(a * (size_t)std::max<int64_t>(H.p_elems, 1));
+           align256(a * ((size_t)std::max<int64_t>(H.t_elems, 1) + 4)) + align256(a * (size_t)std::max<int64_t>(pe, 1));
 }
 
 void launch_matvec_noalloc(Handle& H, const double* x, double* y, int prec, hipStream_t s)

@@ -7,10 +7,9 @@
 // products accumulate in FP32 (the accuracy of the single-RHS half path).
 // Schedule, storage and the tree are those of the single-RHS path
 // (matvec.hip); only the inner products differ.  The half pools keep their
-// per-block scales: T_b carries the scale of U_b (as t does in the
-// single-RHS path), dense blocks scale the x values they multiply, and the
-// self-block diagonal held apart in FP32 is added when the result is
-// scattered back.
+// per-block scales: phase B multiplies each 4-column group of U or D by its
+// block's scale (the phase-B table entries carry it), and the self-block
+// diagonal held apart in FP32 is added when the result is scattered back.
 //
 // MFMA operand layout (16 x 16 output, K = 4 per instruction), lane l:
 //   A (16 x 4):  A[l % 16][l / 16]
@@ -260,7 +259,8 @@ __device__ __forceinline__ void srcA_tiles(typename MrT<T>::V4 (&acc)[4], const 
 // Phase A grouped by source box: one workgroup per item stages the item's
 // rows of X in LDS once; its four waves take the blocks sharing that source
 // in turn, T (k x 16, row-major) = V(rows, :)^T X(rows, :), up to 4 M tiles
-// of 16 columns q per pass (half pools: times the block's U scale).
+// of 16 columns q per pass (on the half pools the block's U scale is
+// applied in phase B, with the U values).
 // Dynamic LDS: 16 values per row, rows rounded up to 16.
 template <typename T>
 __device__ __forceinline__ void
@@ -280,10 +280,9 @@ phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restric
         const MRBlk B = blks[b];
         const int64_t voff = uni_l(B.voff);
         const int32_t k = uni_i(B.k), out = uni_i(B.out);
-        // FP64 V rows hold k values; the half pools pad each row to a multiple of 4
-        const int32_t ldv = sizeof(T) == 8 ? k : ((k + 3) & ~3);
-        A sc = (A)1;
-        if constexpr (sizeof(T) != 8) sc = (A)scale[uni_i(B.blk)];
+        // FP64 V rows hold k values; the half pools hold the V of every
+        // block with this source side by side (row stride in B.pad)
+        const int32_t ldv = sizeof(T) == 8 ? k : uni_i(B.pad);
         A* Tt = out >= 0 ? tpool + (int64_t)out * kR : ppool + ((int64_t)(-out - 1) + (int64_t)it.p * k) * kR;
         const T* Vb = V + voff + (int64_t)it.j0 * ldv;
         for (int32_t q0 = 0; q0 < k; q0 += 64) {
@@ -300,7 +299,7 @@ phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restric
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int32_t q = q0 + 16 * t + MrT<T>::row(v, lk);
-                    if (t < nt && q < k) Tt[(int64_t)q * kR + li] = acc[t][v] * sc;
+                    if (t < nt && q < k) Tt[(int64_t)q * kR + li] = acc[t][v];
                 }
         }
     }
@@ -755,7 +754,10 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
         HIPCK(hipMemcpyAsync(H.mr_ritems.p, red.data(), sizeof(RDesc) * red.size(), hipMemcpyHostToDevice, s));
     if (H.v16_elems > 0) {   // the same blocks on the padded half V pools
         std::vector<MRBlk> b16(blks);
-        for (MRBlk& B : b16) B.voff = H.h_il_voff16[B.blk];
+        for (MRBlk& B : b16) {
+            B.voff = H.h_il_voff16[B.blk];
+            B.pad = H.h_il_vld16[B.blk];   // row stride: the source box's wide rows
+        }
         H.mr_blks16.alloc(std::max<size_t>(b16.size(), 1));
         if (!b16.empty())
             HIPCK(hipMemcpyAsync(H.mr_blks16.p, b16.data(), sizeof(MRBlk) * b16.size(), hipMemcpyHostToDevice, s));
