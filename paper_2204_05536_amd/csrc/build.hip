@@ -1401,7 +1401,7 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
     std::vector<AWDesc> items;
     std::vector<AWRed> red;
     std::vector<int32_t> map;
-    int64_t vo = 0, po = 0;
+    int64_t vo = 0, po = 0, t_direct = 0, t_split = 0;
     for (size_t i = 0; i < order.size();) {
         size_t e = i;
         int32_t w = 0;
@@ -1431,6 +1431,9 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
         if (parts > 1) {
             red.push_back(AWRed{(int32_t)po, parts, w4, mo});
             po += (int64_t)parts * w4;
+            t_split += w;
+        } else {
+            t_direct += w;
         }
         vo += (int64_t)ny * w4;
         i = e;
@@ -1441,6 +1444,13 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
                      [](const AWDesc& a, const AWDesc& b) { return (int64_t)a.rows * a.w4 > (int64_t)b.rows * b.w4; });
     H.v16_elems = vo;
     H.p16_elems = po;
+    // algorithmic bytes of the half phase A (V once, x once, t and the
+    // partial rows written once) and of its reduction (partial rows read,
+    // t written); the library's count for the half product
+    H.phase_bytes[1][1] = (double)H.v_elems * 2 + (double)H.n * 4 + (double)t_direct * 4 + (double)po * 4;
+    H.phase_bytes[1][2] = po ? (double)po * 4 + (double)t_split * 4 : 0.0;
+    H.alg_bytes_half = 0;
+    for (int p = 0; p < 5; ++p) H.alg_bytes_half += H.phase_bytes[1][p];
     upload(H.aw_items, items, s);
     upload(H.aw_map, map, s);
     upload(H.aw_red, red, s);
