@@ -1362,12 +1362,13 @@ __global__ void k_half_q(const HalfJob* jobs, const double* src, T* dst, float* 
     }
 }
 
-// V of one low-rank block, FP64 row-major n x k at src_off, to the half
-// pool at dst_off with row stride ld (its place in its source box's wide
-// rows; the pool is zeroed beforehand, which covers the padding).
+// V of one low-rank block, FP64 row-major n x k at src_off, to its place
+// in its source box's wide V: element (j, q) at dst_off + (j / 4) rg + 4 q
+// + j mod 4 (rg = 4 x the box's width; the pool is zeroed beforehand,
+// which covers the padding rows).
 struct HalfVJob {
     int64_t src_off, dst_off;
-    int32_t n, k, ld, pad;
+    int32_t n, k, rg, pad;
 };
 
 template <typename T>
@@ -1376,17 +1377,17 @@ __global__ void k_half_v(const HalfVJob* jobs, const double* src, T* dst)
     const HalfVJob J = jobs[blockIdx.x];
     for (int64_t e = threadIdx.x; e < (int64_t)J.n * J.k; e += blockDim.x) {
         const int32_t j = (int32_t)(e / J.k), q = (int32_t)(e % J.k);
-        dst[J.dst_off + (int64_t)j * J.ld + q] = to_half<T>((float)src[J.src_off + e]);
+        dst[J.dst_off + (int64_t)(j >> 2) * J.rg + 4 * q + (j & 3)] = to_half<T>((float)src[J.src_off + e]);
     }
 }
 
 // The half V pools grouped by source box: for every source box (per
-// level) the V of its low-rank blocks side by side, row j holding each
-// block's row j in table order, padded with zeros to a multiple of 4
-// values.  Sets the blocks' offsets and row strides, the phase-A items
-// (at most kPhaseARows rows of one source box each, largest first), the
-// column maps to the t pool and the reductions of split source boxes;
-// returns the conversion jobs.
+// level) the V of its low-rank blocks side by side (table order), stored in
+// groups of 4 rows (element (j, c) at ((j / 4) w + c) 4 + j mod 4, rows
+// padded with zeros to a multiple of 4).  Sets the blocks' offsets and
+// row-group strides, the phase-A items (at most kPhaseARows rows of one
+// source box each, largest first), the column maps to the t pool and the
+// reductions of split source boxes; returns the conversion jobs.
 static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
 {
     std::vector<int64_t> order;
@@ -1408,7 +1409,6 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
         while (e < order.size() && H.h_il_level[order[e]] == H.h_il_level[order[i]] &&
                H.h_il_src[order[e]] == H.h_il_src[order[i]])
             w += H.h_il_k[order[e++]];
-        const int32_t w4 = (w + 3) & ~3;
         const Level& L = H.lev[H.h_il_level[order[i]]];
         const int32_t ny = L.h_count[H.h_il_src[order[i]]], y0 = L.h_begin[H.h_il_src[order[i]]];
         const int32_t mo = (int32_t)map.size();
@@ -1416,32 +1416,32 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
         for (size_t b = i; b < e; ++b) {
             const int64_t q = order[b];
             const int32_t k = H.h_il_k[q];
-            H.h_il_voff16[q] = vo + c0;
-            H.h_il_vld16[q] = w4;
-            jobs.push_back(HalfVJob{H.h_il_voff[q], vo + c0, ny, k, w4, 0});
+            H.h_il_voff16[q] = vo + 4 * (int64_t)c0;
+            H.h_il_vld16[q] = 4 * w;
+            jobs.push_back(HalfVJob{H.h_il_voff[q], vo + 4 * (int64_t)c0, ny, k, 4 * w, 0});
             for (int32_t c = 0; c < k; ++c) map.push_back(H.h_il_toff[q] + c);
             c0 += k;
         }
-        for (int32_t c = w; c < w4; ++c) map.push_back(-1);
-        const int32_t parts = (ny + kPhaseARows - 1) / kPhaseARows;
+        const int32_t parts = (ny + kPhaseARows - 1) / kPhaseARows;   // kPhaseARows: a multiple of 4
         for (int32_t p = 0; p < parts; ++p) {
             const int32_t j0 = p * kPhaseARows, rows = std::min(kPhaseARows, ny - j0);
-            items.push_back(AWDesc{vo + (int64_t)j0 * w4, rows, w4, y0 + j0, mo, parts > 1 ? (int32_t)(po + (int64_t)p * w4) : -1, 0});
+            items.push_back(AWDesc{vo + (int64_t)(j0 / 4) * 4 * w, rows, w, y0 + j0, mo,
+                                   parts > 1 ? (int32_t)(po + (int64_t)p * w) : -1, 0});
         }
         if (parts > 1) {
-            red.push_back(AWRed{(int32_t)po, parts, w4, mo});
-            po += (int64_t)parts * w4;
+            red.push_back(AWRed{(int32_t)po, parts, w, mo});
+            po += (int64_t)parts * w;
             t_split += w;
         } else {
             t_direct += w;
         }
-        vo += (int64_t)ny * w4;
+        vo += (int64_t)((ny + 3) / 4) * 4 * w;
         i = e;
     }
     if (po > INT32_MAX || map.size() > (size_t)INT32_MAX)
         fail(H2D_EUNSUPPORTED, "half-precision phase-A tables above 2^31 entries");
     std::stable_sort(items.begin(), items.end(),
-                     [](const AWDesc& a, const AWDesc& b) { return (int64_t)a.rows * a.w4 > (int64_t)b.rows * b.w4; });
+                     [](const AWDesc& a, const AWDesc& b) { return (int64_t)a.rows * a.w > (int64_t)b.rows * b.w; });
     H.v16_elems = vo;
     H.p16_elems = po;
     // algorithmic bytes of the half phase A (V once, x once, t and the

@@ -131,19 +131,20 @@ struct ADesc {
 };
 
 // Phase A on the half pools, grouped by source box: rows of one source
-// box's wide V (the V of all its low-rank blocks side by side).
+// box's wide V (the V of all its low-rank blocks side by side, stored in
+// groups of 4 rows: element (j, c) at ((j / 4) w + c) 4 + j mod 4).
 struct AWDesc {
-    int64_t voff;     // element offset of the item's first row
-    int32_t rows, w4; // rows (at most kPhaseARows), width (a multiple of 4)
+    int64_t voff;     // element offset of the item's first row group
+    int32_t rows, w;  // rows (at most kPhaseARows, a multiple of 4 unless last), width
     int32_t x0;       // tree index of the item's first row
-    int32_t map;      // offset of the source box's column map (t index of each column, -1 for padding)
+    int32_t map;      // offset of the source box's column map (t index of each column)
     int32_t part;     // -1: t written through the map; else offset of the item's partial row
     int32_t pad;
 };
 // A source box whose phase-A rows were split: t[map[c]] = sum of the
-// nparts partial rows (w4 values each, consecutive from pbeg).
+// nparts partial rows (w values each, consecutive from pbeg).
 struct AWRed {
-    int32_t pbeg, nparts, w4, map;
+    int32_t pbeg, nparts, w, map;
 };
 
 // Blocks whose phase-A work was split: t = sum of consecutive partials.
@@ -167,7 +168,7 @@ struct MRItem {
 struct MRBlk {
     int64_t voff;
     int32_t k, out;
-    int32_t blk, pad;   // the block; pad: the half pools' V row stride
+    int32_t blk, pad;   // the block; pad: the half pools' V row-group stride
 };
 
 // Static data of one instance for the table-driven multi-RHS kernels (a
@@ -289,12 +290,14 @@ struct Handle {
     DBuf<BDesc> bnear, bil;  // phase-B descriptors: near blocks, IL blocks
     DBuf<ADesc> aitems;
     // FP16/BF16 V pools, grouped by source box: for every source box (per
-    // level) the V of its low-rank blocks side by side, row j of the box
-    // holding each block's row j in table order, padded with zeros to w4 (a
-    // multiple of 4) values; block b's V starts at h_il_voff16[b] with row
-    // stride h_il_vld16[b].  Phase-A items over these rows (aw_items), the
-    // column maps to the t pool (aw_map), the reductions of split source
-    // boxes (aw_red) and their partial rows (p16_elems values).
+    // level) the V of its low-rank blocks side by side (w columns in table
+    // order), stored in groups of 4 rows: element (j, c) of the box at
+    // ((j / 4) w + c) 4 + j mod 4, the rows padded with zeros to a multiple
+    // of 4, so 4 rows of one column are one aligned 8-byte group.  Block
+    // b's element (j, q) sits at h_il_voff16[b] + (j / 4) h_il_vld16[b] + 4
+    // q + j mod 4.  Phase-A items over these rows (aw_items), the column
+    // maps to the t pool (aw_map), the reductions of split source boxes
+    // (aw_red) and their partial rows (p16_elems values).
     std::vector<int64_t> h_il_voff16;
     std::vector<int32_t> h_il_vld16;
     int64_t v16_elems = 0, p16_elems = 0;

@@ -222,14 +222,16 @@ k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ pp
 }
 
 // Phase A on the half pools, grouped by source box: one wave per item (at
-// most kPhaseARows rows of a source box's wide V, w4 values per row: the V
-// of every low-rank block with that source side by side).  The item's x
-// rows are staged in LDS.  With nc = w4 / 4 column groups per row, lane
-// (g, c) takes group c of rows g, g + G, ... (G = 64 / nc rows per load:
-// one aligned 8-byte load per lane, G whole rows per wave load) and the G
-// row-group sums of each column are added in a fixed order; wider rows
-// (nc > 64) are taken 64 groups per pass.  Each column's sum goes to its t
-// entry through the source box's column map, or to the item's partial row.
+// most kPhaseARows rows of a source box's wide V: the V of every low-rank
+// block with that source side by side, w columns, stored in groups of 4
+// rows so that 4 rows of one column are one aligned 8-byte group).  The
+// item's x rows are staged in LDS (zeros past its last row).  A lane owns
+// columns and walks the item's row groups: with w <= 64, lane (g, c) takes
+// column c of row groups g, g + G, ... (G = 64 / w) and the G sums of a
+// column are added in a fixed order; wider items take 64 columns per pass.
+// A wave load is 64 consecutive 8-byte groups (512 contiguous bytes) when
+// w >= 64.  Each column's sum goes to its t entry through the source box's
+// column map, or to the item's partial row.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_phaseA_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t* __restrict__ map,
@@ -237,70 +239,51 @@ k_phaseA_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t* _
               float* __restrict__ ppool)
 {
     __shared__ float xw[4][kPhaseARows];
-    __shared__ float red4[4][4 * kWave];
+    __shared__ float red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t it = (int64_t)blockIdx.x * 4 + wave;
     if (it >= nitems) return;
     const AWDesc D = items[it];
     const int64_t voff = uni(D.voff);
-    const int32_t rows = uni(D.rows), w4 = uni(D.w4), x0 = uni(D.x0), mo = uni(D.map), part = uni(D.part);
+    const int32_t rows = uni(D.rows), w = uni(D.w), x0 = uni(D.x0), mo = uni(D.map), part = uni(D.part);
+    const int32_t nq = (rows + 3) >> 2;
     float* xl = xw[wave];
-    for (int32_t j = lane; j < rows; j += kWave) xl[j] = xs[x0 + j];
+    for (int32_t j = lane; j < 4 * nq; j += kWave) xl[j] = j < rows ? xs[x0 + j] : 0.f;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    auto put = [&](int32_t q, float v) {
-        if (part >= 0) {
-            ppool[part + q] = v;
-        } else {
-            const int32_t m = map[mo + q];
-            if (m >= 0) tpool[m] = v;
-        }
+    auto put = [&](int32_t c, float v) {
+        if (part >= 0) ppool[part + c] = v;
+        else tpool[map[mo + c]] = v;
     };
-    const int32_t nc = w4 >> 2;
     const T* Vb = V + voff;
-    if (nc <= kWave) {
-        const int G = kWave / nc, g = lane / nc, c = lane % nc;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    const int64_t rg = 4 * (int64_t)w;   // elements per row group
+    auto quad = [&](int32_t jq, int32_t c) -> float {
+        const float4 v = ld4v<T>(Vb + jq * rg + 4 * c);
+        const float* xq = xl + 4 * jq;
+        return v.x * xq[0] + v.y * xq[1] + v.z * xq[2] + v.w * xq[3];
+    };
+    if (w <= kWave) {
+        const int G = kWave / w, g = lane / w, c = lane % w;
+        float a = 0.f;
         if (g < G) {
 #pragma unroll 8
-            for (int32_t j = g; j < rows; j += G) {
-                const float4 v = ld4v<T>(Vb + (int64_t)j * w4 + 4 * c);
-                const float xv = xl[j];
-                a0 += v.x * xv;
-                a1 += v.y * xv;
-                a2 += v.z * xv;
-                a3 += v.w * xv;
-            }
+            for (int32_t jq = g; jq < nq; jq += G) a += quad(jq, c);
         }
-        float* rw = red4[wave];
-        rw[4 * lane] = a0;
-        rw[4 * lane + 1] = a1;
-        rw[4 * lane + 2] = a2;
-        rw[4 * lane + 3] = a3;
+        red[wave][lane] = a;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        for (int32_t q = lane; q < w4; q += kWave) {
-            float acc = 0.f;
-            for (int gg = 0; gg < G; ++gg) acc += rw[4 * (gg * nc + (q >> 2)) + (q & 3)];
-            put(q, acc);
+        if (lane < w) {
+            float sum = 0.f;
+            for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * w + lane];
+            put(lane, sum);
         }
         return;
     }
-    for (int32_t c = lane; c < nc; c += kWave) {
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (int32_t c = lane; c < w; c += kWave) {
+        float a = 0.f;
 #pragma unroll 8
-        for (int32_t j = 0; j < rows; ++j) {
-            const float4 v = ld4v<T>(Vb + (int64_t)j * w4 + 4 * c);
-            const float xv = xl[j];
-            a0 += v.x * xv;
-            a1 += v.y * xv;
-            a2 += v.z * xv;
-            a3 += v.w * xv;
-        }
-        put(4 * c, a0);
-        put(4 * c + 1, a1);
-        put(4 * c + 2, a2);
-        put(4 * c + 3, a3);
+        for (int32_t jq = 0; jq < nq; ++jq) a += quad(jq, c);
+        put(c, a);
     }
 }
 
@@ -314,13 +297,11 @@ k_reduce_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict
     const int64_t r = blockIdx.x;
     if (r >= nr) return;
     const AWRed D = R[r];
-    for (int32_t q = threadIdx.x; q < D.w4; q += blockDim.x) {
-        const int32_t m = map[D.map + q];
-        if (m < 0) continue;
+    for (int32_t q = threadIdx.x; q < D.w; q += blockDim.x) {
         float s = 0.f;
 #pragma unroll 8
-        for (int32_t p = 0; p < D.nparts; ++p) s += ppool[D.pbeg + (int64_t)p * D.w4 + q];
-        tpool[m] = s;
+        for (int32_t p = 0; p < D.nparts; ++p) s += ppool[D.pbeg + (int64_t)p * D.w + q];
+        tpool[map[D.map + q]] = s;
     }
 }
 

@@ -256,12 +256,71 @@ __device__ __forceinline__ void srcA_tiles(typename MrT<T>::V4 (&acc)[4], const 
     }
 }
 
+// The 4 half values of one aligned 8-byte group, widened to FP32.
+template <typename T>
+__device__ __forceinline__ f4 quad_f32(uint64_t w)
+{
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    if constexpr (std::is_same<T, __half>::value)
+        return f4{__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
+                  __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
+                  __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu))),
+                  __half2float(__ushort_as_half((unsigned short)(hi >> 16)))};
+    else
+        return f4{__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
+                  __uint_as_float(hi & 0xffff0000u)};
+}
+
+// acc[t] (columns q0 + 16 t .. + 15 of T_b, t < NT) += V_b(rows, q)^T X(rows)
+// on the half V pools, where 4 rows of one column are one aligned 8-byte
+// group: V_b(j, q) at Vb[(j / 4) rg + 4 q + j mod 4].  A step takes 16
+// rows: lane group lk loads the row group j / 4 + lk of its column, and
+// instruction u takes row j + 4 lk + u of it as its k index lk; two steps
+// are loaded before their instructions.  Row groups past the item re-read
+// its last one (their X rows in LDS are zero); columns past k re-read
+// column k - 1 (dropped on output).
+template <typename T, int NT>
+__device__ __forceinline__ void srcA_tiles_q(f4 (&acc)[4], const T* __restrict__ Vb, int32_t k, int64_t rg,
+                                             int32_t q0, const float* xl, int32_t rows, int lane)
+{
+    const int li = lane % 16, lk = lane / 16;
+    const int32_t nq = (rows + 3) >> 2;
+    int64_t co[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) co[t] = 4 * (int64_t)min(q0 + 16 * t + li, k - 1);
+    for (int32_t j = 0; j < rows; j += 32) {
+        uint64_t w[2][NT];
+        float b[2][4];
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const int32_t jq = min(((j + 16 * st) >> 2) + lk, nq - 1);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                w[st][t] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(Vb + jq * rg + co[t]));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) b[st][u] = xl[(j + 16 * st + 4 * lk + u) * kR + li];
+        }
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            f4 a[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) a[t] = quad_f32<T>(w[st][t]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[st][u], acc[t], 0, 0, 0);
+        }
+    }
+}
+
 // Phase A grouped by source box: one workgroup per item stages the item's
 // rows of X in LDS once; its four waves take the blocks sharing that source
 // in turn, T (k x 16, row-major) = V(rows, :)^T X(rows, :), up to 4 M tiles
 // of 16 columns q per pass (on the half pools the block's U scale is
 // applied in phase B, with the U values).
-// Dynamic LDS: 16 values per row, rows rounded up to 16.
+// Dynamic LDS: 16 values per row, rows rounded up to 16 (FP64) or 32
+// (half pools).
 template <typename T>
 __device__ __forceinline__ void
 phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restrict__ V,
@@ -270,7 +329,8 @@ phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restric
 {
     using A = typename MrT<T>::A;
     using V4 = typename MrT<T>::V4;
-    const int32_t rows = it.j1 - it.j0, rpad = (rows + 15) & ~15;
+    // the half form takes rows 32 at a time
+    const int32_t rows = it.j1 - it.j0, rpad = sizeof(T) == 8 ? (rows + 15) & ~15 : (rows + 31) & ~31;
     const A* src = xs + (int64_t)(it.col0 + it.j0) * kR;
     for (int e = threadIdx.x; e < rpad * kR; e += blockDim.x) xl[e] = e < rows * kR ? src[e] : (A)0;
     __syncthreads();
@@ -280,20 +340,29 @@ phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restric
         const MRBlk B = blks[b];
         const int64_t voff = uni_l(B.voff);
         const int32_t k = uni_i(B.k), out = uni_i(B.out);
-        // FP64 V rows hold k values; the half pools hold the V of every
-        // block with this source side by side (row stride in B.pad)
-        const int32_t ldv = sizeof(T) == 8 ? k : uni_i(B.pad);
         A* Tt = out >= 0 ? tpool + (int64_t)out * kR : ppool + ((int64_t)(-out - 1) + (int64_t)it.p * k) * kR;
-        const T* Vb = V + voff + (int64_t)it.j0 * ldv;
         for (int32_t q0 = 0; q0 < k; q0 += 64) {
             V4 acc[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
             const int32_t nt = min(4, (k - q0 + 15) / 16);
-            if (nt == 4) srcA_tiles<T, 4>(acc, Vb, k, ldv, q0, xl, rows, lane);
-            else if (nt == 3) srcA_tiles<T, 3>(acc, Vb, k, ldv, q0, xl, rows, lane);
-            else if (nt == 2) srcA_tiles<T, 2>(acc, Vb, k, ldv, q0, xl, rows, lane);
-            else srcA_tiles<T, 1>(acc, Vb, k, ldv, q0, xl, rows, lane);
+            if constexpr (sizeof(T) == 8) {
+                // FP64 V: row-major, k values per row
+                const T* Vb = V + voff + (int64_t)it.j0 * k;
+                if (nt == 4) srcA_tiles<T, 4>(acc, Vb, k, k, q0, xl, rows, lane);
+                else if (nt == 3) srcA_tiles<T, 3>(acc, Vb, k, k, q0, xl, rows, lane);
+                else if (nt == 2) srcA_tiles<T, 2>(acc, Vb, k, k, q0, xl, rows, lane);
+                else srcA_tiles<T, 1>(acc, Vb, k, k, q0, xl, rows, lane);
+            } else {
+                // half V: the source box's row groups (stride B.pad); item
+                // chunks start at multiples of 4 rows
+                const int64_t rg = uni_i(B.pad);
+                const T* Vb = V + voff + (int64_t)(it.j0 >> 2) * rg;
+                if (nt == 4) srcA_tiles_q<T, 4>(acc, Vb, k, rg, q0, xl, rows, lane);
+                else if (nt == 3) srcA_tiles_q<T, 3>(acc, Vb, k, rg, q0, xl, rows, lane);
+                else if (nt == 2) srcA_tiles_q<T, 2>(acc, Vb, k, rg, q0, xl, rows, lane);
+                else srcA_tiles_q<T, 1>(acc, Vb, k, rg, q0, xl, rows, lane);
+            }
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -408,21 +477,6 @@ __device__ __forceinline__ void mm_tile(typename MrT<T>::V4 (&acc)[4], const T* 
     else if (rows > 32) mm_tiles<T, 3>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
     else if (rows > 16) mm_tiles<T, 2>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
     else mm_tiles<T, 1>(acc, Ab, lda, rows, Bb, ldb, K, bs, lane);
-}
-
-// The 4 half values of one aligned 8-byte group, widened to FP32.
-template <typename T>
-__device__ __forceinline__ f4 quad_f32(uint64_t w)
-{
-    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    if constexpr (std::is_same<T, __half>::value)
-        return f4{__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
-                  __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
-                  __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu))),
-                  __half2float(__ushort_as_half((unsigned short)(hi >> 16)))};
-    else
-        return f4{__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
-                  __uint_as_float(hi & 0xffff0000u)};
 }
 
 // acc[t] (rows 16 t .. 16 t + 15 of a slice, t < NT) += the products of
@@ -863,7 +917,7 @@ static void run_mr(Handle& H, const MRInst* I, const double* x, double* y, int n
         const int32_t nr = std::min(kR, nrhs - r0);
         k_gather_mr<A><<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
         if (H.n_mr_items)
-            k_phaseA_mr<T><<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(A), s>>>(I, nullptr,
+            k_phaseA_mr<T><<<(unsigned)H.n_mr_items, 256, (size_t)((R + 31) & ~31) * kR * sizeof(A), s>>>(I, nullptr,
                                                                                          (int32_t)H.n_mr_items);
         if (H.n_mr_ritems)
             k_reduce_mr<A><<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256, 0,

@@ -86,7 +86,7 @@ UBF = 2.0 ** -8    # unit roundoff of BF16
 
 
 @pytest.mark.parametrize("prec,u", [("fp16", U16), ("bf16", UBF)])
-@pytest.mark.parametrize("name", ["log4096", "mq5120_leaf100"])
+@pytest.mark.parametrize("name", ["log4096", "mq5120_leaf100", "top_half_300"])
 def test_half_multi_rhs_on_oracle_factors(orc, tmp_path, prec, u, name):
     """FP16 / BF16 pools made from the oracle's factors, 21 right-hand sides
     (a pass of 16 and a pass of 5): every row of every column within 4 u of
@@ -97,9 +97,13 @@ def test_half_multi_rhs_on_oracle_factors(orc, tmp_path, prec, u, name):
     from tests import npref
     if name == "log4096":
         xy, _, kern, leaf, tol = inputs.workload("log4096")
-    else:   # leaves of about 80 points: two 64-row passes per leaf
+    elif name == "mq5120_leaf100":   # leaves of about 80 points: two 64-row passes per leaf
         xy = np.random.default_rng(12).uniform(-1, 1, (5120, 2))
         kern, leaf, tol = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}, 100, 1e-10
+    else:   # top half of B only: kappa = 2, empty walks above the leaves' parents
+        g = np.random.default_rng(12)
+        xy = np.stack([g.uniform(-1, 1, 300), g.uniform(0.01, 1, 300)], 1)
+        kern, leaf, tol = {"kind": "mq", "c": 0.1, "diag_mode": "add", "diag_value": 1e-6}, 64, 1e-10
     n = xy.shape[0]
     O = orc.OracleH(xy, kern, leaf, tol)
     p = tmp_path / "o.h2dx"

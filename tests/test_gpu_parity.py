@@ -36,6 +36,10 @@ def _cases():
     c.append(("ragged_1337_leaf7", rng.uniform(-1, 1, (1337, 2)), MQ, 7, 1e-10))
     # leaves above 64 points: several 64-row chunks per leaf box
     c.append(("unif4000_leaf200", rng.uniform(-1, 1, (4000, 2)), MQ, 200, 1e-10))
+    # points in the top half of B only: the two level-1 boxes share an edge,
+    # so with kappa = 2 no block sits above the leaf level's parents and
+    # every phase-B1 walk (and half-pool table) of a level-1 box is empty
+    c.append(("top_half_300", np.stack([rng.uniform(-1, 1, 300), rng.uniform(0.01, 1, 300)], 1), MQ, 64, 1e-10))
     # points on cell boundaries, on the top / right edge of B, and at 0
     g = np.array([[-1.0, -1.0], [1.0, 1.0], [0.0, 0.0], [0.5, -0.5], [-0.5, 0.5], [1.0, -1.0], [-1.0, 1.0],
                   [0.25, 0.75], [0.0, 1.0], [1.0, 0.0]])
