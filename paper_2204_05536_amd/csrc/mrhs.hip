@@ -314,6 +314,74 @@ __device__ __forceinline__ void srcA_tiles_q(f4 (&acc)[4], const T* __restrict__
     }
 }
 
+// Phase A on the half pools: one workgroup per item of the source-grouped
+// schedule (at most kPhaseARows rows of a source box, all its low-rank
+// blocks side by side: w columns).  The item's X rows are staged in LDS
+// once; the 4 waves take 64-column groups of the wide row in turn, T (w x
+// 16) = V(rows, :)^T X(rows, :) on the matrix cores with no per-block
+// padding of the columns, and each column of T goes to its block's t
+// entry through the source box's column map, or to the item's partial row.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_phaseA_mr_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t* __restrict__ map,
+                 const T* __restrict__ V, const float* __restrict__ xs, float* __restrict__ tp,
+                 float* __restrict__ pp)
+{
+    __shared__ float xl[kPhaseARows * kR];
+    const int64_t it = blockIdx.x;
+    if (it >= nitems) return;
+    const AWDesc D = items[it];
+    const int64_t voff = uni_l(D.voff);
+    const int32_t rows = uni_i(D.rows), w = uni_i(D.w), x0 = uni_i(D.x0), mo = uni_i(D.map), part = uni_i(D.part);
+    const int32_t rpad = (rows + 31) & ~31;
+    const float* src = xs + (int64_t)x0 * kR;
+    for (int32_t e = threadIdx.x; e < rpad * kR; e += blockDim.x) xl[e] = e < rows * kR ? src[e] : 0.f;
+    __syncthreads();
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int li = lane % 16, lk = lane / 16;
+    const T* Vb = V + voff;
+    const int64_t rg = 4 * (int64_t)w;
+    for (int32_t c0 = 64 * wave; c0 < w; c0 += 4 * 64) {
+        f4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+        const int32_t nt = min(4, (w - c0 + 15) / 16);
+        if (nt == 4) srcA_tiles_q<T, 4>(acc, Vb, w, rg, c0, xl, rows, lane);
+        else if (nt == 3) srcA_tiles_q<T, 3>(acc, Vb, w, rg, c0, xl, rows, lane);
+        else if (nt == 2) srcA_tiles_q<T, 2>(acc, Vb, w, rg, c0, xl, rows, lane);
+        else srcA_tiles_q<T, 1>(acc, Vb, w, rg, c0, xl, rows, lane);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int32_t c = c0 + 16 * t + MrT<T>::row(v, lk);
+                if (t < nt && c < w) {
+                    float* dst = part >= 0 ? pp + (int64_t)(part + c) * kR : tp + (int64_t)map[mo + c] * kR;
+                    dst[li] = acc[t][v];
+                }
+            }
+    }
+}
+
+// T of the columns of source boxes whose phase-A rows were split (half
+// pools): the sum of the partial rows in part order, per column and
+// right-hand side.  One workgroup per source box.
+__global__ void __launch_bounds__(256)
+k_reduce_mr_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict__ map,
+                 const float* __restrict__ pp, float* __restrict__ tp)
+{
+    const int64_t r = blockIdx.x;
+    if (r >= nr) return;
+    const AWRed D = R[r];
+    for (int32_t e = threadIdx.x; e < D.w * kR; e += blockDim.x) {
+        const int32_t c = e / kR, rr = e % kR;
+        float s = 0.f;
+#pragma unroll 8
+        for (int32_t p = 0; p < D.nparts; ++p) s += pp[((int64_t)D.pbeg + (int64_t)p * D.w + c) * kR + rr];
+        tp[(int64_t)map[D.map + c] * kR + rr] = s;
+    }
+}
+
 // Phase A grouped by source box: one workgroup per item stages the item's
 // rows of X in LDS once; its four waves take the blocks sharing that source
 // in turn, T (k x 16, row-major) = V(rows, :)^T X(rows, :), up to 4 M tiles
@@ -879,7 +947,7 @@ static void ensure_mr16(Handle& H, hipStream_t s)
     const int32_t n = (int32_t)H.n;
     H.xs_mr32.alloc((size_t)n * kR);
     H.tp_mr32.alloc(std::max<int64_t>(H.t_elems, 1) * kR);
-    H.pp_mr32.alloc(std::max<int64_t>(H.mr_p_elems, 1) * kR);
+    H.pp_mr32.alloc(std::max<int64_t>(H.p16_elems, 1) * kR);
     H.yp_mr32.alloc((size_t)n * kR);
     H.yl_mr32.alloc((size_t)n * kR);
     MRInst I[2];
@@ -916,12 +984,23 @@ static void run_mr(Handle& H, const MRInst* I, const double* x, double* y, int n
     for (int r0 = 0; r0 < nrhs; r0 += kR) {
         const int32_t nr = std::min(kR, nrhs - r0);
         k_gather_mr<A><<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
-        if (H.n_mr_items)
-            k_phaseA_mr<T><<<(unsigned)H.n_mr_items, 256, (size_t)((R + 31) & ~31) * kR * sizeof(A), s>>>(I, nullptr,
-                                                                                         (int32_t)H.n_mr_items);
-        if (H.n_mr_ritems)
-            k_reduce_mr<A><<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256, 0,
-                             s>>>(I, nullptr, (int32_t)H.n_mr_ritems);
+        if constexpr (sizeof(T) == 2) {
+            // the half V pools: the source-grouped items of the single-RHS form
+            const T* V = (const T*)(std::is_same<T, __half>::value ? (const void*)H.V16.p : (const void*)H.Vb16.p);
+            if (H.n_aw_items)
+                k_phaseA_mr_wide<T><<<(unsigned)H.n_aw_items, 256, 0, s>>>(H.n_aw_items, H.aw_items.p, H.aw_map.p, V,
+                                                                            H.xs_mr32.p, H.tp_mr32.p, H.pp_mr32.p);
+            if (H.n_aw_red)
+                k_reduce_mr_wide<<<(unsigned)H.n_aw_red, 256, 0, s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, H.pp_mr32.p,
+                                                                      H.tp_mr32.p);
+        } else {
+            if (H.n_mr_items)
+                k_phaseA_mr<T><<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(A), s>>>(I, nullptr,
+                                                                                             (int32_t)H.n_mr_items);
+            if (H.n_mr_ritems)
+                k_reduce_mr<A><<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256,
+                                 0, s>>>(I, nullptr, (int32_t)H.n_mr_ritems);
+        }
         const int32_t nb1 = (int32_t)((H.n_b1 + 3) / 4), nb2 = (nleaf + 3) / 4;
         k_phaseB_mr<T><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(I, nb1, nullptr, (int32_t)H.n_b1, nullptr, nleaf);
         k_scatter_mr<A><<<(unsigned)pblocks, 256, 0, s>>>(I, nullptr, pblocks, io, nullptr, r0, nr);
