@@ -1384,10 +1384,10 @@ __global__ void k_half_v(const HalfVJob* jobs, const double* src, T* dst)
 // The half V pools grouped by source box: for every source box (per
 // level) the V of its low-rank blocks side by side (table order), stored in
 // groups of 4 rows (element (j, c) at ((j / 4) w + c) 4 + j mod 4, rows
-// padded with zeros to a multiple of 4).  Sets the blocks' offsets and
-// row-group strides, the phase-A items (at most kPhaseARows rows of one
-// source box each, largest first), the column maps to the t pool and the
-// reductions of split source boxes; returns the conversion jobs.
+// padded with zeros to a multiple of 4).  Sets the phase-A items (at most
+// kPhaseARows rows of one source box each, largest first), the column maps
+// to the t pool and the reductions of split source boxes; returns the
+// conversion jobs.
 static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
 {
     std::vector<int64_t> order;
@@ -1396,8 +1396,6 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
         return H.h_il_level[a] != H.h_il_level[b] ? H.h_il_level[a] < H.h_il_level[b] : H.h_il_src[a] < H.h_il_src[b];
     });
-    H.h_il_voff16.assign(H.n_il, 0);
-    H.h_il_vld16.assign(H.n_il, 0);
     std::vector<HalfVJob> jobs;
     std::vector<AWDesc> items;
     std::vector<AWRed> red;
@@ -1416,8 +1414,6 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
         for (size_t b = i; b < e; ++b) {
             const int64_t q = order[b];
             const int32_t k = H.h_il_k[q];
-            H.h_il_voff16[q] = vo + 4 * (int64_t)c0;
-            H.h_il_vld16[q] = 4 * w;
             jobs.push_back(HalfVJob{H.h_il_voff[q], vo + 4 * (int64_t)c0, ny, k, 4 * w, 0});
             for (int32_t c = 0; c < k; ++c) map.push_back(H.h_il_toff[q] + c);
             c0 += k;

@@ -168,7 +168,7 @@ struct MRItem {
 struct MRBlk {
     int64_t voff;
     int32_t k, out;
-    int32_t blk, pad;   // the block; pad: the half pools' V row-group stride
+    int32_t blk, pad;   // the block
 };
 
 // Static data of one instance for the table-driven multi-RHS kernels (a
@@ -293,13 +293,10 @@ struct Handle {
     // level) the V of its low-rank blocks side by side (w columns in table
     // order), stored in groups of 4 rows: element (j, c) of the box at
     // ((j / 4) w + c) 4 + j mod 4, the rows padded with zeros to a multiple
-    // of 4, so 4 rows of one column are one aligned 8-byte group.  Block
-    // b's element (j, q) sits at h_il_voff16[b] + (j / 4) h_il_vld16[b] + 4
-    // q + j mod 4.  Phase-A items over these rows (aw_items), the column
-    // maps to the t pool (aw_map), the reductions of split source boxes
-    // (aw_red) and their partial rows (p16_elems values).
-    std::vector<int64_t> h_il_voff16;
-    std::vector<int32_t> h_il_vld16;
+    // of 4, so 4 rows of one column are one aligned 8-byte group.
+    // Phase-A items over these rows (aw_items), the column maps to the t
+    // pool (aw_map), the reductions of split source boxes (aw_red) and
+    // their partial rows (p16_elems values).
     int64_t v16_elems = 0, p16_elems = 0;
     DBuf<AWDesc> aw_items;
     DBuf<int32_t> aw_map;
@@ -327,10 +324,10 @@ struct Handle {
     int64_t n_mr_items = 0, n_mr_ritems = 0, mr_p_elems = 0;
     std::vector<int64_t> h_mr_work;  // work of each multi-RHS phase-A item, in schedule order
     DBuf<MRInst> mr_inst;            // this handle's entry for the table-driven kernels
-    // the same schedule on the half pools (FP32 work vectors, V offsets of
-    // the padded half V pools), built on the first half-precision product
+    // the half-pool form (FP32 work vectors; phase A on the source-grouped
+    // items, phase B on the tables), set up on the first half-precision
+    // multi-RHS product
     DBuf<float> xs_mr32, tp_mr32, pp_mr32, yp_mr32, yl_mr32;
-    DBuf<MRBlk> mr_blks16;
     DBuf<MRInst> mr_inst16;          // [FP16, BF16]
     int mr16_cap = 0;
     int32_t mr_rows = 256;           // source rows per multi-RHS phase-A item (tuned by h2d_autotune)

@@ -397,8 +397,7 @@ phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restric
 {
     using A = typename MrT<T>::A;
     using V4 = typename MrT<T>::V4;
-    // the half form takes rows 32 at a time
-    const int32_t rows = it.j1 - it.j0, rpad = sizeof(T) == 8 ? (rows + 15) & ~15 : (rows + 31) & ~31;
+    const int32_t rows = it.j1 - it.j0, rpad = (rows + 15) & ~15;
     const A* src = xs + (int64_t)(it.col0 + it.j0) * kR;
     for (int e = threadIdx.x; e < rpad * kR; e += blockDim.x) xl[e] = e < rows * kR ? src[e] : (A)0;
     __syncthreads();
@@ -414,23 +413,11 @@ phaseA_item(const MRItem& it, const MRBlk* __restrict__ blks, const T* __restric
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
             const int32_t nt = min(4, (k - q0 + 15) / 16);
-            if constexpr (sizeof(T) == 8) {
-                // FP64 V: row-major, k values per row
-                const T* Vb = V + voff + (int64_t)it.j0 * k;
-                if (nt == 4) srcA_tiles<T, 4>(acc, Vb, k, k, q0, xl, rows, lane);
-                else if (nt == 3) srcA_tiles<T, 3>(acc, Vb, k, k, q0, xl, rows, lane);
-                else if (nt == 2) srcA_tiles<T, 2>(acc, Vb, k, k, q0, xl, rows, lane);
-                else srcA_tiles<T, 1>(acc, Vb, k, k, q0, xl, rows, lane);
-            } else {
-                // half V: the source box's row groups (stride B.pad); item
-                // chunks start at multiples of 4 rows
-                const int64_t rg = uni_i(B.pad);
-                const T* Vb = V + voff + (int64_t)(it.j0 >> 2) * rg;
-                if (nt == 4) srcA_tiles_q<T, 4>(acc, Vb, k, rg, q0, xl, rows, lane);
-                else if (nt == 3) srcA_tiles_q<T, 3>(acc, Vb, k, rg, q0, xl, rows, lane);
-                else if (nt == 2) srcA_tiles_q<T, 2>(acc, Vb, k, rg, q0, xl, rows, lane);
-                else srcA_tiles_q<T, 1>(acc, Vb, k, rg, q0, xl, rows, lane);
-            }
+            const T* Vb = V + voff + (int64_t)it.j0 * k;   // row-major, k values per row
+            if (nt == 4) srcA_tiles<T, 4>(acc, Vb, k, k, q0, xl, rows, lane);
+            else if (nt == 3) srcA_tiles<T, 3>(acc, Vb, k, k, q0, xl, rows, lane);
+            else if (nt == 2) srcA_tiles<T, 2>(acc, Vb, k, k, q0, xl, rows, lane);
+            else srcA_tiles<T, 1>(acc, Vb, k, k, q0, xl, rows, lane);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -874,16 +861,6 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
         HIPCK(hipMemcpyAsync(H.mr_blks.p, blks.data(), sizeof(MRBlk) * blks.size(), hipMemcpyHostToDevice, s));
     if (!red.empty())
         HIPCK(hipMemcpyAsync(H.mr_ritems.p, red.data(), sizeof(RDesc) * red.size(), hipMemcpyHostToDevice, s));
-    if (H.v16_elems > 0) {   // the same blocks on the padded half V pools
-        std::vector<MRBlk> b16(blks);
-        for (MRBlk& B : b16) {
-            B.voff = H.h_il_voff16[B.blk];
-            B.pad = H.h_il_vld16[B.blk];   // row stride: the source box's wide rows
-        }
-        H.mr_blks16.alloc(std::max<size_t>(b16.size(), 1));
-        if (!b16.empty())
-            HIPCK(hipMemcpyAsync(H.mr_blks16.p, b16.data(), sizeof(MRBlk) * b16.size(), hipMemcpyHostToDevice, s));
-    }
     H.n_mr_items = (int64_t)sorted.size();
     H.n_mr_ritems = (int64_t)red.size();
     H.mr_p_elems = poff;
@@ -958,7 +935,6 @@ static void ensure_mr16(Handle& H, hipStream_t s)
         I[h].D = addr(h ? (const void*)H.Db16.p : (const void*)H.D16.p);
         I[h].xs = addr(H.xs_mr32.p); I[h].tp = addr(H.tp_mr32.p); I[h].pp = addr(H.pp_mr32.p);
         I[h].yp = addr(H.yp_mr32.p); I[h].yl = addr(H.yl_mr32.p);
-        I[h].blks = addr(H.mr_blks16.p);
         I[h].qp1 = addr(H.qp1.p); I[h].qt1 = addr(H.qt1.p);
         I[h].qp2 = addr(H.qp2.p); I[h].qt2 = addr(H.qt2.p);
         I[h].scale = addr(H.scale16.p);
