@@ -1300,15 +1300,20 @@ void build_factors(Handle& H, hipStream_t s)
 // the leaves, as in the FP64 pool; any other block is one tile) is laid out
 // as [column quads][rows][4], so the 4 values of one row in 4 consecutive
 // columns form one aligned 8-byte group; the columns are padded with zeros
-// to a multiple of 4.  Element (i, c) of a p-row tile sits at
-// (floor(c / 4) p + i) 4 + c mod 4, and the tile of a k-column block whose
-// first row is row b of the block starts at k4 b (k4 = k rounded up to 4).
+// to a multiple of 4 and the rows to a multiple of 16 (so every column
+// quad of a tile starts on a 128-byte line, and a 64-row slice of one
+// quad is four whole lines).  Element (i, c) of a tile of p rows (p16
+// rounded) sits at (floor(c / 4) p16 + i) 4 + c mod 4; the tiles of a
+// k-column block follow one another, each k4 p16 values (k4 = k rounded
+// up to 4).
 struct HalfJob {
-    int64_t src, dst;     // FP64 offset, half offset (a multiple of 4)
+    int64_t src, dst;     // FP64 offset, half offset (a multiple of 64)
     int32_t m, n;         // rows, columns (the rank for U)
     int32_t tiled, self;  // U tiled as above; 1 if a self block
-    int32_t row0, pad;    // first tree row of the block
+    int32_t row0, m16;    // first tree row of the block; rows rounded up to 16 (untiled blocks)
 };
+
+__host__ __device__ constexpr int32_t pad16(int32_t m) { return (m + 15) & ~15; }
 
 template <typename T>
 __device__ __forceinline__ T to_half(float v);
@@ -1317,9 +1322,12 @@ __device__ __forceinline__ __half to_half<__half>(float v) { return __float2half
 template <>
 __device__ __forceinline__ __hip_bfloat16 to_half<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
 
+// tbeg, tcnt: per tree row, the first row and the size of its box one
+// level above the leaves; tpad: per tree row, where that box's padded
+// tile starts among the padded tiles of all such boxes (in rows).
 template <typename T>
 __global__ void k_half_q(const HalfJob* jobs, const double* src, T* dst, float* scale, float* diag,
-                         const int32_t* tbeg, const int32_t* tcnt)
+                         const int32_t* tbeg, const int32_t* tcnt, const int64_t* tpad)
 {
     __shared__ double lv[256];
     const HalfJob J = jobs[blockIdx.x];
@@ -1349,15 +1357,19 @@ __global__ void k_half_q(const HalfJob* jobs, const double* src, T* dst, float* 
     const int64_t n4 = (J.n + 3) & ~3;
     for (int64_t e = threadIdx.x; e < (int64_t)J.m * n4; e += blockDim.x) {
         const int64_t c = e / J.m, i = e % J.m;
-        int64_t pb = 0, pc = J.m;   // the tile holding row i: its first row (in the block), its rows
+        // the tile holding row i: its first row in the block (pb), rows (pc),
+        // padded rows (p16) and start in the block's padded rows (tb)
+        int64_t pb = 0, pc = J.m, p16 = J.m16, tb = 0;
         if (J.tiled) {
             pb = tbeg[J.row0 + i] - J.row0;
             pc = tcnt[J.row0 + i];
+            p16 = pad16((int32_t)pc);
+            tb = tpad[J.row0 + i] - tpad[J.row0];
         }
         const bool d = J.self && i == c;
         double v = 0.0;
         if (c < J.n) v = src[J.src + (J.tiled ? (int64_t)J.n * pb + c * pc + (i - pb) : c * J.m + i)];
-        dst[J.dst + n4 * pb + ((c >> 2) * pc + (i - pb)) * 4 + (c & 3)] = to_half<T>(d ? 0.0f : (float)(v * inv));
+        dst[J.dst + n4 * tb + ((c >> 2) * p16 + (i - pb)) * 4 + (c & 3)] = to_half<T>(d ? 0.0f : (float)(v * inv));
         if (d) diag[J.row0 + i] = (float)v;
     }
 }
@@ -1382,9 +1394,10 @@ __global__ void k_half_v(const HalfVJob* jobs, const double* src, T* dst)
 }
 
 // The half V pools grouped by source box: for every source box (per
-// level) the V of its low-rank blocks side by side (table order), stored in
-// groups of 4 rows (element (j, c) at ((j / 4) w + c) 4 + j mod 4, rows
-// padded with zeros to a multiple of 4).  Sets the phase-A items (at most
+// level) the V of its low-rank blocks side by side (table order, w
+// columns), stored in groups of 4 rows (element (j, c) at ((j / 4) ws + c)
+// 4 + j mod 4, ws = w rounded up to 16, rows padded with zeros to a
+// multiple of 4).  Sets the phase-A items (at most
 // kPhaseARows rows of one source box each, largest first), the column maps
 // to the t pool and the reductions of split source boxes; returns the
 // conversion jobs.
@@ -1407,6 +1420,7 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
         while (e < order.size() && H.h_il_level[order[e]] == H.h_il_level[order[i]] &&
                H.h_il_src[order[e]] == H.h_il_src[order[i]])
             w += H.h_il_k[order[e++]];
+        const int32_t ws = pad16(w);   // row-group width: every row group starts on a 128-byte line
         const Level& L = H.lev[H.h_il_level[order[i]]];
         const int32_t ny = L.h_count[H.h_il_src[order[i]]], y0 = L.h_begin[H.h_il_src[order[i]]];
         const int32_t mo = (int32_t)map.size();
@@ -1414,15 +1428,15 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
         for (size_t b = i; b < e; ++b) {
             const int64_t q = order[b];
             const int32_t k = H.h_il_k[q];
-            jobs.push_back(HalfVJob{H.h_il_voff[q], vo + 4 * (int64_t)c0, ny, k, 4 * w, 0});
+            jobs.push_back(HalfVJob{H.h_il_voff[q], vo + 4 * (int64_t)c0, ny, k, 4 * ws, 0});
             for (int32_t c = 0; c < k; ++c) map.push_back(H.h_il_toff[q] + c);
             c0 += k;
         }
         const int32_t parts = (ny + kPhaseARows - 1) / kPhaseARows;   // kPhaseARows: a multiple of 4
         for (int32_t p = 0; p < parts; ++p) {
             const int32_t j0 = p * kPhaseARows, rows = std::min(kPhaseARows, ny - j0);
-            items.push_back(AWDesc{vo + (int64_t)(j0 / 4) * 4 * w, rows, w, y0 + j0, mo,
-                                   parts > 1 ? (int32_t)(po + (int64_t)p * w) : -1, 0});
+            items.push_back(AWDesc{vo + (int64_t)(j0 / 4) * 4 * ws, rows, w, y0 + j0, mo,
+                                   parts > 1 ? (int32_t)(po + (int64_t)p * w) : -1, ws});
         }
         if (parts > 1) {
             red.push_back(AWRed{(int32_t)po, parts, w, mo});
@@ -1431,7 +1445,7 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
         } else {
             t_direct += w;
         }
-        vo += (int64_t)((ny + 3) / 4) * 4 * w;
+        vo += (int64_t)((ny + 3) / 4) * 4 * ws;
         i = e;
     }
     if (po > INT32_MAX || map.size() > (size_t)INT32_MAX)
@@ -1463,7 +1477,7 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
 // interaction-list blocks.  A row slice of the box sums its table's groups
 // in order.
 static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16, const std::vector<float>& sc,
-                              hipStream_t s)
+                              const std::vector<int64_t>& tpad, hipStream_t s)
 {
     const int kappa = H.kappa;
     std::vector<QEnt> t1, t2;
@@ -1492,12 +1506,12 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
                 for (int32_t q = L.h_il_ptr[a_box]; q < L.h_il_ptr[a_box + 1]; ++q) {
                     if (H.h_il_kind[q] == kDense) {
                         const int32_t sb = H.h_il_src[q];
-                        put(t1, H.h_il_off16[q] + (int64_t)(p0 - ab) * 4, (int64_t)ldm * 4, L.h_count[sb], L.h_begin[sb],
-                            true, sc[q]);
+                        put(t1, H.h_il_off16[q] + (int64_t)(p0 - ab) * 4, (int64_t)pad16(ldm) * 4, L.h_count[sb],
+                            L.h_begin[sb], true, sc[q]);
                     } else if (H.h_il_k[q] > 0) {
                         const int32_t k = H.h_il_k[q];
-                        put(t1, H.h_il_off16[q] + (int64_t)((k + 3) & ~3) * (p0 - ab), (int64_t)cnt * 4, k,
-                            H.h_il_toff[q], false, sc[q]);
+                        put(t1, H.h_il_off16[q] + (int64_t)((k + 3) & ~3) * (tpad[p0] - tpad[ab]),
+                            (int64_t)pad16(cnt) * 4, k, H.h_il_toff[q], false, sc[q]);
                     }
                 }
                 a_box = L.h_parent[a_box];
@@ -1507,7 +1521,7 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
     }
     const Level& LL = H.lev[kappa];
     for (int64_t X = 0; X < LL.nbox; ++X) {
-        const int64_t qs = (int64_t)LL.h_count[X] * 4;
+        const int64_t qs = (int64_t)pad16(LL.h_count[X]) * 4;
         for (int32_t q = H.h_near_ptr[X]; q < H.h_near_ptr[X + 1]; ++q) {
             const int32_t y = H.h_near_src[q];
             put(t2, near_off16[q], qs, LL.h_count[y], LL.h_begin[y], true, sc[H.n_il + q]);
@@ -1536,6 +1550,27 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     // jobs: IL blocks (U or D) in table order, then near blocks; each pool
     // gets quad-layout offsets of its own, and the descriptors the half
     // product kernels read
+    // tree row -> first row, size and padded-tile start of its box one
+    // level above the leaves
+    std::vector<int32_t> hb(std::max<int64_t>(H.n, 1), 0), hc(std::max<int64_t>(H.n, 1), 0);
+    std::vector<int64_t> hp(std::max<int64_t>(H.n, 1), 0);
+    if (kappa >= 1) {
+        const Level& T = H.lev[kappa - 1];
+        int64_t g = 0;
+        for (int64_t p = 0; p < T.nbox; ++p) {
+            for (int32_t i = T.h_begin[p]; i < T.h_begin[p] + T.h_count[p]; ++i) {
+                hb[i] = T.h_begin[p];
+                hc[i] = T.h_count[p];
+                hp[i] = g;
+            }
+            g += pad16(T.h_count[p]);
+        }
+    }
+    // padded rows of a tiled block whose rows are [r0, r0 + m)
+    auto tiled_rows = [&](int32_t r0, int32_t m) -> int64_t {
+        const int32_t r1 = r0 + m - 1;
+        return hp[r1] + pad16(hc[r1]) - hp[r0];
+    };
     std::vector<HalfJob> jobs;
     H.h_il_off16.assign(H.n_il, 0);
     int64_t uo = 0, dof = 0;
@@ -1545,14 +1580,14 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         const int32_t row0 = L.h_begin[H.h_il_tgt[q]];
         if (H.h_il_kind[q] == kDense) {
             H.h_il_off16[q] = dof;
-            jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, 0});
-            dof += (int64_t)mm * ((nn + 3) & ~3);
+            jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, pad16(mm)});
+            dof += (int64_t)pad16(mm) * ((nn + 3) & ~3);
         } else {
             const int32_t k = H.h_il_k[q];
             const int32_t tiled = H.h_il_level[q] <= kappa - 1 ? 1 : 0;
             H.h_il_off16[q] = uo;
-            jobs.push_back(HalfJob{H.h_il_off[q], uo, mm, k, tiled, 0, row0, 0});
-            uo += (int64_t)mm * ((k + 3) & ~3);
+            jobs.push_back(HalfJob{H.h_il_off[q], uo, mm, k, tiled, 0, row0, pad16(mm)});
+            uo += (tiled ? tiled_rows(row0, mm) : (int64_t)pad16(mm)) * ((k + 3) & ~3);
         }
     }
     const Level& LL = H.lev[kappa];
@@ -1562,8 +1597,8 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
             const int32_t y = H.h_near_src[q];
             near_off16[q] = dof;
             jobs.push_back(HalfJob{H.h_near_off[q], dof, LL.h_count[x], LL.h_count[y], 0, y == (int32_t)x ? 1 : 0,
-                                   LL.h_begin[x], 0});
-            dof += (int64_t)LL.h_count[x] * ((LL.h_count[y] + 3) & ~3);
+                                   LL.h_begin[x], pad16(LL.h_count[x])});
+            dof += (int64_t)pad16(LL.h_count[x]) * ((LL.h_count[y] + 3) & ~3);
         }
     H.u16_elems = uo;
     H.d16_elems = dof;
@@ -1583,21 +1618,11 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     std::vector<HalfVJob> vjobs = wide_v_layout(H, s);
     DBuf<HalfVJob> dv;
     upload(dv, vjobs, s);
-    // tree row -> first row and size of its box one level above the leaves
     DBuf<int32_t> tbeg, tcnt;
-    {
-        std::vector<int32_t> hb(std::max<int64_t>(H.n, 1), 0), hc(std::max<int64_t>(H.n, 1), 0);
-        if (kappa >= 1) {
-            const Level& T = H.lev[kappa - 1];
-            for (int64_t p = 0; p < T.nbox; ++p)
-                for (int32_t i = T.h_begin[p]; i < T.h_begin[p] + T.h_count[p]; ++i) {
-                    hb[i] = T.h_begin[p];
-                    hc[i] = T.h_count[p];
-                }
-        }
-        upload(tbeg, hb, s);
-        upload(tcnt, hc, s);
-    }
+    DBuf<int64_t> tpad;
+    upload(tbeg, hb, s);
+    upload(tcnt, hc, s);
+    upload(tpad, hp, s);
     DBuf<float> su, sd;
     su.alloc(std::max<size_t>(ujobs.size(), 1));
     sd.alloc(std::max<size_t>(djobs.size(), 1));
@@ -1607,11 +1632,11 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         using T = std::remove_pointer_t<decltype(Up)>;
         for (size_t o = 0; o < ujobs.size(); o += 1u << 20) {
             unsigned c = (unsigned)std::min<size_t>(1u << 20, ujobs.size() - o);
-            k_half_q<T><<<c, 256, 0, s>>>(du.p + o, H.U64.p, Up, su.p + o, H.diag32.p, tbeg.p, tcnt.p);
+            k_half_q<T><<<c, 256, 0, s>>>(du.p + o, H.U64.p, Up, su.p + o, H.diag32.p, tbeg.p, tcnt.p, tpad.p);
         }
         for (size_t o = 0; o < djobs.size(); o += 1u << 20) {
             unsigned c = (unsigned)std::min<size_t>(1u << 20, djobs.size() - o);
-            k_half_q<T><<<c, 256, 0, s>>>(dd.p + o, H.D64.p, Dp, sd.p + o, H.diag32.p, tbeg.p, tcnt.p);
+            k_half_q<T><<<c, 256, 0, s>>>(dd.p + o, H.D64.p, Dp, sd.p + o, H.diag32.p, tbeg.p, tcnt.p, tpad.p);
         }
         for (size_t o = 0; o < vjobs.size(); o += 1u << 20) {
             unsigned c = (unsigned)std::min<size_t>(1u << 20, vjobs.size() - o);
@@ -1626,18 +1651,22 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         buf.alloc((size_t)elems + kHalfSlack);
         HIPCK(hipMemsetAsync(buf.p + elems, 0, sizeof(T) * kHalfSlack, s));
     };
+    // the pools are zeroed first: that fills the padding rows and columns
+    auto zero_half = [&](auto& buf, int64_t elems) {
+        using T = std::remove_pointer_t<decltype(buf.p)>;
+        alloc_half(buf, elems);
+        HIPCK(hipMemsetAsync(buf.p, 0, sizeof(T) * elems, s));
+    };
     if (f16) {
-        alloc_half(H.U16, H.u16_elems);
-        alloc_half(H.V16, H.v16_elems);
-        HIPCK(hipMemsetAsync(H.V16.p, 0, sizeof(__half) * H.v16_elems, s));
-        alloc_half(H.D16, H.d16_elems);
+        zero_half(H.U16, H.u16_elems);
+        zero_half(H.V16, H.v16_elems);
+        zero_half(H.D16, H.d16_elems);
         run(H.U16.p, H.V16.p, H.D16.p);
     }
     if (b16) {
-        alloc_half(H.Ub16, H.u16_elems);
-        alloc_half(H.Vb16, H.v16_elems);
-        HIPCK(hipMemsetAsync(H.Vb16.p, 0, sizeof(__hip_bfloat16) * H.v16_elems, s));
-        alloc_half(H.Db16, H.d16_elems);
+        zero_half(H.Ub16, H.u16_elems);
+        zero_half(H.Vb16, H.v16_elems);
+        zero_half(H.Db16, H.d16_elems);
         run(H.Ub16.p, H.Vb16.p, H.Db16.p);
     }
     // one scale per IL block then per near block (table order)
@@ -1647,7 +1676,7 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
     for (size_t q = 0; q < uidx.size(); ++q) sc[uidx[q]] = hsu[q];
     for (size_t q = 0; q < didx.size(); ++q) sc[didx[q]] = hsd[q];
     upload(H.scale16, sc, s);
-    build_quad_tables(H, near_off16, sc, s);
+    build_quad_tables(H, near_off16, sc, hp, s);
     HIPCK(hipStreamSynchronize(s));
     H.prec_mask |= mask & (H2D_PREC_BIT(H2D_P_FP16) | H2D_PREC_BIT(H2D_P_BF16));
 }

@@ -131,15 +131,16 @@ struct ADesc {
 };
 
 // Phase A on the half pools, grouped by source box: rows of one source
-// box's wide V (the V of all its low-rank blocks side by side, stored in
-// groups of 4 rows: element (j, c) at ((j / 4) w + c) 4 + j mod 4).
+// box's wide V (the V of all its low-rank blocks side by side, w columns,
+// stored in groups of 4 rows: element (j, c) at ((j / 4) ws + c) 4 + j mod
+// 4, ws = w rounded up to 16).
 struct AWDesc {
     int64_t voff;     // element offset of the item's first row group
     int32_t rows, w;  // rows (at most kPhaseARows, a multiple of 4 unless last), width
     int32_t x0;       // tree index of the item's first row
     int32_t map;      // offset of the source box's column map (t index of each column)
     int32_t part;     // -1: t written through the map; else offset of the item's partial row
-    int32_t pad;
+    int32_t ws;       // row-group width
 };
 // A source box whose phase-A rows were split: t[map[c]] = sum of the
 // nparts partial rows (w values each, consecutive from pbeg).
@@ -275,7 +276,8 @@ struct Handle {
     DBuf<__half> U16, V16, D16;
     DBuf<__hip_bfloat16> Ub16, Vb16, Db16;
     // half U and D pools in the quad layout (every tile [column quads][rows][4],
-    // columns padded to a multiple of 4) at offsets of their own, and the
+    // columns padded to a multiple of 4, rows to a multiple of 16) at offsets
+    // of their own, and the
     // phase-B tables: per box one level above the leaves (qt1) and per leaf
     // (qt2), every 4-column group its row slices multiply, in summation order
     std::vector<int64_t> h_il_off16;
@@ -292,8 +294,10 @@ struct Handle {
     // FP16/BF16 V pools, grouped by source box: for every source box (per
     // level) the V of its low-rank blocks side by side (w columns in table
     // order), stored in groups of 4 rows: element (j, c) of the box at
-    // ((j / 4) w + c) 4 + j mod 4, the rows padded with zeros to a multiple
-    // of 4, so 4 rows of one column are one aligned 8-byte group.
+    // ((j / 4) ws + c) 4 + j mod 4 (ws = w rounded up to 16), the rows
+    // padded with zeros to a multiple of 4, so 4 rows of one column are
+    // one aligned 8-byte group and every row group starts on a 128-byte
+    // line.
     // Phase-A items over these rows (aw_items), the column maps to the t
     // pool (aw_map), the reductions of split source boxes (aw_red) and
     // their partial rows (p16_elems values).

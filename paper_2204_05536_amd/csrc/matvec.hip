@@ -224,7 +224,8 @@ k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ pp
 // Phase A on the half pools, grouped by source box: one wave per item (at
 // most kPhaseARows rows of a source box's wide V: the V of every low-rank
 // block with that source side by side, w columns, stored in groups of 4
-// rows so that 4 rows of one column are one aligned 8-byte group).  The
+// rows so that 4 rows of one column are one aligned 8-byte group, each
+// group of rows ws >= w columns wide).  The
 // item's x rows are staged in LDS (zeros past its last row).  A lane owns
 // columns and walks the item's row groups: with w <= 64, lane (g, c) takes
 // column c of row groups g, g + G, ... (G = 64 / w) and the G sums of a
@@ -256,7 +257,7 @@ k_phaseA_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t* _
         else tpool[map[mo + c]] = v;
     };
     const T* Vb = V + voff;
-    const int64_t rg = 4 * (int64_t)w;   // elements per row group
+    const int64_t rg = 4 * (int64_t)uni(D.ws);   // elements per row group
     auto quad = [&](int32_t jq, int32_t c) -> float {
         const float4 v = ld4v<T>(Vb + jq * rg + 4 * c);
         const float* xq = xl + 4 * jq;

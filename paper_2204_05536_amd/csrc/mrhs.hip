@@ -340,7 +340,7 @@ k_phaseA_mr_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int li = lane % 16, lk = lane / 16;
     const T* Vb = V + voff;
-    const int64_t rg = 4 * (int64_t)w;
+    const int64_t rg = 4 * (int64_t)uni_i(D.ws);
     for (int32_t c0 = 64 * wave; c0 < w; c0 += 4 * 64) {
         f4 acc[4];
 #pragma unroll
