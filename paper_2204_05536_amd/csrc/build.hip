@@ -1300,17 +1300,18 @@ void build_factors(Handle& H, hipStream_t s)
 // the leaves, as in the FP64 pool; any other block is one tile) is laid out
 // as [column quads][rows][4], so the 4 values of one row in 4 consecutive
 // columns form one aligned 8-byte group; the columns are padded with zeros
-// to a multiple of 4 and the rows to a multiple of 16 (so every column
-// quad of a tile starts on a 128-byte line, and a 64-row slice of one
-// quad is four whole lines).  Element (i, c) of a tile of p rows (p16
-// rounded) sits at (floor(c / 4) p16 + i) 4 + c mod 4; the tiles of a
-// k-column block follow one another, each k4 p16 values (k4 = k rounded
-// up to 4).
+// to a multiple of 4, and the rows of the tiles of a U above the leaf
+// level to a multiple of 16 (so each of its column quads starts on a
+// 128-byte line and a 64-row slice of one quad is four whole lines; the
+// other tiles are read whole, where padding would only leave partly used
+// lines).  Element (i, c) of a tile of p rows (p16 with the padding) sits
+// at (floor(c / 4) p16 + i) 4 + c mod 4; the tiles of a k-column block
+// follow one another, each k4 p16 values (k4 = k rounded up to 4).
 struct HalfJob {
     int64_t src, dst;     // FP64 offset, half offset (a multiple of 64)
     int32_t m, n;         // rows, columns (the rank for U)
     int32_t tiled, self;  // U tiled as above; 1 if a self block
-    int32_t row0, m16;    // first tree row of the block; rows rounded up to 16 (untiled blocks)
+    int32_t row0, m16;    // first tree row of the block; tile rows of an untiled block
 };
 
 __host__ __device__ constexpr int32_t pad16(int32_t m) { return (m + 15) & ~15; }
@@ -1506,7 +1507,7 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
                 for (int32_t q = L.h_il_ptr[a_box]; q < L.h_il_ptr[a_box + 1]; ++q) {
                     if (H.h_il_kind[q] == kDense) {
                         const int32_t sb = H.h_il_src[q];
-                        put(t1, H.h_il_off16[q] + (int64_t)(p0 - ab) * 4, (int64_t)pad16(ldm) * 4, L.h_count[sb],
+                        put(t1, H.h_il_off16[q] + (int64_t)(p0 - ab) * 4, (int64_t)ldm * 4, L.h_count[sb],
                             L.h_begin[sb], true, sc[q]);
                     } else if (H.h_il_k[q] > 0) {
                         const int32_t k = H.h_il_k[q];
@@ -1521,7 +1522,7 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
     }
     const Level& LL = H.lev[kappa];
     for (int64_t X = 0; X < LL.nbox; ++X) {
-        const int64_t qs = (int64_t)pad16(LL.h_count[X]) * 4;
+        const int64_t qs = (int64_t)LL.h_count[X] * 4;
         for (int32_t q = H.h_near_ptr[X]; q < H.h_near_ptr[X + 1]; ++q) {
             const int32_t y = H.h_near_src[q];
             put(t2, near_off16[q], qs, LL.h_count[y], LL.h_begin[y], true, sc[H.n_il + q]);
@@ -1580,14 +1581,14 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         const int32_t row0 = L.h_begin[H.h_il_tgt[q]];
         if (H.h_il_kind[q] == kDense) {
             H.h_il_off16[q] = dof;
-            jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, pad16(mm)});
-            dof += (int64_t)pad16(mm) * ((nn + 3) & ~3);
+            jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, mm});
+            dof += (int64_t)mm * ((nn + 3) & ~3);
         } else {
             const int32_t k = H.h_il_k[q];
             const int32_t tiled = H.h_il_level[q] <= kappa - 1 ? 1 : 0;
             H.h_il_off16[q] = uo;
-            jobs.push_back(HalfJob{H.h_il_off[q], uo, mm, k, tiled, 0, row0, pad16(mm)});
-            uo += (tiled ? tiled_rows(row0, mm) : (int64_t)pad16(mm)) * ((k + 3) & ~3);
+            jobs.push_back(HalfJob{H.h_il_off[q], uo, mm, k, tiled, 0, row0, mm});
+            uo += (tiled ? tiled_rows(row0, mm) : (int64_t)mm) * ((k + 3) & ~3);
         }
     }
     const Level& LL = H.lev[kappa];
@@ -1597,8 +1598,8 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
             const int32_t y = H.h_near_src[q];
             near_off16[q] = dof;
             jobs.push_back(HalfJob{H.h_near_off[q], dof, LL.h_count[x], LL.h_count[y], 0, y == (int32_t)x ? 1 : 0,
-                                   LL.h_begin[x], pad16(LL.h_count[x])});
-            dof += (int64_t)pad16(LL.h_count[x]) * ((LL.h_count[y] + 3) & ~3);
+                                   LL.h_begin[x], LL.h_count[x]});
+            dof += (int64_t)LL.h_count[x] * ((LL.h_count[y] + 3) & ~3);
         }
     H.u16_elems = uo;
     H.d16_elems = dof;

@@ -276,8 +276,8 @@ struct Handle {
     DBuf<__half> U16, V16, D16;
     DBuf<__hip_bfloat16> Ub16, Vb16, Db16;
     // half U and D pools in the quad layout (every tile [column quads][rows][4],
-    // columns padded to a multiple of 4, rows to a multiple of 16) at offsets
-    // of their own, and the
+    // columns padded to a multiple of 4, the rows of the U tiles above the
+    // leaf level to a multiple of 16) at offsets of their own, and the
     // phase-B tables: per box one level above the leaves (qt1) and per leaf
     // (qt2), every 4-column group its row slices multiply, in summation order
     std::vector<int64_t> h_il_off16;
