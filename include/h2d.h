@@ -364,14 +364,16 @@ h2d_status h2d_profile_read(h2d_t H, h2d_profile* out);
 
 /* Work-item sizes of the product kernels (h2d_set_item_rows, h2d_autotune). */
 typedef enum {
-    H2D_TILE_A_ROWS = 0,   /* V rows per single-RHS phase-A item: 16..512 (default 512) */
-    H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS phase-A item: 16..512, multiple of 16 (default 256) */
-    H2D_TILE_B1_ROWS = 2,  /* rows per single-RHS phase-B1 item: 16, 32 or 64 (default 64); with
-                              64 the FP16/BF16 products take runs of up to 256 rows of sibling
-                              boxes instead (four rows per lane) */
-    H2D_TILE_B2_ROWS = 3   /* rows per single-RHS phase-B2 item (a chunk of a leaf box): 16, 32 or
-                              64 (default 64); chunks of fewer rows take several column groups
-                              per wave, so big leaves spread over more waves */
+    H2D_TILE_A_ROWS = 0,   /* V rows per single-RHS FP64 phase-A item: 16..512 (default 512) */
+    H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS FP64 phase-A item: 16..512, multiple of 16
+                              (default 256) */
+    H2D_TILE_B1_ROWS = 2,  /* rows per single-RHS FP64 phase-B1 item: 16, 32 or 64 (default 64) */
+    H2D_TILE_B2_ROWS = 3   /* rows per single-RHS phase-B2 item (a chunk of a leaf box), every
+                              precision: 16, 32 or 64 (default 64); chunks of fewer rows take
+                              several column groups per wave, so big leaves spread over more
+                              waves */
+    /* The FP16/BF16 pools use fixed work items for the rest: phase A 512
+     * rows of one source box, phase B1 64-row slices. */
 } h2d_tile;
 
 /* Tile tuning: times 5 FP64 products with nrhs right-hand sides for each
