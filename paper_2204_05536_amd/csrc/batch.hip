@@ -168,6 +168,7 @@ static void set_rows(Handle& H, int which, int32_t rows, hipStream_t s)
         H.mr_cap = 0;   // rebuilt with the next multi-RHS product
     } else {
         (which == 0 ? H.a_rows : which == 2 ? H.b1_rows : H.b2_rows) = rows;
+        if (which == 2) H.b1_rows_set = true;
         finalize(H, s);
     }
 }

@@ -313,6 +313,7 @@ struct Handle {
     DBuf<int2> b1s_items;       // single-RHS phase-B1 work: (box, first row of a b1_rows-row slice)
     int64_t n_b1s = 0;
     int32_t b1_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
+    bool b1_rows_set = false;   // b1_rows set by the caller or the tuner; else chosen from the box sizes
     DBuf<int2> b2items;         // single-RHS phase-B2 work: (leaf box, first row of a b2_rows-row chunk)
     int32_t b2_rows = 64;       // 16, 32 or 64 (tuned by h2d_autotune)
     int64_t n_b2 = 0;

@@ -567,7 +567,8 @@ __device__ __forceinline__ void qt_sweep(float& acc, const QEnt* __restrict__ qt
 
 // Phase B on the half pools, both halves in one launch.  B1: one wave per
 // 64-row slice of a box P one level above the leaves; lane r owns row r and
-// walks P's table (the groups of every block of P and its ancestors).  B2:
+// walks P's table (the groups of every block of P and its ancestors); a
+// slice of at most 32 rows takes the table in lane groups, as below.  B2:
 // one wave per chunk of at most S2 rows of a leaf X; lane (g, r) owns row r
 // and the table entries g, g + G, ... (G = 64 / rows) of X's table (near
 // blocks, then X's own interaction-list blocks); the G sums of a row are
@@ -590,10 +591,24 @@ k_phaseB_half(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int k
         const int32_t P = uni(wi.x), rc = uni(wi.y);
         const int32_t p0 = uni(L.begin[kappa - 1][P]), cnt = uni(L.count[kappa - 1][P]);
         const int32_t rows = min(kWave, cnt - rc);
+        const int32_t j0 = uni(qp1[P]), j1 = uni(qp1[P + 1]);
         float acc = 0.f;
-        qt_sweep<T, true>(acc, qt1, uni(qp1[P]), uni(qp1[P + 1]), 0, 1, (int64_t)(rc + min(lane, rows - 1)) * 4, Up, Dp,
-                          tpool, xs);
-        if (lane < rows) ypart[p0 + rc + lane] = acc;
+        if (rows > kWave / 2) {
+            qt_sweep<T, true>(acc, qt1, j0, j1, 0, 1, (int64_t)(rc + min(lane, rows - 1)) * 4, Up, Dp, tpool, xs);
+            if (lane < rows) ypart[p0 + rc + lane] = acc;
+            return;
+        }
+        // a box of at most 32 rows: lane groups take the table in turn
+        const int G = kWave / rows, g = lane / rows, r = lane % rows;
+        if (g < G) qt_sweep<T, false>(acc, qt1, j0, j1, g, G, (int64_t)(rc + r) * 4, Up, Dp, tpool, xs);
+        red[wave][lane] = g < G ? acc : 0.f;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rows) {
+            float sum = 0.f;
+            for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * rows + lane];
+            ypart[p0 + rc + lane] = sum;
+        }
         return;
     }
     const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
@@ -782,7 +797,25 @@ void finalize(Handle& H, hipStream_t s)
     flops += 2.0 * near_e;
     store_leaf += near_e;
     // phase-B1 work: 64-row chunks (multi-RHS) and b1_rows-row slices
-    // (single-RHS) of the boxes one level above the leaves
+    // (single-RHS) of the boxes one level above the leaves.  Unless set, the
+    // slice rows S minimise sum over boxes of ceil(rows / S) (S + 16): the
+    // slots of padded rows plus a fixed cost per item in row units (every
+    // item walks its box's ancestors once).  Uniform points (boxes of a few
+    // hundred points) take 64; clustered ones, whose boxes at that level
+    // mostly hold a few points, take 16 (a wave then covers 4 column groups
+    // of a 16-row slice instead of idling most of 64 lanes).
+    if (!H.b1_rows_set && kappa >= 2) {
+        const Level& T = H.lev[kappa - 1];
+        int64_t best = -1;
+        for (int32_t S : {64, 32, 16}) {
+            int64_t cost = 0;
+            for (int64_t p = 0; p < T.nbox; ++p) cost += (int64_t)((T.h_count[p] + S - 1) / S) * (S + 16);
+            if (best < 0 || cost < best) {
+                best = cost;
+                H.b1_rows = S;
+            }
+        }
+    }
     std::vector<int2> b1, b1s;
     const int32_t S = H.b1_rows;
     if (kappa >= 2) {
