@@ -367,7 +367,9 @@ typedef enum {
     H2D_TILE_A_ROWS = 0,   /* V rows per single-RHS FP64 phase-A item: 16..512 (default 512) */
     H2D_TILE_MR_ROWS = 1,  /* source rows per multi-RHS FP64 phase-A item: 16..512, multiple of 16
                               (default 256) */
-    H2D_TILE_B1_ROWS = 2,  /* rows per single-RHS FP64 phase-B1 item: 16, 32 or 64 (default 64) */
+    H2D_TILE_B1_ROWS = 2,  /* rows per single-RHS FP64 phase-B1 item: 16, 32 or 64 (until set, chosen
+                              from the sizes of the boxes one level above the leaves: 64 for
+                              boxes of hundreds of points, 16 for boxes of a few) */
     H2D_TILE_B2_ROWS = 3   /* rows per single-RHS phase-B2 item (a chunk of a leaf box), every
                               precision: 16, 32 or 64 (default 64); chunks of fewer rows take
                               several column groups per wave, so big leaves spread over more
