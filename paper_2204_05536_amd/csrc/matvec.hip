@@ -35,21 +35,9 @@ struct LevelPtrs {
     const int32_t* il_ptr[kMaxLevel + 1];
 };
 
-template <typename T> __device__ __forceinline__ float ldf(const T* p);
-template <> __device__ __forceinline__ float ldf<__half>(const __half* p)
-{
-    return __half2float(__builtin_nontemporal_load(reinterpret_cast<const _Float16*>(p)));
-}
-template <> __device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfloat16* p)
-{
-    unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
-    return __uint_as_float((unsigned)b << 16);
-}
-
-// Factor values are streamed once per matvec: nontemporal loads keep them
-// from evicting x, t and the descriptors from the caches.
-template <typename T, typename A> __device__ __forceinline__ A ld(const T* p) { return (A)ldf<T>(p); }
-template <> __device__ __forceinline__ double ld<double, double>(const double* p) { return __builtin_nontemporal_load(p); }
+// Phase A streams the V values once per matvec: nontemporal loads keep
+// them from evicting x, t and the descriptors from the caches.
+__device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
 
 // The t and x values of a block are the same for every lane of a phase-B1
 // wave (all lanes walk the same columns): read through the constant address
@@ -58,33 +46,27 @@ template <> __device__ __forceinline__ double ld<double, double>(const double* p
 // kernels only.
 template <typename A> using ConstAS = const __attribute__((address_space(4))) A;
 
-// Phase B reads FP64 factors with ordinary loads (measured slightly faster
-// there than nontemporal ones); half factors keep the nontemporal path.
-template <typename T, typename A>
-__device__ __forceinline__ A ldv(const T* p)
-{
-    if constexpr (sizeof(T) == sizeof(A)) return *p;
-    else return ld<T, A>(p);
-}
-
+// Phase B reads the FP64 factors with ordinary loads (measured slightly
+// faster there than nontemporal ones).
 // acc += sum over c = g, g + G, ... < n of base[c ld] w[c], eight columns
 // per lane loaded before any is multiplied: the loads of a chunk are in
 // flight together, and a short tail is padded with zero products instead of
 // running one load (and one memory latency) at a time.  The products are
 // added in increasing c, as the plain loop adds them.
-template <typename T, typename A, typename W>
-__device__ __forceinline__ void dot_cols(A& acc, const T* base, int64_t ld, const W* w, int32_t n, int g, int G)
+template <typename W>
+__device__ __forceinline__ void dot_cols(double& acc, const double* base, int64_t ld, const W* w, int32_t n, int g,
+                                         int G)
 {
     for (int32_t c0 = 0; c0 < n; c0 += 8 * G) {
-        A v[8], t[8];
+        double v[8], t[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int32_t c = c0 + u * G + g;
-            v[u] = (A)0;
-            t[u] = (A)0;
+            v[u] = 0.0;
+            t[u] = 0.0;
             if (c < n) {
-                v[u] = ldv<T, A>(base + (int64_t)c * ld);
-                t[u] = (A)w[c];
+                v[u] = base[(int64_t)c * ld];
+                t[u] = (double)w[c];
             }
         }
 #pragma unroll
@@ -148,13 +130,12 @@ __device__ __forceinline__ int32_t xcd_tile()
 // j0 + g, j0 + g + G, ... (G = 64 / k): each load covers G whole rows, G k
 // consecutive values.  Items are ordered largest first (a static
 // longest-processing-time schedule).
-template <typename T, typename A, bool kScaled>
 __global__ void __launch_bounds__(256)
-k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ V, const A* __restrict__ xs,
-         A* __restrict__ tpool, A* __restrict__ ppool, const float* __restrict__ scale)
+k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const double* __restrict__ V,
+         const double* __restrict__ xs, double* __restrict__ tpool, double* __restrict__ ppool)
 {
-    __shared__ A xw[4][kPhaseARows];
-    __shared__ A red[4][kWave];
+    __shared__ double xw[4][kPhaseARows];
+    __shared__ double red[4][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t it = (int64_t)blockIdx.x * 4 + wave;
     if (it >= nitems) return;
@@ -162,38 +143,36 @@ k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const T* __restrict__ 
     D.voff = uni(D.voff); D.j0 = uni(D.j0); D.j1 = uni(D.j1); D.col0 = uni(D.col0); D.k = uni(D.k);
     D.out = uni(D.out); D.pad = uni(D.pad);
     const int32_t k = D.k, rows = D.j1 - D.j0;
-    const T* Vb = V + D.voff + (int64_t)D.j0 * k;
-    const A* xb = xs + D.col0 + D.j0;
-    A* xl = xw[wave];
+    const double* Vb = V + D.voff + (int64_t)D.j0 * k;
+    const double* xb = xs + D.col0 + D.j0;
+    double* xl = xw[wave];
     for (int32_t j = lane; j < rows; j += kWave) xl[j] = xb[j];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    A* out = (D.out >= 0) ? (tpool + D.out) : (ppool + (-D.out - 1));
-    A sc = (A)1;
-    if constexpr (kScaled) sc = (A)scale[D.pad];
+    double* out = (D.out >= 0) ? (tpool + D.out) : (ppool + (-D.out - 1));
     if (k <= kWave) {
         const int G = kWave / k, g = lane / k, q = lane % k;
-        A acc = (A)0;
+        double acc = 0.0;
         if (g < G) {
 #pragma unroll 8
-            for (int32_t j = g; j < rows; j += G) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xl[j];
+            for (int32_t j = g; j < rows; j += G) acc += ld_nt(Vb + (int64_t)j * k + q) * xl[j];
         }
         red[wave][lane] = acc;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
         if (lane < k) {
-            A s = (A)0;
+            double s = 0.0;
             for (int gg = 0; gg < G; ++gg) s += red[wave][gg * k + lane];
-            out[lane] = s * sc;
+            out[lane] = s;
         }
     } else {
         for (int32_t qc = 0; qc < k; qc += kWave) {
             const int32_t q = qc + lane;
             if (q < k) {
-                A acc = (A)0;
+                double acc = 0.0;
 #pragma unroll 8
-                for (int32_t j = 0; j < rows; ++j) acc += ld<T, A>(Vb + (int64_t)j * k + q) * xl[j];
-                out[q] = acc * sc;
+                for (int32_t j = 0; j < rows; ++j) acc += ld_nt(Vb + (int64_t)j * k + q) * xl[j];
+                out[q] = acc;
             }
         }
     }
@@ -324,13 +303,13 @@ k_reduce_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict
 // consecutive values.  The G column-group sums are added in a fixed order.
 // Smaller slices give more, shorter work items (a shorter tail when the
 // items do not fill a whole number of rounds of the machine).
-template <typename T, typename A, bool kHalf, int S>
+template <int S>
 __device__ __forceinline__ void
-b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict__ items, int tl, const LevelPtrs& L,
-        const BDesc* __restrict__ bil, const T* __restrict__ Up, const T* __restrict__ Dp,
-        const A* __restrict__ tpool, const A* __restrict__ xs, A* __restrict__ ypart, const float* __restrict__ scale)
+b1_item(int32_t it, int wave, int lane, double (*red)[kWave], const int2* __restrict__ items, int tl,
+        const LevelPtrs& L, const BDesc* __restrict__ bil, const double* __restrict__ Up, const double* __restrict__ Dp,
+        const double* __restrict__ tpool, const double* __restrict__ xs, double* __restrict__ ypart)
 {
-    using cA = ConstAS<A>;
+    using cA = ConstAS<double>;
     const int2 w = items[it];
     const int32_t P = uni(w.x), rc = uni(w.y);
     const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
@@ -338,7 +317,7 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
     constexpr int G = kWave / S;
     const int g = G == 1 ? 0 : lane / S, r = G == 1 ? lane : lane % S;
     const bool act = r < rows;
-    A acc = (A)0;
+    double acc = 0.0;
     int32_t a_box = P;
     for (int l = tl; l >= 1; --l) {
         const int32_t ab = uni(L.begin[l][a_box]), ld_m = uni(L.count[l][a_box]);
@@ -349,16 +328,15 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
             if (d.cols > 0) {
                 // U is tiled by level-(kappa - 1) boxes: this box's tile is
                 // a contiguous cnt x k column-major matrix
-                const T* base = Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + r;
+                const double* base = Up + d.off + (int64_t)d.cols * (p0 - ab) + rc + r;
                 const cA* tv = (const cA*)(tpool + d.tsrc);
-                if (act) dot_cols<T, A>(acc, base, cnt, tv, d.cols, g, G);
+                if (act) dot_cols(acc, base, cnt, tv, d.cols, g, G);
             } else if (d.cols < 0) {
-                const T* base = Dp + d.off + off;
+                const double* base = Dp + d.off + off;
                 const cA* tv = (const cA*)(xs + d.tsrc);
-                A a = (A)0;
-                if (act) dot_cols<T, A>(a, base, ld_m, tv, -d.cols, g, G);
-                if constexpr (kHalf) acc += a * (A)scale[q];
-                else acc += a;
+                double a = 0.0;
+                if (act) dot_cols(a, base, ld_m, tv, -d.cols, g, G);
+                acc += a;
             }
         }
         a_box = uni(L.parent[l][a_box]);
@@ -367,11 +345,11 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
         if (act) ypart[p0 + rc + r] = acc;
         return;
     }
-    red[wave][lane] = act ? acc : (A)0;
+    red[wave][lane] = act ? acc : 0.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
     if (lane < rows) {
-        A s = (A)0;
+        double s = 0.0;
         for (int gg = 0; gg < G; ++gg) s += red[wave][gg * S + lane];
         ypart[p0 + rc + lane] = s;
     }
@@ -383,12 +361,11 @@ b1_item(int32_t it, int wave, int lane, A (*red)[kWave], const int2* __restrict_
 // most 64 rows;
 // lane (g, r) takes row r and the columns g, g + G, ... (G = 64 / rows), so
 // a load covers G consecutive columns of the column-major block.
-template <typename T, typename A, bool kHalf>
 __device__ __forceinline__ void
-b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, A (*red)[kWave], A* tst, int kappa, const LevelPtrs& L,
-        const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
-        const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
-        A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il)
+b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, double (*red)[kWave], double* tst, int kappa,
+        const LevelPtrs& L, const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear,
+        const BDesc* __restrict__ bil, const double* __restrict__ Up, const double* __restrict__ Dp,
+        const double* __restrict__ tpool, const double* __restrict__ xs, double* __restrict__ yleaf)
 {
     const int32_t r0 = uni(L.begin[kappa][X]), cnt = uni(L.count[kappa][X]);
     const int32_t q0 = uni(L.il_ptr[kappa][X]), q1 = uni(L.il_ptr[kappa][X + 1]);
@@ -399,41 +376,37 @@ b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, A (*red)[kWave], 
     // one block: its multiplier values (t, or x of the source box) are
     // staged in this wave's LDS slice, kB2Stage at a time, with one load per
     // lane, instead of one gather load per lane and column group
-    auto sweep = [&](const T* base, const A* tv, int32_t nc) -> A {
-        A a = (A)0;
+    auto sweep = [&](const double* base, const double* tv, int32_t nc) -> double {
+        double a = 0.0;
         for (int32_t c0 = 0; c0 < nc; c0 += kB2Stage) {
             const int32_t m = min(kB2Stage, nc - c0);
             for (int32_t j = lane; j < m; j += kWave) tst[j] = tv[c0 + j];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
-            if (act) dot_cols<T, A>(a, base + (int64_t)c0 * cnt, cnt, tst, m, g, G);
+            if (act) dot_cols(a, base + (int64_t)c0 * cnt, cnt, tst, m, g, G);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
         return a;
     };
-    A acc = (A)0;
+    double acc = 0.0;
     for (int32_t q = n0; q < n1; ++q) {
         const BDesc d = uni(bnear[q]);
-        const A a = sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
-        if constexpr (kHalf) acc += a * (A)scale[n_il + q];
-        else acc += a;
+        acc += sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
     }
     for (int32_t q = q0; q < q1; ++q) {
         const BDesc d = uni(bil[q]);
         if (d.cols > 0) {
             acc += sweep(Up + d.off + rc + r, tpool + d.tsrc, d.cols);
         } else if (d.cols < 0) {
-            const A a = sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
-            if constexpr (kHalf) acc += a * (A)scale[q];
-            else acc += a;
+            acc += sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
         }
     }
-    red[wave][lane] = act ? acc : (A)0;
+    red[wave][lane] = act ? acc : 0.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
     if (lane < rows) {
-        A s = (A)0;
+        double s = 0.0;
         for (int gg = 0; gg < G; ++gg) s += red[wave][gg * rows + lane];
         yleaf[r0 + rc + lane] = s;
     }
@@ -462,28 +435,27 @@ __device__ __forceinline__ int32_t xcd_sub(int32_t w, int32_t w0, int32_t n)
 // field, into yleaf).  The two halves write different
 // arrays and do not depend on each other; the latency-bound leaf work is
 // dispatched as the ancestor work drains, filling its tail.
-template <typename T, typename A, bool kHalf, int S>
+template <int S>
 __global__ void __launch_bounds__(256)
 k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa, LevelPtrs L,
          const int32_t* __restrict__ near_ptr, const BDesc* __restrict__ bnear, const BDesc* __restrict__ bil,
-         const T* __restrict__ Up, const T* __restrict__ Dp, const A* __restrict__ tpool, const A* __restrict__ xs,
-         A* __restrict__ ypart, A* __restrict__ yleaf, const float* __restrict__ scale, int64_t n_il,
+         const double* __restrict__ Up, const double* __restrict__ Dp, const double* __restrict__ tpool,
+         const double* __restrict__ xs, double* __restrict__ ypart, double* __restrict__ yleaf,
          const int2* __restrict__ b2items, int32_t nb2items, int32_t b2_rows)
 {
-    __shared__ A red[4][kWave];
-    __shared__ A tst[4][kB2Stage];
+    __shared__ double red[4][kWave];
+    __shared__ double tst[4][kB2Stage];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t w = blockIdx.x;
     if (w < nb1) {
         const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
-        if (it < nitems)
-            b1_item<T, A, kHalf, S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, scale);
+        if (it < nitems) b1_item<S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart);
     } else {
         const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
         if (it < nb2items) {
             const int2 c = b2items[it];
-            b2_item<T, A, kHalf>(uni(c.x), uni(c.y), b2_rows, wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up,
-                                 Dp, tpool, xs, yleaf, scale, n_il);
+            b2_item(uni(c.x), uni(c.y), b2_rows, wave, lane, red, tst[wave], kappa, L, near_ptr, bnear, bil, Up, Dp, tpool,
+                    xs, yleaf);
         }
     }
 }
@@ -672,7 +644,7 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
         if (!act) continue;
         const double* base = Dp + d.off + rc + r;
         const double* xv = xs + d.tsrc;
-        dot_cols<double, double>(acc, base, cnt, xv, -d.cols, g, G);
+        dot_cols(acc, base, cnt, xv, -d.cols, g, G);
     }
     int32_t a = box;
     for (int l = lx; l >= 1; --l) {
@@ -685,11 +657,11 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
             if (d.cols > 0) {
                 const double* base = Up + d.off + roff;
                 const double* tv = tpool + d.tsrc;
-                dot_cols<double, double>(acc, base, m, tv, d.cols, g, G);
+                dot_cols(acc, base, m, tv, d.cols, g, G);
             } else {
                 const double* base = Dp + d.off + roff;
                 const double* xv = xs + d.tsrc;
-                dot_cols<double, double>(acc, base, m, xv, -d.cols, g, G);
+                dot_cols(acc, base, m, xv, -d.cols, g, G);
             }
         }
         a = uni(L.parent[l][a]);
@@ -1026,8 +998,7 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
         if (H.n_aw_red) k_reduce_wide<<<(unsigned)H.n_aw_red, 256, 0, s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, pp, tp);
     } else {
         if (H.n_aitems)
-            k_phaseA<T, A, false><<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp,
-                                                                                nullptr);
+            k_phaseA<<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp);
         if (ev) HIPCK(hipEventRecord(ev[2], s));
         if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
     }
@@ -1064,10 +1035,9 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
         ni = (int32_t)H.n_b1s;
         const int32_t nb1 = (ni + 3) / 4, nb2 = (int32_t)((H.n_b2 + 3) / 4);
 #define H2D_PHASE_B(SR)                                                                                              \
-    k_phaseB<T, A, kHalf, SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, \
-                                                                   H.bnear.p, H.bil.p, U, D, tp, xs, yp, yl,         \
-                                                                   H.scale16.p, H.n_il, H.b2items.p, (int32_t)H.n_b2, \
-                                                                   H.b2_rows)
+    k_phaseB<SR><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(nb1, ni, H.b1s_items.p, H.kappa, LP, H.near_ptr.p, H.bnear.p,  \
+                                                      H.bil.p, U, D, tp, xs, yp, yl, H.b2items.p, (int32_t)H.n_b2,      \
+                                                      H.b2_rows)
         if (H.b1_rows == 16) H2D_PHASE_B(16);
         else if (H.b1_rows == 32) H2D_PHASE_B(32);
         else H2D_PHASE_B(64);
