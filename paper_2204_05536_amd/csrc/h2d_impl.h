@@ -119,16 +119,6 @@ struct QEnt {
     int32_t nv;
 };
 
-// Phase-A work item: t(out) = V(rows j0..j1)^T x(col0 + j0 .. col0 + j1).
-// V is row-major n x k starting at V pool + voff.
-struct ADesc {
-    int64_t voff;     // element offset of row 0 of the block's V
-    int32_t j0, j1;   // row range of this item
-    int32_t col0;     // first tree column of the source box
-    int32_t k;        // rank
-    int32_t out;      // t pool offset (whole block) or partial pool offset
-    int32_t pad;
-};
 
 // Phase A on the half pools, grouped by source box: rows of one source
 // box's wide V (the V of all its low-rank blocks side by side, w columns,
@@ -156,10 +146,10 @@ struct RDesc {
     int32_t nparts;   // partials, each k long, stored consecutively
 };
 
-// Multi-RHS phase A, grouped by source box: one work item is a row range
-// [j0, j1) of one source box (points col0 + j0 .. col0 + j1 - 1 in tree
-// order) and the blocks b0 .. b1 - 1 of the block list that share it; the
-// item is chunk p of the source's rows.
+// Phase A on the FP64 pools (single- and multi-RHS), grouped by source
+// box: one work item is a row range [j0, j1) of one source box (points
+// col0 + j0 .. col0 + j1 - 1 in tree order) and the blocks b0 .. b1 - 1 of
+// the block list that share it; the item is chunk p of the source's rows.
 struct MRItem {
     int32_t col0, j0, j1, b0, b1, p;
 };
@@ -290,7 +280,8 @@ struct Handle {
 
     // matvec schedule
     DBuf<BDesc> bnear, bil;  // phase-B descriptors: near blocks, IL blocks
-    DBuf<ADesc> aitems;
+    DBuf<MRItem> a_items;       // single-RHS phase A: source-box chunks (FP64 pools)
+    DBuf<MRBlk> a_blks;         // their blocks (V offset, rank, t or partial offset)
     // FP16/BF16 V pools, grouped by source box: for every source box (per
     // level) the V of its low-rank blocks side by side (w columns in table
     // order), stored in groups of 4 rows: element (j, c) of the box at

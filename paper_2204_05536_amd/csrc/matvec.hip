@@ -124,55 +124,56 @@ __device__ __forceinline__ int32_t xcd_tile()
     return xcd * q8 + min(xcd, r8) + i8;
 }
 
-// Phase A: one wave per work item (rows j0..j1 of one block's V, at most
-// kPhaseARows rows).  The item's slice of x is staged in LDS first, so the
-// vector-memory pipe carries only V.  Lane (g, q) takes column q of rows
-// j0 + g, j0 + g + G, ... (G = 64 / k): each load covers G whole rows, G k
-// consecutive values.  Items are ordered largest first (a static
-// longest-processing-time schedule).
+// Phase A, grouped by source box: one workgroup per item (rows j0 .. j1 -
+// 1, at most kPhaseARows, of one source box, and every low-rank block with
+// that source).  The item's slice of x is staged in LDS once; the four
+// waves take the blocks in turn.  For a block of rank k, lane (g, q) takes
+// column q of rows g, g + G, ... (G = 64 / k): each load covers G whole
+// rows, G k consecutive values, and the G sums of a column are added in a
+// fixed order; ranks above 64 take 64 columns per pass.  Items are ordered
+// largest first (a static longest-processing-time schedule).
 __global__ void __launch_bounds__(256)
-k_phaseA(int64_t nitems, const ADesc* __restrict__ items, const double* __restrict__ V,
+k_phaseA(const MRItem* __restrict__ items, const MRBlk* __restrict__ blks, const double* __restrict__ V,
          const double* __restrict__ xs, double* __restrict__ tpool, double* __restrict__ ppool)
 {
-    __shared__ double xw[4][kPhaseARows];
+    __shared__ double xl[kPhaseARows];
     __shared__ double red[4][kWave];
+    const MRItem it = items[blockIdx.x];
+    const int32_t rows = it.j1 - it.j0;
+    for (int32_t j = threadIdx.x; j < rows; j += blockDim.x) xl[j] = xs[it.col0 + it.j0 + j];
+    __syncthreads();
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t it = (int64_t)blockIdx.x * 4 + wave;
-    if (it >= nitems) return;
-    ADesc D = items[it];
-    D.voff = uni(D.voff); D.j0 = uni(D.j0); D.j1 = uni(D.j1); D.col0 = uni(D.col0); D.k = uni(D.k);
-    D.out = uni(D.out); D.pad = uni(D.pad);
-    const int32_t k = D.k, rows = D.j1 - D.j0;
-    const double* Vb = V + D.voff + (int64_t)D.j0 * k;
-    const double* xb = xs + D.col0 + D.j0;
-    double* xl = xw[wave];
-    for (int32_t j = lane; j < rows; j += kWave) xl[j] = xb[j];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    double* out = (D.out >= 0) ? (tpool + D.out) : (ppool + (-D.out - 1));
-    if (k <= kWave) {
-        const int G = kWave / k, g = lane / k, q = lane % k;
-        double acc = 0.0;
-        if (g < G) {
+    for (int32_t bi = it.b0 + wave; bi < it.b1; bi += 4) {
+        const MRBlk B = blks[bi];
+        const int32_t k = uni(B.k), out = uni(B.out);
+        const double* Vb = V + uni(B.voff) + (int64_t)it.j0 * k;
+        double* o = out >= 0 ? tpool + out : ppool + (int64_t)(-out - 1) + (int64_t)it.p * k;
+        if (k <= kWave) {
+            const int G = kWave / k, g = lane / k, q = lane % k;
+            double acc = 0.0;
+            if (g < G) {
 #pragma unroll 8
-            for (int32_t j = g; j < rows; j += G) acc += ld_nt(Vb + (int64_t)j * k + q) * xl[j];
-        }
-        red[wave][lane] = acc;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        if (lane < k) {
-            double s = 0.0;
-            for (int gg = 0; gg < G; ++gg) s += red[wave][gg * k + lane];
-            out[lane] = s;
-        }
-    } else {
-        for (int32_t qc = 0; qc < k; qc += kWave) {
-            const int32_t q = qc + lane;
-            if (q < k) {
-                double acc = 0.0;
+                for (int32_t j = g; j < rows; j += G) acc += ld_nt(Vb + (int64_t)j * k + q) * xl[j];
+            }
+            red[wave][lane] = acc;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            if (lane < k) {
+                double sum = 0.0;
+                for (int gg = 0; gg < G; ++gg) sum += red[wave][gg * k + lane];
+                o[lane] = sum;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            for (int32_t qc = 0; qc < k; qc += kWave) {
+                const int32_t q = qc + lane;
+                if (q < k) {
+                    double acc = 0.0;
 #pragma unroll 8
-                for (int32_t j = 0; j < rows; ++j) acc += ld_nt(Vb + (int64_t)j * k + q) * xl[j];
-                out[q] = acc;
+                    for (int32_t j = 0; j < rows; ++j) acc += ld_nt(Vb + (int64_t)j * k + q) * xl[j];
+                    o[q] = acc;
+                }
             }
         }
     }
@@ -698,6 +699,69 @@ static void upload_vec(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
     if (!h.empty()) HIPCK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// The phase-A schedule, grouped by source box: the low-rank blocks in
+// (source level, source box) order, each source box cut into chunks of
+// a_rows rows; one item per chunk lists the blocks of its source.  A block
+// whose source spans several chunks gets one partial per chunk (k values at
+// partial offset + chunk k) and a reduction.  Items largest work first.
+// Needs the t offsets; returns the partial values.
+static int64_t build_phase_a(Handle& H, hipStream_t s)
+{
+    const int32_t ar = std::max(16, std::min<int32_t>(H.a_rows, kPhaseARows));
+    std::vector<int64_t> idx;
+    for (int64_t b = 0; b < H.n_il; ++b)
+        if (H.h_il_kind[b] != kDense && H.h_il_k[b] > 0) idx.push_back(b);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        const int la = il_src_level(H, a), lb = il_src_level(H, b);
+        return la != lb ? la < lb : H.h_il_src[a] < H.h_il_src[b];
+    });
+    std::vector<MRBlk> blks;
+    std::vector<MRItem> items;
+    std::vector<int64_t> work;
+    std::vector<RDesc> red;
+    int64_t poff = 0;
+    for (size_t g0 = 0; g0 < idx.size();) {
+        const int ls = il_src_level(H, idx[g0]);
+        const int32_t src = H.h_il_src[idx[g0]];
+        size_t g1 = g0;
+        while (g1 < idx.size() && il_src_level(H, idx[g1]) == ls && H.h_il_src[idx[g1]] == src) ++g1;
+        const int32_t n = H.lev[ls].h_count[src], c0 = H.lev[ls].h_begin[src];
+        const int32_t parts = (n + ar - 1) / ar;
+        const int32_t b0 = (int32_t)blks.size();
+        int64_t ksum = 0;
+        for (size_t g = g0; g < g1; ++g) {
+            const int64_t b = idx[g];
+            const int32_t k = H.h_il_k[b];
+            ksum += k;
+            if (parts == 1) {
+                blks.push_back(MRBlk{H.h_il_voff[b], k, H.h_il_toff[b], (int32_t)b, 0});
+            } else {
+                blks.push_back(MRBlk{H.h_il_voff[b], k, (int32_t)(-poff - 1), (int32_t)b, 0});
+                red.push_back(RDesc{H.h_il_toff[b], k, (int32_t)poff, parts});
+                poff += (int64_t)parts * k;
+            }
+        }
+        for (int32_t p = 0; p < parts; ++p) {
+            const int32_t j0 = p * ar, j1 = std::min(n, j0 + ar);
+            items.push_back(MRItem{c0, j0, j1, b0, (int32_t)blks.size(), p});
+            work.push_back((int64_t)(j1 - j0) * ksum);
+        }
+        g0 = g1;
+    }
+    if (poff > INT32_MAX) fail(H2D_EUNSUPPORTED, "phase-A partial pool above 2^31 values");
+    std::vector<int64_t> ord(items.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int64_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+    std::vector<MRItem> sorted(items.size());
+    for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[ord[i]];
+    upload_vec(H.a_items, sorted, s);
+    upload_vec(H.a_blks, blks, s);
+    upload_vec(H.ritems, red, s);
+    H.n_aitems = (int64_t)sorted.size();
+    H.n_ritems = (int64_t)red.size();
+    return poff;
+}
+
 // Device tables and the matvec schedule from the host block tables.
 void finalize(Handle& H, hipStream_t s)
 {
@@ -717,10 +781,8 @@ void finalize(Handle& H, hipStream_t s)
     upload_vec(H.bnear, bn, s);
     const int64_t nil = H.n_il;
     std::vector<BDesc> bi(nil);
-    std::vector<ADesc> items;
-    std::vector<RDesc> red;
     H.h_il_toff.assign(nil, -1);
-    int64_t toff = 0, poff = 0;
+    int64_t toff = 0;
     H.max_rank = 0; H.sum_rank = 0; H.n_il_dense = 0;
     double flops = 0;
     double store_anc = 0, store_leaf = 0, t_leaf = 0;   // stored values read by the B1 / B2 halves, t values by B2
@@ -744,24 +806,9 @@ void finalize(Handle& H, hipStream_t s)
         (leaf ? store_leaf : store_anc) += (double)m * k;
         if (leaf) t_leaf += k;
         flops += 2.0 * k * (double)(m + n);
-        const int32_t ar = std::max(16, std::min<int32_t>(H.a_rows, kPhaseARows));
-        if (n <= ar) {
-            items.push_back(ADesc{H.h_il_voff[b], 0, n, c0, k, (int32_t)toff, (int32_t)b});
-        } else {
-            int32_t parts = (n + ar - 1) / ar;
-            red.push_back(RDesc{(int32_t)toff, k, (int32_t)poff, parts});
-            for (int32_t p = 0; p < parts; ++p) {
-                int32_t j0 = p * ar, j1 = std::min(n, j0 + ar);
-                items.push_back(ADesc{H.h_il_voff[b], j0, j1, c0, k, (int32_t)(-(poff + (int64_t)p * k) - 1), (int32_t)b});
-            }
-            poff += (int64_t)parts * k;
-        }
         toff += k;
     }
-    // largest work first (ties keep table order)
-    std::stable_sort(items.begin(), items.end(), [](const ADesc& x, const ADesc& y) {
-            return (int64_t)(x.j1 - x.j0) * x.k > (int64_t)(y.j1 - y.j0) * y.k;
-        });
+    const int64_t poff = build_phase_a(H, s);
     double near_e = 0;
     for (int64_t x = 0; x < LL.nbox; ++x)
         for (int32_t q = H.h_near_ptr[x]; q < H.h_near_ptr[x + 1]; ++q)
@@ -831,10 +878,6 @@ void finalize(Handle& H, hipStream_t s)
         (h ? H.alg_bytes_half : H.alg_bytes_fp64) = t;
     }
     upload_vec(H.bil, bi, s);
-    upload_vec(H.aitems, items, s);
-    upload_vec(H.ritems, red, s);
-    H.n_aitems = (int64_t)items.size();
-    H.n_ritems = (int64_t)red.size();
     H.ws_nrhs = 0;   // partial pools depend on the schedule: reallocate on next use
     H.mr_cap = 0;
     HIPCK(hipStreamSynchronize(s));
@@ -867,12 +910,9 @@ void finalize_adaptive(Handle& H, hipStream_t s)
     upload_vec(H.bnear, bn, s);
     const int64_t nil = H.n_il;
     std::vector<BDesc> bi(nil);
-    std::vector<ADesc> items;
-    std::vector<RDesc> red;
     H.h_il_toff.assign(nil, -1);
-    int64_t toff = 0, poff = 0;
+    int64_t toff = 0;
     H.max_rank = 0; H.sum_rank = 0; H.n_il_dense = 0;
-    const int32_t ar = std::max(16, std::min<int32_t>(H.a_rows, kPhaseARows));
     for (int64_t b = 0; b < nil; ++b) {
         const Level& L = H.lev[H.h_il_level[b]];
         const Level& Ls = H.lev[il_src_level(H, b)];
@@ -892,22 +932,9 @@ void finalize_adaptive(Handle& H, hipStream_t s)
         H.h_il_toff[b] = (int32_t)toff;
         store += (double)m * k;
         flops += 2.0 * k * (double)(m + n);
-        if (n <= ar) {
-            items.push_back(ADesc{H.h_il_voff[b], 0, n, c0, k, (int32_t)toff, (int32_t)b});
-        } else {
-            const int32_t parts = (n + ar - 1) / ar;
-            red.push_back(RDesc{(int32_t)toff, k, (int32_t)poff, parts});
-            for (int32_t p = 0; p < parts; ++p) {
-                const int32_t j0 = p * ar, j1 = std::min(n, j0 + ar);
-                items.push_back(ADesc{H.h_il_voff[b], j0, j1, c0, k, (int32_t)(-(poff + (int64_t)p * k) - 1), (int32_t)b});
-            }
-            poff += (int64_t)parts * k;
-        }
         toff += k;
     }
-    std::stable_sort(items.begin(), items.end(), [](const ADesc& x, const ADesc& y) {
-        return (int64_t)(x.j1 - x.j0) * x.k > (int64_t)(y.j1 - y.j0) * y.k;
-    });
+    const int64_t poff = build_phase_a(H, s);
     std::vector<int2> ad;
     for (int64_t x = 0; x < nleaf; ++x)
         for (int32_t rc = 0; rc < H.h_leaf_count[x]; rc += kWave) ad.push_back(make_int2((int32_t)x, rc));
@@ -926,10 +953,6 @@ void finalize_adaptive(Handle& H, hipStream_t s)
     for (int p = 0; p < 5; ++p) H.alg_bytes_fp64 += H.phase_bytes[0][p];
     H.alg_bytes_half = 0;
     upload_vec(H.bil, bi, s);
-    upload_vec(H.aitems, items, s);
-    upload_vec(H.ritems, red, s);
-    H.n_aitems = (int64_t)items.size();
-    H.n_ritems = (int64_t)red.size();
     H.ws_nrhs = 0;
     H.mr_cap = 0;
     HIPCK(hipStreamSynchronize(s));
@@ -997,8 +1020,7 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
         if (ev) HIPCK(hipEventRecord(ev[2], s));
         if (H.n_aw_red) k_reduce_wide<<<(unsigned)H.n_aw_red, 256, 0, s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, pp, tp);
     } else {
-        if (H.n_aitems)
-            k_phaseA<<<(unsigned)((H.n_aitems + 3) / 4), 256, 0, s>>>(H.n_aitems, H.aitems.p, V, xs, tp, pp);
+        if (H.n_aitems) k_phaseA<<<(unsigned)H.n_aitems, 256, 0, s>>>(H.a_items.p, H.a_blks.p, V, xs, tp, pp);
         if (ev) HIPCK(hipEventRecord(ev[2], s));
         if (H.n_ritems) k_reduce_parts<A><<<(unsigned)H.n_ritems, 256, 0, s>>>(H.n_ritems, H.ritems.p, pp, tp);
     }
