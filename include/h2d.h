@@ -220,8 +220,9 @@ h2d_status h2d_solve(h2d_t H, const double* b, double* x, double rtol, const h2d
                      h2d_solve_info* info, void* stream);
 
 /* Block-Jacobi set-up: LU with partial pivoting of every leaf's self block
- * (leaf boxes of at most 64 points).  Needed before solving with
- * H2D_PC_BLOCK_JACOBI.  Errors: EUNSUPPORTED (a leaf above 64 points). */
+ * (leaf boxes of at most 1024 points).  Needed before solving with
+ * H2D_PC_BLOCK_JACOBI.  Errors: EUNSUPPORTED (a leaf above 1024 points, an
+ * adaptive or symmetric handle), EINVAL (a singular self block). */
 h2d_status h2d_bj_setup(h2d_t H, void* stream);
 
 /* z = M r for one of the set-up preconditioners (device FP64 vectors in

@@ -338,6 +338,8 @@ struct Handle {
     DBuf<double> bj_lu;        // per leaf: LU of the self block, m x m column-major
     DBuf<int32_t> bj_piv;      // per tree row: pivot row chosen at that step of its leaf
     DBuf<int64_t> bj_off;      // per leaf: offset into bj_lu
+    DBuf<int32_t> bj_big;      // leaves of more than 64 points (their own LU and solve kernels)
+    int32_t n_bj_big = 0;
     bool bj_ready = false;
     // solver work space, kept between solves and grown on demand: Krylov
     // basis, preconditioned directions, vectors, dot-product partials, and

@@ -19,9 +19,20 @@ def _lib():
     return hodlr2d
 
 
-def test_bj_apply_matches_leaf_solves(orc, tmp_path):
-    xy, b, kern, leaf, tol = inputs.workload("log4096")
+@pytest.mark.parametrize("case", ["log4096", "log3000_leaf500", "log3000_leaf100"])
+def test_bj_apply_matches_leaf_solves(orc, tmp_path, case):
+    """Leaves of up to 64 points factorised in LDS, larger ones (the paper's
+    leaves of up to 500 points) in the LU pool; both against numpy."""
+    if case == "log4096":
+        xy, b, kern, leaf, tol = inputs.workload("log4096")
+    else:
+        xy, b, kern, _, tol = inputs.workload("log4096", n=3000)
+        leaf = 500 if case.endswith("500") else 100
     O = orc.OracleH(xy, kern, leaf, tol)
+    counts = O.level(O.kappa)["count"]
+    if case != "log4096":
+        assert counts.max() > 64   # the large-leaf kernels run
+    say(f"{case}: leaves {len(counts)}, largest {counts.max()}")
     p = tmp_path / "o.h2dx"
     O.export(p)
     H = _lib().HODLR2D.import_file(p)
@@ -36,6 +47,20 @@ def test_bj_apply_matches_leaf_solves(orc, tmp_path):
         idx = perm[L["begin"][X]:L["begin"][X] + L["count"][X]]
         zr[idx] = np.linalg.solve(O.near_factor(q), r[idx])
     assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+
+
+def test_fgmres_block_jacobi_large_leaves():
+    """Block-Jacobi FGMRES with leaves of up to 500 points (the paper's
+    N_max) against the plain solve."""
+    xy, b, kern, _, tol = inputs.workload("log4096", n=20000)
+    H = _lib().HODLR2D.build(dev(xy), kern, 500, tol)
+    H.bj_setup()
+    x0, i0 = H.solve(dev(b), tol=1e-10)
+    x1, i1 = H.solve(dev(b), tol=1e-10, precond="bj")
+    say("leaf 500: plain", i0, "bj", i1)
+    assert i1["converged"] and i1["relres"] <= 1e-10
+    assert i1["iters"] <= i0["iters"]
+    assert np.linalg.norm(host(x1) - host(x0)) <= 1e-8 * np.linalg.norm(host(x0))
 
 
 def test_fgmres_block_jacobi_converges():
