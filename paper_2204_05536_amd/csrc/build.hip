@@ -1300,11 +1300,10 @@ void build_factors(Handle& H, hipStream_t s)
 // the leaves, as in the FP64 pool; any other block is one tile) is laid out
 // as [column quads][rows][4], so the 4 values of one row in 4 consecutive
 // columns form one aligned 8-byte group; the columns are padded with zeros
-// to a multiple of 4, and the rows of the tiles of a U above the leaf
-// level to a multiple of 16 (so each of its column quads starts on a
-// 128-byte line and a 64-row slice of one quad is four whole lines; the
-// other tiles are read whole, where padding would only leave partly used
-// lines).  Element (i, c) of a tile of p rows (p16 with the padding) sits
+// to a multiple of 4, and the rows of the tiles above the leaf level to a
+// multiple of 16 (so each of their column quads starts on a 128-byte line
+// and a 64-row slice of one quad is four whole lines; the leaf-level tiles
+// are read whole, where padding would only leave partly used lines).  Element (i, c) of a tile of p rows (p16 with the padding) sits
 // at (floor(c / 4) p16 + i) 4 + c mod 4; the tiles of a k-column block
 // follow one another, each k4 p16 values (k4 = k rounded up to 4).
 struct HalfJob {
@@ -1507,7 +1506,7 @@ static void build_quad_tables(Handle& H, const std::vector<int64_t>& near_off16,
                 for (int32_t q = L.h_il_ptr[a_box]; q < L.h_il_ptr[a_box + 1]; ++q) {
                     if (H.h_il_kind[q] == kDense) {
                         const int32_t sb = H.h_il_src[q];
-                        put(t1, H.h_il_off16[q] + (int64_t)(p0 - ab) * 4, (int64_t)ldm * 4, L.h_count[sb],
+                        put(t1, H.h_il_off16[q] + (int64_t)(p0 - ab) * 4, (int64_t)pad16(ldm) * 4, L.h_count[sb],
                             L.h_begin[sb], true, sc[q]);
                     } else if (H.h_il_k[q] > 0) {
                         const int32_t k = H.h_il_k[q];
@@ -1580,9 +1579,12 @@ void make_half_pools(Handle& H, uint32_t mask, hipStream_t s)
         const int32_t mm = L.h_count[H.h_il_tgt[q]], nn = L.h_count[H.h_il_src[q]];
         const int32_t row0 = L.h_begin[H.h_il_tgt[q]];
         if (H.h_il_kind[q] == kDense) {
+            // above the leaf level the tile is read in 64-row slices: rows
+            // padded to 16 (at the leaf level it is read whole: packed)
+            const int32_t m16 = H.h_il_level[q] < kappa ? pad16(mm) : mm;
             H.h_il_off16[q] = dof;
-            jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, mm});
-            dof += (int64_t)mm * ((nn + 3) & ~3);
+            jobs.push_back(HalfJob{H.h_il_off[q], dof, mm, nn, 0, 0, row0, m16});
+            dof += (int64_t)m16 * ((nn + 3) & ~3);
         } else {
             const int32_t k = H.h_il_k[q];
             const int32_t tiled = H.h_il_level[q] <= kappa - 1 ? 1 : 0;
