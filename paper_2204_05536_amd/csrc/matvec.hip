@@ -303,19 +303,23 @@ k_reduce_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict
 // that box and of each ancestor, so one load covers G columns of S
 // consecutive values.  The G column-group sums are added in a fixed order.
 // Smaller slices give more, shorter work items (a shorter tail when the
-// items do not fill a whole number of rounds of the machine).
-template <int S>
+// items do not fill a whole number of rounds of the machine).  S0 = 0 takes
+// the slice width Sr at run time: the 16- and 32-row forms use it (one code
+// path for every width keeps them at the 64-row form's registers), so the
+// last slice of a box, when it holds few rows, runs with more column groups.
+template <int S0>
 __device__ __forceinline__ void
 b1_item(int32_t it, int wave, int lane, double (*red)[kWave], const int2* __restrict__ items, int tl,
         const LevelPtrs& L, const BDesc* __restrict__ bil, const double* __restrict__ Up, const double* __restrict__ Dp,
-        const double* __restrict__ tpool, const double* __restrict__ xs, double* __restrict__ ypart)
+        const double* __restrict__ tpool, const double* __restrict__ xs, double* __restrict__ ypart, int Sr = 0)
 {
     using cA = ConstAS<double>;
     const int2 w = items[it];
     const int32_t P = uni(w.x), rc = uni(w.y);
     const int32_t p0 = uni(L.begin[tl][P]), cnt = uni(L.count[tl][P]);
+    const int S = S0 ? S0 : Sr;
     const int32_t rows = min(S, cnt - rc);
-    constexpr int G = kWave / S;
+    const int G = kWave / S;
     const int g = G == 1 ? 0 : lane / S, r = G == 1 ? lane : lane % S;
     const bool act = r < rows;
     double acc = 0.0;
@@ -342,7 +346,7 @@ b1_item(int32_t it, int wave, int lane, double (*red)[kWave], const int2* __rest
         }
         a_box = uni(L.parent[l][a_box]);
     }
-    if constexpr (G == 1) {
+    if (G == 1) {
         if (act) ypart[p0 + rc + r] = acc;
         return;
     }
@@ -450,7 +454,20 @@ k_phaseB(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int kappa,
     const int32_t w = blockIdx.x;
     if (w < nb1) {
         const int32_t it = xcd_sub(w, 0, nb1) * 4 + wave;
-        if (it < nitems) b1_item<S>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart);
+        if (it >= nitems) return;
+        // 16- and 32-row slices: the width is the slice's rows rounded up to
+        // a power of two (at least 8), so a short last slice of a box takes
+        // its columns in more lane groups; 64-row slices keep the fixed form
+        // (measured: a run-time-width path for their short last slices made
+        // the uniform case 9% slower)
+        if constexpr (S == 64) {
+            b1_item<64>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart);
+        } else {
+            const int2 wi = items[it];
+            const int32_t rem = uni(L.count[kappa - 1][uni(wi.x)]) - uni(wi.y);
+            const int Sr = min(S, rem <= 8 ? 8 : rem <= 16 ? 16 : 32);
+            b1_item<0>(it, wave, lane, red, items, kappa - 1, L, bil, Up, Dp, tpool, xs, ypart, Sr);
+        }
     } else {
         const int32_t it = xcd_sub(w, nb1, (int32_t)gridDim.x - nb1) * 4 + wave;
         if (it < nb2items) {
