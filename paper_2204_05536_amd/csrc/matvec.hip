@@ -179,25 +179,31 @@ k_phaseA(const MRItem* __restrict__ items, const MRBlk* __restrict__ blks, const
     }
 }
 
-// t = sum of a split block's partials, in part order.  One workgroup per
-// split block; lanes take parts p = lane, lane + 64, ...; each wave owns
-// columns q = wave, wave + 4, ...; the lane sums are combined by a fixed
-// butterfly.
+// t = sum of a split block's partials.  One workgroup per split block; lane
+// = column (a part's k values are contiguous, so each wave load is one
+// coalesced row of partials); wave w sums the parts w, w + 4, ... in order
+// and the four wave sums are added in wave order.
 template <typename A>
 __global__ void __launch_bounds__(256)
 k_reduce_parts(int64_t nr, const RDesc* __restrict__ R, const A* __restrict__ ppool, A* __restrict__ tpool)
 {
+    __shared__ A red[4][kWave];
     const int64_t r = blockIdx.x;
     if (r >= nr) return;
     RDesc D = R[r];
     D.tout = uni(D.tout); D.k = uni(D.k); D.pbeg = uni(D.pbeg); D.nparts = uni(D.nparts);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    for (int q = wave; q < D.k; q += 4) {
+    for (int32_t q0 = 0; q0 < D.k; q0 += kWave) {
+        const int32_t q = q0 + lane;
         A s = (A)0;
+        if (q < D.k) {
 #pragma unroll 8
-        for (int p = lane; p < D.nparts; p += kWave) s += ppool[D.pbeg + (int64_t)p * D.k + q];
-        for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
-        if (lane == 0) tpool[D.tout + q] = s;
+            for (int32_t p = wave; p < D.nparts; p += 4) s += ppool[D.pbeg + (int64_t)p * D.k + q];
+        }
+        red[wave][lane] = s;
+        __syncthreads();
+        if (wave == 0 && q < D.k) tpool[D.tout + q] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        __syncthreads();
     }
 }
 
@@ -627,8 +633,8 @@ k_phaseB_half(int32_t nb1, int32_t nitems, const int2* __restrict__ items, int k
 }
 
 // Phase B on an adaptive tree (leaves at several levels).  One wave per
-// 64-row chunk of a leaf; the chunk's rows are rounded up to S = 16, 32 or
-// 64 and lane (g, r) owns row r and the columns g, g + G, ... (G = 64 / S)
+// 64-row chunk of a leaf; the chunk's rows are rounded up to S = 8, 16, 32
+// or 64 and lane (g, r) owns row r and the columns g, g + G, ... (G = 64 / S)
 // of every block, so small leaves still keep every lane loading.  The
 // wave sums, in a fixed order, the leaf's dense near-field blocks, then
 // the blocks whose target is the leaf or one of its ancestors, from the
@@ -651,7 +657,7 @@ k_phaseB_adaptive(int32_t nitems, const int2* __restrict__ items, const int32_t*
     const int32_t box = uni(leaf_box[X]);
     const int32_t r0 = uni(L.begin[lx][box]), cnt = uni(L.count[lx][box]);
     const int32_t rows = min(kWave, cnt - rc);
-    const int S = rows <= 16 ? 16 : rows <= 32 ? 32 : 64, G = kWave / S;
+    const int S = rows <= 8 ? 8 : rows <= 16 ? 16 : rows <= 32 ? 32 : 64, G = kWave / S;
     const int g = lane / S, r = lane % S;
     const bool act = r < rows;
     const int32_t row = r0 + rc + r;
