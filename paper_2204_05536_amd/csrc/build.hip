@@ -1466,6 +1466,12 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
     upload(H.aw_red, red, s);
     H.n_aw_items = (int64_t)items.size();
     H.n_aw_red = (int64_t)red.size();
+    H.aw_red_maxw = 0;
+    for (const AWRed& r : red) H.aw_red_maxw = std::max(H.aw_red_maxw, r.w);
+    // the reductions launch ceil(w * 16 / 64) workgroups per box along y
+    // (16 values per column with 16 right-hand sides)
+    if (((int64_t)H.aw_red_maxw * 16 + kWave - 1) / kWave > 65535)
+        fail(H2D_EUNSUPPORTED, "half-precision phase-A source box wider than 2^18 columns");
     H.ws_nrhs = 0;   // the half partial rows are sized here: reallocate on next use
     return jobs;
 }

@@ -297,6 +297,7 @@ struct Handle {
     DBuf<int32_t> aw_map;
     DBuf<AWRed> aw_red;
     int64_t n_aw_items = 0, n_aw_red = 0;
+    int32_t aw_red_maxw = 0;   // widest split source box (columns)
     DBuf<RDesc> ritems;
     int64_t n_aitems = 0, n_ritems = 0;
     DBuf<int2> b1items;         // multi-RHS phase-B1 work: (box at level kappa - 1, first row of a 64-row chunk)

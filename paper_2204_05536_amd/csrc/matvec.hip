@@ -286,21 +286,34 @@ k_phaseA_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t* _
 }
 
 // t of the columns of source boxes whose phase-A rows were split: the sum
-// of the partial rows in part order.  One workgroup per source box, one
-// thread per column.
+// of the partial rows.  Grid (split source boxes, ceil(max w / 64)):
+// workgroup (b, g) owns columns 64 g .. 64 g + 63 of box b (one coalesced
+// row of a part per wave load), its four waves take every fourth part, and
+// the four wave sums are added in a fixed order.
 __global__ void __launch_bounds__(256)
 k_reduce_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict__ map,
               const float* __restrict__ ppool, float* __restrict__ tpool)
 {
+    __shared__ float part[4][kWave];
     const int64_t r = blockIdx.x;
     if (r >= nr) return;
     const AWRed D = R[r];
-    for (int32_t q = threadIdx.x; q < D.w; q += blockDim.x) {
-        float s = 0.f;
-#pragma unroll 8
-        for (int32_t p = 0; p < D.nparts; ++p) s += ppool[D.pbeg + (int64_t)p * D.w + q];
-        tpool[map[D.map + q]] = s;
+    if ((int32_t)blockIdx.y * kWave >= D.w) return;   // whole workgroup
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t q = blockIdx.y * kWave + lane;
+    const float* base = ppool + D.pbeg + min(q, D.w - 1);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int32_t p = wave;
+    for (; p + 12 < D.nparts; p += 16) {
+        s0 += base[(int64_t)p * D.w];
+        s1 += base[(int64_t)(p + 4) * D.w];
+        s2 += base[(int64_t)(p + 8) * D.w];
+        s3 += base[(int64_t)(p + 12) * D.w];
     }
+    for (; p < D.nparts; p += 4) s0 += base[(int64_t)p * D.w];
+    part[wave][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (wave == 0 && q < D.w) tpool[map[D.map + q]] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // Phase B1: ancestor levels.  One wave per slice of S rows (S = 16, 32 or
@@ -1041,7 +1054,9 @@ static void run_one(Handle& H, const T* U, const T* V, const T* D, A* xs, A* tp,
             k_phaseA_wide<T><<<(unsigned)((H.n_aw_items + 3) / 4), 256, 0, s>>>(H.n_aw_items, H.aw_items.p, H.aw_map.p, V,
                                                                                xs, tp, pp);
         if (ev) HIPCK(hipEventRecord(ev[2], s));
-        if (H.n_aw_red) k_reduce_wide<<<(unsigned)H.n_aw_red, 256, 0, s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, pp, tp);
+        if (H.n_aw_red)
+            k_reduce_wide<<<dim3((unsigned)H.n_aw_red, (unsigned)((H.aw_red_maxw + kWave - 1) / kWave)), 256, 0, s>>>(
+                H.n_aw_red, H.aw_red.p, H.aw_map.p, pp, tp);
     } else {
         if (H.n_aitems) k_phaseA<<<(unsigned)H.n_aitems, 256, 0, s>>>(H.a_items.p, H.a_blks.p, V, xs, tp, pp);
         if (ev) HIPCK(hipEventRecord(ev[2], s));

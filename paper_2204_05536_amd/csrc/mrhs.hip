@@ -364,22 +364,39 @@ k_phaseA_mr_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t
 }
 
 // T of the columns of source boxes whose phase-A rows were split (half
-// pools): the sum of the partial rows in part order, per column and
-// right-hand side.  One workgroup per source box.
+// pools): the sum of the partial rows, per column and right-hand side.
+// Grid (split source boxes, ceil(max w * 16 / 64)): workgroup (b, g) owns
+// elements 64 g .. 64 g + 63 of box b's w x 16 result (one coalesced row
+// of a part per wave load), its four waves take every fourth part, and the
+// four wave sums are added in a fixed order.
 __global__ void __launch_bounds__(256)
 k_reduce_mr_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict__ map,
                  const float* __restrict__ pp, float* __restrict__ tp)
 {
+    __shared__ float part[4][kWave];
     const int64_t r = blockIdx.x;
     if (r >= nr) return;
     const AWRed D = R[r];
-    for (int32_t e = threadIdx.x; e < D.w * kR; e += blockDim.x) {
-        const int32_t c = e / kR, rr = e % kR;
-        float s = 0.f;
-#pragma unroll 8
-        for (int32_t p = 0; p < D.nparts; ++p) s += pp[((int64_t)D.pbeg + (int64_t)p * D.w + c) * kR + rr];
-        tp[(int64_t)map[D.map + c] * kR + rr] = s;
+    const int32_t E = D.w * kR;
+    if ((int32_t)blockIdx.y * kWave >= E) return;   // whole workgroup
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t e = blockIdx.y * kWave + lane;
+    const int64_t stride = (int64_t)D.w * kR;
+    const float* base = pp + (int64_t)D.pbeg * kR + min(e, E - 1);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int32_t p = wave;
+    for (; p + 12 < D.nparts; p += 16) {
+        s0 += base[(int64_t)p * stride];
+        s1 += base[(int64_t)(p + 4) * stride];
+        s2 += base[(int64_t)(p + 8) * stride];
+        s3 += base[(int64_t)(p + 12) * stride];
     }
+    for (; p < D.nparts; p += 4) s0 += base[(int64_t)p * stride];
+    part[wave][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (wave == 0 && e < E)
+        tp[(int64_t)map[D.map + e / kR] * kR + e % kR] =
+            (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // Phase A grouped by source box: one workgroup per item stages the item's
@@ -463,16 +480,14 @@ k_reduce_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int
     const int32_t e = blockIdx.y * kWave + lane;
     const int64_t stride = (int64_t)D.k * kR;
     const A* base = ppool + (int64_t)D.pbeg * kR + min(e, E - 1);
-    A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    A sv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t p = wave;
-    for (; p + 12 < D.nparts; p += 16) {
-        s0 += base[(int64_t)p * stride];
-        s1 += base[(int64_t)(p + 4) * stride];
-        s2 += base[(int64_t)(p + 8) * stride];
-        s3 += base[(int64_t)(p + 12) * stride];
+    for (; p + 28 < D.nparts; p += 32) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sv[u] += base[(int64_t)(p + 4 * u) * stride];
     }
-    for (; p < D.nparts; p += 4) s0 += base[(int64_t)p * stride];
-    part[wave][lane] = (s0 + s1) + (s2 + s3);
+    for (; p < D.nparts; p += 4) sv[0] += base[(int64_t)p * stride];
+    part[wave][lane] = ((sv[0] + sv[1]) + (sv[2] + sv[3])) + ((sv[4] + sv[5]) + (sv[6] + sv[7]));
     __syncthreads();
     if (wave == 0 && e < E)
         tpool[(int64_t)D.tout * kR + e] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
@@ -967,7 +982,8 @@ static void run_mr(Handle& H, const MRInst* I, const double* x, double* y, int n
                 k_phaseA_mr_wide<T><<<(unsigned)H.n_aw_items, 256, 0, s>>>(H.n_aw_items, H.aw_items.p, H.aw_map.p, V,
                                                                             H.xs_mr32.p, H.tp_mr32.p, H.pp_mr32.p);
             if (H.n_aw_red)
-                k_reduce_mr_wide<<<(unsigned)H.n_aw_red, 256, 0, s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, H.pp_mr32.p,
+                k_reduce_mr_wide<<<dim3((unsigned)H.n_aw_red, (unsigned)((H.aw_red_maxw * kR + kWave - 1) / kWave)), 256, 0,
+                                   s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, H.pp_mr32.p,
                                                                       H.tp_mr32.p);
         } else {
             if (H.n_mr_items)
