@@ -1468,10 +1468,17 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
     H.n_aw_red = (int64_t)red.size();
     H.aw_red_maxw = 0;
     for (const AWRed& r : red) H.aw_red_maxw = std::max(H.aw_red_maxw, r.w);
-    // the reductions launch ceil(w * 16 / 64) workgroups per box along y
-    // (16 values per column with 16 right-hand sides)
-    if (((int64_t)H.aw_red_maxw * 16 + kWave - 1) / kWave > 65535)
-        fail(H2D_EUNSUPPORTED, "half-precision phase-A source box wider than 2^18 columns");
+    // the single-RHS reduction launches ceil(w / 64) workgroups per box
+    // along y; the 16-RHS one takes a list of 64-value chunks (16 values per
+    // column), so that no workgroup is launched empty
+    if ((H.aw_red_maxw + kWave - 1) / kWave > 65535)
+        fail(H2D_EUNSUPPORTED, "half-precision phase-A source box wider than 2^22 columns");
+    std::vector<int2> chunks;
+    for (size_t r = 0; r < red.size(); ++r)
+        for (int32_t e0 = 0; e0 < red[r].w * 16; e0 += kWave) chunks.push_back(make_int2((int32_t)r, e0));
+    if (chunks.size() > (size_t)INT32_MAX) fail(H2D_EUNSUPPORTED, "half-precision reduction list above 2^31 chunks");
+    upload(H.aw_rchunks, chunks, s);
+    H.n_aw_rchunks = (int64_t)chunks.size();
     H.ws_nrhs = 0;   // the half partial rows are sized here: reallocate on next use
     return jobs;
 }

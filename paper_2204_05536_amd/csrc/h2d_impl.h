@@ -176,6 +176,7 @@ struct MRInst {
     uint64_t scale, diag;             // half pools: const float* block scales (IL blocks, then near blocks) and
                                       // self-block diagonal (tree order); unused in FP64
     uint64_t qp1, qt1, qp2, qt2;      // half pools: phase-B tables (CSR pointers, entries); unused in FP64
+    uint64_t rchunks;                 // const int2*: (split block, first element) of each 64-value reduction chunk
     int32_t n, kappa, has_b1, n_il;
 };
 // Right-hand sides of one instance: x and y column-major, leading dimension ld.
@@ -296,7 +297,8 @@ struct Handle {
     DBuf<AWDesc> aw_items;
     DBuf<int32_t> aw_map;
     DBuf<AWRed> aw_red;
-    int64_t n_aw_items = 0, n_aw_red = 0;
+    DBuf<int2> aw_rchunks;     // 16 right-hand sides: (reduction, first of its w x 16 values) per 64 values
+    int64_t n_aw_items = 0, n_aw_red = 0, n_aw_rchunks = 0;
     int32_t aw_red_maxw = 0;   // widest split source box (columns)
     DBuf<RDesc> ritems;
     int64_t n_aitems = 0, n_ritems = 0;
@@ -317,8 +319,9 @@ struct Handle {
     DBuf<MRItem> mr_items;           // multi-RHS phase-A items (source-grouped)
     DBuf<MRBlk> mr_blks;
     DBuf<RDesc> mr_ritems;           // their split-block reductions
+    DBuf<int2> mr_rchunks;           // (reduction, first of its k x 16 values) per 64 values
     DBuf<int32_t> iperm;             // caller index -> tree position
-    int64_t n_mr_items = 0, n_mr_ritems = 0, mr_p_elems = 0;
+    int64_t n_mr_items = 0, n_mr_ritems = 0, n_mr_rchunks = 0, mr_p_elems = 0;
     std::vector<int64_t> h_mr_work;  // work of each multi-RHS phase-A item, in schedule order
     DBuf<MRInst> mr_inst;            // this handle's entry for the table-driven kernels
     // the half-pool form (FP32 work vectors; phase A on the source-grouped
@@ -392,7 +395,6 @@ struct MRBatchPlan {
     DBuf<int2> wg, wa, wr, wb1, wb2;   // work lists: (instance, item)
     int32_t ng = 0, nr = 0, nb1 = 0, nb2 = 0;
     std::vector<int32_t> a_rows, a_beg, a_cnt;   // phase A: one launch per source-chunk size (LDS need)
-    int32_t red_y = 1;
 };
 void mr_plan(MRBatchPlan& P, Handle* const* hs, const MRIo* io, int count, hipStream_t s);
 void mr_plan_launch(const MRBatchPlan& P, int32_t r0, int32_t nr, hipStream_t s);

@@ -364,23 +364,22 @@ k_phaseA_mr_wide(int64_t nitems, const AWDesc* __restrict__ items, const int32_t
 }
 
 // T of the columns of source boxes whose phase-A rows were split (half
-// pools): the sum of the partial rows, per column and right-hand side.
-// Grid (split source boxes, ceil(max w * 16 / 64)): workgroup (b, g) owns
-// elements 64 g .. 64 g + 63 of box b's w x 16 result (one coalesced row
-// of a part per wave load), its four waves take every fourth part, and the
-// four wave sums are added in a fixed order.
+// pools): the sum of the partial rows, per column and right-hand side.  One
+// workgroup per chunk (b, e0) of the list: it owns values e0 .. e0 + 63 of
+// box b's w x 16 result (one coalesced row of a part per wave load), its
+// four waves take every fourth part, and the four wave sums are added in a
+// fixed order.
 __global__ void __launch_bounds__(256)
-k_reduce_mr_wide(int64_t nr, const AWRed* __restrict__ R, const int32_t* __restrict__ map,
-                 const float* __restrict__ pp, float* __restrict__ tp)
+k_reduce_mr_wide(int64_t nc, const int2* __restrict__ chunks, const AWRed* __restrict__ R,
+                 const int32_t* __restrict__ map, const float* __restrict__ pp, float* __restrict__ tp)
 {
     __shared__ float part[4][kWave];
-    const int64_t r = blockIdx.x;
-    if (r >= nr) return;
-    const AWRed D = R[r];
+    if ((int64_t)blockIdx.x >= nc) return;
+    const int2 C = chunks[blockIdx.x];
+    const AWRed D = R[__builtin_amdgcn_readfirstlane(C.x)];
     const int32_t E = D.w * kR;
-    if ((int32_t)blockIdx.y * kWave >= E) return;   // whole workgroup
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t e = blockIdx.y * kWave + lane;
+    const int32_t e = __builtin_amdgcn_readfirstlane(C.y) + lane;
     const int64_t stride = (int64_t)D.w * kR;
     const float* base = pp + (int64_t)D.pbeg * kR + min(e, E - 1);
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
@@ -459,10 +458,10 @@ k_phaseA_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int
                    gp<A>(I.tp), gp<A>(I.pp), (A*)xl_raw, I.scale ? gp<const float>(I.scale) : nullptr);
 }
 
-// t = sum of the partial products of one split block.  Grid (split blocks,
-// ceil(max k / 4)): workgroup (b, g) owns elements 64 g .. 64 g + 63 of the
-// k x 16 result, its four waves take every fourth part, and the four wave
-// sums are added in a fixed order.
+// t = sum of the partial products of one split block.  One workgroup per
+// chunk (b, e0) of the instance's list: it owns elements e0 .. e0 + 63 of
+// block b's k x 16 result, its four waves take every fourth part, and the
+// four wave sums are added in a fixed order.
 template <typename A>
 __global__ void __launch_bounds__(256)
 k_reduce_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int32_t nwork)
@@ -473,11 +472,11 @@ k_reduce_mr(const MRInst* __restrict__ insts, const int2* __restrict__ work, int
     const MRInst& I = insts[wk.x];
     const A* __restrict__ ppool = gp<const A>(I.pp);
     A* __restrict__ tpool = gp<A>(I.tp);
-    const RDesc D = gp<const RDesc>(I.ritems)[wk.y];
+    const int2 C = gp<const int2>(I.rchunks)[wk.y];
+    const RDesc D = gp<const RDesc>(I.ritems)[__builtin_amdgcn_readfirstlane(C.x)];
     const int32_t E = D.k * kR;
-    if ((int32_t)blockIdx.y * kWave >= E) return;   // whole workgroup
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t e = blockIdx.y * kWave + lane;
+    const int32_t e = __builtin_amdgcn_readfirstlane(C.y) + lane;
     const int64_t stride = (int64_t)D.k * kR;
     const A* base = ppool + (int64_t)D.pbeg * kR + min(e, E - 1);
     A sv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -878,6 +877,16 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
         HIPCK(hipMemcpyAsync(H.mr_ritems.p, red.data(), sizeof(RDesc) * red.size(), hipMemcpyHostToDevice, s));
     H.n_mr_items = (int64_t)sorted.size();
     H.n_mr_ritems = (int64_t)red.size();
+    // the reductions in chunks of 64 of their k x 16 values (no workgroup
+    // launched empty)
+    std::vector<int2> chunks;
+    for (size_t r = 0; r < red.size(); ++r)
+        for (int32_t e0 = 0; e0 < red[r].k * kR; e0 += kWave) chunks.push_back(make_int2((int32_t)r, e0));
+    if (chunks.size() > (size_t)INT32_MAX) fail(H2D_EUNSUPPORTED, "multi-RHS reduction list above 2^31 chunks");
+    H.mr_rchunks.alloc(std::max<size_t>(chunks.size(), 1));
+    if (!chunks.empty())
+        HIPCK(hipMemcpyAsync(H.mr_rchunks.p, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, s));
+    H.n_mr_rchunks = (int64_t)chunks.size();
     H.mr_p_elems = poff;
     HIPCK(hipStreamSynchronize(s));
 }
@@ -891,6 +900,7 @@ MRInst mr_inst_of(const Handle& H)
     I.xs = addr(H.xs_mr.p); I.tp = addr(H.tp_mr.p); I.pp = addr(H.pp_mr.p);
     I.yp = addr(H.yp_mr.p); I.yl = addr(H.yl_mr.p);
     I.items = addr(H.mr_items.p); I.blks = addr(H.mr_blks.p); I.ritems = addr(H.mr_ritems.p);
+    I.rchunks = addr(H.mr_rchunks.p);
     I.b1items = addr(H.b1items.p); I.bil = addr(H.bil.p); I.bnear = addr(H.bnear.p);
     I.near_ptr = addr(H.near_ptr.p); I.iperm = addr(H.iperm.p); I.lvl = addr(H.lvl_ptrs.p);
     I.scale = 0; I.diag = 0;
@@ -982,16 +992,15 @@ static void run_mr(Handle& H, const MRInst* I, const double* x, double* y, int n
                 k_phaseA_mr_wide<T><<<(unsigned)H.n_aw_items, 256, 0, s>>>(H.n_aw_items, H.aw_items.p, H.aw_map.p, V,
                                                                             H.xs_mr32.p, H.tp_mr32.p, H.pp_mr32.p);
             if (H.n_aw_red)
-                k_reduce_mr_wide<<<dim3((unsigned)H.n_aw_red, (unsigned)((H.aw_red_maxw * kR + kWave - 1) / kWave)), 256, 0,
-                                   s>>>(H.n_aw_red, H.aw_red.p, H.aw_map.p, H.pp_mr32.p,
+                k_reduce_mr_wide<<<(unsigned)H.n_aw_rchunks, 256, 0, s>>>(H.n_aw_rchunks, H.aw_rchunks.p, H.aw_red.p,
+                                                                          H.aw_map.p, H.pp_mr32.p,
                                                                       H.tp_mr32.p);
         } else {
             if (H.n_mr_items)
                 k_phaseA_mr<T><<<(unsigned)H.n_mr_items, 256, (size_t)R * kR * sizeof(A), s>>>(I, nullptr,
                                                                                              (int32_t)H.n_mr_items);
-            if (H.n_mr_ritems)
-                k_reduce_mr<A><<<dim3((unsigned)H.n_mr_ritems, (unsigned)((H.max_rank * kR + kWave - 1) / kWave)), 256,
-                                 0, s>>>(I, nullptr, (int32_t)H.n_mr_ritems);
+            if (H.n_mr_rchunks)
+                k_reduce_mr<A><<<(unsigned)H.n_mr_rchunks, 256, 0, s>>>(I, nullptr, (int32_t)H.n_mr_rchunks);
         }
         const int32_t nb1 = (int32_t)((H.n_b1 + 3) / 4), nb2 = (nleaf + 3) / 4;
         k_phaseB_mr<T><<<(unsigned)(nb1 + nb2), 256, 0, s>>>(I, nb1, nullptr, (int32_t)H.n_b1, nullptr, nleaf);
@@ -1027,7 +1036,6 @@ void mr_plan(MRBatchPlan& P, Handle* const* hs, const MRIo* io, int count, hipSt
     std::vector<int2> wg, wr;
     std::vector<std::pair<int64_t, int2>> wa;
     std::vector<int32_t> rows(count);
-    P.red_y = 1;
     for (int i = 0; i < count; ++i) {
         Handle& H = *hs[i];
         ensure_mr(H, s);
@@ -1036,8 +1044,7 @@ void mr_plan(MRBatchPlan& P, Handle* const* hs, const MRIo* io, int count, hipSt
         const int32_t n = (int32_t)H.n;
         for (int32_t b = 0; b < (n + kWave - 1) / kWave; ++b) wg.push_back(make_int2(i, b));
         for (int32_t a = 0; a < (int32_t)H.n_mr_items; ++a) wa.push_back({H.h_mr_work[a], make_int2(i, a)});
-        for (int32_t r = 0; r < (int32_t)H.n_mr_ritems; ++r) wr.push_back(make_int2(i, r));
-        P.red_y = std::max<int32_t>(P.red_y, (int32_t)((H.max_rank * kR + kWave - 1) / kWave));
+        for (int32_t r = 0; r < (int32_t)H.n_mr_rchunks; ++r) wr.push_back(make_int2(i, r));
     }
     // phase B: the XCD-aware mapping gives each XCD one eighth of the list;
     // deal every instance's items over the eighths (contiguous inside each)
@@ -1091,7 +1098,7 @@ void mr_plan_launch(const MRBatchPlan& P, int32_t r0, int32_t nr, hipStream_t s)
     for (size_t g = 0; g < P.a_rows.size(); ++g)
         k_phaseA_mr<double><<<(unsigned)P.a_cnt[g], 256, (size_t)P.a_rows[g] * kR * sizeof(double), s>>>(
             P.insts.p, P.wa.p + P.a_beg[g], P.a_cnt[g]);
-    if (P.nr) k_reduce_mr<double><<<dim3((unsigned)P.nr, (unsigned)P.red_y), 256, 0, s>>>(P.insts.p, P.wr.p, P.nr);
+    if (P.nr) k_reduce_mr<double><<<(unsigned)P.nr, 256, 0, s>>>(P.insts.p, P.wr.p, P.nr);
     const int32_t g1 = (P.nb1 + 3) / 4, g2 = (P.nb2 + 3) / 4;
     k_phaseB_mr<double><<<(unsigned)(g1 + g2), 256, 0, s>>>(P.insts.p, g1, P.wb1.p, P.nb1, P.wb2.p, P.nb2);
     k_scatter_mr<double><<<(unsigned)P.ng, 256, 0, s>>>(P.insts.p, P.wg.p, P.ng, none, P.io.p, r0, nr);
