@@ -1470,12 +1470,17 @@ static std::vector<HalfVJob> wide_v_layout(Handle& H, hipStream_t s)
     for (const AWRed& r : red) H.aw_red_maxw = std::max(H.aw_red_maxw, r.w);
     // the single-RHS reduction launches ceil(w / 64) workgroups per box
     // along y; the 16-RHS one takes a list of 64-value chunks (16 values per
-    // column), so that no workgroup is launched empty
+    // column), so that no workgroup is launched empty: the first chunk of
+    // every box, then the second, ... (the long reductions of the few wide
+    // boxes spread over the launch)
     if ((H.aw_red_maxw + kWave - 1) / kWave > 65535)
         fail(H2D_EUNSUPPORTED, "half-precision phase-A source box wider than 2^22 columns");
     std::vector<int2> chunks;
-    for (size_t r = 0; r < red.size(); ++r)
-        for (int32_t e0 = 0; e0 < red[r].w * 16; e0 += kWave) chunks.push_back(make_int2((int32_t)r, e0));
+    int32_t nch = 0;
+    for (const AWRed& r : red) nch = std::max(nch, (r.w * 16 + kWave - 1) / kWave);
+    for (int32_t c = 0; c < nch; ++c)
+        for (size_t r = 0; r < red.size(); ++r)
+            if (c * kWave < red[r].w * 16) chunks.push_back(make_int2((int32_t)r, c * kWave));
     if (chunks.size() > (size_t)INT32_MAX) fail(H2D_EUNSUPPORTED, "half-precision reduction list above 2^31 chunks");
     upload(H.aw_rchunks, chunks, s);
     H.n_aw_rchunks = (int64_t)chunks.size();

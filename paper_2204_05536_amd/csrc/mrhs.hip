@@ -878,10 +878,13 @@ static void build_mr_schedule(Handle& H, hipStream_t s)
     H.n_mr_items = (int64_t)sorted.size();
     H.n_mr_ritems = (int64_t)red.size();
     // the reductions in chunks of 64 of their k x 16 values (no workgroup
-    // launched empty)
+    // launched empty): the first chunk of every reduction, then the second, ...
     std::vector<int2> chunks;
-    for (size_t r = 0; r < red.size(); ++r)
-        for (int32_t e0 = 0; e0 < red[r].k * kR; e0 += kWave) chunks.push_back(make_int2((int32_t)r, e0));
+    int32_t nch = 0;
+    for (const RDesc& r : red) nch = std::max(nch, (r.k * kR + kWave - 1) / kWave);
+    for (int32_t c = 0; c < nch; ++c)
+        for (size_t r = 0; r < red.size(); ++r)
+            if (c * kWave < red[r].k * kR) chunks.push_back(make_int2((int32_t)r, c * kWave));
     if (chunks.size() > (size_t)INT32_MAX) fail(H2D_EUNSUPPORTED, "multi-RHS reduction list above 2^31 chunks");
     H.mr_rchunks.alloc(std::max<size_t>(chunks.size(), 1));
     if (!chunks.empty())
