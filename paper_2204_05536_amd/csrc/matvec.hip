@@ -397,9 +397,10 @@ b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, double (*red)[kWa
     const int32_t rows = min(S2, cnt - rc);
     const int G = kWave / rows, g = lane / rows, r = lane % rows;
     const bool act = g < G;
-    // one block: its multiplier values (t, or x of the source box) are
-    // staged in this wave's LDS slice, kB2Stage at a time, with one load per
-    // lane, instead of one gather load per lane and column group
+    // one block wider than a wave: its multiplier values (t, or x of the
+    // source box) are staged in this wave's LDS slice, kB2Stage at a time,
+    // with one load per lane, instead of one gather load per lane and column
+    // group
     auto sweep = [&](const double* base, const double* tv, int32_t nc) -> double {
         double a = 0.0;
         for (int32_t c0 = 0; c0 < nc; c0 += kB2Stage) {
@@ -413,18 +414,44 @@ b2_item(int32_t X, int32_t rc, int32_t S2, int wave, int lane, double (*red)[kWa
         }
         return a;
     };
+    // the blocks in order (near blocks, then the interaction list); a block
+    // of at most 64 values is staged from a register loaded while the
+    // previous block's values were read, so the staging load and the block's
+    // own loads share one wait
+    const int32_t nn = n1 - n0, nt = nn + (q1 - q0);
+    auto desc = [&](int32_t i) -> BDesc {
+        if (i >= nt) return BDesc{0, 0, 0};
+        return i < nn ? uni(bnear[n0 + i]) : uni(bil[q0 + i - nn]);
+    };
+    auto mult = [&](const BDesc& d) -> const double* { return (d.cols > 0 ? tpool : xs) + d.tsrc; };
+    auto fbase = [&](const BDesc& d) -> const double* { return (d.cols > 0 ? Up : Dp) + d.off + rc + r; };
+    auto first = [&](const BDesc& d, int32_t n) -> double { return n <= kWave && lane < n ? mult(d)[lane] : 0.0; };
     double acc = 0.0;
-    for (int32_t q = n0; q < n1; ++q) {
-        const BDesc d = uni(bnear[q]);
-        acc += sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
-    }
-    for (int32_t q = q0; q < q1; ++q) {
-        const BDesc d = uni(bil[q]);
-        if (d.cols > 0) {
-            acc += sweep(Up + d.off + rc + r, tpool + d.tsrc, d.cols);
-        } else if (d.cols < 0) {
-            acc += sweep(Dp + d.off + rc + r, xs + d.tsrc, -d.cols);
+    BDesc d = desc(0);
+    int32_t n = d.cols > 0 ? d.cols : -d.cols;
+    double v = first(d, n);
+    for (int32_t i = 0; i < nt; ++i) {
+        const BDesc dn = desc(i + 1);
+        const int32_t nx = dn.cols > 0 ? dn.cols : -dn.cols;
+        if (n > kWave) {
+            acc += sweep(fbase(d), mult(d), n);
+            v = first(dn, nx);
+        } else if (n > 0) {
+            if (lane < n) tst[lane] = v;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            const double vn = first(dn, nx);
+            double a = 0.0;
+            if (act) dot_cols(a, fbase(d), cnt, tst, n, g, G);
+            acc += a;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            v = vn;
+        } else {
+            v = first(dn, nx);
         }
+        d = dn;
+        n = nx;
     }
     red[wave][lane] = act ? acc : 0.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
